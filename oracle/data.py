@@ -1,0 +1,83 @@
+"""What gread() must deliver, and what the benchmark consumers compute from it.
+
+Test infrastructure only (see the package docstring).
+
+* gread(fd, offset, size) delivers exactly the file bytes
+  [offset, min(offset + size, file_size)) -- a POSIX read at an offset, which is
+  what the paper's GPU file API exposes to threadblocks (Sec. 2.2, "GPUfs").
+  The oracle gets those bytes with a plain ``os.pread``.
+* checksum: wrapping uint64 sum of the little-endian uint32 words of each
+  delivered buffer, a trailing partial word zero-padded; a block's checksum is
+  the sum over its reads in order (integer addition, so order-independent).
+* histogram: uint32 count of each byte value over every byte a block receives.
+"""
+from __future__ import annotations
+
+import os
+from typing import Iterable
+
+import numpy as np
+
+
+def delivered(path: str, offset: int, size: int) -> bytes:
+    """The bytes a read of ``size`` at ``offset`` returns (short at EOF, empty past it)."""
+    fsize = os.path.getsize(path)
+    if size <= 0 or offset >= fsize:
+        return b""
+    n = min(size, fsize - offset)
+    fd = os.open(path, os.O_RDONLY)
+    try:
+        out = bytearray()
+        while len(out) < n:
+            chunk = os.pread(fd, n - len(out), offset + len(out))
+            if not chunk:
+                raise IOError(f"unexpected EOF in {path} at {offset + len(out)}")
+            out += chunk
+        return bytes(out)
+    finally:
+        os.close(fd)
+
+
+def checksum_of(buf: bytes) -> int:
+    """Wrapping u64 sum of LE u32 words; a trailing partial word is zero-padded."""
+    pad = (-len(buf)) % 4
+    b = buf + b"\0" * pad
+    words = np.frombuffer(b, dtype="<u4").astype(np.uint64)
+    with np.errstate(over="ignore"):
+        return int(words.sum(dtype=np.uint64))
+
+
+def histogram_of(buf: bytes) -> np.ndarray:
+    """Count of each byte value 0..255 (uint32)."""
+    a = np.frombuffer(buf, dtype=np.uint8)
+    return np.bincount(a, minlength=256).astype(np.uint32)
+
+
+def block_checksums(path: str, offsets: np.ndarray, read_size: int,
+                    blocks: Iterable[int] | None = None) -> np.ndarray:
+    """Per-block u64 checksums; ``offsets[b, k]`` is block b's k-th read.
+
+    If ``blocks`` is given only those rows are computed (the rest stay 0)."""
+    nb = offsets.shape[0]
+    out = np.zeros(nb, dtype=np.uint64)
+    rows = range(nb) if blocks is None else blocks
+    for b in rows:
+        s = 0
+        for off in offsets[b]:
+            s = (s + checksum_of(delivered(path, int(off), read_size))) & ((1 << 64) - 1)
+        out[b] = np.uint64(s)
+    return out
+
+
+def block_histograms(path: str, offsets: np.ndarray, read_size: int,
+                     blocks: Iterable[int] | None = None) -> np.ndarray:
+    """Per-block 256-bin u32 histograms; rows not in ``blocks`` stay 0."""
+    nb = offsets.shape[0]
+    out = np.zeros((nb, 256), dtype=np.uint32)
+    rows = range(nb) if blocks is None else blocks
+    for b in rows:
+        h = np.zeros(256, dtype=np.uint64)
+        for off in offsets[b]:
+            h += histogram_of(delivered(path, int(off), read_size))
+        out[b] = h.astype(np.uint32)
+    return out

@@ -1,0 +1,148 @@
+"""A second, independently written policy model: plain lists and linear scans.
+
+Test infrastructure only. It exists to cross-check ``oracle.policy`` by brute
+force over every interleaving of tiny workloads; it implements the same rules
+(page split, lookup, synchronous windowed miss, clock hand, stream detector) from
+their statement, without sharing code or data structures with ``policy``.
+
+Frame record: [state, file, page, pins, ref, ra] with state 0 free, 1 filling, 2 valid.
+Stream record: [in_use, next, size, last_use].
+"""
+from __future__ import annotations
+
+
+def _find(frames, file_id, page):
+    for i in range(len(frames)):
+        fr = frames[i]
+        if fr[0] != 0 and fr[1] == file_id and fr[2] == page:
+            return i
+    return -1
+
+
+class NaiveModel:
+    def __init__(self, nframes, page_size, w0, cap, nstreams):
+        self.frames = [[0, -1, -1, 0, 0, 0] for _ in range(nframes)]
+        self.page_size = page_size
+        self.w0 = w0
+        self.cap = cap
+        self.nstreams = nstreams
+        self.hand = 0
+        self.size = {}
+        self.advice = {}
+        self.streams = {}
+        self.tick = {}
+        self.log = []
+
+    def open(self, file_id, size, advice="normal"):
+        self.size[file_id] = size
+        self.advice[file_id] = advice
+        self.streams[file_id] = [[False, 0, 0, 0] for _ in range(self.nstreams)]
+        self.tick[file_id] = 0
+
+    def _window(self, file_id, p):
+        if self.cap == 0 or self.advice[file_id] == "random":
+            return p, 1
+        self.tick[file_id] = self.tick[file_id] + 1
+        now = self.tick[file_id]
+        table = self.streams[file_id]
+        i = 0
+        while i < len(table):
+            st = table[i]
+            if st[0] and p >= st[1] and p < st[1] + st[2]:
+                start = st[1]
+                n = 2 * st[2]
+                if n > self.cap:
+                    n = self.cap
+                table[i] = [True, start + n, n, now]
+                return start, n
+            i += 1
+        slot = -1
+        for i in range(len(table)):
+            if not table[i][0]:
+                slot = i
+                break
+        if slot < 0:
+            slot = 0
+            for i in range(1, len(table)):
+                if table[i][3] < table[slot][3]:
+                    slot = i
+        if p == 0 or self.advice[file_id] == "sequential":
+            n = self.w0
+        else:
+            n = 1
+        if n > self.cap:
+            n = self.cap
+        if n < 1:
+            n = 1
+        table[slot] = [True, p + n, n, now]
+        return p, n
+
+    def _take_frame(self):
+        C = len(self.frames)
+        visits = 0
+        while visits < 2 * C:
+            t = self.hand
+            self.hand = t + 1
+            visits += 1
+            i = t % C
+            fr = self.frames[i]
+            if fr[0] == 0:
+                self.log.append(("HAND", t, i, "FREE", -1, -1, 0))
+                return i
+            if fr[0] == 1 or fr[3] != 0:
+                self.log.append(("HAND", t, i, "SKIP", -1, -1, 0))
+                continue
+            if fr[4] == 1:
+                fr[4] = 0
+                self.log.append(("HAND", t, i, "CLEAR", -1, -1, 0))
+                continue
+            self.log.append(("HAND", t, i, "EVICT", fr[1], fr[2], fr[5]))
+            self.frames[i] = [0, -1, -1, 0, 0, 0]
+            return i
+        return -1
+
+    def read(self, block, file_id, offset, size):
+        fsize = self.size[file_id]
+        if size <= 0 or offset >= fsize:
+            return 0
+        last_byte = offset + size
+        if last_byte > fsize:
+            last_byte = fsize
+        P = self.page_size
+        npages = (fsize + P - 1) // P
+        page = offset // P
+        while page * P < last_byte:
+            i = _find(self.frames, file_id, page)
+            if i >= 0:
+                self.frames[i][4] = 1
+                self.frames[i][5] = 0
+                self.log.append(("HIT", block, file_id, page, i))
+            else:
+                start, n = self._window(file_id, page)
+                if start + n > npages:
+                    n = npages - start
+                self.log.append(("MISS", block, file_id, page, start, n))
+                todo = [page]
+                for q in range(start, start + n):
+                    if q != page and _find(self.frames, file_id, q) < 0:
+                        todo.append(q)
+                got = []
+                for q in todo:
+                    i = self._take_frame()
+                    if i < 0:
+                        if q == page:
+                            raise RuntimeError("no frame for demanded page")
+                        self.log.append(("NOFRAME", block, file_id, q))
+                        break
+                    self.frames[i] = [1, file_id, q, 1 if q == page else 0, 0, 0 if q == page else 1]
+                    self.log.append(("ALLOC", file_id, q, i, 0 if q == page else 1))
+                    got.append(i)
+                pages = [self.frames[i][2] for i in got]
+                self.log.append(("REQ", file_id, min(pages), max(pages) - min(pages) + 1))
+                for i in got:
+                    self.frames[i][0] = 2
+                    self.frames[i][4] = 1
+                j = _find(self.frames, file_id, page)
+                self.frames[j][3] = self.frames[j][3] - 1
+            page += 1
+        return last_byte - offset

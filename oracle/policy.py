@@ -1,0 +1,273 @@
+"""Step-by-step CPU model of the page cache, readahead detector and clock replacement.
+
+Test infrastructure only (see the package docstring).
+
+What the model follows:
+
+* Sec. 2.2 (GPUfs read path): a threadblock's read is divided into pages; each
+  page is looked up in the GPU page cache; a hit is served from the cache, a miss
+  becomes a request to the host and the block waits for it.
+* Sec. 4.1 (GPU-side mechanism, steps 2, 3, 6 and 7): on a miss the block asks
+  the host for the missed page plus a prefetch window, and all of the window's
+  pages are placed in the cache. The paper's window is static; the window here
+  grows like the Linux readahead the paper describes in Sec. 2.3 (sequentiality
+  detected per stream, several streams per file, size doubled on each sequential
+  hit up to a maximum). A first read at offset 0 opens a window of ``W0`` pages,
+  the Sec. 3.2 example (a 4 KB read at offset 0 prefetches 16 KB) with W0 = 4.
+* Sec. 4 (read-only gating, fadvise hint): readahead is on only for read-only
+  files and can be switched off per file with the RANDOM hint.
+* Sec. 5.1 (replacement): frames are reused in place without being freed and
+  re-allocated. The victim is chosen by clock (second chance) over a global
+  hand; for read-once streams this evicts in allocation order, like the paper's
+  least-recently-allocated queue (pinned in tests against ``oracle.lra``).
+
+Readings where the paper is silent (the same list is in the design notes):
+window = [s.next, s.next + min(2 s.size, cap)) for a stream s whose zone
+[s.next, s.next + s.size) holds the missed page p (lowest slot wins); otherwise a
+new stream replaces an empty slot or the least recently used one (lowest index
+on ties) with window [p, p + w), w = W0 if p == 0 or the file is SEQUENTIAL, else
+1; windows are clamped to EOF; the demanded page is allocated first, then the
+other unmapped window pages in ascending order; one host request covers the span
+of allocated pages; the prefetch is synchronous (the requester waits for the
+whole window); a filled frame gets its reference bit set; a pin sets it and
+clears the unconsumed-prefetch mark; the hand starts at frame 0, skips frames
+that are filling or pinned, clears a set reference bit, and otherwise evicts.
+
+Events produced (tuples; the GPU trace is decoded into the same vocabulary):
+
+  ("HIT",  block, file, page, frame)
+  ("MISS", block, file, page, ws, wn)          wn already clamped to EOF
+  ("HAND", ticket, frame, action, vfile, vpage, vra)
+        action in FREE / SKIP / CLEAR / EVICT; victim fields are -1, -1, 0 unless EVICT
+  ("ALLOC", file, page, frame, ra)             ra = 1 for prefetched (non-demand) pages
+  ("REQ",  file, first_page, npages)           one host read of the allocated span
+  ("NOFRAME", block, file, page)               no frame for a non-demand page: window cut
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Optional, Tuple
+
+FREE, FILLING, VALID = "FREE", "FILLING", "VALID"
+ADV_NORMAL, ADV_SEQUENTIAL, ADV_RANDOM = "normal", "sequential", "random"
+
+
+@dataclasses.dataclass
+class Frame:
+    state: str = FREE
+    file: int = -1
+    page: int = -1
+    pins: int = 0
+    ref: int = 0
+    ra: int = 0
+
+
+@dataclasses.dataclass
+class Stream:
+    valid: bool = False
+    next: int = 0
+    size: int = 0
+    last_use: int = 0
+
+
+@dataclasses.dataclass
+class FileState:
+    size: int
+    advice: str = ADV_NORMAL
+    read_only: bool = True
+    streams: List[Stream] = dataclasses.field(default_factory=list)
+    clock: int = 0          # per-file count of readahead decisions (stream last_use)
+
+
+class PolicyModel:
+    def __init__(self, nframes: int, page_size: int, ra_init_pages: int = 4,
+                 ra_cap_pages: int = 0, streams_per_file: int = 8):
+        if nframes <= 0 or page_size <= 0:
+            raise ValueError("nframes and page_size must be positive")
+        self.C = nframes
+        self.P = page_size
+        self.W0 = ra_init_pages
+        self.cap = ra_cap_pages
+        self.S = streams_per_file
+        self.frames = [Frame() for _ in range(nframes)]
+        self.map: Dict[Tuple[int, int], int] = {}
+        self.hand = 0
+        self.files: Dict[int, FileState] = {}
+        self.events: List[tuple] = []
+        # counters
+        self.hits = 0
+        self.misses = 0
+        self.evictions = 0
+        self.fetched_pages = 0
+        self.ra_pages = 0
+        self.wasted_pages = 0
+        self.fetched_bytes = 0
+        self.wasted_bytes = 0
+        self.requests = 0
+        self.request_bytes = 0
+        self.delivered_bytes = 0
+
+    # ---- files ------------------------------------------------------------------------
+    def open(self, file_id: int, size: int, advice: str = ADV_NORMAL, read_only: bool = True) -> None:
+        self.files[file_id] = FileState(size=size, advice=advice, read_only=read_only,
+                                        streams=[Stream() for _ in range(self.S)])
+
+    def npages(self, file_id: int) -> int:
+        return (self.files[file_id].size + self.P - 1) // self.P
+
+    def page_bytes(self, file_id: int, page: int) -> int:
+        return max(0, min(self.P, self.files[file_id].size - page * self.P))
+
+    # ---- readahead decision (one per miss) -----------------------------------------------
+    def ra_decide(self, file_id: int, p: int) -> Tuple[int, int]:
+        fs = self.files[file_id]
+        if self.cap == 0 or fs.advice == ADV_RANDOM or not fs.read_only:
+            return p, 1
+        fs.clock += 1
+        for s in fs.streams:                       # lowest slot index wins
+            if s.valid and s.next <= p < s.next + s.size:
+                ws = s.next
+                wn = min(2 * s.size, self.cap)
+                s.next = ws + wn
+                s.size = wn
+                s.last_use = fs.clock
+                return ws, wn
+        victim = None
+        for s in fs.streams:                       # an empty slot first (lowest index)
+            if not s.valid:
+                victim = s
+                break
+        if victim is None:                         # else least recently used, lowest index on ties
+            victim = min(fs.streams, key=lambda s: s.last_use)
+        wn = self.W0 if (p == 0 or fs.advice == ADV_SEQUENTIAL) else 1
+        wn = max(1, min(wn, self.cap))
+        victim.valid = True
+        victim.next = p + wn
+        victim.size = wn
+        victim.last_use = fs.clock
+        return p, wn
+
+    # ---- clock ----------------------------------------------------------------------------
+    def alloc(self) -> Optional[int]:
+        for _ in range(2 * self.C):
+            t = self.hand
+            self.hand += 1
+            f = t % self.C
+            fr = self.frames[f]
+            if fr.state == FREE:
+                self.events.append(("HAND", t, f, "FREE", -1, -1, 0))
+                return f
+            if fr.state == FILLING or fr.pins > 0:
+                self.events.append(("HAND", t, f, "SKIP", -1, -1, 0))
+                continue
+            if fr.ref:
+                fr.ref = 0
+                self.events.append(("HAND", t, f, "CLEAR", -1, -1, 0))
+                continue
+            # evict: unmap the old tag, reuse the frame in place
+            self.events.append(("HAND", t, f, "EVICT", fr.file, fr.page, fr.ra))
+            del self.map[(fr.file, fr.page)]
+            self.evictions += 1
+            if fr.ra:
+                self.wasted_pages += 1
+                self.wasted_bytes += self.page_bytes(fr.file, fr.page)
+            self.frames[f] = Frame()
+            return f
+        return None
+
+    # ---- one page access ------------------------------------------------------------------
+    def access(self, block: int, file_id: int, p: int) -> int:
+        """Serve page p of file_id for a block; returns the frame (pinned, then unpinned)."""
+        f = self.map.get((file_id, p))
+        if f is not None:
+            fr = self.frames[f]
+            fr.pins += 1
+            fr.ref = 1
+            fr.ra = 0
+            self.hits += 1
+            self.events.append(("HIT", block, file_id, p, f))
+            fr.pins -= 1
+            return f
+        self.misses += 1
+        ws, wn = self.ra_decide(file_id, p)
+        wn = min(wn, self.npages(file_id) - ws)
+        self.events.append(("MISS", block, file_id, p, ws, wn))
+        order = [p] + [q for q in range(ws, ws + wn) if q != p and (file_id, q) not in self.map]
+        allocated = []
+        for q in order:
+            g = self.alloc()
+            if g is None:
+                if q == p:
+                    raise RuntimeError("no frame for a demanded page: every frame pinned or filling")
+                self.events.append(("NOFRAME", block, file_id, q))
+                break
+            fr = self.frames[g]
+            fr.state = FILLING
+            fr.file, fr.page = file_id, q
+            fr.pins = 1 if q == p else 0
+            fr.ref = 0
+            fr.ra = 0 if q == p else 1
+            self.map[(file_id, q)] = g
+            self.events.append(("ALLOC", file_id, q, g, fr.ra))
+            allocated.append((q, g))
+            self.fetched_pages += 1
+            self.fetched_bytes += self.page_bytes(file_id, q)
+            if q != p:
+                self.ra_pages += 1
+        first = min(q for q, _ in allocated)
+        last = max(q for q, _ in allocated)
+        self.events.append(("REQ", file_id, first, last - first + 1))
+        self.requests += 1
+        self.request_bytes += sum(self.page_bytes(file_id, q) for q in range(first, last + 1))
+        # synchronous prefetch: the requester waits until the whole window is filled
+        for q, g in allocated:
+            fr = self.frames[g]
+            fr.state = VALID
+            fr.ref = 1
+        fp = self.map[(file_id, p)]
+        self.frames[fp].pins -= 1
+        return fp
+
+    # ---- one block-collective read ------------------------------------------------------------
+    def gread(self, block: int, file_id: int, offset: int, size: int) -> int:
+        """Split [offset, offset+size) into pages (ascending) and access each; returns bytes."""
+        fsize = self.files[file_id].size
+        if size <= 0 or offset >= fsize:
+            return 0
+        end = min(offset + size, fsize)
+        for p in range(offset // self.P, (end - 1) // self.P + 1):
+            self.access(block, file_id, p)
+        self.delivered_bytes += end - offset
+        return end - offset
+
+    # ---- end of run ---------------------------------------------------------------------------
+    def leftover_wasted(self) -> Tuple[int, int]:
+        """Prefetched pages still unconsumed in the cache: (pages, bytes)."""
+        pages = 0
+        nbytes = 0
+        for fr in self.frames:
+            if fr.state != FREE and fr.ra:
+                pages += 1
+                nbytes += self.page_bytes(fr.file, fr.page)
+        return pages, nbytes
+
+    def check_invariants(self) -> None:
+        seen = set()
+        for f, fr in enumerate(self.frames):
+            assert fr.pins >= 0
+            if fr.state == FREE:
+                continue
+            key = (fr.file, fr.page)
+            assert key not in seen, f"{key} mapped twice"
+            seen.add(key)
+            assert self.map.get(key) == f, f"map/frame disagree for {key}"
+        assert len(seen) == len(self.map)
+
+
+def run_serialized(model: PolicyModel, file_id: int, offsets, read_size: int) -> PolicyModel:
+    """Run every block's reads in (round, block) order: round k does read k of blocks 0..B-1."""
+    nb, K = offsets.shape
+    for k in range(K):
+        for b in range(nb):
+            model.gread(b, file_id, int(offsets[b, k]), read_size)
+    return model

@@ -1,0 +1,224 @@
+"""Pins for the policy half of the oracle (CPU only).
+
+Each test fixes the model against something other than itself:
+* the paper's worked readahead example (Sec. 3.2: a 4 KB read at offset 0 makes
+  the prefetcher fetch 16 KB) and the doubling-to-a-maximum rule (Sec. 2.3), in
+  closed form for a single stream;
+* textbook second-chance behaviour on a hand-worked reference string (it differs
+  from both FIFO and LRU there);
+* the paper's per-threadblock least-recently-allocated replacement (Sec. 5.1) for
+  a single read-once stream: same eviction order;
+* closed forms: cache >= file gives misses = distinct pages and no evictions;
+  a larger-than-cache strided stream gives misses = pages, evictions = pages - frames;
+  uniform random pages give a steady-state hit ratio of frames/pages;
+* brute force: every interleaving of tiny workloads, against an independently
+  written naive model, event for event;
+* invariants after every run.
+"""
+import itertools
+import random
+
+import numpy as np
+import pytest
+
+from oracle.lra import LRACache
+from oracle.naive import NaiveModel
+from oracle.policy import PolicyModel, run_serialized
+from workloads import configs
+
+
+def _misses(ev):
+    return [e for e in ev if e[0] == "MISS"]
+
+
+def _evicted(ev):
+    return [(e[4], e[5]) for e in ev if e[0] == "HAND" and e[3] == "EVICT"]
+
+
+def test_paper_example_first_window_is_16KB():
+    # Sec. 3.2: 4 KB read at offset 0 -> the prefetcher fetches 16 KB (W0 = 4 pages of 4 KiB).
+    m = PolicyModel(nframes=64, page_size=4096, ra_init_pages=4, ra_cap_pages=32)
+    m.open(0, 1 << 20)
+    m.gread(0, 0, 0, 4096)
+    req = [e for e in m.events if e[0] == "REQ"]
+    assert req == [("REQ", 0, 0, 4)]
+    assert m.request_bytes == 16 * 1024
+    # the next 4 KB read is served from the prefetched window
+    m.gread(0, 0, 4096, 4096)
+    assert m.events[-1][0] == "HIT"
+
+
+def test_single_stream_window_doubles_to_cap():
+    W0, cap, npages = 4, 16, 200
+    m = PolicyModel(nframes=512, page_size=1 << 16, ra_init_pages=W0, ra_cap_pages=cap)
+    m.open(0, npages << 16)
+    for p in range(npages):
+        m.gread(0, 0, p << 16, 1 << 16)
+    got = [(e[4], e[5]) for e in _misses(m.events)]
+    expect = []
+    ws, wn = 0, W0
+    while ws < npages:
+        expect.append((ws, min(wn, npages - ws)))
+        ws += wn
+        wn = min(2 * wn, cap)
+    assert got == expect
+    assert m.fetched_pages == npages and m.wasted_pages == 0
+    # closed-form request count: W0, 2W0, ... up to cap, then cap
+    assert m.requests == len(expect)
+
+
+def test_textbook_second_chance():
+    # hand-worked: 3 frames, RA off, reference string 0 1 2 0 3 1 4 5
+    # fills set the reference bit; the hit on page 1 saves it from the next sweep.
+    m = PolicyModel(nframes=3, page_size=1, ra_cap_pages=0)
+    m.open(0, 100)
+    for p in [0, 1, 2, 0, 3, 1, 4, 5]:
+        m.gread(0, 0, p, 1)
+    assert _evicted(m.events) == [(0, 0), (0, 2), (0, 1)]
+    hand = [(e[1], e[2], e[3]) for e in m.events if e[0] == "HAND"]
+    assert hand == [(0, 0, "FREE"), (1, 1, "FREE"), (2, 2, "FREE"),
+                    (3, 0, "CLEAR"), (4, 1, "CLEAR"), (5, 2, "CLEAR"), (6, 0, "EVICT"),
+                    (7, 1, "CLEAR"), (8, 2, "EVICT"),
+                    (9, 0, "CLEAR"), (10, 1, "EVICT")]
+    # FIFO would evict 0,1,2 and LRU would evict 1 first: second chance is neither
+    assert _evicted(m.events) != [(0, 0), (0, 1), (0, 2)]
+
+
+@pytest.mark.parametrize("nframes,npages", [(8, 40), (16, 16 * 5 + 3)])
+def test_single_reader_evicts_in_allocation_order_like_lra(nframes, npages):
+    m = PolicyModel(nframes=nframes, page_size=64, ra_cap_pages=0)
+    m.open(0, npages * 64)
+    lra = LRACache(nframes=nframes, resident_blocks=1, page_size=64)
+    for p in range(npages):
+        m.gread(0, 0, p * 64, 64)
+        lra.read_page(0, 0, p)
+    ev = _evicted(m.events)
+    assert ev == [(0, q) for q in range(npages - nframes)]
+    assert ev == lra.evicted
+    assert m.misses == npages == lra.misses
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_cache_holds_file_no_evictions_any_order(seed):
+    rng = random.Random(seed)
+    npages = 50
+    m = PolicyModel(nframes=64, page_size=1024, ra_cap_pages=0)
+    m.open(0, npages * 1024 - 100)
+    order = [rng.randrange(npages) for _ in range(400)]
+    for blk, p in enumerate(order):
+        m.gread(blk % 7, 0, p * 1024, 1024)
+    assert m.misses == len(set(order)) and m.evictions == 0
+    m.check_invariants()
+
+
+def test_strided_larger_than_cache_counts():
+    # C2 shape scaled down: 64 blocks, 128 KiB strides, 256 KiB pages, 32 MiB file, 8 MiB cache
+    wl = configs.c2_small()
+    C = wl.cache_bytes // wl.page_size
+    N = wl.file.size // wl.page_size
+    m = PolicyModel(nframes=C, page_size=wl.page_size, ra_cap_pages=0)
+    m.open(0, wl.file.size)
+    run_serialized(m, 0, wl.offsets, wl.read_size)
+    assert m.misses == N and m.evictions == N - C and m.fetched_pages == N
+    assert m.hits == N  # the second half of every page is a hit for the neighbouring block
+    m.check_invariants()
+
+
+def test_uniform_random_hit_ratio_is_frames_over_pages():
+    # independent reference model: any demand policy hits with probability C/N in steady state
+    C, N, n = 64, 256, 120_000
+    m = PolicyModel(nframes=C, page_size=1, ra_cap_pages=0)
+    m.open(0, N)
+    rng = np.random.default_rng(12345)
+    pages = rng.integers(0, N, size=n)
+    for i, p in enumerate(pages):
+        m.gread(i % 32, 0, int(p), 1)
+    warm = 10_000
+    # count hits among the accesses after warm-up
+    acc = [e for e in m.events if e[0] in ("HIT", "MISS")]
+    steady = acc[warm:]
+    ratio = sum(1 for e in steady if e[0] == "HIT") / len(steady)
+    assert abs(ratio - C / N) < 0.01, ratio
+    assert sum(1 for e in acc if e[0] == "HIT") == m.hits
+
+
+def test_readahead_accounting_identities():
+    wl = configs.c2_small()
+    C = wl.cache_bytes // wl.page_size
+    m = PolicyModel(nframes=C, page_size=wl.page_size, ra_init_pages=4, ra_cap_pages=16)
+    m.open(0, wl.file.size)
+    run_serialized(m, 0, wl.offsets, wl.read_size)
+    demand = m.misses
+    assert m.fetched_pages == demand + m.ra_pages
+    left, _ = m.leftover_wasted()
+    assert m.wasted_pages + left <= m.ra_pages
+    assert m.misses < wl.file.size // wl.page_size   # readahead removed most demand misses
+    m.check_invariants()
+
+
+def test_random_advice_disables_readahead():
+    m = PolicyModel(nframes=32, page_size=4096, ra_init_pages=4, ra_cap_pages=16)
+    m.open(0, 1 << 20, advice="random")
+    for p in range(10):
+        m.gread(0, 0, p * 4096, 4096)
+    assert [(e[4], e[5]) for e in _misses(m.events)] == [(p, 1) for p in range(10)]
+    m2 = PolicyModel(nframes=32, page_size=4096, ra_init_pages=4, ra_cap_pages=16)
+    m2.open(0, 1 << 20, advice="sequential")
+    m2.gread(0, 0, 5 * 4096, 4096)             # not at offset 0, but SEQUENTIAL opens at W0
+    assert _misses(m2.events)[0][4:] == (5, 4)
+
+
+def test_window_clamped_at_eof_and_partial_page():
+    m = PolicyModel(nframes=32, page_size=4096, ra_init_pages=4, ra_cap_pages=16)
+    m.open(0, 2 * 4096 + 10)                   # 3 pages, the last one 10 bytes
+    assert m.gread(0, 0, 0, 4096 * 8) == 2 * 4096 + 10
+    assert _misses(m.events) == [("MISS", 0, 0, 0, 0, 3)]
+    assert m.fetched_bytes == 2 * 4096 + 10
+    assert m.gread(0, 0, 3 * 4096, 10) == 0    # at/after EOF: nothing
+
+
+def _interleavings(seqs):
+    """Every merge of the per-block sequences that keeps each block's own order."""
+    counts = [len(s) for s in seqs]
+    labels = []
+    for b, c in enumerate(counts):
+        labels += [b] * c
+    seen = set()
+    for perm in itertools.permutations(labels):
+        if perm in seen:
+            continue
+        seen.add(perm)
+        yield perm
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_brute_force_against_naive_model(case):
+    rng = random.Random(1000 + case)
+    nblocks = 3 if case % 2 == 0 else 2
+    nacc = 3 if nblocks == 3 else 4
+    npages = rng.randint(4, 8)
+    nframes = rng.randint(2, 4)
+    w0 = rng.randint(1, 2)
+    cap = rng.choice([0, 2, 4])
+    psz = 8
+    fsize = npages * psz - rng.randint(0, 7)
+    seqs = [[(rng.randrange(npages), rng.choice([psz, 2 * psz])) for _ in range(nacc)] for _ in range(nblocks)]
+    outcomes = set()
+    n = 0
+    for order in _interleavings(seqs):
+        pos = [0] * nblocks
+        m = PolicyModel(nframes, psz, ra_init_pages=w0, ra_cap_pages=cap, streams_per_file=2)
+        m.open(0, fsize)
+        nv = NaiveModel(nframes, psz, w0, cap, 2)
+        nv.open(0, fsize)
+        for b in order:
+            page, size = seqs[b][pos[b]]
+            pos[b] += 1
+            r1 = m.gread(b, 0, page * psz, size)
+            r2 = nv.read(b, 0, page * psz, size)
+            assert r1 == r2
+        assert m.events == nv.log, (case, order)
+        m.check_invariants()
+        outcomes.add(tuple(_evicted(m.events)))
+        n += 1
+    assert n > 1 and len(outcomes) >= 1

@@ -1,0 +1,209 @@
+"""Synthetic workloads: files, cache geometry and per-block access lists.
+
+Shared by the oracle and by the GPU tests/benchmarks. Nothing here computes a
+page-cache, readahead or replacement decision; it only says which file bytes
+exist and which (offset, size) reads each threadblock issues, in order.
+
+Workload shapes (sizes are the ones the benchmark and parity tests use):
+
+* ``c1`` plain method, small: 64 MiB file (seed 1), 64 KiB pages, 256 MiB cache,
+  64 blocks x 256 threads; block b reads 64 KiB strides b, b+64, ... (16 reads);
+  per-block u64 checksum.
+* ``c2`` larger-than-cache stream: 8 GiB file (seed 2), 256 KiB pages, 2 GiB cache,
+  1024 blocks; block b reads 128 KiB strides b + 1024 k, k = 0..63; per-block
+  256-bin u32 byte histogram.
+* ``c3a/c3b/c3c`` access-pattern sweep on a 4 GiB file (seed 3), 64 KiB pages,
+  1 GiB cache, 1024 blocks x 256 threads: (a) block b reads its own 4 MiB chunk
+  in 64 reads of 64 KiB; (b) 64 KiB strides b + 1024 k; (c) 2**20 reads of whole
+  64 KiB pages, read i issued by block i mod 1024, page index = top 16 bits of
+  SplitMix64 output i+1 with seed 1000003. Per-block u64 checksum.
+
+Scaled-down variants (``*_small``) keep the pattern and the ratios that matter
+(file larger than cache, several tiles and a ragged tail) at sizes the oracle
+finishes in seconds.
+"""
+from __future__ import annotations
+
+import dataclasses
+import os
+import shutil
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+from . import splitmix
+
+KiB = 1 << 10
+MiB = 1 << 20
+GiB = 1 << 30
+
+CONSUMER_CHECKSUM = 0
+CONSUMER_HISTOGRAM = 1
+
+
+@dataclasses.dataclass(frozen=True)
+class FileSpec:
+    name: str
+    seed: int
+    size: int
+
+
+@dataclasses.dataclass
+class Workload:
+    """One launch of the strided/list reader: B blocks, K reads each, fixed read size."""
+    name: str
+    file: FileSpec
+    page_size: int
+    cache_bytes: int
+    blocks: int
+    threads: int
+    read_size: int
+    offsets: np.ndarray            # uint64 [blocks, K]: block b's k-th read offset
+    consumer: int                  # CONSUMER_CHECKSUM or CONSUMER_HISTOGRAM
+
+    @property
+    def reads_per_block(self) -> int:
+        return int(self.offsets.shape[1])
+
+    @property
+    def delivered_bytes(self) -> int:
+        """Bytes gread() delivers over the whole launch (EOF-clamped)."""
+        o = self.offsets.astype(np.int64)
+        end = np.minimum(o + self.read_size, self.file.size)
+        return int(np.maximum(end - o, 0).sum())
+
+
+def strided_offsets(blocks: int, reads: int, stride: int) -> np.ndarray:
+    """Block b's k-th read is stride number b + blocks*k."""
+    b = np.arange(blocks, dtype=np.uint64)[:, None]
+    k = np.arange(reads, dtype=np.uint64)[None, :]
+    return (b + np.uint64(blocks) * k) * np.uint64(stride)
+
+
+def chunked_offsets(blocks: int, reads: int, read_size: int) -> np.ndarray:
+    """Block b reads its own contiguous chunk of reads*read_size bytes, in order."""
+    b = np.arange(blocks, dtype=np.uint64)[:, None]
+    k = np.arange(reads, dtype=np.uint64)[None, :]
+    return (b * np.uint64(reads) + k) * np.uint64(read_size)
+
+
+def random_page_offsets(blocks: int, nreads: int, npages_log2: int, page: int, seed: int) -> np.ndarray:
+    """Read i goes to block i mod blocks; its page is the top npages_log2 bits of output i+1."""
+    if nreads % blocks:
+        raise ValueError("nreads must be a multiple of blocks")
+    x = splitmix.outputs(seed, 1, nreads)
+    pages = x >> np.uint64(64 - npages_log2)
+    # read i -> block i % blocks, position i // blocks
+    return (pages * np.uint64(page)).reshape(nreads // blocks, blocks).T.copy()
+
+
+def c1() -> Workload:
+    f = FileSpec("c1_seed1_64MiB.bin", 1, 64 * MiB)
+    return Workload("c1", f, 64 * KiB, 256 * MiB, 64, 256, 64 * KiB,
+                    strided_offsets(64, 16, 64 * KiB), CONSUMER_CHECKSUM)
+
+
+def c2() -> Workload:
+    f = FileSpec("c2_seed2_8GiB.bin", 2, 8 * GiB)
+    return Workload("c2", f, 256 * KiB, 2 * GiB, 1024, 256, 128 * KiB,
+                    strided_offsets(1024, 64, 128 * KiB), CONSUMER_HISTOGRAM)
+
+
+def _c3_file() -> FileSpec:
+    return FileSpec("c3_seed3_4GiB.bin", 3, 4 * GiB)
+
+
+def c3(pattern: str) -> Workload:
+    f = _c3_file()
+    if pattern == "a":
+        off = chunked_offsets(1024, 64, 64 * KiB)
+    elif pattern == "b":
+        off = strided_offsets(1024, 64, 64 * KiB)
+    elif pattern == "c":
+        off = random_page_offsets(1024, 1 << 20, 16, 64 * KiB, 1000003)
+    else:
+        raise ValueError(pattern)
+    return Workload("c3" + pattern, f, 64 * KiB, 1 * GiB, 1024, 256, 64 * KiB, off, CONSUMER_CHECKSUM)
+
+
+# ---- scaled-down variants the oracle finishes in seconds --------------------------------
+
+def c1_small() -> Workload:
+    """C1 shape with a ragged tail: the file ends 24 KiB + 8 B into its last page."""
+    size = 3 * MiB + 24 * KiB + 8
+    f = FileSpec("c1s_seed1.bin", 1, size)
+    stride = 64 * KiB
+    nstrides = (size + stride - 1) // stride     # 49 strides, the last one partial
+    blocks = 8
+    reads = (nstrides + blocks - 1) // blocks    # 7 reads; some land at/after EOF
+    return Workload("c1_small", f, 64 * KiB, 16 * MiB, blocks, 256, stride,
+                    strided_offsets(blocks, reads, stride), CONSUMER_CHECKSUM)
+
+
+def c2_small() -> Workload:
+    """C2 shape at 1/256 scale: 32 MiB file through an 8 MiB cache, histograms."""
+    f = FileSpec("c2s_seed2.bin", 2, 32 * MiB)
+    return Workload("c2_small", f, 256 * KiB, 8 * MiB, 64, 256, 128 * KiB,
+                    strided_offsets(64, 4, 128 * KiB), CONSUMER_HISTOGRAM)
+
+
+def c3_small(pattern: str) -> Workload:
+    f = FileSpec("c3s_seed3.bin", 3, 16 * MiB)
+    blocks = 32
+    if pattern == "a":
+        off = chunked_offsets(blocks, 8, 64 * KiB)
+    elif pattern == "b":
+        off = strided_offsets(blocks, 8, 64 * KiB)
+    elif pattern == "c":
+        off = random_page_offsets(blocks, 32 * 64, 8, 64 * KiB, 1000003)
+    else:
+        raise ValueError(pattern)
+    return Workload("c3" + pattern + "_small", f, 64 * KiB, 4 * MiB, blocks, 256, 64 * KiB, off, CONSUMER_CHECKSUM)
+
+
+REGISTRY = {
+    "c1": c1, "c2": c2,
+    "c3a": lambda: c3("a"), "c3b": lambda: c3("b"), "c3c": lambda: c3("c"),
+    "c1_small": c1_small, "c2_small": c2_small,
+    "c3a_small": lambda: c3_small("a"), "c3b_small": lambda: c3_small("b"),
+    "c3c_small": lambda: c3_small("c"),
+}
+
+
+def get(name: str) -> Workload:
+    return REGISTRY[name]()
+
+
+# ---- files on disk ----------------------------------------------------------------------
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_GEN_SRC = os.path.join(_HERE, "genfile.c")
+_GEN_BIN = os.path.join(_HERE, "genfile")
+
+
+def data_dir() -> str:
+    d = os.environ.get("GFS_DATA_DIR") or os.path.join(os.path.dirname(_HERE), "_data")
+    os.makedirs(d, exist_ok=True)
+    return d
+
+
+def build_generator(force: bool = False) -> str:
+    """Compile the C file writer with gcc (a build step; no method code inside)."""
+    if force or not os.path.exists(_GEN_BIN) or os.path.getmtime(_GEN_BIN) < os.path.getmtime(_GEN_SRC):
+        cc = shutil.which("gcc") or shutil.which("cc")
+        if not cc:
+            raise RuntimeError("no C compiler to build workloads/genfile")
+        subprocess.check_call([cc, "-O2", "-o", _GEN_BIN, _GEN_SRC, "-lpthread"])
+    return _GEN_BIN
+
+
+def ensure_file(spec: FileSpec, directory: Optional[str] = None, threads: int = 8) -> str:
+    """Create the SplitMix64 file if it is missing or has the wrong size; return its path."""
+    d = directory or data_dir()
+    path = os.path.join(d, spec.name)
+    if os.path.exists(path) and os.path.getsize(path) == spec.size:
+        return path
+    gen = build_generator()
+    subprocess.check_call([gen, path, str(spec.seed), str(spec.size), str(threads)])
+    return path
