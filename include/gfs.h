@@ -1,0 +1,200 @@
+/* gfs.h -- host C-ABI of the GPU-resident file page cache with readahead.
+ *
+ * The operation (Sec. 2.2 of the paper, "GPUfs"): GPU threadblocks read files
+ * through a POSIX-like call made by every thread of the block; the library keeps
+ * a page cache in GPU memory, serves hits from it, and forwards misses to host
+ * threads that read the file and hand the data to the GPU. Sec. 4 adds a GPU-side
+ * readahead prefetcher (a miss asks the host for the page plus a prefetch
+ * window), enabled for read-only files and switchable off by an fadvise-style
+ * hint; Sec. 5 adds a replacement mechanism that reuses frames in place so files
+ * larger than the cache stream through.
+ *
+ * This header is the host side: create a cache over caller-owned device memory,
+ * register files, read statistics and the event trace, reset, shut down. The
+ * device side (gopen/gread/gclose, called from HIP kernels) is in gfs_device.h.
+ * Workload launchers used by the benchmarks and tests are declared at the end.
+ *
+ * Conventions for every function returning int: 0 on success or a negative errno
+ * value; out-parameters are left untouched on error. All pointers are plain host
+ * or device addresses as stated per argument; no call takes ownership of caller
+ * memory unless stated. Host calls on one context are not thread-safe with each
+ * other, except gfs_stats.
+ */
+#ifndef GFS_H
+#define GFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GFS_ABI_VERSION 1u
+
+/* limits of the encoding (page-table entry = file:11 | page:28 | frame:24 bits) */
+#define GFS_MAX_FILES 1024u
+#define GFS_MAX_PAGES_PER_FILE (1u << 28)
+#define GFS_MAX_FRAMES (1u << 24)
+#define GFS_MAX_STREAMS 8u
+#define GFS_MAX_WINDOW_PAGES 1024u   /* readahead cap, in pages */
+
+/* open flags and fadvise advice */
+#define GFS_O_RDONLY 0
+#define GFS_ADV_NORMAL 0
+#define GFS_ADV_SEQUENTIAL 2
+#define GFS_ADV_RANDOM 1
+
+/* host read backends */
+#define GFS_IO_PREAD 0
+
+/* o_direct modes */
+#define GFS_DIRECT_OFF 0      /* buffered reads */
+#define GFS_DIRECT_ON 1       /* O_DIRECT; gfs_open fails if the file system refuses it */
+#define GFS_DIRECT_PREFER 2   /* O_DIRECT where the file system supports it, else buffered */
+
+typedef struct gfs_config {
+  uint32_t abi_version;          /* must be GFS_ABI_VERSION */
+  uint32_t streams_per_file;     /* readahead streams tracked per file, 1..GFS_MAX_STREAMS */
+  uint64_t page_size;            /* bytes; power of two, 4 KiB .. 2 MiB */
+  uint64_t cache_bytes;          /* bytes of frames; a multiple of page_size, >= 64 pages */
+  uint64_t ra_init_bytes;        /* first window of a stream at offset 0 or SEQUENTIAL advice */
+  uint64_t ra_cap_bytes;         /* largest window; 0 switches readahead off (demand paging) */
+  uint32_t host_threads;         /* host I/O threads polling the request ring, 1..64 */
+  uint32_t rpc_slots;            /* request ring slots (each has its own staging buffer), 1..4096 */
+  uint32_t io_backend;           /* GFS_IO_PREAD */
+  uint32_t o_direct;             /* GFS_DIRECT_* */
+  uint32_t trace_level;          /* 0 off, 1 policy events, 2 also hits/joins */
+  uint32_t trace_capacity;       /* events kept in the device trace ring (32 B each) */
+  uint64_t wait_timeout_ns;      /* device waits give up with -ETIMEDOUT after this long; 0 = 10 s */
+} gfs_config;
+
+/* Fill *cfg with defaults: 64 KiB pages, 256 MiB cache, readahead 4 pages growing to
+ * 16 MiB, 8 streams per file, 8 host threads, 64 slots, O_DIRECT preferred, trace off. */
+void gfs_config_default(gfs_config* cfg);
+
+typedef struct gfs_ctx gfs_ctx;
+struct gfs_dev;
+
+/* Device memory the caller must provide for a configuration: the frame pool
+ * (cache_bytes, 256-byte aligned) and the metadata region (page table, frame words,
+ * tags, per-file state, counters, trace ring). -EINVAL if the configuration is invalid. */
+int gfs_device_bytes(const gfs_config* cfg, size_t* frames_bytes, size_t* meta_bytes);
+
+/* Create a cache. frames_dev and meta_dev are device pointers (e.g. from PyTorch) of at
+ * least the sizes gfs_device_bytes reports; they stay owned by the caller and must
+ * outlive the context. hip_stream is the hipStream_t the library uses for its own
+ * set-up work (may be NULL for the null stream). The call initialises the metadata,
+ * allocates the pinned request ring and staging buffers, and starts the host I/O
+ * threads. Errors: -EINVAL (bad config/pointers), -ENOMEM (pinned memory), -EIO (HIP). */
+int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_stream,
+             gfs_ctx** out);
+
+/* Register a file for device reads. flags must be GFS_O_RDONLY (the paper enables
+ * prefetching only for read-only files; there is no write path): anything else gives
+ * -EROFS. The path is copied. *file_id receives the id that gopen resolves the same
+ * path to, and that the workload launchers take. Must not run concurrently with
+ * kernels using the context. Errors: -ENFILE (table full), -errno from open/fstat,
+ * -EFBIG (more pages than the encoding holds). */
+int gfs_open(gfs_ctx* ctx, const char* path, int flags, int* file_id);
+
+/* Readahead hint for a registered file (Sec. 4, runtime hints like posix_fadvise):
+ * GFS_ADV_RANDOM switches readahead off for it, GFS_ADV_SEQUENTIAL opens every new
+ * stream with the initial window, GFS_ADV_NORMAL restores the default. */
+int gfs_fadvise(gfs_ctx* ctx, int file_id, int advice);
+
+/* Unregister a file. -EBUSY if a kernel still holds it open (gopen without gclose);
+ * cached pages of the file stay until they are evicted or the cache is reset. */
+int gfs_close(gfs_ctx* ctx, int file_id);
+
+/* Device pointer to the cache handle; pass it to kernels that call gread. */
+const struct gfs_dev* gfs_device_handle(gfs_ctx* ctx);
+
+typedef struct gfs_stats {
+  /* device counters */
+  uint64_t hits;              /* page lookups served from a valid frame */
+  uint64_t joins;             /* page lookups that waited for a frame being filled */
+  uint64_t misses;            /* page lookups that issued a host request */
+  uint64_t ra_pages;          /* pages fetched ahead of demand */
+  uint64_t fetched_pages;     /* pages filled from the host (demand + readahead) */
+  uint64_t evictions;         /* frames reused for another page */
+  uint64_t wasted_pages;      /* prefetched pages evicted before any demand access */
+  uint64_t hand_visits;       /* clock hand steps */
+  uint64_t requests;          /* host requests posted */
+  uint64_t request_bytes;     /* bytes asked of the host (span of each request) */
+  uint64_t delivered_bytes;   /* bytes gread copied to user buffers */
+  uint64_t retries;           /* lookups retried after a lost race */
+  uint64_t noframe;           /* allocations that found every frame pinned or filling */
+  uint64_t timeouts;          /* device waits that gave up */
+  uint64_t io_errors;         /* host reads that failed or came back short */
+  uint64_t trace_events;      /* events recorded (including dropped ones) */
+  /* host counters */
+  uint64_t host_requests;     /* requests served by the host threads */
+  uint64_t host_bytes;        /* bytes the host read from files */
+  uint64_t host_read_ns;      /* summed time inside pread */
+  uint64_t host_spins[64];    /* per host thread: polls of the ring before its first request */
+  uint32_t host_threads;
+  uint32_t direct_io;         /* 1 if the last gfs_open used O_DIRECT */
+} gfs_stats;
+
+/* Snapshot the counters. Call when no kernel using the context is running. */
+int gfs_stats_read(gfs_ctx* ctx, gfs_stats* out);
+
+/* Trace record (32 bytes), written by device code when trace_level > 0. */
+typedef struct gfs_event {
+  uint32_t op;      /* GFS_EV_* */
+  uint32_t block;   /* flattened blockIdx of the caller */
+  uint32_t file;
+  uint32_t page;
+  uint32_t frame;   /* 0xffffffff when not applicable */
+  uint32_t a;       /* op-specific: window length, hand action, ra bit, ... */
+  uint64_t b;       /* op-specific: window start, hand ticket, request ticket, ... */
+} gfs_event;
+
+enum {
+  GFS_EV_HIT = 1,    /* file,page,frame                                         */
+  GFS_EV_JOIN = 2,   /* file,page,frame                                         */
+  GFS_EV_MISS = 3,   /* file,page; a = window length (EOF-clamped), b = window start */
+  GFS_EV_HAND = 4,   /* frame; b = ticket; a = action | ra<<8; file,page = victim (EVICT) */
+  GFS_EV_ALLOC = 5,  /* file,page,frame; a = ra (1 if prefetched)               */
+  GFS_EV_REQ = 6,    /* file, page = first page, a = pages in span, b = ring ticket */
+  GFS_EV_NOFRAME = 7 /* file,page: window cut short, no frame left              */
+};
+enum { GFS_HAND_FREE = 0, GFS_HAND_SKIP = 1, GFS_HAND_CLEAR = 2, GFS_HAND_EVICT = 3 };
+
+/* Copy up to cap_bytes of recorded events (in record order) to host memory dst;
+ * *n_bytes receives the bytes copied. Call when no kernel using the context runs. */
+int gfs_trace_read(gfs_ctx* ctx, void* dst, size_t cap_bytes, size_t* n_bytes);
+
+/* Drop every cached page, readahead stream, counter and trace record (cold start).
+ * Registered files stay registered. Call when no kernel using the context runs. */
+int gfs_reset_cache(gfs_ctx* ctx);
+
+/* Stop the host threads, free the ring and staging, close files, free the context.
+ * Kernels using the handle must have completed. */
+int gfs_shutdown(gfs_ctx* ctx);
+
+/* ---- workload launchers (the benchmark consumers of gread; not part of the method) ----
+ *
+ * gfs_launch_list_reader: one kernel of `blocks` threadblocks x `threads` threads
+ * (a multiple of 64, <= 1024). Block b calls gread(file, offsets[b*reads + k],
+ * read_size, buf + b*read_size) for k = 0..reads-1 in order and folds every delivered
+ * buffer into its consumer output:
+ *   consumer 0 (checksum): out is uint64[blocks]; wrapping sum of the delivered
+ *     little-endian uint32 words, a trailing partial word zero-padded;
+ *   consumer 1 (histogram): out is uint32[blocks*256]; count of each byte value.
+ * status (int64[blocks]) receives the total bytes delivered to the block, or the first
+ * negative errno gread returned. turn, if not NULL, serialises the reads: read k of
+ * block b waits until *turn == k*blocks + b and then increments it (test-only; every
+ * block must be resident at once). All pointers are device pointers; the kernel is
+ * enqueued on hip_stream and the call returns without waiting. -EINVAL on bad shapes. */
+int gfs_launch_list_reader(gfs_ctx* ctx, int file_id, const uint64_t* offsets, uint32_t blocks,
+                           uint32_t reads, uint64_t read_size, uint32_t threads, int consumer,
+                           void* buf, void* out, int64_t* status, uint64_t* turn,
+                           void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GFS_H */

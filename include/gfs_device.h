@@ -1,0 +1,826 @@
+/* gfs_device.h -- device side of the GPU file page cache: gopen / gread / gclose.
+ *
+ * Include from HIP code compiled for gfx950. The functions are block-collective
+ * (Sec. 2.2: each threadblock issues a file call by invoking it from all of its
+ * threads): every thread of the block must call them with the same arguments, and
+ * every thread gets the same result. Blocks must have a multiple of 64 threads.
+ *
+ *   int     gopen (const gfs_dev* d, const char* path, int flags);
+ *       Resolve a path registered with gfs_open (path: NUL-terminated, device-readable
+ *       memory) to a descriptor. flags must be GFS_O_RDONLY (-EROFS otherwise); an
+ *       unknown path gives -ENOENT.
+ *   int     gopen_id(const gfs_dev* d, int file_id, int flags);
+ *       Same, from the id gfs_open returned.
+ *   int64_t gread (const gfs_dev* d, int fd, uint64_t offset, uint64_t size, void* dst);
+ *       Copy file bytes [offset, min(offset+size, file size)) to dst (device memory of
+ *       at least that many bytes; 16-byte alignment of dst and offset takes the vector
+ *       path). Returns the byte count (short only at EOF, 0 at or past it) or -EBADF,
+ *       -EINVAL, -EIO (host read failed), -ENOSPC (page table full), -ETIMEDOUT (a wait
+ *       exceeded the configured timeout; the cache must then be reset).
+ *   int     gclose(const gfs_dev* d, int fd);
+ *
+ * How a read is served (Sec. 2.2 and Sec. 4.1): the request is divided into pages; each
+ * page is looked up in the hashed page table and, on a hit, pinned and copied out. On a
+ * miss the block takes the file's miss lock, asks the readahead detector for a window,
+ * allocates frames for the window's unmapped pages with the clock hand (evicting in place,
+ * Sec. 5.1), posts one request for the span to the host ring and waits for it
+ * (synchronous prefetch, Sec. 4), pulls the fetched bytes from pinned staging into the
+ * frames, publishes them, and copies its own page out. Blocks that find a page whose
+ * frame is still being filled wait for it instead of fetching it again.
+ */
+#ifndef GFS_DEVICE_H
+#define GFS_DEVICE_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gfs.h"
+#include "gfs_layout.h"
+
+namespace gfsd {
+
+constexpr int kENOENT = 2, kEIO = 5, kEBADF = 9, kEINVAL = 22, kENOSPC = 28, kEROFS = 30,
+              kETIMEDOUT = 110;
+constexpr uint32_t kMaxWindow = GFS_MAX_WINDOW_PAGES;
+constexpr uint64_t kFrameMask = (1ull << GFS_ENTRY_FRAME_BITS) - 1;
+
+/* Per-block scratch for one page access (LDS). */
+struct ReadShared {
+  int64_t status;           /* 0 or -errno for the current page */
+  int64_t result;           /* host read result for the request this block pulls */
+  uint64_t first_page;      /* first page of the request span */
+  uint64_t gen;             /* ring generation of the request */
+  int32_t frame;            /* pinned frame of the current page */
+  int32_t pull;             /* 1: this block must pull its request into the frames */
+  uint32_t slot;            /* ring slot of the request */
+  uint32_t list_n;          /* pages in list[] */
+  uint32_t file;
+  uint32_t pad;
+  uint32_t list[kMaxWindow];    /* window pages to allocate: the demanded page, then ascending */
+  uint32_t lframe[kMaxWindow];  /* frame given to list[k], or GFS_NO_FRAME */
+};
+
+/* ------------------------------------------------------------------ thread / wave ids */
+__device__ __forceinline__ uint32_t thread_id() {
+  return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+}
+__device__ __forceinline__ uint32_t block_threads() { return blockDim.x * blockDim.y * blockDim.z; }
+__device__ __forceinline__ uint32_t block_id() {
+  return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+__device__ __forceinline__ uint32_t lane() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const uint32_t l = __lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+/* ------------------------------------------------------------------ atomics (agent scope) */
+__device__ __forceinline__ uint64_t ld_rlx(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_acq(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_rlx32(uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rlx(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rlx32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas64(uint64_t* p, uint64_t& expected, uint64_t desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL,
+                                              __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas32(uint32_t* p, uint32_t& expected, uint32_t desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL,
+                                              __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t fadd64(uint64_t* p, uint64_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void count(const gfs_dev* d, int c, uint64_t v) {
+  if (v) fadd64(&d->g->ctr[c], v);
+}
+
+/* ------------------------------------------------------------------ waiting */
+__device__ __forceinline__ void nap(uint32_t& n) {
+  if (n < 8) __builtin_amdgcn_s_sleep(2);
+  else if (n < 64) __builtin_amdgcn_s_sleep(16);
+  else __builtin_amdgcn_s_sleep(127);
+  ++n;
+}
+__device__ __forceinline__ bool expired(const gfs_dev* d, uint64_t t0) {
+  return wall_clock64() - t0 > d->timeout_ticks;
+}
+
+/* ------------------------------------------------------------------ trace */
+__device__ __forceinline__ void trace_ev(const gfs_dev* d, uint32_t level, uint32_t op,
+                                         uint32_t block, uint32_t file, uint32_t page,
+                                         uint32_t frame, uint32_t a, uint64_t b) {
+  if (d->trace_level < level) return;
+  const uint64_t i = fadd64(&d->g->trace_n, 1);
+  if (i >= d->trace_cap) return;
+  gfs_event* e = ((gfs_event*)d->trace) + i;
+  e->op = op;
+  e->block = block;
+  e->file = file;
+  e->page = page;
+  e->frame = frame;
+  e->a = a;
+  e->b = b;
+}
+
+/* ------------------------------------------------------------------ hashed page table
+ * Two candidate buckets of 16 entries (128 B) per key; an entry is key<<24 | frame and is
+ * written and cleared only by compare-and-swap. Lookups take no lock. Inserts of a file's
+ * keys happen under that file's miss lock, so one key is never inserted twice; clearing
+ * is done by the evictor that claimed the frame. */
+__device__ __forceinline__ uint64_t page_key(uint32_t file, uint64_t page) {
+  return ((uint64_t)(file + 1) << GFS_KEY_PAGE_BITS) | page;
+}
+__device__ __forceinline__ uint64_t key_hash(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+__device__ __forceinline__ void key_buckets(const gfs_dev* d, uint64_t key, uint32_t& b1,
+                                            uint32_t& b2) {
+  const uint64_t h = key_hash(key);
+  b1 = (uint32_t)h & d->nbuckets_mask;
+  b2 = (uint32_t)(h >> 32) & d->nbuckets_mask;
+  if (b2 == b1) b2 = b1 ^ 1u;
+}
+
+/* wave-collective: lanes 0-15 read bucket 1, lanes 16-31 bucket 2; uniform result */
+__device__ int32_t pt_lookup_wave(const gfs_dev* d, uint64_t key) {
+  uint32_t b1, b2;
+  key_buckets(d, key, b1, b2);
+  const uint32_t l = lane();
+  uint64_t e = 0;
+  if (l < 32) e = ld_rlx(&d->pt[(uint64_t)(l < 16 ? b1 : b2) * GFS_BUCKET_SLOTS + (l & 15)]);
+  const uint64_t m = __ballot(l < 32 && (e >> GFS_ENTRY_FRAME_BITS) == key);
+  if (m == 0) return -1;
+  const uint64_t hit = __shfl(e, __ffsll((unsigned long long)m) - 1, 64);
+  return (int32_t)(hit & kFrameMask);
+}
+
+/* per lane */
+__device__ int32_t pt_find_lane(const gfs_dev* d, uint64_t key) {
+  uint32_t b[2];
+  key_buckets(d, key, b[0], b[1]);
+  for (int j = 0; j < 2; ++j) {
+    uint64_t* bk = d->pt + (uint64_t)b[j] * GFS_BUCKET_SLOTS;
+    uint64_t e[GFS_BUCKET_SLOTS];
+#pragma unroll
+    for (int i = 0; i < GFS_BUCKET_SLOTS; ++i) e[i] = ld_rlx(&bk[i]);
+#pragma unroll
+    for (int i = 0; i < GFS_BUCKET_SLOTS; ++i)
+      if ((e[i] >> GFS_ENTRY_FRAME_BITS) == key) return (int32_t)(e[i] & kFrameMask);
+  }
+  return -1;
+}
+
+__device__ bool pt_insert_lane(const gfs_dev* d, uint64_t key, uint32_t frame) {
+  const uint64_t ent = (key << GFS_ENTRY_FRAME_BITS) | frame;
+  uint32_t b[2];
+  key_buckets(d, key, b[0], b[1]);
+  for (int attempt = 0; attempt < 256; ++attempt) {
+    int cnt[2] = {0, 0}, first[2] = {-1, -1};
+    for (int j = 0; j < 2; ++j) {
+      uint64_t* bk = d->pt + (uint64_t)b[j] * GFS_BUCKET_SLOTS;
+      uint64_t e[GFS_BUCKET_SLOTS];
+#pragma unroll
+      for (int i = 0; i < GFS_BUCKET_SLOTS; ++i) e[i] = ld_rlx(&bk[i]);
+#pragma unroll
+      for (int i = 0; i < GFS_BUCKET_SLOTS; ++i) {
+        if (e[i] != 0) ++cnt[j];
+        else if (first[j] < 0) first[j] = i;
+      }
+    }
+    int j = cnt[1] < cnt[0] ? 1 : 0;   /* less loaded bucket, ties to the first */
+    if (first[j] < 0) j ^= 1;
+    if (first[j] < 0) return false;
+    uint64_t expect = 0;
+    if (cas64(&d->pt[(uint64_t)b[j] * GFS_BUCKET_SLOTS + first[j]], expect, ent)) return true;
+  }
+  return false;
+}
+
+__device__ bool pt_delete_lane(const gfs_dev* d, uint64_t key, uint32_t frame) {
+  const uint64_t ent = (key << GFS_ENTRY_FRAME_BITS) | frame;
+  uint32_t b[2];
+  key_buckets(d, key, b[0], b[1]);
+  for (int j = 0; j < 2; ++j) {
+    uint64_t* bk = d->pt + (uint64_t)b[j] * GFS_BUCKET_SLOTS;
+    for (int i = 0; i < GFS_BUCKET_SLOTS; ++i) {
+      uint64_t e = ld_rlx(&bk[i]);
+      if (e == ent && cas64(&bk[i], e, 0ull)) return true;
+    }
+  }
+  return false;
+}
+
+/* ------------------------------------------------------------------ frame words */
+enum { PIN_RETRY = 0, PIN_VALID = 1, PIN_FILLING = 2 };
+
+__device__ void frame_unpin(const gfs_dev* d, uint32_t f) {
+  uint64_t* fw = &d->fword[f];
+  uint64_t w = ld_rlx(fw);
+  while (!cas64(fw, w, w - GFS_FW_PIN_ONE + GFS_FW_VER_ONE)) {
+  }
+}
+
+/* Pin frame f if it is filling or valid and still holds key; sets the reference bit and
+ * clears the prefetched mark (the page has now been demanded). */
+__device__ int frame_pin(const gfs_dev* d, uint32_t f, uint64_t key) {
+  uint64_t* fw = &d->fword[f];
+  uint64_t w = ld_rlx(fw);
+  for (int i = 0; i < 64; ++i) {
+    const uint64_t st = w & GFS_FW_STATE;
+    if (st != GFS_FS_FILLING && st != GFS_FS_VALID) return PIN_RETRY;
+    if ((w & GFS_FW_PINS) == GFS_FW_PINS) return PIN_RETRY;
+    const uint64_t nw = ((w + GFS_FW_PIN_ONE + GFS_FW_VER_ONE) | GFS_FW_REF) & ~GFS_FW_RA;
+    if (cas64(fw, w, nw)) {
+      if (ld_acq(&d->ftag[f]) != key) {
+        frame_unpin(d, f);
+        return PIN_RETRY;
+      }
+      return st == GFS_FS_VALID ? PIN_VALID : PIN_FILLING;
+    }
+  }
+  return PIN_RETRY;
+}
+
+/* One clock step at frame f (per lane). FREE or EVICT leave the frame CLAIMED by the
+ * caller; EVICT reports the victim's key and prefetched mark. */
+__device__ int hand_visit(const gfs_dev* d, uint32_t f, uint64_t& vkey, uint32_t& vra) {
+  uint64_t* fw = &d->fword[f];
+  uint64_t w = ld_rlx(fw);
+  const uint64_t st = w & GFS_FW_STATE;
+  const uint64_t claimed = (((w >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT) | GFS_FS_CLAIMED;
+  if (st == GFS_FS_FREE) return cas64(fw, w, claimed) ? GFS_HAND_FREE : GFS_HAND_SKIP;
+  if (st != GFS_FS_VALID || (w & GFS_FW_PINS)) return GFS_HAND_SKIP;
+  if (w & GFS_FW_REF)
+    return cas64(fw, w, (w & ~GFS_FW_REF) + GFS_FW_VER_ONE) ? GFS_HAND_CLEAR : GFS_HAND_SKIP;
+  const uint64_t old = w;
+  if (!cas64(fw, w, claimed)) return GFS_HAND_SKIP;
+  vkey = ld_rlx(&d->ftag[f]);
+  vra = (old & GFS_FW_RA) ? 1u : 0u;
+  return GFS_HAND_EVICT;
+}
+
+/* Wait (lane) until the pinned frame f is VALID. 0, -EIO or -ETIMEDOUT (pin dropped on error). */
+__device__ int64_t wait_valid_lane(const gfs_dev* d, uint32_t f, uint64_t t0) {
+  uint32_t n = 0;
+  while (true) {
+    const uint64_t w = ld_acq(&d->fword[f]);
+    if ((w & GFS_FW_STATE) == GFS_FS_VALID) {
+      if (w & GFS_FW_ERR) {
+        frame_unpin(d, f);
+        return -kEIO;
+      }
+      return 0;
+    }
+    if (expired(d, t0)) {
+      frame_unpin(d, f);
+      count(d, GFS_C_TIMEOUTS, 1);
+      return -kETIMEDOUT;
+    }
+    nap(n);
+  }
+}
+
+/* ------------------------------------------------------------------ per-file miss lock */
+__device__ bool lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t t0) {
+  uint32_t* lk = &d->files[file].lock;
+  int ok = 0;
+  if (lane() == 0) {
+    uint32_t n = 0;
+    while (true) {
+      uint32_t e = 0;
+      if (ld_rlx32(lk) == 0 && cas32(lk, e, 1u)) {
+        ok = 1;
+        break;
+      }
+      if (expired(d, t0)) break;
+      nap(n);
+    }
+  }
+  ok = __shfl(ok, 0, 64);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok != 0;
+}
+__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (lane() == 0)
+    __hip_atomic_store(&d->files[file].lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+/* ------------------------------------------------------------------ readahead detector
+ * Wave-collective, under the file's miss lock. Streams live in the file record; lane i
+ * looks at stream slot i. Sec. 2.3 (Linux readahead: per-descriptor sequential streams,
+ * window doubled up to a maximum) and Sec. 4 (GPU-side window, RANDOM hint disables it). */
+__device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint64_t& ws,
+                               uint32_t& wn) {
+  gfs_file_dev* fe = &d->files[file];
+  const uint32_t advice = ld_rlx32(&fe->advice);
+  ws = p;
+  wn = 1;
+  if (d->ra_cap == 0 || advice == GFS_ADV_RANDOM) return;
+  const uint32_t l = lane();
+  uint32_t clk = 0;
+  if (l == 0) {
+    clk = ld_rlx32(&fe->clock) + 1;
+    st_rlx32(&fe->clock, clk);
+  }
+  clk = __shfl(clk, 0, 64);
+  uint64_t s_next = 0;
+  uint32_t s_size = 0, s_last = 0, s_valid = 0;
+  if (l < d->streams) {
+    gfs_stream* s = &fe->streams[l];
+    s_next = ld_rlx(&s->next);
+    s_size = ld_rlx32(&s->size);
+    s_last = ld_rlx32(&s->last_use);
+    s_valid = ld_rlx32(&s->valid);
+  }
+  const bool cov = l < d->streams && s_valid && s_next <= p && p < s_next + s_size;
+  const uint64_t cm = __ballot(cov);
+  int j;
+  uint64_t new_next;
+  uint32_t new_size;
+  if (cm) {
+    j = __ffsll((unsigned long long)cm) - 1;
+    const uint64_t nx = __shfl(s_next, j, 64);
+    const uint32_t sz = __shfl(s_size, j, 64);
+    ws = nx;
+    wn = 2 * sz < d->ra_cap ? 2 * sz : d->ra_cap;
+    new_next = ws + wn;
+    new_size = wn;
+  } else {
+    const uint64_t inv = __ballot(l < d->streams && !s_valid);
+    if (inv) {
+      j = __ffsll((unsigned long long)inv) - 1;
+    } else {
+      uint64_t k = l < d->streams ? (((uint64_t)s_last << 8) | l) : ~0ull;
+      for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(k, off, 64);
+        k = o < k ? o : k;
+      }
+      j = (int)(k & 0xff);
+    }
+    uint32_t w0 = (p == 0 || advice == GFS_ADV_SEQUENTIAL) ? d->ra_init : 1u;
+    if (w0 > d->ra_cap) w0 = d->ra_cap;
+    if (w0 < 1) w0 = 1;
+    ws = p;
+    wn = w0;
+    new_next = p + w0;
+    new_size = w0;
+  }
+  if (l == 0) {
+    gfs_stream* s = &fe->streams[j];
+    st_rlx(&s->next, new_next);
+    st_rlx32(&s->size, new_size);
+    st_rlx32(&s->last_use, clk);
+    st_rlx32(&s->valid, 1u);
+  }
+}
+
+/* ------------------------------------------------------------------ clock allocation
+ * Wave-collective, under the miss lock. Gives frames to sh->list[0..n) in order: each
+ * round takes as many consecutive hand tickets as pages remain, visits those frames in
+ * parallel, and hands the k-th successful ticket to the next unserved page, which is the
+ * order a one-at-a-time hand would produce. Returns how many pages got frames (a prefix
+ * of the list); stops after 2 * nframes visits without enough frames. */
+__device__ uint32_t alloc_wave(const gfs_dev* d, uint32_t file, uint64_t demand, ReadShared* sh,
+                               uint32_t n, uint32_t bid) {
+  const uint32_t l = lane();
+  uint32_t assigned = 0;
+  uint64_t visits = 0;
+  const uint64_t limit = 2ull * d->nframes;
+  while (assigned < n && visits < limit) {
+    const uint32_t need = (n - assigned) < 64u ? (n - assigned) : 64u;
+    uint64_t base = 0;
+    if (l == 0) base = fadd64(&d->g->hand, need);
+    base = __shfl(base, 0, 64);
+    int act = -1;
+    uint32_t f = 0;
+    uint64_t vkey = 0;
+    uint32_t vra = 0;
+    if (l < need) {
+      const uint64_t t = base + l;
+      f = (uint32_t)(t % d->nframes);
+      act = hand_visit(d, f, vkey, vra);
+      if (act == GFS_HAND_EVICT) {
+        const uint32_t vf = (uint32_t)(vkey >> GFS_KEY_PAGE_BITS) - 1u;
+        const uint32_t vp = (uint32_t)(vkey & ((1ull << GFS_KEY_PAGE_BITS) - 1));
+        trace_ev(d, 1, GFS_EV_HAND, bid, vf, vp, f, GFS_HAND_EVICT | (vra << 8), t);
+      } else {
+        trace_ev(d, 1, GFS_EV_HAND, bid, 0xffffffffu, 0xffffffffu, f, (uint32_t)act, t);
+      }
+    }
+    const bool ok = (act == GFS_HAND_FREE || act == GFS_HAND_EVICT);
+    const uint64_t sm = __ballot(ok);
+    if (ok) {
+      const uint32_t k = assigned + (uint32_t)__popcll(sm & lanemask_lt());
+      const uint64_t q = sh->list[k];
+      if (act == GFS_HAND_EVICT) {
+        pt_delete_lane(d, vkey, f);
+        count(d, GFS_C_EVICTIONS, 1);
+        if (vra) count(d, GFS_C_WASTED, 1);
+      }
+      const uint64_t key = page_key(file, q);
+      st_rlx(&d->ftag[f], key);
+      const uint64_t w = ld_rlx(&d->fword[f]);   /* CLAIMED by this lane */
+      uint64_t nw = (((w >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT) | GFS_FS_FILLING;
+      if (q == demand) nw += GFS_FW_PIN_ONE;
+      else nw |= GFS_FW_RA;
+      st_rel(&d->fword[f], nw);
+      if (pt_insert_lane(d, key, f)) {
+        sh->lframe[k] = f;
+        trace_ev(d, 1, GFS_EV_ALLOC, bid, file, (uint32_t)q, f, q == demand ? 0u : 1u, 0);
+      } else {
+        /* page table full: give the frame back */
+        st_rlx(&d->ftag[f], 0ull);
+        st_rel(&d->fword[f], ((nw >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT);
+        sh->lframe[k] = GFS_NO_FRAME;
+      }
+    }
+    count(d, GFS_C_HAND, l == 0 ? need : 0);
+    assigned += (uint32_t)__popcll(sm);
+    visits += need;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  return assigned;
+}
+
+/* ------------------------------------------------------------------ vector copy */
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+/* Block-cooperative copy of n bytes; both pointers 16-byte aligned. */
+__device__ __forceinline__ void copy_block_aligned(uint8_t* dst, const uint8_t* src, uint64_t n,
+                                                   uint32_t tid, uint32_t nt) {
+  const uint64_t n16 = n >> 4;
+  const v4u* s = (const v4u*)src;
+  v4u* o = (v4u*)dst;
+  uint64_t i = tid;
+  for (; i + 3ull * nt < n16; i += 4ull * nt) {
+    const v4u a = s[i], b = s[i + nt], c = s[i + 2ull * nt], e = s[i + 3ull * nt];
+    o[i] = a;
+    o[i + nt] = b;
+    o[i + 2ull * nt] = c;
+    o[i + 3ull * nt] = e;
+  }
+  for (; i < n16; i += nt) o[i] = s[i];
+  for (uint64_t j = (n16 << 4) + tid; j < n; j += nt) dst[j] = src[j];
+}
+
+__device__ __forceinline__ void copy_block(uint8_t* dst, const uint8_t* src, uint64_t n,
+                                           uint32_t tid, uint32_t nt) {
+  if ((((uintptr_t)dst | (uintptr_t)src) & 15) == 0) {
+    copy_block_aligned(dst, src, n, tid, nt);
+  } else {
+    for (uint64_t j = tid; j < n; j += nt) dst[j] = src[j];
+  }
+}
+
+/* ------------------------------------------------------------------ one page, wave 0
+ * Leaves in sh: status; on success the pinned frame, and pull = 1 when this block posted
+ * the request and must pull it. */
+__device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint64_t fsize,
+                                  ReadShared* sh, uint32_t bid) {
+  const uint64_t key = page_key(file, p);
+  const uint32_t l = lane();
+  const uint64_t t0 = wall_clock64();
+  uint32_t naps = 0;
+  while (true) {
+    int32_t f = pt_lookup_wave(d, key);
+    if (f >= 0) {
+      int r = PIN_RETRY;
+      if (l == 0) r = frame_pin(d, (uint32_t)f, key);
+      r = __shfl(r, 0, 64);
+      if (r == PIN_VALID) {
+        if (l == 0) {
+          count(d, GFS_C_HITS, 1);
+          trace_ev(d, 2, GFS_EV_HIT, bid, file, (uint32_t)p, (uint32_t)f, 0, 0);
+          sh->frame = f;
+          sh->status = 0;
+          sh->pull = 0;
+        }
+        return;
+      }
+      if (r == PIN_FILLING) {
+        if (l == 0) {
+          count(d, GFS_C_JOINS, 1);
+          trace_ev(d, 2, GFS_EV_JOIN, bid, file, (uint32_t)p, (uint32_t)f, 0, 0);
+          sh->status = wait_valid_lane(d, (uint32_t)f, t0);
+          sh->frame = f;
+          sh->pull = 0;
+        }
+        return;
+      }
+      if (l == 0) count(d, GFS_C_RETRIES, 1);
+    } else {
+      if (!lock_file_wave(d, file, t0)) break;
+      f = pt_lookup_wave(d, key);
+      if (f < 0) {
+        /* miss: decide the window, allocate, publish, unlock, post, wait */
+        uint64_t ws;
+        uint32_t wn;
+        ra_decide_wave(d, file, p, ws, wn);
+        const uint64_t npages = d->files[file].npages;
+        if (ws + wn > npages) wn = (uint32_t)(npages - ws);
+        if (l == 0) {
+          trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, GFS_NO_FRAME, wn, ws);
+          sh->list[0] = (uint32_t)p;
+        }
+        uint32_t n = 1;
+        for (uint64_t base = ws; base < ws + wn; base += 64) {
+          const uint64_t q = base + l;
+          bool want = false;
+          if (q < ws + wn && q != p) want = pt_find_lane(d, page_key(file, q)) < 0;
+          const uint64_t m = __ballot(want);
+          if (want) sh->list[n + __popcll(m & lanemask_lt())] = (uint32_t)q;
+          n += (uint32_t)__popcll(m);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        const uint32_t got = alloc_wave(d, file, p, sh, n, bid);
+        if (got == 0) {
+          /* every frame pinned or filling: back off and retry the access */
+          unlock_file_wave(d, file);
+          if (l == 0) count(d, GFS_C_NOFRAME, 1);
+          if (expired(d, t0)) break;
+          if (l == 0) nap(naps);
+          continue;
+        }
+        if (got < n && l == 0)
+          trace_ev(d, 1, GFS_EV_NOFRAME, bid, file, sh->list[got], GFS_NO_FRAME, 0, 0);
+        /* span of the pages that got frames (a page-table insert can fail only if the
+           table is full; such pages are left out of the request) */
+        uint64_t lo = ~0ull, hi = 0;
+        for (uint32_t k = l; k < got; k += 64) {
+          if (sh->lframe[k] != GFS_NO_FRAME) {
+            const uint64_t q = sh->list[k];
+            lo = q < lo ? q : lo;
+            hi = q > hi ? q : hi;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          const uint64_t a = __shfl_xor(lo, off, 64), b = __shfl_xor(hi, off, 64);
+          lo = a < lo ? a : lo;
+          hi = b > hi ? b : hi;
+        }
+        unlock_file_wave(d, file);
+        if (lo > hi) {
+          if (l == 0) {
+            sh->status = -kENOSPC;
+            sh->pull = 0;
+            sh->frame = -1;
+          }
+          return;
+        }
+        /* post the request for the span [lo, hi] */
+        const uint32_t span = (uint32_t)(hi - lo + 1);
+        const uint64_t off0 = lo << d->page_shift;
+        uint64_t len = (uint64_t)span << d->page_shift;
+        if (off0 + len > fsize) len = fsize - off0;
+        int64_t status = 0;
+        if (l == 0) {
+          const uint64_t t = fadd64(&d->g->ring_tail, 1);
+          const uint32_t s = (uint32_t)(t % d->rpc_slots);
+          const uint64_t gen = t / d->rpc_slots + 1;
+          uint32_t nn = 0;
+          while (ld_acq(&d->slot_free[s]) != gen - 1) {
+            if (expired(d, t0)) {
+              status = -kETIMEDOUT;
+              break;
+            }
+            nap(nn);
+          }
+          if (status == 0) {
+            gfs_rpc_slot* rs = &d->ring[s];
+            rs->file_id = file;
+            rs->npages = span;
+            rs->offset = off0;
+            rs->length = len;
+            rs->ticket = t;
+            __hip_atomic_store(&rs->req_seq, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            trace_ev(d, 1, GFS_EV_REQ, bid, file, (uint32_t)lo, GFS_NO_FRAME, span, t);
+            count(d, GFS_C_MISSES, 1);
+            count(d, GFS_C_REQUESTS, 1);
+            count(d, GFS_C_REQ_BYTES, len);
+            count(d, GFS_C_FETCHED, got);
+            count(d, GFS_C_RA_PAGES, got - 1);
+            nn = 0;
+            while (__hip_atomic_load(&rs->done_seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) !=
+                   gen) {
+              if (expired(d, t0)) {
+                status = -kETIMEDOUT;
+                break;
+              }
+              nap(nn);
+            }
+            sh->result = rs->result;
+          }
+          if (status) count(d, GFS_C_TIMEOUTS, 1);
+          /* the demanded page is list[0]; if it alone failed to enter the table the block
+             still pulls the rest of the window, then reports -ENOSPC */
+          const bool demand_ok = sh->lframe[0] != GFS_NO_FRAME;
+          sh->status = status ? status : (demand_ok ? 0 : -kENOSPC);
+          sh->frame = demand_ok ? (int32_t)sh->lframe[0] : -1;
+          sh->pull = status == 0 ? 1 : 0;
+          sh->slot = s;
+          sh->gen = gen;
+          sh->first_page = lo;
+          sh->list_n = got;
+          sh->file = file;
+        }
+        return;
+      }
+      unlock_file_wave(d, file);
+    }
+    if (expired(d, t0)) break;
+    if (l == 0) nap(naps);
+  }
+  if (l == 0) {
+    count(d, GFS_C_TIMEOUTS, 1);
+    sh->status = -kETIMEDOUT;
+    sh->pull = 0;
+    sh->frame = -1;
+  }
+}
+
+/* Block-collective: copy the fetched span from the ring slot's staging into the frames. */
+__device__ void block_pull(const gfs_dev* d, const ReadShared* sh, uint64_t fsize) {
+  const uint32_t tid = thread_id(), nt = block_threads();
+  const uint64_t P = d->page_size;
+  const uint8_t* stg = d->staging + (uint64_t)sh->slot * d->max_req_bytes;
+  const int64_t result = sh->result;
+  for (uint32_t k = 0; k < sh->list_n; ++k) {
+    const uint32_t f = sh->lframe[k];
+    if (f == GFS_NO_FRAME) continue;
+    const uint64_t q = sh->list[k];
+    const uint64_t rel = (q - sh->first_page) * P;
+    int64_t avail = result - (int64_t)rel;
+    if (avail < 0) avail = 0;
+    uint64_t pb = fsize - (q << d->page_shift);
+    if (pb > P) pb = P;
+    const uint64_t n = (uint64_t)avail < pb ? (uint64_t)avail : pb;
+    copy_block_aligned(d->frames + (uint64_t)f * P, stg + rel, n, tid, nt);
+  }
+}
+
+/* Wave 0, after the block's pull and a barrier: make the frames VALID, free the slot.
+ * Returns the status of the demanded page (list[0]). */
+__device__ int64_t publish_pull_wave(const gfs_dev* d, const ReadShared* sh, uint64_t fsize) {
+  const uint32_t l = lane();
+  const uint64_t P = d->page_size;
+  int bad_demand = 0;
+  for (uint32_t k = l; k < sh->list_n; k += 64) {
+    const uint32_t f = sh->lframe[k];
+    if (f == GFS_NO_FRAME) continue;
+    const uint64_t q = sh->list[k];
+    const uint64_t rel = (q - sh->first_page) * P;
+    uint64_t pb = fsize - (q << d->page_shift);
+    if (pb > P) pb = P;
+    const bool short_read = sh->result < 0 || (uint64_t)sh->result < rel + pb;
+    uint64_t* fw = &d->fword[f];
+    uint64_t w = ld_rlx(fw);
+    while (true) {
+      uint64_t nw = ((w & ~GFS_FW_STATE) | GFS_FS_VALID | GFS_FW_REF) + GFS_FW_VER_ONE;
+      if (short_read) nw |= GFS_FW_ERR;
+      if (cas64(fw, w, nw)) break;
+    }
+    if (short_read && k == 0 && sh->status == 0) bad_demand = 1;
+    if (short_read) count(d, GFS_C_IOERR, 1);
+  }
+  bad_demand = __shfl(bad_demand, 0, 64);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (l == 0) st_rel(&d->slot_free[sh->slot], sh->gen);
+  return bad_demand ? -kEIO : 0;
+}
+
+__device__ __forceinline__ void block_barrier() { __syncthreads(); }
+
+}  // namespace gfsd
+
+/* ====================================================================== public API */
+
+__device__ int gopen_id(const gfs_dev* d, int file_id, int flags) {
+  __shared__ int gfs_open_result;
+  if (gfsd::thread_id() == 0) {
+    int v;
+    if (flags != GFS_O_RDONLY) {
+      v = -gfsd::kEROFS;
+    } else if (file_id < 0 || (uint32_t)file_id >= GFS_MAX_FILES ||
+               gfsd::ld_rlx32(&d->files[file_id].open) == 0) {
+      v = -gfsd::kENOENT;
+    } else {
+      __hip_atomic_fetch_add(&d->files[file_id].handles, 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      v = file_id;
+    }
+    gfs_open_result = v;
+  }
+  __syncthreads();
+  const int v = gfs_open_result;
+  __syncthreads();
+  return v;
+}
+
+__device__ int gopen(const gfs_dev* d, const char* path, int flags) {
+  __shared__ int gfs_open_path_id;
+  if (gfsd::thread_id() == 0) {
+    int id = -1;
+    for (uint32_t i = 0; i < GFS_MAX_FILES && id < 0; ++i) {
+      if (gfsd::ld_rlx32(&d->files[i].open) == 0) continue;
+      const char* nm = d->names + (uint64_t)i * GFS_NAME_MAX;
+      uint32_t j = 0;
+      while (j < GFS_NAME_MAX && nm[j] == path[j] && nm[j] != 0) ++j;
+      if (j < GFS_NAME_MAX && nm[j] == 0 && path[j] == 0) id = (int)i;
+    }
+    gfs_open_path_id = id;
+  }
+  __syncthreads();
+  const int id = gfs_open_path_id;
+  __syncthreads();
+  if (flags != GFS_O_RDONLY) return -gfsd::kEROFS;
+  if (id < 0) return -gfsd::kENOENT;
+  return gopen_id(d, id, flags);
+}
+
+__device__ int gclose(const gfs_dev* d, int fd) {
+  if (fd < 0 || (uint32_t)fd >= GFS_MAX_FILES) return -gfsd::kEBADF;
+  __syncthreads();
+  if (gfsd::thread_id() == 0)
+    __hip_atomic_fetch_sub(&d->files[fd].handles, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  return 0;
+}
+
+__device__ int64_t gread(const gfs_dev* d, int fd, uint64_t offset, uint64_t size, void* dst) {
+  using namespace gfsd;
+  __shared__ ReadShared gfs_read_sh;
+  ReadShared* sh = &gfs_read_sh;
+  if (fd < 0 || (uint32_t)fd >= GFS_MAX_FILES) return -kEBADF;
+  gfs_file_dev* fe = &d->files[fd];
+  if (ld_rlx32(&fe->open) == 0) return -kEBADF;
+  const uint32_t nt = block_threads();
+  if (nt & 63u) return -kEINVAL;
+  const uint64_t fsize = fe->size;
+  if (size == 0 || offset >= fsize) return 0;
+  const uint64_t end = (size > fsize - offset) ? fsize : offset + size;
+  const uint32_t tid = thread_id();
+  const uint32_t bid = block_id();
+  const uint64_t P = d->page_size;
+  const uint32_t sh_bits = d->page_shift;
+  int64_t err = 0;
+  for (uint64_t p = offset >> sh_bits; p <= (end - 1) >> sh_bits; ++p) {
+    if (tid < 64) acquire_page_wave(d, (uint32_t)fd, p, fsize, sh, bid);
+    __syncthreads();
+    if (sh->pull) {
+      block_pull(d, sh, fsize);
+      __threadfence();
+      __syncthreads();
+      if (tid < 64) {
+        const int64_t st = publish_pull_wave(d, sh, fsize);
+        if (tid == 0 && st < 0) {
+          frame_unpin(d, (uint32_t)sh->frame);
+          sh->status = st;
+        }
+      }
+      __syncthreads();
+    }
+    const int64_t st = sh->status;
+    const int32_t f = sh->frame;
+    if (st < 0) {
+      err = st;
+      __syncthreads();
+      break;
+    }
+    const uint64_t pbase = p << sh_bits;
+    const uint64_t lo = offset > pbase ? offset : pbase;
+    const uint64_t hi = end < pbase + P ? end : pbase + P;
+    copy_block((uint8_t*)dst + (lo - offset), d->frames + (uint64_t)f * P + (lo - pbase), hi - lo,
+               tid, nt);
+    __syncthreads();
+    if (tid == 0) frame_unpin(d, (uint32_t)f);
+  }
+  if (err) return err;
+  if (tid == 0) count(d, GFS_C_DELIVERED, end - offset);
+  return (int64_t)(end - offset);
+}
+
+#endif /* GFS_DEVICE_H */

@@ -1,0 +1,130 @@
+/* gfs_layout.h -- memory layout shared by the host runtime and the device library.
+ *
+ * Internal to the library (users include gfs.h and gfs_device.h). Everything here is
+ * plain data: the device handle, the per-file and global records in HBM, the frame
+ * word and page-table entry encodings, and the request-ring slot in pinned host memory.
+ *
+ * HBM layout of the metadata region (offsets computed by the host, stored in gfs_dev):
+ *   gfs_globals                      256 B
+ *   gfs_dev (the handle)             512 B
+ *   files[GFS_MAX_FILES]             224 B each
+ *   names[GFS_MAX_FILES]             GFS_NAME_MAX B each (registered paths)
+ *   fword[nframes]  u64              frame word (state, pins, ref, ra, version)
+ *   ftag[nframes]   u64              key of the page held (valid while not FREE)
+ *   pt[nbuckets*16] u64              hashed page table, 16-entry buckets (128 B)
+ *   slot_free[rpc_slots] u64         generation of the last completed use of each ring slot
+ *   req_frames[rpc_slots*max_req_pages] u32  frame of each page of the slot's request
+ *   trace[trace_capacity]            32 B records
+ * Frames (cache_bytes) are a separate caller allocation. The ring and staging live in
+ * pinned, device-mapped host memory owned by the context.
+ */
+#ifndef GFS_LAYOUT_H
+#define GFS_LAYOUT_H
+
+#include <stdint.h>
+
+/* ---- frame word (64 bit), changed only by compare-and-swap, version bumped each time ---- */
+#define GFS_FS_FREE 0ull
+#define GFS_FS_CLAIMED 1ull   /* owned by an allocator; not pinnable, not visible */
+#define GFS_FS_FILLING 2ull   /* mapped, data on its way; pinnable (joiners wait) */
+#define GFS_FS_VALID 3ull     /* mapped, data present */
+#define GFS_FW_STATE 0x3ull
+#define GFS_FW_REF (1ull << 2)   /* clock reference bit */
+#define GFS_FW_RA (1ull << 3)    /* prefetched, not yet demanded */
+#define GFS_FW_ERR (1ull << 4)   /* the host read for this page failed */
+#define GFS_FW_PIN_SHIFT 8
+#define GFS_FW_PIN_ONE (1ull << GFS_FW_PIN_SHIFT)
+#define GFS_FW_PINS (0xffffull << GFS_FW_PIN_SHIFT)
+#define GFS_FW_VER_SHIFT 32
+#define GFS_FW_VER_ONE (1ull << GFS_FW_VER_SHIFT)
+
+/* ---- page key and page-table entry ----
+ * key = (file+1) << 28 | page   (39 bits, never 0)
+ * entry = key << 24 | frame      (0 = empty slot)                                  */
+#define GFS_KEY_PAGE_BITS 28
+#define GFS_ENTRY_FRAME_BITS 24
+#define GFS_BUCKET_SLOTS 16
+#define GFS_NO_FRAME 0xffffffffu
+
+typedef struct gfs_globals {
+  uint64_t hand;          /* clock hand ticket counter */
+  uint64_t ring_tail;     /* request ring ticket counter */
+  uint64_t trace_n;       /* trace records appended (including dropped) */
+  uint64_t pad0[5];
+  uint64_t ctr[24];       /* device counters, GFS_C_* */
+} gfs_globals;
+
+enum {
+  GFS_C_HITS = 0, GFS_C_JOINS, GFS_C_MISSES, GFS_C_RA_PAGES, GFS_C_FETCHED, GFS_C_EVICTIONS,
+  GFS_C_WASTED, GFS_C_HAND, GFS_C_REQUESTS, GFS_C_REQ_BYTES, GFS_C_DELIVERED, GFS_C_RETRIES,
+  GFS_C_NOFRAME, GFS_C_TIMEOUTS, GFS_C_IOERR, GFS_C_COUNT
+};
+
+typedef struct gfs_stream {
+  uint64_t next;          /* first page after the last window */
+  uint32_t size;          /* last window length (pages) */
+  uint32_t last_use;      /* per-file decision clock at last use */
+  uint32_t valid;
+  uint32_t pad;
+} gfs_stream;             /* 24 B */
+
+typedef struct gfs_file_dev {
+  uint64_t size;          /* bytes */
+  uint32_t npages;
+  uint32_t open;          /* 1 while registered */
+  uint32_t advice;        /* GFS_ADV_* */
+  uint32_t lock;          /* miss-path lock (0 free, 1 held) */
+  uint32_t clock;         /* readahead decision counter (stream last_use) */
+  uint32_t handles;       /* device gopen count minus gclose count */
+  gfs_stream streams[8];  /* 192 B */
+} gfs_file_dev;           /* 224 B */
+
+#define GFS_NAME_MAX 256     /* registered path, NUL-terminated, for gopen(path) */
+
+/* request ring slot in pinned host memory: the device writes the first cache line,
+ * the host the second */
+typedef struct gfs_rpc_slot {
+  uint64_t req_seq;       /* generation, published last (system-scope release) */
+  uint32_t file_id;
+  uint32_t npages;        /* pages in the span */
+  uint64_t offset;        /* file byte offset of the first page */
+  uint64_t length;        /* bytes to read (span, clamped to EOF) */
+  uint64_t ticket;
+  uint64_t pad0[3];
+  uint64_t done_seq;      /* generation completed, published last by the host */
+  int64_t result;         /* bytes read, or -errno */
+  uint64_t t_claim_ns;
+  uint64_t t_done_ns;
+  uint64_t pad1[4];
+} gfs_rpc_slot;           /* 128 B */
+
+typedef struct gfs_dev {
+  uint64_t page_size;
+  uint32_t page_shift;
+  uint32_t nframes;
+  uint32_t nbuckets_mask;       /* buckets - 1 (power of two) */
+  uint32_t streams;
+  uint32_t ra_init;             /* pages */
+  uint32_t ra_cap;              /* pages; 0 = readahead off */
+  uint32_t rpc_slots;
+  uint32_t max_req_pages;
+  uint32_t trace_level;
+  uint32_t trace_cap;
+  uint64_t max_req_bytes;
+  uint64_t timeout_ticks;       /* wall_clock64 ticks */
+  uint8_t* frames;
+  uint64_t* fword;
+  uint64_t* ftag;
+  uint64_t* pt;
+  gfs_globals* g;
+  gfs_file_dev* files;
+  uint64_t* slot_free;
+  uint32_t* req_frames;
+  void* trace;                  /* gfs_event[trace_cap] */
+  char* names;                  /* [GFS_MAX_FILES][GFS_NAME_MAX] registered paths */
+  gfs_rpc_slot* ring;           /* device-visible address of the pinned ring */
+  uint8_t* staging;             /* device-visible address of the pinned staging */
+  uint64_t pad[7];
+} gfs_dev;
+
+#endif /* GFS_LAYOUT_H */

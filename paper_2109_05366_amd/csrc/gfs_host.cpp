@@ -1,0 +1,523 @@
+// Host runtime of the GPU file page cache: context set-up, file registry, and the host
+// I/O threads that serve the device's request ring (Sec. 2.2: host threads poll the shared
+// CPU-GPU request queue and read the file for the GPU; Sec. 4.1: the host reads the whole
+// requested span, and the GPU side places every page of it in the cache).
+//
+// Differences from the paper's host side, on purpose: any idle host thread takes the next
+// request in ring order (the paper's per-thread slot partition left threads idle, Sec. 3.4);
+// one read covers a whole readahead span instead of one page per read; the data is read
+// straight into pinned staging that the GPU pulls from, so the host issues no copy calls.
+#include <errno.h>
+#include <fcntl.h>
+#include <sched.h>
+#include <string.h>
+#include <sys/stat.h>
+#include <time.h>
+#include <unistd.h>
+
+#include <atomic>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "gfs.h"
+#include "gfs_layout.h"
+
+extern "C" int gfs_internal_zero(void* p, size_t bytes, hipStream_t s);
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+constexpr uint64_t kDirectAlign = 4096;
+
+uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+uint64_t now_ns() {
+  timespec t;
+  clock_gettime(CLOCK_MONOTONIC, &t);
+  return (uint64_t)t.tv_sec * 1000000000ull + (uint64_t)t.tv_nsec;
+}
+bool pow2(uint64_t v) { return v && !(v & (v - 1)); }
+uint32_t log2u(uint64_t v) {
+  uint32_t s = 0;
+  while ((1ull << s) < v) ++s;
+  return s;
+}
+
+struct Layout {
+  uint64_t nframes = 0, nbuckets = 0, ra_init = 0, ra_cap = 0, max_req_pages = 0;
+  uint64_t max_req_bytes = 0;
+  uint64_t off_globals = 0, off_dev = 0, off_files = 0, off_names = 0, off_fword = 0,
+           off_ftag = 0, off_pt = 0, off_slot_free = 0, off_trace = 0, meta_bytes = 0;
+};
+
+int make_layout(const gfs_config* c, Layout* L) {
+  if (!c || c->abi_version != GFS_ABI_VERSION) return -EINVAL;
+  const uint64_t P = c->page_size;
+  if (!pow2(P) || P < 4096 || P > (2ull << 20)) return -EINVAL;
+  if (c->cache_bytes == 0 || c->cache_bytes % P) return -EINVAL;
+  L->nframes = c->cache_bytes / P;
+  if (L->nframes < 64 || L->nframes > GFS_MAX_FRAMES - 1) return -EINVAL;
+  if (c->streams_per_file < 1 || c->streams_per_file > GFS_MAX_STREAMS) return -EINVAL;
+  if (c->ra_cap_bytes % P || c->ra_init_bytes % P) return -EINVAL;
+  L->ra_cap = c->ra_cap_bytes / P;
+  L->ra_init = c->ra_init_bytes / P;
+  if (L->ra_cap > GFS_MAX_WINDOW_PAGES) return -EINVAL;
+  if (L->ra_cap && (L->ra_init < 1 || L->ra_init > L->ra_cap)) return -EINVAL;
+  if (c->host_threads < 1 || c->host_threads > 64) return -EINVAL;
+  if (c->rpc_slots < 1 || c->rpc_slots > 4096) return -EINVAL;
+  if (c->io_backend != GFS_IO_PREAD) return -EINVAL;
+  if (c->o_direct > GFS_DIRECT_PREFER) return -EINVAL;
+  if (c->trace_level > 2) return -EINVAL;
+  L->max_req_pages = L->ra_cap ? L->ra_cap : 1;
+  L->max_req_bytes = L->max_req_pages * P;
+  // page table: 4 entries per frame, 16-entry buckets, power-of-two bucket count
+  uint64_t nb = 2;
+  while (nb * GFS_BUCKET_SLOTS < 4 * L->nframes) nb <<= 1;
+  L->nbuckets = nb;
+  uint64_t o = 0;
+  L->off_globals = o; o = align_up(o + sizeof(gfs_globals), kAlign);
+  L->off_dev = o; o = align_up(o + sizeof(gfs_dev), kAlign);
+  L->off_files = o; o = align_up(o + sizeof(gfs_file_dev) * GFS_MAX_FILES, kAlign);
+  L->off_names = o; o = align_up(o + (uint64_t)GFS_NAME_MAX * GFS_MAX_FILES, kAlign);
+  L->off_fword = o; o = align_up(o + 8 * L->nframes, kAlign);
+  L->off_ftag = o; o = align_up(o + 8 * L->nframes, kAlign);
+  L->off_pt = o; o = align_up(o + 8 * GFS_BUCKET_SLOTS * L->nbuckets, kAlign);
+  L->off_slot_free = o; o = align_up(o + 8ull * c->rpc_slots, kAlign);
+  L->off_trace = o; o = align_up(o + sizeof(gfs_event) * (uint64_t)c->trace_capacity, kAlign);
+  L->meta_bytes = o;
+  return 0;
+}
+
+struct HostFile {
+  std::atomic<int> fd{-1};
+  bool open = false;
+  bool direct = false;
+  uint64_t size = 0;
+  std::string path;
+};
+
+}  // namespace
+
+struct gfs_ctx {
+  gfs_config cfg{};
+  Layout L;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint8_t* frames = nullptr;
+  uint8_t* meta = nullptr;
+  gfs_dev hdev{};
+  gfs_dev* ddev = nullptr;
+  gfs_rpc_slot* ring = nullptr;   // host address (pinned, mapped)
+  uint8_t* staging = nullptr;     // host address (pinned, mapped)
+  HostFile files[GFS_MAX_FILES];
+  std::vector<std::thread> threads;
+  std::atomic<uint64_t> head{0};
+  std::atomic<bool> stop{false};
+  std::atomic<uint64_t> host_requests{0}, host_bytes{0}, host_read_ns{0};
+  std::atomic<uint64_t> spins[64];
+  bool last_direct = false;
+};
+
+namespace {
+
+int64_t read_span(int fd, bool direct, uint8_t* dst, uint64_t off, uint64_t len) {
+  const uint64_t want = direct ? align_up(len, kDirectAlign) : len;
+  uint64_t done = 0;
+  while (done < want) {
+    const ssize_t r = pread(fd, dst + done, want - done, (off_t)(off + done));
+    if (r < 0) {
+      if (errno == EINTR) continue;
+      return -(int64_t)errno;
+    }
+    if (r == 0) break;
+    done += (uint64_t)r;
+    if (direct && ((uint64_t)r % kDirectAlign)) break;   // short read at end of file
+  }
+  return (int64_t)(done < len ? done : len);
+}
+
+inline void cpu_relax() { __builtin_ia32_pause(); }
+
+// One host I/O thread: take ring tickets in order, wait for the device to publish the
+// ticket's request, read the span into the slot's staging buffer, publish the result.
+void io_thread(gfs_ctx* c, int idx) {
+  const uint32_t NS = c->cfg.rpc_slots;
+  bool first = true;
+  uint64_t idle_spins = 0;
+  while (!c->stop.load(std::memory_order_relaxed)) {
+    const uint64_t h = c->head.fetch_add(1, std::memory_order_relaxed);
+    const uint32_t s = (uint32_t)(h % NS);
+    const uint64_t gen = h / NS + 1;
+    gfs_rpc_slot* rs = &c->ring[s];
+    uint64_t spins = 0;
+    while (__atomic_load_n(&rs->req_seq, __ATOMIC_ACQUIRE) != gen) {
+      if (c->stop.load(std::memory_order_relaxed)) return;
+      ++spins;
+      if (spins < (1u << 20)) {
+        cpu_relax();
+      } else {
+        usleep(50);   // long idle: stop burning the core, at some wake-up latency
+      }
+    }
+    idle_spins += spins;
+    if (first) {
+      c->spins[idx].store(idle_spins, std::memory_order_relaxed);
+      first = false;
+    }
+    rs->t_claim_ns = now_ns();
+    const uint32_t fid = rs->file_id;
+    const uint64_t off = rs->offset, len = rs->length;
+    int64_t res;
+    HostFile* hf = fid < GFS_MAX_FILES ? &c->files[fid] : nullptr;
+    const int fd = hf ? hf->fd.load(std::memory_order_acquire) : -1;
+    if (fd < 0 || len > c->L.max_req_bytes) {
+      res = -EBADF;
+    } else {
+      uint8_t* dst = c->staging + (uint64_t)s * c->L.max_req_bytes;
+      const uint64_t t0 = now_ns();
+      res = read_span(fd, hf->direct, dst, off, len);
+      c->host_read_ns.fetch_add(now_ns() - t0, std::memory_order_relaxed);
+      if (res > 0) c->host_bytes.fetch_add((uint64_t)res, std::memory_order_relaxed);
+    }
+    rs->result = res;
+    rs->t_done_ns = now_ns();
+    __atomic_store_n(&rs->done_seq, gen, __ATOMIC_RELEASE);
+    c->host_requests.fetch_add(1, std::memory_order_relaxed);
+  }
+}
+
+void start_threads(gfs_ctx* c) {
+  c->stop.store(false);
+  c->head.store(0);
+  for (uint32_t i = 0; i < c->cfg.host_threads; ++i) c->threads.emplace_back(io_thread, c, (int)i);
+}
+
+void stop_threads(gfs_ctx* c) {
+  c->stop.store(true);
+  for (auto& t : c->threads) t.join();
+  c->threads.clear();
+}
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : -EIO; }
+
+int upload_file_record(gfs_ctx* c, int id, const gfs_file_dev& rec) {
+  gfs_file_dev* dst = (gfs_file_dev*)(c->meta + c->L.off_files) + id;
+  if (hipMemcpyAsync(dst, &rec, sizeof rec, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return -EIO;
+  return hip_ok(hipStreamSynchronize(c->stream));
+}
+
+int download_file_record(gfs_ctx* c, int id, gfs_file_dev* rec) {
+  const gfs_file_dev* src = (const gfs_file_dev*)(c->meta + c->L.off_files) + id;
+  if (hipMemcpyAsync(rec, src, sizeof *rec, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return -EIO;
+  return hip_ok(hipStreamSynchronize(c->stream));
+}
+
+// zero the dynamic state: counters, hand, ring tail, frames, tags, table, slots, trace
+int zero_dynamic(gfs_ctx* c) {
+  const Layout& L = c->L;
+  int rc = gfs_internal_zero(c->meta + L.off_globals, sizeof(gfs_globals), c->stream);
+  if (!rc) rc = gfs_internal_zero(c->meta + L.off_fword, L.off_slot_free + 8ull * c->cfg.rpc_slots - L.off_fword, c->stream);
+  if (!rc && c->cfg.trace_capacity)
+    rc = gfs_internal_zero(c->meta + L.off_trace, sizeof(gfs_event) * (uint64_t)c->cfg.trace_capacity, c->stream);
+  if (!rc) rc = hip_ok(hipStreamSynchronize(c->stream));
+  memset(c->ring, 0, sizeof(gfs_rpc_slot) * c->cfg.rpc_slots);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gfs_config_default(gfs_config* cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof *cfg);
+  cfg->abi_version = GFS_ABI_VERSION;
+  cfg->streams_per_file = 8;
+  cfg->page_size = 64 << 10;
+  cfg->cache_bytes = 256ull << 20;
+  cfg->ra_init_bytes = 4 * cfg->page_size;
+  cfg->ra_cap_bytes = 16ull << 20;
+  cfg->host_threads = 8;
+  cfg->rpc_slots = 64;
+  cfg->io_backend = GFS_IO_PREAD;
+  cfg->o_direct = GFS_DIRECT_PREFER;
+  cfg->trace_level = 0;
+  cfg->trace_capacity = 0;
+  cfg->wait_timeout_ns = 0;
+}
+
+int gfs_device_bytes(const gfs_config* cfg, size_t* frames_bytes, size_t* meta_bytes) {
+  Layout L;
+  const int rc = make_layout(cfg, &L);
+  if (rc) return rc;
+  if (frames_bytes) *frames_bytes = cfg->cache_bytes;
+  if (meta_bytes) *meta_bytes = L.meta_bytes;
+  return 0;
+}
+
+int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_stream,
+             gfs_ctx** out) {
+  if (!out || !frames_dev || !meta_dev) return -EINVAL;
+  if (((uintptr_t)frames_dev | (uintptr_t)meta_dev) & (kAlign - 1)) return -EINVAL;
+  Layout L;
+  int rc = make_layout(cfg, &L);
+  if (rc) return rc;
+  gfs_ctx* c = new (std::nothrow) gfs_ctx();
+  if (!c) return -ENOMEM;
+  for (auto& s : c->spins) s.store(0);
+  c->cfg = *cfg;
+  c->L = L;
+  c->stream = (hipStream_t)hip_stream;
+  c->frames = (uint8_t*)frames_dev;
+  c->meta = (uint8_t*)meta_dev;
+  if (hipGetDevice(&c->device) != hipSuccess) { delete c; return -EIO; }
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess || khz <= 0) {
+    delete c;
+    return -EIO;
+  }
+  const uint64_t ring_bytes = sizeof(gfs_rpc_slot) * (uint64_t)cfg->rpc_slots;
+  const uint64_t staging_bytes = L.max_req_bytes * (uint64_t)cfg->rpc_slots;
+  if (hipHostMalloc((void**)&c->ring, ring_bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+    delete c;
+    return -ENOMEM;
+  }
+  if (hipHostMalloc((void**)&c->staging, staging_bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+    (void)hipHostFree(c->ring);
+    delete c;
+    return -ENOMEM;
+  }
+  void* dring = nullptr;
+  void* dstg = nullptr;
+  if (hipHostGetDevicePointer(&dring, c->ring, 0) != hipSuccess ||
+      hipHostGetDevicePointer(&dstg, c->staging, 0) != hipSuccess) {
+    (void)hipHostFree(c->staging);
+    (void)hipHostFree(c->ring);
+    delete c;
+    return -EIO;
+  }
+  gfs_dev& h = c->hdev;
+  memset(&h, 0, sizeof h);
+  h.page_size = cfg->page_size;
+  h.page_shift = log2u(cfg->page_size);
+  h.nframes = (uint32_t)L.nframes;
+  h.nbuckets_mask = (uint32_t)(L.nbuckets - 1);
+  h.streams = cfg->streams_per_file;
+  h.ra_init = (uint32_t)L.ra_init;
+  h.ra_cap = (uint32_t)L.ra_cap;
+  h.rpc_slots = cfg->rpc_slots;
+  h.max_req_pages = (uint32_t)L.max_req_pages;
+  h.trace_level = cfg->trace_level;
+  h.trace_cap = cfg->trace_capacity;
+  h.max_req_bytes = L.max_req_bytes;
+  const uint64_t tns = cfg->wait_timeout_ns ? cfg->wait_timeout_ns : 10000000000ull;
+  h.timeout_ticks = tns / 1000 * (uint64_t)khz / 1000;
+  h.frames = c->frames;
+  h.g = (gfs_globals*)(c->meta + L.off_globals);
+  h.files = (gfs_file_dev*)(c->meta + L.off_files);
+  h.names = (char*)(c->meta + L.off_names);
+  h.fword = (uint64_t*)(c->meta + L.off_fword);
+  h.ftag = (uint64_t*)(c->meta + L.off_ftag);
+  h.pt = (uint64_t*)(c->meta + L.off_pt);
+  h.slot_free = (uint64_t*)(c->meta + L.off_slot_free);
+  h.trace = c->meta + L.off_trace;
+  h.ring = (gfs_rpc_slot*)dring;
+  h.staging = (uint8_t*)dstg;
+  c->ddev = (gfs_dev*)(c->meta + L.off_dev);
+  rc = gfs_internal_zero(c->meta, L.meta_bytes, c->stream);
+  if (!rc && hipMemcpyAsync(c->ddev, &h, sizeof h, hipMemcpyHostToDevice, c->stream) != hipSuccess) rc = -EIO;
+  if (!rc) rc = hip_ok(hipStreamSynchronize(c->stream));
+  if (rc) {
+    (void)hipHostFree(c->staging);
+    (void)hipHostFree(c->ring);
+    delete c;
+    return rc;
+  }
+  memset(c->ring, 0, ring_bytes);
+  start_threads(c);
+  *out = c;
+  return 0;
+}
+
+int gfs_open(gfs_ctx* c, const char* path, int flags, int* file_id) {
+  if (!c || !path || !file_id) return -EINVAL;
+  if (flags != GFS_O_RDONLY) return -EROFS;
+  const size_t plen = strlen(path);
+  if (plen == 0 || plen >= GFS_NAME_MAX) return -ENAMETOOLONG;
+  int id = -1;
+  for (int i = 0; i < (int)GFS_MAX_FILES; ++i)
+    if (!c->files[i].open) { id = i; break; }
+  if (id < 0) return -ENFILE;
+  bool direct = false;
+  int fd = -1;
+  if (c->cfg.o_direct != GFS_DIRECT_OFF) {
+    fd = open(path, O_RDONLY | O_DIRECT | O_CLOEXEC);
+    if (fd >= 0) direct = true;
+    else if (c->cfg.o_direct == GFS_DIRECT_ON || errno != EINVAL) return -errno;
+  }
+  if (fd < 0) {
+    fd = open(path, O_RDONLY | O_CLOEXEC);
+    if (fd < 0) return -errno;
+  }
+  struct stat st;
+  if (fstat(fd, &st) != 0) { const int e = errno; close(fd); return -e; }
+  const uint64_t size = (uint64_t)st.st_size;
+  const uint64_t npages = (size + c->cfg.page_size - 1) / c->cfg.page_size;
+  if (npages >= GFS_MAX_PAGES_PER_FILE) { close(fd); return -EFBIG; }
+  posix_fadvise(fd, 0, 0, POSIX_FADV_DONTNEED);
+  gfs_file_dev rec;
+  memset(&rec, 0, sizeof rec);
+  rec.size = size;
+  rec.npages = (uint32_t)npages;
+  rec.open = 1;
+  rec.advice = GFS_ADV_NORMAL;
+  char name[GFS_NAME_MAX];
+  memset(name, 0, sizeof name);
+  memcpy(name, path, plen);
+  int rc = upload_file_record(c, id, rec);
+  if (!rc && hipMemcpyAsync(c->meta + c->L.off_names + (uint64_t)id * GFS_NAME_MAX, name, GFS_NAME_MAX,
+                            hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    rc = -EIO;
+  if (!rc) rc = hip_ok(hipStreamSynchronize(c->stream));
+  if (rc) { close(fd); return rc; }
+  HostFile& hf = c->files[id];
+  hf.open = true;
+  hf.direct = direct;
+  hf.size = size;
+  hf.path = path;
+  hf.fd.store(fd, std::memory_order_release);
+  c->last_direct = direct;
+  *file_id = id;
+  return 0;
+}
+
+int gfs_fadvise(gfs_ctx* c, int file_id, int advice) {
+  if (!c || file_id < 0 || file_id >= (int)GFS_MAX_FILES || !c->files[file_id].open) return -EBADF;
+  if (advice != GFS_ADV_NORMAL && advice != GFS_ADV_RANDOM && advice != GFS_ADV_SEQUENTIAL) return -EINVAL;
+  gfs_file_dev rec;
+  int rc = download_file_record(c, file_id, &rec);
+  if (rc) return rc;
+  rec.advice = (uint32_t)advice;
+  return upload_file_record(c, file_id, rec);
+}
+
+int gfs_close(gfs_ctx* c, int file_id) {
+  if (!c || file_id < 0 || file_id >= (int)GFS_MAX_FILES || !c->files[file_id].open) return -EBADF;
+  gfs_file_dev rec;
+  int rc = download_file_record(c, file_id, &rec);
+  if (rc) return rc;
+  if (rec.handles != 0) return -EBUSY;
+  rec.open = 0;
+  rc = upload_file_record(c, file_id, rec);
+  if (rc) return rc;
+  HostFile& hf = c->files[file_id];
+  const int fd = hf.fd.exchange(-1);
+  if (fd >= 0) close(fd);
+  hf.open = false;
+  hf.path.clear();
+  return 0;
+}
+
+const struct gfs_dev* gfs_device_handle(gfs_ctx* c) { return c ? c->ddev : nullptr; }
+
+int gfs_stats_read(gfs_ctx* c, gfs_stats* out) {
+  if (!c || !out) return -EINVAL;
+  gfs_globals g;
+  if (hipMemcpyAsync(&g, c->meta + c->L.off_globals, sizeof g, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return -EIO;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return -EIO;
+  gfs_stats s;
+  memset(&s, 0, sizeof s);
+  s.hits = g.ctr[GFS_C_HITS];
+  s.joins = g.ctr[GFS_C_JOINS];
+  s.misses = g.ctr[GFS_C_MISSES];
+  s.ra_pages = g.ctr[GFS_C_RA_PAGES];
+  s.fetched_pages = g.ctr[GFS_C_FETCHED];
+  s.evictions = g.ctr[GFS_C_EVICTIONS];
+  s.wasted_pages = g.ctr[GFS_C_WASTED];
+  s.hand_visits = g.ctr[GFS_C_HAND];
+  s.requests = g.ctr[GFS_C_REQUESTS];
+  s.request_bytes = g.ctr[GFS_C_REQ_BYTES];
+  s.delivered_bytes = g.ctr[GFS_C_DELIVERED];
+  s.retries = g.ctr[GFS_C_RETRIES];
+  s.noframe = g.ctr[GFS_C_NOFRAME];
+  s.timeouts = g.ctr[GFS_C_TIMEOUTS];
+  s.io_errors = g.ctr[GFS_C_IOERR];
+  s.trace_events = g.trace_n;
+  s.host_requests = c->host_requests.load();
+  s.host_bytes = c->host_bytes.load();
+  s.host_read_ns = c->host_read_ns.load();
+  for (uint32_t i = 0; i < 64; ++i) s.host_spins[i] = c->spins[i].load();
+  s.host_threads = c->cfg.host_threads;
+  s.direct_io = c->last_direct ? 1 : 0;
+  *out = s;
+  return 0;
+}
+
+int gfs_trace_read(gfs_ctx* c, void* dst, size_t cap_bytes, size_t* n_bytes) {
+  if (!c || (!dst && cap_bytes) || !n_bytes) return -EINVAL;
+  uint64_t n = 0;
+  if (hipMemcpyAsync(&n, c->meta + c->L.off_globals + offsetof(gfs_globals, trace_n), 8,
+                     hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return -EIO;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return -EIO;
+  if (n > c->cfg.trace_capacity) n = c->cfg.trace_capacity;
+  uint64_t bytes = n * sizeof(gfs_event);
+  if (bytes > cap_bytes) bytes = cap_bytes / sizeof(gfs_event) * sizeof(gfs_event);
+  if (bytes) {
+    if (hipMemcpyAsync(dst, c->meta + c->L.off_trace, bytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      return -EIO;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return -EIO;
+  }
+  *n_bytes = bytes;
+  return 0;
+}
+
+int gfs_reset_cache(gfs_ctx* c) {
+  if (!c) return -EINVAL;
+  stop_threads(c);
+  int rc = zero_dynamic(c);
+  // clear readahead streams, locks and clocks of registered files
+  for (int i = 0; !rc && i < (int)GFS_MAX_FILES; ++i) {
+    if (!c->files[i].open) continue;
+    gfs_file_dev rec;
+    rc = download_file_record(c, i, &rec);
+    if (rc) break;
+    const uint32_t advice = rec.advice;
+    const uint32_t handles = rec.handles;
+    memset(&rec, 0, sizeof rec);
+    rec.size = c->files[i].size;
+    rec.npages = (uint32_t)((rec.size + c->cfg.page_size - 1) / c->cfg.page_size);
+    rec.open = 1;
+    rec.advice = advice;
+    rec.handles = handles;
+    rc = upload_file_record(c, i, rec);
+    if (c->files[i].direct) posix_fadvise(c->files[i].fd.load(), 0, 0, POSIX_FADV_DONTNEED);
+  }
+  c->host_requests = 0;
+  c->host_bytes = 0;
+  c->host_read_ns = 0;
+  for (auto& s : c->spins) s.store(0);
+  start_threads(c);
+  return rc;
+}
+
+int gfs_shutdown(gfs_ctx* c) {
+  if (!c) return -EINVAL;
+  stop_threads(c);
+  for (auto& f : c->files) {
+    const int fd = f.fd.exchange(-1);
+    if (fd >= 0) close(fd);
+  }
+  (void)hipHostFree(c->staging);
+  (void)hipHostFree(c->ring);
+  delete c;
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+"""Python binding of libgfs.so (ctypes): the C-ABI of include/gfs.h, same names.
+
+Argument marshalling only: every step of the page-cache path runs in the library's HIP
+kernels and host threads. PyTorch provides device memory and streams. If the library is
+not built this module raises at first use; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgfs.so")
+
+GFS_ABI_VERSION = 1
+GFS_O_RDONLY = 0
+GFS_ADV_NORMAL, GFS_ADV_RANDOM, GFS_ADV_SEQUENTIAL = 0, 1, 2
+GFS_DIRECT_OFF, GFS_DIRECT_ON, GFS_DIRECT_PREFER = 0, 1, 2
+GFS_MAX_WINDOW_PAGES = 1024
+
+EV_HIT, EV_JOIN, EV_MISS, EV_HAND, EV_ALLOC, EV_REQ, EV_NOFRAME = 1, 2, 3, 4, 5, 6, 7
+HAND_FREE, HAND_SKIP, HAND_CLEAR, HAND_EVICT = 0, 1, 2, 3
+
+
+class gfs_config(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("streams_per_file", C.c_uint32),
+        ("page_size", C.c_uint64), ("cache_bytes", C.c_uint64),
+        ("ra_init_bytes", C.c_uint64), ("ra_cap_bytes", C.c_uint64),
+        ("host_threads", C.c_uint32), ("rpc_slots", C.c_uint32),
+        ("io_backend", C.c_uint32), ("o_direct", C.c_uint32),
+        ("trace_level", C.c_uint32), ("trace_capacity", C.c_uint32),
+        ("wait_timeout_ns", C.c_uint64),
+    ]
+
+
+_STAT_U64 = ["hits", "joins", "misses", "ra_pages", "fetched_pages", "evictions", "wasted_pages",
+             "hand_visits", "requests", "request_bytes", "delivered_bytes", "retries", "noframe",
+             "timeouts", "io_errors", "trace_events", "host_requests", "host_bytes", "host_read_ns"]
+
+
+class gfs_stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in _STAT_U64] + [
+        ("host_spins", C.c_uint64 * 64), ("host_threads", C.c_uint32), ("direct_io", C.c_uint32)]
+
+
+EVENT_DTYPE = np.dtype([("op", "<u4"), ("block", "<u4"), ("file", "<u4"), ("page", "<u4"),
+                        ("frame", "<u4"), ("a", "<u4"), ("b", "<u8")])
+
+_lib: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    L = C.CDLL(LIB_PATH)
+    vp, u32, u64, i32, sz = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int, C.c_size_t
+    L.gfs_config_default.argtypes = [C.POINTER(gfs_config)]
+    L.gfs_config_default.restype = None
+    L.gfs_device_bytes.argtypes = [C.POINTER(gfs_config), C.POINTER(sz), C.POINTER(sz)]
+    L.gfs_init.argtypes = [C.POINTER(gfs_config), vp, vp, vp, C.POINTER(vp)]
+    L.gfs_open.argtypes = [vp, C.c_char_p, i32, C.POINTER(i32)]
+    L.gfs_fadvise.argtypes = [vp, i32, i32]
+    L.gfs_close.argtypes = [vp, i32]
+    L.gfs_device_handle.argtypes = [vp]
+    L.gfs_device_handle.restype = vp
+    L.gfs_stats_read.argtypes = [vp, C.POINTER(gfs_stats)]
+    L.gfs_trace_read.argtypes = [vp, vp, sz, C.POINTER(sz)]
+    L.gfs_reset_cache.argtypes = [vp]
+    L.gfs_shutdown.argtypes = [vp]
+    L.gfs_launch_list_reader.argtypes = [vp, i32, vp, u32, u32, u64, u32, i32, vp, vp, vp, vp, vp]
+    for name in ("gfs_device_bytes", "gfs_init", "gfs_open", "gfs_fadvise", "gfs_close",
+                 "gfs_stats_read", "gfs_trace_read", "gfs_reset_cache", "gfs_shutdown",
+                 "gfs_launch_list_reader"):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        raise OSError(-rc, f"{what}: {os.strerror(-rc)}")
+    return rc
+
+
+# ---- thin wrappers, one per C function ---------------------------------------------------
+
+def gfs_config_default(**overrides) -> gfs_config:
+    cfg = gfs_config()
+    lib().gfs_config_default(C.byref(cfg))
+    for k, v in overrides.items():
+        if not hasattr(cfg, k):
+            raise AttributeError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+def gfs_device_bytes(cfg: gfs_config) -> Tuple[int, int]:
+    fb, mb = C.c_size_t(0), C.c_size_t(0)
+    _check(lib().gfs_device_bytes(C.byref(cfg), C.byref(fb), C.byref(mb)), "gfs_device_bytes")
+    return fb.value, mb.value
+
+
+def gfs_init(cfg: gfs_config, frames_dev: int, meta_dev: int, stream: int) -> int:
+    ctx = C.c_void_p(0)
+    _check(lib().gfs_init(C.byref(cfg), C.c_void_p(frames_dev), C.c_void_p(meta_dev),
+                          C.c_void_p(stream), C.byref(ctx)), "gfs_init")
+    return ctx.value
+
+
+def gfs_open(ctx: int, path: str, flags: int = GFS_O_RDONLY) -> int:
+    fid = C.c_int(-1)
+    _check(lib().gfs_open(C.c_void_p(ctx), path.encode(), flags, C.byref(fid)), f"gfs_open({path})")
+    return fid.value
+
+
+def gfs_fadvise(ctx: int, file_id: int, advice: int) -> None:
+    _check(lib().gfs_fadvise(C.c_void_p(ctx), file_id, advice), "gfs_fadvise")
+
+
+def gfs_close(ctx: int, file_id: int) -> None:
+    _check(lib().gfs_close(C.c_void_p(ctx), file_id), "gfs_close")
+
+
+def gfs_device_handle(ctx: int) -> int:
+    return lib().gfs_device_handle(C.c_void_p(ctx))
+
+
+def gfs_stats_read(ctx: int) -> Dict[str, object]:
+    s = gfs_stats()
+    _check(lib().gfs_stats_read(C.c_void_p(ctx), C.byref(s)), "gfs_stats_read")
+    out: Dict[str, object] = {n: int(getattr(s, n)) for n in _STAT_U64}
+    out["host_threads"] = int(s.host_threads)
+    out["host_spins"] = [int(x) for x in s.host_spins[: s.host_threads]]
+    out["direct_io"] = int(s.direct_io)
+    return out
+
+
+def gfs_trace_read(ctx: int, max_events: int) -> np.ndarray:
+    buf = np.zeros(max_events, dtype=EVENT_DTYPE)
+    n = C.c_size_t(0)
+    _check(lib().gfs_trace_read(C.c_void_p(ctx), C.c_void_p(buf.ctypes.data), buf.nbytes, C.byref(n)),
+           "gfs_trace_read")
+    return buf[: n.value // EVENT_DTYPE.itemsize].copy()
+
+
+def gfs_reset_cache(ctx: int) -> None:
+    _check(lib().gfs_reset_cache(C.c_void_p(ctx)), "gfs_reset_cache")
+
+
+def gfs_shutdown(ctx: int) -> None:
+    _check(lib().gfs_shutdown(C.c_void_p(ctx)), "gfs_shutdown")
+
+
+def gfs_launch_list_reader(ctx: int, file_id: int, offsets_dev: int, blocks: int, reads: int,
+                           read_size: int, threads: int, consumer: int, buf_dev: int, out_dev: int,
+                           status_dev: int, turn_dev: int, stream: int) -> None:
+    _check(lib().gfs_launch_list_reader(C.c_void_p(ctx), file_id, C.c_void_p(offsets_dev), blocks, reads,
+                                        read_size, threads, consumer, C.c_void_p(buf_dev),
+                                        C.c_void_p(out_dev), C.c_void_p(status_dev),
+                                        C.c_void_p(turn_dev or 0), C.c_void_p(stream)),
+           "gfs_launch_list_reader")
+
+
+# ---- convenience: a cache over torch-allocated device memory ----------------------------
+
+class PageCache:
+    """Owns the torch allocations a context needs; closes the context on close()."""
+
+    def __init__(self, cfg: gfs_config, device: str = "cuda:0", stream=None):
+        import torch
+        self.cfg = cfg
+        fb, mb = gfs_device_bytes(cfg)
+        self.frames = torch.empty(fb, dtype=torch.uint8, device=device)
+        self.meta = torch.empty(mb, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.ctx = gfs_init(cfg, self.frames.data_ptr(), self.meta.data_ptr(), self.stream.cuda_stream)
+        self.handle = gfs_device_handle(self.ctx)
+
+    def open(self, path: str, flags: int = GFS_O_RDONLY) -> int:
+        return gfs_open(self.ctx, path, flags)
+
+    def fadvise(self, fid: int, advice: int) -> None:
+        gfs_fadvise(self.ctx, fid, advice)
+
+    def close_file(self, fid: int) -> None:
+        gfs_close(self.ctx, fid)
+
+    def stats(self) -> Dict[str, object]:
+        return gfs_stats_read(self.ctx)
+
+    def trace(self, max_events: Optional[int] = None) -> np.ndarray:
+        return gfs_trace_read(self.ctx, max_events or int(self.cfg.trace_capacity))
+
+    def reset(self) -> None:
+        gfs_reset_cache(self.ctx)
+
+    def close(self) -> None:
+        if self.ctx:
+            gfs_shutdown(self.ctx)
+            self.ctx = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

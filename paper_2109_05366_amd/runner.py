@@ -1,0 +1,74 @@
+"""Launch a list-reader workload through the C-ABI (marshalling and torch allocations only)."""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+from . import gfs
+
+
+def make_config(page_size: int, cache_bytes: int, ra_cap_bytes: int = 16 << 20, ra_init_pages: int = 4,
+                streams: int = 8, host_threads: int = 8, rpc_slots: int = 64,
+                o_direct: int = gfs.GFS_DIRECT_PREFER, trace_level: int = 0, trace_capacity: int = 0,
+                timeout_s: float = 30.0) -> gfs.gfs_config:
+    cap_pages = min(ra_cap_bytes // page_size, gfs.GFS_MAX_WINDOW_PAGES)
+    init = min(ra_init_pages, cap_pages) if cap_pages else 0
+    return gfs.gfs_config_default(
+        page_size=page_size, cache_bytes=cache_bytes, ra_cap_bytes=cap_pages * page_size,
+        ra_init_bytes=init * page_size, streams_per_file=streams, host_threads=host_threads,
+        rpc_slots=rpc_slots, o_direct=o_direct, trace_level=trace_level,
+        trace_capacity=trace_capacity, wait_timeout_ns=int(timeout_s * 1e9))
+
+
+@dataclasses.dataclass
+class ListResult:
+    out: np.ndarray        # checksums [blocks] uint64 or histograms [blocks, 256] uint32
+    status: np.ndarray     # int64 [blocks]: bytes delivered or -errno
+
+
+class ListReader:
+    """Device buffers for one list-reader launch shape: offsets, user buffers, outputs."""
+
+    def __init__(self, offsets: np.ndarray, read_size: int, consumer: int, threads: int = 256,
+                 device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.blocks, self.reads = offsets.shape
+        self.read_size = read_size
+        self.consumer = consumer
+        self.threads = threads
+        self.offsets = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.uint64).view(np.int64)).to(device)
+        self.buf = torch.empty(self.blocks * read_size, dtype=torch.uint8, device=device)
+        if consumer == 0:
+            self.out = torch.zeros(self.blocks, dtype=torch.int64, device=device)
+        else:
+            self.out = torch.zeros(self.blocks * 256, dtype=torch.int32, device=device)
+        self.status = torch.zeros(self.blocks, dtype=torch.int64, device=device)
+        self.turn = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def launch(self, cache: gfs.PageCache, file_id: int, stream=None, serialize: bool = False) -> None:
+        s = stream if stream is not None else self.torch.cuda.current_stream()
+        if serialize:
+            self.turn.zero_()
+        gfs.gfs_launch_list_reader(cache.ctx, file_id, self.offsets.data_ptr(), self.blocks, self.reads,
+                                   self.read_size, self.threads, self.consumer, self.buf.data_ptr(),
+                                   self.out.data_ptr(), self.status.data_ptr(),
+                                   self.turn.data_ptr() if serialize else 0, s.cuda_stream)
+
+    def result(self) -> ListResult:
+        self.torch.cuda.synchronize()
+        st = self.status.cpu().numpy()
+        if self.consumer == 0:
+            out = self.out.cpu().numpy().view(np.uint64).copy()
+        else:
+            out = self.out.cpu().numpy().view(np.uint32).reshape(self.blocks, 256).copy()
+        return ListResult(out=out, status=st)
+
+
+def run_list(cache: gfs.PageCache, file_id: int, offsets: np.ndarray, read_size: int, consumer: int,
+             threads: int = 256, serialize: bool = False) -> ListResult:
+    r = ListReader(offsets, read_size, consumer, threads)
+    r.launch(cache, file_id, serialize=serialize)
+    return r.result()

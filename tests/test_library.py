@@ -1,0 +1,82 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared symbol, and its
+host-side configuration logic behaves as documented (no GPU calls)."""
+import ctypes
+import errno
+import os
+import re
+
+import pytest
+
+from paper_2109_05366_amd import gfs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in ("gfs.h",):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?(?:struct\s+)?[A-Za-z_][A-Za-z_0-9]*\s*\*?\s*(gfs_[a-z_0-9]+)\s*\(",
+                             src, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = gfs.lib()
+    names = _declared_functions()
+    assert "gfs_init" in names and "gfs_launch_list_reader" in names and len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/gfs.h but not exported"
+
+
+def test_config_default_values():
+    cfg = gfs.gfs_config_default()
+    assert cfg.abi_version == gfs.GFS_ABI_VERSION
+    assert cfg.page_size == 64 << 10 and cfg.cache_bytes == 256 << 20
+    assert cfg.ra_init_bytes == 4 * cfg.page_size and cfg.ra_cap_bytes == 16 << 20
+    assert cfg.streams_per_file == 8 and cfg.host_threads == 8 and cfg.rpc_slots == 64
+    assert ctypes.sizeof(gfs.gfs_config) == 72
+    assert gfs.EVENT_DTYPE.itemsize == 32
+
+
+def test_device_bytes_layout_scales_with_frames():
+    f1, m1 = gfs.gfs_device_bytes(gfs.gfs_config_default(cache_bytes=256 << 20))
+    f2, m2 = gfs.gfs_device_bytes(gfs.gfs_config_default(cache_bytes=512 << 20))
+    assert f1 == 256 << 20 and f2 == 512 << 20
+    # frame words + tags (16 B) + table (4 entries x 8 B) per frame
+    assert m2 - m1 == (4096 * (8 + 8 + 32))
+    f3, m3 = gfs.gfs_device_bytes(gfs.gfs_config_default(trace_level=1, trace_capacity=1000))
+    assert m3 - m1 >= 1000 * 32
+
+
+@pytest.mark.parametrize("field,value", [
+    ("abi_version", 99), ("page_size", 3000), ("page_size", 1 << 12 - 1), ("page_size", 4 << 20),
+    ("cache_bytes", 0), ("cache_bytes", 100 << 10), ("cache_bytes", (64 << 10) * 63),
+    ("streams_per_file", 0), ("streams_per_file", 9), ("ra_cap_bytes", 100),
+    ("ra_cap_bytes", (64 << 10) * 1025), ("host_threads", 0), ("host_threads", 65),
+    ("rpc_slots", 0), ("o_direct", 3), ("trace_level", 3), ("io_backend", 1),
+])
+def test_invalid_configs_rejected(field, value):
+    cfg = gfs.gfs_config_default()
+    setattr(cfg, field, value)
+    with pytest.raises(OSError) as e:
+        gfs.gfs_device_bytes(cfg)
+    assert e.value.errno == errno.EINVAL
+
+
+def test_readahead_init_must_fit_cap():
+    cfg = gfs.gfs_config_default(ra_cap_bytes=4 * (64 << 10), ra_init_bytes=8 * (64 << 10))
+    with pytest.raises(OSError):
+        gfs.gfs_device_bytes(cfg)
+    cfg = gfs.gfs_config_default(ra_cap_bytes=0, ra_init_bytes=0)   # readahead off
+    assert gfs.gfs_device_bytes(cfg)[0] == cfg.cache_bytes
+
+
+def test_null_arguments_rejected_without_gpu():
+    lib = gfs.lib()
+    assert lib.gfs_init(None, None, None, None, None) == -errno.EINVAL
+    assert lib.gfs_open(None, b"x", 0, None) == -errno.EINVAL
+    assert lib.gfs_shutdown(None) == -errno.EINVAL
+    assert lib.gfs_device_handle(None) is None

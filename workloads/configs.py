@@ -142,10 +142,10 @@ def c1_small() -> Workload:
 
 
 def c2_small() -> Workload:
-    """C2 shape at 1/256 scale: 32 MiB file through an 8 MiB cache, histograms."""
-    f = FileSpec("c2s_seed2.bin", 2, 32 * MiB)
-    return Workload("c2_small", f, 256 * KiB, 8 * MiB, 64, 256, 128 * KiB,
-                    strided_offsets(64, 4, 128 * KiB), CONSUMER_HISTOGRAM)
+    """C2 shape at 1/128 scale: 64 MiB file through a 16 MiB cache (64 frames), histograms."""
+    f = FileSpec("c2s_seed2.bin", 2, 64 * MiB)
+    return Workload("c2_small", f, 256 * KiB, 16 * MiB, 64, 256, 128 * KiB,
+                    strided_offsets(64, 8, 128 * KiB), CONSUMER_HISTOGRAM)
 
 
 def c3_small(pattern: str) -> Workload:
