@@ -132,6 +132,8 @@ typedef struct gfs_stats {
   uint64_t host_requests;     /* requests served by the host threads */
   uint64_t host_bytes;        /* bytes the host read from files */
   uint64_t host_read_ns;      /* summed time inside pread */
+  uint64_t host_errors;       /* host reads that returned an error */
+  uint64_t host_last_errno;   /* errno of the last failed host read (0 if none) */
   uint64_t host_spins[64];    /* per host thread: polls of the ring before its first request */
   uint32_t host_threads;
   uint32_t direct_io;         /* 1 if the last gfs_open used O_DIRECT */

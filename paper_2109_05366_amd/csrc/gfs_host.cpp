@@ -10,6 +10,7 @@
 #include <errno.h>
 #include <fcntl.h>
 #include <sched.h>
+#include <stdlib.h>
 #include <string.h>
 #include <sys/stat.h>
 #include <time.h>
@@ -116,27 +117,49 @@ struct gfs_ctx {
   std::vector<std::thread> threads;
   std::atomic<uint64_t> head{0};
   std::atomic<bool> stop{false};
-  std::atomic<uint64_t> host_requests{0}, host_bytes{0}, host_read_ns{0};
+  std::atomic<uint64_t> host_requests{0}, host_bytes{0}, host_read_ns{0}, host_errors{0};
+  std::atomic<int64_t> host_last_errno{0};
   std::atomic<uint64_t> spins[64];
   bool last_direct = false;
 };
 
 namespace {
 
-int64_t read_span(int fd, bool direct, uint8_t* dst, uint64_t off, uint64_t len) {
-  const uint64_t want = direct ? align_up(len, kDirectAlign) : len;
+constexpr uint64_t kBounceChunk = 2ull << 20;
+
+// Read file bytes [off, off+len) into dst (pinned staging). Returns bytes read (short only
+// at end of file) or -errno. Direct reads cannot target the GPU driver's pinned pages (the
+// kernel refuses to pin them for DMA, EFAULT), so they go through the thread's aligned
+// bounce buffer in chunks and are copied into staging; buffered reads go straight in.
+int64_t read_span(int fd, bool direct, uint8_t* dst, uint64_t off, uint64_t len, uint8_t* bounce) {
   uint64_t done = 0;
-  while (done < want) {
-    const ssize_t r = pread(fd, dst + done, want - done, (off_t)(off + done));
-    if (r < 0) {
-      if (errno == EINTR) continue;
-      return -(int64_t)errno;
+  if (!direct) {
+    while (done < len) {
+      const ssize_t r = pread(fd, dst + done, len - done, (off_t)(off + done));
+      if (r < 0) {
+        if (errno == EINTR) continue;
+        return -(int64_t)errno;
+      }
+      if (r == 0) break;
+      done += (uint64_t)r;
     }
-    if (r == 0) break;
-    done += (uint64_t)r;
-    if (direct && ((uint64_t)r % kDirectAlign)) break;   // short read at end of file
+    return (int64_t)done;
   }
-  return (int64_t)(done < len ? done : len);
+  while (done < len) {
+    const uint64_t want = len - done < kBounceChunk ? align_up(len - done, kDirectAlign) : kBounceChunk;
+    ssize_t r;
+    do {
+      r = pread(fd, bounce, want, (off_t)(off + done));
+    } while (r < 0 && errno == EINTR);
+    if (r < 0) return -(int64_t)errno;
+    if (r == 0) break;
+    uint64_t take = (uint64_t)r;
+    if (take > len - done) take = len - done;
+    memcpy(dst + done, bounce, take);
+    done += take;
+    if ((uint64_t)r < want) break;   // end of file
+  }
+  return (int64_t)done;
 }
 
 inline void cpu_relax() { __builtin_ia32_pause(); }
@@ -147,6 +170,8 @@ void io_thread(gfs_ctx* c, int idx) {
   const uint32_t NS = c->cfg.rpc_slots;
   bool first = true;
   uint64_t idle_spins = 0;
+  uint8_t* bounce = (uint8_t*)aligned_alloc(kDirectAlign, kBounceChunk);
+  if (!bounce) return;
   while (!c->stop.load(std::memory_order_relaxed)) {
     const uint64_t h = c->head.fetch_add(1, std::memory_order_relaxed);
     const uint32_t s = (uint32_t)(h % NS);
@@ -154,7 +179,10 @@ void io_thread(gfs_ctx* c, int idx) {
     gfs_rpc_slot* rs = &c->ring[s];
     uint64_t spins = 0;
     while (__atomic_load_n(&rs->req_seq, __ATOMIC_ACQUIRE) != gen) {
-      if (c->stop.load(std::memory_order_relaxed)) return;
+      if (c->stop.load(std::memory_order_relaxed)) {
+        free(bounce);
+        return;
+      }
       ++spins;
       if (spins < (1u << 20)) {
         cpu_relax();
@@ -178,15 +206,20 @@ void io_thread(gfs_ctx* c, int idx) {
     } else {
       uint8_t* dst = c->staging + (uint64_t)s * c->L.max_req_bytes;
       const uint64_t t0 = now_ns();
-      res = read_span(fd, hf->direct, dst, off, len);
+      res = read_span(fd, hf->direct, dst, off, len, bounce);
       c->host_read_ns.fetch_add(now_ns() - t0, std::memory_order_relaxed);
       if (res > 0) c->host_bytes.fetch_add((uint64_t)res, std::memory_order_relaxed);
+    }
+    if (res < 0) {
+      c->host_errors.fetch_add(1, std::memory_order_relaxed);
+      c->host_last_errno.store(-res, std::memory_order_relaxed);
     }
     rs->result = res;
     rs->t_done_ns = now_ns();
     __atomic_store_n(&rs->done_seq, gen, __ATOMIC_RELEASE);
     c->host_requests.fetch_add(1, std::memory_order_relaxed);
   }
+  free(bounce);
 }
 
 void start_threads(gfs_ctx* c) {
@@ -452,6 +485,8 @@ int gfs_stats_read(gfs_ctx* c, gfs_stats* out) {
   s.host_requests = c->host_requests.load();
   s.host_bytes = c->host_bytes.load();
   s.host_read_ns = c->host_read_ns.load();
+  s.host_errors = c->host_errors.load();
+  s.host_last_errno = (uint64_t)c->host_last_errno.load();
   for (uint32_t i = 0; i < 64; ++i) s.host_spins[i] = c->spins[i].load();
   s.host_threads = c->cfg.host_threads;
   s.direct_io = c->last_direct ? 1 : 0;
@@ -502,6 +537,8 @@ int gfs_reset_cache(gfs_ctx* c) {
   c->host_requests = 0;
   c->host_bytes = 0;
   c->host_read_ns = 0;
+  c->host_errors = 0;
+  c->host_last_errno = 0;
   for (auto& s : c->spins) s.store(0);
   start_threads(c);
   return rc;

@@ -39,7 +39,8 @@ class gfs_config(C.Structure):
 
 _STAT_U64 = ["hits", "joins", "misses", "ra_pages", "fetched_pages", "evictions", "wasted_pages",
              "hand_visits", "requests", "request_bytes", "delivered_bytes", "retries", "noframe",
-             "timeouts", "io_errors", "trace_events", "host_requests", "host_bytes", "host_read_ns"]
+             "timeouts", "io_errors", "trace_events", "host_requests", "host_bytes", "host_read_ns",
+             "host_errors", "host_last_errno"]
 
 
 class gfs_stats(C.Structure):
