@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Benchmark: delivered file-read GB/s of the GPU page cache, readahead on vs off.
+
+Workload (one step): the larger-than-cache sequential stream -- an 8 GiB SplitMix64 file
+(seed 2) read through a 2 GiB cache of 256 KiB pages by 1024 threadblocks x 256 threads,
+block b reading 128 KiB strides b + 1024 k (k = 0..63) and folding them into a per-block
+256-bin byte histogram. Every step starts cold: the cache is reset and file reads use
+O_DIRECT (or buffered reads after POSIX_FADV_DONTNEED where the file system has no
+O_DIRECT), so each step reads the whole file from storage.
+
+Measured in the same run: the storage peak (O_DIRECT sequential read of the same file
+with 4 threads, 4 MiB requests), the pinned host-to-device copy peak (256 MiB), the
+readahead-off rate of the same code, the list-reader kernel duration (HIP events on its
+stream), an all-hit pass over a cached file (the kernel's HBM-bound hit path), and the
+CPU oracle on a bounded sample. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import mmap
+import os
+import sys
+import threading
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def storage_peak(path: str, threads: int = 4, chunk: int = 4 << 20, limit: int = 8 << 30) -> float:
+    """O_DIRECT (if available) sequential read of the file with `threads` readers; GB/s."""
+    size = min(os.path.getsize(path), limit)
+    try:
+        fd = os.open(path, os.O_RDONLY | os.O_DIRECT)
+    except OSError:
+        fd = os.open(path, os.O_RDONLY)
+        os.posix_fadvise(fd, 0, 0, os.POSIX_FADV_DONTNEED)
+    nchunks = size // chunk
+    got = [0] * threads
+
+    def worker(t):
+        buf = mmap.mmap(-1, chunk)
+        for c in range(t, nchunks, threads):
+            got[t] += os.preadv(fd, [buf], c * chunk)
+        buf.close()
+
+    t0 = time.perf_counter()
+    ths = [threading.Thread(target=worker, args=(t,)) for t in range(threads)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    dt = time.perf_counter() - t0
+    os.close(fd)
+    return sum(got) / dt / 1e9
+
+
+def h2d_peak(torch, nbytes: int = 256 << 20, reps: int = 5) -> float:
+    src = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    best = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src, non_blocking=True)
+        e1.record()
+        e1.synchronize()
+        best = max(best, nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    return best
+
+
+def run_steps(torch, cache, fid, reader, steps: int, warmup: int):
+    """Warm-up then `steps` timed cold passes; returns (wall s, kernel ms list, stats of last)."""
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        cache.reset()
+        reader.launch(cache, fid, stream)
+        torch.cuda.synchronize()
+        log(f"  warmup {i} done")
+    kms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = None
+    for i in range(steps):
+        cache.reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        reader.launch(cache, fid, stream)
+        e1.record(stream)
+        e1.synchronize()
+        kms.append(e0.elapsed_time(e1))
+        log(f"  step {i}: kernel {kms[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = cache.stats()
+    return wall, kms, st
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--data-dir", default=None, help="where the synthetic files live")
+    ap.add_argument("--ra-cap-mib", type=int, default=16)
+    ap.add_argument("--host-threads", type=int, default=8)
+    ap.add_argument("--rpc-slots", type=int, default=64)
+    ap.add_argument("--no-ra-off", action="store_true", help="skip the readahead-off comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3a", "c3b", "c3c"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the path is per-GPU and would shard by file/chunk across GPUs, see DESIGN.md",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2109_05366_amd import gfs, runner
+    from workloads import configs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = configs.get(args.workload)
+    ddir = args.data_dir or os.environ.get("GFS_DATA_DIR") or configs.data_dir()
+    log(f"workload {wl.name}: file {wl.file.size >> 20} MiB, cache {wl.cache_bytes >> 20} MiB, "
+        f"page {wl.page_size >> 10} KiB, {wl.blocks} blocks x {wl.threads}, data dir {ddir}")
+    t = time.perf_counter()
+    path = configs.ensure_file(wl.file, ddir)
+    log(f"file ready ({time.perf_counter() - t:.1f} s): {path}")
+
+    nvme = storage_peak(path)
+    log(f"storage peak {nvme:.2f} GB/s")
+    h2d = h2d_peak(torch)
+    log(f"pinned H2D peak {h2d:.2f} GB/s")
+
+    delivered = wl.delivered_bytes
+    results = {}
+    stats = {}
+    kernel_ms = {}
+    for label, cap_mib in (("ra", args.ra_cap_mib), ("no_ra", 0)):
+        if label == "no_ra" and args.no_ra_off:
+            continue
+        cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=cap_mib << 20,
+                                 host_threads=args.host_threads, rpc_slots=args.rpc_slots, timeout_s=60)
+        with gfs.PageCache(cfg) as cache:
+            fid = cache.open(path)
+            reader = runner.ListReader(wl.offsets, wl.read_size, wl.consumer, wl.threads)
+            log(f"{label}: cap {cap_mib} MiB")
+            wall, kms, st = run_steps(torch, cache, fid, reader, args.steps, args.warmup)
+            res = reader.result()
+        if st["timeouts"] or st["io_errors"]:
+            raise RuntimeError(f"{label}: device errors {st}")
+        if not np.array_equal(res.status, np.full(wl.blocks, delivered // wl.blocks)):
+            raise RuntimeError(f"{label}: wrong delivered byte counts")
+        results[label] = {"wall_s": wall, "GBps": args.steps * delivered / wall / 1e9,
+                          "kernel_GBps": delivered / (np.mean(kms) * 1e-3) / 1e9,
+                          "out": res.out}
+        stats[label] = {k: st[k] for k in ("hits", "joins", "misses", "ra_pages", "fetched_pages",
+                                           "evictions", "wasted_pages", "requests", "request_bytes",
+                                           "host_bytes", "retries", "noframe")}
+        kernel_ms[label] = float(np.mean(kms))
+        log(f"{label}: {results[label]['GBps']:.2f} GB/s wall, {results[label]['kernel_GBps']:.2f} GB/s kernel")
+
+    # parity on sampled blocks against the oracle (the full run's outputs)
+    from oracle import data as odata
+    rng = np.random.default_rng(0)
+    sample = sorted(set(int(x) for x in rng.integers(0, wl.blocks, size=4)) | {0, wl.blocks - 1})
+    if wl.consumer == configs.CONSUMER_HISTOGRAM:
+        want = odata.block_histograms(path, wl.offsets, wl.read_size, blocks=sample)
+    else:
+        want = odata.block_checksums(path, wl.offsets, wl.read_size, blocks=sample)
+    parity_ok = all(np.array_equal(r["out"][sample], want[sample]) for r in results.values())
+    if not parity_ok:
+        raise RuntimeError("parity failure on sampled blocks")
+
+    # all-hit pass: a 1 GiB file held entirely in a 2 GiB cache, read twice; the second pass
+    # is lookup + pin + copy-out + consumer only
+    hit = None
+    hf = configs.FileSpec("hit_seed9_1GiB.bin", 9, 1 << 30)
+    hpath = configs.ensure_file(hf, ddir)
+    hoff = configs.strided_offsets(1024, 16, 64 << 10)
+    hcfg = runner.make_config(64 << 10, 2 << 30, ra_cap_bytes=16 << 20, host_threads=args.host_threads,
+                              timeout_s=60)
+    with gfs.PageCache(hcfg) as cache:
+        fid = cache.open(hpath)
+        reader = runner.ListReader(hoff, 64 << 10, configs.CONSUMER_CHECKSUM, 256)
+        reader.launch(cache, fid)
+        torch.cuda.synchronize()
+        s0 = cache.stats()
+        hms = []
+        stream = torch.cuda.current_stream()
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            reader.launch(cache, fid, stream)
+            e1.record(stream)
+            e1.synchronize()
+            hms.append(e0.elapsed_time(e1))
+        s1 = cache.stats()
+    hbytes = 1 << 30
+    hk = float(np.median(hms))
+    hit = {"workload": "1 GiB file cached in a 2 GiB cache (64 KiB pages), 1024 blocks x 16 reads of 64 KiB, all hits",
+           "kernel_ms": hk, "delivered_GBps": hbytes / (hk * 1e-3) / 1e9,
+           "hbm_GBps": 3 * hbytes / (hk * 1e-3) / 1e9,
+           "misses_after_warm": s1["misses"] - s0["misses"]}
+    log(f"hit path: {hit['delivered_GBps']:.1f} GB/s delivered, {hit['hbm_GBps']:.1f} GB/s HBM")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cblocks = list(range(0, wl.blocks, max(1, wl.blocks // 64)))[:64]
+        t0 = time.perf_counter()
+        if wl.consumer == configs.CONSUMER_HISTOGRAM:
+            odata.block_histograms(path, wl.offsets, wl.read_size, blocks=cblocks)
+        else:
+            odata.block_checksums(path, wl.offsets, wl.read_size, blocks=cblocks)
+        dt = time.perf_counter() - t0
+        cbytes = len(cblocks) * wl.reads_per_block * wl.read_size
+        cpu = {"value": cbytes / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(cblocks)} of {wl.blocks} blocks ({cbytes >> 20} MiB): plain pread + "
+                         f"numpy per-block {'histograms' if wl.consumer else 'checksums'}, {dt:.1f} s"}
+        log(f"cpu oracle: {cpu['value']:.2f} GB/s on {cbytes >> 20} MiB")
+
+    ra = results["ra"]
+    value = ra["GBps"]
+    bound_name = "storage" if nvme < h2d else "h2d"
+    min_peak = min(nvme, h2d)
+    # dominant kernel: the list reader; algorithmic HBM bytes per delivered byte = 3
+    # (frame fill write, copy-out read, user-buffer write)
+    kms_ra = kernel_ms["ra"]
+    achieved = 3 * delivered / (kms_ra * 1e-3) / 1e9
+    line = {
+        "metric": "delivered file-read GB/s (readahead vs none) + fraction of min(NVMe, H2D) peak",
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ra["wall_s"] / args.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.file.size >> 30} GiB splitmix64(seed={wl.file.seed}) file, "
+                               f"{wl.cache_bytes >> 30} GiB cache, {wl.page_size >> 10} KiB pages, "
+                               f"{wl.blocks} blocks x {wl.threads} threads, {wl.read_size >> 10} KiB reads, "
+                               f"cold per step",
+                   "ra_cap_MiB": args.ra_cap_mib, "host_threads": args.host_threads,
+                   "rpc_slots": args.rpc_slots, "data_dir": ddir},
+        "readahead_off_GBps": round(results["no_ra"]["GBps"], 3) if "no_ra" in results else None,
+        "readahead_speedup": round(value / results["no_ra"]["GBps"], 3) if "no_ra" in results else None,
+        "storage_peak_GBps": round(nvme, 3),
+        "h2d_peak_GBps": round(h2d, 3),
+        "frac_of_min_peak": round(value / min_peak, 3),
+        "io_bound": {"bound": bound_name, "achieved": round(value, 3), "peak": round(min_peak, 3),
+                     "unit": "GB/s", "frac": round(value / min_peak, 3)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": "list_reader_kernel", "kernel_ms": round(kms_ra, 2),
+                     "bytes_per_launch": 3 * delivered},
+        "hit_path": hit,
+        "kernel_GBps": {k: round(v["kernel_GBps"], 3) for k, v in results.items()},
+        "stats": stats,
+        "parity_sampled_blocks": sample,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

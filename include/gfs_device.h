@@ -328,7 +328,14 @@ __device__ void unlock_file_wave(const gfs_dev* d, uint32_t file) {
 /* ------------------------------------------------------------------ readahead detector
  * Wave-collective, under the file's miss lock. Streams live in the file record; lane i
  * looks at stream slot i. Sec. 2.3 (Linux readahead: per-descriptor sequential streams,
- * window doubled up to a maximum) and Sec. 4 (GPU-side window, RANDOM hint disables it). */
+ * window doubled up to a maximum, several interleaved readers followed on one file) and
+ * Sec. 4 (GPU-side window, RANDOM hint disables it). A miss inside a stream's zone
+ * [next, next+size) doubles that stream's window. Otherwise a new stream replaces an empty
+ * or the least recently used slot: if several of the file's recent misses are near p the
+ * file is being read in aggregate by many blocks and the window is the cap-sized aligned
+ * chunk around p; else the history of cached pages right behind p sizes it (context
+ * readahead); with neither, it opens with the initial window at offset 0 or under
+ * SEQUENTIAL advice, else with one page. */
 __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint64_t& ws,
                                uint32_t& wn) {
   gfs_file_dev* fe = &d->files[file];
@@ -337,12 +344,26 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint
   wn = 1;
   if (d->ra_cap == 0 || advice == GFS_ADV_RANDOM) return;
   const uint32_t l = lane();
+  const uint32_t cap = d->ra_cap;
   uint32_t clk = 0;
   if (l == 0) {
     clk = ld_rlx32(&fe->clock) + 1;
     st_rlx32(&fe->clock, clk);
   }
   clk = __shfl(clk, 0, 64);
+  /* how many of the file's last misses lie near p; then remember p */
+  const uint64_t radius = cap > GFS_NEAR_PAGES ? cap : GFS_NEAR_PAGES;
+  const uint32_t rn = ld_rlx32(&fe->recent_n);
+  bool near_l = false;
+  if (l < GFS_RECENT_MISSES && l < rn) {
+    const uint64_t r = ld_rlx(&fe->recent[l]);
+    near_l = r + radius >= p && r <= p + radius;
+  }
+  const uint32_t near = (uint32_t)__popcll(__ballot(near_l));
+  if (l == 0) {
+    st_rlx(&fe->recent[rn % GFS_RECENT_MISSES], p);
+    st_rlx32(&fe->recent_n, rn + 1);
+  }
   uint64_t s_next = 0;
   uint32_t s_size = 0, s_last = 0, s_valid = 0;
   if (l < d->streams) {
@@ -355,16 +376,13 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint
   const bool cov = l < d->streams && s_valid && s_next <= p && p < s_next + s_size;
   const uint64_t cm = __ballot(cov);
   int j;
-  uint64_t new_next;
-  uint32_t new_size;
   if (cm) {
+    /* p is inside a stream's zone: double that stream's window from its frontier */
     j = __ffsll((unsigned long long)cm) - 1;
     const uint64_t nx = __shfl(s_next, j, 64);
     const uint32_t sz = __shfl(s_size, j, 64);
     ws = nx;
-    wn = 2 * sz < d->ra_cap ? 2 * sz : d->ra_cap;
-    new_next = ws + wn;
-    new_size = wn;
+    wn = 2 * sz < cap ? 2 * sz : cap;
   } else {
     const uint64_t inv = __ballot(l < d->streams && !s_valid);
     if (inv) {
@@ -377,18 +395,37 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint
       }
       j = (int)(k & 0xff);
     }
-    uint32_t w0 = (p == 0 || advice == GFS_ADV_SEQUENTIAL) ? d->ra_init : 1u;
-    if (w0 > d->ra_cap) w0 = d->ra_cap;
-    if (w0 < 1) w0 = 1;
-    ws = p;
-    wn = w0;
-    new_next = p + w0;
-    new_size = w0;
+    if (near >= GFS_NEAR_MIN) {
+      /* many blocks missing close together: the file is read in aggregate (interleaved
+         strides); take the cap-sized chunk aligned around p */
+      wn = cap;
+      ws = p - p % cap;
+    } else {
+      /* context: count the consecutive cached pages right behind p (64 per round); a
+         stream that no slot tracks shows up as that history */
+      uint32_t h = 0;
+      while (h < cap) {
+        const uint64_t back = (uint64_t)h + 1 + l;
+        bool mapped = false;
+        if (back <= p && h + l < cap) mapped = pt_find_lane(d, page_key(file, p - back)) >= 0;
+        const uint64_t m = __ballot(mapped);
+        const uint32_t run = (~m == 0ull) ? 64u : (uint32_t)__builtin_ctzll(~m);
+        h += run;
+        if (run < 64) break;
+      }
+      uint32_t w0;
+      if (h > 0) w0 = 2 * h;
+      else w0 = (p == 0 || advice == GFS_ADV_SEQUENTIAL) ? d->ra_init : 1u;
+      if (w0 > cap) w0 = cap;
+      if (w0 < 1) w0 = 1;
+      ws = p;
+      wn = w0;
+    }
   }
   if (l == 0) {
     gfs_stream* s = &fe->streams[j];
-    st_rlx(&s->next, new_next);
-    st_rlx32(&s->size, new_size);
+    st_rlx(&s->next, ws + wn);
+    st_rlx32(&s->size, wn);
     st_rlx32(&s->last_use, clk);
     st_rlx32(&s->valid, 1u);
   }
@@ -540,18 +577,38 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
         ra_decide_wave(d, file, p, ws, wn);
         const uint64_t npages = d->files[file].npages;
         if (ws + wn > npages) wn = (uint32_t)(npages - ws);
-        if (l == 0) {
-          trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, GFS_NO_FRAME, wn, ws);
-          sh->list[0] = (uint32_t)p;
+        if (l == 0) trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, GFS_NO_FRAME, wn, ws);
+        /* the run of unmapped window pages around p, [a, b]: one request without holes */
+        uint64_t a = p;
+        for (uint64_t base = p; base > ws;) {
+          const bool valid = (uint64_t)l < base - ws;
+          bool stop = !valid;
+          if (valid) stop = pt_find_lane(d, page_key(file, base - 1 - l)) >= 0;
+          const uint64_t sm = __ballot(stop);
+          const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
+          a = base - k;
+          if (k < 64) break;
+          base -= 64;
         }
-        uint32_t n = 1;
-        for (uint64_t base = ws; base < ws + wn; base += 64) {
-          const uint64_t q = base + l;
-          bool want = false;
-          if (q < ws + wn && q != p) want = pt_find_lane(d, page_key(file, q)) < 0;
-          const uint64_t m = __ballot(want);
-          if (want) sh->list[n + __popcll(m & lanemask_lt())] = (uint32_t)q;
-          n += (uint32_t)__popcll(m);
+        uint64_t b = p;
+        for (uint64_t base = p + 1; base < ws + wn;) {
+          const bool valid = (uint64_t)l < ws + wn - base;
+          bool stop = !valid;
+          if (valid) stop = pt_find_lane(d, page_key(file, base + l)) >= 0;
+          const uint64_t sm = __ballot(stop);
+          const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
+          b = base + k - 1;
+          if (k < 64) break;
+          base += 64;
+        }
+        const uint32_t n = (uint32_t)(b - a + 1);
+        /* allocation order: the demanded page first, then the rest of the run ascending */
+        for (uint32_t i = l; i < n; i += 64) {
+          uint64_t q;
+          if (i == 0) q = p;
+          else if (i <= p - a) q = a + i - 1;
+          else q = a + i;
+          sh->list[i] = (uint32_t)q;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
@@ -578,9 +635,9 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
           }
         }
         for (int off = 32; off > 0; off >>= 1) {
-          const uint64_t a = __shfl_xor(lo, off, 64), b = __shfl_xor(hi, off, 64);
-          lo = a < lo ? a : lo;
-          hi = b > hi ? b : hi;
+          const uint64_t olo = __shfl_xor(lo, off, 64), ohi = __shfl_xor(hi, off, 64);
+          lo = olo < lo ? olo : lo;
+          hi = ohi > hi ? ohi : hi;
         }
         unlock_file_wave(d, file);
         if (lo > hi) {

@@ -7,7 +7,7 @@
  * HBM layout of the metadata region (offsets computed by the host, stored in gfs_dev):
  *   gfs_globals                      256 B
  *   gfs_dev (the handle)             512 B
- *   files[GFS_MAX_FILES]             224 B each
+ *   files[GFS_MAX_FILES]             512 B each
  *   names[GFS_MAX_FILES]             GFS_NAME_MAX B each (registered paths)
  *   fword[nframes]  u64              frame word (state, pins, ref, ra, version)
  *   ftag[nframes]   u64              key of the page held (valid while not FREE)
@@ -60,6 +60,10 @@ enum {
   GFS_C_NOFRAME, GFS_C_TIMEOUTS, GFS_C_IOERR, GFS_C_COUNT
 };
 
+#define GFS_RECENT_MISSES 32   /* misses remembered per file by the readahead detector */
+#define GFS_NEAR_MIN 3         /* remembered misses near a miss that mark aggregate reading */
+#define GFS_NEAR_PAGES 64      /* "near" = within max(ra_cap, GFS_NEAR_PAGES) pages */
+
 typedef struct gfs_stream {
   uint64_t next;          /* first page after the last window */
   uint32_t size;          /* last window length (pages) */
@@ -77,7 +81,10 @@ typedef struct gfs_file_dev {
   uint32_t clock;         /* readahead decision counter (stream last_use) */
   uint32_t handles;       /* device gopen count minus gclose count */
   gfs_stream streams[8];  /* 192 B */
-} gfs_file_dev;           /* 224 B */
+  uint64_t recent[GFS_RECENT_MISSES];  /* pages of the last misses (ring) */
+  uint32_t recent_n;      /* misses pushed into the ring so far */
+  uint32_t pad[7];
+} gfs_file_dev;           /* 512 B */
 
 #define GFS_NAME_MAX 256     /* registered path, NUL-terminated, for gopen(path) */
 

@@ -31,6 +31,7 @@ class NaiveModel:
         self.advice = {}
         self.streams = {}
         self.tick = {}
+        self.last_misses = {}
         self.log = []
 
     def open(self, file_id, size, advice="normal"):
@@ -38,6 +39,7 @@ class NaiveModel:
         self.advice[file_id] = advice
         self.streams[file_id] = [[False, 0, 0, 0] for _ in range(self.nstreams)]
         self.tick[file_id] = 0
+        self.last_misses[file_id] = []
 
     def _window(self, file_id, p):
         if self.cap == 0 or self.advice[file_id] == "random":
@@ -45,6 +47,15 @@ class NaiveModel:
         self.tick[file_id] = self.tick[file_id] + 1
         now = self.tick[file_id]
         table = self.streams[file_id]
+        hist = self.last_misses[file_id]
+        reach = self.cap if self.cap > 64 else 64
+        close = 0
+        for r in hist:
+            if p - reach <= r <= p + reach:
+                close += 1
+        hist.append(p)
+        while len(hist) > 32:
+            del hist[0]
         i = 0
         while i < len(table):
             st = table[i]
@@ -56,6 +67,11 @@ class NaiveModel:
                 table[i] = [True, start + n, n, now]
                 return start, n
             i += 1
+        behind = 0
+        q = p - 1
+        while q >= 0 and behind < self.cap and _find(self.frames, file_id, q) >= 0:
+            behind += 1
+            q -= 1
         slot = -1
         for i in range(len(table)):
             if not table[i][0]:
@@ -66,7 +82,13 @@ class NaiveModel:
             for i in range(1, len(table)):
                 if table[i][3] < table[slot][3]:
                     slot = i
-        if p == 0 or self.advice[file_id] == "sequential":
+        start = p
+        if close >= 3:
+            n = self.cap
+            start = p - p % n
+        elif behind > 0:
+            n = 2 * behind
+        elif p == 0 or self.advice[file_id] == "sequential":
             n = self.w0
         else:
             n = 1
@@ -74,8 +96,8 @@ class NaiveModel:
             n = self.cap
         if n < 1:
             n = 1
-        table[slot] = [True, p + n, n, now]
-        return p, n
+        table[slot] = [True, start + n, n, now]
+        return start, n
 
     def _take_frame(self):
         C = len(self.frames)
@@ -122,9 +144,15 @@ class NaiveModel:
                 if start + n > npages:
                     n = npages - start
                 self.log.append(("MISS", block, file_id, page, start, n))
+                lo = page
+                while lo > start and _find(self.frames, file_id, lo - 1) < 0:
+                    lo -= 1
+                hi = page
+                while hi < start + n - 1 and _find(self.frames, file_id, hi + 1) < 0:
+                    hi += 1
                 todo = [page]
-                for q in range(start, start + n):
-                    if q != page and _find(self.frames, file_id, q) < 0:
+                for q in range(lo, hi + 1):
+                    if q != page:
                         todo.append(q)
                 got = []
                 for q in todo:

@@ -25,10 +25,16 @@ Readings where the paper is silent (the same list is in the design notes):
 window = [s.next, s.next + min(2 s.size, cap)) for a stream s whose zone
 [s.next, s.next + s.size) holds the missed page p (lowest slot wins); otherwise a
 new stream replaces an empty slot or the least recently used one (lowest index
-on ties) with window [p, p + w), w = W0 if p == 0 or the file is SEQUENTIAL, else
-1; windows are clamped to EOF; the demanded page is allocated first, then the
-other unmapped window pages in ascending order; one host request covers the span
-of allocated pages; the prefetch is synchronous (the requester waits for the
+on ties): if at least 3 of the file's last 32 misses lie within max(cap, 64) pages
+of p, many blocks are reading the file in aggregate (interleaved strides) and the
+window is the cap-sized chunk aligned around p; else [p, p + w) with w = min(2 h,
+cap) if the h >= 1 pages right before p are already cached (context readahead:
+Linux's way of following readers that interleave on one descriptor, Sec. 2.3); else
+w = W0 if p == 0 or the file is SEQUENTIAL, else 1. Windows are clamped to EOF; the
+block fetches the run of unmapped window pages that contains p (pages beyond a
+mapped page are left for later demand, so a request has no holes); the demanded
+page is allocated first, then the rest of the run in ascending order; one host
+request covers the run; the prefetch is synchronous (the requester waits for the
 whole window); a filled frame gets its reference bit set; a pin sets it and
 clears the unconsumed-prefetch mark; the hand starts at frame 0, skips frames
 that are filling or pinned, clears a set reference bit, and otherwise evicts.
@@ -49,6 +55,9 @@ import dataclasses
 from typing import Dict, List, Optional, Tuple
 
 FREE, FILLING, VALID = "FREE", "FILLING", "VALID"
+RECENT = 32          # misses remembered per file
+NEAR_MIN = 3         # remembered misses near p that make the file look read in aggregate
+NEAR_PAGES = 64      # "near" = within max(cap, NEAR_PAGES) pages
 ADV_NORMAL, ADV_SEQUENTIAL, ADV_RANDOM = "normal", "sequential", "random"
 
 
@@ -77,6 +86,7 @@ class FileState:
     read_only: bool = True
     streams: List[Stream] = dataclasses.field(default_factory=list)
     clock: int = 0          # per-file count of readahead decisions (stream last_use)
+    recent: List[int] = dataclasses.field(default_factory=list)   # last RECENT misses (pages)
 
 
 class PolicyModel:
@@ -124,6 +134,11 @@ class PolicyModel:
         if self.cap == 0 or fs.advice == ADV_RANDOM or not fs.read_only:
             return p, 1
         fs.clock += 1
+        radius = max(self.cap, NEAR_PAGES)
+        near = sum(1 for r in fs.recent if abs(r - p) <= radius)
+        fs.recent.append(p)
+        if len(fs.recent) > RECENT:
+            fs.recent.pop(0)
         for s in fs.streams:                       # lowest slot index wins
             if s.valid and s.next <= p < s.next + s.size:
                 ws = s.next
@@ -132,6 +147,11 @@ class PolicyModel:
                 s.size = wn
                 s.last_use = fs.clock
                 return ws, wn
+        # context: the pages right behind p are already cached (read or being read by other
+        # blocks), so p continues a sequential stream that no slot tracks
+        h = 0
+        while h < self.cap and p - 1 - h >= 0 and (file_id, p - 1 - h) in self.map:
+            h += 1
         victim = None
         for s in fs.streams:                       # an empty slot first (lowest index)
             if not s.valid:
@@ -139,13 +159,23 @@ class PolicyModel:
                 break
         if victim is None:                         # else least recently used, lowest index on ties
             victim = min(fs.streams, key=lambda s: s.last_use)
-        wn = self.W0 if (p == 0 or fs.advice == ADV_SEQUENTIAL) else 1
+        if near >= NEAR_MIN:
+            # many blocks missing close together: the file is read in aggregate (interleaved
+            # strides), take the whole cap-sized aligned chunk around p
+            wn = self.cap
+            ws = p // wn * wn
+        elif h > 0:
+            wn = min(2 * h, self.cap)
+            ws = p
+        else:
+            wn = self.W0 if (p == 0 or fs.advice == ADV_SEQUENTIAL) else 1
+            ws = p
         wn = max(1, min(wn, self.cap))
         victim.valid = True
-        victim.next = p + wn
+        victim.next = ws + wn
         victim.size = wn
         victim.last_use = fs.clock
-        return p, wn
+        return ws, wn
 
     # ---- clock ----------------------------------------------------------------------------
     def alloc(self) -> Optional[int]:
@@ -192,7 +222,14 @@ class PolicyModel:
         ws, wn = self.ra_decide(file_id, p)
         wn = min(wn, self.npages(file_id) - ws)
         self.events.append(("MISS", block, file_id, p, ws, wn))
-        order = [p] + [q for q in range(ws, ws + wn) if q != p and (file_id, q) not in self.map]
+        # fetch the run of unmapped window pages that contains p (no holes in a request)
+        a = p
+        while a - 1 >= ws and (file_id, a - 1) not in self.map:
+            a -= 1
+        b = p
+        while b + 1 < ws + wn and (file_id, b + 1) not in self.map:
+            b += 1
+        order = [p] + [q for q in range(a, b + 1) if q != p]
         allocated = []
         for q in order:
             g = self.alloc()

@@ -222,3 +222,38 @@ def test_brute_force_against_naive_model(case):
         outcomes.add(tuple(_evicted(m.events)))
         n += 1
     assert n > 1 and len(outcomes) >= 1
+
+
+def test_context_readahead_follows_a_stream_no_slot_tracks():
+    # hand-worked, one stream slot: 0 opens [0,4); 100 takes the only slot; 4 is outside every
+    # zone, but pages 0..3 right behind it are cached, so it is sequential with history 4:
+    # window [4, 4 + min(2*4, cap)) (Sec. 2.3: Linux follows interleaved readers of one file)
+    m = PolicyModel(nframes=64, page_size=4096, ra_init_pages=4, ra_cap_pages=16, streams_per_file=1)
+    m.open(0, 1 << 20)
+    for p in (0, 100, 4):
+        m.gread(0, 0, p * 4096, 4096)
+    assert [(e[4], e[5]) for e in _misses(m.events)] == [(0, 4), (100, 1), (4, 8)]
+    # with no history behind it a page outside every zone is on probation (window 1)
+    m.gread(0, 0, 200 * 4096, 4096)
+    assert _misses(m.events)[-1][4:] == (200, 1)
+
+
+def test_aggregate_read_takes_aligned_cap_chunk():
+    # hand-worked, one slot, cap 16 (near = within 64 pages): misses at 10, 30, 50 each start a
+    # probation stream; at 70 three of the last misses are near, so the block takes the aligned
+    # chunk [64, 80) -- the interleaved-strides case where many blocks miss close together
+    m = PolicyModel(nframes=256, page_size=4096, ra_init_pages=4, ra_cap_pages=16, streams_per_file=1)
+    m.open(0, 1 << 20)
+    for p in (10, 30, 50, 70):
+        m.gread(0, 0, p * 4096, 4096)
+    assert [(e[4], e[5]) for e in _misses(m.events)] == [(10, 1), (30, 1), (50, 1), (64, 16)]
+    assert [e for e in m.events if e[0] == "REQ"][-1] == ("REQ", 0, 64, 16)
+
+
+def test_request_is_the_unmapped_run_around_the_miss():
+    # window [0, 8) with page 5 already cached: the miss at 0 fetches the run [0, 5) only
+    m = PolicyModel(nframes=64, page_size=4096, ra_init_pages=8, ra_cap_pages=8, streams_per_file=1)
+    m.open(0, 1 << 20)
+    m.gread(0, 0, 5 * 4096, 4096)                  # page 5: probation window of 1
+    m.gread(0, 0, 0, 4096)                         # page 0: W0 = 8 -> [0, 8), run stops at 5
+    assert [e for e in m.events if e[0] == "REQ"][-1] == ("REQ", 0, 0, 5)
