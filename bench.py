@@ -204,7 +204,9 @@ def main() -> int:
                           "out": res.out}
         stats[label] = {k: st[k] for k in ("hits", "joins", "misses", "ra_pages", "fetched_pages",
                                            "evictions", "wasted_pages", "requests", "request_bytes",
-                                           "host_bytes", "retries", "noframe")}
+                                           "host_bytes", "retries", "noframe", "host_read_ns",
+                                           "t_lock_ns", "t_crit_ns", "t_alloc_ns", "t_slot_ns",
+                                           "t_host_ns", "t_pull_ns", "t_join_ns")}
         kernel_ms[label] = float(np.mean(kms))
         log(f"{label}: {results[label]['GBps']:.2f} GB/s wall, {results[label]['kernel_GBps']:.2f} GB/s kernel")
 

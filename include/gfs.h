@@ -132,6 +132,14 @@ typedef struct gfs_stats {
   uint64_t host_requests;     /* requests served by the host threads */
   uint64_t host_bytes;        /* bytes the host read from files */
   uint64_t host_read_ns;      /* summed time inside pread */
+  /* device time by phase of the miss path, summed over blocks (ns) */
+  uint64_t t_lock_ns;         /* waiting for a file's miss lock */
+  uint64_t t_crit_ns;         /* holding it (readahead decision, run, reservations) */
+  uint64_t t_alloc_ns;        /* clock allocation and table updates */
+  uint64_t t_slot_ns;         /* waiting for a free ring slot */
+  uint64_t t_host_ns;         /* waiting for the host read */
+  uint64_t t_pull_ns;         /* pulling staging into frames and publishing them */
+  uint64_t t_join_ns;         /* waiting on frames other blocks are filling */
   uint64_t host_errors;       /* host reads that returned an error */
   uint64_t host_last_errno;   /* errno of the last failed host read (0 if none) */
   uint64_t host_spins[64];    /* per host thread: polls of the ring before its first request */
@@ -156,7 +164,8 @@ typedef struct gfs_event {
 enum {
   GFS_EV_HIT = 1,    /* file,page,frame                                         */
   GFS_EV_JOIN = 2,   /* file,page,frame                                         */
-  GFS_EV_MISS = 3,   /* file,page; a = window length (EOF-clamped), b = window start */
+  GFS_EV_MISS = 3,   /* file,page; a = window length (EOF-clamped), b = window start,
+                        frame = recent misses of the file near page (detector input) */
   GFS_EV_HAND = 4,   /* frame; b = ticket; a = action | ra<<8; file,page = victim (EVICT) */
   GFS_EV_ALLOC = 5,  /* file,page,frame; a = ra (1 if prefetched)               */
   GFS_EV_REQ = 6,    /* file, page = first page, a = pages in span, b = ring ticket */

@@ -3,7 +3,9 @@
  * Include from HIP code compiled for gfx950. The functions are block-collective
  * (Sec. 2.2: each threadblock issues a file call by invoking it from all of its
  * threads): every thread of the block must call them with the same arguments, and
- * every thread gets the same result. Blocks must have a multiple of 64 threads.
+ * every thread gets the same result. Blocks must have a multiple of 64 threads. A
+ * kernel must obtain its descriptor with gopen/gopen_id before calling gread, and
+ * should gclose it at the end: the block's statistics are flushed there.
  *
  *   int     gopen (const gfs_dev* d, const char* path, int flags);
  *       Resolve a path registered with gfs_open (path: NUL-terminated, device-readable
@@ -22,11 +24,12 @@
  * How a read is served (Sec. 2.2 and Sec. 4.1): the request is divided into pages; each
  * page is looked up in the hashed page table and, on a hit, pinned and copied out. On a
  * miss the block takes the file's miss lock, asks the readahead detector for a window,
- * allocates frames for the window's unmapped pages with the clock hand (evicting in place,
- * Sec. 5.1), posts one request for the span to the host ring and waits for it
+ * reserves the run of unmapped window pages around the miss in the page table, and
+ * unlocks; it then gives the reserved pages frames with the clock hand (evicting in
+ * place, Sec. 5.1), posts one request for the run to the host ring and waits for it
  * (synchronous prefetch, Sec. 4), pulls the fetched bytes from pinned staging into the
  * frames, publishes them, and copies its own page out. Blocks that find a page whose
- * frame is still being filled wait for it instead of fetching it again.
+ * frame is reserved or still being filled wait for it instead of fetching it again.
  */
 #ifndef GFS_DEVICE_H
 #define GFS_DEVICE_H
@@ -43,9 +46,11 @@ constexpr int kENOENT = 2, kEIO = 5, kEBADF = 9, kEINVAL = 22, kENOSPC = 28, kER
               kETIMEDOUT = 110;
 constexpr uint32_t kMaxWindow = GFS_MAX_WINDOW_PAGES;
 constexpr uint64_t kFrameMask = (1ull << GFS_ENTRY_FRAME_BITS) - 1;
+/* page-table entry frame value of a page reserved by a miss that has no frame yet */
+constexpr uint32_t kReserved = (uint32_t)kFrameMask;
 
-/* Per-block scratch for one page access (LDS). */
-struct ReadShared {
+/* Per-block state in LDS, shared by gopen/gread/gclose within one kernel. */
+struct BlockState {
   int64_t status;           /* 0 or -errno for the current page */
   int64_t result;           /* host read result for the request this block pulls */
   uint64_t first_page;      /* first page of the request span */
@@ -53,12 +58,19 @@ struct ReadShared {
   int32_t frame;            /* pinned frame of the current page */
   int32_t pull;             /* 1: this block must pull its request into the frames */
   uint32_t slot;            /* ring slot of the request */
-  uint32_t list_n;          /* pages in list[] */
+  uint32_t list_n;          /* pages in list[] that got frames (a prefix) */
   uint32_t file;
-  uint32_t pad;
-  uint32_t list[kMaxWindow];    /* window pages to allocate: the demanded page, then ascending */
+  int32_t open_result;
+  uint64_t ctr[GFS_C_COUNT];    /* block-local statistics, added to the globals by gclose */
+  uint32_t list[kMaxWindow];    /* run pages: the demanded page, then the rest ascending */
   uint32_t lframe[kMaxWindow];  /* frame given to list[k], or GFS_NO_FRAME */
+  uint32_t lslot[kMaxWindow];   /* page-table slot reserved for list[k] (0xffffffff: none) */
 };
+
+__device__ __forceinline__ BlockState* block_state() {
+  __shared__ BlockState gfs_block_state;
+  return &gfs_block_state;
+}
 
 /* ------------------------------------------------------------------ thread / wave ids */
 __device__ __forceinline__ uint32_t thread_id() {
@@ -72,6 +84,11 @@ __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const uint32_t l = __lane_id();
   return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 /* ------------------------------------------------------------------ atomics (agent scope) */
@@ -97,6 +114,10 @@ __device__ __forceinline__ bool cas64(uint64_t* p, uint64_t& expected, uint64_t 
   return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL,
                                               __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ bool cas64_rlx(uint64_t* p, uint64_t& expected, uint64_t desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ bool cas32(uint32_t* p, uint32_t& expected, uint32_t desired) {
   return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL,
                                               __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -104,15 +125,20 @@ __device__ __forceinline__ bool cas32(uint32_t* p, uint32_t& expected, uint32_t 
 __device__ __forceinline__ uint64_t fadd64(uint64_t* p, uint64_t v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void count(const gfs_dev* d, int c, uint64_t v) {
-  if (v) fadd64(&d->g->ctr[c], v);
-}
+/* block-local statistics: only thread 0 of the block (lane 0 of wave 0) adds */
+__device__ __forceinline__ void bcount(BlockState* bs, int c, uint64_t v) { bs->ctr[c] += v; }
 
 /* ------------------------------------------------------------------ waiting */
 __device__ __forceinline__ void nap(uint32_t& n) {
   if (n < 8) __builtin_amdgcn_s_sleep(2);
   else if (n < 64) __builtin_amdgcn_s_sleep(16);
   else __builtin_amdgcn_s_sleep(127);
+  ++n;
+}
+/* shorter naps for the miss lock, whose holder keeps it for a few microseconds */
+__device__ __forceinline__ void nap_short(uint32_t& n) {
+  if (n < 16) __builtin_amdgcn_s_sleep(2);
+  else __builtin_amdgcn_s_sleep(24);
   ++n;
 }
 __device__ __forceinline__ bool expired(const gfs_dev* d, uint64_t t0) {
@@ -138,9 +164,10 @@ __device__ __forceinline__ void trace_ev(const gfs_dev* d, uint32_t level, uint3
 
 /* ------------------------------------------------------------------ hashed page table
  * Two candidate buckets of 16 entries (128 B) per key; an entry is key<<24 | frame and is
- * written and cleared only by compare-and-swap. Lookups take no lock. Inserts of a file's
- * keys happen under that file's miss lock, so one key is never inserted twice; clearing
- * is done by the evictor that claimed the frame. */
+ * changed only by atomics. Lookups take no lock. A file's keys are inserted only under
+ * that file's miss lock, first as reservations (frame field kReserved), so one key is never
+ * inserted twice; the reserving block later stores the frame into its own entry, or
+ * clears it. An evicting block clears the entry of the frame it claimed. */
 __device__ __forceinline__ uint64_t page_key(uint32_t file, uint64_t page) {
   return ((uint64_t)(file + 1) << GFS_KEY_PAGE_BITS) | page;
 }
@@ -159,88 +186,101 @@ __device__ __forceinline__ void key_buckets(const gfs_dev* d, uint64_t key, uint
   b2 = (uint32_t)(h >> 32) & d->nbuckets_mask;
   if (b2 == b1) b2 = b1 ^ 1u;
 }
+__device__ __forceinline__ uint64_t* slot_ptr(const gfs_dev* d, uint32_t b1, uint32_t b2, int i) {
+  return d->pt + (uint64_t)(i < GFS_BUCKET_SLOTS ? b1 : b2) * GFS_BUCKET_SLOTS + (i & 15);
+}
 
-/* wave-collective: lanes 0-15 read bucket 1, lanes 16-31 bucket 2; uniform result */
+/* wave-collective: lanes 0-15 read bucket 1, lanes 16-31 bucket 2; uniform result: the
+ * frame, kReserved, or -1 when absent */
 __device__ int32_t pt_lookup_wave(const gfs_dev* d, uint64_t key) {
   uint32_t b1, b2;
   key_buckets(d, key, b1, b2);
   const uint32_t l = lane();
   uint64_t e = 0;
-  if (l < 32) e = ld_rlx(&d->pt[(uint64_t)(l < 16 ? b1 : b2) * GFS_BUCKET_SLOTS + (l & 15)]);
+  if (l < 32) e = ld_rlx(slot_ptr(d, b1, b2, (int)l));
   const uint64_t m = __ballot(l < 32 && (e >> GFS_ENTRY_FRAME_BITS) == key);
   if (m == 0) return -1;
   const uint64_t hit = __shfl(e, __ffsll((unsigned long long)m) - 1, 64);
   return (int32_t)(hit & kFrameMask);
 }
 
-/* per lane */
-__device__ int32_t pt_find_lane(const gfs_dev* d, uint64_t key) {
-  uint32_t b[2];
-  key_buckets(d, key, b[0], b[1]);
-  for (int j = 0; j < 2; ++j) {
-    uint64_t* bk = d->pt + (uint64_t)b[j] * GFS_BUCKET_SLOTS;
-    uint64_t e[GFS_BUCKET_SLOTS];
+/* per lane: the 32 candidate entries of a key, loaded together (one round trip) */
+__device__ __forceinline__ void pt_load_lane(const gfs_dev* d, uint32_t b1, uint32_t b2,
+                                             uint64_t e[2 * GFS_BUCKET_SLOTS]) {
 #pragma unroll
-    for (int i = 0; i < GFS_BUCKET_SLOTS; ++i) e[i] = ld_rlx(&bk[i]);
+  for (int i = 0; i < 2 * GFS_BUCKET_SLOTS; ++i) e[i] = ld_rlx(slot_ptr(d, b1, b2, i));
+}
+
+/* per lane: true if key has an entry (a frame or a reservation) */
+__device__ bool pt_present_lane(const gfs_dev* d, uint64_t key) {
+  uint32_t b1, b2;
+  key_buckets(d, key, b1, b2);
+  uint64_t e[2 * GFS_BUCKET_SLOTS];
+  pt_load_lane(d, b1, b2, e);
+  bool hit = false;
 #pragma unroll
-    for (int i = 0; i < GFS_BUCKET_SLOTS; ++i)
-      if ((e[i] >> GFS_ENTRY_FRAME_BITS) == key) return (int32_t)(e[i] & kFrameMask);
+  for (int i = 0; i < 2 * GFS_BUCKET_SLOTS; ++i) hit |= (e[i] >> GFS_ENTRY_FRAME_BITS) == key;
+  return hit;
+}
+
+/* per lane, under key's file lock: reserve key; returns the global slot index or -1 if
+ * both buckets are full */
+__device__ int64_t pt_reserve_lane(const gfs_dev* d, uint64_t key) {
+  const uint64_t ent = (key << GFS_ENTRY_FRAME_BITS) | kReserved;
+  uint32_t b1, b2;
+  key_buckets(d, key, b1, b2);
+  for (int attempt = 0; attempt < 256; ++attempt) {
+    uint64_t e[2 * GFS_BUCKET_SLOTS];
+    pt_load_lane(d, b1, b2, e);
+    int cnt1 = 0, cnt2 = 0, f1 = -1, f2 = -1;
+#pragma unroll
+    for (int i = 0; i < GFS_BUCKET_SLOTS; ++i) {
+      if (e[i]) ++cnt1;
+      else if (f1 < 0) f1 = i;
+      if (e[GFS_BUCKET_SLOTS + i]) ++cnt2;
+      else if (f2 < 0) f2 = GFS_BUCKET_SLOTS + i;
+    }
+    int pick = cnt2 < cnt1 ? f2 : f1;   /* less loaded bucket, ties to the first */
+    if (pick < 0) pick = f1 >= 0 ? f1 : f2;
+    if (pick < 0) return -1;
+    uint64_t expect = 0;
+    uint64_t* sp = slot_ptr(d, b1, b2, pick);
+    if (cas64_rlx(sp, expect, ent)) return (int64_t)(sp - d->pt);
   }
   return -1;
 }
 
-__device__ bool pt_insert_lane(const gfs_dev* d, uint64_t key, uint32_t frame) {
-  const uint64_t ent = (key << GFS_ENTRY_FRAME_BITS) | frame;
-  uint32_t b[2];
-  key_buckets(d, key, b[0], b[1]);
-  for (int attempt = 0; attempt < 256; ++attempt) {
-    int cnt[2] = {0, 0}, first[2] = {-1, -1};
-    for (int j = 0; j < 2; ++j) {
-      uint64_t* bk = d->pt + (uint64_t)b[j] * GFS_BUCKET_SLOTS;
-      uint64_t e[GFS_BUCKET_SLOTS];
-#pragma unroll
-      for (int i = 0; i < GFS_BUCKET_SLOTS; ++i) e[i] = ld_rlx(&bk[i]);
-#pragma unroll
-      for (int i = 0; i < GFS_BUCKET_SLOTS; ++i) {
-        if (e[i] != 0) ++cnt[j];
-        else if (first[j] < 0) first[j] = i;
-      }
-    }
-    int j = cnt[1] < cnt[0] ? 1 : 0;   /* less loaded bucket, ties to the first */
-    if (first[j] < 0) j ^= 1;
-    if (first[j] < 0) return false;
-    uint64_t expect = 0;
-    if (cas64(&d->pt[(uint64_t)b[j] * GFS_BUCKET_SLOTS + first[j]], expect, ent)) return true;
-  }
-  return false;
-}
-
+/* per lane: clear the entry key -> frame (the caller owns it) */
 __device__ bool pt_delete_lane(const gfs_dev* d, uint64_t key, uint32_t frame) {
   const uint64_t ent = (key << GFS_ENTRY_FRAME_BITS) | frame;
-  uint32_t b[2];
-  key_buckets(d, key, b[0], b[1]);
-  for (int j = 0; j < 2; ++j) {
-    uint64_t* bk = d->pt + (uint64_t)b[j] * GFS_BUCKET_SLOTS;
-    for (int i = 0; i < GFS_BUCKET_SLOTS; ++i) {
-      uint64_t e = ld_rlx(&bk[i]);
-      if (e == ent && cas64(&bk[i], e, 0ull)) return true;
-    }
-  }
-  return false;
+  uint32_t b1, b2;
+  key_buckets(d, key, b1, b2);
+  uint64_t e[2 * GFS_BUCKET_SLOTS];
+  pt_load_lane(d, b1, b2, e);
+  int at = -1;
+#pragma unroll
+  for (int i = 0; i < 2 * GFS_BUCKET_SLOTS; ++i)
+    if (at < 0 && e[i] == ent) at = i;
+  if (at < 0) return false;
+  uint64_t expect = ent;
+  return cas64_rlx(slot_ptr(d, b1, b2, at), expect, 0ull);
 }
 
 /* ------------------------------------------------------------------ frame words */
-enum { PIN_RETRY = 0, PIN_VALID = 1, PIN_FILLING = 2 };
+enum { PIN_RETRY = 0, PIN_VALID = 1, PIN_FILLING = 2, PIN_ERROR = 3 };
 
+/* Drop a pin. Relaxed: the caller's reads of the frame have completed (a block barrier
+ * waits for them) before this is issued, and unpinning publishes nothing. */
 __device__ void frame_unpin(const gfs_dev* d, uint32_t f) {
   uint64_t* fw = &d->fword[f];
   uint64_t w = ld_rlx(fw);
-  while (!cas64(fw, w, w - GFS_FW_PIN_ONE + GFS_FW_VER_ONE)) {
+  while (!cas64_rlx(fw, w, w - GFS_FW_PIN_ONE + GFS_FW_VER_ONE)) {
   }
 }
 
 /* Pin frame f if it is filling or valid and still holds key; sets the reference bit and
- * clears the prefetched mark (the page has now been demanded). */
+ * clears the prefetched mark (the page has now been demanded). Acquire: a valid frame's
+ * bytes, published with release by the block that filled it, are visible afterwards. */
 __device__ int frame_pin(const gfs_dev* d, uint32_t f, uint64_t key) {
   uint64_t* fw = &d->fword[f];
   uint64_t w = ld_rlx(fw);
@@ -254,6 +294,10 @@ __device__ int frame_pin(const gfs_dev* d, uint32_t f, uint64_t key) {
         frame_unpin(d, f);
         return PIN_RETRY;
       }
+      if (st == GFS_FS_VALID && (w & GFS_FW_ERR)) {
+        frame_unpin(d, f);   /* the host read of this page failed */
+        return PIN_ERROR;
+      }
       return st == GFS_FS_VALID ? PIN_VALID : PIN_FILLING;
     }
   }
@@ -265,15 +309,18 @@ __device__ int frame_pin(const gfs_dev* d, uint32_t f, uint64_t key) {
 __device__ int hand_visit(const gfs_dev* d, uint32_t f, uint64_t& vkey, uint32_t& vra) {
   uint64_t* fw = &d->fword[f];
   uint64_t w = ld_rlx(fw);
+  const uint64_t tag = ld_rlx(&d->ftag[f]);   /* loaded with the word; used only on EVICT */
   const uint64_t st = w & GFS_FW_STATE;
   const uint64_t claimed = (((w >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT) | GFS_FS_CLAIMED;
   if (st == GFS_FS_FREE) return cas64(fw, w, claimed) ? GFS_HAND_FREE : GFS_HAND_SKIP;
   if (st != GFS_FS_VALID || (w & GFS_FW_PINS)) return GFS_HAND_SKIP;
   if (w & GFS_FW_REF)
-    return cas64(fw, w, (w & ~GFS_FW_REF) + GFS_FW_VER_ONE) ? GFS_HAND_CLEAR : GFS_HAND_SKIP;
+    return cas64_rlx(fw, w, (w & ~GFS_FW_REF) + GFS_FW_VER_ONE) ? GFS_HAND_CLEAR : GFS_HAND_SKIP;
   const uint64_t old = w;
   if (!cas64(fw, w, claimed)) return GFS_HAND_SKIP;
-  vkey = ld_rlx(&d->ftag[f]);
+  /* the tag read with the word is still the frame's: a tag is rewritten only by the block
+     that claims the frame, and the CAS just succeeded against the word read with it */
+  vkey = tag;
   vra = (old & GFS_FW_RA) ? 1u : 0u;
   return GFS_HAND_EVICT;
 }
@@ -292,37 +339,48 @@ __device__ int64_t wait_valid_lane(const gfs_dev* d, uint32_t f, uint64_t t0) {
     }
     if (expired(d, t0)) {
       frame_unpin(d, f);
-      count(d, GFS_C_TIMEOUTS, 1);
       return -kETIMEDOUT;
     }
     nap(n);
   }
 }
 
-/* ------------------------------------------------------------------ per-file miss lock */
-__device__ bool lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t t0) {
-  uint32_t* lk = &d->files[file].lock;
+/* ------------------------------------------------------------------ per-file miss lock
+ * A FIFO ticket lock: blocks get the lock in arrival order, which keeps the readers of a
+ * file together (an unfair lock lets a few blocks run far ahead and spreads the misses
+ * over the whole file). Waiters sleep in proportion to their distance from the head. */
+__device__ bool lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t t0, uint32_t& ticket) {
+  gfs_file_lock* lk = &d->locks[file];
   int ok = 0;
+  uint32_t t = 0;
   if (lane() == 0) {
-    uint32_t n = 0;
+    t = __hip_atomic_fetch_add(&lk->next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     while (true) {
-      uint32_t e = 0;
-      if (ld_rlx32(lk) == 0 && cas32(lk, e, 1u)) {
+      const uint32_t s = ld_rlx32(&lk->serving);
+      if (s == t) {
         ok = 1;
         break;
       }
       if (expired(d, t0)) break;
-      nap(n);
+      const uint32_t dist = t - s;
+      if (dist <= 1) {
+        __builtin_amdgcn_s_sleep(4);
+      } else {
+        const uint32_t reps = dist < 16 ? dist : 16;
+        for (uint32_t i = 0; i < reps; ++i) __builtin_amdgcn_s_sleep(32);
+      }
     }
   }
   ok = __shfl(ok, 0, 64);
+  ticket = __shfl(t, 0, 64);
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return ok != 0;
 }
-__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file) {
+__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint32_t ticket) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   if (lane() == 0)
-    __hip_atomic_store(&d->files[file].lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&d->locks[file].serving, ticket + 1, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
 }
 
 /* ------------------------------------------------------------------ readahead detector
@@ -337,33 +395,21 @@ __device__ void unlock_file_wave(const gfs_dev* d, uint32_t file) {
  * readahead); with neither, it opens with the initial window at offset 0 or under
  * SEQUENTIAL advice, else with one page. */
 __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint64_t& ws,
-                               uint32_t& wn) {
+                               uint32_t& wn, uint32_t& near_out) {
   gfs_file_dev* fe = &d->files[file];
   const uint32_t advice = ld_rlx32(&fe->advice);
   ws = p;
   wn = 1;
+  near_out = 0;
   if (d->ra_cap == 0 || advice == GFS_ADV_RANDOM) return;
   const uint32_t l = lane();
   const uint32_t cap = d->ra_cap;
+  /* every load the decision needs, issued together */
   uint32_t clk = 0;
-  if (l == 0) {
-    clk = ld_rlx32(&fe->clock) + 1;
-    st_rlx32(&fe->clock, clk);
-  }
-  clk = __shfl(clk, 0, 64);
-  /* how many of the file's last misses lie near p; then remember p */
-  const uint64_t radius = cap > GFS_NEAR_PAGES ? cap : GFS_NEAR_PAGES;
+  if (l == 0) clk = ld_rlx32(&fe->clock);
   const uint32_t rn = ld_rlx32(&fe->recent_n);
-  bool near_l = false;
-  if (l < GFS_RECENT_MISSES && l < rn) {
-    const uint64_t r = ld_rlx(&fe->recent[l]);
-    near_l = r + radius >= p && r <= p + radius;
-  }
-  const uint32_t near = (uint32_t)__popcll(__ballot(near_l));
-  if (l == 0) {
-    st_rlx(&fe->recent[rn % GFS_RECENT_MISSES], p);
-    st_rlx32(&fe->recent_n, rn + 1);
-  }
+  uint64_t r = 0;
+  if (l < GFS_RECENT_MISSES) r = ld_rlx(&fe->recent[l]);
   uint64_t s_next = 0;
   uint32_t s_size = 0, s_last = 0, s_valid = 0;
   if (l < d->streams) {
@@ -372,6 +418,17 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint
     s_size = ld_rlx32(&s->size);
     s_last = ld_rlx32(&s->last_use);
     s_valid = ld_rlx32(&s->valid);
+  }
+  clk = __shfl(clk, 0, 64) + 1;
+  /* how many of the file's last misses lie near p; then remember p */
+  const uint64_t radius = GFS_NEAR_PAGES;
+  const bool near_l = l < GFS_RECENT_MISSES && l < rn && r + radius >= p && r <= p + radius;
+  const uint32_t near = (uint32_t)__popcll(__ballot(near_l));
+  near_out = near;
+  if (l == 0) {
+    st_rlx32(&fe->clock, clk);
+    st_rlx(&fe->recent[rn % GFS_RECENT_MISSES], p);
+    st_rlx32(&fe->recent_n, rn + 1);
   }
   const bool cov = l < d->streams && s_valid && s_next <= p && p < s_next + s_size;
   const uint64_t cm = __ballot(cov);
@@ -407,7 +464,7 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint
       while (h < cap) {
         const uint64_t back = (uint64_t)h + 1 + l;
         bool mapped = false;
-        if (back <= p && h + l < cap) mapped = pt_find_lane(d, page_key(file, p - back)) >= 0;
+        if (back <= p && h + l < cap) mapped = pt_present_lane(d, page_key(file, p - back));
         const uint64_t m = __ballot(mapped);
         const uint32_t run = (~m == 0ull) ? 64u : (uint32_t)__builtin_ctzll(~m);
         h += run;
@@ -432,16 +489,19 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint
 }
 
 /* ------------------------------------------------------------------ clock allocation
- * Wave-collective, under the miss lock. Gives frames to sh->list[0..n) in order: each
+ * Wave-collective, outside the miss lock. Gives frames to bs->list[0..n) in order: each
  * round takes as many consecutive hand tickets as pages remain, visits those frames in
  * parallel, and hands the k-th successful ticket to the next unserved page, which is the
- * order a one-at-a-time hand would produce. Returns how many pages got frames (a prefix
- * of the list); stops after 2 * nframes visits without enough frames. */
-__device__ uint32_t alloc_wave(const gfs_dev* d, uint32_t file, uint64_t demand, ReadShared* sh,
+ * order a one-at-a-time hand would produce. Each page that gets a frame is tagged, made
+ * FILLING (pinned for the demanded page, marked prefetched otherwise) and its reserved
+ * table entry is pointed at the frame. Returns how many pages got frames (a prefix of the
+ * list); stops after 2 * nframes visits without enough frames. */
+__device__ uint32_t alloc_wave(const gfs_dev* d, uint32_t file, uint64_t demand, BlockState* bs,
                                uint32_t n, uint32_t bid) {
   const uint32_t l = lane();
   uint32_t assigned = 0;
   uint64_t visits = 0;
+  uint32_t evicted = 0, wasted = 0;
   const uint64_t limit = 2ull * d->nframes;
   while (assigned < n && visits < limit) {
     const uint32_t need = (n - assigned) < 64u ? (n - assigned) : 64u;
@@ -466,38 +526,32 @@ __device__ uint32_t alloc_wave(const gfs_dev* d, uint32_t file, uint64_t demand,
     }
     const bool ok = (act == GFS_HAND_FREE || act == GFS_HAND_EVICT);
     const uint64_t sm = __ballot(ok);
+    evicted += (uint32_t)__popcll(__ballot(act == GFS_HAND_EVICT));
+    wasted += (uint32_t)__popcll(__ballot(act == GFS_HAND_EVICT && vra));
     if (ok) {
       const uint32_t k = assigned + (uint32_t)__popcll(sm & lanemask_lt());
-      const uint64_t q = sh->list[k];
-      if (act == GFS_HAND_EVICT) {
-        pt_delete_lane(d, vkey, f);
-        count(d, GFS_C_EVICTIONS, 1);
-        if (vra) count(d, GFS_C_WASTED, 1);
-      }
+      const uint64_t q = bs->list[k];
+      if (act == GFS_HAND_EVICT) pt_delete_lane(d, vkey, f);
       const uint64_t key = page_key(file, q);
       st_rlx(&d->ftag[f], key);
-      const uint64_t w = ld_rlx(&d->fword[f]);   /* CLAIMED by this lane */
-      uint64_t nw = (((w >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT) | GFS_FS_FILLING;
+      uint64_t nw = (((ld_rlx(&d->fword[f]) >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT) |
+                    GFS_FS_FILLING;
       if (q == demand) nw += GFS_FW_PIN_ONE;
       else nw |= GFS_FW_RA;
       st_rel(&d->fword[f], nw);
-      if (pt_insert_lane(d, key, f)) {
-        sh->lframe[k] = f;
-        trace_ev(d, 1, GFS_EV_ALLOC, bid, file, (uint32_t)q, f, q == demand ? 0u : 1u, 0);
-      } else {
-        /* page table full: give the frame back */
-        st_rlx(&d->ftag[f], 0ull);
-        st_rel(&d->fword[f], ((nw >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT);
-        sh->lframe[k] = GFS_NO_FRAME;
-      }
+      st_rel(d->pt + bs->lslot[k], (key << GFS_ENTRY_FRAME_BITS) | f);
+      bs->lframe[k] = f;
+      trace_ev(d, 1, GFS_EV_ALLOC, bid, file, (uint32_t)q, f, q == demand ? 0u : 1u, 0);
     }
-    count(d, GFS_C_HAND, l == 0 ? need : 0);
+    if (l == 0) bcount(bs, GFS_C_HAND, need);
     assigned += (uint32_t)__popcll(sm);
     visits += need;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  if (l == 0) {
+    bcount(bs, GFS_C_EVICTIONS, evicted);
+    bcount(bs, GFS_C_WASTED, wasted);
+  }
+  wave_sync_lds();
   return assigned;
 }
 
@@ -532,204 +586,241 @@ __device__ __forceinline__ void copy_block(uint8_t* dst, const uint8_t* src, uin
 }
 
 /* ------------------------------------------------------------------ one page, wave 0
- * Leaves in sh: status; on success the pinned frame, and pull = 1 when this block posted
+ * Leaves in bs: status; on success the pinned frame, and pull = 1 when this block posted
  * the request and must pull it. */
 __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint64_t fsize,
-                                  ReadShared* sh, uint32_t bid) {
+                                  BlockState* bs, uint32_t bid) {
   const uint64_t key = page_key(file, p);
   const uint32_t l = lane();
   const uint64_t t0 = wall_clock64();
   uint32_t naps = 0;
   while (true) {
     int32_t f = pt_lookup_wave(d, key);
-    if (f >= 0) {
+    if (f >= 0 && (uint32_t)f != kReserved) {
       int r = PIN_RETRY;
       if (l == 0) r = frame_pin(d, (uint32_t)f, key);
       r = __shfl(r, 0, 64);
       if (r == PIN_VALID) {
         if (l == 0) {
-          count(d, GFS_C_HITS, 1);
+          bcount(bs, GFS_C_HITS, 1);
           trace_ev(d, 2, GFS_EV_HIT, bid, file, (uint32_t)p, (uint32_t)f, 0, 0);
-          sh->frame = f;
-          sh->status = 0;
-          sh->pull = 0;
+          bs->frame = f;
+          bs->status = 0;
+          bs->pull = 0;
         }
         return;
       }
       if (r == PIN_FILLING) {
         if (l == 0) {
-          count(d, GFS_C_JOINS, 1);
+          bcount(bs, GFS_C_JOINS, 1);
           trace_ev(d, 2, GFS_EV_JOIN, bid, file, (uint32_t)p, (uint32_t)f, 0, 0);
-          sh->status = wait_valid_lane(d, (uint32_t)f, t0);
-          sh->frame = f;
-          sh->pull = 0;
+          const uint64_t tj0 = wall_clock64();
+          const int64_t st = wait_valid_lane(d, (uint32_t)f, t0);
+          bcount(bs, GFS_T_JOIN, wall_clock64() - tj0);
+          if (st == -kETIMEDOUT) bcount(bs, GFS_C_TIMEOUTS, 1);
+          bs->status = st;
+          bs->frame = f;
+          bs->pull = 0;
         }
         return;
       }
-      if (l == 0) count(d, GFS_C_RETRIES, 1);
-    } else {
-      if (!lock_file_wave(d, file, t0)) break;
-      f = pt_lookup_wave(d, key);
-      if (f < 0) {
-        /* miss: decide the window, allocate, publish, unlock, post, wait */
-        uint64_t ws;
-        uint32_t wn;
-        ra_decide_wave(d, file, p, ws, wn);
-        const uint64_t npages = d->files[file].npages;
-        if (ws + wn > npages) wn = (uint32_t)(npages - ws);
-        if (l == 0) trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, GFS_NO_FRAME, wn, ws);
-        /* the run of unmapped window pages around p, [a, b]: one request without holes */
-        uint64_t a = p;
-        for (uint64_t base = p; base > ws;) {
-          const bool valid = (uint64_t)l < base - ws;
-          bool stop = !valid;
-          if (valid) stop = pt_find_lane(d, page_key(file, base - 1 - l)) >= 0;
-          const uint64_t sm = __ballot(stop);
-          const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
-          a = base - k;
-          if (k < 64) break;
-          base -= 64;
+      if (r == PIN_ERROR) {
+        if (l == 0) {
+          bs->status = -kEIO;
+          bs->frame = -1;
+          bs->pull = 0;
         }
-        uint64_t b = p;
-        for (uint64_t base = p + 1; base < ws + wn;) {
-          const bool valid = (uint64_t)l < ws + wn - base;
-          bool stop = !valid;
-          if (valid) stop = pt_find_lane(d, page_key(file, base + l)) >= 0;
-          const uint64_t sm = __ballot(stop);
-          const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
-          b = base + k - 1;
-          if (k < 64) break;
-          base += 64;
-        }
-        const uint32_t n = (uint32_t)(b - a + 1);
-        /* allocation order: the demanded page first, then the rest of the run ascending */
-        for (uint32_t i = l; i < n; i += 64) {
-          uint64_t q;
-          if (i == 0) q = p;
-          else if (i <= p - a) q = a + i - 1;
-          else q = a + i;
-          sh->list[i] = (uint32_t)q;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        const uint32_t got = alloc_wave(d, file, p, sh, n, bid);
-        if (got == 0) {
-          /* every frame pinned or filling: back off and retry the access */
-          unlock_file_wave(d, file);
-          if (l == 0) count(d, GFS_C_NOFRAME, 1);
-          if (expired(d, t0)) break;
-          if (l == 0) nap(naps);
-          continue;
-        }
-        if (got < n && l == 0)
-          trace_ev(d, 1, GFS_EV_NOFRAME, bid, file, sh->list[got], GFS_NO_FRAME, 0, 0);
-        /* span of the pages that got frames (a page-table insert can fail only if the
-           table is full; such pages are left out of the request) */
-        uint64_t lo = ~0ull, hi = 0;
-        for (uint32_t k = l; k < got; k += 64) {
-          if (sh->lframe[k] != GFS_NO_FRAME) {
-            const uint64_t q = sh->list[k];
-            lo = q < lo ? q : lo;
-            hi = q > hi ? q : hi;
-          }
-        }
+        return;
+      }
+      if (l == 0) bcount(bs, GFS_C_RETRIES, 1);
+    } else if (f < 0) {
+      const uint64_t tl0 = wall_clock64();
+      uint32_t ticket;
+      if (!lock_file_wave(d, file, t0, ticket)) break;
+      const uint64_t tl1 = wall_clock64();
+      if (l == 0) bcount(bs, GFS_T_LOCK, tl1 - tl0);
+      if (pt_lookup_wave(d, key) >= 0) {
+        unlock_file_wave(d, file, ticket);   /* filled or reserved meanwhile: go to the pin path */
+        if (l == 0) bcount(bs, GFS_T_CRIT, wall_clock64() - tl1);
+        continue;
+      }
+      /* miss: decide the window, reserve the run of unmapped pages around p, unlock */
+      uint64_t ws;
+      uint32_t wn, near;
+      ra_decide_wave(d, file, p, ws, wn, near);
+      const uint64_t npages = d->files[file].npages;
+      if (ws + wn > npages) wn = (uint32_t)(npages - ws);
+      if (l == 0) trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, near, wn, ws);
+      uint64_t a = p;
+      for (uint64_t base = p; base > ws;) {
+        const bool valid = (uint64_t)l < base - ws;
+        bool stop = !valid;
+        if (valid) stop = pt_present_lane(d, page_key(file, base - 1 - l));
+        const uint64_t sm = __ballot(stop);
+        const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
+        a = base - k;
+        if (k < 64) break;
+        base -= 64;
+      }
+      uint64_t b = p;
+      for (uint64_t base = p + 1; base < ws + wn;) {
+        const bool valid = (uint64_t)l < ws + wn - base;
+        bool stop = !valid;
+        if (valid) stop = pt_present_lane(d, page_key(file, base + l));
+        const uint64_t sm = __ballot(stop);
+        const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
+        b = base + k - 1;
+        if (k < 64) break;
+        base += 64;
+      }
+      const uint32_t n = (uint32_t)(b - a + 1);
+      /* allocation order: the demanded page first, then the rest of the run ascending */
+      uint32_t failed = 0;
+      for (uint32_t i = l; i < n; i += 64) {
+        uint64_t q;
+        if (i == 0) q = p;
+        else if (i <= p - a) q = a + i - 1;
+        else q = a + i;
+        const int64_t slot = pt_reserve_lane(d, page_key(file, q));
+        bs->list[i] = (uint32_t)q;
+        bs->lslot[i] = slot < 0 ? 0xffffffffu : (uint32_t)slot;
+        bs->lframe[i] = GFS_NO_FRAME;
+        failed |= slot < 0 ? 1u : 0u;
+      }
+      failed = (uint32_t)(__ballot(failed != 0) != 0);
+      unlock_file_wave(d, file, ticket);
+      wave_sync_lds();
+      const uint64_t tl2 = wall_clock64();
+      if (l == 0) bcount(bs, GFS_T_CRIT, tl2 - tl1);
+      /* a reservation can fail only if both buckets are full: keep the prefix before the
+         first failure (the demanded page comes first) and drop the rest */
+      uint32_t keep = n;
+      if (failed) {
+        uint32_t firstbad = n;
+        for (uint32_t i = l; i < n; i += 64)
+          if (bs->lslot[i] == 0xffffffffu) firstbad = i < firstbad ? i : firstbad;
         for (int off = 32; off > 0; off >>= 1) {
-          const uint64_t olo = __shfl_xor(lo, off, 64), ohi = __shfl_xor(hi, off, 64);
-          lo = olo < lo ? olo : lo;
-          hi = ohi > hi ? ohi : hi;
+          const uint32_t o = __shfl_xor(firstbad, off, 64);
+          firstbad = o < firstbad ? o : firstbad;
         }
-        unlock_file_wave(d, file);
-        if (lo > hi) {
+        keep = firstbad;
+      }
+      const uint32_t got = keep ? alloc_wave(d, file, p, bs, keep, bid) : 0;
+      if (l == 0) bcount(bs, GFS_T_ALLOC, wall_clock64() - tl2);
+      /* release reservations that got no frame (the table was full or no frame was free) */
+      for (uint32_t i = got + l; i < n; i += 64) {
+        if (bs->lslot[i] != 0xffffffffu)
+          st_rel(d->pt + bs->lslot[i], 0ull);
+      }
+      if (got == 0) {
+        if (l == 0) bcount(bs, keep ? GFS_C_NOFRAME : GFS_C_RETRIES, 1);
+        if (keep == 0) {
           if (l == 0) {
-            sh->status = -kENOSPC;
-            sh->pull = 0;
-            sh->frame = -1;
+            bs->status = -kENOSPC;
+            bs->pull = 0;
+            bs->frame = -1;
           }
           return;
         }
-        /* post the request for the span [lo, hi] */
-        const uint32_t span = (uint32_t)(hi - lo + 1);
-        const uint64_t off0 = lo << d->page_shift;
-        uint64_t len = (uint64_t)span << d->page_shift;
-        if (off0 + len > fsize) len = fsize - off0;
+        if (expired(d, t0)) break;
+        if (l == 0) nap(naps);
+        continue;   /* every frame pinned or filling: back off and retry the access */
+      }
+      if (got < n && l == 0)
+        trace_ev(d, 1, GFS_EV_NOFRAME, bid, file, bs->list[got], GFS_NO_FRAME, 0, 0);
+      /* span of the pages that got frames: p and a contiguous piece of the run */
+      uint64_t lo = ~0ull, hi = 0;
+      for (uint32_t k = l; k < got; k += 64) {
+        const uint64_t q = bs->list[k];
+        lo = q < lo ? q : lo;
+        hi = q > hi ? q : hi;
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t olo = __shfl_xor(lo, off, 64), ohi = __shfl_xor(hi, off, 64);
+        lo = olo < lo ? olo : lo;
+        hi = ohi > hi ? ohi : hi;
+      }
+      /* post the request for the span [lo, hi] and wait for the host */
+      const uint32_t span = (uint32_t)(hi - lo + 1);
+      const uint64_t off0 = lo << d->page_shift;
+      uint64_t len = (uint64_t)span << d->page_shift;
+      if (off0 + len > fsize) len = fsize - off0;
+      if (l == 0) {
         int64_t status = 0;
-        if (l == 0) {
-          const uint64_t t = fadd64(&d->g->ring_tail, 1);
-          const uint32_t s = (uint32_t)(t % d->rpc_slots);
-          const uint64_t gen = t / d->rpc_slots + 1;
-          uint32_t nn = 0;
-          while (ld_acq(&d->slot_free[s]) != gen - 1) {
+        const uint64_t t = fadd64(&d->g->ring_tail, 1);
+        const uint32_t s = (uint32_t)(t % d->rpc_slots);
+        const uint64_t gen = t / d->rpc_slots + 1;
+        uint32_t nn = 0;
+        const uint64_t ts0 = wall_clock64();
+        while (ld_acq(&d->slot_free[s]) != gen - 1) {
+          if (expired(d, t0)) {
+            status = -kETIMEDOUT;
+            break;
+          }
+          nap(nn);
+        }
+        const uint64_t ts1 = wall_clock64();
+        bcount(bs, GFS_T_SLOT, ts1 - ts0);
+        if (status == 0) {
+          gfs_rpc_slot* rs = &d->ring[s];
+          rs->file_id = file;
+          rs->npages = span;
+          rs->offset = off0;
+          rs->length = len;
+          rs->ticket = t;
+          __hip_atomic_store(&rs->req_seq, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+          trace_ev(d, 1, GFS_EV_REQ, bid, file, (uint32_t)lo, GFS_NO_FRAME, span, t);
+          bcount(bs, GFS_C_MISSES, 1);
+          bcount(bs, GFS_C_REQUESTS, 1);
+          bcount(bs, GFS_C_REQ_BYTES, len);
+          bcount(bs, GFS_C_FETCHED, got);
+          bcount(bs, GFS_C_RA_PAGES, got - 1);
+          nn = 0;
+          while (__hip_atomic_load(&rs->done_seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) !=
+                 gen) {
             if (expired(d, t0)) {
               status = -kETIMEDOUT;
               break;
             }
             nap(nn);
           }
-          if (status == 0) {
-            gfs_rpc_slot* rs = &d->ring[s];
-            rs->file_id = file;
-            rs->npages = span;
-            rs->offset = off0;
-            rs->length = len;
-            rs->ticket = t;
-            __hip_atomic_store(&rs->req_seq, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-            trace_ev(d, 1, GFS_EV_REQ, bid, file, (uint32_t)lo, GFS_NO_FRAME, span, t);
-            count(d, GFS_C_MISSES, 1);
-            count(d, GFS_C_REQUESTS, 1);
-            count(d, GFS_C_REQ_BYTES, len);
-            count(d, GFS_C_FETCHED, got);
-            count(d, GFS_C_RA_PAGES, got - 1);
-            nn = 0;
-            while (__hip_atomic_load(&rs->done_seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) !=
-                   gen) {
-              if (expired(d, t0)) {
-                status = -kETIMEDOUT;
-                break;
-              }
-              nap(nn);
-            }
-            sh->result = rs->result;
-          }
-          if (status) count(d, GFS_C_TIMEOUTS, 1);
-          /* the demanded page is list[0]; if it alone failed to enter the table the block
-             still pulls the rest of the window, then reports -ENOSPC */
-          const bool demand_ok = sh->lframe[0] != GFS_NO_FRAME;
-          sh->status = status ? status : (demand_ok ? 0 : -kENOSPC);
-          sh->frame = demand_ok ? (int32_t)sh->lframe[0] : -1;
-          sh->pull = status == 0 ? 1 : 0;
-          sh->slot = s;
-          sh->gen = gen;
-          sh->first_page = lo;
-          sh->list_n = got;
-          sh->file = file;
+          bcount(bs, GFS_T_HOST, wall_clock64() - ts1);
+          bs->result = rs->result;
         }
-        return;
+        if (status) bcount(bs, GFS_C_TIMEOUTS, 1);
+        bs->status = status;
+        bs->frame = (int32_t)bs->lframe[0];
+        bs->pull = status == 0 ? 1 : 0;
+        bs->slot = s;
+        bs->gen = gen;
+        bs->first_page = lo;
+        bs->list_n = got;
+        bs->file = file;
       }
-      unlock_file_wave(d, file);
+      return;
     }
+    /* reserved by another block's miss, or a lost race: wait a little and look again */
     if (expired(d, t0)) break;
     if (l == 0) nap(naps);
   }
   if (l == 0) {
-    count(d, GFS_C_TIMEOUTS, 1);
-    sh->status = -kETIMEDOUT;
-    sh->pull = 0;
-    sh->frame = -1;
+    bcount(bs, GFS_C_TIMEOUTS, 1);
+    bs->status = -kETIMEDOUT;
+    bs->pull = 0;
+    bs->frame = -1;
   }
 }
 
 /* Block-collective: copy the fetched span from the ring slot's staging into the frames. */
-__device__ void block_pull(const gfs_dev* d, const ReadShared* sh, uint64_t fsize) {
+__device__ void block_pull(const gfs_dev* d, const BlockState* bs, uint64_t fsize) {
   const uint32_t tid = thread_id(), nt = block_threads();
   const uint64_t P = d->page_size;
-  const uint8_t* stg = d->staging + (uint64_t)sh->slot * d->max_req_bytes;
-  const int64_t result = sh->result;
-  for (uint32_t k = 0; k < sh->list_n; ++k) {
-    const uint32_t f = sh->lframe[k];
-    if (f == GFS_NO_FRAME) continue;
-    const uint64_t q = sh->list[k];
-    const uint64_t rel = (q - sh->first_page) * P;
+  const uint8_t* stg = d->staging + (uint64_t)bs->slot * d->max_req_bytes;
+  const int64_t result = bs->result;
+  for (uint32_t k = 0; k < bs->list_n; ++k) {
+    const uint32_t f = bs->lframe[k];
+    const uint64_t q = bs->list[k];
+    const uint64_t rel = (q - bs->first_page) * P;
     int64_t avail = result - (int64_t)rel;
     if (avail < 0) avail = 0;
     uint64_t pb = fsize - (q << d->page_shift);
@@ -739,20 +830,20 @@ __device__ void block_pull(const gfs_dev* d, const ReadShared* sh, uint64_t fsiz
   }
 }
 
-/* Wave 0, after the block's pull and a barrier: make the frames VALID, free the slot.
- * Returns the status of the demanded page (list[0]). */
-__device__ int64_t publish_pull_wave(const gfs_dev* d, const ReadShared* sh, uint64_t fsize) {
+/* Wave 0, after the block's pull, a fence by every thread and a barrier: make the frames
+ * VALID, free the slot. Returns the status of the demanded page (list[0]). */
+__device__ int64_t publish_pull_wave(const gfs_dev* d, BlockState* bs, uint64_t fsize) {
   const uint32_t l = lane();
   const uint64_t P = d->page_size;
   int bad_demand = 0;
-  for (uint32_t k = l; k < sh->list_n; k += 64) {
-    const uint32_t f = sh->lframe[k];
-    if (f == GFS_NO_FRAME) continue;
-    const uint64_t q = sh->list[k];
-    const uint64_t rel = (q - sh->first_page) * P;
+  uint32_t bad = 0;
+  for (uint32_t k = l; k < bs->list_n; k += 64) {
+    const uint32_t f = bs->lframe[k];
+    const uint64_t q = bs->list[k];
+    const uint64_t rel = (q - bs->first_page) * P;
     uint64_t pb = fsize - (q << d->page_shift);
     if (pb > P) pb = P;
-    const bool short_read = sh->result < 0 || (uint64_t)sh->result < rel + pb;
+    const bool short_read = bs->result < 0 || (uint64_t)bs->result < rel + pb;
     uint64_t* fw = &d->fword[f];
     uint64_t w = ld_rlx(fw);
     while (true) {
@@ -760,23 +851,25 @@ __device__ int64_t publish_pull_wave(const gfs_dev* d, const ReadShared* sh, uin
       if (short_read) nw |= GFS_FW_ERR;
       if (cas64(fw, w, nw)) break;
     }
-    if (short_read && k == 0 && sh->status == 0) bad_demand = 1;
-    if (short_read) count(d, GFS_C_IOERR, 1);
+    if (short_read && k == 0) bad_demand = 1;
+    bad += short_read ? 1u : 0u;
   }
   bad_demand = __shfl(bad_demand, 0, 64);
+  for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off, 64);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  if (l == 0) st_rel(&d->slot_free[sh->slot], sh->gen);
+  if (l == 0) {
+    st_rel(&d->slot_free[bs->slot], bs->gen);
+    bcount(bs, GFS_C_IOERR, bad);
+  }
   return bad_demand ? -kEIO : 0;
 }
-
-__device__ __forceinline__ void block_barrier() { __syncthreads(); }
 
 }  // namespace gfsd
 
 /* ====================================================================== public API */
 
 __device__ int gopen_id(const gfs_dev* d, int file_id, int flags) {
-  __shared__ int gfs_open_result;
+  gfsd::BlockState* bs = gfsd::block_state();
   if (gfsd::thread_id() == 0) {
     int v;
     if (flags != GFS_O_RDONLY) {
@@ -789,16 +882,18 @@ __device__ int gopen_id(const gfs_dev* d, int file_id, int flags) {
                              __HIP_MEMORY_SCOPE_AGENT);
       v = file_id;
     }
-    gfs_open_result = v;
+    for (int c = 0; c < GFS_C_COUNT; ++c) bs->ctr[c] = 0;
+    bs->pull = 0;
+    bs->open_result = v;
   }
   __syncthreads();
-  const int v = gfs_open_result;
+  const int v = bs->open_result;
   __syncthreads();
   return v;
 }
 
 __device__ int gopen(const gfs_dev* d, const char* path, int flags) {
-  __shared__ int gfs_open_path_id;
+  gfsd::BlockState* bs = gfsd::block_state();
   if (gfsd::thread_id() == 0) {
     int id = -1;
     for (uint32_t i = 0; i < GFS_MAX_FILES && id < 0; ++i) {
@@ -808,10 +903,10 @@ __device__ int gopen(const gfs_dev* d, const char* path, int flags) {
       while (j < GFS_NAME_MAX && nm[j] == path[j] && nm[j] != 0) ++j;
       if (j < GFS_NAME_MAX && nm[j] == 0 && path[j] == 0) id = (int)i;
     }
-    gfs_open_path_id = id;
+    bs->open_result = id;
   }
   __syncthreads();
-  const int id = gfs_open_path_id;
+  const int id = bs->open_result;
   __syncthreads();
   if (flags != GFS_O_RDONLY) return -gfsd::kEROFS;
   if (id < 0) return -gfsd::kENOENT;
@@ -820,17 +915,22 @@ __device__ int gopen(const gfs_dev* d, const char* path, int flags) {
 
 __device__ int gclose(const gfs_dev* d, int fd) {
   if (fd < 0 || (uint32_t)fd >= GFS_MAX_FILES) return -gfsd::kEBADF;
+  gfsd::BlockState* bs = gfsd::block_state();
   __syncthreads();
-  if (gfsd::thread_id() == 0)
+  if (gfsd::thread_id() == 0) {
     __hip_atomic_fetch_sub(&d->files[fd].handles, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int c = 0; c < GFS_C_COUNT; ++c) {
+      if (bs->ctr[c]) gfsd::fadd64(&d->g->ctr[c], bs->ctr[c]);
+      bs->ctr[c] = 0;
+    }
+  }
   __syncthreads();
   return 0;
 }
 
 __device__ int64_t gread(const gfs_dev* d, int fd, uint64_t offset, uint64_t size, void* dst) {
   using namespace gfsd;
-  __shared__ ReadShared gfs_read_sh;
-  ReadShared* sh = &gfs_read_sh;
+  BlockState* bs = block_state();
   if (fd < 0 || (uint32_t)fd >= GFS_MAX_FILES) return -kEBADF;
   gfs_file_dev* fe = &d->files[fd];
   if (ld_rlx32(&fe->open) == 0) return -kEBADF;
@@ -845,23 +945,28 @@ __device__ int64_t gread(const gfs_dev* d, int fd, uint64_t offset, uint64_t siz
   const uint32_t sh_bits = d->page_shift;
   int64_t err = 0;
   for (uint64_t p = offset >> sh_bits; p <= (end - 1) >> sh_bits; ++p) {
-    if (tid < 64) acquire_page_wave(d, (uint32_t)fd, p, fsize, sh, bid);
+    if (tid < 64) acquire_page_wave(d, (uint32_t)fd, p, fsize, bs, bid);
     __syncthreads();
-    if (sh->pull) {
-      block_pull(d, sh, fsize);
+    if (bs->pull) {
+      const uint64_t tp0 = wall_clock64();
+      block_pull(d, bs, fsize);
       __threadfence();
       __syncthreads();
       if (tid < 64) {
-        const int64_t st = publish_pull_wave(d, sh, fsize);
-        if (tid == 0 && st < 0) {
-          frame_unpin(d, (uint32_t)sh->frame);
-          sh->status = st;
+        const int64_t st = publish_pull_wave(d, bs, fsize);
+        if (tid == 0) {
+          if (st < 0) {
+            frame_unpin(d, (uint32_t)bs->frame);
+            bs->status = st;
+          }
+          bs->pull = 0;
+          bcount(bs, GFS_T_PULL, wall_clock64() - tp0);
         }
       }
       __syncthreads();
     }
-    const int64_t st = sh->status;
-    const int32_t f = sh->frame;
+    const int64_t st = bs->status;
+    const int32_t f = bs->frame;
     if (st < 0) {
       err = st;
       __syncthreads();
@@ -876,7 +981,7 @@ __device__ int64_t gread(const gfs_dev* d, int fd, uint64_t offset, uint64_t siz
     if (tid == 0) frame_unpin(d, (uint32_t)f);
   }
   if (err) return err;
-  if (tid == 0) count(d, GFS_C_DELIVERED, end - offset);
+  if (tid == 0) bcount(bs, GFS_C_DELIVERED, end - offset);
   return (int64_t)(end - offset);
 }
 

@@ -7,7 +7,8 @@
  * HBM layout of the metadata region (offsets computed by the host, stored in gfs_dev):
  *   gfs_globals                      256 B
  *   gfs_dev (the handle)             512 B
- *   files[GFS_MAX_FILES]             512 B each
+ *   files[GFS_MAX_FILES]             768 B each
+ *   locks[GFS_MAX_FILES]             128 B each (miss ticket locks)
  *   names[GFS_MAX_FILES]             GFS_NAME_MAX B each (registered paths)
  *   fword[nframes]  u64              frame word (state, pins, ref, ra, version)
  *   ftag[nframes]   u64              key of the page held (valid while not FREE)
@@ -57,12 +58,15 @@ typedef struct gfs_globals {
 enum {
   GFS_C_HITS = 0, GFS_C_JOINS, GFS_C_MISSES, GFS_C_RA_PAGES, GFS_C_FETCHED, GFS_C_EVICTIONS,
   GFS_C_WASTED, GFS_C_HAND, GFS_C_REQUESTS, GFS_C_REQ_BYTES, GFS_C_DELIVERED, GFS_C_RETRIES,
-  GFS_C_NOFRAME, GFS_C_TIMEOUTS, GFS_C_IOERR, GFS_C_COUNT
+  GFS_C_NOFRAME, GFS_C_TIMEOUTS, GFS_C_IOERR,
+  /* wall-clock ticks summed over blocks, by phase of the miss path */
+  GFS_T_LOCK, GFS_T_CRIT, GFS_T_ALLOC, GFS_T_SLOT, GFS_T_HOST, GFS_T_PULL, GFS_T_JOIN,
+  GFS_C_COUNT
 };
 
-#define GFS_RECENT_MISSES 32   /* misses remembered per file by the readahead detector */
+#define GFS_RECENT_MISSES 64   /* misses remembered per file by the readahead detector */
 #define GFS_NEAR_MIN 3         /* remembered misses near a miss that mark aggregate reading */
-#define GFS_NEAR_PAGES 64      /* "near" = within max(ra_cap, GFS_NEAR_PAGES) pages */
+#define GFS_NEAR_PAGES 64      /* "near" = within GFS_NEAR_PAGES pages */
 
 typedef struct gfs_stream {
   uint64_t next;          /* first page after the last window */
@@ -77,14 +81,22 @@ typedef struct gfs_file_dev {
   uint32_t npages;
   uint32_t open;          /* 1 while registered */
   uint32_t advice;        /* GFS_ADV_* */
-  uint32_t lock;          /* miss-path lock (0 free, 1 held) */
+  uint32_t pad0;
   uint32_t clock;         /* readahead decision counter (stream last_use) */
   uint32_t handles;       /* device gopen count minus gclose count */
   gfs_stream streams[8];  /* 192 B */
   uint64_t recent[GFS_RECENT_MISSES];  /* pages of the last misses (ring) */
   uint32_t recent_n;      /* misses pushed into the ring so far */
   uint32_t pad[7];
-} gfs_file_dev;           /* 512 B */
+} gfs_file_dev;           /* 768 B */
+
+/* per-file miss lock: a ticket lock on a cache line of its own, so that waiters polling
+   it do not slow the holder's accesses to the file record */
+typedef struct gfs_file_lock {
+  uint32_t next;          /* tickets handed out */
+  uint32_t serving;       /* ticket that holds the lock */
+  uint32_t pad[30];
+} gfs_file_lock;          /* 128 B */
 
 #define GFS_NAME_MAX 256     /* registered path, NUL-terminated, for gopen(path) */
 
@@ -125,13 +137,14 @@ typedef struct gfs_dev {
   uint64_t* pt;
   gfs_globals* g;
   gfs_file_dev* files;
+  gfs_file_lock* locks;
   uint64_t* slot_free;
   uint32_t* req_frames;
   void* trace;                  /* gfs_event[trace_cap] */
   char* names;                  /* [GFS_MAX_FILES][GFS_NAME_MAX] registered paths */
   gfs_rpc_slot* ring;           /* device-visible address of the pinned ring */
   uint8_t* staging;             /* device-visible address of the pinned staging */
-  uint64_t pad[7];
+  uint64_t pad[6];
 } gfs_dev;
 
 #endif /* GFS_LAYOUT_H */

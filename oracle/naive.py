@@ -48,13 +48,13 @@ class NaiveModel:
         now = self.tick[file_id]
         table = self.streams[file_id]
         hist = self.last_misses[file_id]
-        reach = self.cap if self.cap > 64 else 64
+        reach = 64
         close = 0
         for r in hist:
             if p - reach <= r <= p + reach:
                 close += 1
         hist.append(p)
-        while len(hist) > 32:
+        while len(hist) > 64:
             del hist[0]
         i = 0
         while i < len(table):

@@ -25,8 +25,7 @@ Readings where the paper is silent (the same list is in the design notes):
 window = [s.next, s.next + min(2 s.size, cap)) for a stream s whose zone
 [s.next, s.next + s.size) holds the missed page p (lowest slot wins); otherwise a
 new stream replaces an empty slot or the least recently used one (lowest index
-on ties): if at least 3 of the file's last 32 misses lie within max(cap, 64) pages
-of p, many blocks are reading the file in aggregate (interleaved strides) and the
+on ties): if at least 3 of the file's last 64 misses lie within 64 pages of p, many blocks are reading the file in aggregate (interleaved strides) and the
 window is the cap-sized chunk aligned around p; else [p, p + w) with w = min(2 h,
 cap) if the h >= 1 pages right before p are already cached (context readahead:
 Linux's way of following readers that interleave on one descriptor, Sec. 2.3); else
@@ -55,9 +54,9 @@ import dataclasses
 from typing import Dict, List, Optional, Tuple
 
 FREE, FILLING, VALID = "FREE", "FILLING", "VALID"
-RECENT = 32          # misses remembered per file
+RECENT = 64          # misses remembered per file
 NEAR_MIN = 3         # remembered misses near p that make the file look read in aggregate
-NEAR_PAGES = 64      # "near" = within max(cap, NEAR_PAGES) pages
+NEAR_PAGES = 64      # "near" = within NEAR_PAGES pages
 ADV_NORMAL, ADV_SEQUENTIAL, ADV_RANDOM = "normal", "sequential", "random"
 
 
@@ -134,8 +133,7 @@ class PolicyModel:
         if self.cap == 0 or fs.advice == ADV_RANDOM or not fs.read_only:
             return p, 1
         fs.clock += 1
-        radius = max(self.cap, NEAR_PAGES)
-        near = sum(1 for r in fs.recent if abs(r - p) <= radius)
+        near = sum(1 for r in fs.recent if abs(r - p) <= NEAR_PAGES)
         fs.recent.append(p)
         if len(fs.recent) > RECENT:
             fs.recent.pop(0)

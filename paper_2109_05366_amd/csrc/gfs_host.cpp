@@ -50,7 +50,7 @@ uint32_t log2u(uint64_t v) {
 struct Layout {
   uint64_t nframes = 0, nbuckets = 0, ra_init = 0, ra_cap = 0, max_req_pages = 0;
   uint64_t max_req_bytes = 0;
-  uint64_t off_globals = 0, off_dev = 0, off_files = 0, off_names = 0, off_fword = 0,
+  uint64_t off_globals = 0, off_dev = 0, off_files = 0, off_locks = 0, off_names = 0, off_fword = 0,
            off_ftag = 0, off_pt = 0, off_slot_free = 0, off_trace = 0, meta_bytes = 0;
 };
 
@@ -82,6 +82,7 @@ int make_layout(const gfs_config* c, Layout* L) {
   L->off_globals = o; o = align_up(o + sizeof(gfs_globals), kAlign);
   L->off_dev = o; o = align_up(o + sizeof(gfs_dev), kAlign);
   L->off_files = o; o = align_up(o + sizeof(gfs_file_dev) * GFS_MAX_FILES, kAlign);
+  L->off_locks = o; o = align_up(o + sizeof(gfs_file_lock) * GFS_MAX_FILES, kAlign);
   L->off_names = o; o = align_up(o + (uint64_t)GFS_NAME_MAX * GFS_MAX_FILES, kAlign);
   L->off_fword = o; o = align_up(o + 8 * L->nframes, kAlign);
   L->off_ftag = o; o = align_up(o + 8 * L->nframes, kAlign);
@@ -121,6 +122,7 @@ struct gfs_ctx {
   std::atomic<int64_t> host_last_errno{0};
   std::atomic<uint64_t> spins[64];
   bool last_direct = false;
+  int clock_khz = 100000;
 };
 
 namespace {
@@ -254,6 +256,7 @@ int download_file_record(gfs_ctx* c, int id, gfs_file_dev* rec) {
 int zero_dynamic(gfs_ctx* c) {
   const Layout& L = c->L;
   int rc = gfs_internal_zero(c->meta + L.off_globals, sizeof(gfs_globals), c->stream);
+  if (!rc) rc = gfs_internal_zero(c->meta + L.off_locks, sizeof(gfs_file_lock) * GFS_MAX_FILES, c->stream);
   if (!rc) rc = gfs_internal_zero(c->meta + L.off_fword, L.off_slot_free + 8ull * c->cfg.rpc_slots - L.off_fword, c->stream);
   if (!rc && c->cfg.trace_capacity)
     rc = gfs_internal_zero(c->meta + L.off_trace, sizeof(gfs_event) * (uint64_t)c->cfg.trace_capacity, c->stream);
@@ -348,11 +351,13 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   h.trace_level = cfg->trace_level;
   h.trace_cap = cfg->trace_capacity;
   h.max_req_bytes = L.max_req_bytes;
+  c->clock_khz = khz;
   const uint64_t tns = cfg->wait_timeout_ns ? cfg->wait_timeout_ns : 10000000000ull;
   h.timeout_ticks = tns / 1000 * (uint64_t)khz / 1000;
   h.frames = c->frames;
   h.g = (gfs_globals*)(c->meta + L.off_globals);
   h.files = (gfs_file_dev*)(c->meta + L.off_files);
+  h.locks = (gfs_file_lock*)(c->meta + L.off_locks);
   h.names = (char*)(c->meta + L.off_names);
   h.fword = (uint64_t*)(c->meta + L.off_fword);
   h.ftag = (uint64_t*)(c->meta + L.off_ftag);
@@ -485,6 +490,14 @@ int gfs_stats_read(gfs_ctx* c, gfs_stats* out) {
   s.host_requests = c->host_requests.load();
   s.host_bytes = c->host_bytes.load();
   s.host_read_ns = c->host_read_ns.load();
+  const double ns_per_tick = 1e6 / (double)c->clock_khz;
+  s.t_lock_ns = (uint64_t)(g.ctr[GFS_T_LOCK] * ns_per_tick);
+  s.t_crit_ns = (uint64_t)(g.ctr[GFS_T_CRIT] * ns_per_tick);
+  s.t_alloc_ns = (uint64_t)(g.ctr[GFS_T_ALLOC] * ns_per_tick);
+  s.t_slot_ns = (uint64_t)(g.ctr[GFS_T_SLOT] * ns_per_tick);
+  s.t_host_ns = (uint64_t)(g.ctr[GFS_T_HOST] * ns_per_tick);
+  s.t_pull_ns = (uint64_t)(g.ctr[GFS_T_PULL] * ns_per_tick);
+  s.t_join_ns = (uint64_t)(g.ctr[GFS_T_JOIN] * ns_per_tick);
   s.host_errors = c->host_errors.load();
   s.host_last_errno = (uint64_t)c->host_last_errno.load();
   for (uint32_t i = 0; i < 64; ++i) s.host_spins[i] = c->spins[i].load();

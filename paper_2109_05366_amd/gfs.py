@@ -40,6 +40,7 @@ class gfs_config(C.Structure):
 _STAT_U64 = ["hits", "joins", "misses", "ra_pages", "fetched_pages", "evictions", "wasted_pages",
              "hand_visits", "requests", "request_bytes", "delivered_bytes", "retries", "noframe",
              "timeouts", "io_errors", "trace_events", "host_requests", "host_bytes", "host_read_ns",
+             "t_lock_ns", "t_crit_ns", "t_alloc_ns", "t_slot_ns", "t_host_ns", "t_pull_ns", "t_join_ns",
              "host_errors", "host_last_errno"]
 
 
