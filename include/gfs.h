@@ -167,7 +167,7 @@ enum {
   GFS_EV_MISS = 3,   /* file,page; a = window length (EOF-clamped), b = window start,
                         frame = recent misses of the file near page (detector input) */
   GFS_EV_HAND = 4,   /* frame; b = ticket; a = action | ra<<8; file,page = victim (EVICT) */
-  GFS_EV_ALLOC = 5,  /* file,page,frame; a = ra (1 if prefetched)               */
+  GFS_EV_ALLOC = 5,  /* file,page,frame; a = ra (1 if prefetched), b = hand ticket */
   GFS_EV_REQ = 6,    /* file, page = first page, a = pages in span, b = ring ticket */
   GFS_EV_NOFRAME = 7 /* file,page: window cut short, no frame left              */
 };

@@ -56,7 +56,7 @@ struct BlockState {
   uint64_t first_page;      /* first page of the request span */
   uint64_t gen;             /* ring generation of the request */
   int32_t frame;            /* pinned frame of the current page */
-  int32_t pull;             /* 1: this block must pull its request into the frames */
+  int32_t pull;             /* 1: pull this block's own request; 2: help pull one frame */
   uint32_t slot;            /* ring slot of the request */
   uint32_t list_n;          /* pages in list[] that got frames (a prefix) */
   uint32_t file;
@@ -64,7 +64,10 @@ struct BlockState {
   uint64_t ctr[GFS_C_COUNT];    /* block-local statistics, added to the globals by gclose */
   uint32_t list[kMaxWindow];    /* run pages: the demanded page, then the rest ascending */
   uint32_t lframe[kMaxWindow];  /* frame given to list[k], or GFS_NO_FRAME */
-  uint32_t lslot[kMaxWindow];   /* page-table slot reserved for list[k] (0xffffffff: none) */
+  uint32_t lslot[kMaxWindow];   /* page-table slot reserved for list[k] (0xffffffff: none);
+                                   after allocation, the indices of the frames this block pulls */
+  uint32_t nclaim;              /* entries of lslot[] claimed for pulling */
+  uint32_t help_page;           /* page of the frame a helping block pulls */
 };
 
 __device__ __forceinline__ BlockState* block_state() {
@@ -512,8 +515,8 @@ __device__ uint32_t alloc_wave(const gfs_dev* d, uint32_t file, uint64_t demand,
     uint32_t f = 0;
     uint64_t vkey = 0;
     uint32_t vra = 0;
+    const uint64_t t = base + l;
     if (l < need) {
-      const uint64_t t = base + l;
       f = (uint32_t)(t % d->nframes);
       act = hand_visit(d, f, vkey, vra);
       if (act == GFS_HAND_EVICT) {
@@ -534,6 +537,7 @@ __device__ uint32_t alloc_wave(const gfs_dev* d, uint32_t file, uint64_t demand,
       if (act == GFS_HAND_EVICT) pt_delete_lane(d, vkey, f);
       const uint64_t key = page_key(file, q);
       st_rlx(&d->ftag[f], key);
+      st_rlx(&d->ffill[f], 0ull);   /* the request that fills it is not known yet */
       uint64_t nw = (((ld_rlx(&d->fword[f]) >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT) |
                     GFS_FS_FILLING;
       if (q == demand) nw += GFS_FW_PIN_ONE;
@@ -541,7 +545,7 @@ __device__ uint32_t alloc_wave(const gfs_dev* d, uint32_t file, uint64_t demand,
       st_rel(&d->fword[f], nw);
       st_rel(d->pt + bs->lslot[k], (key << GFS_ENTRY_FRAME_BITS) | f);
       bs->lframe[k] = f;
-      trace_ev(d, 1, GFS_EV_ALLOC, bid, file, (uint32_t)q, f, q == demand ? 0u : 1u, 0);
+      trace_ev(d, 1, GFS_EV_ALLOC, bid, file, (uint32_t)q, f, q == demand ? 0u : 1u, t);
     }
     if (l == 0) bcount(bs, GFS_C_HAND, need);
     assigned += (uint32_t)__popcll(sm);
@@ -585,6 +589,59 @@ __device__ __forceinline__ void copy_block(uint8_t* dst, const uint8_t* src, uin
   }
 }
 
+/* Lane: this block holds a pin on frame f (page p), which another block's request is
+ * filling. Wait for it to become VALID; meanwhile, once the request's host read is done,
+ * try to take over copying this frame's bytes from staging (the PULL bit), so that blocks
+ * waiting on a large window pull its pages in parallel. Leaves in bs: status, frame, and
+ * pull = 2 with slot/gen/first_page/result when this block must pull frame f. */
+__device__ void join_or_help_lane(const gfs_dev* d, uint32_t f, uint64_t p, uint64_t t0,
+                                  BlockState* bs) {
+  uint64_t* fw = &d->fword[f];
+  uint32_t n = 0;
+  bs->frame = (int32_t)f;
+  bs->pull = 0;
+  while (true) {
+    uint64_t w = ld_acq(fw);
+    if ((w & GFS_FW_STATE) == GFS_FS_VALID) {
+      if (w & GFS_FW_ERR) {
+        frame_unpin(d, f);
+        bs->status = -kEIO;
+      } else {
+        bs->status = 0;
+      }
+      return;
+    }
+    if (!(w & GFS_FW_PULL)) {
+      const uint64_t ff = ld_acq(&d->ffill[f]);
+      if (ff) {
+        const uint32_t s = (uint32_t)(ff >> 40) - 1;
+        gfs_req_dev* rq = &d->reqd[s];
+        const uint64_t ready = ld_acq(&rq->ready);
+        if (ready != 0 && (ready & ((1ull << 40) - 1)) == (ff & ((1ull << 40) - 1))) {
+          if (cas64(fw, w, (w | GFS_FW_PULL) + GFS_FW_VER_ONE)) {
+            bs->status = 0;
+            bs->pull = 2;
+            bs->slot = s;
+            bs->gen = ready;
+            bs->first_page = rq->first_page;
+            bs->result = rq->result;
+            bs->help_page = (uint32_t)p;
+            return;
+          }
+          continue;
+        }
+      }
+    }
+    if (expired(d, t0)) {
+      frame_unpin(d, f);
+      bcount(bs, GFS_C_TIMEOUTS, 1);
+      bs->status = -kETIMEDOUT;
+      return;
+    }
+    nap(n);
+  }
+}
+
 /* ------------------------------------------------------------------ one page, wave 0
  * Leaves in bs: status; on success the pinned frame, and pull = 1 when this block posted
  * the request and must pull it. */
@@ -615,12 +672,8 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
           bcount(bs, GFS_C_JOINS, 1);
           trace_ev(d, 2, GFS_EV_JOIN, bid, file, (uint32_t)p, (uint32_t)f, 0, 0);
           const uint64_t tj0 = wall_clock64();
-          const int64_t st = wait_valid_lane(d, (uint32_t)f, t0);
+          join_or_help_lane(d, (uint32_t)f, p, t0, bs);
           bcount(bs, GFS_T_JOIN, wall_clock64() - tj0);
-          if (st == -kETIMEDOUT) bcount(bs, GFS_C_TIMEOUTS, 1);
-          bs->status = st;
-          bs->frame = f;
-          bs->pull = 0;
         }
         return;
       }
@@ -745,11 +798,12 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       const uint64_t off0 = lo << d->page_shift;
       uint64_t len = (uint64_t)span << d->page_shift;
       if (off0 + len > fsize) len = fsize - off0;
+      int64_t status = 0;
+      uint64_t tk = 0;
       if (l == 0) {
-        int64_t status = 0;
-        const uint64_t t = fadd64(&d->g->ring_tail, 1);
-        const uint32_t s = (uint32_t)(t % d->rpc_slots);
-        const uint64_t gen = t / d->rpc_slots + 1;
+        tk = fadd64(&d->g->ring_tail, 1);
+        const uint32_t s = (uint32_t)(tk % d->rpc_slots);
+        const uint64_t gen = tk / d->rpc_slots + 1;
         uint32_t nn = 0;
         const uint64_t ts0 = wall_clock64();
         while (ld_acq(&d->slot_free[s]) != gen - 1) {
@@ -759,23 +813,37 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
           }
           nap(nn);
         }
-        const uint64_t ts1 = wall_clock64();
-        bcount(bs, GFS_T_SLOT, ts1 - ts0);
+        bcount(bs, GFS_T_SLOT, wall_clock64() - ts0);
         if (status == 0) {
           gfs_rpc_slot* rs = &d->ring[s];
           rs->file_id = file;
           rs->npages = span;
           rs->offset = off0;
           rs->length = len;
-          rs->ticket = t;
+          rs->ticket = tk;
           __hip_atomic_store(&rs->req_seq, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-          trace_ev(d, 1, GFS_EV_REQ, bid, file, (uint32_t)lo, GFS_NO_FRAME, span, t);
+          trace_ev(d, 1, GFS_EV_REQ, bid, file, (uint32_t)lo, GFS_NO_FRAME, span, tk);
           bcount(bs, GFS_C_MISSES, 1);
           bcount(bs, GFS_C_REQUESTS, 1);
           bcount(bs, GFS_C_REQ_BYTES, len);
           bcount(bs, GFS_C_FETCHED, got);
           bcount(bs, GFS_C_RA_PAGES, got - 1);
-          nn = 0;
+        }
+      }
+      status = __shfl(status, 0, 64);
+      tk = __shfl(tk, 0, 64);
+      const uint32_t s = (uint32_t)(tk % d->rpc_slots);
+      const uint64_t gen = tk / d->rpc_slots + 1;
+      if (status == 0) {
+        /* tell waiting blocks which request fills each frame: (slot + 1) << 40 | gen */
+        const uint64_t fill = ((uint64_t)(s + 1) << 40) | (gen & ((1ull << 40) - 1));
+        for (uint32_t k = l; k < got; k += 64) st_rel(&d->ffill[bs->lframe[k]], fill);
+      }
+      if (l == 0) {
+        if (status == 0) {
+          gfs_rpc_slot* rs = &d->ring[s];
+          uint32_t nn = 0;
+          const uint64_t th0 = wall_clock64();
           while (__hip_atomic_load(&rs->done_seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) !=
                  gen) {
             if (expired(d, t0)) {
@@ -784,8 +852,17 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
             }
             nap(nn);
           }
-          bcount(bs, GFS_T_HOST, wall_clock64() - ts1);
-          bs->result = rs->result;
+          bcount(bs, GFS_T_HOST, wall_clock64() - th0);
+          if (status == 0) {
+            bs->result = rs->result;
+            /* let blocks waiting on frames of this request pull their own pages */
+            gfs_req_dev* rq = &d->reqd[s];
+            rq->result = bs->result;
+            rq->first_page = lo;
+            rq->file = file;
+            __hip_atomic_store(&rq->remaining, got, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st_rel(&rq->ready, gen);
+          }
         }
         if (status) bcount(bs, GFS_C_TIMEOUTS, 1);
         bs->status = status;
@@ -811,57 +888,130 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
   }
 }
 
-/* Block-collective: copy the fetched span from the ring slot's staging into the frames. */
+/* Bytes of page q held in the staging of a request whose span starts at first (clamped to
+ * what the host returned and to the file). */
+__device__ __forceinline__ uint64_t staged_bytes(const gfs_dev* d, uint64_t q, uint64_t first,
+                                                 int64_t result, uint64_t fsize) {
+  const uint64_t P = d->page_size;
+  const uint64_t rel = (q - first) * P;
+  int64_t avail = result - (int64_t)rel;
+  if (avail < 0) avail = 0;
+  uint64_t pb = fsize - (q << d->page_shift);
+  if (pb > P) pb = P;
+  return (uint64_t)avail < pb ? (uint64_t)avail : pb;
+}
+__device__ __forceinline__ bool staged_short(const gfs_dev* d, uint64_t q, uint64_t first,
+                                             int64_t result, uint64_t fsize) {
+  const uint64_t P = d->page_size;
+  uint64_t pb = fsize - (q << d->page_shift);
+  if (pb > P) pb = P;
+  return result < 0 || (uint64_t)result < (q - first) * P + pb;
+}
+
+/* Wave 0: claim the request's frames that no helping block has taken (PULL bit); their
+ * indices go to bs->lslot[0..nclaim). */
+__device__ void claim_pulls_wave(const gfs_dev* d, BlockState* bs) {
+  const uint32_t l = lane();
+  uint32_t nclaim = 0;
+  for (uint32_t base = 0; base < bs->list_n; base += 64) {
+    const uint32_t k = base + l;
+    bool won = false;
+    if (k < bs->list_n) {
+      uint64_t* fw = &d->fword[bs->lframe[k]];
+      uint64_t w = ld_rlx(fw);
+      while ((w & GFS_FW_STATE) == GFS_FS_FILLING && !(w & GFS_FW_PULL)) {
+        if (cas64(fw, w, (w | GFS_FW_PULL) + GFS_FW_VER_ONE)) {
+          won = true;
+          break;
+        }
+      }
+    }
+    const uint64_t m = __ballot(won);
+    if (won) bs->lslot[nclaim + __popcll(m & lanemask_lt())] = k;
+    nclaim += (uint32_t)__popcll(m);
+  }
+  if (l == 0) bs->nclaim = nclaim;
+  wave_sync_lds();
+}
+
+/* Block-collective: copy claimed pages from the ring slot's staging into their frames.
+ * pull == 1: the frames listed in lslot[0..nclaim); pull == 2: the one helped frame. */
 __device__ void block_pull(const gfs_dev* d, const BlockState* bs, uint64_t fsize) {
   const uint32_t tid = thread_id(), nt = block_threads();
   const uint64_t P = d->page_size;
   const uint8_t* stg = d->staging + (uint64_t)bs->slot * d->max_req_bytes;
-  const int64_t result = bs->result;
-  for (uint32_t k = 0; k < bs->list_n; ++k) {
-    const uint32_t f = bs->lframe[k];
+  if (bs->pull == 2) {
+    const uint64_t q = bs->help_page;
+    copy_block_aligned(d->frames + (uint64_t)(uint32_t)bs->frame * P, stg + (q - bs->first_page) * P,
+                       staged_bytes(d, q, bs->first_page, bs->result, fsize), tid, nt);
+    return;
+  }
+  for (uint32_t c = 0; c < bs->nclaim; ++c) {
+    const uint32_t k = bs->lslot[c];
     const uint64_t q = bs->list[k];
-    const uint64_t rel = (q - bs->first_page) * P;
-    int64_t avail = result - (int64_t)rel;
-    if (avail < 0) avail = 0;
-    uint64_t pb = fsize - (q << d->page_shift);
-    if (pb > P) pb = P;
-    const uint64_t n = (uint64_t)avail < pb ? (uint64_t)avail : pb;
-    copy_block_aligned(d->frames + (uint64_t)f * P, stg + rel, n, tid, nt);
+    copy_block_aligned(d->frames + (uint64_t)bs->lframe[k] * P, stg + (q - bs->first_page) * P,
+                       staged_bytes(d, q, bs->first_page, bs->result, fsize), tid, nt);
   }
 }
 
-/* Wave 0, after the block's pull, a fence by every thread and a barrier: make the frames
- * VALID, free the slot. Returns the status of the demanded page (list[0]). */
-__device__ int64_t publish_pull_wave(const gfs_dev* d, BlockState* bs, uint64_t fsize) {
+/* Lane: publish a pulled frame VALID (reference bit set, ERR if the host read came short). */
+__device__ __forceinline__ void publish_frame(const gfs_dev* d, uint32_t f, bool short_read) {
+  uint64_t* fw = &d->fword[f];
+  uint64_t w = ld_rlx(fw);
+  while (true) {
+    uint64_t nw = ((w & ~(GFS_FW_STATE | GFS_FW_PULL)) | GFS_FS_VALID | GFS_FW_REF) + GFS_FW_VER_ONE;
+    if (short_read) nw |= GFS_FW_ERR;
+    if (cas64(fw, w, nw)) break;
+  }
+}
+
+/* Lane 0 (after the frames are published): count them off the request; the block that
+ * publishes the last one frees the ring slot. */
+__device__ __forceinline__ void request_done_lane(const gfs_dev* d, uint32_t s, uint64_t gen,
+                                                  uint32_t cnt) {
+  if (cnt == 0) return;
+  const uint32_t before = __hip_atomic_fetch_sub(&d->reqd[s].remaining, cnt, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+  if (before == cnt) st_rel(&d->slot_free[s], gen);
+}
+
+/* Wave 0, after the block's pull, a fence by every thread and a barrier: publish the frames
+ * this block pulled and count them off. Returns the status of this block's page: for its
+ * own request the demanded page (list[0]), which a helper may be pulling, so it may wait.
+ * On an error the block's pin on its page has been dropped. */
+__device__ int64_t publish_pull_wave(const gfs_dev* d, BlockState* bs, uint64_t fsize,
+                                     uint64_t t0) {
   const uint32_t l = lane();
-  const uint64_t P = d->page_size;
-  int bad_demand = 0;
   uint32_t bad = 0;
-  for (uint32_t k = l; k < bs->list_n; k += 64) {
-    const uint32_t f = bs->lframe[k];
-    const uint64_t q = bs->list[k];
-    const uint64_t rel = (q - bs->first_page) * P;
-    uint64_t pb = fsize - (q << d->page_shift);
-    if (pb > P) pb = P;
-    const bool short_read = bs->result < 0 || (uint64_t)bs->result < rel + pb;
-    uint64_t* fw = &d->fword[f];
-    uint64_t w = ld_rlx(fw);
-    while (true) {
-      uint64_t nw = ((w & ~GFS_FW_STATE) | GFS_FS_VALID | GFS_FW_REF) + GFS_FW_VER_ONE;
-      if (short_read) nw |= GFS_FW_ERR;
-      if (cas64(fw, w, nw)) break;
+  int64_t st = 0;
+  if (bs->pull == 2) {
+    if (l == 0) {
+      const bool sh = staged_short(d, bs->help_page, bs->first_page, bs->result, fsize);
+      publish_frame(d, (uint32_t)bs->frame, sh);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      request_done_lane(d, bs->slot, bs->gen, 1);
+      bad = sh ? 1u : 0u;
+      st = sh ? -kEIO : 0;
+      if (sh) frame_unpin(d, (uint32_t)bs->frame);
     }
-    if (short_read && k == 0) bad_demand = 1;
-    bad += short_read ? 1u : 0u;
+  } else {
+    for (uint32_t c = l; c < bs->nclaim; c += 64) {
+      const uint32_t k = bs->lslot[c];
+      const bool sh = staged_short(d, bs->list[k], bs->first_page, bs->result, fsize);
+      publish_frame(d, bs->lframe[k], sh);
+      bad += sh ? 1u : 0u;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (l == 0) {
+      request_done_lane(d, bs->slot, bs->gen, bs->nclaim);
+      /* the demanded page: pulled here, or by a helper that may still be copying it */
+      st = wait_valid_lane(d, (uint32_t)bs->frame, t0);
+      if (st == -kETIMEDOUT) bcount(bs, GFS_C_TIMEOUTS, 1);
+    }
   }
-  bad_demand = __shfl(bad_demand, 0, 64);
   for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off, 64);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  if (l == 0) {
-    st_rel(&d->slot_free[bs->slot], bs->gen);
-    bcount(bs, GFS_C_IOERR, bad);
-  }
-  return bad_demand ? -kEIO : 0;
+  if (l == 0) bcount(bs, GFS_C_IOERR, bad);
+  return __shfl(st, 0, 64);
 }
 
 }  // namespace gfsd
@@ -949,22 +1099,24 @@ __device__ int64_t gread(const gfs_dev* d, int fd, uint64_t offset, uint64_t siz
     __syncthreads();
     if (bs->pull) {
       const uint64_t tp0 = wall_clock64();
+      if (bs->pull == 1) {
+        if (tid < 64) claim_pulls_wave(d, bs);
+        __syncthreads();
+      }
       block_pull(d, bs, fsize);
       __threadfence();
       __syncthreads();
       if (tid < 64) {
-        const int64_t st = publish_pull_wave(d, bs, fsize);
+        const int64_t st = publish_pull_wave(d, bs, fsize, wall_clock64());
         if (tid == 0) {
-          if (st < 0) {
-            frame_unpin(d, (uint32_t)bs->frame);
-            bs->status = st;
-          }
+          if (st < 0) bs->status = st;
           bs->pull = 0;
           bcount(bs, GFS_T_PULL, wall_clock64() - tp0);
         }
       }
       __syncthreads();
     }
+
     const int64_t st = bs->status;
     const int32_t f = bs->frame;
     if (st < 0) {

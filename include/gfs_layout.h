@@ -13,8 +13,9 @@
  *   fword[nframes]  u64              frame word (state, pins, ref, ra, version)
  *   ftag[nframes]   u64              key of the page held (valid while not FREE)
  *   pt[nbuckets*16] u64              hashed page table, 16-entry buckets (128 B)
+ *   ffill[nframes]  u64              ring slot and generation filling the frame (0: not yet known)
  *   slot_free[rpc_slots] u64         generation of the last completed use of each ring slot
- *   req_frames[rpc_slots*max_req_pages] u32  frame of each page of the slot's request
+ *   reqd[rpc_slots]                  64 B: a finished host read, for blocks that help pull it
  *   trace[trace_capacity]            32 B records
  * Frames (cache_bytes) are a separate caller allocation. The ring and staging live in
  * pinned, device-mapped host memory owned by the context.
@@ -33,6 +34,7 @@
 #define GFS_FW_REF (1ull << 2)   /* clock reference bit */
 #define GFS_FW_RA (1ull << 3)    /* prefetched, not yet demanded */
 #define GFS_FW_ERR (1ull << 4)   /* the host read for this page failed */
+#define GFS_FW_PULL (1ull << 5)  /* filling, and a block is copying the bytes into the frame */
 #define GFS_FW_PIN_SHIFT 8
 #define GFS_FW_PIN_ONE (1ull << GFS_FW_PIN_SHIFT)
 #define GFS_FW_PINS (0xffffull << GFS_FW_PIN_SHIFT)
@@ -117,6 +119,17 @@ typedef struct gfs_rpc_slot {
   uint64_t pad1[4];
 } gfs_rpc_slot;           /* 128 B */
 
+/* a ring slot's finished host read, published by the requester so that blocks waiting on
+   frames of the request can copy their own pages from staging */
+typedef struct gfs_req_dev {
+  uint64_t ready;         /* generation whose bytes are in staging */
+  int64_t result;         /* host read result (bytes or -errno) */
+  uint64_t first_page;    /* first page of the span */
+  uint32_t remaining;     /* frames of the request not yet published */
+  uint32_t file;
+  uint64_t pad[4];
+} gfs_req_dev;            /* 64 B */
+
 typedef struct gfs_dev {
   uint64_t page_size;
   uint32_t page_shift;
@@ -139,12 +152,14 @@ typedef struct gfs_dev {
   gfs_file_dev* files;
   gfs_file_lock* locks;
   uint64_t* slot_free;
+  uint64_t* ffill;
+  gfs_req_dev* reqd;
   uint32_t* req_frames;
   void* trace;                  /* gfs_event[trace_cap] */
   char* names;                  /* [GFS_MAX_FILES][GFS_NAME_MAX] registered paths */
   gfs_rpc_slot* ring;           /* device-visible address of the pinned ring */
   uint8_t* staging;             /* device-visible address of the pinned staging */
-  uint64_t pad[6];
+  uint64_t pad[4];
 } gfs_dev;
 
 #endif /* GFS_LAYOUT_H */

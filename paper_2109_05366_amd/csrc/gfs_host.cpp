@@ -17,6 +17,9 @@
 #include <unistd.h>
 
 #include <atomic>
+#include <deque>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -51,7 +54,8 @@ struct Layout {
   uint64_t nframes = 0, nbuckets = 0, ra_init = 0, ra_cap = 0, max_req_pages = 0;
   uint64_t max_req_bytes = 0;
   uint64_t off_globals = 0, off_dev = 0, off_files = 0, off_locks = 0, off_names = 0, off_fword = 0,
-           off_ftag = 0, off_pt = 0, off_slot_free = 0, off_trace = 0, meta_bytes = 0;
+           off_ftag = 0, off_pt = 0, off_ffill = 0, off_slot_free = 0, off_reqd = 0, off_trace = 0,
+           meta_bytes = 0;
 };
 
 int make_layout(const gfs_config* c, Layout* L) {
@@ -87,7 +91,9 @@ int make_layout(const gfs_config* c, Layout* L) {
   L->off_fword = o; o = align_up(o + 8 * L->nframes, kAlign);
   L->off_ftag = o; o = align_up(o + 8 * L->nframes, kAlign);
   L->off_pt = o; o = align_up(o + 8 * GFS_BUCKET_SLOTS * L->nbuckets, kAlign);
+  L->off_ffill = o; o = align_up(o + 8 * L->nframes, kAlign);
   L->off_slot_free = o; o = align_up(o + 8ull * c->rpc_slots, kAlign);
+  L->off_reqd = o; o = align_up(o + sizeof(gfs_req_dev) * (uint64_t)c->rpc_slots, kAlign);
   L->off_trace = o; o = align_up(o + sizeof(gfs_event) * (uint64_t)c->trace_capacity, kAlign);
   L->meta_bytes = o;
   return 0;
@@ -123,6 +129,23 @@ struct gfs_ctx {
   std::atomic<uint64_t> spins[64];
   bool last_direct = false;
   int clock_khz = 100000;
+  /* a request larger than one chunk is split; any I/O thread may read any chunk */
+  struct Chunk {
+    uint32_t slot;
+    uint64_t gen;
+    uint64_t off;       /* file offset */
+    uint64_t len;
+    uint64_t dst;       /* byte offset in the slot's staging */
+  };
+  struct Track {
+    std::atomic<uint32_t> remaining{0};
+    std::atomic<int64_t> total{0};
+    std::atomic<int64_t> err{0};
+  };
+  std::mutex qmu;
+  std::deque<Chunk> queue;
+  std::atomic<uint32_t> queued{0};
+  std::unique_ptr<Track[]> track;
 };
 
 namespace {
@@ -166,60 +189,102 @@ int64_t read_span(int fd, bool direct, uint8_t* dst, uint64_t off, uint64_t len,
 
 inline void cpu_relax() { __builtin_ia32_pause(); }
 
-// One host I/O thread: take ring tickets in order, wait for the device to publish the
-// ticket's request, read the span into the slot's staging buffer, publish the result.
+// Read one chunk of a request into the slot's staging; the thread that finishes a
+// request's last chunk publishes its result to the device.
+void run_chunk(gfs_ctx* c, const gfs_ctx::Chunk& ch, uint8_t* bounce) {
+  gfs_rpc_slot* rs = &c->ring[ch.slot];
+  gfs_ctx::Track& tr = c->track[ch.slot];
+  const uint32_t fid = rs->file_id;
+  HostFile* hf = fid < GFS_MAX_FILES ? &c->files[fid] : nullptr;
+  const int fd = hf ? hf->fd.load(std::memory_order_acquire) : -1;
+  int64_t r;
+  if (fd < 0) {
+    r = -EBADF;
+  } else {
+    const uint64_t t0 = now_ns();
+    r = read_span(fd, hf->direct, c->staging + (uint64_t)ch.slot * c->L.max_req_bytes + ch.dst,
+                  ch.off, ch.len, bounce);
+    c->host_read_ns.fetch_add(now_ns() - t0, std::memory_order_relaxed);
+  }
+  if (r < 0) {
+    tr.err.store(r, std::memory_order_relaxed);
+    c->host_errors.fetch_add(1, std::memory_order_relaxed);
+    c->host_last_errno.store(-r, std::memory_order_relaxed);
+  } else {
+    tr.total.fetch_add(r, std::memory_order_relaxed);
+    c->host_bytes.fetch_add((uint64_t)r, std::memory_order_relaxed);
+  }
+  if (tr.remaining.fetch_sub(1, std::memory_order_acq_rel) == 1) {
+    const int64_t e = tr.err.load(std::memory_order_relaxed);
+    rs->result = e ? e : tr.total.load(std::memory_order_relaxed);
+    rs->t_done_ns = now_ns();
+    __atomic_store_n(&rs->done_seq, ch.gen, __ATOMIC_RELEASE);
+    c->host_requests.fetch_add(1, std::memory_order_relaxed);
+  }
+}
+
+bool pop_chunk(gfs_ctx* c, gfs_ctx::Chunk* out) {
+  if (c->queued.load(std::memory_order_relaxed) == 0) return false;
+  std::lock_guard<std::mutex> g(c->qmu);
+  if (c->queue.empty()) return false;
+  *out = c->queue.front();
+  c->queue.pop_front();
+  c->queued.fetch_sub(1, std::memory_order_relaxed);
+  return true;
+}
+
+// One host I/O thread: read queued chunks when there are any; otherwise hold the next ring
+// ticket, and when the device publishes that ticket's request split it into chunks, queue
+// all but the first, and read the first.
 void io_thread(gfs_ctx* c, int idx) {
   const uint32_t NS = c->cfg.rpc_slots;
   bool first = true;
-  uint64_t idle_spins = 0;
+  bool holding = false;
+  uint64_t h = 0, spins = 0, idle_spins = 0;
   uint8_t* bounce = (uint8_t*)aligned_alloc(kDirectAlign, kBounceChunk);
   if (!bounce) return;
+  gfs_ctx::Chunk ch;
   while (!c->stop.load(std::memory_order_relaxed)) {
-    const uint64_t h = c->head.fetch_add(1, std::memory_order_relaxed);
+    if (pop_chunk(c, &ch)) {
+      run_chunk(c, ch, bounce);
+      continue;
+    }
+    if (!holding) {
+      h = c->head.fetch_add(1, std::memory_order_relaxed);
+      holding = true;
+      spins = 0;
+    }
     const uint32_t s = (uint32_t)(h % NS);
     const uint64_t gen = h / NS + 1;
     gfs_rpc_slot* rs = &c->ring[s];
-    uint64_t spins = 0;
-    while (__atomic_load_n(&rs->req_seq, __ATOMIC_ACQUIRE) != gen) {
-      if (c->stop.load(std::memory_order_relaxed)) {
-        free(bounce);
-        return;
-      }
+    if (__atomic_load_n(&rs->req_seq, __ATOMIC_ACQUIRE) != gen) {
       ++spins;
-      if (spins < (1u << 20)) {
-        cpu_relax();
-      } else {
-        usleep(50);   // long idle: stop burning the core, at some wake-up latency
-      }
+      if (spins < (1u << 20)) cpu_relax();
+      else usleep(50);   // long idle: stop burning the core, at some wake-up latency
+      continue;
     }
+    holding = false;
     idle_spins += spins;
     if (first) {
       c->spins[idx].store(idle_spins, std::memory_order_relaxed);
       first = false;
     }
     rs->t_claim_ns = now_ns();
-    const uint32_t fid = rs->file_id;
     const uint64_t off = rs->offset, len = rs->length;
-    int64_t res;
-    HostFile* hf = fid < GFS_MAX_FILES ? &c->files[fid] : nullptr;
-    const int fd = hf ? hf->fd.load(std::memory_order_acquire) : -1;
-    if (fd < 0 || len > c->L.max_req_bytes) {
-      res = -EBADF;
-    } else {
-      uint8_t* dst = c->staging + (uint64_t)s * c->L.max_req_bytes;
-      const uint64_t t0 = now_ns();
-      res = read_span(fd, hf->direct, dst, off, len, bounce);
-      c->host_read_ns.fetch_add(now_ns() - t0, std::memory_order_relaxed);
-      if (res > 0) c->host_bytes.fetch_add((uint64_t)res, std::memory_order_relaxed);
+    const uint64_t n = len > c->L.max_req_bytes ? 0 : (len + kBounceChunk - 1) / kBounceChunk;
+    gfs_ctx::Track& tr = c->track[s];
+    tr.total.store(0, std::memory_order_relaxed);
+    tr.err.store(n == 0 && len ? -EINVAL : 0, std::memory_order_relaxed);
+    tr.remaining.store(n ? (uint32_t)n : 1u, std::memory_order_release);
+    if (n > 1) {
+      std::lock_guard<std::mutex> g(c->qmu);
+      for (uint64_t i = 1; i < n; ++i) {
+        const uint64_t o = i * kBounceChunk;
+        c->queue.push_back({s, gen, off + o, (len - o) < kBounceChunk ? (len - o) : kBounceChunk, o});
+      }
+      c->queued.fetch_add((uint32_t)(n - 1), std::memory_order_relaxed);
     }
-    if (res < 0) {
-      c->host_errors.fetch_add(1, std::memory_order_relaxed);
-      c->host_last_errno.store(-res, std::memory_order_relaxed);
-    }
-    rs->result = res;
-    rs->t_done_ns = now_ns();
-    __atomic_store_n(&rs->done_seq, gen, __ATOMIC_RELEASE);
-    c->host_requests.fetch_add(1, std::memory_order_relaxed);
+    run_chunk(c, {s, gen, off, n ? (len < kBounceChunk ? len : kBounceChunk) : 0, 0}, bounce);
   }
   free(bounce);
 }
@@ -234,6 +299,9 @@ void stop_threads(gfs_ctx* c) {
   c->stop.store(true);
   for (auto& t : c->threads) t.join();
   c->threads.clear();
+  std::lock_guard<std::mutex> g(c->qmu);
+  c->queue.clear();
+  c->queued.store(0);
 }
 
 int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : -EIO; }
@@ -257,7 +325,7 @@ int zero_dynamic(gfs_ctx* c) {
   const Layout& L = c->L;
   int rc = gfs_internal_zero(c->meta + L.off_globals, sizeof(gfs_globals), c->stream);
   if (!rc) rc = gfs_internal_zero(c->meta + L.off_locks, sizeof(gfs_file_lock) * GFS_MAX_FILES, c->stream);
-  if (!rc) rc = gfs_internal_zero(c->meta + L.off_fword, L.off_slot_free + 8ull * c->cfg.rpc_slots - L.off_fword, c->stream);
+  if (!rc) rc = gfs_internal_zero(c->meta + L.off_fword, L.off_trace - L.off_fword, c->stream);
   if (!rc && c->cfg.trace_capacity)
     rc = gfs_internal_zero(c->meta + L.off_trace, sizeof(gfs_event) * (uint64_t)c->cfg.trace_capacity, c->stream);
   if (!rc) rc = hip_ok(hipStreamSynchronize(c->stream));
@@ -363,6 +431,8 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   h.ftag = (uint64_t*)(c->meta + L.off_ftag);
   h.pt = (uint64_t*)(c->meta + L.off_pt);
   h.slot_free = (uint64_t*)(c->meta + L.off_slot_free);
+  h.ffill = (uint64_t*)(c->meta + L.off_ffill);
+  h.reqd = (gfs_req_dev*)(c->meta + L.off_reqd);
   h.trace = c->meta + L.off_trace;
   h.ring = (gfs_rpc_slot*)dring;
   h.staging = (uint8_t*)dstg;
@@ -377,6 +447,13 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
     return rc;
   }
   memset(c->ring, 0, ring_bytes);
+  c->track.reset(new (std::nothrow) gfs_ctx::Track[cfg->rpc_slots]);
+  if (!c->track) {
+    (void)hipHostFree(c->staging);
+    (void)hipHostFree(c->ring);
+    delete c;
+    return -ENOMEM;
+  }
   start_threads(c);
   *out = c;
   return 0;

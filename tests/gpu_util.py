@@ -85,3 +85,27 @@ def canon(events):
             flush()
     flush()
     return out
+
+
+def decode_replay(ev: np.ndarray):
+    """Device trace records -> the tuples oracle.replay takes (tickets and blocks kept)."""
+    out = []
+    for r in ev:
+        op = int(r["op"])
+        blk, f, p, fr, a, b = (int(r["block"]), int(r["file"]), int(r["page"]), int(r["frame"]),
+                              int(r["a"]), int(r["b"]))
+        if op == 3:
+            out.append(("MISS", blk, f, p, b, a, fr))
+        elif op == 4:
+            act = _ACTIONS[a & 0xFF]
+            if act == "EVICT":
+                out.append(("HAND", b, fr, act, f, p, a >> 8, blk))
+            else:
+                out.append(("HAND", b, fr, act, -1, -1, 0, blk))
+        elif op == 5:
+            out.append(("ALLOC", blk, f, p, fr, a, b))
+        elif op == 6:
+            out.append(("REQ", blk, f, p, a))
+        elif op == 7:
+            out.append(("NOFRAME", blk, f, p))
+    return out

@@ -45,8 +45,8 @@ def test_device_bytes_layout_scales_with_frames():
     f1, m1 = gfs.gfs_device_bytes(gfs.gfs_config_default(cache_bytes=256 << 20))
     f2, m2 = gfs.gfs_device_bytes(gfs.gfs_config_default(cache_bytes=512 << 20))
     assert f1 == 256 << 20 and f2 == 512 << 20
-    # frame words + tags (16 B) + table (4 entries x 8 B) per frame
-    assert m2 - m1 == (4096 * (8 + 8 + 32))
+    # frame words, tags and fill tags (24 B) + table (4 entries x 8 B) per frame
+    assert m2 - m1 == (4096 * (8 + 8 + 8 + 32))
     f3, m3 = gfs.gfs_device_bytes(gfs.gfs_config_default(trace_level=1, trace_capacity=1000))
     assert m3 - m1 >= 1000 * 32
 

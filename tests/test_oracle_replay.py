@@ -1,0 +1,127 @@
+"""The concurrent-trace replay checker (oracle.replay), pinned on the CPU.
+
+It must accept traces that follow the rules -- here the serialized model's own traces,
+re-labelled with tickets and blocks -- and reject traces with a planted mistake: a wrong
+eviction victim, a page held twice, a reused ticket, a wrong window, a request with a hole.
+"""
+import random
+
+import pytest
+
+from oracle import replay
+from oracle.policy import PolicyModel, run_serialized
+from workloads import configs
+
+
+def _to_replay(events):
+    """Model events -> replay tuples: give ALLOC the ticket of the claim before it and the
+    block of the current miss; give HAND the block too."""
+    out = []
+    blk = -1
+    last_claim = None
+    for e in events:
+        if e[0] == "MISS":
+            blk = e[1]
+            out.append(("MISS", blk, e[2], e[3], e[4], e[5], None))
+        elif e[0] == "HAND":
+            out.append(("HAND",) + tuple(e[1:]) + (blk,))
+            if e[3] in ("FREE", "EVICT"):
+                last_claim = e[1]
+        elif e[0] == "ALLOC":
+            out.append(("ALLOC", blk, e[1], e[2], e[3], e[4], last_claim))
+        elif e[0] == "REQ":
+            out.append(("REQ", blk, e[1], e[2], e[3]))
+        elif e[0] == "NOFRAME":
+            out.append(e)
+    return out
+
+
+def _fill_near(events, page_size, cap):
+    """The model does not log its near count; recompute it the way the detector does."""
+    out = []
+    recent = {}
+    for e in events:
+        if e[0] == "MISS" and cap:
+            r = recent.setdefault(e[2], [])
+            near = sum(1 for x in r if abs(x - e[3]) <= 64)
+            r.append(e[3])
+            if len(r) > 64:
+                r.pop(0)
+            e = e[:6] + (near,)
+        elif e[0] == "MISS":
+            e = e[:6] + (0,)
+        out.append(e)
+    return out
+
+
+def _model_trace(name, cap):
+    wl = configs.get(name)
+    C = wl.cache_bytes // wl.page_size
+    m = PolicyModel(C, wl.page_size, ra_init_pages=4, ra_cap_pages=cap, streams_per_file=8)
+    m.open(0, wl.file.size)
+    run_serialized(m, 0, wl.offsets, wl.read_size)
+    ev = _fill_near(_to_replay(m.events), wl.page_size, cap)
+    return wl, C, m, ev
+
+
+@pytest.mark.parametrize("name,cap", [("c2_small", 0), ("c2_small", 16), ("c3c_small", 8), ("c3a_small", 16)])
+def test_replay_accepts_rule_following_traces(name, cap):
+    wl, C, m, ev = _model_trace(name, cap)
+    rc = replay.replay_clock(ev, C)
+    assert [(f, p) for _, _, f, p in rc["evictions"]] == \
+        [(e[4], e[5]) for e in m.events if e[0] == "HAND" and e[3] == "EVICT"]
+    assert rc["allocations"] == m.fetched_pages and rc["wasted_pages"] == m.wasted_pages
+    rr = replay.replay_readahead(ev, 4, cap, 8, {0: wl.file.size}, wl.page_size)
+    assert rr["exact"] + rr["shape_only"] == m.misses
+    assert replay.replay_requests(ev) == m.requests
+
+
+def _mutate(ev, pred, fn):
+    out = list(ev)
+    for i, e in enumerate(out):
+        if pred(e):
+            out[i] = fn(e)
+            return out
+    raise AssertionError("nothing to mutate")
+
+
+def test_replay_rejects_wrong_victim():
+    wl, C, m, ev = _model_trace("c2_small", 0)
+    bad = _mutate(ev, lambda e: e[0] == "HAND" and e[3] == "EVICT", lambda e: e[:5] + (e[5] + 1,) + e[6:])
+    with pytest.raises(replay.ReplayError):
+        replay.replay_clock(bad, C)
+
+
+def test_replay_rejects_page_held_twice():
+    wl, C, m, ev = _model_trace("c2_small", 0)
+    allocs = [e for e in ev if e[0] == "ALLOC"]
+    # allocate the first page again at the second claim while it is still resident
+    first = allocs[0]
+    bad = _mutate(ev, lambda e: e is allocs[1], lambda e: e[:2] + (first[2], first[3]) + e[4:])
+    with pytest.raises(replay.ReplayError):
+        replay.replay_clock(bad, C)
+
+
+def test_replay_rejects_reused_ticket():
+    wl, C, m, ev = _model_trace("c2_small", 0)
+    hands = [e for e in ev if e[0] == "HAND"]
+    bad = _mutate(ev, lambda e: e is hands[5], lambda e: (e[0], hands[4][1]) + e[2:])
+    with pytest.raises(replay.ReplayError):
+        replay.replay_clock(bad, C)
+
+
+def test_replay_rejects_wrong_window():
+    wl, C, m, ev = _model_trace("c2_small", 16)
+    misses = [e for e in ev if e[0] == "MISS"]
+    target = misses[3]
+    bad = _mutate(ev, lambda e: e is target, lambda e: e[:5] + (e[5] + 1,) + e[6:])
+    with pytest.raises(replay.ReplayError):
+        replay.replay_readahead(bad, 4, 16, 8, {0: wl.file.size}, wl.page_size)
+
+
+def test_replay_rejects_request_with_hole():
+    wl, C, m, ev = _model_trace("c2_small", 16)
+    reqs = [e for e in ev if e[0] == "REQ" and e[4] >= 3]
+    bad = _mutate(ev, lambda e: e is reqs[0], lambda e: e[:4] + (e[4] + 1,))
+    with pytest.raises(replay.ReplayError):
+        replay.replay_requests(bad)
