@@ -204,6 +204,43 @@ int gfs_launch_list_reader(gfs_ctx* ctx, int file_id, const uint64_t* offsets, u
                            void* buf, void* out, int64_t* status, uint64_t* turn,
                            void* hip_stream);
 
+/* ---- batched persistent launch (many files, one kernel) ----
+ *
+ * A unit is one gread of one file: bytes [offset, offset+size) of file `file`, folded into
+ * output row `out` (per-file checksum and histogram). */
+typedef struct gfs_unit {
+  uint32_t file;      /* registered file id */
+  uint32_t out;       /* output row */
+  uint64_t offset;
+  uint64_t size;
+} gfs_unit;           /* 24 B */
+
+/* Plan the unit order of a batch (host only, no GPU): files in the given order are cut
+ * into units of at most unit_bytes; `grid / blocks_per_file` files are read at a time,
+ * their units interleaved round-robin, and a finished file's place is taken by the next
+ * one, so that a grid pulling units in order has about blocks_per_file blocks on each
+ * file. sizes: host array of nfiles file sizes; ids: host array of the registered file ids
+ * (out row i belongs to sizes[i]); out: host array of cap units; *nout receives the count.
+ * -EINVAL on bad arguments, -ENOSPC if cap is too small (*nout then holds the count needed). */
+int gfs_batch_plan(const uint64_t* sizes, const uint32_t* ids, uint32_t nfiles, uint64_t unit_bytes,
+                   uint32_t grid, uint32_t blocks_per_file, gfs_unit* out, uint64_t cap,
+                   uint64_t* nout);
+
+/* gfs_launch_batch: one persistent kernel of `grid` blocks x `threads` threads (a multiple
+ * of 64, <= 1024); blocks take units from units[0..nunits) in order through the device
+ * counter *counter (reset by the call), gread each into their own buf + b*unit_bytes, and
+ * fold the bytes into csum[out] (wrapping u64 sum of LE u32 words) and hist[out*256 + v]
+ * (u32 byte counts) with atomics. status (int64[grid]) receives the bytes each block read
+ * or the first negative errno. All pointers are device pointers; csum and hist must be
+ * zeroed by the caller; enqueued on hip_stream without waiting. -EINVAL on bad shapes. */
+int gfs_launch_batch(gfs_ctx* ctx, const gfs_unit* units, uint64_t nunits, uint32_t grid,
+                     uint32_t threads, uint64_t unit_bytes, void* buf, uint64_t* counter,
+                     uint64_t* csum, uint32_t* hist, int64_t* status, void* hip_stream);
+
+/* Blocks of `threads` threads that fit on the device at once for the batch kernel (the grid
+ * a persistent launch should use); -EIO on a HIP error. */
+int gfs_batch_grid(uint32_t threads, uint32_t* grid);
+
 #ifdef __cplusplus
 }
 #endif

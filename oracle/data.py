@@ -81,3 +81,22 @@ def block_histograms(path: str, offsets: np.ndarray, read_size: int,
             h += histogram_of(delivered(path, int(off), read_size))
         out[b] = h.astype(np.uint32)
     return out
+
+
+def file_checksum(path: str, chunk: int = 64 << 20) -> int:
+    """Checksum of the whole file: its bytes are one delivered buffer (chunks are multiples of
+    4 bytes, so summing per chunk changes nothing)."""
+    size = os.path.getsize(path)
+    s = 0
+    for off in range(0, size, chunk):
+        s = (s + checksum_of(delivered(path, off, chunk))) & ((1 << 64) - 1)
+    return s
+
+
+def file_histogram(path: str, chunk: int = 64 << 20) -> np.ndarray:
+    """Byte-value counts of the whole file (uint32; files here are below 4 GiB)."""
+    size = os.path.getsize(path)
+    h = np.zeros(256, dtype=np.uint64)
+    for off in range(0, size, chunk):
+        h += histogram_of(delivered(path, off, chunk))
+    return h.astype(np.uint32)

@@ -648,3 +648,50 @@ int gfs_shutdown(gfs_ctx* c) {
 }
 
 }  // extern "C"
+
+// ---- batch planning (host only) --------------------------------------------------------
+extern "C" int gfs_batch_plan(const uint64_t* sizes, const uint32_t* ids, uint32_t nfiles,
+                              uint64_t unit_bytes, uint32_t grid, uint32_t blocks_per_file,
+                              gfs_unit* out, uint64_t cap, uint64_t* nout) {
+  if (!sizes || !ids || !nout || nfiles == 0 || unit_bytes == 0 || unit_bytes % 16 || grid == 0 ||
+      blocks_per_file == 0)
+    return -EINVAL;
+  uint64_t need = 0;
+  for (uint32_t i = 0; i < nfiles; ++i) need += (sizes[i] + unit_bytes - 1) / unit_bytes;
+  *nout = need;
+  if (need > cap || (need && !out)) return -ENOSPC;
+  uint32_t lanes = grid / blocks_per_file;
+  if (lanes == 0) lanes = 1;
+  struct Lane {
+    uint32_t file;
+    uint64_t next;
+    bool busy;
+  };
+  std::vector<Lane> lane(lanes, Lane{0, 0, false});
+  uint32_t next_file = 0;
+  auto refill = [&](Lane& ln) {
+    while (next_file < nfiles && sizes[next_file] == 0) ++next_file;
+    if (next_file < nfiles) {
+      ln = Lane{next_file++, 0, true};
+    } else {
+      ln.busy = false;
+    }
+  };
+  for (auto& ln : lane) refill(ln);
+  uint64_t n = 0;
+  bool any = true;
+  while (any) {
+    any = false;
+    for (auto& ln : lane) {
+      if (!ln.busy) continue;
+      any = true;
+      const uint64_t left = sizes[ln.file] - ln.next;
+      const uint64_t sz = left < unit_bytes ? left : unit_bytes;
+      out[n++] = gfs_unit{ids[ln.file], ln.file, ln.next, sz};
+      ln.next += sz;
+      if (ln.next >= sizes[ln.file]) refill(ln);
+    }
+  }
+  *nout = n;
+  return 0;
+}

@@ -8,6 +8,8 @@
 #include "gfs_device.h"
 #include "gfs_layout.h"
 
+extern "C" int gfs_internal_zero(void* p, size_t bytes, hipStream_t s);
+
 namespace {
 
 __global__ void zero_kernel(uint64_t* p, uint64_t n8) {
@@ -119,7 +121,111 @@ __global__ void list_reader_kernel(const gfs_dev* d, int file_id, const uint64_t
   if (tid == 0) status[b] = err ? err : total;
 }
 
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* red, uint32_t tid, uint32_t nt) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  uint64_t s = 0;
+  if (tid == 0)
+    for (uint32_t w = 0; w < (nt + 63) / 64; ++w) s += red[w];
+  return s;   /* valid in thread 0 */
+}
+
+// Persistent batch reader: blocks take units in order from one device counter; a block
+// keeps its descriptor and its partial checksum/histogram while consecutive units belong
+// to the same file, and adds them into that file's output row when it moves on.
+__global__ void batch_reader_kernel(const gfs_dev* d, const gfs_unit* units, uint64_t nunits,
+                                    uint64_t* counter, uint8_t* buf, uint64_t unit_bytes,
+                                    uint64_t* csum, uint32_t* hist, int64_t* status) {
+  __shared__ uint32_t lhist[256];
+  __shared__ uint64_t red[16];
+  __shared__ uint64_t s_unit;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  uint8_t* mybuf = buf + (uint64_t)blockIdx.x * unit_bytes;
+  for (uint32_t i = tid; i < 256; i += nt) lhist[i] = 0;
+  int fd = -1;
+  uint32_t cur_file = 0xffffffffu, cur_out = 0;
+  uint64_t part = 0;
+  int64_t err = 0, total = 0;
+  bool dirty = false;
+  while (true) {
+    if (tid == 0) s_unit = __hip_atomic_fetch_add(counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const uint64_t u = s_unit;
+    __syncthreads();
+    if (u >= nunits) break;
+    const gfs_unit un = units[u];
+    if (un.file != cur_file) {
+      if (dirty) {
+        const uint64_t s = block_sum_u64(part, red, tid, nt);
+        if (tid == 0) __hip_atomic_fetch_add(&csum[cur_out], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        for (uint32_t i = tid; i < 256; i += nt) {
+          if (lhist[i]) atomicAdd(&hist[(uint64_t)cur_out * 256 + i], lhist[i]);
+          lhist[i] = 0;
+        }
+        part = 0;
+        dirty = false;
+      }
+      if (fd >= 0) gclose(d, fd);
+      fd = gopen_id(d, (int)un.file, GFS_O_RDONLY);
+      if (fd < 0) {
+        err = fd;
+        break;
+      }
+      cur_file = un.file;
+      cur_out = un.out;
+    }
+    const int64_t r = gread(d, fd, un.offset, un.size, mybuf);
+    if (r < 0) {
+      err = r;
+      break;
+    }
+    total += r;
+    part += checksum_part(mybuf, (uint64_t)r, tid, nt);
+    histogram_part(mybuf, (uint64_t)r, tid, nt, lhist);
+    dirty = true;
+    __syncthreads();
+  }
+  if (dirty) {
+    const uint64_t s = block_sum_u64(part, red, tid, nt);
+    if (tid == 0) __hip_atomic_fetch_add(&csum[cur_out], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    for (uint32_t i = tid; i < 256; i += nt)
+      if (lhist[i]) atomicAdd(&hist[(uint64_t)cur_out * 256 + i], lhist[i]);
+  }
+  if (fd >= 0) gclose(d, fd);
+  if (tid == 0) status[blockIdx.x] = err ? err : total;
+}
+
 }  // namespace
+
+extern "C" int gfs_launch_batch(gfs_ctx* ctx, const gfs_unit* units, uint64_t nunits, uint32_t grid,
+                                uint32_t threads, uint64_t unit_bytes, void* buf, uint64_t* counter,
+                                uint64_t* csum, uint32_t* hist, int64_t* status, void* hip_stream) {
+  if (!ctx || !units || !buf || !counter || !csum || !hist || !status) return -EINVAL;
+  if (grid == 0 || grid > (1u << 20) || threads == 0 || threads % 64 || threads > 1024) return -EINVAL;
+  if (unit_bytes == 0 || unit_bytes % 16) return -EINVAL;
+  if (((uintptr_t)buf | (uintptr_t)counter | (uintptr_t)csum) & 7) return -EINVAL;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int rc = gfs_internal_zero(counter, 8, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(batch_reader_kernel, dim3(grid), dim3(threads), 0, s, gfs_device_handle(ctx), units,
+                     nunits, counter, (uint8_t*)buf, unit_bytes, csum, hist, status);
+  return hipGetLastError() == hipSuccess ? 0 : -EIO;
+}
+
+extern "C" int gfs_batch_grid(uint32_t threads, uint32_t* grid) {
+  if (!grid || threads == 0 || threads % 64 || threads > 1024) return -EINVAL;
+  int dev = 0, per_cu = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -EIO;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_reader_kernel, (int)threads, 0) != hipSuccess)
+    return -EIO;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -EIO;
+  *grid = (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)cus;
+  return 0;
+}
 
 extern "C" int gfs_internal_zero(void* p, size_t bytes, hipStream_t s) {
   if (bytes % 8) return -EINVAL;

@@ -49,6 +49,8 @@ class gfs_stats(C.Structure):
         ("host_spins", C.c_uint64 * 64), ("host_threads", C.c_uint32), ("direct_io", C.c_uint32)]
 
 
+UNIT_DTYPE = np.dtype([("file", "<u4"), ("out", "<u4"), ("offset", "<u8"), ("size", "<u8")])
+
 EVENT_DTYPE = np.dtype([("op", "<u4"), ("block", "<u4"), ("file", "<u4"), ("page", "<u4"),
                         ("frame", "<u4"), ("a", "<u4"), ("b", "<u8")])
 
@@ -77,9 +79,12 @@ def lib() -> C.CDLL:
     L.gfs_reset_cache.argtypes = [vp]
     L.gfs_shutdown.argtypes = [vp]
     L.gfs_launch_list_reader.argtypes = [vp, i32, vp, u32, u32, u64, u32, i32, vp, vp, vp, vp, vp]
+    L.gfs_batch_plan.argtypes = [vp, vp, u32, u64, u32, u32, vp, u64, C.POINTER(u64)]
+    L.gfs_launch_batch.argtypes = [vp, vp, u64, u32, u32, u64, vp, vp, vp, vp, vp, vp]
+    L.gfs_batch_grid.argtypes = [u32, C.POINTER(u32)]
     for name in ("gfs_device_bytes", "gfs_init", "gfs_open", "gfs_fadvise", "gfs_close",
                  "gfs_stats_read", "gfs_trace_read", "gfs_reset_cache", "gfs_shutdown",
-                 "gfs_launch_list_reader"):
+                 "gfs_launch_list_reader", "gfs_batch_plan", "gfs_launch_batch", "gfs_batch_grid"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -168,6 +173,38 @@ def gfs_launch_list_reader(ctx: int, file_id: int, offsets_dev: int, blocks: int
                                         C.c_void_p(out_dev), C.c_void_p(status_dev),
                                         C.c_void_p(turn_dev or 0), C.c_void_p(stream)),
            "gfs_launch_list_reader")
+
+
+def gfs_batch_plan(sizes, ids, unit_bytes: int, grid: int, blocks_per_file: int) -> np.ndarray:
+    sizes = np.ascontiguousarray(sizes, dtype=np.uint64)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    if sizes.shape != ids.shape:
+        raise ValueError("sizes and ids differ in length")
+    n = C.c_uint64(0)
+    rc = lib().gfs_batch_plan(C.c_void_p(sizes.ctypes.data), C.c_void_p(ids.ctypes.data), len(sizes), unit_bytes,
+                              grid, blocks_per_file, None, 0, C.byref(n))
+    if rc not in (0, -28):
+        _check(rc, "gfs_batch_plan")
+    out = np.zeros(n.value, dtype=UNIT_DTYPE)
+    _check(lib().gfs_batch_plan(C.c_void_p(sizes.ctypes.data), C.c_void_p(ids.ctypes.data), len(sizes),
+                                unit_bytes, grid, blocks_per_file, C.c_void_p(out.ctypes.data), len(out),
+                                C.byref(n)), "gfs_batch_plan")
+    return out[: n.value]
+
+
+def gfs_launch_batch(ctx: int, units_dev: int, nunits: int, grid: int, threads: int, unit_bytes: int,
+                     buf_dev: int, counter_dev: int, csum_dev: int, hist_dev: int, status_dev: int,
+                     stream: int) -> None:
+    _check(lib().gfs_launch_batch(C.c_void_p(ctx), C.c_void_p(units_dev), nunits, grid, threads, unit_bytes,
+                                  C.c_void_p(buf_dev), C.c_void_p(counter_dev), C.c_void_p(csum_dev),
+                                  C.c_void_p(hist_dev), C.c_void_p(status_dev), C.c_void_p(stream)),
+           "gfs_launch_batch")
+
+
+def gfs_batch_grid(threads: int) -> int:
+    g = C.c_uint32(0)
+    _check(lib().gfs_batch_grid(threads, C.byref(g)), "gfs_batch_grid")
+    return g.value
 
 
 # ---- convenience: a cache over torch-allocated device memory ----------------------------

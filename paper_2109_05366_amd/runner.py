@@ -72,3 +72,46 @@ def run_list(cache: gfs.PageCache, file_id: int, offsets: np.ndarray, read_size:
     r = ListReader(offsets, read_size, consumer, threads)
     r.launch(cache, file_id, serialize=serialize)
     return r.result()
+
+
+@dataclasses.dataclass
+class BatchResult:
+    csum: np.ndarray       # uint64 [files]
+    hist: np.ndarray       # uint32 [files, 256]
+    status: np.ndarray     # int64 [grid]
+    units: int
+
+
+class BatchReader:
+    """Device buffers and unit plan for one persistent batch launch over registered files."""
+
+    def __init__(self, file_ids, sizes, unit_bytes: int, blocks_per_file: int, grid: int = 0,
+                 threads: int = 256, device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.threads = threads
+        self.grid = grid or gfs.gfs_batch_grid(threads)
+        self.unit_bytes = unit_bytes
+        self.nfiles = len(sizes)
+        plan = gfs.gfs_batch_plan(sizes, file_ids, unit_bytes, self.grid, blocks_per_file)
+        self.nunits = len(plan)
+        self.units = torch.from_numpy(plan.view(np.uint8).copy()).to(device)
+        self.buf = torch.empty(self.grid * unit_bytes, dtype=torch.uint8, device=device)
+        self.counter = torch.zeros(1, dtype=torch.int64, device=device)
+        self.csum = torch.zeros(self.nfiles, dtype=torch.int64, device=device)
+        self.hist = torch.zeros(self.nfiles * 256, dtype=torch.int32, device=device)
+        self.status = torch.zeros(self.grid, dtype=torch.int64, device=device)
+
+    def launch(self, cache: gfs.PageCache, stream=None) -> None:
+        s = stream if stream is not None else self.torch.cuda.current_stream()
+        self.csum.zero_()
+        self.hist.zero_()
+        gfs.gfs_launch_batch(cache.ctx, self.units.data_ptr(), self.nunits, self.grid, self.threads,
+                             self.unit_bytes, self.buf.data_ptr(), self.counter.data_ptr(),
+                             self.csum.data_ptr(), self.hist.data_ptr(), self.status.data_ptr(), s.cuda_stream)
+
+    def result(self) -> BatchResult:
+        self.torch.cuda.synchronize()
+        return BatchResult(csum=self.csum.cpu().numpy().view(np.uint64).copy(),
+                           hist=self.hist.cpu().numpy().view(np.uint32).reshape(self.nfiles, 256).copy(),
+                           status=self.status.cpu().numpy(), units=self.nunits)

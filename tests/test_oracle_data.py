@@ -132,3 +132,12 @@ def test_block_histograms_vs_closed_form(data_dir):
                 h[(w >> (8 * t)) & 0xFF] += 1
     assert [int(x) for x in got[5]] == h
     assert int(got[5].sum()) == wl.reads_per_block * wl.read_size
+
+
+def test_whole_file_checksum_and_histogram(data_dir):
+    spec = configs.FileSpec("pin_whole.bin", 11, (3 << 20) + 40)
+    path = configs.ensure_file(spec, data_dir)
+    raw = splitmix.file_bytes(11, 0, spec.size)
+    assert data.file_checksum(path, chunk=1 << 20) == _closed_form_checksum(raw)
+    h = data.file_histogram(path, chunk=1 << 20)
+    assert [int(x) for x in h] == [raw.count(bytes([v])) for v in range(256)]
