@@ -241,6 +241,67 @@ int gfs_launch_batch(gfs_ctx* ctx, const gfs_unit* units, uint64_t nunits, uint3
  * a persistent launch should use); -EIO on a HIP error. */
 int gfs_batch_grid(uint32_t threads, uint32_t* grid);
 
+/* Size in bytes of a registered file (host only). -EBADF if file_id is not registered. */
+int gfs_file_size(gfs_ctx* ctx, int file_id, uint64_t* size);
+
+/* The configuration the context was created with (host only). */
+int gfs_get_config(gfs_ctx* ctx, gfs_config* out);
+
+/* ---- serving loop (a stream of whole-file read requests, one persistent kernel) ----
+ *
+ * Every request reads one registered file from start to end through gread, in chunks of
+ * chunk_bytes, and yields the wrapping u64 sum of the file's little-endian u32 words (a
+ * trailing partial word zero-padded). Requests arrive at given times; the host admits them
+ * in arrival order while the cache bytes reserved by admitted, unfinished requests (file
+ * size rounded up to whole pages) plus the next request's stay within budget_bytes (a
+ * request is always admitted when nothing else is in flight). One persistent kernel of
+ * `grid` blocks serves every admitted request: blocks take (request, chunk) units, oldest
+ * request first, and newly admitted requests join between chunks. */
+typedef struct gfs_serve_request {
+  uint32_t file_id;       /* registered file */
+  uint32_t pad;
+  uint64_t arrival_ns;    /* arrival time after the start of the run; non-decreasing */
+} gfs_serve_request;      /* 16 B */
+
+typedef struct gfs_serve_params {
+  uint64_t budget_bytes;     /* cache bytes admitted requests may reserve (> 0) */
+  uint64_t chunk_bytes;      /* bytes per gread, a multiple of 16, <= 64 MiB */
+  uint32_t grid;             /* persistent blocks (0: as many as fit on the device) */
+  uint32_t threads;          /* threads per block, a multiple of 64, <= 1024 */
+  uint64_t idle_timeout_ns;  /* the kernel gives up when the host is silent this long (0: 60 s) */
+} gfs_serve_params;
+
+typedef struct gfs_serve_record {
+  uint64_t csum;          /* checksum of the file's bytes */
+  int64_t result;         /* bytes delivered, or -errno of the first failed gread */
+  uint64_t arrival_ns;    /* times after the start of the run, host clock */
+  uint64_t admit_ns;      /* the host handed the request to the kernel */
+  uint64_t first_ns;      /* first chunk delivered (device clock mapped to the host's) */
+  uint64_t done_ns;       /* the host saw the request complete */
+  uint64_t seq;           /* admission order */
+  uint64_t reserved;      /* cache bytes reserved for it */
+} gfs_serve_record;       /* 64 B */
+
+typedef struct gfs_serve_summary {
+  uint64_t span_ns;          /* start of the run to the last completion */
+  uint64_t delivered_bytes;  /* summed over requests */
+  uint64_t peak_reserved;    /* largest reservation total reached */
+  uint32_t peak_pending;     /* longest admission queue */
+  uint32_t grid;             /* blocks the kernel ran with */
+  uint64_t clock_skew_ns;    /* uncertainty of the device-to-host clock mapping */
+} gfs_serve_summary;
+
+/* Run a whole request stream and return when every request has completed (blocking).
+ * reqs: host array of n requests (1 <= n <= 2^20); out: host array of n records, in the
+ * order of reqs; summary may be NULL. Times are replayed on the host clock from the moment
+ * the kernel is seen running. The call allocates its own device and pinned buffers and frees
+ * them before returning; the kernel runs on hip_stream, which must not carry other work that
+ * waits on it. Errors: -EINVAL (bad arguments), -EBADF (a file not registered), -ENOMEM,
+ * -EIO (HIP error), -ETIMEDOUT (the kernel stopped serving); per-request failures are
+ * reported in out[i].result with the call returning 0. */
+int gfs_serve_run(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32_t n, const gfs_serve_params* params,
+                  gfs_serve_record* out, gfs_serve_summary* summary, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgfs.so")
 
-SOURCES = ["gfs_host.cpp", "gfs_kernels.hip"]
+SOURCES = ["gfs_host.cpp", "gfs_kernels.hip", "gfs_serve.hip"]
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed fp32 instructions are not used in this build

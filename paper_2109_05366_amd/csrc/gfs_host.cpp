@@ -521,6 +521,19 @@ int gfs_fadvise(gfs_ctx* c, int file_id, int advice) {
   return upload_file_record(c, file_id, rec);
 }
 
+int gfs_file_size(gfs_ctx* c, int file_id, uint64_t* size) {
+  if (!c || file_id < 0 || file_id >= (int)GFS_MAX_FILES || !c->files[file_id].open) return -EBADF;
+  if (!size) return -EINVAL;
+  *size = c->files[file_id].size;
+  return 0;
+}
+
+int gfs_get_config(gfs_ctx* c, gfs_config* out) {
+  if (!c || !out) return -EINVAL;
+  *out = c->cfg;
+  return 0;
+}
+
 int gfs_close(gfs_ctx* c, int file_id) {
   if (!c || file_id < 0 || file_id >= (int)GFS_MAX_FILES || !c->files[file_id].open) return -EBADF;
   gfs_file_dev rec;

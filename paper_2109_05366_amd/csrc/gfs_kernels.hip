@@ -7,51 +7,19 @@
 #include "gfs.h"
 #include "gfs_device.h"
 #include "gfs_layout.h"
+#include "gfs_consumers.h"
 
 extern "C" int gfs_internal_zero(void* p, size_t bytes, hipStream_t s);
 
 namespace {
 
+using gfs_consumers::block_sum_u64;
+using gfs_consumers::checksum_part;
+using gfs_consumers::histogram_part;
+
 __global__ void zero_kernel(uint64_t* p, uint64_t n8) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8; i += stride) p[i] = 0;
-}
-
-// Fold a delivered buffer into the block's consumer state.
-// checksum: wrapping u64 sum of LE u32 words, a trailing partial word zero-padded.
-__device__ __forceinline__ uint64_t checksum_part(const uint8_t* buf, uint64_t n, uint32_t tid,
-                                                  uint32_t nt) {
-  uint64_t s = 0;
-  const uint64_t n16 = n >> 4;
-  const gfsd::v4u* v = (const gfsd::v4u*)buf;
-  for (uint64_t i = tid; i < n16; i += nt) {
-    const gfsd::v4u x = v[i];
-    s += (uint64_t)x.x + x.y + x.z + x.w;
-  }
-  // remaining bytes (n not a multiple of 16): whole words, then the zero-padded last word
-  const uint64_t rem0 = n16 << 4;
-  for (uint64_t w = rem0 + 4ull * tid; w < n; w += 4ull * nt) {
-    uint32_t word = 0;
-    for (int b = 0; b < 4; ++b)
-      if (w + b < n) word |= (uint32_t)buf[w + b] << (8 * b);
-    s += word;
-  }
-  return s;
-}
-
-__device__ __forceinline__ void histogram_part(const uint8_t* buf, uint64_t n, uint32_t tid,
-                                               uint32_t nt, uint32_t* hist) {
-  const uint64_t n16 = n >> 4;
-  const gfsd::v4u* v = (const gfsd::v4u*)buf;
-  for (uint64_t i = tid; i < n16; i += nt) {
-    const gfsd::v4u x = v[i];
-    const uint32_t w[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) atomicAdd(&hist[(w[k] >> (8 * b)) & 0xff], 1u);
-  }
-  for (uint64_t j = (n16 << 4) + tid; j < n; j += nt) atomicAdd(&hist[buf[j]], 1u);
 }
 
 __global__ void list_reader_kernel(const gfs_dev* d, int file_id, const uint64_t* offsets,
@@ -119,17 +87,6 @@ __global__ void list_reader_kernel(const gfs_dev* d, int file_id, const uint64_t
     for (uint32_t i = tid; i < 256; i += nt) ((uint32_t*)out)[(uint64_t)b * 256 + i] = hist[i];
   }
   if (tid == 0) status[b] = err ? err : total;
-}
-
-__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* red, uint32_t tid, uint32_t nt) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  __syncthreads();
-  if ((tid & 63) == 0) red[tid >> 6] = v;
-  __syncthreads();
-  uint64_t s = 0;
-  if (tid == 0)
-    for (uint32_t w = 0; w < (nt + 63) / 64; ++w) s += red[w];
-  return s;   /* valid in thread 0 */
 }
 
 // Persistent batch reader: blocks take units in order from one device counter; a block

@@ -51,6 +51,21 @@ class gfs_stats(C.Structure):
 
 UNIT_DTYPE = np.dtype([("file", "<u4"), ("out", "<u4"), ("offset", "<u8"), ("size", "<u8")])
 
+SERVE_REQUEST_DTYPE = np.dtype([("file_id", "<u4"), ("pad", "<u4"), ("arrival_ns", "<u8")])
+SERVE_RECORD_DTYPE = np.dtype([("csum", "<u8"), ("result", "<i8"), ("arrival_ns", "<u8"), ("admit_ns", "<u8"),
+                               ("first_ns", "<u8"), ("done_ns", "<u8"), ("seq", "<u8"), ("reserved", "<u8")])
+
+
+class gfs_serve_params(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("chunk_bytes", C.c_uint64), ("grid", C.c_uint32),
+                ("threads", C.c_uint32), ("idle_timeout_ns", C.c_uint64)]
+
+
+class gfs_serve_summary(C.Structure):
+    _fields_ = [("span_ns", C.c_uint64), ("delivered_bytes", C.c_uint64), ("peak_reserved", C.c_uint64),
+                ("peak_pending", C.c_uint32), ("grid", C.c_uint32), ("clock_skew_ns", C.c_uint64)]
+
+
 EVENT_DTYPE = np.dtype([("op", "<u4"), ("block", "<u4"), ("file", "<u4"), ("page", "<u4"),
                         ("frame", "<u4"), ("a", "<u4"), ("b", "<u8")])
 
@@ -82,9 +97,13 @@ def lib() -> C.CDLL:
     L.gfs_batch_plan.argtypes = [vp, vp, u32, u64, u32, u32, vp, u64, C.POINTER(u64)]
     L.gfs_launch_batch.argtypes = [vp, vp, u64, u32, u32, u64, vp, vp, vp, vp, vp, vp]
     L.gfs_batch_grid.argtypes = [u32, C.POINTER(u32)]
+    L.gfs_file_size.argtypes = [vp, i32, C.POINTER(u64)]
+    L.gfs_get_config.argtypes = [vp, C.POINTER(gfs_config)]
+    L.gfs_serve_run.argtypes = [vp, vp, u32, C.POINTER(gfs_serve_params), vp, C.POINTER(gfs_serve_summary), vp]
     for name in ("gfs_device_bytes", "gfs_init", "gfs_open", "gfs_fadvise", "gfs_close",
                  "gfs_stats_read", "gfs_trace_read", "gfs_reset_cache", "gfs_shutdown",
-                 "gfs_launch_list_reader", "gfs_batch_plan", "gfs_launch_batch", "gfs_batch_grid"):
+                 "gfs_launch_list_reader", "gfs_batch_plan", "gfs_launch_batch", "gfs_batch_grid",
+                 "gfs_file_size", "gfs_get_config", "gfs_serve_run"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -205,6 +224,29 @@ def gfs_batch_grid(threads: int) -> int:
     g = C.c_uint32(0)
     _check(lib().gfs_batch_grid(threads, C.byref(g)), "gfs_batch_grid")
     return g.value
+
+
+def gfs_file_size(ctx: int, file_id: int) -> int:
+    v = C.c_uint64(0)
+    _check(lib().gfs_file_size(C.c_void_p(ctx), file_id, C.byref(v)), "gfs_file_size")
+    return v.value
+
+
+def gfs_get_config(ctx: int) -> gfs_config:
+    cfg = gfs_config()
+    _check(lib().gfs_get_config(C.c_void_p(ctx), C.byref(cfg)), "gfs_get_config")
+    return cfg
+
+
+def gfs_serve_run(ctx: int, requests: np.ndarray, params: gfs_serve_params,
+                  stream: int) -> Tuple[np.ndarray, Dict[str, int]]:
+    """requests: SERVE_REQUEST_DTYPE array; returns (SERVE_RECORD_DTYPE records, summary)."""
+    reqs = np.ascontiguousarray(requests, dtype=SERVE_REQUEST_DTYPE)
+    out = np.zeros(len(reqs), dtype=SERVE_RECORD_DTYPE)
+    summ = gfs_serve_summary()
+    _check(lib().gfs_serve_run(C.c_void_p(ctx), C.c_void_p(reqs.ctypes.data), len(reqs), C.byref(params),
+                               C.c_void_p(out.ctypes.data), C.byref(summ), C.c_void_p(stream)), "gfs_serve_run")
+    return out, {n: int(getattr(summ, n)) for n, _ in gfs_serve_summary._fields_}
 
 
 # ---- convenience: a cache over torch-allocated device memory ----------------------------

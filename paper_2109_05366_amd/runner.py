@@ -115,3 +115,25 @@ class BatchReader:
         return BatchResult(csum=self.csum.cpu().numpy().view(np.uint64).copy(),
                            hist=self.hist.cpu().numpy().view(np.uint32).reshape(self.nfiles, 256).copy(),
                            status=self.status.cpu().numpy(), units=self.nunits)
+
+
+def serve(cache: gfs.PageCache, file_ids, arrival_ns, budget_bytes: int, chunk_bytes: int = 1 << 20,
+          grid: int = 0, threads: int = 256, idle_timeout_s: float = 60.0, stream=None):
+    """Run a request stream through gfs_serve_run. file_ids[i] is request i's registered file,
+    arrival_ns[i] its arrival time. Returns (records, summary) as the binding gives them."""
+    import torch
+    req = np.zeros(len(file_ids), dtype=gfs.SERVE_REQUEST_DTYPE)
+    req["file_id"] = np.asarray(file_ids, dtype=np.uint32)
+    req["arrival_ns"] = np.asarray(arrival_ns, dtype=np.uint64)
+    params = gfs.gfs_serve_params(budget_bytes=budget_bytes, chunk_bytes=chunk_bytes, grid=grid, threads=threads,
+                                  idle_timeout_ns=int(idle_timeout_s * 1e9))
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return gfs.gfs_serve_run(cache.ctx, req, params, s.cuda_stream)
+
+
+def latency_ms(records: np.ndarray) -> dict:
+    """p50/p99 of time to first chunk and of completion, from arrival, in milliseconds."""
+    ttfp = (records["first_ns"].astype(np.float64) - records["arrival_ns"]) / 1e6
+    done = (records["done_ns"].astype(np.float64) - records["arrival_ns"]) / 1e6
+    return {"ttfp_p50": float(np.percentile(ttfp, 50)), "ttfp_p99": float(np.percentile(ttfp, 99)),
+            "done_p50": float(np.percentile(done, 50)), "done_p99": float(np.percentile(done, 99))}
