@@ -349,41 +349,108 @@ __device__ int64_t wait_valid_lane(const gfs_dev* d, uint32_t f, uint64_t t0) {
 }
 
 /* ------------------------------------------------------------------ per-file miss lock
- * A FIFO ticket lock: blocks get the lock in arrival order, which keeps the readers of a
- * file together (an unfair lock lets a few blocks run far ahead and spreads the misses
- * over the whole file). Waiters sleep in proportion to their distance from the head. */
-__device__ bool lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t t0, uint32_t& ticket) {
-  gfs_file_lock* lk = &d->locks[file];
-  int ok = 0;
-  uint32_t t = 0;
-  if (lane() == 0) {
-    t = __hip_atomic_fetch_add(&lk->next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while (true) {
-      const uint32_t s = ld_rlx32(&lk->serving);
-      if (s == t) {
-        ok = 1;
+ * A FIFO ticket lock whose waiters can leave the queue. Blocks get the lock in ticket
+ * order, which keeps the readers of a file together (an unfair lock lets a few blocks run
+ * far ahead and spreads the misses over the whole file). Each ticket has a queue slot
+ * (GFS_LOCK_SLOTS per file, more than the blocks the device can hold at once): the holder
+ * passes the lock by writing "granted n" into the slot of ticket n; a waiter whose page
+ * appears in the table while it waits (another block's window covered it) writes "left n"
+ * into its own slot instead, by compare-and-swap against the grant, and goes to the pin
+ * path; the holder skips left tickets. Ticket 0 of a cold file holds the lock at once.
+ * Slot values carry the ticket, so stale values of earlier tickets never match. */
+enum { LOCK_OWN = 0, LOCK_LEFT = 1, LOCK_TIMEOUT = 2 };
+
+__device__ __forceinline__ uint32_t lock_granted(uint64_t n) { return ((uint32_t)n << 2) | 1u; }
+__device__ __forceinline__ uint32_t lock_left(uint64_t n) { return ((uint32_t)n << 2) | 2u; }
+__device__ __forceinline__ uint32_t* lock_slot(const gfs_dev* d, uint32_t file, uint64_t n) {
+  return d->lockq + (uint64_t)file * GFS_LOCK_SLOTS + (n & (GFS_LOCK_SLOTS - 1));
+}
+
+/* Lane 0: leave the queue if ticket t is not granted yet; true if it left, false if the
+   lock was granted meanwhile (then the caller holds it). */
+__device__ bool lock_try_leave_lane(const gfs_dev* d, uint32_t file, uint64_t t) {
+  uint32_t* sl = lock_slot(d, file, t);
+  uint32_t v = __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while (v != lock_granted(t)) {
+    if (__hip_atomic_compare_exchange_strong(sl, &v, lock_left(t), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return true;
+  }
+  return false;
+}
+
+/* Wave-collective. Waits for the file's miss lock; while waiting, looks up `key` in the
+ * table now and then and leaves the queue if it appeared. Returns LOCK_OWN (ticket set),
+ * LOCK_LEFT, or LOCK_TIMEOUT (left the queue after the wait timeout). */
+__device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uint64_t t0, uint64_t& ticket);
+__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket);
+
+__device__ int32_t pt_lookup_wave(const gfs_dev* d, uint64_t key);
+
+__device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uint64_t t0, uint64_t& ticket) {
+  uint64_t t = 0;
+  if (lane() == 0)
+    t = __hip_atomic_fetch_add(&d->locks[file].next, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  t = __shfl(t, 0, 64);
+  ticket = t;
+  int res = LOCK_OWN;
+  if (t != 0) {
+    uint32_t* sl = lock_slot(d, file, t);
+    for (uint32_t n = 0;; ++n) {
+      int st = -1;   /* -1: keep waiting */
+      if (lane() == 0 &&
+          __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == lock_granted(t))
+        st = LOCK_OWN;
+      st = __shfl(st, 0, 64);
+      if (st < 0 && (n & 7) == 7) {
+        /* the page may have been reserved by a window that covers it */
+        const bool present = pt_lookup_wave(d, key) >= 0;
+        const bool late = expired(d, t0);
+        if (present || late) {
+          int left = 0;
+          if (lane() == 0) left = lock_try_leave_lane(d, file, t) ? 1 : 0;
+          left = __shfl(left, 0, 64);
+          st = left ? (present ? LOCK_LEFT : LOCK_TIMEOUT) : LOCK_OWN;
+        }
+      }
+      if (st >= 0) {
+        res = st;
         break;
       }
-      if (expired(d, t0)) break;
-      const uint32_t dist = t - s;
-      if (dist <= 1) {
-        __builtin_amdgcn_s_sleep(4);
-      } else {
-        const uint32_t reps = dist < 16 ? dist : 16;
-        for (uint32_t i = 0; i < reps; ++i) __builtin_amdgcn_s_sleep(32);
+      if (lane() == 0) {
+        if (n < 64) __builtin_amdgcn_s_sleep(2);
+        else __builtin_amdgcn_s_sleep(16);
       }
     }
   }
-  ok = __shfl(ok, 0, 64);
-  ticket = __shfl(t, 0, 64);
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return ok != 0;
+  return res;
 }
-__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint32_t ticket) {
+
+/* Wave-collective: pass the lock to the first later ticket that has not left. */
+__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  if (lane() == 0)
-    __hip_atomic_store(&d->locks[file].serving, ticket + 1, __ATOMIC_RELEASE,
-                       __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t l = lane();
+  uint64_t n = ticket + 1;
+  while (true) {
+    uint32_t* sl = lock_slot(d, file, n + l);
+    const uint32_t v = __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t gone = __ballot(v == lock_left(n + l));
+    if (~gone == 0ull) {
+      n += 64;
+      continue;
+    }
+    const uint32_t j = (uint32_t)__builtin_ctzll(~gone);
+    int ok = 0;
+    if (l == j) {
+      uint32_t expect = v;
+      ok = __hip_atomic_compare_exchange_strong(sl, &expect, lock_granted(n + j), __ATOMIC_RELAXED,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1 : 0;
+    }
+    ok = __shfl(ok, (int)j, 64);
+    if (ok) return;
+    n += j;   /* that waiter left just now: look again from its ticket */
+  }
 }
 
 /* ------------------------------------------------------------------ readahead detector
@@ -688,10 +755,16 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       if (l == 0) bcount(bs, GFS_C_RETRIES, 1);
     } else if (f < 0) {
       const uint64_t tl0 = wall_clock64();
-      uint32_t ticket;
-      if (!lock_file_wave(d, file, t0, ticket)) break;
+      uint64_t ticket;
+      const int lk = lock_file_wave(d, file, key, t0, ticket);
       const uint64_t tl1 = wall_clock64();
       if (l == 0) bcount(bs, GFS_T_LOCK, tl1 - tl0);
+      if (lk == LOCK_TIMEOUT) break;
+      if (lk == LOCK_LEFT) {
+        if (l == 0) bcount(bs, GFS_C_LOCK_LEFT, 1);
+        continue;   /* the page was reserved while this block waited: go to the pin path */
+      }
+      if (l == 0) bcount(bs, GFS_C_LOCKS, 1);
       if (pt_lookup_wave(d, key) >= 0) {
         unlock_file_wave(d, file, ticket);   /* filled or reserved meanwhile: go to the pin path */
         if (l == 0) bcount(bs, GFS_T_CRIT, wall_clock64() - tl1);
@@ -700,7 +773,10 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       /* miss: decide the window, reserve the run of unmapped pages around p, unlock */
       uint64_t ws;
       uint32_t wn, near;
+      const uint64_t td0 = wall_clock64();
       ra_decide_wave(d, file, p, ws, wn, near);
+      const uint64_t td1 = wall_clock64();
+      if (l == 0) bcount(bs, GFS_T_DECIDE, td1 - td0);
       const uint64_t npages = d->files[file].npages;
       if (ws + wn > npages) wn = (uint32_t)(npages - ws);
       if (l == 0) trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, near, wn, ws);
@@ -741,10 +817,15 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
         failed |= slot < 0 ? 1u : 0u;
       }
       failed = (uint32_t)(__ballot(failed != 0) != 0);
+      const uint64_t tu0 = wall_clock64();
       unlock_file_wave(d, file, ticket);
       wave_sync_lds();
       const uint64_t tl2 = wall_clock64();
-      if (l == 0) bcount(bs, GFS_T_CRIT, tl2 - tl1);
+      if (l == 0) {
+        bcount(bs, GFS_T_CRIT, tl2 - tl1);
+        bcount(bs, GFS_T_RUN, tu0 - td1);
+        bcount(bs, GFS_T_UNLOCK, tl2 - tu0);
+      }
       /* a reservation can fail only if both buckets are full: keep the prefix before the
          first failure (the demanded page comes first) and drop the rest */
       uint32_t keep = n;

@@ -5,10 +5,11 @@
  * word and page-table entry encodings, and the request-ring slot in pinned host memory.
  *
  * HBM layout of the metadata region (offsets computed by the host, stored in gfs_dev):
- *   gfs_globals                      256 B
+ *   gfs_globals                      320 B
  *   gfs_dev (the handle)             512 B
  *   files[GFS_MAX_FILES]             768 B each
  *   locks[GFS_MAX_FILES]             128 B each (miss ticket locks)
+ *   lockq[GFS_MAX_FILES][GFS_LOCK_SLOTS] u32   queue slots of the miss locks
  *   names[GFS_MAX_FILES]             GFS_NAME_MAX B each (registered paths)
  *   fword[nframes]  u64              frame word (state, pins, ref, ra, version)
  *   ftag[nframes]   u64              key of the page held (valid while not FREE)
@@ -54,7 +55,7 @@ typedef struct gfs_globals {
   uint64_t ring_tail;     /* request ring ticket counter */
   uint64_t trace_n;       /* trace records appended (including dropped) */
   uint64_t pad0[5];
-  uint64_t ctr[24];       /* device counters, GFS_C_* */
+  uint64_t ctr[32];       /* device counters, GFS_C_* */
 } gfs_globals;
 
 enum {
@@ -63,6 +64,10 @@ enum {
   GFS_C_NOFRAME, GFS_C_TIMEOUTS, GFS_C_IOERR,
   /* wall-clock ticks summed over blocks, by phase of the miss path */
   GFS_T_LOCK, GFS_T_CRIT, GFS_T_ALLOC, GFS_T_SLOT, GFS_T_HOST, GFS_T_PULL, GFS_T_JOIN,
+  /* parts of GFS_T_CRIT: readahead decision, run finding + reservation, unlock */
+  GFS_T_DECIDE, GFS_T_RUN, GFS_T_UNLOCK,
+  GFS_C_LOCKS,       /* miss locks taken */
+  GFS_C_LOCK_LEFT,   /* waits for a miss lock given up because the page appeared */
   GFS_C_COUNT
 };
 
@@ -95,10 +100,13 @@ typedef struct gfs_file_dev {
 /* per-file miss lock: a ticket lock on a cache line of its own, so that waiters polling
    it do not slow the holder's accesses to the file record */
 typedef struct gfs_file_lock {
-  uint32_t next;          /* tickets handed out */
-  uint32_t serving;       /* ticket that holds the lock */
-  uint32_t pad[30];
+  uint64_t next;          /* tickets handed out */
+  uint64_t pad[15];
 } gfs_file_lock;          /* 128 B */
+
+/* queue slots of each file's miss lock (u32 each); at least the number of blocks the
+   device can hold at once (256 CUs x 32 waves) */
+#define GFS_LOCK_SLOTS 8192u
 
 #define GFS_NAME_MAX 256     /* registered path, NUL-terminated, for gopen(path) */
 
@@ -151,6 +159,7 @@ typedef struct gfs_dev {
   gfs_globals* g;
   gfs_file_dev* files;
   gfs_file_lock* locks;
+  uint32_t* lockq;              /* [GFS_MAX_FILES][GFS_LOCK_SLOTS] miss-lock queue slots */
   uint64_t* slot_free;
   uint64_t* ffill;
   gfs_req_dev* reqd;
@@ -159,7 +168,7 @@ typedef struct gfs_dev {
   char* names;                  /* [GFS_MAX_FILES][GFS_NAME_MAX] registered paths */
   gfs_rpc_slot* ring;           /* device-visible address of the pinned ring */
   uint8_t* staging;             /* device-visible address of the pinned staging */
-  uint64_t pad[4];
+  uint64_t pad[3];
 } gfs_dev;
 
 #endif /* GFS_LAYOUT_H */

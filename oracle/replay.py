@@ -160,19 +160,22 @@ def replay_requests(events) -> int:
     n = 0
     for blk, seq in per_block.items():
         cur = None
-        pages: List[int] = []
+        allocs: List[tuple] = []
         for e in seq:
             if e[0] == "MISS":
                 # a miss that got no frame at all is retried: it leaves no allocation behind
-                _check(cur is None or not pages, f"block {blk}: miss at {e[3]} before the previous request")
+                _check(cur is None or not allocs, f"block {blk}: miss at {e[3]} before the previous request")
                 cur = e
-                pages = []
+                allocs = []
             elif e[0] == "ALLOC":
                 _check(cur is not None, f"block {blk}: allocation outside a miss")
-                pages.append(e[3])
+                allocs.append((e[6], e[3]))
             elif e[0] == "REQ":
                 _check(cur is not None, f"block {blk}: request without a miss")
                 _, _b, fid, p, ws, wn, _near = cur
+                # the lanes of one wave append their records in no fixed order; the hand
+                # tickets fix the order in which the run's pages were given frames
+                pages = [q for _, q in sorted(allocs)]
                 _check(pages and pages[0] == p, f"block {blk}: first allocation is not the demanded page {p}")
                 lo, hi = min(pages), max(pages)
                 _check(sorted(pages) == list(range(lo, hi + 1)), f"block {blk}: request run has holes {sorted(pages)}")
@@ -180,5 +183,5 @@ def replay_requests(events) -> int:
                 _check((e[3], e[4]) == (lo, hi - lo + 1), f"block {blk}: request {e[3:]} != run {(lo, hi - lo + 1)}")
                 n += 1
                 cur = None
-        _check(cur is None or not pages, f"block {blk}: trailing miss without request")
+        _check(cur is None or not allocs, f"block {blk}: trailing miss without request")
     return n

@@ -53,7 +53,7 @@ uint32_t log2u(uint64_t v) {
 struct Layout {
   uint64_t nframes = 0, nbuckets = 0, ra_init = 0, ra_cap = 0, max_req_pages = 0;
   uint64_t max_req_bytes = 0;
-  uint64_t off_globals = 0, off_dev = 0, off_files = 0, off_locks = 0, off_names = 0, off_fword = 0,
+  uint64_t off_globals = 0, off_dev = 0, off_files = 0, off_locks = 0, off_lockq = 0, off_names = 0, off_fword = 0,
            off_ftag = 0, off_pt = 0, off_ffill = 0, off_slot_free = 0, off_reqd = 0, off_trace = 0,
            meta_bytes = 0;
 };
@@ -87,6 +87,7 @@ int make_layout(const gfs_config* c, Layout* L) {
   L->off_dev = o; o = align_up(o + sizeof(gfs_dev), kAlign);
   L->off_files = o; o = align_up(o + sizeof(gfs_file_dev) * GFS_MAX_FILES, kAlign);
   L->off_locks = o; o = align_up(o + sizeof(gfs_file_lock) * GFS_MAX_FILES, kAlign);
+  L->off_lockq = o; o = align_up(o + 4ull * GFS_LOCK_SLOTS * GFS_MAX_FILES, kAlign);
   L->off_names = o; o = align_up(o + (uint64_t)GFS_NAME_MAX * GFS_MAX_FILES, kAlign);
   L->off_fword = o; o = align_up(o + 8 * L->nframes, kAlign);
   L->off_ftag = o; o = align_up(o + 8 * L->nframes, kAlign);
@@ -324,7 +325,8 @@ int download_file_record(gfs_ctx* c, int id, gfs_file_dev* rec) {
 int zero_dynamic(gfs_ctx* c) {
   const Layout& L = c->L;
   int rc = gfs_internal_zero(c->meta + L.off_globals, sizeof(gfs_globals), c->stream);
-  if (!rc) rc = gfs_internal_zero(c->meta + L.off_locks, sizeof(gfs_file_lock) * GFS_MAX_FILES, c->stream);
+  // miss locks and their queue slots
+  if (!rc) rc = gfs_internal_zero(c->meta + L.off_locks, L.off_names - L.off_locks, c->stream);
   if (!rc) rc = gfs_internal_zero(c->meta + L.off_fword, L.off_trace - L.off_fword, c->stream);
   if (!rc && c->cfg.trace_capacity)
     rc = gfs_internal_zero(c->meta + L.off_trace, sizeof(gfs_event) * (uint64_t)c->cfg.trace_capacity, c->stream);
@@ -385,6 +387,18 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
     delete c;
     return -EIO;
   }
+  // every block the device can hold at once may wait on one file's miss lock: each needs
+  // its own queue slot
+  int cus = 0, thr_per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+      hipDeviceGetAttribute(&thr_per_cu, hipDeviceAttributeMaxThreadsPerMultiProcessor, c->device) != hipSuccess) {
+    delete c;
+    return -EIO;
+  }
+  if ((uint64_t)cus * (uint64_t)(thr_per_cu / 64) > GFS_LOCK_SLOTS) {
+    delete c;
+    return -EINVAL;
+  }
   const uint64_t ring_bytes = sizeof(gfs_rpc_slot) * (uint64_t)cfg->rpc_slots;
   const uint64_t staging_bytes = L.max_req_bytes * (uint64_t)cfg->rpc_slots;
   if (hipHostMalloc((void**)&c->ring, ring_bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
@@ -426,6 +440,7 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   h.g = (gfs_globals*)(c->meta + L.off_globals);
   h.files = (gfs_file_dev*)(c->meta + L.off_files);
   h.locks = (gfs_file_lock*)(c->meta + L.off_locks);
+  h.lockq = (uint32_t*)(c->meta + L.off_lockq);
   h.names = (char*)(c->meta + L.off_names);
   h.fword = (uint64_t*)(c->meta + L.off_fword);
   h.ftag = (uint64_t*)(c->meta + L.off_ftag);
@@ -588,6 +603,11 @@ int gfs_stats_read(gfs_ctx* c, gfs_stats* out) {
   s.t_host_ns = (uint64_t)(g.ctr[GFS_T_HOST] * ns_per_tick);
   s.t_pull_ns = (uint64_t)(g.ctr[GFS_T_PULL] * ns_per_tick);
   s.t_join_ns = (uint64_t)(g.ctr[GFS_T_JOIN] * ns_per_tick);
+  s.t_decide_ns = (uint64_t)(g.ctr[GFS_T_DECIDE] * ns_per_tick);
+  s.t_run_ns = (uint64_t)(g.ctr[GFS_T_RUN] * ns_per_tick);
+  s.t_unlock_ns = (uint64_t)(g.ctr[GFS_T_UNLOCK] * ns_per_tick);
+  s.lock_acquired = g.ctr[GFS_C_LOCKS];
+  s.lock_left = g.ctr[GFS_C_LOCK_LEFT];
   s.host_errors = c->host_errors.load();
   s.host_last_errno = (uint64_t)c->host_last_errno.load();
   for (uint32_t i = 0; i < 64; ++i) s.host_spins[i] = c->spins[i].load();

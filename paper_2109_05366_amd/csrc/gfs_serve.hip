@@ -144,10 +144,13 @@ __device__ bool poll_host(SrvCtrl* ctl, SrvEntry* tab, uint32_t cap, const SrvSu
     gfsd::st_rel(&ctl->final_n, ing + 1);
     return false;
   }
-  uint64_t last = gfsd::ld_acq(&ctl->progress);
+  // other blocks store newer clock values into progress at any time: read the clock after
+  // it, and compare signed, so that a value stored after `now` was read is not "idle"
+  const uint64_t last = gfsd::ld_acq(&ctl->progress);
+  const uint64_t t = wall_clock64();
   if (last == 0) {
-    gfsd::st_rlx(&ctl->progress, now);
-  } else if (now - last > idle_ticks) {
+    gfsd::st_rlx(&ctl->progress, t);
+  } else if ((int64_t)(t - last) > (int64_t)idle_ticks) {
     gfsd::st_rel(&ctl->abort, 1);
   }
   return false;

@@ -44,8 +44,10 @@ def small_batch(data_dir):
 @pytest.mark.parametrize("cache_mib", [256, 32])
 def test_batch_small_parity(cfg, cache_mib, small_batch, cuda):
     m, paths, sizes, want_c, want_h = small_batch
-    print(f"[gpu] batch_small cfg={cfg} cache={cache_mib} MiB", flush=True)
-    bb = autotune.BatchBench(paths, sizes, cache_mib << 20, rpc_slots=16)
+    # the cache must hold at least 64 pages; 128 MiB of 2 MiB pages is still below the batch
+    cache_bytes = max(cache_mib << 20, 64 * cfg[0])
+    print(f"[gpu] batch_small cfg={cfg} cache={cache_bytes >> 20} MiB", flush=True)
+    bb = autotune.BatchBench(paths, sizes, cache_bytes, rpc_slots=16)
     gbs, res, st = bb.run(cfg)
     assert st["timeouts"] == 0 and st["io_errors"] == 0
     assert int(res.status.sum()) == sum(sizes)

@@ -125,3 +125,31 @@ def test_replay_rejects_request_with_hole():
     bad = _mutate(ev, lambda e: e is reqs[0], lambda e: e[:4] + (e[4] + 1,))
     with pytest.raises(replay.ReplayError):
         replay.replay_requests(bad)
+
+
+def test_replay_requests_orders_allocations_by_ticket():
+    """Records of one wave's allocations may appear in any order; the tickets decide. Swapping
+    two records keeps the trace valid; giving the demanded page a later ticket does not."""
+    wl, C, m, ev = _model_trace("c2_small", 16)
+    n = replay.replay_requests(ev)
+    # the first two allocations of one request (same block, no MISS or REQ between them)
+    i = j = None
+    for k, e in enumerate(ev):
+        if e[0] == "MISS":
+            i = None
+        elif e[0] == "ALLOC":
+            if i is None:
+                i = k
+            elif ev[i][1] == e[1]:
+                j = k
+                break
+    assert i is not None and j is not None
+    swapped = list(ev)
+    swapped[i], swapped[j] = ev[j], ev[i]
+    assert replay.replay_requests(swapped) == n
+    a, b = ev[i], ev[j]
+    retick = list(ev)
+    retick[i] = a[:6] + (b[6],)
+    retick[j] = b[:6] + (a[6],)
+    with pytest.raises(replay.ReplayError):
+        replay.replay_requests(retick)
