@@ -35,6 +35,39 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# sources the list-reader kernel is compiled from: HBM traffic counted for one version of
+# them is reported only while they are unchanged
+KERNEL_SOURCES = ("include/gfs_device.h", "include/gfs_layout.h", "include/gfs.h",
+                  "paper_2109_05366_amd/csrc/gfs_kernels.hip", "paper_2109_05366_amd/csrc/gfs_consumers.h")
+TRAFFIC_SUMMARY = "profiles/list_reader_c2_hbm_traffic.md"
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """(bytes per launch, summary file) from the committed counter summary, if it was taken
+    on the current kernel sources; else (None, reason)."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.split(":", 1)[0].strip() in ("kernel_source_sha256", "traffic_bytes_per_launch"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    return int(fields["traffic_bytes_per_launch"]), TRAFFIC_SUMMARY
+
+
 def storage_peak(path: str, threads: int = 4, chunk: int = 4 << 20, limit: int = 8 << 30) -> float:
     """O_DIRECT (if available) sequential read of the file with `threads` readers; GB/s."""
     size = min(os.path.getsize(path), limit)
@@ -412,6 +445,7 @@ def main() -> int:
     # (frame fill write, copy-out read, user-buffer write)
     kms_ra = kernel_ms["ra"]
     achieved = 3 * delivered / (kms_ra * 1e-3) / 1e9
+    traffic, traffic_src = recorded_traffic()
     line = {
         "metric": "delivered file-read GB/s (readahead vs none) + fraction of min(NVMe, H2D) peak",
         "value": round(value, 3),
@@ -439,7 +473,9 @@ def main() -> int:
         "io_bound": {"bound": bound_name, "achieved": round(value, 3), "peak": round(min_peak, 3),
                      "unit": "GB/s", "frac": round(value / min_peak, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": traffic if wl.name == "c2" else None,
+                     "traffic_source": traffic_src if wl.name == "c2" else "counters taken on c2 only",
                      "kernel": "list_reader_kernel", "kernel_ms": round(kms_ra, 2),
                      "bytes_per_launch": 3 * delivered},
         "hit_path": hit,

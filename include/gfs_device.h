@@ -427,29 +427,32 @@ __device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uin
   return res;
 }
 
-/* Wave-collective: pass the lock to the first later ticket that has not left. */
+/* Wave-collective: pass the lock to the first later ticket that has not left. One exchange
+ * writes the grant into the next ticket's slot; if that waiter had already left (its slot
+ * said so), the wave scans the following slots 64 at a time and grants the first ticket
+ * that has not left. A waiter leaving concurrently loses its compare-and-swap against the
+ * grant and holds the lock instead. */
 __device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   const uint32_t l = lane();
   uint64_t n = ticket + 1;
   while (true) {
-    uint32_t* sl = lock_slot(d, file, n + l);
-    const uint32_t v = __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t gone = __ballot(v == lock_left(n + l));
-    if (~gone == 0ull) {
+    uint32_t old = 0;
+    if (l == 0)
+      old = __hip_atomic_exchange(lock_slot(d, file, n), lock_granted(n), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+    old = __shfl(old, 0, 64);
+    if (old != lock_left(n)) return;
+    ++n;
+    while (true) {
+      const uint32_t v = ld_rlx32(lock_slot(d, file, n + l));
+      const uint64_t gone = __ballot(v == lock_left(n + l));
+      if (~gone != 0ull) {
+        n += (uint32_t)__builtin_ctzll(~gone);
+        break;
+      }
       n += 64;
-      continue;
     }
-    const uint32_t j = (uint32_t)__builtin_ctzll(~gone);
-    int ok = 0;
-    if (l == j) {
-      uint32_t expect = v;
-      ok = __hip_atomic_compare_exchange_strong(sl, &expect, lock_granted(n + j), __ATOMIC_RELAXED,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1 : 0;
-    }
-    ok = __shfl(ok, (int)j, 64);
-    if (ok) return;
-    n += j;   /* that waiter left just now: look again from its ticket */
   }
 }
 
@@ -709,6 +712,66 @@ __device__ void join_or_help_lane(const gfs_dev* d, uint32_t f, uint64_t p, uint
   }
 }
 
+/* Wave-collective, under the file's miss lock, for a window of at most 64 pages with p
+ * absent: find the run of absent pages around p inside [ws, ws + wn) and reserve them.
+ * Lane i loads both buckets of page ws + i once; the run is read off the ballot of
+ * present pages; each run lane takes a free entry of its less loaded bucket from the
+ * loaded copy with one compare-and-swap (and reloads only if that swap loses a race).
+ * Fills bs->list/lslot/lframe in allocation order (p first, then the rest ascending);
+ * returns the run length and sets failed if some page found both buckets full. */
+__device__ uint32_t reserve_run_small_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint64_t ws,
+                                           uint32_t wn, BlockState* bs, uint32_t& failed) {
+  const uint32_t l = lane();
+  const uint64_t q = ws + l;
+  const uint64_t key = page_key(file, q);
+  const uint64_t ent = (key << GFS_ENTRY_FRAME_BITS) | kReserved;
+  uint32_t b1 = 0, b2 = 0;
+  uint64_t e[2 * GFS_BUCKET_SLOTS];
+  bool present = false;
+  if (l < wn) {
+    key_buckets(d, key, b1, b2);
+    pt_load_lane(d, b1, b2, e);
+#pragma unroll
+    for (int i = 0; i < 2 * GFS_BUCKET_SLOTS; ++i) present |= (e[i] >> GFS_ENTRY_FRAME_BITS) == key;
+  }
+  const uint32_t pi = (uint32_t)(p - ws);
+  uint64_t pm = __ballot(l < wn && present);
+  if (wn < 64) pm |= ~0ull << wn;             /* pages outside the window stop the run */
+  pm &= ~(1ull << pi);                         /* p itself is absent (probed under the lock) */
+  const uint64_t below = pm & ((1ull << pi) - 1);
+  const uint64_t above = pi == 63 ? 0ull : (pm >> (pi + 1)) << (pi + 1);
+  const uint32_t a = below ? 64u - (uint32_t)__builtin_clzll(below) : 0u;
+  const uint32_t b = above ? (uint32_t)__builtin_ctzll(above) - 1u : 63u;
+  const uint32_t n = b - a + 1;
+  uint32_t bad = 0;
+  if (l >= a && l <= b) {
+    const uint32_t i = l == pi ? 0u : (l < pi ? l - a + 1 : l - a);
+    int64_t slot = -1;
+    int cnt1 = 0, cnt2 = 0, f1 = -1, f2 = -1;
+#pragma unroll
+    for (int k = 0; k < GFS_BUCKET_SLOTS; ++k) {
+      if (e[k]) ++cnt1;
+      else if (f1 < 0) f1 = k;
+      if (e[GFS_BUCKET_SLOTS + k]) ++cnt2;
+      else if (f2 < 0) f2 = GFS_BUCKET_SLOTS + k;
+    }
+    int pick = cnt2 < cnt1 ? f2 : f1;
+    if (pick < 0) pick = f1 >= 0 ? f1 : f2;
+    if (pick >= 0) {
+      uint64_t expect = 0;
+      uint64_t* sp = slot_ptr(d, b1, b2, pick);
+      if (cas64_rlx(sp, expect, ent)) slot = (int64_t)(sp - d->pt);
+      else slot = pt_reserve_lane(d, key);    /* the entry was taken meanwhile: reload */
+    }
+    bs->list[i] = (uint32_t)q;
+    bs->lslot[i] = slot < 0 ? 0xffffffffu : (uint32_t)slot;
+    bs->lframe[i] = GFS_NO_FRAME;
+    bad = slot < 0 ? 1u : 0u;
+  }
+  failed = bad;
+  return n;
+}
+
 /* ------------------------------------------------------------------ one page, wave 0
  * Leaves in bs: status; on success the pinned frame, and pull = 1 when this block posted
  * the request and must pull it. */
@@ -765,8 +828,11 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
         continue;   /* the page was reserved while this block waited: go to the pin path */
       }
       if (l == 0) bcount(bs, GFS_C_LOCKS, 1);
+      /* every block waiting on this file's lock waits for this wave: let it issue first */
+      __builtin_amdgcn_s_setprio(3);
       if (pt_lookup_wave(d, key) >= 0) {
         unlock_file_wave(d, file, ticket);   /* filled or reserved meanwhile: go to the pin path */
+        __builtin_amdgcn_s_setprio(0);
         if (l == 0) bcount(bs, GFS_T_CRIT, wall_clock64() - tl1);
         continue;
       }
@@ -780,45 +846,53 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       const uint64_t npages = d->files[file].npages;
       if (ws + wn > npages) wn = (uint32_t)(npages - ws);
       if (l == 0) trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, near, wn, ws);
-      uint64_t a = p;
-      for (uint64_t base = p; base > ws;) {
-        const bool valid = (uint64_t)l < base - ws;
-        bool stop = !valid;
-        if (valid) stop = pt_present_lane(d, page_key(file, base - 1 - l));
-        const uint64_t sm = __ballot(stop);
-        const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
-        a = base - k;
-        if (k < 64) break;
-        base -= 64;
-      }
-      uint64_t b = p;
-      for (uint64_t base = p + 1; base < ws + wn;) {
-        const bool valid = (uint64_t)l < ws + wn - base;
-        bool stop = !valid;
-        if (valid) stop = pt_present_lane(d, page_key(file, base + l));
-        const uint64_t sm = __ballot(stop);
-        const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
-        b = base + k - 1;
-        if (k < 64) break;
-        base += 64;
-      }
-      const uint32_t n = (uint32_t)(b - a + 1);
-      /* allocation order: the demanded page first, then the rest of the run ascending */
-      uint32_t failed = 0;
-      for (uint32_t i = l; i < n; i += 64) {
-        uint64_t q;
-        if (i == 0) q = p;
-        else if (i <= p - a) q = a + i - 1;
-        else q = a + i;
-        const int64_t slot = pt_reserve_lane(d, page_key(file, q));
-        bs->list[i] = (uint32_t)q;
-        bs->lslot[i] = slot < 0 ? 0xffffffffu : (uint32_t)slot;
-        bs->lframe[i] = GFS_NO_FRAME;
-        failed |= slot < 0 ? 1u : 0u;
+      uint32_t n = 0, failed = 0;
+      if (wn <= 64) {
+        /* one round: lane i loads the buckets of window page ws + i, the run around p is
+           read off the ballot of present pages, and each run lane reserves its page from
+           the buckets it already holds */
+        n = reserve_run_small_wave(d, file, p, ws, wn, bs, failed);
+      } else {
+        uint64_t a = p;
+        for (uint64_t base = p; base > ws;) {
+          const bool valid = (uint64_t)l < base - ws;
+          bool stop = !valid;
+          if (valid) stop = pt_present_lane(d, page_key(file, base - 1 - l));
+          const uint64_t sm = __ballot(stop);
+          const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
+          a = base - k;
+          if (k < 64) break;
+          base -= 64;
+        }
+        uint64_t b = p;
+        for (uint64_t base = p + 1; base < ws + wn;) {
+          const bool valid = (uint64_t)l < ws + wn - base;
+          bool stop = !valid;
+          if (valid) stop = pt_present_lane(d, page_key(file, base + l));
+          const uint64_t sm = __ballot(stop);
+          const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
+          b = base + k - 1;
+          if (k < 64) break;
+          base += 64;
+        }
+        n = (uint32_t)(b - a + 1);
+        /* allocation order: the demanded page first, then the rest of the run ascending */
+        for (uint32_t i = l; i < n; i += 64) {
+          uint64_t q;
+          if (i == 0) q = p;
+          else if (i <= p - a) q = a + i - 1;
+          else q = a + i;
+          const int64_t slot = pt_reserve_lane(d, page_key(file, q));
+          bs->list[i] = (uint32_t)q;
+          bs->lslot[i] = slot < 0 ? 0xffffffffu : (uint32_t)slot;
+          bs->lframe[i] = GFS_NO_FRAME;
+          failed |= slot < 0 ? 1u : 0u;
+        }
       }
       failed = (uint32_t)(__ballot(failed != 0) != 0);
       const uint64_t tu0 = wall_clock64();
       unlock_file_wave(d, file, ticket);
+      __builtin_amdgcn_s_setprio(0);
       wave_sync_lds();
       const uint64_t tl2 = wall_clock64();
       if (l == 0) {
