@@ -321,6 +321,58 @@ def bench_serve(args, torch) -> int:
     return 0
 
 
+def bench_small_pages(args, torch) -> int:
+    """Small-page regime: the same strided reads of a 1 GiB file with 4 KiB pages and a
+    64 KiB readahead window, 4 KiB pages without readahead, 64 KiB pages without
+    readahead, and 64 KiB pages with a 16 MiB window; cold per pass."""
+    import numpy as np
+
+    from oracle import data as odata
+    from paper_2109_05366_amd import gfs, runner
+    from workloads import configs
+    wl = configs.get("f3")
+    ddir = args.data_dir or os.environ.get("GFS_DATA_DIR") or configs.data_dir()
+    path = configs.ensure_file(wl.file, ddir)
+    nvme = storage_peak(path)
+    h2d = h2d_peak(torch)
+    variants = [("p4k_ra64k", 4 << 10, 64 << 10), ("p4k_none", 4 << 10, 0),
+                ("p64k_none", 64 << 10, 0), ("p64k_ra16m", 64 << 10, 16 << 20)]
+    out = {}
+    sample = [0, 1, 511, 1023]
+    want = odata.block_checksums(path, wl.offsets, wl.read_size, blocks=sample)
+    for name, page, cap in variants:
+        cfg = runner.make_config(page, wl.cache_bytes, ra_cap_bytes=cap, host_threads=args.host_threads,
+                                 rpc_slots=args.rpc_slots, timeout_s=60)
+        with gfs.PageCache(cfg) as cache:
+            fid = cache.open(path)
+            reader = runner.ListReader(wl.offsets, wl.read_size, wl.consumer, wl.threads)
+            wall, kms, st = run_steps(torch, cache, fid, reader, args.steps, args.warmup)
+            res = reader.result()
+        if st["timeouts"] or st["io_errors"] or not np.array_equal(res.out[sample], want[sample]):
+            raise RuntimeError(f"f3 {name}: device errors or parity failure {st}")
+        out[name] = {"GBps": round(args.steps * wl.delivered_bytes / wall / 1e9, 3),
+                     "kernel_ms": round(float(np.mean(kms)), 2), "requests": st["requests"],
+                     "request_bytes": st["request_bytes"], "lock_acquired": st["lock_acquired"]}
+        log(f"{name}: {out[name]}")
+    value = out["p4k_ra64k"]["GBps"]
+    line = {
+        "metric": "delivered file-read GB/s (readahead vs none) + fraction of min(NVMe, H2D) peak",
+        "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": out["p4k_ra64k"]["kernel_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "f3: 1 GiB splitmix64(seed=4) file, 256 MiB cache, 1024 blocks x 256 threads, "
+                               "128 KiB strided reads, 4 KiB pages + 64 KiB readahead (value) vs the variants",
+                   "data_dir": ddir},
+        "variants": out,
+        "readahead_speedup_4k": round(value / out["p4k_none"]["GBps"], 3),
+        "vs_64k_no_readahead": round(value / out["p64k_none"]["GBps"], 3),
+        "storage_peak_GBps": round(nvme, 3), "h2d_peak_GBps": round(h2d, 3),
+        "parity_sampled_blocks": sample,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,7 +384,7 @@ def main() -> int:
     ap.add_argument("--rpc-slots", type=int, default=64)
     ap.add_argument("--no-ra-off", action="store_true", help="skip the readahead-off comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3a", "c3b", "c3c", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3a", "c3b", "c3c", "c4", "c5", "f3"])
     ap.add_argument("--no-hit-path", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="c4: search page size, cap and blocks per file")
     ap.add_argument("--rates", default="200", help="c5: comma-separated arrival rates per second")
@@ -354,6 +406,8 @@ def main() -> int:
         return bench_batch(args, torch)
     if args.workload == "c5":
         return bench_serve(args, torch)
+    if args.workload == "f3":
+        return bench_small_pages(args, torch)
     wl = configs.get(args.workload)
     ddir = args.data_dir or os.environ.get("GFS_DATA_DIR") or configs.data_dir()
     log(f"workload {wl.name}: file {wl.file.size >> 20} MiB, cache {wl.cache_bytes >> 20} MiB, "

@@ -39,6 +39,11 @@ extern "C" {
 #define GFS_MAX_STREAMS 8u
 #define GFS_MAX_WINDOW_PAGES 1024u   /* readahead cap, in pages */
 
+/* Threads per block of the library's workload kernels. gread is inlined into its caller;
+ * at 256 threads the compiler keeps the whole miss path in registers (about 220 VGPRs, no
+ * scratch), where a 1024-thread bound would cap it at 128 and spill to scratch memory. */
+#define GFS_MAX_BLOCK_THREADS 256u
+
 /* open flags and fadvise advice */
 #define GFS_O_RDONLY 0
 #define GFS_ADV_NORMAL 0
@@ -193,7 +198,7 @@ int gfs_shutdown(gfs_ctx* ctx);
 /* ---- workload launchers (the benchmark consumers of gread; not part of the method) ----
  *
  * gfs_launch_list_reader: one kernel of `blocks` threadblocks x `threads` threads
- * (a multiple of 64, <= 1024). Block b calls gread(file, offsets[b*reads + k],
+ * (a multiple of 64, <= GFS_MAX_BLOCK_THREADS). Block b calls gread(file, offsets[b*reads + k],
  * read_size, buf + b*read_size) for k = 0..reads-1 in order and folds every delivered
  * buffer into its consumer output:
  *   consumer 0 (checksum): out is uint64[blocks]; wrapping sum of the delivered
@@ -202,7 +207,8 @@ int gfs_shutdown(gfs_ctx* ctx);
  * status (int64[blocks]) receives the total bytes delivered to the block, or the first
  * negative errno gread returned. turn, if not NULL, serialises the reads: read k of
  * block b waits until *turn == k*blocks + b and then increments it (test-only; every
- * block must be resident at once). All pointers are device pointers; the kernel is
+ * block must be resident at once: -EINVAL if `blocks` exceeds what the device holds).
+ * All pointers are device pointers; the kernel is
  * enqueued on hip_stream and the call returns without waiting. -EINVAL on bad shapes. */
 int gfs_launch_list_reader(gfs_ctx* ctx, int file_id, const uint64_t* offsets, uint32_t blocks,
                            uint32_t reads, uint64_t read_size, uint32_t threads, int consumer,
@@ -232,7 +238,7 @@ int gfs_batch_plan(const uint64_t* sizes, const uint32_t* ids, uint32_t nfiles, 
                    uint64_t* nout);
 
 /* gfs_launch_batch: one persistent kernel of `grid` blocks x `threads` threads (a multiple
- * of 64, <= 1024); blocks take units from units[0..nunits) in order through the device
+ * of 64, <= GFS_MAX_BLOCK_THREADS); blocks take units from units[0..nunits) in order through the device
  * counter *counter (reset by the call), gread each into their own buf + b*unit_bytes, and
  * fold the bytes into csum[out] (wrapping u64 sum of LE u32 words) and hist[out*256 + v]
  * (u32 byte counts) with atomics. status (int64[grid]) receives the bytes each block read
@@ -272,7 +278,7 @@ typedef struct gfs_serve_params {
   uint64_t budget_bytes;     /* cache bytes admitted requests may reserve (> 0) */
   uint64_t chunk_bytes;      /* bytes per gread, a multiple of 16, <= 64 MiB */
   uint32_t grid;             /* persistent blocks (0: as many as fit on the device) */
-  uint32_t threads;          /* threads per block, a multiple of 64, <= 1024 */
+  uint32_t threads;          /* threads per block, a multiple of 64, <= GFS_MAX_BLOCK_THREADS */
   uint64_t idle_timeout_ns;  /* the kernel gives up when the host is silent this long (0: 60 s) */
 } gfs_serve_params;
 

@@ -30,6 +30,10 @@
  * (synchronous prefetch, Sec. 4), pulls the fetched bytes from pinned staging into the
  * frames, publishes them, and copies its own page out. Blocks that find a page whose
  * frame is reserved or still being filled wait for it instead of fetching it again.
+ *
+ * Calling kernels: gread is inlined into its caller and its miss path needs about 220
+ * VGPRs; give the kernel __launch_bounds__(GFS_MAX_BLOCK_THREADS) or less, or the compiler
+ * caps registers lower and spills every call's state to scratch memory.
  */
 #ifndef GFS_DEVICE_H
 #define GFS_DEVICE_H
@@ -1233,7 +1237,8 @@ __device__ int gclose(const gfs_dev* d, int fd) {
   return 0;
 }
 
-__device__ int64_t gread(const gfs_dev* d, int fd, uint64_t offset, uint64_t size, void* dst) {
+__device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd, uint64_t offset,
+                                                        uint64_t size, void* dst) {
   using namespace gfsd;
   BlockState* bs = block_state();
   if (fd < 0 || (uint32_t)fd >= GFS_MAX_FILES) return -kEBADF;

@@ -22,7 +22,7 @@ __global__ void zero_kernel(uint64_t* p, uint64_t n8) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8; i += stride) p[i] = 0;
 }
 
-__global__ void list_reader_kernel(const gfs_dev* d, int file_id, const uint64_t* offsets,
+__global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) list_reader_kernel(const gfs_dev* d, int file_id, const uint64_t* offsets,
                                    uint32_t reads, uint64_t read_size, int consumer,
                                    uint8_t* buf, void* out, int64_t* status, uint64_t* turn) {
   __shared__ uint32_t hist[256];
@@ -92,7 +92,7 @@ __global__ void list_reader_kernel(const gfs_dev* d, int file_id, const uint64_t
 // Persistent batch reader: blocks take units in order from one device counter; a block
 // keeps its descriptor and its partial checksum/histogram while consecutive units belong
 // to the same file, and adds them into that file's output row when it moves on.
-__global__ void batch_reader_kernel(const gfs_dev* d, const gfs_unit* units, uint64_t nunits,
+__global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) batch_reader_kernel(const gfs_dev* d, const gfs_unit* units, uint64_t nunits,
                                     uint64_t* counter, uint8_t* buf, uint64_t unit_bytes,
                                     uint64_t* csum, uint32_t* hist, int64_t* status) {
   __shared__ uint32_t lhist[256];
@@ -162,7 +162,7 @@ extern "C" int gfs_launch_batch(gfs_ctx* ctx, const gfs_unit* units, uint64_t nu
                                 uint32_t threads, uint64_t unit_bytes, void* buf, uint64_t* counter,
                                 uint64_t* csum, uint32_t* hist, int64_t* status, void* hip_stream) {
   if (!ctx || !units || !buf || !counter || !csum || !hist || !status) return -EINVAL;
-  if (grid == 0 || grid > (1u << 20) || threads == 0 || threads % 64 || threads > 1024) return -EINVAL;
+  if (grid == 0 || grid > (1u << 20) || threads == 0 || threads % 64 || threads > GFS_MAX_BLOCK_THREADS) return -EINVAL;
   if (unit_bytes == 0 || unit_bytes % 16) return -EINVAL;
   if (((uintptr_t)buf | (uintptr_t)counter | (uintptr_t)csum) & 7) return -EINVAL;
   hipStream_t s = (hipStream_t)hip_stream;
@@ -174,7 +174,7 @@ extern "C" int gfs_launch_batch(gfs_ctx* ctx, const gfs_unit* units, uint64_t nu
 }
 
 extern "C" int gfs_batch_grid(uint32_t threads, uint32_t* grid) {
-  if (!grid || threads == 0 || threads % 64 || threads > 1024) return -EINVAL;
+  if (!grid || threads == 0 || threads % 64 || threads > GFS_MAX_BLOCK_THREADS) return -EINVAL;
   int dev = 0, per_cu = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -EIO;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_reader_kernel, (int)threads, 0) != hipSuccess)
@@ -200,10 +200,19 @@ extern "C" int gfs_launch_list_reader(gfs_ctx* ctx, int file_id, const uint64_t*
                                       int64_t* status, uint64_t* turn, void* hip_stream) {
   if (!ctx || !offsets || !buf || !out || !status) return -EINVAL;
   if (blocks == 0 || blocks > (1u << 20) || reads == 0) return -EINVAL;
-  if (threads == 0 || threads % 64 || threads > 1024) return -EINVAL;
+  if (threads == 0 || threads % 64 || threads > GFS_MAX_BLOCK_THREADS) return -EINVAL;
   if (read_size == 0 || read_size % 16) return -EINVAL;
   if (consumer != 0 && consumer != 1) return -EINVAL;
   if (((uintptr_t)buf | (uintptr_t)out) & 15) return -EINVAL;
+  if (turn) {
+    // the serialising gate waits on other blocks: every block must be resident at once
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, list_reader_kernel, (int)threads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return -EIO;
+    if ((uint64_t)blocks > (uint64_t)per_cu * (uint64_t)cus) return -EINVAL;
+  }
   const gfs_dev* d = gfs_device_handle(ctx);
   hipLaunchKernelGGL(list_reader_kernel, dim3(blocks), dim3(threads), 0, (hipStream_t)hip_stream, d,
                      file_id, offsets, reads, read_size, consumer, (uint8_t*)buf, out, status, turn);

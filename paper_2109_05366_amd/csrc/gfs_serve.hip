@@ -197,7 +197,7 @@ __device__ int pick_unit(SrvCtrl* ctl, SrvEntry* tab, uint32_t cap, const SrvSub
   }
 }
 
-__global__ void serve_kernel(const gfs_dev* d, SrvEntry* tab, uint32_t cap, SrvCtrl* ctl, const SrvSub* subs,
+__global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) serve_kernel(const gfs_dev* d, SrvEntry* tab, uint32_t cap, SrvCtrl* ctl, const SrvSub* subs,
                              SrvHost* host, SrvDone* done, uint8_t* buf, uint64_t chunk, uint64_t idle_ticks,
                              int64_t* status) {
   __shared__ uint64_t red[16];
@@ -297,7 +297,7 @@ extern "C" int gfs_serve_run(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32
   if (!ctx || !reqs || !p || !out || n == 0 || n > (1u << 20)) return -EINVAL;
   if (p->budget_bytes == 0 || p->chunk_bytes == 0 || p->chunk_bytes % 16 || p->chunk_bytes > (64ull << 20))
     return -EINVAL;
-  if (p->threads == 0 || p->threads % 64 || p->threads > 1024) return -EINVAL;
+  if (p->threads == 0 || p->threads % 64 || p->threads > GFS_MAX_BLOCK_THREADS) return -EINVAL;
   gfs_config cfg;
   if (gfs_get_config(ctx, &cfg)) return -EINVAL;
   std::vector<uint64_t> size(n), resv(n);

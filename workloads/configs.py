@@ -110,6 +110,16 @@ def c2() -> Workload:
                     strided_offsets(1024, 64, 128 * KiB), CONSUMER_HISTOGRAM)
 
 
+def f3() -> Workload:
+    """Small-page regime: a 1 GiB file (seed 4) through a 256 MiB cache of 4 KiB pages,
+    1024 blocks reading 128 KiB strides b + 1024 k (8 reads each), per-block checksums.
+    The page size here is the small one; the comparison runs the same reads with 64 KiB
+    pages."""
+    f = FileSpec("f3_seed4_1GiB.bin", 4, 1 * GiB)
+    return Workload("f3", f, 4 * KiB, 256 * MiB, 1024, 256, 128 * KiB,
+                    strided_offsets(1024, 8, 128 * KiB), CONSUMER_CHECKSUM)
+
+
 def _c3_file() -> FileSpec:
     return FileSpec("c3_seed3_4GiB.bin", 3, 4 * GiB)
 
@@ -167,7 +177,7 @@ REGISTRY = {
     "c3a": lambda: c3("a"), "c3b": lambda: c3("b"), "c3c": lambda: c3("c"),
     "c1_small": c1_small, "c2_small": c2_small,
     "c3a_small": lambda: c3_small("a"), "c3b_small": lambda: c3_small("b"),
-    "c3c_small": lambda: c3_small("c"),
+    "c3c_small": lambda: c3_small("c"), "f3": f3,
 }
 
 
