@@ -150,6 +150,10 @@ typedef struct gfs_stats {
   uint64_t t_unlock_ns;       /* part of t_crit: releasing the miss lock */
   uint64_t lock_acquired;     /* miss locks taken */
   uint64_t lock_left;         /* lock waits given up because another block's window covered the page */
+  /* time of every page gread serves, summed over blocks (ns) */
+  uint64_t t_acquire_ns;      /* finding and pinning it: hit, join or miss, pulls included */
+  uint64_t t_copy_ns;         /* copying it to the caller's buffer */
+  uint64_t t_unpin_ns;        /* dropping the pin */
   uint64_t host_errors;       /* host reads that returned an error */
   uint64_t host_last_errno;   /* errno of the last failed host read (0 if none) */
   uint64_t host_spins[64];    /* per host thread: polls of the ring before its first request */

@@ -276,39 +276,41 @@ __device__ bool pt_delete_lane(const gfs_dev* d, uint64_t key, uint32_t frame) {
 /* ------------------------------------------------------------------ frame words */
 enum { PIN_RETRY = 0, PIN_VALID = 1, PIN_FILLING = 2, PIN_ERROR = 3 };
 
+/* Pins are counted with fetch-and-add and fetch-and-subtract, so a pin costs one atomic
+ * round trip and dropping one costs none (the wave does not wait for it). Every other change
+ * of a frame word is a compare-and-swap against the word just read, or an addition (the
+ * allocator's CLAIMED -> FILLING step), so a pin taken and dropped at any moment is never
+ * lost: a block that pins a frame which turns out not to hold its page (or is not FILLING
+ * or VALID) just drops the pin again. The clock hand claims only frames with no pins. */
+
 /* Drop a pin. Relaxed: the caller's reads of the frame have completed (a block barrier
  * waits for them) before this is issued, and unpinning publishes nothing. */
-__device__ void frame_unpin(const gfs_dev* d, uint32_t f) {
-  uint64_t* fw = &d->fword[f];
-  uint64_t w = ld_rlx(fw);
-  while (!cas64_rlx(fw, w, w - GFS_FW_PIN_ONE + GFS_FW_VER_ONE)) {
-  }
+__device__ __forceinline__ void frame_unpin(const gfs_dev* d, uint32_t f) {
+  __hip_atomic_fetch_sub(&d->fword[f], GFS_FW_PIN_ONE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 /* Pin frame f if it is filling or valid and still holds key; sets the reference bit and
  * clears the prefetched mark (the page has now been demanded). Acquire: a valid frame's
- * bytes, published with release by the block that filled it, are visible afterwards. */
+ * bytes, published with release by the block that filled it, are visible afterwards, and
+ * the tag is read after the pin is in place (a frame cannot be claimed while pinned). */
 __device__ int frame_pin(const gfs_dev* d, uint32_t f, uint64_t key) {
   uint64_t* fw = &d->fword[f];
-  uint64_t w = ld_rlx(fw);
-  for (int i = 0; i < 64; ++i) {
-    const uint64_t st = w & GFS_FW_STATE;
-    if (st != GFS_FS_FILLING && st != GFS_FS_VALID) return PIN_RETRY;
-    if ((w & GFS_FW_PINS) == GFS_FW_PINS) return PIN_RETRY;
-    const uint64_t nw = ((w + GFS_FW_PIN_ONE + GFS_FW_VER_ONE) | GFS_FW_REF) & ~GFS_FW_RA;
-    if (cas64(fw, w, nw)) {
-      if (ld_acq(&d->ftag[f]) != key) {
-        frame_unpin(d, f);
-        return PIN_RETRY;
-      }
-      if (st == GFS_FS_VALID && (w & GFS_FW_ERR)) {
-        frame_unpin(d, f);   /* the host read of this page failed */
-        return PIN_ERROR;
-      }
-      return st == GFS_FS_VALID ? PIN_VALID : PIN_FILLING;
-    }
+  const uint64_t w = __hip_atomic_fetch_add(fw, GFS_FW_PIN_ONE, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t st = w & GFS_FW_STATE;
+  if ((st != GFS_FS_FILLING && st != GFS_FS_VALID) || ld_rlx(&d->ftag[f]) != key) {
+    frame_unpin(d, f);
+    return PIN_RETRY;
   }
-  return PIN_RETRY;
+  if (st == GFS_FS_VALID && (w & GFS_FW_ERR)) {
+    frame_unpin(d, f);   /* the host read of this page failed */
+    return PIN_ERROR;
+  }
+  /* idempotent bit updates; the wave does not wait for them */
+  if (!(w & GFS_FW_REF))
+    __hip_atomic_fetch_or(fw, GFS_FW_REF, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (w & GFS_FW_RA)
+    __hip_atomic_fetch_and(fw, ~GFS_FW_RA, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return st == GFS_FS_VALID ? PIN_VALID : PIN_FILLING;
 }
 
 /* One clock step at frame f (per lane). FREE or EVICT leave the frame CLAIMED by the
@@ -319,8 +321,9 @@ __device__ int hand_visit(const gfs_dev* d, uint32_t f, uint64_t& vkey, uint32_t
   const uint64_t tag = ld_rlx(&d->ftag[f]);   /* loaded with the word; used only on EVICT */
   const uint64_t st = w & GFS_FW_STATE;
   const uint64_t claimed = (((w >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT) | GFS_FS_CLAIMED;
+  if (w & GFS_FW_PINS) return GFS_HAND_SKIP;
   if (st == GFS_FS_FREE) return cas64(fw, w, claimed) ? GFS_HAND_FREE : GFS_HAND_SKIP;
-  if (st != GFS_FS_VALID || (w & GFS_FW_PINS)) return GFS_HAND_SKIP;
+  if (st != GFS_FS_VALID) return GFS_HAND_SKIP;
   if (w & GFS_FW_REF)
     return cas64_rlx(fw, w, (w & ~GFS_FW_REF) + GFS_FW_VER_ONE) ? GFS_HAND_CLEAR : GFS_HAND_SKIP;
   const uint64_t old = w;
@@ -612,11 +615,11 @@ __device__ uint32_t alloc_wave(const gfs_dev* d, uint32_t file, uint64_t demand,
       const uint64_t key = page_key(file, q);
       st_rlx(&d->ftag[f], key);
       st_rlx(&d->ffill[f], 0ull);   /* the request that fills it is not known yet */
-      uint64_t nw = (((ld_rlx(&d->fword[f]) >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT) |
-                    GFS_FS_FILLING;
-      if (q == demand) nw += GFS_FW_PIN_ONE;
-      else nw |= GFS_FW_RA;
-      st_rel(&d->fword[f], nw);
+      /* CLAIMED (no flags, no pins of ours) -> FILLING, version + 1, pinned for the demanded
+         page, prefetched mark otherwise; an addition keeps pins other blocks hold briefly */
+      const uint64_t delta = (GFS_FS_FILLING - GFS_FS_CLAIMED) + GFS_FW_VER_ONE +
+                             (q == demand ? GFS_FW_PIN_ONE : GFS_FW_RA);
+      __hip_atomic_fetch_add(&d->fword[f], delta, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       st_rel(d->pt + bs->lslot[k], (key << GFS_ENTRY_FRAME_BITS) | f);
       bs->lframe[k] = f;
       trace_ev(d, 1, GFS_EV_ALLOC, bid, file, (uint32_t)q, f, q == demand ? 0u : 1u, t);
@@ -636,19 +639,23 @@ __device__ uint32_t alloc_wave(const gfs_dev* d, uint32_t file, uint64_t demand,
 /* ------------------------------------------------------------------ vector copy */
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
-/* Block-cooperative copy of n bytes; both pointers 16-byte aligned. */
+/* Block-cooperative copy of n bytes; both pointers 16-byte aligned and in global memory
+ * (frames, user buffers). Global rather than generic accesses let loads and stores be
+ * waited on separately, so eight 16-byte loads per lane are in flight per round. */
+typedef __attribute__((address_space(1))) v4u gv4u;
+
 __device__ __forceinline__ void copy_block_aligned(uint8_t* dst, const uint8_t* src, uint64_t n,
                                                    uint32_t tid, uint32_t nt) {
   const uint64_t n16 = n >> 4;
-  const v4u* s = (const v4u*)src;
-  v4u* o = (v4u*)dst;
+  const gv4u* s = (const gv4u*)src;
+  gv4u* o = (gv4u*)dst;
   uint64_t i = tid;
-  for (; i + 3ull * nt < n16; i += 4ull * nt) {
-    const v4u a = s[i], b = s[i + nt], c = s[i + 2ull * nt], e = s[i + 3ull * nt];
-    o[i] = a;
-    o[i + nt] = b;
-    o[i + 2ull * nt] = c;
-    o[i + 3ull * nt] = e;
+  for (; i + 7ull * nt < n16; i += 8ull * nt) {
+    v4u a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = s[i + (uint64_t)k * nt];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[i + (uint64_t)k * nt] = a[k];
   }
   for (; i < n16; i += nt) o[i] = s[i];
   for (uint64_t j = (n16 << 4) + tid; j < n; j += nt) dst[j] = src[j];
@@ -1255,6 +1262,7 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
   const uint32_t sh_bits = d->page_shift;
   int64_t err = 0;
   for (uint64_t p = offset >> sh_bits; p <= (end - 1) >> sh_bits; ++p) {
+    const uint64_t ta0 = wall_clock64();
     if (tid < 64) acquire_page_wave(d, (uint32_t)fd, p, fsize, bs, bid);
     __syncthreads();
     if (bs->pull) {
@@ -1284,13 +1292,20 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
       __syncthreads();
       break;
     }
+    const uint64_t ta1 = wall_clock64();
     const uint64_t pbase = p << sh_bits;
     const uint64_t lo = offset > pbase ? offset : pbase;
     const uint64_t hi = end < pbase + P ? end : pbase + P;
     copy_block((uint8_t*)dst + (lo - offset), d->frames + (uint64_t)f * P + (lo - pbase), hi - lo,
                tid, nt);
     __syncthreads();
-    if (tid == 0) frame_unpin(d, (uint32_t)f);
+    if (tid == 0) {
+      const uint64_t ta2 = wall_clock64();
+      frame_unpin(d, (uint32_t)f);
+      bcount(bs, GFS_T_ACQUIRE, ta1 - ta0);
+      bcount(bs, GFS_T_COPY, ta2 - ta1);
+      bcount(bs, GFS_T_UNPIN, wall_clock64() - ta2);
+    }
   }
   if (err) return err;
   if (tid == 0) bcount(bs, GFS_C_DELIVERED, end - offset);

@@ -68,6 +68,9 @@ enum {
   GFS_T_DECIDE, GFS_T_RUN, GFS_T_UNLOCK,
   GFS_C_LOCKS,       /* miss locks taken */
   GFS_C_LOCK_LEFT,   /* waits for a miss lock given up because the page appeared */
+  /* every page gread serves, summed over blocks: finding and pinning it (hit, join or
+     miss, including pulls), copying it out, dropping the pin */
+  GFS_T_ACQUIRE, GFS_T_COPY, GFS_T_UNPIN,
   GFS_C_COUNT
 };
 

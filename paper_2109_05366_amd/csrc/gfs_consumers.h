@@ -16,8 +16,16 @@ __device__ __forceinline__ uint64_t checksum_part(const uint8_t* buf, uint64_t n
                                                   uint32_t nt) {
   uint64_t s = 0;
   const uint64_t n16 = n >> 4;
-  const gfsd::v4u* v = (const gfsd::v4u*)buf;
-  for (uint64_t i = tid; i < n16; i += nt) {
+  const gfsd::gv4u* v = (const gfsd::gv4u*)buf;   /* user buffers are global memory */
+  uint64_t i = tid;
+  for (; i + 3ull * nt < n16; i += 4ull * nt) {
+    gfsd::v4u x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = v[i + (uint64_t)k * nt];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s += (uint64_t)x[k].x + x[k].y + x[k].z + x[k].w;
+  }
+  for (; i < n16; i += nt) {
     const gfsd::v4u x = v[i];
     s += (uint64_t)x.x + x.y + x.z + x.w;
   }
@@ -35,7 +43,7 @@ __device__ __forceinline__ uint64_t checksum_part(const uint8_t* buf, uint64_t n
 __device__ __forceinline__ void histogram_part(const uint8_t* buf, uint64_t n, uint32_t tid,
                                                uint32_t nt, uint32_t* hist) {
   const uint64_t n16 = n >> 4;
-  const gfsd::v4u* v = (const gfsd::v4u*)buf;
+  const gfsd::gv4u* v = (const gfsd::gv4u*)buf;
   for (uint64_t i = tid; i < n16; i += nt) {
     const gfsd::v4u x = v[i];
     const uint32_t w[4] = {x.x, x.y, x.z, x.w};

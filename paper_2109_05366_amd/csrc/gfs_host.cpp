@@ -608,6 +608,9 @@ int gfs_stats_read(gfs_ctx* c, gfs_stats* out) {
   s.t_unlock_ns = (uint64_t)(g.ctr[GFS_T_UNLOCK] * ns_per_tick);
   s.lock_acquired = g.ctr[GFS_C_LOCKS];
   s.lock_left = g.ctr[GFS_C_LOCK_LEFT];
+  s.t_acquire_ns = (uint64_t)(g.ctr[GFS_T_ACQUIRE] * ns_per_tick);
+  s.t_copy_ns = (uint64_t)(g.ctr[GFS_T_COPY] * ns_per_tick);
+  s.t_unpin_ns = (uint64_t)(g.ctr[GFS_T_UNPIN] * ns_per_tick);
   s.host_errors = c->host_errors.load();
   s.host_last_errno = (uint64_t)c->host_last_errno.load();
   for (uint32_t i = 0; i < 64; ++i) s.host_spins[i] = c->spins[i].load();

@@ -41,7 +41,8 @@ _STAT_U64 = ["hits", "joins", "misses", "ra_pages", "fetched_pages", "evictions"
              "hand_visits", "requests", "request_bytes", "delivered_bytes", "retries", "noframe",
              "timeouts", "io_errors", "trace_events", "host_requests", "host_bytes", "host_read_ns",
              "t_lock_ns", "t_crit_ns", "t_alloc_ns", "t_slot_ns", "t_host_ns", "t_pull_ns", "t_join_ns",
-             "t_decide_ns", "t_run_ns", "t_unlock_ns", "lock_acquired", "lock_left",
+             "t_decide_ns", "t_run_ns", "t_unlock_ns", "lock_acquired", "lock_left", "t_acquire_ns", "t_copy_ns",
+             "t_unpin_ns",
              "host_errors", "host_last_errno"]
 
 
