@@ -146,7 +146,7 @@ typedef struct gfs_stats {
   uint64_t t_pull_ns;         /* pulling staging into frames and publishing them */
   uint64_t t_join_ns;         /* waiting on frames other blocks are filling */
   uint64_t t_decide_ns;       /* part of t_crit: the readahead decision */
-  uint64_t t_run_ns;          /* part of t_crit: finding and reserving the run */
+  uint64_t t_run_ns;          /* finding and reserving the run (after the unlock, under a claim) */
   uint64_t t_unlock_ns;       /* part of t_crit: releasing the miss lock */
   uint64_t lock_acquired;     /* miss locks taken */
   uint64_t lock_left;         /* lock waits given up because another block's window covered the page */

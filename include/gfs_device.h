@@ -474,31 +474,46 @@ __device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticke
  * chunk around p; else the history of cached pages right behind p sizes it (context
  * readahead); with neither, it opens with the initial window at offset 0 or under
  * SEQUENTIAL advice, else with one page. */
-__device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint64_t& ws,
+/* Per lane: the file's detector state, loaded together (lane i: recent miss i, stream
+   slot i); the decision below uses it after the caller's acquire fence. */
+struct RaState {
+  uint32_t advice, clk, rn;
+  uint64_t r, s_next;
+  uint32_t s_size, s_last, s_valid;
+};
+__device__ __forceinline__ RaState ra_load_lane(const gfs_dev* d, uint32_t file) {
+  gfs_file_dev* fe = &d->files[file];
+  const uint32_t l = lane();
+  RaState st{};
+  st.advice = ld_rlx32(&fe->advice);
+  if (l == 0) st.clk = ld_rlx32(&fe->clock);
+  st.rn = ld_rlx32(&fe->recent_n);
+  if (l < GFS_RECENT_MISSES) st.r = ld_rlx(&fe->recent[l]);
+  if (l < d->streams) {
+    gfs_stream* sp = &fe->streams[l];
+    st.s_next = ld_rlx(&sp->next);
+    st.s_size = ld_rlx32(&sp->size);
+    st.s_last = ld_rlx32(&sp->last_use);
+    st.s_valid = ld_rlx32(&sp->valid);
+  }
+  return st;
+}
+
+__device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, const RaState& st, uint64_t& ws,
                                uint32_t& wn, uint32_t& near_out) {
   gfs_file_dev* fe = &d->files[file];
-  const uint32_t advice = ld_rlx32(&fe->advice);
+  const uint32_t advice = st.advice;
   ws = p;
   wn = 1;
   near_out = 0;
   if (d->ra_cap == 0 || advice == GFS_ADV_RANDOM) return;
   const uint32_t l = lane();
   const uint32_t cap = d->ra_cap;
-  /* every load the decision needs, issued together */
-  uint32_t clk = 0;
-  if (l == 0) clk = ld_rlx32(&fe->clock);
-  const uint32_t rn = ld_rlx32(&fe->recent_n);
-  uint64_t r = 0;
-  if (l < GFS_RECENT_MISSES) r = ld_rlx(&fe->recent[l]);
-  uint64_t s_next = 0;
-  uint32_t s_size = 0, s_last = 0, s_valid = 0;
-  if (l < d->streams) {
-    gfs_stream* s = &fe->streams[l];
-    s_next = ld_rlx(&s->next);
-    s_size = ld_rlx32(&s->size);
-    s_last = ld_rlx32(&s->last_use);
-    s_valid = ld_rlx32(&s->valid);
-  }
+  uint32_t clk = st.clk;
+  const uint32_t rn = st.rn;
+  const uint64_t r = st.r;
+  const uint64_t s_next = st.s_next;
+  const uint32_t s_size = st.s_size, s_last = st.s_last, s_valid = st.s_valid;
   clk = __shfl(clk, 0, 64) + 1;
   /* how many of the file's last misses lie near p; then remember p */
   const uint64_t radius = GFS_NEAR_PAGES;
@@ -841,32 +856,74 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       if (l == 0) bcount(bs, GFS_C_LOCKS, 1);
       /* every block waiting on this file's lock waits for this wave: let it issue first */
       __builtin_amdgcn_s_setprio(3);
-      if (pt_lookup_wave(d, key) >= 0) {
-        unlock_file_wave(d, file, ticket);   /* filled or reserved meanwhile: go to the pin path */
+      /* one round: the detector state and the file's window claims; then, ordered after the
+         claims, the table probe (a claim cleared after its reservations means they show) */
+      const RaState ras = ra_load_lane(d, file);
+      uint64_t cl = 0;
+      if (l < GFS_CLAIMS) cl = ld_rlx(&d->claims[file].e[l]);
+      const uint64_t npages = d->files[file].npages;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const bool cl_on = l < GFS_CLAIMS && (cl & 1ull);
+      const uint64_t cl_lo = cl >> 32, cl_hi = (cl >> 32) + ((cl & 0xffffffffull) >> 1);
+      const bool covered = __ballot(cl_on && cl_lo <= p && p < cl_hi) != 0;
+      const uint64_t free_cl = __ballot(l < GFS_CLAIMS && !cl_on);
+      const bool present = pt_lookup_wave(d, key) >= 0;
+      if (present || covered || free_cl == 0) {
+        /* filled, reserved, or about to be reserved by a window being claimed: go to the pin
+           path (after a nap if the claim is still running) */
+        unlock_file_wave(d, file, ticket);
         __builtin_amdgcn_s_setprio(0);
         if (l == 0) bcount(bs, GFS_T_CRIT, wall_clock64() - tl1);
+        if (!present) {
+          if (expired(d, t0)) break;
+          if (l == 0) nap(naps);
+        }
         continue;
       }
-      /* miss: decide the window, reserve the run of unmapped pages around p, unlock */
+      /* miss: decide the window, clip it to stay out of running claims, claim it, unlock */
       uint64_t ws;
       uint32_t wn, near;
       const uint64_t td0 = wall_clock64();
-      ra_decide_wave(d, file, p, ws, wn, near);
+      ra_decide_wave(d, file, p, ras, ws, wn, near);
       const uint64_t td1 = wall_clock64();
       if (l == 0) bcount(bs, GFS_T_DECIDE, td1 - td0);
-      const uint64_t npages = d->files[file].npages;
       if (ws + wn > npages) wn = (uint32_t)(npages - ws);
       if (l == 0) trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, near, wn, ws);
+      uint64_t cws = ws, cwe = ws + wn;
+      {
+        uint64_t lo_b = cl_on && cl_hi <= p ? cl_hi : 0;
+        uint64_t hi_b = cl_on && cl_lo > p ? cl_lo : ~0ull;
+        for (int off = 32; off > 0; off >>= 1) {
+          const uint64_t a = __shfl_xor(lo_b, off, 64), b = __shfl_xor(hi_b, off, 64);
+          lo_b = a > lo_b ? a : lo_b;
+          hi_b = b < hi_b ? b : hi_b;
+        }
+        cws = cws > lo_b ? cws : lo_b;
+        cwe = cwe < hi_b ? cwe : hi_b;
+      }
+      const uint32_t cj = (uint32_t)__builtin_ctzll(free_cl);
+      uint64_t* claim = &d->claims[file].e[cj];
+      if (l == 0) st_rlx(claim, (cws << 32) | ((cwe - cws) << 1) | 1ull);
+      const uint64_t tu0 = wall_clock64();
+      unlock_file_wave(d, file, ticket);
+      __builtin_amdgcn_s_setprio(0);
+      const uint64_t tl2 = wall_clock64();
+      if (l == 0) {
+        bcount(bs, GFS_T_CRIT, tl2 - tl1);
+        bcount(bs, GFS_T_UNLOCK, tl2 - tu0);
+      }
+      /* reserve the run of unmapped pages around p inside the claimed window */
+      const uint32_t cwn = (uint32_t)(cwe - cws);
       uint32_t n = 0, failed = 0;
-      if (wn <= 64) {
-        /* one round: lane i loads the buckets of window page ws + i, the run around p is
+      if (cwn <= 64) {
+        /* one round: lane i loads the buckets of window page cws + i, the run around p is
            read off the ballot of present pages, and each run lane reserves its page from
            the buckets it already holds */
-        n = reserve_run_small_wave(d, file, p, ws, wn, bs, failed);
+        n = reserve_run_small_wave(d, file, p, cws, cwn, bs, failed);
       } else {
         uint64_t a = p;
-        for (uint64_t base = p; base > ws;) {
-          const bool valid = (uint64_t)l < base - ws;
+        for (uint64_t base = p; base > cws;) {
+          const bool valid = (uint64_t)l < base - cws;
           bool stop = !valid;
           if (valid) stop = pt_present_lane(d, page_key(file, base - 1 - l));
           const uint64_t sm = __ballot(stop);
@@ -876,8 +933,8 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
           base -= 64;
         }
         uint64_t b = p;
-        for (uint64_t base = p + 1; base < ws + wn;) {
-          const bool valid = (uint64_t)l < ws + wn - base;
+        for (uint64_t base = p + 1; base < cwe;) {
+          const bool valid = (uint64_t)l < cwe - base;
           bool stop = !valid;
           if (valid) stop = pt_present_lane(d, page_key(file, base + l));
           const uint64_t sm = __ballot(stop);
@@ -901,16 +958,12 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
         }
       }
       failed = (uint32_t)(__ballot(failed != 0) != 0);
-      const uint64_t tu0 = wall_clock64();
-      unlock_file_wave(d, file, ticket);
-      __builtin_amdgcn_s_setprio(0);
+      /* the reservations are in the table: release the claim */
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (l == 0) st_rlx(claim, 0ull);
       wave_sync_lds();
-      const uint64_t tl2 = wall_clock64();
-      if (l == 0) {
-        bcount(bs, GFS_T_CRIT, tl2 - tl1);
-        bcount(bs, GFS_T_RUN, tu0 - td1);
-        bcount(bs, GFS_T_UNLOCK, tl2 - tu0);
-      }
+      const uint64_t tl3 = wall_clock64();
+      if (l == 0) bcount(bs, GFS_T_RUN, tl3 - tl2);
       /* a reservation can fail only if both buckets are full: keep the prefix before the
          first failure (the demanded page comes first) and drop the rest */
       uint32_t keep = n;
@@ -925,7 +978,7 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
         keep = firstbad;
       }
       const uint32_t got = keep ? alloc_wave(d, file, p, bs, keep, bid) : 0;
-      if (l == 0) bcount(bs, GFS_T_ALLOC, wall_clock64() - tl2);
+      if (l == 0) bcount(bs, GFS_T_ALLOC, wall_clock64() - tl3);
       /* release reservations that got no frame (the table was full or no frame was free) */
       for (uint32_t i = got + l; i < n; i += 64) {
         if (bs->lslot[i] != 0xffffffffu)

@@ -10,6 +10,7 @@
  *   files[GFS_MAX_FILES]             768 B each
  *   locks[GFS_MAX_FILES]             128 B each (miss ticket locks)
  *   lockq[GFS_MAX_FILES][GFS_LOCK_SLOTS] u32   queue slots of the miss locks
+ *   claims[GFS_MAX_FILES]            128 B each (windows being reserved)
  *   names[GFS_MAX_FILES]             GFS_NAME_MAX B each (registered paths)
  *   fword[nframes]  u64              frame word (state, pins, ref, ra, version)
  *   ftag[nframes]   u64              key of the page held (valid while not FREE)
@@ -64,7 +65,8 @@ enum {
   GFS_C_NOFRAME, GFS_C_TIMEOUTS, GFS_C_IOERR,
   /* wall-clock ticks summed over blocks, by phase of the miss path */
   GFS_T_LOCK, GFS_T_CRIT, GFS_T_ALLOC, GFS_T_SLOT, GFS_T_HOST, GFS_T_PULL, GFS_T_JOIN,
-  /* parts of GFS_T_CRIT: readahead decision, run finding + reservation, unlock */
+  /* readahead decision and unlock (parts of GFS_T_CRIT); run finding + reservation
+     (after the unlock, under a window claim) */
   GFS_T_DECIDE, GFS_T_RUN, GFS_T_UNLOCK,
   GFS_C_LOCKS,       /* miss locks taken */
   GFS_C_LOCK_LEFT,   /* waits for a miss lock given up because the page appeared */
@@ -110,6 +112,15 @@ typedef struct gfs_file_lock {
 /* queue slots of each file's miss lock (u32 each); at least the number of blocks the
    device can hold at once (256 CUs x 32 waves) */
 #define GFS_LOCK_SLOTS 8192u
+
+/* window claims: a block that decided a window under the miss lock records it here and
+   reserves the window's pages after unlocking; other misses inside an active claim wait for
+   it, and later windows are clipped to stay out of it. Entry = start << 32 | len << 1 | 1
+   (0 = free). */
+#define GFS_CLAIMS 16
+typedef struct gfs_file_claims {
+  uint64_t e[GFS_CLAIMS];
+} gfs_file_claims;        /* 128 B */
 
 #define GFS_NAME_MAX 256     /* registered path, NUL-terminated, for gopen(path) */
 
@@ -163,6 +174,7 @@ typedef struct gfs_dev {
   gfs_file_dev* files;
   gfs_file_lock* locks;
   uint32_t* lockq;              /* [GFS_MAX_FILES][GFS_LOCK_SLOTS] miss-lock queue slots */
+  gfs_file_claims* claims;      /* [GFS_MAX_FILES] windows being reserved */
   uint64_t* slot_free;
   uint64_t* ffill;
   gfs_req_dev* reqd;
@@ -171,7 +183,7 @@ typedef struct gfs_dev {
   char* names;                  /* [GFS_MAX_FILES][GFS_NAME_MAX] registered paths */
   gfs_rpc_slot* ring;           /* device-visible address of the pinned ring */
   uint8_t* staging;             /* device-visible address of the pinned staging */
-  uint64_t pad[3];
+  uint64_t pad[2];
 } gfs_dev;
 
 #endif /* GFS_LAYOUT_H */

@@ -53,7 +53,7 @@ uint32_t log2u(uint64_t v) {
 struct Layout {
   uint64_t nframes = 0, nbuckets = 0, ra_init = 0, ra_cap = 0, max_req_pages = 0;
   uint64_t max_req_bytes = 0;
-  uint64_t off_globals = 0, off_dev = 0, off_files = 0, off_locks = 0, off_lockq = 0, off_names = 0, off_fword = 0,
+  uint64_t off_globals = 0, off_dev = 0, off_files = 0, off_locks = 0, off_lockq = 0, off_claims = 0, off_names = 0, off_fword = 0,
            off_ftag = 0, off_pt = 0, off_ffill = 0, off_slot_free = 0, off_reqd = 0, off_trace = 0,
            meta_bytes = 0;
 };
@@ -88,6 +88,7 @@ int make_layout(const gfs_config* c, Layout* L) {
   L->off_files = o; o = align_up(o + sizeof(gfs_file_dev) * GFS_MAX_FILES, kAlign);
   L->off_locks = o; o = align_up(o + sizeof(gfs_file_lock) * GFS_MAX_FILES, kAlign);
   L->off_lockq = o; o = align_up(o + 4ull * GFS_LOCK_SLOTS * GFS_MAX_FILES, kAlign);
+  L->off_claims = o; o = align_up(o + sizeof(gfs_file_claims) * GFS_MAX_FILES, kAlign);
   L->off_names = o; o = align_up(o + (uint64_t)GFS_NAME_MAX * GFS_MAX_FILES, kAlign);
   L->off_fword = o; o = align_up(o + 8 * L->nframes, kAlign);
   L->off_ftag = o; o = align_up(o + 8 * L->nframes, kAlign);
@@ -325,7 +326,7 @@ int download_file_record(gfs_ctx* c, int id, gfs_file_dev* rec) {
 int zero_dynamic(gfs_ctx* c) {
   const Layout& L = c->L;
   int rc = gfs_internal_zero(c->meta + L.off_globals, sizeof(gfs_globals), c->stream);
-  // miss locks and their queue slots
+  // miss locks, their queue slots, window claims
   if (!rc) rc = gfs_internal_zero(c->meta + L.off_locks, L.off_names - L.off_locks, c->stream);
   if (!rc) rc = gfs_internal_zero(c->meta + L.off_fword, L.off_trace - L.off_fword, c->stream);
   if (!rc && c->cfg.trace_capacity)
@@ -441,6 +442,7 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   h.files = (gfs_file_dev*)(c->meta + L.off_files);
   h.locks = (gfs_file_lock*)(c->meta + L.off_locks);
   h.lockq = (uint32_t*)(c->meta + L.off_lockq);
+  h.claims = (gfs_file_claims*)(c->meta + L.off_claims);
   h.names = (char*)(c->meta + L.off_names);
   h.fword = (uint64_t*)(c->meta + L.off_fword);
   h.ftag = (uint64_t*)(c->meta + L.off_ftag);
