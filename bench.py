@@ -214,7 +214,9 @@ def bench_batch(args, torch) -> int:
     log(f"storage peak {nvme:.2f} GB/s, H2D peak {h2d:.2f} GB/s")
     bb = autotune.BatchBench(paths, sizes, m["cache_bytes"], host_threads=args.host_threads,
                              rpc_slots=args.rpc_slots)
-    best = (256 << 10, args.ra_cap_mib << 20, 4)
+    # the autotuner's pick on the box's disk (coordinate descent over 17 cold passes):
+    # 64 KiB pages, 1 MiB windows, 8 blocks per file
+    best = (64 << 10, 1 << 20, 8)
     history = []
     if args.autotune:
         r = autotune.coordinate_descent(bb.measure, start=best, max_passes=2)
@@ -377,7 +379,7 @@ def bench_small_pages(args, torch) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--data-dir", default=None, help="where the synthetic files live")
     ap.add_argument("--ra-cap-mib", type=int, default=16)
@@ -389,6 +391,8 @@ def main() -> int:
     ap.add_argument("--no-hit-path", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="c4: search page size, cap and blocks per file")
     ap.add_argument("--rates", default="200", help="c5: comma-separated arrival rates per second")
+    ap.add_argument("--advice", default="normal", choices=["normal", "random", "sequential"],
+                    help="fadvise-style hint for the file of c2/c3 (random switches readahead off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -433,6 +437,8 @@ def main() -> int:
                                  host_threads=args.host_threads, rpc_slots=args.rpc_slots, timeout_s=60)
         with gfs.PageCache(cfg) as cache:
             fid = cache.open(path)
+            if args.advice != "normal":
+                cache.fadvise(fid, {"random": gfs.GFS_ADV_RANDOM, "sequential": gfs.GFS_ADV_SEQUENTIAL}[args.advice])
             reader = runner.ListReader(wl.offsets, wl.read_size, wl.consumer, wl.threads)
             log(f"{label}: cap {cap_mib} MiB")
             wall, kms, st = run_steps(torch, cache, fid, reader, args.steps, args.warmup)
@@ -441,8 +447,10 @@ def main() -> int:
             raise RuntimeError(f"{label}: device errors {st}")
         if not np.array_equal(res.status, np.full(wl.blocks, delivered // wl.blocks)):
             raise RuntimeError(f"{label}: wrong delivered byte counts")
+        per_step = [delivered / (k * 1e-3) / 1e9 for k in kms]
         results[label] = {"wall_s": wall, "GBps": args.steps * delivered / wall / 1e9,
                           "kernel_GBps": delivered / (np.mean(kms) * 1e-3) / 1e9,
+                          "step_min_GBps": min(per_step), "step_max_GBps": max(per_step),
                           "out": res.out}
         stats[label] = {k: st[k] for k in ("hits", "joins", "misses", "ra_pages", "fetched_pages",
                                            "evictions", "wasted_pages", "requests", "request_bytes",
@@ -520,7 +528,7 @@ def main() -> int:
                                f"{wl.cache_bytes >> 30} GiB cache, {wl.page_size >> 10} KiB pages, "
                                f"{wl.blocks} blocks x {wl.threads} threads, {wl.read_size >> 10} KiB reads, "
                                f"cold per step",
-                   "ra_cap_MiB": args.ra_cap_mib, "host_threads": args.host_threads,
+                   "ra_cap_MiB": args.ra_cap_mib, "advice": args.advice, "host_threads": args.host_threads,
                    "rpc_slots": args.rpc_slots, "data_dir": ddir},
         "readahead_off_GBps": round(results["no_ra"]["GBps"], 3) if "no_ra" in results else None,
         "readahead_speedup": round(value / results["no_ra"]["GBps"], 3) if "no_ra" in results else None,
@@ -537,6 +545,8 @@ def main() -> int:
                      "bytes_per_launch": 3 * delivered},
         "hit_path": hit,
         "kernel_GBps": {k: round(v["kernel_GBps"], 3) for k, v in results.items()},
+        "step_min_max_GBps": {k: [round(v["step_min_GBps"], 3), round(v["step_max_GBps"], 3)]
+                              for k, v in results.items()},
         "stats": stats,
         "parity_sampled_blocks": sample,
         "cpu_baseline": cpu,
