@@ -53,6 +53,12 @@ extern "C" {
 /* host read backends */
 #define GFS_IO_PREAD 0
 
+/* cache policies */
+#define GFS_POLICY_SHARED 0    /* readahead windows into the shared page cache, global clock */
+#define GFS_POLICY_PRIVATE 1   /* the paper's design (Sec. 4.1, Sec. 5.1): every threadblock
+                                  prefetches into a private buffer and replaces pages in its own
+                                  least-recently-allocated share of the frames */
+
 /* o_direct modes */
 #define GFS_DIRECT_OFF 0      /* buffered reads */
 #define GFS_DIRECT_ON 1       /* O_DIRECT; gfs_open fails if the file system refuses it */
@@ -72,17 +78,30 @@ typedef struct gfs_config {
   uint32_t trace_level;          /* 0 off, 1 policy events, 2 also hits/joins */
   uint32_t trace_capacity;       /* events kept in the device trace ring (32 B each) */
   uint64_t wait_timeout_ns;      /* device waits give up with -ETIMEDOUT after this long; 0 = 10 s */
+  uint32_t policy;               /* GFS_POLICY_* */
+  uint32_t private_slots;        /* GFS_POLICY_PRIVATE: per-block slots (private buffer + frame
+                                    share), at least the blocks resident at once; 1..65536 */
 } gfs_config;
 
 /* Fill *cfg with defaults: 64 KiB pages, 256 MiB cache, readahead 4 pages growing to
- * 16 MiB, 8 streams per file, 8 host threads, 64 slots, O_DIRECT preferred, trace off. */
+ * 16 MiB, 8 streams per file, 8 host threads, 64 slots, O_DIRECT preferred, trace off,
+ * shared policy (512 private slots if the private policy is chosen).
+ *
+ * GFS_POLICY_PRIVATE: a miss that the block's private buffer cannot serve asks the host for
+ * the page plus ra_cap_bytes that follow it (PREFETCH_SIZE, static); the page goes into the
+ * cache, the rest into the block's private buffer; a later miss of the same block on a page
+ * held there is filled from it without a host request. Frames are split evenly among
+ * private_slots; a block (one slot, taken at gopen, given back at gclose) reuses its own
+ * frames in allocation order. The frames allocation then also holds the private buffers:
+ * private_slots * ra_cap_bytes more bytes (gfs_device_bytes reports the total). */
 void gfs_config_default(gfs_config* cfg);
 
 typedef struct gfs_ctx gfs_ctx;
 struct gfs_dev;
 
 /* Device memory the caller must provide for a configuration: the frame pool
- * (cache_bytes, 256-byte aligned) and the metadata region (page table, frame words,
+ * (cache_bytes, plus the private buffers under GFS_POLICY_PRIVATE; 256-byte aligned) and
+ * the metadata region (page table, frame words,
  * tags, per-file state, counters, trace ring). -EINVAL if the configuration is invalid. */
 int gfs_device_bytes(const gfs_config* cfg, size_t* frames_bytes, size_t* meta_bytes);
 
@@ -154,6 +173,9 @@ typedef struct gfs_stats {
   uint64_t t_acquire_ns;      /* finding and pinning it: hit, join or miss, pulls included */
   uint64_t t_copy_ns;         /* copying it to the caller's buffer */
   uint64_t t_unpin_ns;        /* dropping the pin */
+  /* GFS_POLICY_PRIVATE */
+  uint64_t private_hits;      /* misses filled from the block's private buffer */
+  uint64_t private_wasted;    /* private-buffer pages dropped without being used */
   uint64_t host_errors;       /* host reads that returned an error */
   uint64_t host_last_errno;   /* errno of the last failed host read (0 if none) */
   uint64_t host_spins[64];    /* per host thread: polls of the ring before its first request */
@@ -183,7 +205,8 @@ enum {
   GFS_EV_HAND = 4,   /* frame; b = ticket; a = action | ra<<8; file,page = victim (EVICT) */
   GFS_EV_ALLOC = 5,  /* file,page,frame; a = ra (1 if prefetched), b = hand ticket */
   GFS_EV_REQ = 6,    /* file, page = first page, a = pages in span, b = ring ticket */
-  GFS_EV_NOFRAME = 7 /* file,page: window cut short, no frame left              */
+  GFS_EV_NOFRAME = 7, /* file,page: window cut short, no frame left             */
+  GFS_EV_PBHIT = 8    /* private policy: file,page,frame filled from the private buffer */
 };
 enum { GFS_HAND_FREE = 0, GFS_HAND_SKIP = 1, GFS_HAND_CLEAR = 2, GFS_HAND_EVICT = 3 };
 

@@ -60,7 +60,9 @@ struct BlockState {
   uint64_t first_page;      /* first page of the request span */
   uint64_t gen;             /* ring generation of the request */
   int32_t frame;            /* pinned frame of the current page */
-  int32_t pull;             /* 1: pull this block's own request; 2: help pull one frame */
+  int32_t pull;             /* 1: pull this block's own request; 2: help pull one frame;
+                               3: fill the frame from the private buffer; 4: pull a private-policy
+                               request (page into the frame, the rest into the private buffer) */
   uint32_t slot;            /* ring slot of the request */
   uint32_t list_n;          /* pages in list[] that got frames (a prefix) */
   uint32_t file;
@@ -72,6 +74,7 @@ struct BlockState {
                                    after allocation, the indices of the frames this block pulls */
   uint32_t nclaim;              /* entries of lslot[] claimed for pulling */
   uint32_t help_page;           /* page of the frame a helping block pulls */
+  int32_t pslot;                /* private policy: the block's slot (-1: none) */
 };
 
 __device__ __forceinline__ BlockState* block_state() {
@@ -798,6 +801,183 @@ __device__ uint32_t reserve_run_small_wave(const gfs_dev* d, uint32_t file, uint
   return n;
 }
 
+/* ------------------------------------------------------------------ private policy
+ * The paper's design (Sec. 4.1 and Sec. 5.1). A miss takes the file's lock only to reserve
+ * the one page in the table; the frame comes from the block's own share of the frames,
+ * least recently allocated first (a frame another block has pinned is passed over); the
+ * bytes come from the block's private buffer if it holds the page, else from a host read of
+ * the page plus the static prefetch size, whose tail becomes the new private buffer. */
+
+/* Lane: claim frame f of the block's share: FREE, or VALID with no pins (its page is
+   evicted; the reference bit plays no part). CLAIMED on success. */
+__device__ int lra_visit(const gfs_dev* d, uint32_t f, uint64_t& vkey, uint32_t& vra) {
+  uint64_t* fw = &d->fword[f];
+  uint64_t w = ld_rlx(fw);
+  const uint64_t tag = ld_rlx(&d->ftag[f]);
+  const uint64_t st = w & GFS_FW_STATE;
+  const uint64_t claimed = (((w >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT) | GFS_FS_CLAIMED;
+  if (w & GFS_FW_PINS) return GFS_HAND_SKIP;
+  if (st == GFS_FS_FREE) return cas64(fw, w, claimed) ? GFS_HAND_FREE : GFS_HAND_SKIP;
+  if (st != GFS_FS_VALID) return GFS_HAND_SKIP;
+  const uint64_t old = w;
+  if (!cas64(fw, w, claimed)) return GFS_HAND_SKIP;
+  vkey = tag;
+  vra = (old & GFS_FW_RA) ? 1u : 0u;
+  return GFS_HAND_EVICT;
+}
+
+/* Wave 0: the miss path of the private policy. 0: done (bs filled in), 1: look again,
+   2: timed out. */
+__device__ int miss_private_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint64_t key, uint64_t fsize,
+                                 BlockState* bs, uint32_t bid, uint64_t t0, uint32_t& naps) {
+  const uint32_t l = lane();
+  const uint64_t tl0 = wall_clock64();
+  uint64_t ticket;
+  const int lk = lock_file_wave(d, file, key, t0, ticket);
+  const uint64_t tl1 = wall_clock64();
+  if (l == 0) bcount(bs, GFS_T_LOCK, tl1 - tl0);
+  if (lk == LOCK_TIMEOUT) return 2;
+  if (lk == LOCK_LEFT) {
+    if (l == 0) bcount(bs, GFS_C_LOCK_LEFT, 1);
+    return 1;
+  }
+  if (l == 0) bcount(bs, GFS_C_LOCKS, 1);
+  __builtin_amdgcn_s_setprio(3);
+  const bool present = pt_lookup_wave(d, key) >= 0;
+  int64_t slot = -1;
+  if (!present && l == 0) slot = pt_reserve_lane(d, key);
+  slot = __shfl(slot, 0, 64);
+  unlock_file_wave(d, file, ticket);
+  __builtin_amdgcn_s_setprio(0);
+  if (l == 0) bcount(bs, GFS_T_CRIT, wall_clock64() - tl1);
+  if (present) return 1;
+  if (slot < 0) {
+    if (l == 0) {
+      bs->status = -kENOSPC;
+      bs->pull = 0;
+      bs->frame = -1;
+    }
+    return 0;
+  }
+  int status = 0;
+  if (l == 0) {
+    gfs_pslot* ps = &d->pslots[bs->pslot];
+    const uint64_t npages = d->files[file].npages;
+    const uint32_t cap = d->ra_cap;
+    const uint32_t span = (uint32_t)((npages - p) < (uint64_t)(1 + cap) ? (npages - p) : (uint64_t)(1 + cap));
+    const bool in_pb = ps->n && ps->file == file && ps->first <= p && p < ps->first + ps->n;
+    trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, 0, in_pb ? 1u : span, p);
+    /* a frame of the block's share, least recently allocated first */
+    const uint64_t ta0 = wall_clock64();
+    const uint32_t q = d->quota;
+    const uint32_t base = (uint32_t)bs->pslot * q;
+    int32_t fr = -1;
+    for (uint32_t i = 0; i < 2 * q && fr < 0; ++i) {
+      const uint32_t idx = ps->lra_next;
+      ps->lra_next = idx + 1 == q ? 0 : idx + 1;
+      const uint32_t f = base + idx;
+      uint64_t vkey = 0;
+      uint32_t vra = 0;
+      const int act = lra_visit(d, f, vkey, vra);
+      if (act == GFS_HAND_EVICT) {
+        pt_delete_lane(d, vkey, f);
+        bcount(bs, GFS_C_EVICTIONS, 1);
+        const uint32_t vf = (uint32_t)(vkey >> GFS_KEY_PAGE_BITS) - 1u;
+        const uint32_t vp = (uint32_t)(vkey & ((1ull << GFS_KEY_PAGE_BITS) - 1));
+        trace_ev(d, 1, GFS_EV_HAND, bid, vf, vp, f, GFS_HAND_EVICT, idx);
+      } else if (act == GFS_HAND_SKIP) {
+        trace_ev(d, 1, GFS_EV_HAND, bid, 0xffffffffu, 0xffffffffu, f, GFS_HAND_SKIP, idx);
+      }
+      if (act == GFS_HAND_FREE || act == GFS_HAND_EVICT) fr = (int32_t)f;
+    }
+    bcount(bs, GFS_C_HAND, 1);
+    if (fr < 0) {
+      /* every frame of the share is pinned by other blocks: give the page back, retry */
+      st_rel(d->pt + slot, 0ull);
+      bcount(bs, GFS_C_NOFRAME, 1);
+      status = 1;
+    } else {
+      st_rlx(&d->ftag[fr], key);
+      st_rlx(&d->ffill[fr], 0ull);
+      __hip_atomic_fetch_add(&d->fword[fr], (GFS_FS_FILLING - GFS_FS_CLAIMED) + GFS_FW_VER_ONE + GFS_FW_PIN_ONE,
+                             __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      st_rel(d->pt + slot, (key << GFS_ENTRY_FRAME_BITS) | (uint64_t)fr);
+      trace_ev(d, 1, GFS_EV_ALLOC, bid, file, (uint32_t)p, (uint32_t)fr, 0, (uint64_t)ps->lra_next);
+      bcount(bs, GFS_T_ALLOC, wall_clock64() - ta0);
+      bcount(bs, GFS_C_MISSES, 1);
+      bs->frame = fr;
+      bs->file = file;
+      bs->status = 0;
+      if (in_pb) {
+        trace_ev(d, 1, GFS_EV_PBHIT, bid, file, (uint32_t)p, (uint32_t)fr, 0, 0);
+        bcount(bs, GFS_C_PB_HITS, 1);
+        bs->pull = 3;
+        bs->help_page = (uint32_t)p;
+      } else {
+        /* one request: the page and the prefetch that follows it */
+        const uint64_t off0 = p << d->page_shift;
+        uint64_t len = (uint64_t)span << d->page_shift;
+        if (off0 + len > fsize) len = fsize - off0;
+        const uint64_t tk = fadd64(&d->g->ring_tail, 1);
+        const uint32_t s = (uint32_t)(tk % d->rpc_slots);
+        const uint64_t gen = tk / d->rpc_slots + 1;
+        uint32_t nn = 0;
+        const uint64_t ts0 = wall_clock64();
+        while (ld_acq(&d->slot_free[s]) != gen - 1) {
+          if (expired(d, t0)) {
+            status = 2;
+            break;
+          }
+          nap(nn);
+        }
+        bcount(bs, GFS_T_SLOT, wall_clock64() - ts0);
+        if (status == 0) {
+          gfs_rpc_slot* rs = &d->ring[s];
+          rs->file_id = file;
+          rs->npages = span;
+          rs->offset = off0;
+          rs->length = len;
+          rs->ticket = tk;
+          __hip_atomic_store(&rs->req_seq, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+          trace_ev(d, 1, GFS_EV_REQ, bid, file, (uint32_t)p, GFS_NO_FRAME, span, tk);
+          bcount(bs, GFS_C_REQUESTS, 1);
+          bcount(bs, GFS_C_REQ_BYTES, len);
+          bcount(bs, GFS_C_FETCHED, 1);
+          const uint64_t th0 = wall_clock64();
+          while (__hip_atomic_load(&rs->done_seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) != gen) {
+            if (expired(d, t0)) {
+              status = 2;
+              break;
+            }
+            nap(nn);
+          }
+          bcount(bs, GFS_T_HOST, wall_clock64() - th0);
+          if (status == 0) bs->result = rs->result;
+        }
+        if (status == 0) {
+          bs->pull = 4;
+          bs->slot = s;
+          bs->gen = gen;
+          bs->first_page = p;
+          bs->list_n = span;
+        } else {
+          /* the frame stays FILLING with the pin; the cache must be reset after a timeout */
+          bs->status = -kETIMEDOUT;
+          bs->pull = 0;
+          bcount(bs, GFS_C_TIMEOUTS, 1);
+        }
+      }
+    }
+  }
+  status = __shfl(status, 0, 64);
+  if (status == 1) {
+    if (expired(d, t0)) return 2;
+    if (l == 0) nap(naps);
+    return 1;
+  }
+  return 0;
+}
+
 /* ------------------------------------------------------------------ one page, wave 0
  * Leaves in bs: status; on success the pinned frame, and pull = 1 when this block posted
  * the request and must pull it. */
@@ -842,6 +1022,11 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
         return;
       }
       if (l == 0) bcount(bs, GFS_C_RETRIES, 1);
+    } else if (f < 0 && d->policy == GFS_POLICY_PRIVATE) {
+      const int r = miss_private_wave(d, file, p, key, fsize, bs, bid, t0, naps);
+      if (r == 0) return;
+      if (r == 2) break;
+      continue;
     } else if (f < 0) {
       const uint64_t tl0 = wall_clock64();
       uint64_t ticket;
@@ -1233,6 +1418,63 @@ __device__ int64_t publish_pull_wave(const gfs_dev* d, BlockState* bs, uint64_t 
   return __shfl(st, 0, 64);
 }
 
+/* Block-collective: the private policy's fills. pull 3: the page from the block's private
+ * buffer into its frame; pull 4: the staged request's first page into the frame and the
+ * rest of the span into the private buffer. */
+__device__ void private_pull(const gfs_dev* d, const BlockState* bs, uint64_t fsize) {
+  const uint32_t tid = thread_id(), nt = block_threads();
+  const uint64_t P = d->page_size;
+  const uint32_t f = (uint32_t)bs->frame;
+  const gfs_pslot* ps = &d->pslots[bs->pslot];
+  uint8_t* pb = d->pbuf + (uint64_t)bs->pslot * d->ra_cap * P;
+  if (bs->pull == 3) {
+    const uint64_t q = bs->help_page;
+    uint64_t n = fsize - (q << d->page_shift);
+    if (n > P) n = P;
+    copy_block_aligned(d->frames + (uint64_t)f * P, pb + (q - ps->first) * P, n, tid, nt);
+    return;
+  }
+  const uint8_t* stg = d->staging + (uint64_t)bs->slot * d->max_req_bytes;
+  copy_block_aligned(d->frames + (uint64_t)f * P, stg,
+                     staged_bytes(d, bs->first_page, bs->first_page, bs->result, fsize), tid, nt);
+  const int64_t rest = bs->result - (int64_t)P;
+  if (rest > 0) copy_block_aligned(pb, stg + P, (uint64_t)rest, tid, nt);
+}
+
+/* Thread 0, after private_pull and a block barrier: publish the frame; for a host request,
+ * free its ring slot and make the rest of the span the private buffer (only whole pages
+ * unless the read stopped at the end of the file). 0 or -EIO (the pin is then dropped). */
+__device__ int64_t private_publish_lane(const gfs_dev* d, BlockState* bs, uint64_t fsize) {
+  gfs_pslot* ps = &d->pslots[bs->pslot];
+  const uint32_t f = (uint32_t)bs->frame;
+  if (bs->pull == 3) {
+    publish_frame(d, f, false);
+    ps->used += 1;
+    return 0;
+  }
+  const uint64_t P = d->page_size;
+  const bool short_page = staged_short(d, bs->first_page, bs->first_page, bs->result, fsize);
+  publish_frame(d, f, short_page);
+  st_rel(&d->slot_free[bs->slot], bs->gen);
+  const uint64_t off0 = bs->first_page << d->page_shift;
+  uint64_t expect = (uint64_t)bs->list_n * P;
+  if (expect > fsize - off0) expect = fsize - off0;
+  const int64_t rest = bs->result - (int64_t)P;
+  uint32_t n = 0;
+  if (rest > 0) n = (uint32_t)((bs->result == (int64_t)expect) ? ((uint64_t)rest + P - 1) / P : (uint64_t)rest / P);
+  bcount(bs, GFS_C_PB_WASTED, ps->n - ps->used);
+  bcount(bs, GFS_C_RA_PAGES, n);
+  ps->file = bs->file;
+  ps->first = bs->first_page + 1;
+  ps->n = n;
+  ps->used = 0;
+  if (short_page) {
+    frame_unpin(d, f);
+    return -kEIO;
+  }
+  return 0;
+}
+
 }  // namespace gfsd
 
 /* ====================================================================== public API */
@@ -1250,6 +1492,23 @@ __device__ int gopen_id(const gfs_dev* d, int file_id, int flags) {
       __hip_atomic_fetch_add(&d->files[file_id].handles, 1u, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
       v = file_id;
+    }
+    bs->pslot = -1;
+    if (v >= 0 && d->policy == GFS_POLICY_PRIVATE) {
+      /* the block's private slot: its own frames and private buffer until gclose */
+      for (uint32_t i = 0; i < d->npslots && bs->pslot < 0; ++i) {
+        const uint32_t s = (gfsd::block_id() + i) % d->npslots;
+        uint32_t z = 0;
+        if (gfsd::cas32(&d->pslots[s].owner, z, 1u)) bs->pslot = (int32_t)s;
+      }
+      if (bs->pslot < 0) {
+        __hip_atomic_fetch_sub(&d->files[file_id].handles, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v = -gfsd::kENOSPC;
+      } else {
+        gfs_pslot* ps = &d->pslots[bs->pslot];
+        ps->n = 0;   /* a new owner starts with an empty private buffer */
+        ps->used = 0;
+      }
     }
     for (int c = 0; c < GFS_C_COUNT; ++c) bs->ctr[c] = 0;
     bs->pull = 0;
@@ -1288,6 +1547,14 @@ __device__ int gclose(const gfs_dev* d, int fd) {
   __syncthreads();
   if (gfsd::thread_id() == 0) {
     __hip_atomic_fetch_sub(&d->files[fd].handles, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (d->policy == GFS_POLICY_PRIVATE && bs->pslot >= 0) {
+      gfs_pslot* ps = &d->pslots[bs->pslot];
+      bs->ctr[GFS_C_PB_WASTED] += ps->n - ps->used;   /* the private buffer is dropped */
+      ps->n = 0;
+      ps->used = 0;
+      __hip_atomic_store(&ps->owner, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      bs->pslot = -1;
+    }
     for (int c = 0; c < GFS_C_COUNT; ++c) {
       if (bs->ctr[c]) gfsd::fadd64(&d->g->ctr[c], bs->ctr[c]);
       bs->ctr[c] = 0;
@@ -1318,7 +1585,19 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
     const uint64_t ta0 = wall_clock64();
     if (tid < 64) acquire_page_wave(d, (uint32_t)fd, p, fsize, bs, bid);
     __syncthreads();
-    if (bs->pull) {
+    if (bs->pull >= 3) {
+      const uint64_t tp0 = wall_clock64();
+      private_pull(d, bs, fsize);
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) {
+        const int64_t st = private_publish_lane(d, bs, fsize);
+        if (st < 0) bs->status = st;
+        bs->pull = 0;
+        bcount(bs, GFS_T_PULL, wall_clock64() - tp0);
+      }
+      __syncthreads();
+    } else if (bs->pull) {
       const uint64_t tp0 = wall_clock64();
       if (bs->pull == 1) {
         if (tid < 64) claim_pulls_wave(d, bs);

@@ -11,6 +11,7 @@
  *   locks[GFS_MAX_FILES]             128 B each (miss ticket locks)
  *   lockq[GFS_MAX_FILES][GFS_LOCK_SLOTS] u32   queue slots of the miss locks
  *   claims[GFS_MAX_FILES]            128 B each (windows being reserved)
+ *   pslots[private_slots]            64 B each (private policy)
  *   names[GFS_MAX_FILES]             GFS_NAME_MAX B each (registered paths)
  *   fword[nframes]  u64              frame word (state, pins, ref, ra, version)
  *   ftag[nframes]   u64              key of the page held (valid while not FREE)
@@ -73,8 +74,11 @@ enum {
   /* every page gread serves, summed over blocks: finding and pinning it (hit, join or
      miss, including pulls), copying it out, dropping the pin */
   GFS_T_ACQUIRE, GFS_T_COPY, GFS_T_UNPIN,
+  GFS_C_PB_HITS,     /* private policy: misses filled from the private buffer */
+  GFS_C_PB_WASTED,   /* private policy: private-buffer pages dropped unused */
   GFS_C_COUNT
 };
+typedef char gfs_counters_fit[(GFS_C_COUNT <= 32) ? 1 : -1];   /* gfs_globals.ctr */
 
 #define GFS_RECENT_MISSES 64   /* misses remembered per file by the readahead detector */
 #define GFS_NEAR_MIN 3         /* remembered misses near a miss that mark aggregate reading */
@@ -118,6 +122,18 @@ typedef struct gfs_file_lock {
    it, and later windows are clipped to stay out of it. Entry = start << 32 | len << 1 | 1
    (0 = free). */
 #define GFS_CLAIMS 16
+
+/* private policy: one per slot; the slot's frames are [slot * quota, (slot + 1) * quota) and
+   its private buffer holds pages [first, first + n) of file `file` */
+typedef struct gfs_pslot {
+  uint32_t owner;         /* 1 while a block holds the slot */
+  uint32_t file;
+  uint64_t first;
+  uint32_t n;             /* pages in the buffer */
+  uint32_t used;          /* of them, taken into the cache */
+  uint32_t lra_next;      /* next frame of the share to (re)allocate */
+  uint32_t pad[9];
+} gfs_pslot;              /* 64 B */
 typedef struct gfs_file_claims {
   uint64_t e[GFS_CLAIMS];
 } gfs_file_claims;        /* 128 B */
@@ -175,6 +191,12 @@ typedef struct gfs_dev {
   gfs_file_lock* locks;
   uint32_t* lockq;              /* [GFS_MAX_FILES][GFS_LOCK_SLOTS] miss-lock queue slots */
   gfs_file_claims* claims;      /* [GFS_MAX_FILES] windows being reserved */
+  gfs_pslot* pslots;            /* private policy: [private_slots] */
+  uint8_t* pbuf;                /* private policy: [private_slots][ra_cap pages] in the frames allocation */
+  uint32_t policy;              /* GFS_POLICY_* */
+  uint32_t npslots;             /* private slots */
+  uint32_t quota;               /* frames per private slot */
+  uint32_t pad32;
   uint64_t* slot_free;
   uint64_t* ffill;
   gfs_req_dev* reqd;
@@ -183,7 +205,6 @@ typedef struct gfs_dev {
   char* names;                  /* [GFS_MAX_FILES][GFS_NAME_MAX] registered paths */
   gfs_rpc_slot* ring;           /* device-visible address of the pinned ring */
   uint8_t* staging;             /* device-visible address of the pinned staging */
-  uint64_t pad[2];
 } gfs_dev;
 
 #endif /* GFS_LAYOUT_H */

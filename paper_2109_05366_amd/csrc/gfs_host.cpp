@@ -53,7 +53,9 @@ uint32_t log2u(uint64_t v) {
 struct Layout {
   uint64_t nframes = 0, nbuckets = 0, ra_init = 0, ra_cap = 0, max_req_pages = 0;
   uint64_t max_req_bytes = 0;
-  uint64_t off_globals = 0, off_dev = 0, off_files = 0, off_locks = 0, off_lockq = 0, off_claims = 0, off_names = 0, off_fword = 0,
+  uint64_t quota = 0;              /* private policy: frames per slot */
+  uint64_t pbuf_bytes = 0;         /* private policy: all private buffers */
+  uint64_t off_globals = 0, off_dev = 0, off_files = 0, off_locks = 0, off_lockq = 0, off_claims = 0, off_pslots = 0, off_names = 0, off_fword = 0,
            off_ftag = 0, off_pt = 0, off_ffill = 0, off_slot_free = 0, off_reqd = 0, off_trace = 0,
            meta_bytes = 0;
 };
@@ -76,7 +78,18 @@ int make_layout(const gfs_config* c, Layout* L) {
   if (c->io_backend != GFS_IO_PREAD) return -EINVAL;
   if (c->o_direct > GFS_DIRECT_PREFER) return -EINVAL;
   if (c->trace_level > 2) return -EINVAL;
-  L->max_req_pages = L->ra_cap ? L->ra_cap : 1;
+  if (c->policy == GFS_POLICY_SHARED) {
+    L->max_req_pages = L->ra_cap ? L->ra_cap : 1;
+  } else if (c->policy == GFS_POLICY_PRIVATE) {
+    // a request is the missed page plus the static prefetch that follows it
+    if (c->private_slots < 1 || c->private_slots > 65536) return -EINVAL;
+    L->quota = L->nframes / c->private_slots;
+    if (L->quota < 1) return -EINVAL;
+    L->max_req_pages = 1 + L->ra_cap;
+    L->pbuf_bytes = (uint64_t)c->private_slots * L->ra_cap * P;
+  } else {
+    return -EINVAL;
+  }
   L->max_req_bytes = L->max_req_pages * P;
   // page table: 4 entries per frame, 16-entry buckets, power-of-two bucket count
   uint64_t nb = 2;
@@ -89,6 +102,8 @@ int make_layout(const gfs_config* c, Layout* L) {
   L->off_locks = o; o = align_up(o + sizeof(gfs_file_lock) * GFS_MAX_FILES, kAlign);
   L->off_lockq = o; o = align_up(o + 4ull * GFS_LOCK_SLOTS * GFS_MAX_FILES, kAlign);
   L->off_claims = o; o = align_up(o + sizeof(gfs_file_claims) * GFS_MAX_FILES, kAlign);
+  L->off_pslots = o;
+  if (c->policy == GFS_POLICY_PRIVATE) o = align_up(o + sizeof(gfs_pslot) * c->private_slots, kAlign);
   L->off_names = o; o = align_up(o + (uint64_t)GFS_NAME_MAX * GFS_MAX_FILES, kAlign);
   L->off_fword = o; o = align_up(o + 8 * L->nframes, kAlign);
   L->off_ftag = o; o = align_up(o + 8 * L->nframes, kAlign);
@@ -326,7 +341,7 @@ int download_file_record(gfs_ctx* c, int id, gfs_file_dev* rec) {
 int zero_dynamic(gfs_ctx* c) {
   const Layout& L = c->L;
   int rc = gfs_internal_zero(c->meta + L.off_globals, sizeof(gfs_globals), c->stream);
-  // miss locks, their queue slots, window claims
+  // miss locks, their queue slots, window claims, private slots
   if (!rc) rc = gfs_internal_zero(c->meta + L.off_locks, L.off_names - L.off_locks, c->stream);
   if (!rc) rc = gfs_internal_zero(c->meta + L.off_fword, L.off_trace - L.off_fword, c->stream);
   if (!rc && c->cfg.trace_capacity)
@@ -356,13 +371,15 @@ void gfs_config_default(gfs_config* cfg) {
   cfg->trace_level = 0;
   cfg->trace_capacity = 0;
   cfg->wait_timeout_ns = 0;
+  cfg->policy = GFS_POLICY_SHARED;
+  cfg->private_slots = 512;
 }
 
 int gfs_device_bytes(const gfs_config* cfg, size_t* frames_bytes, size_t* meta_bytes) {
   Layout L;
   const int rc = make_layout(cfg, &L);
   if (rc) return rc;
-  if (frames_bytes) *frames_bytes = cfg->cache_bytes;
+  if (frames_bytes) *frames_bytes = cfg->cache_bytes + L.pbuf_bytes;
   if (meta_bytes) *meta_bytes = L.meta_bytes;
   return 0;
 }
@@ -443,6 +460,13 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   h.locks = (gfs_file_lock*)(c->meta + L.off_locks);
   h.lockq = (uint32_t*)(c->meta + L.off_lockq);
   h.claims = (gfs_file_claims*)(c->meta + L.off_claims);
+  h.policy = cfg->policy;
+  if (cfg->policy == GFS_POLICY_PRIVATE) {
+    h.pslots = (gfs_pslot*)(c->meta + L.off_pslots);
+    h.pbuf = c->frames + cfg->cache_bytes;
+    h.npslots = cfg->private_slots;
+    h.quota = (uint32_t)L.quota;
+  }
   h.names = (char*)(c->meta + L.off_names);
   h.fword = (uint64_t*)(c->meta + L.off_fword);
   h.ftag = (uint64_t*)(c->meta + L.off_ftag);
@@ -613,6 +637,8 @@ int gfs_stats_read(gfs_ctx* c, gfs_stats* out) {
   s.t_acquire_ns = (uint64_t)(g.ctr[GFS_T_ACQUIRE] * ns_per_tick);
   s.t_copy_ns = (uint64_t)(g.ctr[GFS_T_COPY] * ns_per_tick);
   s.t_unpin_ns = (uint64_t)(g.ctr[GFS_T_UNPIN] * ns_per_tick);
+  s.private_hits = g.ctr[GFS_C_PB_HITS];
+  s.private_wasted = g.ctr[GFS_C_PB_WASTED];
   s.host_errors = c->host_errors.load();
   s.host_last_errno = (uint64_t)c->host_last_errno.load();
   for (uint32_t i = 0; i < 64; ++i) s.host_spins[i] = c->spins[i].load();

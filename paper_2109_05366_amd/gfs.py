@@ -19,6 +19,7 @@ GFS_ABI_VERSION = 1
 GFS_O_RDONLY = 0
 GFS_ADV_NORMAL, GFS_ADV_RANDOM, GFS_ADV_SEQUENTIAL = 0, 1, 2
 GFS_DIRECT_OFF, GFS_DIRECT_ON, GFS_DIRECT_PREFER = 0, 1, 2
+GFS_POLICY_SHARED, GFS_POLICY_PRIVATE = 0, 1
 GFS_MAX_WINDOW_PAGES = 1024
 
 EV_HIT, EV_JOIN, EV_MISS, EV_HAND, EV_ALLOC, EV_REQ, EV_NOFRAME = 1, 2, 3, 4, 5, 6, 7
@@ -33,7 +34,7 @@ class gfs_config(C.Structure):
         ("host_threads", C.c_uint32), ("rpc_slots", C.c_uint32),
         ("io_backend", C.c_uint32), ("o_direct", C.c_uint32),
         ("trace_level", C.c_uint32), ("trace_capacity", C.c_uint32),
-        ("wait_timeout_ns", C.c_uint64),
+        ("wait_timeout_ns", C.c_uint64), ("policy", C.c_uint32), ("private_slots", C.c_uint32),
     ]
 
 
@@ -42,7 +43,7 @@ _STAT_U64 = ["hits", "joins", "misses", "ra_pages", "fetched_pages", "evictions"
              "timeouts", "io_errors", "trace_events", "host_requests", "host_bytes", "host_read_ns",
              "t_lock_ns", "t_crit_ns", "t_alloc_ns", "t_slot_ns", "t_host_ns", "t_pull_ns", "t_join_ns",
              "t_decide_ns", "t_run_ns", "t_unlock_ns", "lock_acquired", "lock_left", "t_acquire_ns", "t_copy_ns",
-             "t_unpin_ns",
+             "t_unpin_ns", "private_hits", "private_wasted",
              "host_errors", "host_last_errno"]
 
 

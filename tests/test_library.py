@@ -37,7 +37,8 @@ def test_config_default_values():
     assert cfg.page_size == 64 << 10 and cfg.cache_bytes == 256 << 20
     assert cfg.ra_init_bytes == 4 * cfg.page_size and cfg.ra_cap_bytes == 16 << 20
     assert cfg.streams_per_file == 8 and cfg.host_threads == 8 and cfg.rpc_slots == 64
-    assert ctypes.sizeof(gfs.gfs_config) == 72
+    assert ctypes.sizeof(gfs.gfs_config) == 80
+    assert cfg.policy == gfs.GFS_POLICY_SHARED and cfg.private_slots == 512
     assert gfs.EVENT_DTYPE.itemsize == 32
 
 
