@@ -391,6 +391,10 @@ def main() -> int:
     ap.add_argument("--no-hit-path", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="c4: search page size, cap and blocks per file")
     ap.add_argument("--rates", default="200", help="c5: comma-separated arrival rates per second")
+    ap.add_argument("--policy", default="shared", choices=["shared", "private"],
+                    help="cache policy: shared readahead + clock, or the paper's private buffers + per-block LRA")
+    ap.add_argument("--private-slots", type=int, default=512)
+    ap.add_argument("--ra-cap-kib", type=int, default=0, help="readahead cap / prefetch size in KiB (overrides MiB)")
     ap.add_argument("--advice", default="normal", choices=["normal", "random", "sequential"],
                     help="fadvise-style hint for the file of c2/c3 (random switches readahead off)")
     args = ap.parse_args()
@@ -430,17 +434,20 @@ def main() -> int:
     results = {}
     stats = {}
     kernel_ms = {}
-    for label, cap_mib in (("ra", args.ra_cap_mib), ("no_ra", 0)):
+    cap_bytes = (args.ra_cap_kib << 10) if args.ra_cap_kib else (args.ra_cap_mib << 20)
+    policy = gfs.GFS_POLICY_PRIVATE if args.policy == "private" else gfs.GFS_POLICY_SHARED
+    for label, cap in (("ra", cap_bytes), ("no_ra", 0)):
         if label == "no_ra" and args.no_ra_off:
             continue
-        cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=cap_mib << 20,
-                                 host_threads=args.host_threads, rpc_slots=args.rpc_slots, timeout_s=60)
+        cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=cap,
+                                 host_threads=args.host_threads, rpc_slots=args.rpc_slots, timeout_s=60,
+                                 policy=policy, private_slots=args.private_slots)
         with gfs.PageCache(cfg) as cache:
             fid = cache.open(path)
             if args.advice != "normal":
                 cache.fadvise(fid, {"random": gfs.GFS_ADV_RANDOM, "sequential": gfs.GFS_ADV_SEQUENTIAL}[args.advice])
             reader = runner.ListReader(wl.offsets, wl.read_size, wl.consumer, wl.threads)
-            log(f"{label}: cap {cap_mib} MiB")
+            log(f"{label}: cap {cap >> 10} KiB, policy {args.policy}")
             wall, kms, st = run_steps(torch, cache, fid, reader, args.steps, args.warmup)
             res = reader.result()
         if st["timeouts"] or st["io_errors"]:
@@ -456,7 +463,8 @@ def main() -> int:
                                            "evictions", "wasted_pages", "requests", "request_bytes",
                                            "host_bytes", "retries", "noframe", "host_read_ns",
                                            "t_lock_ns", "t_crit_ns", "t_alloc_ns", "t_slot_ns",
-                                           "t_host_ns", "t_pull_ns", "t_join_ns")}
+                                           "t_host_ns", "t_pull_ns", "t_join_ns", "private_hits",
+                                           "private_wasted")}
         kernel_ms[label] = float(np.mean(kms))
         log(f"{label}: {results[label]['GBps']:.2f} GB/s wall, {results[label]['kernel_GBps']:.2f} GB/s kernel")
 
@@ -528,7 +536,8 @@ def main() -> int:
                                f"{wl.cache_bytes >> 30} GiB cache, {wl.page_size >> 10} KiB pages, "
                                f"{wl.blocks} blocks x {wl.threads} threads, {wl.read_size >> 10} KiB reads, "
                                f"cold per step",
-                   "ra_cap_MiB": args.ra_cap_mib, "advice": args.advice, "host_threads": args.host_threads,
+                   "ra_cap_KiB": cap_bytes >> 10, "policy": args.policy, "advice": args.advice,
+                   "host_threads": args.host_threads,
                    "rpc_slots": args.rpc_slots, "data_dir": ddir},
         "readahead_off_GBps": round(results["no_ra"]["GBps"], 3) if "no_ra" in results else None,
         "readahead_speedup": round(value / results["no_ra"]["GBps"], 3) if "no_ra" in results else None,

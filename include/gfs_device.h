@@ -1495,11 +1495,20 @@ __device__ int gopen_id(const gfs_dev* d, int file_id, int flags) {
     }
     bs->pslot = -1;
     if (v >= 0 && d->policy == GFS_POLICY_PRIVATE) {
-      /* the block's private slot: its own frames and private buffer until gclose */
-      for (uint32_t i = 0; i < d->npslots && bs->pslot < 0; ++i) {
-        const uint32_t s = (gfsd::block_id() + i) % d->npslots;
-        uint32_t z = 0;
-        if (gfsd::cas32(&d->pslots[s].owner, z, 1u)) bs->pslot = (int32_t)s;
+      /* the block's private slot: its own frames and private buffer until gclose. A slot
+         given back by a block that just ended may not show yet: look again, with naps,
+         until the wait timeout */
+      const uint64_t t0 = wall_clock64();
+      uint32_t naps = 0;
+      while (bs->pslot < 0) {
+        for (uint32_t i = 0; i < d->npslots && bs->pslot < 0; ++i) {
+          const uint32_t s = (gfsd::block_id() + i) % d->npslots;
+          uint32_t z = 0;
+          if (gfsd::ld_rlx32(&d->pslots[s].owner) == 0 && gfsd::cas32(&d->pslots[s].owner, z, 1u))
+            bs->pslot = (int32_t)s;
+        }
+        if (bs->pslot >= 0 || gfsd::expired(d, t0)) break;
+        gfsd::nap(naps);
       }
       if (bs->pslot < 0) {
         __hip_atomic_fetch_sub(&d->files[file_id].handles, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
