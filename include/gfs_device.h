@@ -75,6 +75,7 @@ struct BlockState {
   uint32_t nclaim;              /* entries of lslot[] claimed for pulling */
   uint32_t help_page;           /* page of the frame a helping block pulls */
   int32_t pslot;                /* private policy: the block's slot (-1: none) */
+  int32_t bframe[64];           /* batched hits: frame pinned for page base + i, or -1 */
 };
 
 __device__ __forceinline__ BlockState* block_state() {
@@ -231,6 +232,19 @@ __device__ bool pt_present_lane(const gfs_dev* d, uint64_t key) {
 #pragma unroll
   for (int i = 0; i < 2 * GFS_BUCKET_SLOTS; ++i) hit |= (e[i] >> GFS_ENTRY_FRAME_BITS) == key;
   return hit;
+}
+
+/* per lane: the frame key maps to, kReserved, or -1 when absent */
+__device__ int32_t pt_find_lane(const gfs_dev* d, uint64_t key) {
+  uint32_t b1, b2;
+  key_buckets(d, key, b1, b2);
+  uint64_t e[2 * GFS_BUCKET_SLOTS];
+  pt_load_lane(d, b1, b2, e);
+  int32_t f = -1;
+#pragma unroll
+  for (int i = 0; i < 2 * GFS_BUCKET_SLOTS; ++i)
+    if ((e[i] >> GFS_ENTRY_FRAME_BITS) == key) f = (int32_t)(e[i] & kFrameMask);
+  return f;
 }
 
 /* per lane, under key's file lock: reserve key; returns the global slot index or -1 if
@@ -1589,8 +1603,87 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
   const uint32_t bid = block_id();
   const uint64_t P = d->page_size;
   const uint32_t sh_bits = d->page_shift;
+  const uint64_t pfirst = offset >> sh_bits, plast = (end - 1) >> sh_bits;
   int64_t err = 0;
-  for (uint64_t p = offset >> sh_bits; p <= (end - 1) >> sh_bits; ++p) {
+  /* Reads of several pages first take every page that is cached and valid in one pass:
+     lane i of wave 0 looks up and pins page base + i, the block copies all of them, and
+     the pins are dropped together. The remaining pages (misses, frames being filled) go
+     through the one-page path below, in order. Off while the policy trace is recorded, so
+     that a traced run makes its accesses one at a time in page order. */
+  const bool batched = plast > pfirst && d->trace_level == 0;
+  if (batched) {
+    const uint32_t cnt = (uint32_t)((plast - pfirst + 1) < 64 ? (plast - pfirst + 1) : 64);
+    const uint64_t tb0 = wall_clock64();
+    if (tid < 64) {
+      int32_t f = -1;
+      if (tid < cnt) {
+        const uint64_t key = page_key((uint32_t)fd, pfirst + tid);
+        f = pt_find_lane(d, key);
+        if (f >= 0 && (uint32_t)f != kReserved) {
+          const int r = frame_pin(d, (uint32_t)f, key);
+          if (r != PIN_VALID) {
+            if (r == PIN_FILLING) frame_unpin(d, (uint32_t)f);   /* the one-page path joins it */
+            f = -1;
+          }
+        } else {
+          f = -1;
+        }
+      }
+      bs->bframe[tid] = f;
+      const uint64_t got = __ballot(f >= 0);
+      if (tid == 0) bcount(bs, GFS_C_HITS, (uint64_t)__popcll(got));
+    }
+    __syncthreads();
+    /* whole pages: one pass over all their 16-byte units, eight in flight per thread */
+    const bool aligned = ((((uintptr_t)dst) | offset) & 15) == 0;
+    const uint32_t ush = sh_bits - 4;
+    const uint64_t total = (uint64_t)cnt << ush;
+    if (aligned) {
+      for (uint64_t u0 = tid; u0 < total; u0 += 8ull * nt) {
+        v4u a[8];
+        bool ok[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const uint64_t u = u0 + (uint64_t)j * nt;
+          const uint32_t i = (uint32_t)(u >> ush);
+          const uint64_t pos = ((pfirst + i) << sh_bits) + ((u & ((1ull << ush) - 1)) << 4);
+          const int32_t f = u < total ? bs->bframe[i] : -1;
+          ok[j] = f >= 0 && pos >= offset && pos + 16 <= end;
+          if (ok[j]) a[j] = ((const gv4u*)(d->frames + (uint64_t)f * P))[u & ((1ull << ush) - 1)];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const uint64_t u = u0 + (uint64_t)j * nt;
+          const uint64_t pos = ((pfirst + (u >> ush)) << sh_bits) + ((u & ((1ull << ush) - 1)) << 4);
+          if (ok[j]) ((gv4u*)((uint8_t*)dst + (pos - offset)))[0] = a[j];
+        }
+      }
+    }
+    /* bytes the unit pass left: unaligned buffers, and the ends of partly covered pages */
+    for (uint32_t i = 0; i < cnt; ++i) {
+      const int32_t f = bs->bframe[i];
+      if (f < 0) continue;
+      const uint64_t pbase = (pfirst + i) << sh_bits;
+      const uint64_t lo = offset > pbase ? offset : pbase;
+      const uint64_t hi = end < pbase + P ? end : pbase + P;
+      if (!aligned) {
+        copy_block((uint8_t*)dst + (lo - offset), d->frames + (uint64_t)f * P + (lo - pbase), hi - lo, tid, nt);
+      } else {
+        /* units cover [lo16, hi16): copy the head and tail bytes outside them */
+        const uint64_t lo16 = (lo + 15) & ~15ull, hi16 = hi & ~15ull;
+        for (uint64_t b = lo + tid; b < (lo16 < hi ? lo16 : hi); b += nt)
+          ((uint8_t*)dst)[b - offset] = d->frames[(uint64_t)f * P + (b - pbase)];
+        for (uint64_t b = (hi16 > lo16 ? hi16 : lo16) + tid; b < hi; b += nt)
+          ((uint8_t*)dst)[b - offset] = d->frames[(uint64_t)f * P + (b - pbase)];
+      }
+    }
+    __syncthreads();
+    if (tid < cnt && bs->bframe[tid] >= 0) frame_unpin(d, (uint32_t)bs->bframe[tid]);
+    if (tid == 0) bcount(bs, GFS_T_COPY, wall_clock64() - tb0);
+    __syncthreads();
+  }
+  for (uint64_t p = pfirst; p <= plast; ++p) {
+    if (batched && p - pfirst < 64 && bs->bframe[p - pfirst] >= 0) continue;
     const uint64_t ta0 = wall_clock64();
     if (tid < 64) acquire_page_wave(d, (uint32_t)fd, p, fsize, bs, bid);
     __syncthreads();

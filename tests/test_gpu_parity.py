@@ -168,3 +168,30 @@ def test_reset_gives_cold_cache(data_dir, cuda):
             assert st["delivered_bytes"] == wl.delivered_bytes
             cache.reset()
             assert cache.stats()["misses"] == 0
+
+
+@pytest.mark.parametrize("shift", [0, 40, 4096 + 12])
+def test_multipage_reads_batched_hits(shift, data_dir, cuda):
+    """Reads spanning many small pages (4 KiB pages, 96 KiB reads, some at offsets that are
+    not page- or 16-byte-aligned): a cold pass mixes misses, joins and hits, a warm pass is
+    all hits taken by the batched pass; both equal the oracle, and so does a pass with the
+    policy trace on (one page at a time)."""
+    from workloads.configs import Workload, FileSpec, strided_offsets, CONSUMER_CHECKSUM
+    f = FileSpec("mp_seed21_6MiB.bin", 21, (6 << 20) + 1234)
+    offs = strided_offsets(32, 2, 96 << 10) + shift
+    wl = Workload("mp", f, 4 << 10, 2 << 20, 32, 256, 96 << 10, offs, CONSUMER_CHECKSUM)
+    path = configs.ensure_file(wl.file, data_dir)
+    exp_out, exp_deliv = expected(wl, path)
+    for trace in (0, 1):
+        cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=64 << 10, trace_level=trace,
+                                 trace_capacity=(1 << 18) if trace else 0, timeout_s=20)
+        with gfs.PageCache(cfg) as cache:
+            fid = cache.open(path)
+            cold = runner.run_list(cache, fid, wl.offsets, wl.read_size, wl.consumer)
+            warm = runner.run_list(cache, fid, wl.offsets, wl.read_size, wl.consumer)
+            st = cache.stats()
+        for res in (cold, warm):
+            np.testing.assert_array_equal(res.status, exp_deliv)
+            np.testing.assert_array_equal(res.out, exp_out)
+        assert st["timeouts"] == 0 and st["io_errors"] == 0
+        assert st["hits"] > 0
