@@ -214,7 +214,7 @@ def bench_batch(args, torch) -> int:
     log(f"storage peak {nvme:.2f} GB/s, H2D peak {h2d:.2f} GB/s")
     bb = autotune.BatchBench(paths, sizes, m["cache_bytes"], host_threads=args.host_threads,
                              rpc_slots=args.rpc_slots)
-    # the autotuner's pick on the box's disk (coordinate descent over 17 cold passes):
+    # the autotuner's pick on a virtio disk (coordinate descent over 17 cold passes):
     # 64 KiB pages, 1 MiB windows, 8 blocks per file
     best = (64 << 10, 1 << 20, 8)
     history = []
@@ -234,6 +234,9 @@ def bench_batch(args, torch) -> int:
     off_cfg = (best[0], 0, best[2])
     off, _, _ = bb.run(off_cfg)
     log(f"readahead off: {off:.2f} GB/s")
+    # the plain form: the same files, one launch per file (each over the whole grid), in turn
+    plain = bb.run_per_file(best)
+    log(f"one launch per file: {plain:.2f} GB/s")
     # sampled parity: the smallest files' checksums and histograms against the oracle
     from oracle import data as odata
     small = np.argsort(sizes)[:3].tolist()
@@ -254,6 +257,7 @@ def bench_batch(args, torch) -> int:
                    "data_dir": ddir},
         "runs_GBps": [round(x, 3) for x in runs],
         "readahead_off_GBps": round(off, 3), "readahead_speedup": round(value / off, 3),
+        "one_launch_per_file_GBps": round(plain, 3), "batched_speedup": round(value / plain, 3),
         "storage_peak_GBps": round(nvme, 3), "h2d_peak_GBps": round(h2d, 3),
         "io_bound": {"bound": "storage" if nvme < h2d else "h2d", "achieved": round(value, 3),
                      "peak": round(min_peak, 3), "unit": "GB/s", "frac": round(value / min_peak, 3)},
@@ -300,6 +304,29 @@ def bench_serve(args, torch) -> int:
                     "hits": st["hits"], "misses": st["misses"], "host_GB": round(st["host_bytes"] / 1e9, 2),
                     "peak_pending": summ["peak_pending"], "grid": summ["grid"],
                     "clock_skew_us": round(summ["clock_skew_ns"] / 1e3, 2), "recs": recs})
+    # the plain form: the first 64 requests, all present at the start, served together by
+    # the loop (their work overlaps) against one request at a time; cold cache for each
+    nsub = min(64, len(files))
+    cfg = runner.make_config(page, budget, ra_cap_bytes=args.ra_cap_mib << 20, host_threads=args.host_threads,
+                             rpc_slots=args.rpc_slots, timeout_s=60)
+    with gfs.PageCache(cfg) as cache:
+        ids = [cache.open(p) for p in paths]
+        sub_ids = [ids[f] for f in files[:nsub]]
+        t0 = time.perf_counter()
+        recs_t, summ_t = runner.serve(cache, sub_ids, [0] * nsub, budget)
+        together = summ_t["delivered_bytes"] / (time.perf_counter() - t0) / 1e9
+        cache.reset()
+        t0 = time.perf_counter()
+        alone_bytes = 0
+        alone_csum = []
+        for i in sub_ids:
+            r, s_ = runner.serve(cache, [i], [0], budget)
+            alone_bytes += s_["delivered_bytes"]
+            alone_csum.append(int(r["csum"][0]))
+        alone = alone_bytes / (time.perf_counter() - t0) / 1e9
+    if [int(c) for c in recs_t["csum"]] != alone_csum:
+        raise RuntimeError("c5: a request's checksum differs alone and in the mix")
+    log(f"first {nsub} requests: together {together:.2f} GB/s, one at a time {alone:.2f} GB/s")
     from oracle import data as odata
     small = sorted(set(files[np.argsort(sizes[files])[:3]].tolist()))
     for f in small:
@@ -318,6 +345,7 @@ def bench_serve(args, torch) -> int:
                    "page_KiB": page >> 10, "ra_cap_MiB": args.ra_cap_mib, "chunk_MiB": 1, "data_dir": ddir},
         "storage_peak_GBps": round(nvme, 3),
         "rates": [{k: v for k, v in o.items() if k != "recs"} for o in out],
+        "first64_together_GBps": round(together, 3), "first64_one_at_a_time_GBps": round(alone, 3),
         "parity_sampled_files": small,
     }
     print(json.dumps(line), flush=True)
@@ -457,7 +485,7 @@ def main() -> int:
                     help="fadvise-style hint for the file of c2/c3 (random switches readahead off)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); "
               "the path is per-GPU and would shard by file/chunk across GPUs, see DESIGN.md",
               file=sys.stderr)
         return 2

@@ -98,5 +98,27 @@ class BatchBench:
             st = cache.stats()
         return passes * self.total / dt / 1e9, res, st
 
+    def run_per_file(self, cfg: Config) -> float:
+        """The plain form for comparison: one cold pass with a separate launch per file (each
+        over the whole grid, blocks_per_file = the grid), one after another. GB/s."""
+        import torch
+        page, cap, _ = cfg
+        cache_bytes = self.cache_bytes // page * page
+        conf = runner.make_config(page, cache_bytes, ra_cap_bytes=cap, host_threads=self.host_threads,
+                                  rpc_slots=self.rpc_slots, timeout_s=120)
+        with gfs.PageCache(conf) as cache:
+            ids = [cache.open(p) for p in self.paths]
+            unit = max(page, 256 << 10)
+            readers = [runner.BatchReader([i], [s], unit, 1 << 20, threads=self.threads)
+                       for i, s in zip(ids, self.sizes)]
+            cache.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for br in readers:
+                br.launch(cache)
+                br.result()
+            dt = time.perf_counter() - t0
+        return self.total / dt / 1e9
+
     def measure(self, cfg: Config) -> float:
         return self.run(cfg)[0]

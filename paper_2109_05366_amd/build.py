@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libgfs.so")
 SOURCES = ["gfs_host.cpp", "gfs_kernels.hip", "gfs_serve.hip"]
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
-    # packed fp32 instructions are not used in this build
+    # no packed fp32 instructions in the code objects
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
