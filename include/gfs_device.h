@@ -1469,6 +1469,7 @@ __device__ int64_t private_publish_lane(const gfs_dev* d, BlockState* bs, uint64
   const uint64_t P = d->page_size;
   const bool short_page = staged_short(d, bs->first_page, bs->first_page, bs->result, fsize);
   publish_frame(d, f, short_page);
+  if (short_page) bcount(bs, GFS_C_IOERR, 1);
   st_rel(&d->slot_free[bs->slot], bs->gen);
   const uint64_t off0 = bs->first_page << d->page_shift;
   uint64_t expect = (uint64_t)bs->list_n * P;

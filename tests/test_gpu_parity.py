@@ -195,3 +195,39 @@ def test_multipage_reads_batched_hits(shift, data_dir, cuda):
             np.testing.assert_array_equal(res.out, exp_out)
         assert st["timeouts"] == 0 and st["io_errors"] == 0
         assert st["hits"] > 0
+
+
+@pytest.mark.parametrize("ra_pages", [0, 16])
+def test_file_shrunk_under_the_cache_reports_eio(ra_pages, data_dir, cuda, tmp_path):
+    """Failure handling forced from the host: a registered 4 MiB file is cut to 3 MiB + 100 B
+    on disk, so the host reads of the pages past that point come back short. Blocks that read
+    only below the cut get the right bytes; blocks that reach past it get -EIO (no hang, no
+    wrong bytes); the cache is usable again after a reset."""
+    import shutil
+    from oracle import data as odata
+    src = configs.ensure_file(configs.FileSpec("shrink_seed31_4MiB.bin", 31, 4 << 20), data_dir)
+    path = str(tmp_path / "shrinking.bin")
+    shutil.copyfile(src, path)
+    page = 64 << 10
+    offs = (np.arange(16 * 4, dtype=np.uint64) * np.uint64(page)).reshape(16, 4)   # block b: pages 4b..4b+3
+    cfg = runner.make_config(page, 16 << 20, ra_cap_bytes=ra_pages * page, timeout_s=20)
+    with gfs.PageCache(cfg) as cache:
+        fid = cache.open(path)
+        os.truncate(path, (3 << 20) + 100)
+        _say(f"shrunk file, ra_pages={ra_pages}")
+        res = runner.run_list(cache, fid, offs, page, configs.CONSUMER_CHECKSUM)
+        st = cache.stats()
+        assert st["io_errors"] > 0 and st["timeouts"] == 0
+        for b in range(12):                                   # pages 0..47: below the cut
+            assert int(res.status[b]) == 4 * page, b
+            want = sum(odata.checksum_of(odata.delivered(src, int(o), page)) for o in offs[b]) & ((1 << 64) - 1)
+            assert int(res.out[b]) == want, b
+        for b in range(12, 16):                               # page 48 holds the cut
+            assert int(res.status[b]) == -5, (b, int(res.status[b]))
+        cache.close_file(fid)
+        cache.reset()
+        fid2 = cache.open(src)
+        res2 = runner.run_list(cache, fid2, offs, page, configs.CONSUMER_CHECKSUM)
+        want2 = odata.block_checksums(src, offs, page)
+        np.testing.assert_array_equal(res2.out, want2)
+        assert cache.stats()["io_errors"] == 0
