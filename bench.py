@@ -352,6 +352,59 @@ def bench_serve(args, torch) -> int:
     return 0
 
 
+def bench_diagnostics(args, torch) -> int:
+    """Analogs of the paper's motivation study (Sec. 3). (a) Host queue balance: the C2 reads
+    without readahead served by 4 host threads from a shared ring (any idle thread takes the
+    next request) and from GPUfs's partitioned queue (a block posts into the slot of its block
+    id, thread i polls its own quarter of the 1024 slots): throughput, each thread's polls
+    before its first request, and requests per thread. (b) Page size: every block reads its
+    own 1 MiB of a 1 GiB file in 64 KiB reads, readahead off, pages 4 KiB .. 1 MiB."""
+    import numpy as np
+
+    from paper_2109_05366_amd import gfs, runner
+    from workloads import configs
+    ddir = args.data_dir or os.environ.get("GFS_DATA_DIR") or configs.data_dir()
+    wl = configs.get("c2")
+    path = configs.ensure_file(wl.file, ddir)
+    queue = {}
+    for name, backend in (("shared_ring", gfs.GFS_IO_PREAD), ("partitioned", gfs.GFS_IO_PREAD_PARTITIONED)):
+        cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=0, host_threads=4, rpc_slots=1024,
+                                 timeout_s=60)
+        cfg.io_backend = backend
+        with gfs.PageCache(cfg) as cache:
+            fid = cache.open(path)
+            reader = runner.ListReader(wl.offsets, wl.read_size, wl.consumer, wl.threads)
+            wall, kms, st = run_steps(torch, cache, fid, reader, max(args.steps // 3, 1), 0)
+        queue[name] = {"GBps": round(wl.delivered_bytes / (np.mean(kms) * 1e-3) / 1e9, 3),
+                       "polls_before_first_request": st["host_spins"],
+                       "requests_per_thread": st["host_thread_requests"]}
+        log(f"queue {name}: {queue[name]}")
+    f = configs.FileSpec("f4_seed5_1GiB.bin", 5, 1 << 30)
+    fpath = configs.ensure_file(f, ddir)
+    off = configs.chunked_offsets(1024, 16, 64 << 10)
+    pages = {}
+    for page in (4 << 10, 16 << 10, 64 << 10, 256 << 10, 1 << 20):
+        cfg = runner.make_config(page, 256 << 20, ra_cap_bytes=0, host_threads=args.host_threads,
+                                 rpc_slots=args.rpc_slots, timeout_s=60)
+        with gfs.PageCache(cfg) as cache:
+            fid = cache.open(fpath)
+            reader = runner.ListReader(off, 64 << 10, configs.CONSUMER_CHECKSUM, 256)
+            wall, kms, st = run_steps(torch, cache, fid, reader, max(args.steps // 3, 1), 1)
+        pages[f"{page >> 10}KiB"] = round((1 << 30) / (np.mean(kms) * 1e-3) / 1e9, 3)
+        log(f"page {page >> 10} KiB: {pages[f'{page >> 10}KiB']} GB/s")
+    line = {
+        "metric": "diagnostics: host queue balance and page size (GB/s)",
+        "value": queue["shared_ring"]["GBps"], "unit": "GB/s", "n_gpus": 1, "steps": max(args.steps // 3, 1),
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "f4: C2 reads without readahead, 4 host threads, 1024 slots; page sweep on a 1 GiB file",
+                   "data_dir": ddir},
+        "queue": queue, "page_size_GBps": pages,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def bench_hits(args, torch) -> int:
     """The kernel's own HBM-bound path: a 1 GiB file held in a 2 GiB cache of 64 KiB pages,
     read in 64 KiB pieces after one cold pass, every read a hit (lookup, pin, copy-out, unpin,
@@ -473,7 +526,7 @@ def main() -> int:
     ap.add_argument("--rpc-slots", type=int, default=64)
     ap.add_argument("--no-ra-off", action="store_true", help="skip the readahead-off comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3a", "c3b", "c3c", "c4", "c5", "f3", "hit"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3a", "c3b", "c3c", "c4", "c5", "f3", "f4", "hit"])
     ap.add_argument("--no-hit-path", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="c4: search page size, cap and blocks per file")
     ap.add_argument("--rates", default="200", help="c5: comma-separated arrival rates per second")
@@ -505,6 +558,8 @@ def main() -> int:
         return bench_small_pages(args, torch)
     if args.workload == "hit":
         return bench_hits(args, torch)
+    if args.workload == "f4":
+        return bench_diagnostics(args, torch)
     wl = configs.get(args.workload)
     ddir = args.data_dir or os.environ.get("GFS_DATA_DIR") or configs.data_dir()
     log(f"workload {wl.name}: file {wl.file.size >> 20} MiB, cache {wl.cache_bytes >> 20} MiB, "

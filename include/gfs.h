@@ -51,7 +51,10 @@ extern "C" {
 #define GFS_ADV_RANDOM 1
 
 /* host read backends */
-#define GFS_IO_PREAD 0
+#define GFS_IO_PREAD 0              /* any idle host thread takes the next request (ring order) */
+#define GFS_IO_PREAD_PARTITIONED 1  /* GPUfs's queue (Sec. 3.4): a block posts into the slot of its
+                                       block id (mod rpc_slots); host thread i serves only its own
+                                       contiguous range of slots, one request at a time */
 
 /* cache policies */
 #define GFS_POLICY_SHARED 0    /* readahead windows into the shared page cache, global clock */
@@ -73,7 +76,7 @@ typedef struct gfs_config {
   uint64_t ra_cap_bytes;         /* largest window; 0 switches readahead off (demand paging) */
   uint32_t host_threads;         /* host I/O threads polling the request ring, 1..64 */
   uint32_t rpc_slots;            /* request ring slots (each has its own staging buffer), 1..4096 */
-  uint32_t io_backend;           /* GFS_IO_PREAD */
+  uint32_t io_backend;           /* GFS_IO_PREAD or GFS_IO_PREAD_PARTITIONED */
   uint32_t o_direct;             /* GFS_DIRECT_* */
   uint32_t trace_level;          /* 0 off, 1 policy events, 2 also hits/joins */
   uint32_t trace_capacity;       /* events kept in the device trace ring (32 B each) */
@@ -181,6 +184,7 @@ typedef struct gfs_stats {
   uint64_t host_spins[64];    /* per host thread: polls of the ring before its first request */
   uint32_t host_threads;
   uint32_t direct_io;         /* 1 if the last gfs_open used O_DIRECT */
+  uint64_t host_thread_requests[64];   /* per host thread: requests it started serving */
 } gfs_stats;
 
 /* Snapshot the counters. Call when no kernel using the context is running. */

@@ -815,6 +815,24 @@ __device__ uint32_t reserve_run_small_wave(const gfs_dev* d, uint32_t file, uint
   return n;
 }
 
+/* ------------------------------------------------------------------ ring slots
+ * Shared ring (default): one ticket counter for the whole ring, ticket t uses slot t mod S in
+ * generation t / S + 1. Partitioned (GPUfs's queue): block b always posts into slot b mod S,
+ * whose own counter gives the generation; the ticket is then (generation - 1) * S + slot, so
+ * the same two helpers recover slot and generation. */
+__device__ __forceinline__ void ring_ticket_lane(const gfs_dev* d, uint32_t bid, uint64_t& tk) {
+  if (d->partitioned) {
+    const uint32_t s = bid % d->rpc_slots;
+    tk = fadd64(&d->slot_tail[s], 1) * d->rpc_slots + s;
+  } else {
+    tk = fadd64(&d->g->ring_tail, 1);
+  }
+}
+__device__ __forceinline__ uint32_t ring_slot(const gfs_dev* d, uint32_t, uint64_t tk) {
+  return (uint32_t)(tk % d->rpc_slots);
+}
+__device__ __forceinline__ uint64_t ring_gen(const gfs_dev* d, uint64_t tk) { return tk / d->rpc_slots + 1; }
+
 /* ------------------------------------------------------------------ private policy
  * The paper's design (Sec. 4.1 and Sec. 5.1). A miss takes the file's lock only to reserve
  * the one page in the table; the frame comes from the block's own share of the frames,
@@ -932,9 +950,10 @@ __device__ int miss_private_wave(const gfs_dev* d, uint32_t file, uint64_t p, ui
         const uint64_t off0 = p << d->page_shift;
         uint64_t len = (uint64_t)span << d->page_shift;
         if (off0 + len > fsize) len = fsize - off0;
-        const uint64_t tk = fadd64(&d->g->ring_tail, 1);
-        const uint32_t s = (uint32_t)(tk % d->rpc_slots);
-        const uint64_t gen = tk / d->rpc_slots + 1;
+        uint64_t tk;
+        ring_ticket_lane(d, bid, tk);
+        const uint32_t s = ring_slot(d, bid, tk);
+        const uint64_t gen = ring_gen(d, tk);
         uint32_t nn = 0;
         const uint64_t ts0 = wall_clock64();
         while (ld_acq(&d->slot_free[s]) != gen - 1) {
@@ -1219,9 +1238,9 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       int64_t status = 0;
       uint64_t tk = 0;
       if (l == 0) {
-        tk = fadd64(&d->g->ring_tail, 1);
-        const uint32_t s = (uint32_t)(tk % d->rpc_slots);
-        const uint64_t gen = tk / d->rpc_slots + 1;
+        ring_ticket_lane(d, bid, tk);
+        const uint32_t s = ring_slot(d, bid, tk);
+        const uint64_t gen = ring_gen(d, tk);
         uint32_t nn = 0;
         const uint64_t ts0 = wall_clock64();
         while (ld_acq(&d->slot_free[s]) != gen - 1) {
@@ -1250,8 +1269,8 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       }
       status = __shfl(status, 0, 64);
       tk = __shfl(tk, 0, 64);
-      const uint32_t s = (uint32_t)(tk % d->rpc_slots);
-      const uint64_t gen = tk / d->rpc_slots + 1;
+      const uint32_t s = ring_slot(d, bid, tk);
+      const uint64_t gen = ring_gen(d, tk);
       if (status == 0) {
         /* tell waiting blocks which request fills each frame: (slot + 1) << 40 | gen */
         const uint64_t fill = ((uint64_t)(s + 1) << 40) | (gen & ((1ull << 40) - 1));

@@ -18,6 +18,7 @@
  *   pt[nbuckets*16] u64              hashed page table, 16-entry buckets (128 B)
  *   ffill[nframes]  u64              ring slot and generation filling the frame (0: not yet known)
  *   slot_free[rpc_slots] u64         generation of the last completed use of each ring slot
+ *   slot_tail[rpc_slots] u64         partitioned queue: requests posted into each slot
  *   reqd[rpc_slots]                  64 B: a finished host read, for blocks that help pull it
  *   trace[trace_capacity]            32 B records
  * Frames (cache_bytes) are a separate caller allocation. The ring and staging live in
@@ -196,8 +197,9 @@ typedef struct gfs_dev {
   uint32_t policy;              /* GFS_POLICY_* */
   uint32_t npslots;             /* private slots */
   uint32_t quota;               /* frames per private slot */
-  uint32_t pad32;
+  uint32_t partitioned;         /* 1: a block posts into the slot of its block id */
   uint64_t* slot_free;
+  uint64_t* slot_tail;          /* partitioned queue: requests posted into each slot so far */
   uint64_t* ffill;
   gfs_req_dev* reqd;
   uint32_t* req_frames;

@@ -56,7 +56,7 @@ struct Layout {
   uint64_t quota = 0;              /* private policy: frames per slot */
   uint64_t pbuf_bytes = 0;         /* private policy: all private buffers */
   uint64_t off_globals = 0, off_dev = 0, off_files = 0, off_locks = 0, off_lockq = 0, off_claims = 0, off_pslots = 0, off_names = 0, off_fword = 0,
-           off_ftag = 0, off_pt = 0, off_ffill = 0, off_slot_free = 0, off_reqd = 0, off_trace = 0,
+           off_ftag = 0, off_pt = 0, off_ffill = 0, off_slot_free = 0, off_slot_tail = 0, off_reqd = 0, off_trace = 0,
            meta_bytes = 0;
 };
 
@@ -75,7 +75,8 @@ int make_layout(const gfs_config* c, Layout* L) {
   if (L->ra_cap && (L->ra_init < 1 || L->ra_init > L->ra_cap)) return -EINVAL;
   if (c->host_threads < 1 || c->host_threads > 64) return -EINVAL;
   if (c->rpc_slots < 1 || c->rpc_slots > 4096) return -EINVAL;
-  if (c->io_backend != GFS_IO_PREAD) return -EINVAL;
+  if (c->io_backend != GFS_IO_PREAD && c->io_backend != GFS_IO_PREAD_PARTITIONED) return -EINVAL;
+  if (c->io_backend == GFS_IO_PREAD_PARTITIONED && c->host_threads > c->rpc_slots) return -EINVAL;
   if (c->o_direct > GFS_DIRECT_PREFER) return -EINVAL;
   if (c->trace_level > 2) return -EINVAL;
   if (c->policy == GFS_POLICY_SHARED) {
@@ -110,6 +111,7 @@ int make_layout(const gfs_config* c, Layout* L) {
   L->off_pt = o; o = align_up(o + 8 * GFS_BUCKET_SLOTS * L->nbuckets, kAlign);
   L->off_ffill = o; o = align_up(o + 8 * L->nframes, kAlign);
   L->off_slot_free = o; o = align_up(o + 8ull * c->rpc_slots, kAlign);
+  L->off_slot_tail = o; o = align_up(o + 8ull * c->rpc_slots, kAlign);
   L->off_reqd = o; o = align_up(o + sizeof(gfs_req_dev) * (uint64_t)c->rpc_slots, kAlign);
   L->off_trace = o; o = align_up(o + sizeof(gfs_event) * (uint64_t)c->trace_capacity, kAlign);
   L->meta_bytes = o;
@@ -144,6 +146,7 @@ struct gfs_ctx {
   std::atomic<uint64_t> host_requests{0}, host_bytes{0}, host_read_ns{0}, host_errors{0};
   std::atomic<int64_t> host_last_errno{0};
   std::atomic<uint64_t> spins[64];
+  std::atomic<uint64_t> thread_requests[64];
   bool last_direct = false;
   int clock_khz = 100000;
   /* a request larger than one chunk is split; any I/O thread may read any chunk */
@@ -250,6 +253,54 @@ bool pop_chunk(gfs_ctx* c, gfs_ctx::Chunk* out) {
   return true;
 }
 
+// Partitioned queue (GPUfs's, Sec. 3.4): thread idx serves only the slots
+// [idx*S/N, (idx+1)*S/N), in turn, each request whole by itself.
+void io_thread_partitioned(gfs_ctx* c, int idx) {
+  const uint32_t NS = c->cfg.rpc_slots, N = c->cfg.host_threads;
+  const uint32_t lo = (uint32_t)((uint64_t)idx * NS / N), hi = (uint32_t)((uint64_t)(idx + 1) * NS / N);
+  std::vector<uint64_t> want(hi - lo, 1);   // next generation of each own slot
+  bool first = true;
+  uint64_t spins = 0;
+  uint8_t* bounce = (uint8_t*)aligned_alloc(kDirectAlign, kBounceChunk);
+  if (!bounce) return;
+  while (!c->stop.load(std::memory_order_relaxed)) {
+    bool served = false;
+    for (uint32_t s = lo; s < hi; ++s) {
+      gfs_rpc_slot* rs = &c->ring[s];
+      const uint64_t gen = want[s - lo];
+      if (__atomic_load_n(&rs->req_seq, __ATOMIC_ACQUIRE) != gen) continue;
+      if (first) {
+        c->spins[idx].store(spins, std::memory_order_relaxed);
+        first = false;
+      }
+      c->thread_requests[idx].fetch_add(1, std::memory_order_relaxed);
+      rs->t_claim_ns = now_ns();
+      const uint64_t off = rs->offset, len = rs->length;
+      const uint64_t n = len > c->L.max_req_bytes ? 0 : (len + kBounceChunk - 1) / kBounceChunk;
+      gfs_ctx::Track& tr = c->track[s];
+      tr.total.store(0, std::memory_order_relaxed);
+      tr.err.store(n == 0 && len ? -EINVAL : 0, std::memory_order_relaxed);
+      tr.remaining.store(n ? (uint32_t)n : 1u, std::memory_order_release);
+      if (n == 0) {
+        run_chunk(c, {s, gen, off, 0, 0}, bounce);
+      } else {
+        for (uint64_t i = 0; i < n; ++i) {
+          const uint64_t o = i * kBounceChunk;
+          run_chunk(c, {s, gen, off + o, (len - o) < kBounceChunk ? (len - o) : kBounceChunk, o}, bounce);
+        }
+      }
+      want[s - lo] = gen + 1;
+      served = true;
+    }
+    if (!served) {
+      ++spins;
+      if (spins < (1u << 20)) cpu_relax();
+      else usleep(50);
+    }
+  }
+  free(bounce);
+}
+
 // One host I/O thread: read queued chunks when there are any; otherwise hold the next ring
 // ticket, and when the device publishes that ticket's request split it into chunks, queue
 // all but the first, and read the first.
@@ -286,6 +337,7 @@ void io_thread(gfs_ctx* c, int idx) {
       c->spins[idx].store(idle_spins, std::memory_order_relaxed);
       first = false;
     }
+    c->thread_requests[idx].fetch_add(1, std::memory_order_relaxed);
     rs->t_claim_ns = now_ns();
     const uint64_t off = rs->offset, len = rs->length;
     const uint64_t n = len > c->L.max_req_bytes ? 0 : (len + kBounceChunk - 1) / kBounceChunk;
@@ -309,7 +361,9 @@ void io_thread(gfs_ctx* c, int idx) {
 void start_threads(gfs_ctx* c) {
   c->stop.store(false);
   c->head.store(0);
-  for (uint32_t i = 0; i < c->cfg.host_threads; ++i) c->threads.emplace_back(io_thread, c, (int)i);
+  for (uint32_t i = 0; i < c->cfg.host_threads; ++i)
+    c->threads.emplace_back(c->cfg.io_backend == GFS_IO_PREAD_PARTITIONED ? io_thread_partitioned : io_thread, c,
+                            (int)i);
 }
 
 void stop_threads(gfs_ctx* c) {
@@ -394,6 +448,7 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   gfs_ctx* c = new (std::nothrow) gfs_ctx();
   if (!c) return -ENOMEM;
   for (auto& s : c->spins) s.store(0);
+  for (auto& s : c->thread_requests) s.store(0);
   c->cfg = *cfg;
   c->L = L;
   c->stream = (hipStream_t)hip_stream;
@@ -472,6 +527,8 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   h.ftag = (uint64_t*)(c->meta + L.off_ftag);
   h.pt = (uint64_t*)(c->meta + L.off_pt);
   h.slot_free = (uint64_t*)(c->meta + L.off_slot_free);
+  h.slot_tail = (uint64_t*)(c->meta + L.off_slot_tail);
+  h.partitioned = cfg->io_backend == GFS_IO_PREAD_PARTITIONED ? 1u : 0u;
   h.ffill = (uint64_t*)(c->meta + L.off_ffill);
   h.reqd = (gfs_req_dev*)(c->meta + L.off_reqd);
   h.trace = c->meta + L.off_trace;
@@ -642,6 +699,7 @@ int gfs_stats_read(gfs_ctx* c, gfs_stats* out) {
   s.host_errors = c->host_errors.load();
   s.host_last_errno = (uint64_t)c->host_last_errno.load();
   for (uint32_t i = 0; i < 64; ++i) s.host_spins[i] = c->spins[i].load();
+  for (uint32_t i = 0; i < 64; ++i) s.host_thread_requests[i] = c->thread_requests[i].load();
   s.host_threads = c->cfg.host_threads;
   s.direct_io = c->last_direct ? 1 : 0;
   *out = s;

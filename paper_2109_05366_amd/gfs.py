@@ -20,6 +20,7 @@ GFS_O_RDONLY = 0
 GFS_ADV_NORMAL, GFS_ADV_RANDOM, GFS_ADV_SEQUENTIAL = 0, 1, 2
 GFS_DIRECT_OFF, GFS_DIRECT_ON, GFS_DIRECT_PREFER = 0, 1, 2
 GFS_POLICY_SHARED, GFS_POLICY_PRIVATE = 0, 1
+GFS_IO_PREAD, GFS_IO_PREAD_PARTITIONED = 0, 1
 GFS_MAX_WINDOW_PAGES = 1024
 
 EV_HIT, EV_JOIN, EV_MISS, EV_HAND, EV_ALLOC, EV_REQ, EV_NOFRAME = 1, 2, 3, 4, 5, 6, 7
@@ -49,7 +50,8 @@ _STAT_U64 = ["hits", "joins", "misses", "ra_pages", "fetched_pages", "evictions"
 
 class gfs_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in _STAT_U64] + [
-        ("host_spins", C.c_uint64 * 64), ("host_threads", C.c_uint32), ("direct_io", C.c_uint32)]
+        ("host_spins", C.c_uint64 * 64), ("host_threads", C.c_uint32), ("direct_io", C.c_uint32),
+        ("host_thread_requests", C.c_uint64 * 64)]
 
 
 UNIT_DTYPE = np.dtype([("file", "<u4"), ("out", "<u4"), ("offset", "<u8"), ("size", "<u8")])
@@ -167,6 +169,7 @@ def gfs_stats_read(ctx: int) -> Dict[str, object]:
     out: Dict[str, object] = {n: int(getattr(s, n)) for n in _STAT_U64}
     out["host_threads"] = int(s.host_threads)
     out["host_spins"] = [int(x) for x in s.host_spins[: s.host_threads]]
+    out["host_thread_requests"] = [int(x) for x in s.host_thread_requests[: s.host_threads]]
     out["direct_io"] = int(s.direct_io)
     return out
 

@@ -231,3 +231,22 @@ def test_file_shrunk_under_the_cache_reports_eio(ra_pages, data_dir, cuda, tmp_p
         want2 = odata.block_checksums(src, offs, page)
         np.testing.assert_array_equal(res2.out, want2)
         assert cache.stats()["io_errors"] == 0
+
+
+@pytest.mark.parametrize("name", ["c2_small", "c3c_small"])
+def test_partitioned_host_queue(name, data_dir, cuda):
+    """GPUfs's partitioned request queue (a block posts into the slot of its block id, each
+    host thread serves its own range of slots) delivers the same bytes."""
+    wl = configs.get(name)
+    path = configs.ensure_file(wl.file, data_dir)
+    exp_out, exp_deliv = expected(wl, path)
+    cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=8 * wl.page_size, host_threads=4,
+                             rpc_slots=16, timeout_s=20)
+    cfg.io_backend = gfs.GFS_IO_PREAD_PARTITIONED
+    with gfs.PageCache(cfg) as cache:
+        fid = cache.open(path)
+        res = runner.run_list(cache, fid, wl.offsets, wl.read_size, wl.consumer)
+        st = cache.stats()
+    np.testing.assert_array_equal(res.status, exp_deliv)
+    np.testing.assert_array_equal(res.out, exp_out)
+    assert sum(st["host_thread_requests"]) == st["requests"]

@@ -57,7 +57,7 @@ def test_device_bytes_layout_scales_with_frames():
     ("cache_bytes", 0), ("cache_bytes", 100 << 10), ("cache_bytes", (64 << 10) * 63),
     ("streams_per_file", 0), ("streams_per_file", 9), ("ra_cap_bytes", 100),
     ("ra_cap_bytes", (64 << 10) * 1025), ("host_threads", 0), ("host_threads", 65),
-    ("rpc_slots", 0), ("o_direct", 3), ("trace_level", 3), ("io_backend", 1),
+    ("rpc_slots", 0), ("o_direct", 3), ("trace_level", 3), ("io_backend", 2), ("policy", 2),
 ])
 def test_invalid_configs_rejected(field, value):
     cfg = gfs.gfs_config_default()
@@ -81,3 +81,19 @@ def test_null_arguments_rejected_without_gpu():
     assert lib.gfs_open(None, b"x", 0, None) == -errno.EINVAL
     assert lib.gfs_shutdown(None) == -errno.EINVAL
     assert lib.gfs_device_handle(None) is None
+
+
+def test_policy_and_queue_limits():
+    P = 64 << 10
+    ok = gfs.gfs_config_default(policy=gfs.GFS_POLICY_PRIVATE, private_slots=64, cache_bytes=64 * P)
+    f, _ = gfs.gfs_device_bytes(ok)
+    assert f == 64 * P + 64 * ok.ra_cap_bytes          # the private buffers live with the frames
+    for bad in (dict(private_slots=0), dict(private_slots=65, cache_bytes=64 * P)):   # quota < 1 frame
+        cfg = gfs.gfs_config_default(policy=gfs.GFS_POLICY_PRIVATE, **bad)
+        with pytest.raises(OSError):
+            gfs.gfs_device_bytes(cfg)
+    cfg = gfs.gfs_config_default(io_backend=gfs.GFS_IO_PREAD_PARTITIONED, host_threads=8, rpc_slots=4)
+    with pytest.raises(OSError):                        # every host thread needs its own slots
+        gfs.gfs_device_bytes(cfg)
+    gfs.gfs_device_bytes(gfs.gfs_config_default(io_backend=gfs.GFS_IO_PREAD_PARTITIONED, host_threads=4,
+                                                rpc_slots=64))
