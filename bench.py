@@ -377,7 +377,10 @@ def bench_diagnostics(args, torch) -> int:
             wall, kms, st = run_steps(torch, cache, fid, reader, max(args.steps // 3, 1), 0)
         queue[name] = {"GBps": round(wl.delivered_bytes / (np.mean(kms) * 1e-3) / 1e9, 3),
                        "polls_before_first_request": st["host_spins"],
-                       "requests_per_thread": st["host_thread_requests"]}
+                       "requests_per_thread": st["host_thread_requests"],
+                       # device side, per request: waiting for a free ring slot, then for the host
+                       "slot_wait_us": round(st["t_slot_ns"] / max(st["requests"], 1) / 1e3, 2),
+                       "host_wait_us": round(st["t_host_ns"] / max(st["requests"], 1) / 1e3, 2)}
         log(f"queue {name}: {queue[name]}")
     f = configs.FileSpec("f4_seed5_1GiB.bin", 5, 1 << 30)
     fpath = configs.ensure_file(f, ddir)

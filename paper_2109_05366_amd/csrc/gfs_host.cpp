@@ -141,7 +141,7 @@ struct gfs_ctx {
   uint8_t* staging = nullptr;     // host address (pinned, mapped)
   HostFile files[GFS_MAX_FILES];
   std::vector<std::thread> threads;
-  std::atomic<uint64_t> head{0};
+  std::unique_ptr<std::atomic<uint64_t>[]> claimed;   // per ring slot: last generation a thread took
   std::atomic<bool> stop{false};
   std::atomic<uint64_t> host_requests{0}, host_bytes{0}, host_read_ns{0}, host_errors{0};
   std::atomic<int64_t> host_last_errno{0};
@@ -301,14 +301,17 @@ void io_thread_partitioned(gfs_ctx* c, int idx) {
   free(bounce);
 }
 
-// One host I/O thread: read queued chunks when there are any; otherwise hold the next ring
-// ticket, and when the device publishes that ticket's request split it into chunks, queue
-// all but the first, and read the first.
+// One host I/O thread: read queued chunks when there are any; otherwise look over the ring
+// for a posted request that no thread has taken (starting after the slot it served last, so
+// every slot is visited in turn), take it with a compare-and-swap on the slot's claimed
+// generation, split it into chunks, queue all but the first, and read the first. Taking
+// any posted request, rather than waiting on the next ticket in ring order, keeps a thread
+// from idling behind a slot whose block has not posted yet.
 void io_thread(gfs_ctx* c, int idx) {
   const uint32_t NS = c->cfg.rpc_slots;
   bool first = true;
-  bool holding = false;
-  uint64_t h = 0, spins = 0, idle_spins = 0;
+  uint64_t spins = 0;
+  uint32_t pos = (uint32_t)((uint64_t)idx * NS / c->cfg.host_threads);
   uint8_t* bounce = (uint8_t*)aligned_alloc(kDirectAlign, kBounceChunk);
   if (!bounce) return;
   gfs_ctx::Chunk ch;
@@ -317,27 +320,32 @@ void io_thread(gfs_ctx* c, int idx) {
       run_chunk(c, ch, bounce);
       continue;
     }
-    if (!holding) {
-      h = c->head.fetch_add(1, std::memory_order_relaxed);
-      holding = true;
-      spins = 0;
+    int32_t got = -1;
+    uint64_t gen = 0;
+    for (uint32_t k = 0; k < NS && got < 0; ++k) {
+      const uint32_t s = pos + k < NS ? pos + k : pos + k - NS;
+      const uint64_t g = __atomic_load_n(&c->ring[s].req_seq, __ATOMIC_ACQUIRE);
+      uint64_t prev = g - 1;
+      if (g != 0 && c->claimed[s].load(std::memory_order_relaxed) == prev &&
+          c->claimed[s].compare_exchange_strong(prev, g, std::memory_order_acq_rel)) {
+        got = (int32_t)s;
+        gen = g;
+      }
     }
-    const uint32_t s = (uint32_t)(h % NS);
-    const uint64_t gen = h / NS + 1;
-    gfs_rpc_slot* rs = &c->ring[s];
-    if (__atomic_load_n(&rs->req_seq, __ATOMIC_ACQUIRE) != gen) {
+    if (got < 0) {
       ++spins;
       if (spins < (1u << 20)) cpu_relax();
       else usleep(50);   // long idle: stop burning the core, at some wake-up latency
       continue;
     }
-    holding = false;
-    idle_spins += spins;
+    const uint32_t s = (uint32_t)got;
+    pos = s + 1 < NS ? s + 1 : 0;
     if (first) {
-      c->spins[idx].store(idle_spins, std::memory_order_relaxed);
+      c->spins[idx].store(spins, std::memory_order_relaxed);
       first = false;
     }
     c->thread_requests[idx].fetch_add(1, std::memory_order_relaxed);
+    gfs_rpc_slot* rs = &c->ring[s];
     rs->t_claim_ns = now_ns();
     const uint64_t off = rs->offset, len = rs->length;
     const uint64_t n = len > c->L.max_req_bytes ? 0 : (len + kBounceChunk - 1) / kBounceChunk;
@@ -360,7 +368,7 @@ void io_thread(gfs_ctx* c, int idx) {
 
 void start_threads(gfs_ctx* c) {
   c->stop.store(false);
-  c->head.store(0);
+  for (uint32_t i = 0; i < c->cfg.rpc_slots; ++i) c->claimed[i].store(0);
   for (uint32_t i = 0; i < c->cfg.host_threads; ++i)
     c->threads.emplace_back(c->cfg.io_backend == GFS_IO_PREAD_PARTITIONED ? io_thread_partitioned : io_thread, c,
                             (int)i);
@@ -546,7 +554,8 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   }
   memset(c->ring, 0, ring_bytes);
   c->track.reset(new (std::nothrow) gfs_ctx::Track[cfg->rpc_slots]);
-  if (!c->track) {
+  c->claimed.reset(new (std::nothrow) std::atomic<uint64_t>[cfg->rpc_slots]);
+  if (!c->track || !c->claimed) {
     (void)hipHostFree(c->staging);
     (void)hipHostFree(c->ring);
     delete c;

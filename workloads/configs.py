@@ -215,5 +215,6 @@ def ensure_file(spec: FileSpec, directory: Optional[str] = None, threads: int = 
     if os.path.exists(path) and os.path.getsize(path) == spec.size:
         return path
     gen = build_generator()
+    os.makedirs(d, exist_ok=True)
     subprocess.check_call([gen, path, str(spec.seed), str(spec.size), str(threads)])
     return path
