@@ -84,11 +84,17 @@ typedef struct gfs_config {
   uint32_t policy;               /* GFS_POLICY_* */
   uint32_t private_slots;        /* GFS_POLICY_PRIVATE: per-block slots (private buffer + frame
                                     share), at least the blocks resident at once; 1..65536 */
+  uint32_t io_chunk_bytes;       /* a host request is read in pieces of this size, each by
+                                    whichever host thread is free (so one request keeps several
+                                    reads in flight); a multiple of 4 KiB, 64 KiB .. 64 MiB; each
+                                    host thread holds one bounce buffer of this size for
+                                    O_DIRECT reads */
+  uint32_t reserved0;            /* must be 0 */
 } gfs_config;
 
 /* Fill *cfg with defaults: 64 KiB pages, 256 MiB cache, readahead 4 pages growing to
- * 16 MiB, 8 streams per file, 8 host threads, 64 slots, O_DIRECT preferred, trace off,
- * shared policy (512 private slots if the private policy is chosen).
+ * 16 MiB, 8 streams per file, 8 host threads, 64 slots, 2 MiB host read pieces, O_DIRECT
+ * preferred, trace off, shared policy (512 private slots if the private policy is chosen).
  *
  * GFS_POLICY_PRIVATE: a miss that the block's private buffer cannot serve asks the host for
  * the page plus ra_cap_bytes that follow it (PREFETCH_SIZE, static); the page goes into the

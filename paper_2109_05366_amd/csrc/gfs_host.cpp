@@ -3,8 +3,8 @@
 // CPU-GPU request queue and read the file for the GPU; Sec. 4.1: the host reads the whole
 // requested span, and the GPU side places every page of it in the cache).
 //
-// Differences from the paper's host side, on purpose: any idle host thread takes the next
-// request in ring order (the paper's per-thread slot partition left threads idle, Sec. 3.4);
+// Differences from the paper's host side, on purpose: any idle host thread takes any posted
+// request (the paper's per-thread slot partition left threads idle, Sec. 3.4);
 // one read covers a whole readahead span instead of one page per read; the data is read
 // straight into pinned staging that the GPU pulls from, so the host issues no copy calls.
 #include <errno.h>
@@ -79,6 +79,9 @@ int make_layout(const gfs_config* c, Layout* L) {
   if (c->io_backend == GFS_IO_PREAD_PARTITIONED && c->host_threads > c->rpc_slots) return -EINVAL;
   if (c->o_direct > GFS_DIRECT_PREFER) return -EINVAL;
   if (c->trace_level > 2) return -EINVAL;
+  if (c->io_chunk_bytes % kDirectAlign || c->io_chunk_bytes < (64u << 10) || c->io_chunk_bytes > (64u << 20) ||
+      c->reserved0)
+    return -EINVAL;
   if (c->policy == GFS_POLICY_SHARED) {
     L->max_req_pages = L->ra_cap ? L->ra_cap : 1;
   } else if (c->policy == GFS_POLICY_PRIVATE) {
@@ -170,13 +173,12 @@ struct gfs_ctx {
 
 namespace {
 
-constexpr uint64_t kBounceChunk = 2ull << 20;
-
 // Read file bytes [off, off+len) into dst (pinned staging). Returns bytes read (short only
 // at end of file) or -errno. Direct reads cannot target the GPU driver's pinned pages (the
 // kernel refuses to pin them for DMA, EFAULT), so they go through the thread's aligned
 // bounce buffer in chunks and are copied into staging; buffered reads go straight in.
-int64_t read_span(int fd, bool direct, uint8_t* dst, uint64_t off, uint64_t len, uint8_t* bounce) {
+int64_t read_span(int fd, bool direct, uint8_t* dst, uint64_t off, uint64_t len, uint8_t* bounce,
+                  uint64_t chunk) {
   uint64_t done = 0;
   if (!direct) {
     while (done < len) {
@@ -191,7 +193,7 @@ int64_t read_span(int fd, bool direct, uint8_t* dst, uint64_t off, uint64_t len,
     return (int64_t)done;
   }
   while (done < len) {
-    const uint64_t want = len - done < kBounceChunk ? align_up(len - done, kDirectAlign) : kBounceChunk;
+    const uint64_t want = len - done < chunk ? align_up(len - done, kDirectAlign) : chunk;
     ssize_t r;
     do {
       r = pread(fd, bounce, want, (off_t)(off + done));
@@ -223,7 +225,7 @@ void run_chunk(gfs_ctx* c, const gfs_ctx::Chunk& ch, uint8_t* bounce) {
   } else {
     const uint64_t t0 = now_ns();
     r = read_span(fd, hf->direct, c->staging + (uint64_t)ch.slot * c->L.max_req_bytes + ch.dst,
-                  ch.off, ch.len, bounce);
+                  ch.off, ch.len, bounce, c->cfg.io_chunk_bytes);
     c->host_read_ns.fetch_add(now_ns() - t0, std::memory_order_relaxed);
   }
   if (r < 0) {
@@ -261,7 +263,8 @@ void io_thread_partitioned(gfs_ctx* c, int idx) {
   std::vector<uint64_t> want(hi - lo, 1);   // next generation of each own slot
   bool first = true;
   uint64_t spins = 0;
-  uint8_t* bounce = (uint8_t*)aligned_alloc(kDirectAlign, kBounceChunk);
+  const uint64_t chunk = c->cfg.io_chunk_bytes;
+  uint8_t* bounce = (uint8_t*)aligned_alloc(kDirectAlign, chunk);
   if (!bounce) return;
   while (!c->stop.load(std::memory_order_relaxed)) {
     bool served = false;
@@ -276,7 +279,7 @@ void io_thread_partitioned(gfs_ctx* c, int idx) {
       c->thread_requests[idx].fetch_add(1, std::memory_order_relaxed);
       rs->t_claim_ns = now_ns();
       const uint64_t off = rs->offset, len = rs->length;
-      const uint64_t n = len > c->L.max_req_bytes ? 0 : (len + kBounceChunk - 1) / kBounceChunk;
+      const uint64_t n = len > c->L.max_req_bytes ? 0 : (len + chunk - 1) / chunk;
       gfs_ctx::Track& tr = c->track[s];
       tr.total.store(0, std::memory_order_relaxed);
       tr.err.store(n == 0 && len ? -EINVAL : 0, std::memory_order_relaxed);
@@ -285,8 +288,8 @@ void io_thread_partitioned(gfs_ctx* c, int idx) {
         run_chunk(c, {s, gen, off, 0, 0}, bounce);
       } else {
         for (uint64_t i = 0; i < n; ++i) {
-          const uint64_t o = i * kBounceChunk;
-          run_chunk(c, {s, gen, off + o, (len - o) < kBounceChunk ? (len - o) : kBounceChunk, o}, bounce);
+          const uint64_t o = i * chunk;
+          run_chunk(c, {s, gen, off + o, (len - o) < chunk ? (len - o) : chunk, o}, bounce);
         }
       }
       want[s - lo] = gen + 1;
@@ -312,7 +315,8 @@ void io_thread(gfs_ctx* c, int idx) {
   bool first = true;
   uint64_t spins = 0;
   uint32_t pos = (uint32_t)((uint64_t)idx * NS / c->cfg.host_threads);
-  uint8_t* bounce = (uint8_t*)aligned_alloc(kDirectAlign, kBounceChunk);
+  const uint64_t chunk = c->cfg.io_chunk_bytes;
+  uint8_t* bounce = (uint8_t*)aligned_alloc(kDirectAlign, chunk);
   if (!bounce) return;
   gfs_ctx::Chunk ch;
   while (!c->stop.load(std::memory_order_relaxed)) {
@@ -348,7 +352,7 @@ void io_thread(gfs_ctx* c, int idx) {
     gfs_rpc_slot* rs = &c->ring[s];
     rs->t_claim_ns = now_ns();
     const uint64_t off = rs->offset, len = rs->length;
-    const uint64_t n = len > c->L.max_req_bytes ? 0 : (len + kBounceChunk - 1) / kBounceChunk;
+    const uint64_t n = len > c->L.max_req_bytes ? 0 : (len + chunk - 1) / chunk;
     gfs_ctx::Track& tr = c->track[s];
     tr.total.store(0, std::memory_order_relaxed);
     tr.err.store(n == 0 && len ? -EINVAL : 0, std::memory_order_relaxed);
@@ -356,12 +360,12 @@ void io_thread(gfs_ctx* c, int idx) {
     if (n > 1) {
       std::lock_guard<std::mutex> g(c->qmu);
       for (uint64_t i = 1; i < n; ++i) {
-        const uint64_t o = i * kBounceChunk;
-        c->queue.push_back({s, gen, off + o, (len - o) < kBounceChunk ? (len - o) : kBounceChunk, o});
+        const uint64_t o = i * chunk;
+        c->queue.push_back({s, gen, off + o, (len - o) < chunk ? (len - o) : chunk, o});
       }
       c->queued.fetch_add((uint32_t)(n - 1), std::memory_order_relaxed);
     }
-    run_chunk(c, {s, gen, off, n ? (len < kBounceChunk ? len : kBounceChunk) : 0, 0}, bounce);
+    run_chunk(c, {s, gen, off, n ? (len < chunk ? len : chunk) : 0, 0}, bounce);
   }
   free(bounce);
 }
@@ -435,6 +439,7 @@ void gfs_config_default(gfs_config* cfg) {
   cfg->wait_timeout_ns = 0;
   cfg->policy = GFS_POLICY_SHARED;
   cfg->private_slots = 512;
+  cfg->io_chunk_bytes = 2u << 20;
 }
 
 int gfs_device_bytes(const gfs_config* cfg, size_t* frames_bytes, size_t* meta_bytes) {

@@ -36,6 +36,7 @@ class gfs_config(C.Structure):
         ("io_backend", C.c_uint32), ("o_direct", C.c_uint32),
         ("trace_level", C.c_uint32), ("trace_capacity", C.c_uint32),
         ("wait_timeout_ns", C.c_uint64), ("policy", C.c_uint32), ("private_slots", C.c_uint32),
+        ("io_chunk_bytes", C.c_uint32), ("reserved0", C.c_uint32),
     ]
 
 

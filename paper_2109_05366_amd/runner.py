@@ -13,7 +13,7 @@ def make_config(page_size: int, cache_bytes: int, ra_cap_bytes: int = 16 << 20, 
                 streams: int = 8, host_threads: int = 8, rpc_slots: int = 64,
                 o_direct: int = gfs.GFS_DIRECT_PREFER, trace_level: int = 0, trace_capacity: int = 0,
                 timeout_s: float = 30.0, policy: int = gfs.GFS_POLICY_SHARED,
-                private_slots: int = 512) -> gfs.gfs_config:
+                private_slots: int = 512, io_chunk_bytes: int = 2 << 20) -> gfs.gfs_config:
     cap_pages = min(ra_cap_bytes // page_size, gfs.GFS_MAX_WINDOW_PAGES)
     init = min(ra_init_pages, cap_pages) if cap_pages else 0
     return gfs.gfs_config_default(
@@ -21,7 +21,7 @@ def make_config(page_size: int, cache_bytes: int, ra_cap_bytes: int = 16 << 20, 
         ra_init_bytes=init * page_size, streams_per_file=streams, host_threads=host_threads,
         rpc_slots=rpc_slots, o_direct=o_direct, trace_level=trace_level,
         trace_capacity=trace_capacity, wait_timeout_ns=int(timeout_s * 1e9), policy=policy,
-        private_slots=private_slots)
+        private_slots=private_slots, io_chunk_bytes=io_chunk_bytes)
 
 
 @dataclasses.dataclass

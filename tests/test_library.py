@@ -37,8 +37,9 @@ def test_config_default_values():
     assert cfg.page_size == 64 << 10 and cfg.cache_bytes == 256 << 20
     assert cfg.ra_init_bytes == 4 * cfg.page_size and cfg.ra_cap_bytes == 16 << 20
     assert cfg.streams_per_file == 8 and cfg.host_threads == 8 and cfg.rpc_slots == 64
-    assert ctypes.sizeof(gfs.gfs_config) == 80
+    assert ctypes.sizeof(gfs.gfs_config) == 88
     assert cfg.policy == gfs.GFS_POLICY_SHARED and cfg.private_slots == 512
+    assert cfg.io_chunk_bytes == 2 << 20
     assert gfs.EVENT_DTYPE.itemsize == 32
 
 
@@ -97,3 +98,9 @@ def test_policy_and_queue_limits():
         gfs.gfs_device_bytes(cfg)
     gfs.gfs_device_bytes(gfs.gfs_config_default(io_backend=gfs.GFS_IO_PREAD_PARTITIONED, host_threads=4,
                                                 rpc_slots=64))
+    for chunk in (64 << 10, 8 << 20, 64 << 20):
+        gfs.gfs_device_bytes(gfs.gfs_config_default(io_chunk_bytes=chunk))
+    for bad in (dict(io_chunk_bytes=0), dict(io_chunk_bytes=(1 << 20) + 512), dict(io_chunk_bytes=32 << 10),
+                dict(io_chunk_bytes=128 << 20), dict(reserved0=1)):
+        with pytest.raises(OSError):
+            gfs.gfs_device_bytes(gfs.gfs_config_default(**bad))
