@@ -68,6 +68,11 @@ def recorded_traffic():
     return int(fields["traffic_bytes_per_launch"]), TRAFFIC_SUMMARY
 
 
+def _cap_mib(args, default: int = 16) -> int:
+    """--ra-cap-mib, or the default cap of workloads with no cap of their own (c4, c5)."""
+    return args.ra_cap_mib if args.ra_cap_mib is not None else default
+
+
 def storage_peak(path: str, threads: int = 16, chunk: int = 4 << 20, limit: int = 8 << 30) -> float:
     """O_DIRECT (if available) sequential read of the file with `threads` readers (16 reads
     of 4 MiB in flight), GB/s."""
@@ -258,8 +263,7 @@ def bench_batch(args, torch) -> int:
         "runs_GBps": [round(x, 3) for x in runs],
         "readahead_off_GBps": round(off, 3), "readahead_speedup": round(value / off, 3),
         "one_launch_per_file_GBps": round(plain, 3), "batched_speedup": round(value / plain, 3),
-        "storage_peak_GBps": round(nvme, 3),
-        "storage_peak_samples_GBps": [round(x, 3) for x in nvme_samples], "h2d_peak_GBps": round(h2d, 3),
+        "storage_peak_GBps": round(nvme, 3), "h2d_peak_GBps": round(h2d, 3),
         "io_bound": {"bound": "storage" if nvme < h2d else "h2d", "achieved": round(value, 3),
                      "peak": round(min_peak, 3), "unit": "GB/s", "frac": round(value / min_peak, 3)},
         "autotune_history": history, "parity_sampled_files": small,
@@ -287,7 +291,7 @@ def bench_serve(args, torch) -> int:
     out = []
     for rate in [int(x) for x in args.rates.split(",")]:
         arrivals = manifest.scaled_arrivals(m, rate)
-        cfg = runner.make_config(page, budget, ra_cap_bytes=args.ra_cap_mib << 20, host_threads=args.host_threads,
+        cfg = runner.make_config(page, budget, ra_cap_bytes=_cap_mib(args) << 20, host_threads=args.host_threads,
                                  rpc_slots=args.rpc_slots, timeout_s=60)
         with gfs.PageCache(cfg) as cache:
             ids = [cache.open(p) for p in paths]
@@ -308,7 +312,7 @@ def bench_serve(args, torch) -> int:
     # the plain form: the first 64 requests, all present at the start, served together by
     # the loop (their work overlaps) against one request at a time; cold cache for each
     nsub = min(64, len(files))
-    cfg = runner.make_config(page, budget, ra_cap_bytes=args.ra_cap_mib << 20, host_threads=args.host_threads,
+    cfg = runner.make_config(page, budget, ra_cap_bytes=_cap_mib(args) << 20, host_threads=args.host_threads,
                              rpc_slots=args.rpc_slots, timeout_s=60)
     with gfs.PageCache(cfg) as cache:
         ids = [cache.open(p) for p in paths]
@@ -343,7 +347,7 @@ def bench_serve(args, torch) -> int:
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"c5 scaled: {len(files)} Poisson requests over a {len(sizes)}-file pool "
                                f"({sizes.sum() / 2**30:.1f} GiB), {budget >> 30} GiB cache budget",
-                   "page_KiB": page >> 10, "ra_cap_MiB": args.ra_cap_mib, "chunk_MiB": 1, "data_dir": ddir},
+                   "page_KiB": page >> 10, "ra_cap_MiB": _cap_mib(args), "chunk_MiB": 1, "data_dir": ddir},
         "storage_peak_GBps": round(nvme, 3),
         "rates": [{k: v for k, v in o.items() if k != "recs"} for o in out],
         "first64_together_GBps": round(together, 3), "first64_one_at_a_time_GBps": round(alone, 3),
@@ -525,7 +529,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--data-dir", default=None, help="where the synthetic files live")
-    ap.add_argument("--ra-cap-mib", type=int, default=16)
+    ap.add_argument("--ra-cap-mib", type=int, default=None,
+                    help="readahead cap (default: the workload's own; 16 MiB for c4/c5)")
     ap.add_argument("--host-threads", type=int, default=8)
     ap.add_argument("--rpc-slots", type=int, default=64)
     ap.add_argument("--io-chunk-kib", type=int, default=2048,
@@ -585,7 +590,12 @@ def main() -> int:
     results = {}
     stats = {}
     kernel_ms = {}
-    cap_bytes = (args.ra_cap_kib << 10) if args.ra_cap_kib else (args.ra_cap_mib << 20)
+    if args.ra_cap_kib:
+        cap_bytes = args.ra_cap_kib << 10
+    elif args.ra_cap_mib is not None:
+        cap_bytes = args.ra_cap_mib << 20
+    else:
+        cap_bytes = wl.ra_cap_bytes
     policy = gfs.GFS_POLICY_PRIVATE if args.policy == "private" else gfs.GFS_POLICY_SHARED
     for label, cap in (("ra", cap_bytes), ("no_ra", 0)):
         if label == "no_ra" and args.no_ra_off:
@@ -698,6 +708,7 @@ def main() -> int:
         "readahead_off_GBps": round(results["no_ra"]["GBps"], 3) if "no_ra" in results else None,
         "readahead_speedup": round(value / results["no_ra"]["GBps"], 3) if "no_ra" in results else None,
         "storage_peak_GBps": round(nvme, 3),
+        "storage_peak_samples_GBps": [round(x, 3) for x in nvme_samples],
         "h2d_peak_GBps": round(h2d, 3),
         "frac_of_min_peak": round(value / min_peak, 3),
         "io_bound": {"bound": bound_name, "achieved": round(value, 3), "peak": round(min_peak, 3),
