@@ -375,27 +375,38 @@ __device__ int64_t wait_valid_lane(const gfs_dev* d, uint32_t f, uint64_t t0) {
 /* ------------------------------------------------------------------ per-file miss lock
  * A FIFO ticket lock whose waiters can leave the queue. Blocks get the lock in ticket
  * order, which keeps the readers of a file together (an unfair lock lets a few blocks run
- * far ahead and spreads the misses over the whole file). Each ticket has a queue slot
- * (GFS_LOCK_SLOTS per file, more than the blocks the device can hold at once): the holder
- * passes the lock by writing "granted n" into the slot of ticket n; a waiter whose page
- * appears in the table while it waits (another block's window covered it) writes "left n"
- * into its own slot instead, by compare-and-swap against the grant, and goes to the pin
- * path; the holder skips left tickets. Ticket 0 of a cold file holds the lock at once.
- * Slot values carry the ticket, so stale values of earlier tickets never match. */
-enum { LOCK_OWN = 0, LOCK_LEFT = 1, LOCK_TIMEOUT = 2 };
+ * far ahead and spreads the misses over the whole file). Each ticket has a 64-bit queue
+ * slot (GFS_LOCK_SLOTS per file, more than the blocks the device can hold at once). A
+ * waiter announces the page it missed in its slot ("waiting n, page"); the holder passes
+ * the lock by writing "granted n" into the slot of ticket n. A waiter whose page appears
+ * in the table while it waits (another block's window covered it) writes "left n" instead,
+ * by compare-and-swap against the grant, and goes to the pin path. A holder that has just
+ * claimed a window marks the waiters right behind it whose pages lie in that window
+ * "covered n" (their pages are about to be reserved, so the lock has nothing to decide for
+ * them) and passes the lock to the first ticket that is neither left nor covered. Ticket 0
+ * of a cold file holds the lock at once. The low word of every slot value carries the
+ * ticket, so stale values of earlier tickets never match. */
 
-__device__ __forceinline__ uint32_t lock_granted(uint64_t n) { return ((uint32_t)n << 2) | 1u; }
-__device__ __forceinline__ uint32_t lock_left(uint64_t n) { return ((uint32_t)n << 2) | 2u; }
-__device__ __forceinline__ uint32_t* lock_slot(const gfs_dev* d, uint32_t file, uint64_t n) {
+enum { LOCK_OWN = 0, LOCK_LEFT = 1, LOCK_TIMEOUT = 2, LOCK_COVERED = 3 };
+
+__device__ __forceinline__ uint64_t lock_granted(uint64_t n) { return (uint64_t)(((uint32_t)n << 2) | 1u); }
+__device__ __forceinline__ uint64_t lock_left(uint64_t n) { return (uint64_t)(((uint32_t)n << 2) | 2u); }
+__device__ __forceinline__ uint64_t lock_covered(uint64_t n) { return (uint64_t)(((uint32_t)n << 2) | 3u); }
+__device__ __forceinline__ uint64_t lock_waiting(uint64_t n, uint64_t page) {
+  return (1ull << 63) | (page << 32) | (uint64_t)((uint32_t)n << 2);
+}
+__device__ __forceinline__ uint64_t* lock_slot(const gfs_dev* d, uint32_t file, uint64_t n) {
   return d->lockq + (uint64_t)file * GFS_LOCK_SLOTS + (n & (GFS_LOCK_SLOTS - 1));
 }
 
-/* Lane 0: leave the queue if ticket t is not granted yet; true if it left, false if the
-   lock was granted meanwhile (then the caller holds it). */
+/* Lane 0: leave the queue if ticket t is not granted yet; true if it is out of the queue
+   (left, or marked covered by the holder), false if the lock was granted meanwhile (then
+   the caller holds it). */
 __device__ bool lock_try_leave_lane(const gfs_dev* d, uint32_t file, uint64_t t) {
-  uint32_t* sl = lock_slot(d, file, t);
-  uint32_t v = __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t* sl = lock_slot(d, file, t);
+  uint64_t v = __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   while (v != lock_granted(t)) {
+    if (v == lock_covered(t)) return true;
     if (__hip_atomic_compare_exchange_strong(sl, &v, lock_left(t), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT))
       return true;
@@ -403,15 +414,20 @@ __device__ bool lock_try_leave_lane(const gfs_dev* d, uint32_t file, uint64_t t)
   return false;
 }
 
-/* Wave-collective. Waits for the file's miss lock; while waiting, looks up `key` in the
- * table now and then and leaves the queue if it appeared. Returns LOCK_OWN (ticket set),
- * LOCK_LEFT, or LOCK_TIMEOUT (left the queue after the wait timeout). */
-__device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uint64_t t0, uint64_t& ticket);
-__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket);
+/* Wave-collective. Waits for the file's miss lock for page `page` (key `key`); while
+ * waiting, looks up `key` in the table now and then and leaves the queue if it appeared.
+ * Returns LOCK_OWN (ticket set), LOCK_LEFT, LOCK_COVERED (the holder's window covers the
+ * page) or LOCK_TIMEOUT (left the queue after the wait timeout). */
+__device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uint64_t page, uint64_t t0,
+                              uint64_t& ticket);
+/* Wave-collective: pass the lock on; [lo, hi) is the window the holder has just claimed
+   (lo == hi: none). */
+__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket, uint64_t lo, uint64_t hi);
 
 __device__ int32_t pt_lookup_wave(const gfs_dev* d, uint64_t key);
 
-__device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uint64_t t0, uint64_t& ticket) {
+__device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uint64_t page, uint64_t t0,
+                              uint64_t& ticket) {
   uint64_t t = 0;
   if (lane() == 0)
     t = __hip_atomic_fetch_add(&d->locks[file].next, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -419,22 +435,36 @@ __device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uin
   ticket = t;
   int res = LOCK_OWN;
   if (t != 0) {
-    uint32_t* sl = lock_slot(d, file, t);
-    for (uint32_t n = 0;; ++n) {
+    uint64_t* sl = lock_slot(d, file, t);
+    /* announce the page, unless the grant is already there */
+    int own = 0;
+    if (lane() == 0) {
+      uint64_t v = __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      while (v != lock_granted(t)) {
+        if (__hip_atomic_compare_exchange_strong(sl, &v, lock_waiting(t, page), __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+          break;
+      }
+      own = v == lock_granted(t) ? 1 : 0;
+    }
+    own = __shfl(own, 0, 64);
+    for (uint32_t n = 0; !own; ++n) {
       int st = -1;   /* -1: keep waiting */
-      if (lane() == 0 &&
-          __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == lock_granted(t))
-        st = LOCK_OWN;
+      if (lane() == 0) {
+        const uint64_t v = __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v == lock_granted(t)) st = LOCK_OWN;
+        else if (v == lock_covered(t)) st = LOCK_COVERED;
+      }
       st = __shfl(st, 0, 64);
       if (st < 0 && (n & 7) == 7) {
         /* the page may have been reserved by a window that covers it */
         const bool present = pt_lookup_wave(d, key) >= 0;
         const bool late = expired(d, t0);
         if (present || late) {
-          int left = 0;
-          if (lane() == 0) left = lock_try_leave_lane(d, file, t) ? 1 : 0;
-          left = __shfl(left, 0, 64);
-          st = left ? (present ? LOCK_LEFT : LOCK_TIMEOUT) : LOCK_OWN;
+          int out = 0;
+          if (lane() == 0) out = lock_try_leave_lane(d, file, t) ? 1 : 0;
+          out = __shfl(out, 0, 64);
+          st = out ? (present ? LOCK_LEFT : LOCK_TIMEOUT) : LOCK_OWN;
         }
       }
       if (st >= 0) {
@@ -451,32 +481,49 @@ __device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uin
   return res;
 }
 
-/* Wave-collective: pass the lock to the first later ticket that has not left. One exchange
- * writes the grant into the next ticket's slot; if that waiter had already left (its slot
- * said so), the wave scans the following slots 64 at a time and grants the first ticket
- * that has not left. A waiter leaving concurrently loses its compare-and-swap against the
- * grant and holds the lock instead. */
-__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket) {
+/* Wave-collective: pass the lock to the first later ticket that is still waiting for it
+ * and whose page is outside [lo, hi). Without a window the next ticket gets the grant by
+ * one exchange, and only if that waiter had left does the wave read the following slots,
+ * 64 at a time, for the first ticket still in the queue. With a window the wave reads the
+ * slots first: tickets that left or were marked covered are passed over, waiting tickets
+ * whose announced page lies in the window are marked covered (a compare-and-swap that
+ * loses only to the waiter leaving), and the first other ticket gets the grant; if that
+ * waiter left just before the exchange, the scan goes on after it. A ticket that has not
+ * announced its page yet is granted the lock like any other. */
+__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket, uint64_t lo, uint64_t hi) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   const uint32_t l = lane();
   uint64_t n = ticket + 1;
+  bool look = hi > lo;
   while (true) {
-    uint32_t old = 0;
+    if (look) {
+      const uint64_t nl = n + l;
+      uint64_t* sl = lock_slot(d, file, nl);
+      uint64_t v = ld_rlx(sl);
+      const uint64_t pg = (v >> 32) & 0x7fffffffull;
+      const bool gone = v == lock_left(nl) || v == lock_covered(nl);
+      const bool cov = hi > lo && (v >> 63) && (uint32_t)v == ((uint32_t)nl << 2) && pg >= lo && pg < hi;
+      const uint64_t skip = __ballot(gone || cov);
+      const uint32_t first = ~skip ? (uint32_t)__builtin_ctzll(~skip) : 64u;
+      if (cov && l < first) {
+        /* loses only to the waiter leaving, which takes it out of the queue as well */
+        (void)__hip_atomic_compare_exchange_strong(sl, &v, lock_covered(nl), __ATOMIC_RELAXED,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (first == 64) {
+        n += 64;
+        continue;
+      }
+      n += first;
+    }
+    uint64_t old = 0;
     if (l == 0)
       old = __hip_atomic_exchange(lock_slot(d, file, n), lock_granted(n), __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
     old = __shfl(old, 0, 64);
     if (old != lock_left(n)) return;
-    ++n;
-    while (true) {
-      const uint32_t v = ld_rlx32(lock_slot(d, file, n + l));
-      const uint64_t gone = __ballot(v == lock_left(n + l));
-      if (~gone != 0ull) {
-        n += (uint32_t)__builtin_ctzll(~gone);
-        break;
-      }
-      n += 64;
-    }
+    ++n;   /* that waiter had left: look for the next one still in the queue */
+    look = true;
   }
 }
 
@@ -865,11 +912,11 @@ __device__ int miss_private_wave(const gfs_dev* d, uint32_t file, uint64_t p, ui
   const uint32_t l = lane();
   const uint64_t tl0 = wall_clock64();
   uint64_t ticket;
-  const int lk = lock_file_wave(d, file, key, t0, ticket);
+  const int lk = lock_file_wave(d, file, key, p, t0, ticket);
   const uint64_t tl1 = wall_clock64();
   if (l == 0) bcount(bs, GFS_T_LOCK, tl1 - tl0);
   if (lk == LOCK_TIMEOUT) return 2;
-  if (lk == LOCK_LEFT) {
+  if (lk == LOCK_LEFT || lk == LOCK_COVERED) {
     if (l == 0) bcount(bs, GFS_C_LOCK_LEFT, 1);
     return 1;
   }
@@ -879,7 +926,7 @@ __device__ int miss_private_wave(const gfs_dev* d, uint32_t file, uint64_t p, ui
   int64_t slot = -1;
   if (!present && l == 0) slot = pt_reserve_lane(d, key);
   slot = __shfl(slot, 0, 64);
-  unlock_file_wave(d, file, ticket);
+  unlock_file_wave(d, file, ticket, 0, 0);
   __builtin_amdgcn_s_setprio(0);
   if (l == 0) bcount(bs, GFS_T_CRIT, wall_clock64() - tl1);
   if (present) return 1;
@@ -1063,13 +1110,27 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
     } else if (f < 0) {
       const uint64_t tl0 = wall_clock64();
       uint64_t ticket;
-      const int lk = lock_file_wave(d, file, key, t0, ticket);
+      const int lk = lock_file_wave(d, file, key, p, t0, ticket);
       const uint64_t tl1 = wall_clock64();
       if (l == 0) bcount(bs, GFS_T_LOCK, tl1 - tl0);
       if (lk == LOCK_TIMEOUT) break;
       if (lk == LOCK_LEFT) {
         if (l == 0) bcount(bs, GFS_C_LOCK_LEFT, 1);
         continue;   /* the page was reserved while this block waited: go to the pin path */
+      }
+      if (lk == LOCK_COVERED) {
+        /* the holder's window covers the page: wait until its reservation shows in the
+           table or no running claim covers the page any more, then look again */
+        if (l == 0) bcount(bs, GFS_C_LOCK_LEFT, 1);
+        uint32_t nw = 0;
+        while (pt_lookup_wave(d, key) < 0 && !expired(d, t0)) {
+          uint64_t cl = 0;
+          if (l < GFS_CLAIMS) cl = ld_acq(&d->claims[file].e[l]);
+          const uint64_t c_lo = cl >> 32, c_hi = (cl >> 32) + ((cl & 0xffffffffull) >> 1);
+          if (__ballot(l < GFS_CLAIMS && (cl & 1ull) && c_lo <= p && p < c_hi) == 0) break;
+          if (l == 0) nap_short(nw);
+        }
+        continue;
       }
       if (l == 0) bcount(bs, GFS_C_LOCKS, 1);
       /* every block waiting on this file's lock waits for this wave: let it issue first */
@@ -1089,7 +1150,7 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       if (present || covered || free_cl == 0) {
         /* filled, reserved, or about to be reserved by a window being claimed: go to the pin
            path (after a nap if the claim is still running) */
-        unlock_file_wave(d, file, ticket);
+        unlock_file_wave(d, file, ticket, 0, 0);
         __builtin_amdgcn_s_setprio(0);
         if (l == 0) bcount(bs, GFS_T_CRIT, wall_clock64() - tl1);
         if (!present) {
@@ -1123,7 +1184,7 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       uint64_t* claim = &d->claims[file].e[cj];
       if (l == 0) st_rlx(claim, (cws << 32) | ((cwe - cws) << 1) | 1ull);
       const uint64_t tu0 = wall_clock64();
-      unlock_file_wave(d, file, ticket);
+      unlock_file_wave(d, file, ticket, cws, cwe);
       __builtin_amdgcn_s_setprio(0);
       const uint64_t tl2 = wall_clock64();
       if (l == 0) {

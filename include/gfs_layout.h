@@ -9,7 +9,7 @@
  *   gfs_dev (the handle)             512 B
  *   files[GFS_MAX_FILES]             768 B each
  *   locks[GFS_MAX_FILES]             128 B each (miss ticket locks)
- *   lockq[GFS_MAX_FILES][GFS_LOCK_SLOTS] u32   queue slots of the miss locks
+ *   lockq[GFS_MAX_FILES][GFS_LOCK_SLOTS] u64   queue slots of the miss locks
  *   claims[GFS_MAX_FILES]            128 B each (windows being reserved)
  *   pslots[private_slots]            64 B each (private policy)
  *   names[GFS_MAX_FILES]             GFS_NAME_MAX B each (registered paths)
@@ -190,7 +190,7 @@ typedef struct gfs_dev {
   gfs_globals* g;
   gfs_file_dev* files;
   gfs_file_lock* locks;
-  uint32_t* lockq;              /* [GFS_MAX_FILES][GFS_LOCK_SLOTS] miss-lock queue slots */
+  uint64_t* lockq;              /* [GFS_MAX_FILES][GFS_LOCK_SLOTS] miss-lock queue slots */
   gfs_file_claims* claims;      /* [GFS_MAX_FILES] windows being reserved */
   gfs_pslot* pslots;            /* private policy: [private_slots] */
   uint8_t* pbuf;                /* private policy: [private_slots][ra_cap pages] in the frames allocation */

@@ -104,7 +104,7 @@ int make_layout(const gfs_config* c, Layout* L) {
   L->off_dev = o; o = align_up(o + sizeof(gfs_dev), kAlign);
   L->off_files = o; o = align_up(o + sizeof(gfs_file_dev) * GFS_MAX_FILES, kAlign);
   L->off_locks = o; o = align_up(o + sizeof(gfs_file_lock) * GFS_MAX_FILES, kAlign);
-  L->off_lockq = o; o = align_up(o + 4ull * GFS_LOCK_SLOTS * GFS_MAX_FILES, kAlign);
+  L->off_lockq = o; o = align_up(o + 8ull * GFS_LOCK_SLOTS * GFS_MAX_FILES, kAlign);
   L->off_claims = o; o = align_up(o + sizeof(gfs_file_claims) * GFS_MAX_FILES, kAlign);
   L->off_pslots = o;
   if (c->policy == GFS_POLICY_PRIVATE) o = align_up(o + sizeof(gfs_pslot) * c->private_slots, kAlign);
@@ -526,7 +526,7 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   h.g = (gfs_globals*)(c->meta + L.off_globals);
   h.files = (gfs_file_dev*)(c->meta + L.off_files);
   h.locks = (gfs_file_lock*)(c->meta + L.off_locks);
-  h.lockq = (uint32_t*)(c->meta + L.off_lockq);
+  h.lockq = (uint64_t*)(c->meta + L.off_lockq);
   h.claims = (gfs_file_claims*)(c->meta + L.off_claims);
   h.policy = cfg->policy;
   if (cfg->policy == GFS_POLICY_PRIVATE) {
