@@ -17,7 +17,8 @@ from gpu_util import decode_replay, expected
 
 pytestmark = pytest.mark.gpu
 
-RA_CAP = 16 << 20        # bench.py default
+RA_CAP = configs.c2().ra_cap_bytes     # the cap bench.py runs C2 and C3 with
+RA_CAP_LARGE = 16 << 20                # windows of 64 pages
 HOST_THREADS = 8
 RPC_SLOTS = 64
 
@@ -40,7 +41,7 @@ def _sample(blocks, n, seed):
     return sorted(set(int(x) for x in rng.integers(0, blocks, size=n)) | {0, blocks - 1})
 
 
-@pytest.mark.parametrize("ra_cap", [RA_CAP, 0])
+@pytest.mark.parametrize("ra_cap", [RA_CAP, RA_CAP_LARGE, 0])
 def test_c2_full_size_parity_and_trace_replay(ra_cap, data_dir, cuda):
     wl = configs.c2()
     path = configs.ensure_file(wl.file, data_dir)

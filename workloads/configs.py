@@ -61,7 +61,7 @@ class Workload:
     read_size: int
     offsets: np.ndarray            # uint64 [blocks, K]: block b's k-th read offset
     consumer: int                  # CONSUMER_CHECKSUM or CONSUMER_HISTOGRAM
-    ra_cap_bytes: int = 16 * MiB   # readahead cap the benchmark uses for this workload
+    ra_cap_bytes: int = 2 * MiB    # readahead cap the benchmark uses for this workload
 
     @property
     def reads_per_block(self) -> int:
@@ -106,10 +106,10 @@ def c1() -> Workload:
 
 
 def c2() -> Workload:
-    """Cap 2 MiB (8 pages: the 4-page first window doubles once): on tmpfs a cold pass runs
-    at 31-33 GB/s with it against 22 GB/s with 16 MiB, whose large requests keep the blocks
-    that wait on their pages waiting for the whole window; on disk the cap makes no
-    measurable difference."""
+    """Readahead cap 2 MiB (8 pages: the 4-page first window doubles once): on tmpfs a cold
+    pass runs at 31-33 GB/s with it against 22 GB/s with 16 MiB, whose large requests keep
+    the blocks that wait on their pages waiting for the whole window; on disk the cap
+    makes no measurable difference."""
     f = FileSpec("c2_seed2_8GiB.bin", 2, 8 * GiB)
     return Workload("c2", f, 256 * KiB, 2 * GiB, 1024, 256, 128 * KiB,
                     strided_offsets(1024, 64, 128 * KiB), CONSUMER_HISTOGRAM, ra_cap_bytes=2 * MiB)
