@@ -234,47 +234,6 @@ __device__ bool pt_present_lane(const gfs_dev* d, uint64_t key) {
   return hit;
 }
 
-/* Wave-collective: p's table lookup (as pt_lookup_wave) and, in the same round trip, the
- * presence of the k <= 16 pages right behind p that the readahead detector's context rule
- * looks at first: bit i of behind is set if page p-1-i (>= 0) has a table entry. Like p's
- * lookup, each key is probed by 32 lanes, one entry each (lane l: entry l mod 32 of key
- * 2j + l / 32 in round j), so sixteen keys cost eight loads per lane. Returns p's frame or
- * -1. */
-__device__ int32_t pt_lookup_behind_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint32_t k,
-                                         uint64_t& behind) {
-  const uint64_t key = page_key(file, p);
-  uint32_t b1, b2;
-  key_buckets(d, key, b1, b2);
-  const uint32_t l = lane();
-  uint64_t e = 0;
-  if (l < 32) e = ld_rlx(slot_ptr(d, b1, b2, (int)l));
-  uint64_t ev[8], kk[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const uint64_t i = 2ull * j + (l >> 5);
-    ev[j] = 0;
-    kk[j] = 0;
-    if (i < k && i + 1 <= p) {
-      kk[j] = page_key(file, p - 1 - i);
-      uint32_t c1, c2;
-      key_buckets(d, kk[j], c1, c2);
-      ev[j] = ld_rlx(slot_ptr(d, c1, c2, (int)(l & 31)));
-    }
-  }
-  uint64_t bits = 0;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const uint64_t m = __ballot(kk[j] != 0 && (ev[j] >> GFS_ENTRY_FRAME_BITS) == kk[j]);
-    if (m & 0xffffffffull) bits |= 1ull << (2 * j);
-    if (m >> 32) bits |= 1ull << (2 * j + 1);
-  }
-  behind = bits;
-  const uint64_t m = __ballot(l < 32 && (e >> GFS_ENTRY_FRAME_BITS) == key);
-  if (m == 0) return -1;
-  const uint64_t hit = __shfl(e, __ffsll((unsigned long long)m) - 1, 64);
-  return (int32_t)(hit & kFrameMask);
-}
-
 /* per lane: the frame key maps to, kReserved, or -1 when absent */
 __device__ int32_t pt_find_lane(const gfs_dev* d, uint64_t key) {
   uint32_t b1, b2;
@@ -462,10 +421,8 @@ __device__ bool lock_try_leave_lane(const gfs_dev* d, uint32_t file, uint64_t t)
 __device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uint64_t page, uint64_t t0,
                               uint64_t& ticket);
 /* Wave-collective: pass the lock on; [lo, hi) is the window the holder has just claimed
-   (lo == hi: none). With have_pre, pre (lane i) is the slot of ticket + 1 + i as read
-   earlier in the critical section; it stands in for the first read of those slots. */
-__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket, uint64_t lo, uint64_t hi,
-                                 uint64_t pre, bool have_pre);
+   (lo == hi: none). */
+__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket, uint64_t lo, uint64_t hi);
 
 __device__ int32_t pt_lookup_wave(const gfs_dev* d, uint64_t key);
 
@@ -533,8 +490,7 @@ __device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uin
  * loses only to the waiter leaving), and the first other ticket gets the grant; if that
  * waiter left just before the exchange, the scan goes on after it. A ticket that has not
  * announced its page yet is granted the lock like any other. */
-__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket, uint64_t lo, uint64_t hi,
-                                 uint64_t pre, bool have_pre) {
+__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket, uint64_t lo, uint64_t hi) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   const uint32_t l = lane();
   uint64_t n = ticket + 1;
@@ -543,11 +499,7 @@ __device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticke
     if (look) {
       const uint64_t nl = n + l;
       uint64_t* sl = lock_slot(d, file, nl);
-      /* a slot read earlier is as good as a fresh one: the compare-and-swap and the
-         exchange below act on the current value, and a waiter that announced or left
-         since is handled the same way as one that does so just after a fresh read */
-      uint64_t v = have_pre ? pre : ld_rlx(sl);
-      have_pre = false;
+      uint64_t v = ld_rlx(sl);
       const uint64_t pg = (v >> 32) & 0x7fffffffull;
       const bool gone = v == lock_left(nl) || v == lock_covered(nl);
       const bool cov = hi > lo && (v >> 63) && (uint32_t)v == ((uint32_t)nl << 2) && pg >= lo && pg < hi;
@@ -592,8 +544,6 @@ struct RaState {
   uint32_t advice, clk, rn;
   uint64_t r, s_next;
   uint32_t s_size, s_last, s_valid;
-  uint64_t behind;     /* bit i: page p-1-i has a table entry (i < behind_n), if probed */
-  uint32_t behind_n;   /* pages right behind p probed together with p's own probe (0: none) */
 };
 __device__ __forceinline__ RaState ra_load_lane(const gfs_dev* d, uint32_t file) {
   gfs_file_dev* fe = &d->files[file];
@@ -611,21 +561,6 @@ __device__ __forceinline__ RaState ra_load_lane(const gfs_dev* d, uint32_t file)
     st.s_valid = ld_rlx32(&sp->valid);
   }
   return st;
-}
-
-/* Wave-collective, registers only: true if the decision for p below will fall to the
- * context rule (readahead on, no stream zone holds p, fewer than GFS_NEAR_MIN recent misses
- * near p), so that the caller can probe the pages behind p together with p itself. The
- * decision does not depend on this: if it ever disagrees, the context rule probes for
- * itself. */
-__device__ __forceinline__ bool ra_context_expected(const gfs_dev* d, uint64_t p, const RaState& st) {
-  if (d->ra_cap == 0 || st.advice == GFS_ADV_RANDOM) return false;
-  const uint32_t l = lane();
-  const bool cov = l < d->streams && st.s_valid && st.s_next <= p && p < st.s_next + st.s_size;
-  if (__ballot(cov) != 0) return false;
-  const bool near_l = l < GFS_RECENT_MISSES && l < st.rn && st.r + GFS_NEAR_PAGES >= p &&
-                      st.r <= p + GFS_NEAR_PAGES;
-  return __popcll(__ballot(near_l)) < GFS_NEAR_MIN;
 }
 
 __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, const RaState& st, uint64_t& ws,
@@ -685,15 +620,7 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, cons
       /* context: count the consecutive cached pages right behind p (64 per round); a
          stream that no slot tracks shows up as that history */
       uint32_t h = 0;
-      bool more = true;
-      if (st.behind_n) {
-        /* the first pages behind p were probed together with p */
-        const uint32_t k = st.behind_n;
-        const uint64_t gap = ~st.behind & ((1ull << k) - 1);
-        h = gap ? (uint32_t)__builtin_ctzll(gap) : k;
-        more = gap == 0;
-      }
-      while (more && h < cap) {
+      while (h < cap) {
         const uint64_t back = (uint64_t)h + 1 + l;
         bool mapped = false;
         if (back <= p && h + l < cap) mapped = pt_present_lane(d, page_key(file, p - back));
@@ -999,7 +926,7 @@ __device__ int miss_private_wave(const gfs_dev* d, uint32_t file, uint64_t p, ui
   int64_t slot = -1;
   if (!present && l == 0) slot = pt_reserve_lane(d, key);
   slot = __shfl(slot, 0, 64);
-  unlock_file_wave(d, file, ticket, 0, 0, 0, false);
+  unlock_file_wave(d, file, ticket, 0, 0);
   __builtin_amdgcn_s_setprio(0);
   if (l == 0) bcount(bs, GFS_T_CRIT, wall_clock64() - tl1);
   if (present) return 1;
@@ -1210,32 +1137,20 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       __builtin_amdgcn_s_setprio(3);
       /* one round: the detector state and the file's window claims; then, ordered after the
          claims, the table probe (a claim cleared after its reservations means they show) */
-      RaState ras = ra_load_lane(d, file);
+      const RaState ras = ra_load_lane(d, file);
       uint64_t cl = 0;
       if (l < GFS_CLAIMS) cl = ld_rlx(&d->claims[file].e[l]);
       const uint64_t npages = d->files[file].npages;
-      /* the queue slots of the 64 tickets behind this one, for the hand-off below */
-      const uint64_t behind_slot = ld_rlx(lock_slot(d, file, ticket + 1 + l));
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const bool cl_on = l < GFS_CLAIMS && (cl & 1ull);
       const uint64_t cl_lo = cl >> 32, cl_hi = (cl >> 32) + ((cl & 0xffffffffull) >> 1);
       const bool covered = __ballot(cl_on && cl_lo <= p && p < cl_hi) != 0;
       const uint64_t free_cl = __ballot(l < GFS_CLAIMS && !cl_on);
-      /* p's probe; with readahead on, the context rule's first probes go out with it */
-      bool present;
-      if (ra_context_expected(d, p, ras)) {
-        const uint32_t k = d->ra_cap < 16 ? d->ra_cap : 16u;
-        uint64_t behind = 0;
-        present = pt_lookup_behind_wave(d, file, p, k, behind) >= 0;
-        ras.behind = behind;
-        ras.behind_n = k;
-      } else {
-        present = pt_lookup_wave(d, key) >= 0;
-      }
+      const bool present = pt_lookup_wave(d, key) >= 0;
       if (present || covered || free_cl == 0) {
         /* filled, reserved, or about to be reserved by a window being claimed: go to the pin
            path (after a nap if the claim is still running) */
-        unlock_file_wave(d, file, ticket, 0, 0, 0, false);
+        unlock_file_wave(d, file, ticket, 0, 0);
         __builtin_amdgcn_s_setprio(0);
         if (l == 0) bcount(bs, GFS_T_CRIT, wall_clock64() - tl1);
         if (!present) {
@@ -1269,7 +1184,7 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       uint64_t* claim = &d->claims[file].e[cj];
       if (l == 0) st_rlx(claim, (cws << 32) | ((cwe - cws) << 1) | 1ull);
       const uint64_t tu0 = wall_clock64();
-      unlock_file_wave(d, file, ticket, cws, cwe, behind_slot, true);
+      unlock_file_wave(d, file, ticket, cws, cwe);
       __builtin_amdgcn_s_setprio(0);
       const uint64_t tl2 = wall_clock64();
       if (l == 0) {

@@ -17,7 +17,6 @@ from gpu_util import decode_replay, expected
 
 pytestmark = pytest.mark.gpu
 
-RA_CAP = configs.c2().ra_cap_bytes     # the cap bench.py runs C2 and C3 with
 RA_CAP_LARGE = 16 << 20                # windows of 64 pages
 HOST_THREADS = 8
 RPC_SLOTS = 64
@@ -41,9 +40,11 @@ def _sample(blocks, n, seed):
     return sorted(set(int(x) for x in rng.integers(0, blocks, size=n)) | {0, blocks - 1})
 
 
-@pytest.mark.parametrize("ra_cap", [RA_CAP, RA_CAP_LARGE, 0])
+@pytest.mark.parametrize("ra_cap", ["bench", RA_CAP_LARGE, 0])
 def test_c2_full_size_parity_and_trace_replay(ra_cap, data_dir, cuda):
     wl = configs.c2()
+    if ra_cap == "bench":
+        ra_cap = wl.ra_cap_bytes          # the cap bench.py runs this workload with
     path = configs.ensure_file(wl.file, data_dir)
     _say(f"c2 full size, ra cap {ra_cap >> 20} MiB")
     cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=ra_cap, host_threads=HOST_THREADS,
@@ -78,10 +79,12 @@ def test_c2_full_size_parity_and_trace_replay(ra_cap, data_dir, cuda):
          f"{len(rc['evictions'])} evictions, {st['fetched_pages']} pages fetched")
 
 
-@pytest.mark.parametrize("ra_cap", [RA_CAP, 0])
+@pytest.mark.parametrize("ra_cap", ["bench", 0])
 @pytest.mark.parametrize("pattern", ["a", "b", "c"])
 def test_c3_full_size_parity(pattern, ra_cap, data_dir, cuda):
     wl = configs.c3(pattern)
+    if ra_cap == "bench":
+        ra_cap = wl.ra_cap_bytes
     path = configs.ensure_file(wl.file, data_dir)
     _say(f"c3{pattern} full size, ra cap {ra_cap >> 20} MiB")
     cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=ra_cap, host_threads=HOST_THREADS,

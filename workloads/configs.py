@@ -106,10 +106,11 @@ def c1() -> Workload:
 
 
 def c2() -> Workload:
-    """Readahead cap 2 MiB (8 pages: the 4-page first window doubles once): on tmpfs a cold
-    pass runs at 31-33 GB/s with it against 22 GB/s with 16 MiB, whose large requests keep
-    the blocks that wait on their pages waiting for the whole window; on disk the cap
-    makes no measurable difference."""
+    """Readahead cap 2 MiB (8 pages: the 4-page first window doubles once). Many blocks read
+    this file interleaved, so most windows are cap-sized chunks that several blocks wait on
+    at once, and a large cap keeps them waiting for the whole chunk: on tmpfs a cold pass
+    runs at 31 GB/s with 2 MiB against 23-24 GB/s with 16 MiB; on disk the cap makes no
+    measurable difference."""
     f = FileSpec("c2_seed2_8GiB.bin", 2, 8 * GiB)
     return Workload("c2", f, 256 * KiB, 2 * GiB, 1024, 256, 128 * KiB,
                     strided_offsets(1024, 64, 128 * KiB), CONSUMER_HISTOGRAM, ra_cap_bytes=2 * MiB)
