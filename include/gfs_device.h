@@ -109,6 +109,11 @@ __device__ __forceinline__ uint64_t ld_rlx(uint64_t* p) {
 __device__ __forceinline__ uint64_t ld_acq(uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
+/* Spin loops poll with relaxed loads and take one acquire fence once the awaited value is
+   seen: an agent-scope acquire invalidates the XCD's L2, and hundreds of waiting blocks
+   polling with acquire loads would keep every block's cached data flushed. */
+__device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void acquire_system() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, ""); }
 __device__ __forceinline__ uint32_t ld_rlx32(uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -356,8 +361,9 @@ __device__ int hand_visit(const gfs_dev* d, uint32_t f, uint64_t& vkey, uint32_t
 __device__ int64_t wait_valid_lane(const gfs_dev* d, uint32_t f, uint64_t t0) {
   uint32_t n = 0;
   while (true) {
-    const uint64_t w = ld_acq(&d->fword[f]);
+    const uint64_t w = ld_rlx(&d->fword[f]);
     if ((w & GFS_FW_STATE) == GFS_FS_VALID) {
+      acquire_agent();   /* the frame's bytes, published before VALID */
       if (w & GFS_FW_ERR) {
         frame_unpin(d, f);
         return -kEIO;
@@ -761,8 +767,9 @@ __device__ void join_or_help_lane(const gfs_dev* d, uint32_t f, uint64_t p, uint
   bs->frame = (int32_t)f;
   bs->pull = 0;
   while (true) {
-    uint64_t w = ld_acq(fw);
+    uint64_t w = ld_rlx(fw);
     if ((w & GFS_FW_STATE) == GFS_FS_VALID) {
+      acquire_agent();   /* the frame's bytes, published before VALID */
       if (w & GFS_FW_ERR) {
         frame_unpin(d, f);
         bs->status = -kEIO;
@@ -772,12 +779,13 @@ __device__ void join_or_help_lane(const gfs_dev* d, uint32_t f, uint64_t p, uint
       return;
     }
     if (!(w & GFS_FW_PULL)) {
-      const uint64_t ff = ld_acq(&d->ffill[f]);
+      const uint64_t ff = ld_rlx(&d->ffill[f]);
       if (ff) {
         const uint32_t s = (uint32_t)(ff >> 40) - 1;
         gfs_req_dev* rq = &d->reqd[s];
-        const uint64_t ready = ld_acq(&rq->ready);
+        const uint64_t ready = ld_rlx(&rq->ready);
         if (ready != 0 && (ready & ((1ull << 40) - 1)) == (ff & ((1ull << 40) - 1))) {
+          acquire_agent();   /* the request record, published before ready */
           if (cas64(fw, w, (w | GFS_FW_PULL) + GFS_FW_VER_ONE)) {
             bs->status = 0;
             bs->pull = 2;
@@ -1003,13 +1011,14 @@ __device__ int miss_private_wave(const gfs_dev* d, uint32_t file, uint64_t p, ui
         const uint64_t gen = ring_gen(d, tk);
         uint32_t nn = 0;
         const uint64_t ts0 = wall_clock64();
-        while (ld_acq(&d->slot_free[s]) != gen - 1) {
+        while (ld_rlx(&d->slot_free[s]) != gen - 1) {
           if (expired(d, t0)) {
             status = 2;
             break;
           }
           nap(nn);
         }
+        acquire_agent();   /* the slot's last users are done with its staging */
         bcount(bs, GFS_T_SLOT, wall_clock64() - ts0);
         if (status == 0) {
           gfs_rpc_slot* rs = &d->ring[s];
@@ -1024,13 +1033,14 @@ __device__ int miss_private_wave(const gfs_dev* d, uint32_t file, uint64_t p, ui
           bcount(bs, GFS_C_REQ_BYTES, len);
           bcount(bs, GFS_C_FETCHED, 1);
           const uint64_t th0 = wall_clock64();
-          while (__hip_atomic_load(&rs->done_seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) != gen) {
+          while (__hip_atomic_load(&rs->done_seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != gen) {
             if (expired(d, t0)) {
               status = 2;
               break;
             }
             nap(nn);
           }
+          acquire_system();   /* the staged bytes, written by the host before done_seq */
           bcount(bs, GFS_T_HOST, wall_clock64() - th0);
           if (status == 0) bs->result = rs->result;
         }
@@ -1125,11 +1135,12 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
         uint32_t nw = 0;
         while (pt_lookup_wave(d, key) < 0 && !expired(d, t0)) {
           uint64_t cl = 0;
-          if (l < GFS_CLAIMS) cl = ld_acq(&d->claims[file].e[l]);
+          if (l < GFS_CLAIMS) cl = ld_rlx(&d->claims[file].e[l]);
           const uint64_t c_lo = cl >> 32, c_hi = (cl >> 32) + ((cl & 0xffffffffull) >> 1);
           if (__ballot(l < GFS_CLAIMS && (cl & 1ull) && c_lo <= p && p < c_hi) == 0) break;
           if (l == 0) nap_short(nw);
         }
+        acquire_agent();   /* the reservations, published before the claim was cleared */
         continue;
       }
       if (l == 0) bcount(bs, GFS_C_LOCKS, 1);
@@ -1304,13 +1315,14 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
         const uint64_t gen = ring_gen(d, tk);
         uint32_t nn = 0;
         const uint64_t ts0 = wall_clock64();
-        while (ld_acq(&d->slot_free[s]) != gen - 1) {
+        while (ld_rlx(&d->slot_free[s]) != gen - 1) {
           if (expired(d, t0)) {
             status = -kETIMEDOUT;
             break;
           }
           nap(nn);
         }
+        acquire_agent();   /* the slot's last users are done with its staging */
         bcount(bs, GFS_T_SLOT, wall_clock64() - ts0);
         if (status == 0) {
           gfs_rpc_slot* rs = &d->ring[s];
@@ -1342,7 +1354,7 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
           gfs_rpc_slot* rs = &d->ring[s];
           uint32_t nn = 0;
           const uint64_t th0 = wall_clock64();
-          while (__hip_atomic_load(&rs->done_seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) !=
+          while (__hip_atomic_load(&rs->done_seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) !=
                  gen) {
             if (expired(d, t0)) {
               status = -kETIMEDOUT;
@@ -1350,6 +1362,7 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
             }
             nap(nn);
           }
+          acquire_system();   /* the staged bytes, written by the host before done_seq */
           bcount(bs, GFS_T_HOST, wall_clock64() - th0);
           if (status == 0) {
             bs->result = rs->result;
