@@ -18,10 +18,8 @@ from __future__ import annotations
 
 import argparse
 import json
-import mmap
 import os
 import sys
-import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -74,32 +72,10 @@ def _cap_mib(args, default: int = 16) -> int:
 
 
 def storage_peak(path: str, threads: int = 16, chunk: int = 4 << 20, limit: int = 8 << 30) -> float:
-    """O_DIRECT (if available) sequential read of the file with `threads` readers (16 reads
-    of 4 MiB in flight), GB/s."""
-    size = min(os.path.getsize(path), limit)
-    try:
-        fd = os.open(path, os.O_RDONLY | os.O_DIRECT)
-    except OSError:
-        fd = os.open(path, os.O_RDONLY)
-        os.posix_fadvise(fd, 0, 0, os.POSIX_FADV_DONTNEED)
-    nchunks = size // chunk
-    got = [0] * threads
-
-    def worker(t):
-        buf = mmap.mmap(-1, chunk)
-        for c in range(t, nchunks, threads):
-            got[t] += os.preadv(fd, [buf], c * chunk)
-        buf.close()
-
-    t0 = time.perf_counter()
-    ths = [threading.Thread(target=worker, args=(t,)) for t in range(threads)]
-    for th in ths:
-        th.start()
-    for th in ths:
-        th.join()
-    dt = time.perf_counter() - t0
-    os.close(fd)
-    return sum(got) / dt / 1e9
+    """Sequential read rate of the file by 16 native threads reading 4 MiB pieces with
+    O_DIRECT where allowed (64 MiB in flight), GB/s."""
+    from workloads import configs
+    return configs.read_peak([path], threads=threads, chunk=chunk, limit=limit)
 
 
 def h2d_peak(torch, nbytes: int = 256 << 20, reps: int = 5) -> float:
@@ -188,19 +164,9 @@ def _pool_files(m, ddir):
 
 
 def _multi_storage_peak(paths, limit: int = 8 << 30) -> float:
-    """Sequential O_DIRECT read rate over the largest files until `limit` bytes."""
-    order = sorted(paths, key=os.path.getsize, reverse=True)
-    tot, dt = 0, 0.0
-    for p in order:
-        sz = min(os.path.getsize(p), limit - tot)
-        if sz < (64 << 20):
-            break
-        t = time.perf_counter()
-        r = storage_peak(p, limit=sz)
-        d = time.perf_counter() - t
-        tot += int(r * 1e9 * d)
-        dt += d
-    return tot / dt / 1e9 if dt else 0.0
+    """Sequential read rate over the largest files until `limit` bytes."""
+    from workloads import configs
+    return configs.read_peak(paths, limit=limit)
 
 
 def bench_batch(args, torch) -> int:

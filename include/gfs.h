@@ -93,7 +93,7 @@ typedef struct gfs_config {
 } gfs_config;
 
 /* Fill *cfg with defaults: 64 KiB pages, 256 MiB cache, readahead 4 pages growing to
- * 2 MiB, 8 streams per file, 8 host threads, 64 slots, 2 MiB host read pieces, O_DIRECT
+ * 16 MiB, 8 streams per file, 8 host threads, 64 slots, 2 MiB host read pieces, O_DIRECT
  * preferred, trace off, shared policy (512 private slots if the private policy is chosen).
  *
  * GFS_POLICY_PRIVATE: a miss that the block's private buffer cannot serve asks the host for

@@ -429,7 +429,7 @@ void gfs_config_default(gfs_config* cfg) {
   cfg->page_size = 64 << 10;
   cfg->cache_bytes = 256ull << 20;
   cfg->ra_init_bytes = 4 * cfg->page_size;
-  cfg->ra_cap_bytes = 2ull << 20;
+  cfg->ra_cap_bytes = 16ull << 20;
   cfg->host_threads = 8;
   cfg->rpc_slots = 64;
   cfg->io_backend = GFS_IO_PREAD;

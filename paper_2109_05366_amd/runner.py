@@ -9,7 +9,7 @@ import numpy as np
 from . import gfs
 
 
-def make_config(page_size: int, cache_bytes: int, ra_cap_bytes: int = 2 << 20, ra_init_pages: int = 4,
+def make_config(page_size: int, cache_bytes: int, ra_cap_bytes: int = 16 << 20, ra_init_pages: int = 4,
                 streams: int = 8, host_threads: int = 8, rpc_slots: int = 64,
                 o_direct: int = gfs.GFS_DIRECT_PREFER, trace_level: int = 0, trace_capacity: int = 0,
                 timeout_s: float = 30.0, policy: int = gfs.GFS_POLICY_SHARED,

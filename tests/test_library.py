@@ -35,7 +35,7 @@ def test_config_default_values():
     cfg = gfs.gfs_config_default()
     assert cfg.abi_version == gfs.GFS_ABI_VERSION
     assert cfg.page_size == 64 << 10 and cfg.cache_bytes == 256 << 20
-    assert cfg.ra_init_bytes == 4 * cfg.page_size and cfg.ra_cap_bytes == 2 << 20
+    assert cfg.ra_init_bytes == 4 * cfg.page_size and cfg.ra_cap_bytes == 16 << 20
     assert cfg.streams_per_file == 8 and cfg.host_threads == 8 and cfg.rpc_slots == 64
     assert ctypes.sizeof(gfs.gfs_config) == 88
     assert cfg.policy == gfs.GFS_POLICY_SHARED and cfg.private_slots == 512

@@ -61,7 +61,7 @@ class Workload:
     read_size: int
     offsets: np.ndarray            # uint64 [blocks, K]: block b's k-th read offset
     consumer: int                  # CONSUMER_CHECKSUM or CONSUMER_HISTOGRAM
-    ra_cap_bytes: int = 2 * MiB    # readahead cap the benchmark uses for this workload
+    ra_cap_bytes: int = 16 * MiB   # readahead cap the benchmark uses for this workload
 
     @property
     def reads_per_block(self) -> int:
@@ -106,14 +106,9 @@ def c1() -> Workload:
 
 
 def c2() -> Workload:
-    """Readahead cap 2 MiB (8 pages: the 4-page first window doubles once). Many blocks read
-    this file interleaved, so most windows are cap-sized chunks that several blocks wait on
-    at once, and a large cap keeps them waiting for the whole chunk: on tmpfs a cold pass
-    runs at 31 GB/s with 2 MiB against 23-24 GB/s with 16 MiB; on disk the cap makes no
-    measurable difference."""
     f = FileSpec("c2_seed2_8GiB.bin", 2, 8 * GiB)
     return Workload("c2", f, 256 * KiB, 2 * GiB, 1024, 256, 128 * KiB,
-                    strided_offsets(1024, 64, 128 * KiB), CONSUMER_HISTOGRAM, ra_cap_bytes=2 * MiB)
+                    strided_offsets(1024, 64, 128 * KiB), CONSUMER_HISTOGRAM)
 
 
 def f3() -> Workload:
@@ -196,6 +191,8 @@ def get(name: str) -> Workload:
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _GEN_SRC = os.path.join(_HERE, "genfile.c")
 _GEN_BIN = os.path.join(_HERE, "genfile")
+_PEAK_SRC = os.path.join(_HERE, "readpeak.c")
+_PEAK_BIN = os.path.join(_HERE, "readpeak")
 
 
 def data_dir() -> str:
@@ -212,6 +209,31 @@ def build_generator(force: bool = False) -> str:
             raise RuntimeError("no C compiler to build workloads/genfile")
         subprocess.check_call([cc, "-O2", "-o", _GEN_BIN, _GEN_SRC, "-lpthread"])
     return _GEN_BIN
+
+
+def build_readpeak(force: bool = False) -> str:
+    """Compile the C sequential-read timer (the storage bound of the benchmarks)."""
+    if force or not os.path.exists(_PEAK_BIN) or os.path.getmtime(_PEAK_BIN) < os.path.getmtime(_PEAK_SRC):
+        cc = shutil.which("gcc") or shutil.which("cc")
+        if not cc:
+            raise RuntimeError("no C compiler to build workloads/readpeak")
+        subprocess.check_call([cc, "-O2", "-o", _PEAK_BIN, _PEAK_SRC, "-lpthread"])
+    return _PEAK_BIN
+
+
+def read_peak(paths, threads: int = 16, chunk: int = 4 << 20, limit: int = 8 << 30) -> float:
+    """Sequential read rate (10^9 B/s) of the largest of `paths`, up to `limit` bytes in all,
+    by `threads` native threads reading `chunk`-byte pieces (O_DIRECT where allowed)."""
+    order = sorted(paths, key=os.path.getsize, reverse=True)
+    pick, tot = [], 0
+    for p in order:
+        if tot >= limit:
+            break
+        pick.append(p)
+        tot += os.path.getsize(p)
+    out = subprocess.check_output([build_readpeak(), str(threads), str(chunk), str(limit), *pick], text=True)
+    nbytes, secs = out.split()
+    return int(nbytes) / float(secs) / 1e9
 
 
 def ensure_file(spec: FileSpec, directory: Optional[str] = None, threads: int = 8) -> str:
