@@ -146,7 +146,7 @@ __device__ bool poll_host(SrvCtrl* ctl, SrvEntry* tab, uint32_t cap, const SrvSu
   }
   // other blocks store newer clock values into progress at any time: read the clock after
   // it, and compare signed, so that a value stored after `now` was read is not "idle"
-  const uint64_t last = gfsd::ld_acq(&ctl->progress);
+  const uint64_t last = gfsd::ld_rlx(&ctl->progress);
   const uint64_t t = wall_clock64();
   if (last == 0) {
     gfsd::st_rlx(&ctl->progress, t);
@@ -156,19 +156,23 @@ __device__ bool poll_host(SrvCtrl* ctl, SrvEntry* tab, uint32_t cap, const SrvSu
   return false;
 }
 
-/* Thread 0: find the next unit, oldest request first, or decide to exit. */
+/* Thread 0: find the next unit, oldest request first, or decide to exit. The flags and
+   counters are read relaxed: every block without work runs this loop, and an agent-scope
+   acquire would invalidate its XCD's L2 each time; an entry's fields are read after one
+   acquire fence, once its ready flag is seen. */
 __device__ int pick_unit(SrvCtrl* ctl, SrvEntry* tab, uint32_t cap, const SrvSub* subs, SrvHost* host,
                          SrvDone* done, uint64_t chunk, uint64_t idle_ticks, uint64_t* oi, uint64_t* ok) {
   uint32_t naps = 0;
   while (true) {
-    if (gfsd::ld_acq(&ctl->abort)) return kExit;
-    uint64_t c = gfsd::ld_acq(&ctl->cursor);
+    if (gfsd::ld_rlx(&ctl->abort)) return kExit;
+    uint64_t c = gfsd::ld_rlx(&ctl->cursor);
     for (uint64_t i = c; i < cap; ++i) {
       SrvEntry* e = &tab[i];
-      if (__hip_atomic_load(&e->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+      if (__hip_atomic_load(&e->ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+      gfsd::acquire_agent();   /* the entry's fields, written before ready */
       const uint64_t nch = e->nchunks;
       // look before taking, so that idle blocks only read exhausted entries
-      if (gfsd::ld_acq(&e->next) < nch) {
+      if (gfsd::ld_rlx(&e->next) < nch) {
         const uint64_t k = gfsd::fadd64(&e->next, 1);
         if (k < nch) {
           *oi = i;
@@ -182,10 +186,10 @@ __device__ int pick_unit(SrvCtrl* ctl, SrvEntry* tab, uint32_t cap, const SrvSub
         c = c + 1;
       }
     }
-    const uint64_t fin = gfsd::ld_acq(&ctl->final_n);
-    if (fin && gfsd::ld_acq(&ctl->cursor) >= fin - 1) return kExit;
+    const uint64_t fin = gfsd::ld_rlx(&ctl->final_n);
+    if (fin && gfsd::ld_rlx(&ctl->cursor) >= fin - 1) return kExit;
     uint64_t free_ = 0;
-    if (gfsd::ld_acq(&ctl->poller) == 0 && gfsd::cas64(&ctl->poller, free_, 1)) {
+    if (gfsd::ld_rlx(&ctl->poller) == 0 && gfsd::cas64(&ctl->poller, free_, 1)) {
       const bool fresh = poll_host(ctl, tab, cap, subs, host, done, chunk, idle_ticks);
       gfsd::st_rel(&ctl->poller, 0);
       if (fresh) {
