@@ -101,3 +101,19 @@ def test_reservation_rounds_to_pages():
     assert oserve.reservation(0, 4096) == 0
     assert oserve.reservation(1, 4096) == 4096
     assert oserve.reservation(8192, 4096) == 8192
+
+
+def test_readpeak_reads_every_byte(tmp_path):
+    """The storage-rate timer reads each file whole (or up to the limit), across threads."""
+    from workloads import configs
+    a = tmp_path / "a.bin"
+    b = tmp_path / "b.bin"
+    a.write_bytes(bytes(range(256)) * 4096 * 3 + b"x" * 123)     # not a multiple of the chunk
+    b.write_bytes(b"\0" * (1 << 20))
+    exe = configs.build_readpeak()
+    import subprocess
+    out = subprocess.check_output([exe, "3", str(256 << 10), "0", str(a), str(b)], text=True).split()
+    assert int(out[0]) == a.stat().st_size + b.stat().st_size and float(out[1]) > 0
+    out = subprocess.check_output([exe, "2", str(64 << 10), str(512 << 10), str(a)], text=True).split()
+    assert int(out[0]) == 512 << 10
+    assert configs.read_peak([str(a), str(b)], threads=2, chunk=64 << 10) > 0
