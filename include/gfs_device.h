@@ -114,6 +114,19 @@ __device__ __forceinline__ uint64_t ld_acq(uint64_t* p) {
    polling with acquire loads would keep every block's cached data flushed. */
 __device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 __device__ __forceinline__ void acquire_system() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, ""); }
+/* Ordering for the miss lock's critical section, whose shared reads and writes are all
+   agent-scope atomics (the detector state, the window claims, the page table, the queue
+   slots): these are performed coherently across the XCDs, so passing the lock on needs
+   only the holder's earlier atomics to have completed before the grant is written, and
+   taking it needs only the later reads to be issued after the grant was seen. The wait
+   for outstanding memory operations gives both, without the L2 write-back and
+   invalidation that agent-scope fences add for plain (cached) accesses. The workgroup
+   fences keep the compiler from moving memory operations across the wait. */
+__device__ __forceinline__ void drain_atomics() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0x0F70);   /* vmcnt(0): every load, store and atomic done */
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 __device__ __forceinline__ uint32_t ld_rlx32(uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -483,7 +496,7 @@ __device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uin
       }
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  drain_atomics();
   return res;
 }
 
@@ -497,7 +510,7 @@ __device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uin
  * waiter left just before the exchange, the scan goes on after it. A ticket that has not
  * announced its page yet is granted the lock like any other. */
 __device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket, uint64_t lo, uint64_t hi) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  drain_atomics();
   const uint32_t l = lane();
   uint64_t n = ticket + 1;
   bool look = hi > lo;
@@ -1152,7 +1165,7 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       uint64_t cl = 0;
       if (l < GFS_CLAIMS) cl = ld_rlx(&d->claims[file].e[l]);
       const uint64_t npages = d->files[file].npages;
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      drain_atomics();   /* the table probe below goes out after the claims were read */
       const bool cl_on = l < GFS_CLAIMS && (cl & 1ull);
       const uint64_t cl_lo = cl >> 32, cl_hi = (cl >> 32) + ((cl & 0xffffffffull) >> 1);
       const bool covered = __ballot(cl_on && cl_lo <= p && p < cl_hi) != 0;
