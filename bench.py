@@ -119,6 +119,41 @@ def run_steps(torch, cache, fid, reader, steps: int, warmup: int):
     return wall, kms, st
 
 
+def fast_storage(torch, gfs, runner, configs, wl, cap_bytes, args, h2d):
+    """The same cold passes with the file on tmpfs (a copy in /dev/shm, removed afterwards):
+    storage is then no longer the bound and the pinned host-to-device rate is. Returns the
+    rates with readahead and without, or None if tmpfs has no room for the file."""
+    import shutil
+    import tempfile
+
+    import numpy as np
+    base = "/dev/shm" if os.path.isdir("/dev/shm") else tempfile.gettempdir()
+    if shutil.disk_usage(base).free < wl.file.size + (1 << 30):
+        return None
+    ddir = tempfile.mkdtemp(prefix="gfs_bench_", dir=base)
+    try:
+        path = configs.ensure_file(wl.file, ddir)
+        out = {}
+        for label, cap in (("ra", cap_bytes), ("no_ra", 0)):
+            cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=cap, host_threads=args.host_threads,
+                                     rpc_slots=args.rpc_slots, timeout_s=60, io_chunk_bytes=args.io_chunk_kib << 10)
+            with gfs.PageCache(cfg) as cache:
+                fid = cache.open(path)
+                reader = runner.ListReader(wl.offsets, wl.read_size, wl.consumer, wl.threads)
+                wall, kms, st = run_steps(torch, cache, fid, reader, 3, 1)
+                res = reader.result()
+            if st["timeouts"] or st["io_errors"]:
+                raise RuntimeError(f"tmpfs {label}: device errors {st}")
+            if not np.array_equal(res.status, np.full(wl.blocks, wl.delivered_bytes // wl.blocks)):
+                raise RuntimeError(f"tmpfs {label}: wrong delivered byte counts")
+            out[label] = wl.delivered_bytes * 3 / wall / 1e9
+        return {"data_dir": "tmpfs", "GBps": round(out["ra"], 3), "readahead_off_GBps": round(out["no_ra"], 3),
+                "readahead_speedup": round(out["ra"] / out["no_ra"], 3), "h2d_peak_GBps": round(h2d, 3),
+                "frac_of_h2d_peak": round(out["ra"] / h2d, 3), "steps": 3}
+    finally:
+        shutil.rmtree(ddir, ignore_errors=True)
+
+
 def hit_path(torch, gfs, runner, configs, ddir, host_threads):
     """All-hit passes: a 1 GiB file held entirely in a 2 GiB cache, read after one cold pass;
     each later pass is lookup + pin + copy-out + consumer only."""
@@ -510,6 +545,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3a", "c3b", "c3c", "c4", "c5", "f3", "f4", "hit"])
     ap.add_argument("--no-hit-path", action="store_true")
+    ap.add_argument("--no-tmpfs", action="store_true", help="skip the same passes from a tmpfs copy of the file")
     ap.add_argument("--autotune", action="store_true", help="c4: search page size, cap and blocks per file")
     ap.add_argument("--rates", default="200", help="c5: comma-separated arrival rates per second")
     ap.add_argument("--policy", default="shared", choices=["shared", "private"],
@@ -627,6 +663,12 @@ def main() -> int:
     del calib_src, calib_dst
 
     hit = None if args.no_hit_path else hit_path(torch, gfs, runner, configs, ddir, args.host_threads)
+    fast = None
+    if not args.no_tmpfs and not ddir.startswith("/dev/shm"):
+        fast = fast_storage(torch, gfs, runner, configs, wl, cap_bytes, args, h2d)
+        if fast:
+            log(f"tmpfs: {fast['GBps']:.2f} GB/s ({fast['frac_of_h2d_peak']:.3f} of pinned H2D), "
+                f"readahead off {fast['readahead_off_GBps']:.2f} GB/s")
     if hit:
         log(f"hit path: {hit['delivered_GBps']:.1f} GB/s delivered, {hit['hbm_GBps']:.1f} GB/s HBM")
 
@@ -691,6 +733,7 @@ def main() -> int:
                      "kernel": "list_reader_kernel", "kernel_ms": round(kms_ra, 2),
                      "bytes_per_launch": 3 * delivered},
         "hit_path": hit,
+        "tmpfs": fast,
         "kernel_GBps": {k: round(v["kernel_GBps"], 3) for k, v in results.items()},
         "step_min_max_GBps": {k: [round(v["step_min_GBps"], 3), round(v["step_max_GBps"], 3)]
                               for k, v in results.items()},
