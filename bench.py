@@ -537,9 +537,11 @@ def main() -> int:
     ap.add_argument("--data-dir", default=None, help="where the synthetic files live")
     ap.add_argument("--ra-cap-mib", type=int, default=None,
                     help="readahead cap (default: the workload's own; 16 MiB for c4/c5)")
-    ap.add_argument("--host-threads", type=int, default=8)
+    # 32 reads of 4 MiB in flight: on the virtio disk 12 % faster than 8 x 2 MiB over five
+    # alternating same-box runs (3.42-3.75 against 2.95-3.26 GB/s)
+    ap.add_argument("--host-threads", type=int, default=32)
     ap.add_argument("--rpc-slots", type=int, default=64)
-    ap.add_argument("--io-chunk-kib", type=int, default=2048,
+    ap.add_argument("--io-chunk-kib", type=int, default=4096,
                     help="size of the pieces a host request is read in (one per free host thread)")
     ap.add_argument("--no-ra-off", action="store_true", help="skip the readahead-off comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")

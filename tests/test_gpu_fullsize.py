@@ -18,7 +18,8 @@ from gpu_util import decode_replay, expected
 pytestmark = pytest.mark.gpu
 
 RA_CAP_LARGE = 16 << 20                # windows of 64 pages
-HOST_THREADS = 8
+HOST_THREADS = 32       # bench.py's launch configuration
+IO_CHUNK = 4 << 20
 RPC_SLOTS = 64
 
 
@@ -48,7 +49,8 @@ def test_c2_full_size_parity_and_trace_replay(ra_cap, data_dir, cuda):
     path = configs.ensure_file(wl.file, data_dir)
     _say(f"c2 full size, ra cap {ra_cap >> 20} MiB")
     cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=ra_cap, host_threads=HOST_THREADS,
-                             rpc_slots=RPC_SLOTS, trace_level=1, trace_capacity=1 << 21, timeout_s=60)
+                             rpc_slots=RPC_SLOTS, trace_level=1, trace_capacity=1 << 21, timeout_s=60,
+                             io_chunk_bytes=IO_CHUNK)
     with gfs.PageCache(cfg) as cache:
         fid = cache.open(path)
         res = runner.run_list(cache, fid, wl.offsets, wl.read_size, wl.consumer, threads=wl.threads)
@@ -88,7 +90,7 @@ def test_c3_full_size_parity(pattern, ra_cap, data_dir, cuda):
     path = configs.ensure_file(wl.file, data_dir)
     _say(f"c3{pattern} full size, ra cap {ra_cap >> 20} MiB")
     cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=ra_cap, host_threads=HOST_THREADS,
-                             rpc_slots=RPC_SLOTS, timeout_s=90)
+                             rpc_slots=RPC_SLOTS, timeout_s=90, io_chunk_bytes=IO_CHUNK)
     with gfs.PageCache(cfg) as cache:
         fid = cache.open(path)
         res = runner.run_list(cache, fid, wl.offsets, wl.read_size, wl.consumer, threads=wl.threads)
