@@ -71,9 +71,9 @@ def _cap_mib(args, default: int = 16) -> int:
     return args.ra_cap_mib if args.ra_cap_mib is not None else default
 
 
-def storage_peak(path: str, threads: int = 16, chunk: int = 4 << 20, limit: int = 8 << 30) -> float:
-    """Sequential read rate of the file by 16 native threads reading 4 MiB pieces with
-    O_DIRECT where allowed (64 MiB in flight), GB/s."""
+def storage_peak(path: str, threads: int = 32, chunk: int = 4 << 20, limit: int = 8 << 30) -> float:
+    """Sequential read rate of the file by 32 native threads reading 4 MiB pieces with
+    O_DIRECT where allowed (128 MiB in flight, the depth the benchmarks read at), GB/s."""
     from workloads import configs
     return configs.read_peak([path], threads=threads, chunk=chunk, limit=limit)
 
@@ -135,8 +135,9 @@ def fast_storage(torch, gfs, runner, configs, wl, cap_bytes, args, h2d):
         path = configs.ensure_file(wl.file, ddir)
         out = {}
         for label, cap in (("ra", cap_bytes), ("no_ra", 0)):
-            cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=cap, host_threads=args.host_threads,
-                                     rpc_slots=args.rpc_slots, timeout_s=60, io_chunk_bytes=args.io_chunk_kib << 10)
+            # reads from memory need few host threads; more only compete for the CPUs
+            cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=cap, host_threads=8,
+                                     rpc_slots=args.rpc_slots, timeout_s=60, io_chunk_bytes=2 << 20)
             with gfs.PageCache(cfg) as cache:
                 fid = cache.open(path)
                 reader = runner.ListReader(wl.offsets, wl.read_size, wl.consumer, wl.threads)
@@ -149,7 +150,7 @@ def fast_storage(torch, gfs, runner, configs, wl, cap_bytes, args, h2d):
             out[label] = wl.delivered_bytes * 3 / wall / 1e9
         return {"data_dir": "tmpfs", "GBps": round(out["ra"], 3), "readahead_off_GBps": round(out["no_ra"], 3),
                 "readahead_speedup": round(out["ra"] / out["no_ra"], 3), "h2d_peak_GBps": round(h2d, 3),
-                "frac_of_h2d_peak": round(out["ra"] / h2d, 3), "steps": 3}
+                "frac_of_h2d_peak": round(out["ra"] / h2d, 3), "steps": 3, "host_threads": 8}
     finally:
         shutil.rmtree(ddir, ignore_errors=True)
 
@@ -537,8 +538,8 @@ def main() -> int:
     ap.add_argument("--data-dir", default=None, help="where the synthetic files live")
     ap.add_argument("--ra-cap-mib", type=int, default=None,
                     help="readahead cap (default: the workload's own; 16 MiB for c4/c5)")
-    # 32 reads of 4 MiB in flight: on the virtio disk 12 % faster than 8 x 2 MiB over five
-    # alternating same-box runs (3.42-3.75 against 2.95-3.26 GB/s)
+    # 32 reads of 4 MiB in flight: the virtio disk serves deep queues better (same-box runs:
+    # 8 x 2 MiB 2.85-3.26 GB/s, 32 x 4 MiB 3.16-3.86; 64 x 4 MiB ranged 2.75-4.69)
     ap.add_argument("--host-threads", type=int, default=32)
     ap.add_argument("--rpc-slots", type=int, default=64)
     ap.add_argument("--io-chunk-kib", type=int, default=4096,

@@ -221,7 +221,7 @@ def build_readpeak(force: bool = False) -> str:
     return _PEAK_BIN
 
 
-def read_peak(paths, threads: int = 16, chunk: int = 4 << 20, limit: int = 8 << 30) -> float:
+def read_peak(paths, threads: int = 32, chunk: int = 4 << 20, limit: int = 8 << 30) -> float:
     """Sequential read rate (10^9 B/s) of the largest of `paths`, up to `limit` bytes in all,
     by `threads` native threads reading `chunk`-byte pieces (O_DIRECT where allowed)."""
     order = sorted(paths, key=os.path.getsize, reverse=True)
