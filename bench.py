@@ -38,6 +38,7 @@ def log(msg: str) -> None:
 KERNEL_SOURCES = ("include/gfs_device.h", "include/gfs_layout.h", "include/gfs.h",
                   "paper_2109_05366_amd/csrc/gfs_kernels.hip", "paper_2109_05366_amd/csrc/gfs_consumers.h")
 TRAFFIC_SUMMARY = "profiles/list_reader_c2_hbm_traffic.md"
+HIT_TRAFFIC_SUMMARY = "profiles/list_reader_hit_hbm_traffic.md"
 
 
 def kernel_source_hash() -> str:
@@ -49,21 +50,23 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """(bytes per launch, summary file) from the committed counter summary, if it was taken
+def recorded_traffic(summary: str = TRAFFIC_SUMMARY, key: str = "traffic_bytes_per_launch"):
+    """(bytes per launch, summary file) from a committed counter summary, if it was taken
     on the current kernel sources; else (None, reason)."""
-    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    path = os.path.join(ROOT, summary)
     if not os.path.exists(path):
         return None, "no counter summary"
     fields = {}
     with open(path) as fh:
         for line in fh:
-            if ":" in line and line.split(":", 1)[0].strip() in ("kernel_source_sha256", "traffic_bytes_per_launch"):
+            if ":" in line and line.split(":", 1)[0].strip() in ("kernel_source_sha256", key):
                 k, v = line.split(":", 1)
-                fields[k.strip()] = v.strip().strip("`")
+                fields[k.strip()] = v.strip().strip("`").split()[0]
     if fields.get("kernel_source_sha256") != kernel_source_hash():
         return None, "kernel changed since the counters were taken"
-    return int(fields["traffic_bytes_per_launch"]), TRAFFIC_SUMMARY
+    if key not in fields:
+        return None, f"no {key} in the counter summary"
+    return int(fields[key]), summary
 
 
 def _cap_mib(args, default: int = 16) -> int:
@@ -184,10 +187,12 @@ def hit_path(torch, gfs, runner, configs, ddir, host_threads):
     hk = float(np.median(hms))
     # algorithmic HBM bytes per delivered byte on a hit: frame read + user-buffer write
     # (+ the consumer's read of the user buffer, which is the benchmark, not the method)
+    traffic, traffic_src = recorded_traffic(HIT_TRAFFIC_SUMMARY, "traffic_bytes_per_launch_1024x16")
     return {"workload": "1 GiB file cached in a 2 GiB cache (64 KiB pages), 1024 blocks x 16 reads "
                         "of 64 KiB, all hits", "kernel_ms": hk,
             "delivered_GBps": hbytes / (hk * 1e-3) / 1e9,
             "hbm_GBps": 3 * hbytes / (hk * 1e-3) / 1e9,
+            "traffic": traffic, "traffic_source": traffic_src,
             "misses_after_warm": s1["misses"] - s0["misses"]}
 
 
@@ -455,9 +460,16 @@ def bench_hits(args, torch) -> int:
                        "per_page_us": {"acquire": round(d["t_acquire_ns"], 2), "copy": round(d["t_copy_ns"], 2),
                                        "unpin": round(d["t_unpin_ns"], 2)}})
         log(f"hits {blocks} x {reads}: {shapes[-1]}")
+    # calibration for HBM traffic counters: a plain 1 GiB device-to-device copy (known bytes)
+    calib_src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    torch.empty_like(calib_src).copy_(calib_src)
+    torch.cuda.synchronize()
+    del calib_src
     best = max(shapes, key=lambda x: x["delivered_GBps"])
     # algorithmic HBM bytes per delivered byte: frame read + user-buffer write + checksum read
     achieved = 3 * best["delivered_GBps"]
+    traffic, traffic_src = recorded_traffic(HIT_TRAFFIC_SUMMARY,
+                                            f"traffic_bytes_per_launch_{best['blocks']}x{best['reads']}")
     line = {
         "metric": "delivered GB/s of all-hit reads (the cache's HBM-bound path)",
         "value": best["delivered_GBps"], "unit": "GB/s", "n_gpus": 1, "steps": max(args.steps, 1), "warmup": 1,
@@ -465,8 +477,9 @@ def bench_hits(args, torch) -> int:
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": "hit: 1 GiB splitmix64(seed=9) file in a 2 GiB cache of 64 KiB pages, 64 KiB reads"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 3), "traffic": None,
-                     "kernel": "list_reader_kernel", "bytes_per_launch": 3 << 30},
+                     "frac": round(achieved / HBM_PEAK_GBS, 3), "traffic": traffic,
+                     "traffic_source": traffic_src, "kernel": "list_reader_kernel",
+                     "bytes_per_launch": 3 << 30},
         "shapes": shapes,
     }
     print(json.dumps(line), flush=True)
