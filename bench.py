@@ -9,10 +9,12 @@ O_DIRECT (or buffered reads after POSIX_FADV_DONTNEED where the file system has 
 O_DIRECT), so each step reads the whole file from storage.
 
 Measured in the same run: the storage peak (O_DIRECT sequential read of the same file
-with 4 threads, 4 MiB requests), the pinned host-to-device copy peak (256 MiB), the
-readahead-off rate of the same code, the list-reader kernel duration (HIP events on its
-stream), an all-hit pass over a cached file (the kernel's HBM-bound hit path), and the
-CPU oracle on a bounded sample. Prints one JSON line.
+by 32 native threads in 4 MiB requests, sampled before and after the timed passes), the
+pinned host-to-device copy peak (256 MiB), the readahead-off rate of the same code, the
+list-reader kernel duration (HIP events on its stream), the same passes from a tmpfs copy
+of the file (where the pinned copy, not storage, is the bound), an all-hit pass over a
+cached file (the kernel's HBM-bound hit path), and the CPU oracle on a bounded sample.
+Prints one JSON line.
 """
 from __future__ import annotations
 
