@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define GFS_ABI_VERSION 1u
+#define GFS_ABI_VERSION 2u
 
 /* limits of the encoding (page-table entry = file:11 | page:28 | frame:24 bits) */
 #define GFS_MAX_FILES 1024u
@@ -38,6 +38,7 @@ extern "C" {
 #define GFS_MAX_FRAMES (1u << 24)
 #define GFS_MAX_STREAMS 8u
 #define GFS_MAX_WINDOW_PAGES 1024u   /* readahead cap, in pages */
+#define GFS_MAX_RECENT 64u           /* detector: recent misses remembered per file (one per lane) */
 
 /* Threads per block of the library's workload kernels. gread is inlined into its caller;
  * at 256 threads the compiler keeps the whole miss path in registers (about 220 VGPRs, no
@@ -89,7 +90,24 @@ typedef struct gfs_config {
                                     reads in flight); a multiple of 4 KiB, 64 KiB .. 64 MiB; each
                                     host thread holds one bounce buffer of this size for
                                     O_DIRECT reads */
-  uint32_t reserved0;            /* must be 0 */
+  uint32_t max_files;            /* files registered at once (ids 0..max_files-1), 1..GFS_MAX_FILES;
+                                    sizes the per-file metadata (about 34 KiB per file) */
+  /* Readahead detector (Sec. 2.3: Linux also follows several readers that interleave on one
+     file, by heuristics the paper does not spell out; these are the constants of this library's
+     aggregate-reading rule). A
+     miss at page p whose file has at least ra_near_min of its last ra_recent misses within
+     ra_near_pages pages of p opens the window as the aligned chunk around p. */
+  uint32_t ra_recent;            /* misses remembered per file, 1..GFS_MAX_RECENT */
+  uint32_t ra_near_pages;        /* "near" radius in pages, 0..2^20 */
+  uint32_t ra_near_min;          /* near misses that make the file read in aggregate, 1..ra_recent+1
+                                    (ra_recent + 1 switches the rule off) */
+  /* Thrash guard (Sec. 5.1: each resident threadblock's share of the cache is cache / resident
+     threadblocks): a window is at most cache_pages / R pages, R = min(blocks in the launch,
+     ra_quota_blocks). 0 = the device's resident blocks of 256-thread reader kernels (found at
+     gfs_init); 1 = no guard (R = 1). */
+  uint32_t ra_quota_blocks;
+  uint32_t ra_async;             /* 0 = synchronous prefetch (the paper's choice, Sec. 4
+                                    "Asynchronous operation"); 1 = marker-triggered (Sec. 2.3) */
 } gfs_config;
 
 /* Fill *cfg with defaults: 64 KiB pages, 256 MiB cache, readahead 4 pages growing to
@@ -136,8 +154,11 @@ int gfs_open(gfs_ctx* ctx, const char* path, int flags, int* file_id);
  * stream with the initial window, GFS_ADV_NORMAL restores the default. */
 int gfs_fadvise(gfs_ctx* ctx, int file_id, int advice);
 
-/* Unregister a file. -EBUSY if a kernel still holds it open (gopen without gclose);
- * cached pages of the file stay until they are evicted or the cache is reset. */
+/* Unregister a file (the host half of Sec. 2.2's close). Every cached page, reservation and
+ * readahead stream of the file is dropped and its frames become free, because a later
+ * gfs_open may hand the same id to another file. Must not run concurrently with kernels
+ * using the context. -EBADF if file_id is not registered, -EBUSY if a kernel still holds it
+ * open (gopen without gclose; the file stays registered), -EIO on a HIP error. */
 int gfs_close(gfs_ctx* ctx, int file_id);
 
 /* Device pointer to the cache handle; pass it to kernels that call gread. */
@@ -210,14 +231,23 @@ typedef struct gfs_event {
 enum {
   GFS_EV_HIT = 1,    /* file,page,frame                                         */
   GFS_EV_JOIN = 2,   /* file,page,frame                                         */
-  GFS_EV_MISS = 3,   /* file,page; a = window length (EOF-clamped), b = window start,
-                        frame = recent misses of the file near page (detector input) */
-  GFS_EV_HAND = 4,   /* frame; b = ticket; a = action | ra<<8; file,page = victim (EVICT) */
+  GFS_EV_MISS = 3,   /* file,page; a = window length (EOF-clamped), b = window start;
+                        frame = near | h << 8 | rule << 24: the detector's inputs and choice --
+                        near = the file's recent misses near page, h = cached pages right
+                        behind page (counted only when no stream zone or the aggregate rule
+                        applies), rule = GFS_RA_RULE_* */
+  GFS_EV_HAND = 4,   /* frame; b = ticket; file,page = victim (EVICT); a = action | x << 8,
+                        x = victim prefetched (EVICT) | ref bit seen << 1 | pinned << 2 |
+                        lost a compare-and-swap << 3 | frame state seen << 4 */
   GFS_EV_ALLOC = 5,  /* file,page,frame; a = ra (1 if prefetched), b = hand ticket */
   GFS_EV_REQ = 6,    /* file, page = first page, a = pages in span, b = ring ticket */
   GFS_EV_NOFRAME = 7, /* file,page: window cut short, no frame left             */
   GFS_EV_PBHIT = 8    /* private policy: file,page,frame filled from the private buffer */
 };
+/* readahead rules (GFS_EV_MISS): off (readahead off or RANDOM advice), a stream's zone,
+   aggregate reading, context (cached history behind the page), a new stream (W0 or 1) */
+enum { GFS_RA_RULE_OFF = 0, GFS_RA_RULE_ZONE = 1, GFS_RA_RULE_AGGREGATE = 2, GFS_RA_RULE_CONTEXT = 3,
+       GFS_RA_RULE_NEW = 4 };
 enum { GFS_HAND_FREE = 0, GFS_HAND_SKIP = 1, GFS_HAND_CLEAR = 2, GFS_HAND_EVICT = 3 };
 
 /* Copy up to cap_bytes of recorded events (in record order) to host memory dst;
@@ -292,7 +322,8 @@ int gfs_batch_grid(uint32_t threads, uint32_t* grid);
 /* Size in bytes of a registered file (host only). -EBADF if file_id is not registered. */
 int gfs_file_size(gfs_ctx* ctx, int file_id, uint64_t* size);
 
-/* The configuration the context was created with (host only). */
+/* The configuration the context was created with (host only), with ra_quota_blocks resolved
+ * to the count in use when it was 0. */
 int gfs_get_config(gfs_ctx* ctx, gfs_config* out);
 
 /* ---- serving loop (a stream of whole-file read requests, one persistent kernel) ----

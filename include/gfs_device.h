@@ -349,20 +349,33 @@ __device__ int frame_pin(const gfs_dev* d, uint32_t f, uint64_t key) {
 }
 
 /* One clock step at frame f (per lane). FREE or EVICT leave the frame CLAIMED by the
- * caller; EVICT reports the victim's key and prefetched mark. */
-__device__ int hand_visit(const gfs_dev* d, uint32_t f, uint64_t& vkey, uint32_t& vra) {
+ * caller; EVICT reports the victim's key and prefetched mark. `seen` receives what the step
+ * decided on, for the trace: the reference bit << 1 | pinned << 2 | lost race << 3 |
+ * state << 4 (the word was read, then a compare-and-swap against it failed: SKIP). */
+__device__ int hand_visit(const gfs_dev* d, uint32_t f, uint64_t& vkey, uint32_t& vra, uint32_t& seen) {
   uint64_t* fw = &d->fword[f];
   uint64_t w = ld_rlx(fw);
   const uint64_t tag = ld_rlx(&d->ftag[f]);   /* loaded with the word; used only on EVICT */
   const uint64_t st = w & GFS_FW_STATE;
   const uint64_t claimed = (((w >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT) | GFS_FS_CLAIMED;
+  seen = ((w & GFS_FW_REF) ? 2u : 0u) | ((w & GFS_FW_PINS) ? 4u : 0u) | ((uint32_t)st << 4);
   if (w & GFS_FW_PINS) return GFS_HAND_SKIP;
-  if (st == GFS_FS_FREE) return cas64(fw, w, claimed) ? GFS_HAND_FREE : GFS_HAND_SKIP;
+  if (st == GFS_FS_FREE) {
+    if (cas64(fw, w, claimed)) return GFS_HAND_FREE;
+    seen |= 8u;
+    return GFS_HAND_SKIP;
+  }
   if (st != GFS_FS_VALID) return GFS_HAND_SKIP;
-  if (w & GFS_FW_REF)
-    return cas64_rlx(fw, w, (w & ~GFS_FW_REF) + GFS_FW_VER_ONE) ? GFS_HAND_CLEAR : GFS_HAND_SKIP;
+  if (w & GFS_FW_REF) {
+    if (cas64_rlx(fw, w, (w & ~GFS_FW_REF) + GFS_FW_VER_ONE)) return GFS_HAND_CLEAR;
+    seen |= 8u;
+    return GFS_HAND_SKIP;
+  }
   const uint64_t old = w;
-  if (!cas64(fw, w, claimed)) return GFS_HAND_SKIP;
+  if (!cas64(fw, w, claimed)) {
+    seen |= 8u;
+    return GFS_HAND_SKIP;
+  }
   /* the tag read with the word is still the frame's: a tag is rewritten only by the block
      that claims the frame, and the CAS just succeeded against the word read with it */
   vkey = tag;
@@ -571,7 +584,7 @@ __device__ __forceinline__ RaState ra_load_lane(const gfs_dev* d, uint32_t file)
   st.advice = ld_rlx32(&fe->advice);
   if (l == 0) st.clk = ld_rlx32(&fe->clock);
   st.rn = ld_rlx32(&fe->recent_n);
-  if (l < GFS_RECENT_MISSES) st.r = ld_rlx(&fe->recent[l]);
+  if (l < d->ra_recent) st.r = ld_rlx(&fe->recent[l]);
   if (l < d->streams) {
     gfs_stream* sp = &fe->streams[l];
     st.s_next = ld_rlx(&sp->next);
@@ -582,16 +595,35 @@ __device__ __forceinline__ RaState ra_load_lane(const gfs_dev* d, uint32_t file)
   return st;
 }
 
+/* Which rule decided a window (GFS_RA_RULE_*, recorded in the trace with the detector's inputs). */
+enum { RA_RULE_OFF = GFS_RA_RULE_OFF, RA_RULE_ZONE = GFS_RA_RULE_ZONE, RA_RULE_AGGREGATE = GFS_RA_RULE_AGGREGATE,
+       RA_RULE_CONTEXT = GFS_RA_RULE_CONTEXT, RA_RULE_NEW = GFS_RA_RULE_NEW };
+
+/* The largest window a decision may take: the configured cap, clipped to the share of the
+   cache one resident block may hold (Sec. 5.1's quota: cache pages over the blocks reading at
+   once, the smaller of the launch's grid and the configured resident count), so that the
+   windows of all resident readers together do not exceed the cache. */
+__device__ __forceinline__ uint32_t ra_cap_eff(const gfs_dev* d) {
+  const uint64_t grid = (uint64_t)gridDim.x * gridDim.y * gridDim.z;
+  const uint64_t r = grid < d->ra_quota_blocks ? grid : d->ra_quota_blocks;
+  uint64_t q = d->nframes / (r ? r : 1);
+  if (q < 1) q = 1;
+  return d->ra_cap < q ? d->ra_cap : (uint32_t)q;
+}
+
 __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, const RaState& st, uint64_t& ws,
-                               uint32_t& wn, uint32_t& near_out) {
+                               uint32_t& wn, uint32_t& near_out, uint32_t& h_out, uint32_t& rule_out) {
   gfs_file_dev* fe = &d->files[file];
   const uint32_t advice = st.advice;
   ws = p;
   wn = 1;
   near_out = 0;
+  h_out = 0;
+  rule_out = RA_RULE_OFF;
   if (d->ra_cap == 0 || advice == GFS_ADV_RANDOM) return;
   const uint32_t l = lane();
-  const uint32_t cap = d->ra_cap;
+  const uint32_t cap = ra_cap_eff(d);
+  const uint32_t nrec = d->ra_recent;
   uint32_t clk = st.clk;
   const uint32_t rn = st.rn;
   const uint64_t r = st.r;
@@ -599,13 +631,13 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, cons
   const uint32_t s_size = st.s_size, s_last = st.s_last, s_valid = st.s_valid;
   clk = __shfl(clk, 0, 64) + 1;
   /* how many of the file's last misses lie near p; then remember p */
-  const uint64_t radius = GFS_NEAR_PAGES;
-  const bool near_l = l < GFS_RECENT_MISSES && l < rn && r + radius >= p && r <= p + radius;
+  const uint64_t radius = d->ra_near_pages;
+  const bool near_l = l < nrec && l < rn && r + radius >= p && r <= p + radius;
   const uint32_t near = (uint32_t)__popcll(__ballot(near_l));
   near_out = near;
   if (l == 0) {
     st_rlx32(&fe->clock, clk);
-    st_rlx(&fe->recent[rn % GFS_RECENT_MISSES], p);
+    st_rlx(&fe->recent[rn % nrec], p);
     st_rlx32(&fe->recent_n, rn + 1);
   }
   const bool cov = l < d->streams && s_valid && s_next <= p && p < s_next + s_size;
@@ -618,6 +650,7 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, cons
     const uint32_t sz = __shfl(s_size, j, 64);
     ws = nx;
     wn = 2 * sz < cap ? 2 * sz : cap;
+    rule_out = RA_RULE_ZONE;
   } else {
     const uint64_t inv = __ballot(l < d->streams && !s_valid);
     if (inv) {
@@ -630,11 +663,12 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, cons
       }
       j = (int)(k & 0xff);
     }
-    if (near >= GFS_NEAR_MIN) {
+    if (near >= d->ra_near_min) {
       /* many blocks missing close together: the file is read in aggregate (interleaved
          strides); take the cap-sized chunk aligned around p */
       wn = cap;
       ws = p - p % cap;
+      rule_out = RA_RULE_AGGREGATE;
     } else {
       /* context: count the consecutive cached pages right behind p (64 per round); a
          stream that no slot tracks shows up as that history */
@@ -649,12 +683,18 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, cons
         if (run < 64) break;
       }
       uint32_t w0;
-      if (h > 0) w0 = 2 * h;
-      else w0 = (p == 0 || advice == GFS_ADV_SEQUENTIAL) ? d->ra_init : 1u;
+      if (h > 0) {
+        w0 = 2 * h;
+        rule_out = RA_RULE_CONTEXT;
+      } else {
+        w0 = (p == 0 || advice == GFS_ADV_SEQUENTIAL) ? d->ra_init : 1u;
+        rule_out = RA_RULE_NEW;
+      }
       if (w0 > cap) w0 = cap;
       if (w0 < 1) w0 = 1;
       ws = p;
       wn = w0;
+      h_out = h;
     }
   }
   if (l == 0) {
@@ -689,17 +729,17 @@ __device__ uint32_t alloc_wave(const gfs_dev* d, uint32_t file, uint64_t demand,
     int act = -1;
     uint32_t f = 0;
     uint64_t vkey = 0;
-    uint32_t vra = 0;
+    uint32_t vra = 0, seen = 0;
     const uint64_t t = base + l;
     if (l < need) {
       f = (uint32_t)(t % d->nframes);
-      act = hand_visit(d, f, vkey, vra);
+      act = hand_visit(d, f, vkey, vra, seen);
       if (act == GFS_HAND_EVICT) {
         const uint32_t vf = (uint32_t)(vkey >> GFS_KEY_PAGE_BITS) - 1u;
         const uint32_t vp = (uint32_t)(vkey & ((1ull << GFS_KEY_PAGE_BITS) - 1));
-        trace_ev(d, 1, GFS_EV_HAND, bid, vf, vp, f, GFS_HAND_EVICT | (vra << 8), t);
+        trace_ev(d, 1, GFS_EV_HAND, bid, vf, vp, f, GFS_HAND_EVICT | (vra << 8) | (seen << 8), t);
       } else {
-        trace_ev(d, 1, GFS_EV_HAND, bid, 0xffffffffu, 0xffffffffu, f, (uint32_t)act, t);
+        trace_ev(d, 1, GFS_EV_HAND, bid, 0xffffffffu, 0xffffffffu, f, (uint32_t)act | (seen << 8), t);
       }
     }
     const bool ok = (act == GFS_HAND_FREE || act == GFS_HAND_EVICT);
@@ -1185,13 +1225,14 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       }
       /* miss: decide the window, clip it to stay out of running claims, claim it, unlock */
       uint64_t ws;
-      uint32_t wn, near;
+      uint32_t wn, near, hist, rule;
       const uint64_t td0 = wall_clock64();
-      ra_decide_wave(d, file, p, ras, ws, wn, near);
+      ra_decide_wave(d, file, p, ras, ws, wn, near, hist, rule);
       const uint64_t td1 = wall_clock64();
       if (l == 0) bcount(bs, GFS_T_DECIDE, td1 - td0);
       if (ws + wn > npages) wn = (uint32_t)(npages - ws);
-      if (l == 0) trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, near, wn, ws);
+      if (l == 0)
+        trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, (near & 0xffu) | (hist << 8) | (rule << 24), wn, ws);
       uint64_t cws = ws, cwe = ws + wn;
       {
         uint64_t lo_b = cl_on && cl_hi <= p ? cl_hi : 0;
@@ -1606,7 +1647,7 @@ __device__ int gopen_id(const gfs_dev* d, int file_id, int flags) {
     int v;
     if (flags != GFS_O_RDONLY) {
       v = -gfsd::kEROFS;
-    } else if (file_id < 0 || (uint32_t)file_id >= GFS_MAX_FILES ||
+    } else if (file_id < 0 || (uint32_t)file_id >= d->max_files ||
                gfsd::ld_rlx32(&d->files[file_id].open) == 0) {
       v = -gfsd::kENOENT;
     } else {
@@ -1654,7 +1695,7 @@ __device__ int gopen(const gfs_dev* d, const char* path, int flags) {
   gfsd::BlockState* bs = gfsd::block_state();
   if (gfsd::thread_id() == 0) {
     int id = -1;
-    for (uint32_t i = 0; i < GFS_MAX_FILES && id < 0; ++i) {
+    for (uint32_t i = 0; i < d->max_files && id < 0; ++i) {
       if (gfsd::ld_rlx32(&d->files[i].open) == 0) continue;
       const char* nm = d->names + (uint64_t)i * GFS_NAME_MAX;
       uint32_t j = 0;
@@ -1672,7 +1713,7 @@ __device__ int gopen(const gfs_dev* d, const char* path, int flags) {
 }
 
 __device__ int gclose(const gfs_dev* d, int fd) {
-  if (fd < 0 || (uint32_t)fd >= GFS_MAX_FILES) return -gfsd::kEBADF;
+  if (fd < 0 || (uint32_t)fd >= d->max_files) return -gfsd::kEBADF;
   gfsd::BlockState* bs = gfsd::block_state();
   __syncthreads();
   if (gfsd::thread_id() == 0) {
@@ -1698,7 +1739,7 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
                                                         uint64_t size, void* dst) {
   using namespace gfsd;
   BlockState* bs = block_state();
-  if (fd < 0 || (uint32_t)fd >= GFS_MAX_FILES) return -kEBADF;
+  if (fd < 0 || (uint32_t)fd >= d->max_files) return -kEBADF;
   gfs_file_dev* fe = &d->files[fd];
   if (ld_rlx32(&fe->open) == 0) return -kEBADF;
   const uint32_t nt = block_threads();

@@ -7,12 +7,12 @@
  * HBM layout of the metadata region (offsets computed by the host, stored in gfs_dev):
  *   gfs_globals                      320 B
  *   gfs_dev (the handle)             512 B
- *   files[GFS_MAX_FILES]             768 B each
- *   locks[GFS_MAX_FILES]             128 B each (miss ticket locks)
- *   lockq[GFS_MAX_FILES][GFS_LOCK_SLOTS] u64   queue slots of the miss locks
- *   claims[GFS_MAX_FILES]            128 B each (windows being reserved)
+ *   files[max_files]                 768 B each
+ *   locks[max_files]                 128 B each (miss ticket locks)
+ *   lockq[max_files][GFS_LOCK_SLOTS] u64   queue slots of the miss locks (32 KiB per file)
+ *   claims[max_files]                128 B each (windows being reserved)
  *   pslots[private_slots]            64 B each (private policy)
- *   names[GFS_MAX_FILES]             GFS_NAME_MAX B each (registered paths)
+ *   names[max_files]                 GFS_NAME_MAX B each (registered paths)
  *   fword[nframes]  u64              frame word (state, pins, ref, ra, version)
  *   ftag[nframes]   u64              key of the page held (valid while not FREE)
  *   pt[nbuckets*16] u64              hashed page table, 16-entry buckets (128 B)
@@ -81,9 +81,9 @@ enum {
 };
 typedef char gfs_counters_fit[(GFS_C_COUNT <= 32) ? 1 : -1];   /* gfs_globals.ctr */
 
-#define GFS_RECENT_MISSES 64   /* misses remembered per file by the readahead detector */
-#define GFS_NEAR_MIN 3         /* remembered misses near a miss that mark aggregate reading */
-#define GFS_NEAR_PAGES 64      /* "near" = within GFS_NEAR_PAGES pages */
+/* room for the readahead detector's recent misses (the configured count, ra_recent, is at
+   most this: one per lane of the deciding wave) */
+#define GFS_RECENT_MISSES 64
 
 typedef struct gfs_stream {
   uint64_t next;          /* first page after the last window */
@@ -114,9 +114,12 @@ typedef struct gfs_file_lock {
   uint64_t pad[15];
 } gfs_file_lock;          /* 128 B */
 
-/* queue slots of each file's miss lock (u32 each); at least the number of blocks the
-   device can hold at once (256 CUs x 32 waves) */
-#define GFS_LOCK_SLOTS 8192u
+/* queue slots of each file's miss lock (u64 each); at least the number of blocks that can
+   wait on one lock at once. Every block that calls gread holds at least GFS_BLOCK_LDS_MIN
+   bytes of LDS for its per-block state, so a CU holds at most LDS / GFS_BLOCK_LDS_MIN such
+   blocks (12 on a 160 KiB CU, 3072 on 256 CUs); gfs_init checks the device. */
+#define GFS_LOCK_SLOTS 4096u
+#define GFS_BLOCK_LDS_MIN 12288u
 
 /* window claims: a block that decided a window under the miss lock records it here and
    reserves the window's pages after unlocking; other misses inside an active claim wait for
@@ -181,6 +184,12 @@ typedef struct gfs_dev {
   uint32_t max_req_pages;
   uint32_t trace_level;
   uint32_t trace_cap;
+  uint32_t max_files;           /* file ids below this are valid */
+  uint32_t ra_recent;           /* detector: misses remembered per file (<= GFS_RECENT_MISSES) */
+  uint32_t ra_near_pages;       /* detector: "near" radius */
+  uint32_t ra_near_min;         /* detector: near misses that mark aggregate reading */
+  uint32_t ra_quota_blocks;     /* thrash guard: resident blocks the cache is shared by */
+  uint32_t pad_dev0;
   uint64_t max_req_bytes;
   uint64_t timeout_ticks;       /* wall_clock64 ticks */
   uint8_t* frames;
@@ -190,8 +199,8 @@ typedef struct gfs_dev {
   gfs_globals* g;
   gfs_file_dev* files;
   gfs_file_lock* locks;
-  uint64_t* lockq;              /* [GFS_MAX_FILES][GFS_LOCK_SLOTS] miss-lock queue slots */
-  gfs_file_claims* claims;      /* [GFS_MAX_FILES] windows being reserved */
+  uint64_t* lockq;              /* [max_files][GFS_LOCK_SLOTS] miss-lock queue slots */
+  gfs_file_claims* claims;      /* [max_files] windows being reserved */
   gfs_pslot* pslots;            /* private policy: [private_slots] */
   uint8_t* pbuf;                /* private policy: [private_slots][ra_cap pages] in the frames allocation */
   uint32_t policy;              /* GFS_POLICY_* */
@@ -204,7 +213,7 @@ typedef struct gfs_dev {
   gfs_req_dev* reqd;
   uint32_t* req_frames;
   void* trace;                  /* gfs_event[trace_cap] */
-  char* names;                  /* [GFS_MAX_FILES][GFS_NAME_MAX] registered paths */
+  char* names;                  /* [max_files][GFS_NAME_MAX] registered paths */
   gfs_rpc_slot* ring;           /* device-visible address of the pinned ring */
   uint8_t* staging;             /* device-visible address of the pinned staging */
 } gfs_dev;

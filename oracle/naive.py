@@ -20,12 +20,15 @@ def _find(frames, file_id, page):
 
 
 class NaiveModel:
-    def __init__(self, nframes, page_size, w0, cap, nstreams):
+    def __init__(self, nframes, page_size, w0, cap, nstreams, recent=64, reach=64, enough=3):
         self.frames = [[0, -1, -1, 0, 0, 0] for _ in range(nframes)]
         self.page_size = page_size
         self.w0 = w0
         self.cap = cap
         self.nstreams = nstreams
+        self.keep = recent        # misses remembered per file
+        self.reach = reach        # how far a remembered miss may be from p and still count
+        self.enough = enough      # close misses that mean the file is read in aggregate
         self.hand = 0
         self.size = {}
         self.advice = {}
@@ -48,13 +51,13 @@ class NaiveModel:
         now = self.tick[file_id]
         table = self.streams[file_id]
         hist = self.last_misses[file_id]
-        reach = 64
+        reach = self.reach
         close = 0
         for r in hist:
             if p - reach <= r <= p + reach:
                 close += 1
         hist.append(p)
-        while len(hist) > 64:
+        while len(hist) > self.keep:
             del hist[0]
         i = 0
         while i < len(table):
@@ -83,7 +86,7 @@ class NaiveModel:
                 if table[i][3] < table[slot][3]:
                     slot = i
         start = p
-        if close >= 3:
+        if close >= self.enough:
             n = self.cap
             start = p - p % n
         elif behind > 0:
@@ -108,17 +111,20 @@ class NaiveModel:
             visits += 1
             i = t % C
             fr = self.frames[i]
+            # what the hand found: ref bit, pinned, (never a lost race), state 0/2/3
+            code = 0 if fr[0] == 0 else (2 if fr[0] == 1 else 3)
+            found = fr[4] + 2 * (1 if fr[3] != 0 else 0) + 8 * code
             if fr[0] == 0:
-                self.log.append(("HAND", t, i, "FREE", -1, -1, 0))
+                self.log.append(("HAND", t, i, "FREE", -1, -1, 0, found))
                 return i
             if fr[0] == 1 or fr[3] != 0:
-                self.log.append(("HAND", t, i, "SKIP", -1, -1, 0))
+                self.log.append(("HAND", t, i, "SKIP", -1, -1, 0, found))
                 continue
             if fr[4] == 1:
                 fr[4] = 0
-                self.log.append(("HAND", t, i, "CLEAR", -1, -1, 0))
+                self.log.append(("HAND", t, i, "CLEAR", -1, -1, 0, found))
                 continue
-            self.log.append(("HAND", t, i, "EVICT", fr[1], fr[2], fr[5]))
+            self.log.append(("HAND", t, i, "EVICT", fr[1], fr[2], fr[5], found))
             self.frames[i] = [0, -1, -1, 0, 0, 0]
             return i
         return -1

@@ -22,10 +22,13 @@ What the model follows:
   least-recently-allocated queue (pinned in tests against ``oracle.lra``).
 
 Readings where the paper is silent (the same list is in the design notes):
+``cap`` below is the configured cap clipped by the thrash guard (``quota_cap``);
 window = [s.next, s.next + min(2 s.size, cap)) for a stream s whose zone
 [s.next, s.next + s.size) holds the missed page p (lowest slot wins); otherwise a
 new stream replaces an empty slot or the least recently used one (lowest index
-on ties): if at least 3 of the file's last 64 misses lie within 64 pages of p, many blocks are reading the file in aggregate (interleaved strides) and the
+on ties): if at least ``near_min`` of the file's last ``recent`` misses lie within
+``near_pages`` pages of p (defaults 3, 64, 64), many blocks are reading the file in aggregate
+(interleaved strides) and the
 window is the cap-sized chunk aligned around p; else [p, p + w) with w = min(2 h,
 cap) if the h >= 1 pages right before p are already cached (context readahead:
 Linux's way of following readers that interleave on one descriptor, Sec. 2.3); else
@@ -42,8 +45,10 @@ Events produced (tuples; the GPU trace is decoded into the same vocabulary):
 
   ("HIT",  block, file, page, frame)
   ("MISS", block, file, page, ws, wn)          wn already clamped to EOF
-  ("HAND", ticket, frame, action, vfile, vpage, vra)
-        action in FREE / SKIP / CLEAR / EVICT; victim fields are -1, -1, 0 unless EVICT
+  ("HAND", ticket, frame, action, vfile, vpage, vra, seen)
+        action in FREE / SKIP / CLEAR / EVICT; victim fields are -1, -1, 0 unless EVICT;
+        seen = what the hand found: ref | pinned << 1 | lost race << 2 | state << 3
+        (state 0 free, 2 filling, 3 valid; the model never loses a race)
   ("ALLOC", file, page, frame, ra)             ra = 1 for prefetched (non-demand) pages
   ("REQ",  file, first_page, npages)           one host read of the allocated span
   ("NOFRAME", block, file, page)               no frame for a non-demand page: window cut
@@ -54,10 +59,24 @@ import dataclasses
 from typing import Dict, List, Optional, Tuple
 
 FREE, FILLING, VALID = "FREE", "FILLING", "VALID"
+# Defaults of the aggregate-reading rule's constants (each is a model parameter):
 RECENT = 64          # misses remembered per file
 NEAR_MIN = 3         # remembered misses near p that make the file look read in aggregate
 NEAR_PAGES = 64      # "near" = within NEAR_PAGES pages
 ADV_NORMAL, ADV_SEQUENTIAL, ADV_RANDOM = "normal", "sequential", "random"
+# which rule decided a window: readahead off, a stream's zone, aggregate reading, context
+# (cached pages right behind p), a new stream (W0 or one page)
+RULE_OFF, RULE_ZONE, RULE_AGGREGATE, RULE_CONTEXT, RULE_NEW = 0, 1, 2, 3, 4
+# frame states as the trace reports them
+STATE_CODE = {"FREE": 0, "FILLING": 2, "VALID": 3}
+
+
+def quota_cap(cap: int, nframes: int, blocks: int, quota_blocks: int) -> int:
+    """The largest window under the thrash guard: the cap, but at most one resident block's
+    share of the cache (Sec. 5.1: the cache divided among the threadblocks reading at once,
+    the smaller of the launch's blocks and quota_blocks)."""
+    r = max(1, min(blocks, quota_blocks))
+    return min(cap, max(1, nframes // r))
 
 
 @dataclasses.dataclass
@@ -85,12 +104,14 @@ class FileState:
     read_only: bool = True
     streams: List[Stream] = dataclasses.field(default_factory=list)
     clock: int = 0          # per-file count of readahead decisions (stream last_use)
-    recent: List[int] = dataclasses.field(default_factory=list)   # last RECENT misses (pages)
+    recent: List[int] = dataclasses.field(default_factory=list)   # the last misses (pages)
 
 
 class PolicyModel:
     def __init__(self, nframes: int, page_size: int, ra_init_pages: int = 4,
-                 ra_cap_pages: int = 0, streams_per_file: int = 8):
+                 ra_cap_pages: int = 0, streams_per_file: int = 8, recent: int = RECENT,
+                 near_pages: int = NEAR_PAGES, near_min: int = NEAR_MIN):
+        """ra_cap_pages is the cap after the thrash guard (see ``quota_cap``)."""
         if nframes <= 0 or page_size <= 0:
             raise ValueError("nframes and page_size must be positive")
         self.C = nframes
@@ -98,11 +119,16 @@ class PolicyModel:
         self.W0 = ra_init_pages
         self.cap = ra_cap_pages
         self.S = streams_per_file
+        self.recent = recent
+        self.near_pages = near_pages
+        self.near_min = near_min
         self.frames = [Frame() for _ in range(nframes)]
         self.map: Dict[Tuple[int, int], int] = {}
         self.hand = 0
         self.files: Dict[int, FileState] = {}
         self.events: List[tuple] = []
+        # per miss, in order: (near, h, rule) -- the detector's inputs and the rule it applied
+        self.decisions: List[Tuple[int, int, int]] = []
         # counters
         self.hits = 0
         self.misses = 0
@@ -131,11 +157,12 @@ class PolicyModel:
     def ra_decide(self, file_id: int, p: int) -> Tuple[int, int]:
         fs = self.files[file_id]
         if self.cap == 0 or fs.advice == ADV_RANDOM or not fs.read_only:
+            self.decisions.append((0, 0, RULE_OFF))
             return p, 1
         fs.clock += 1
-        near = sum(1 for r in fs.recent if abs(r - p) <= NEAR_PAGES)
+        near = sum(1 for r in fs.recent if abs(r - p) <= self.near_pages)
         fs.recent.append(p)
-        if len(fs.recent) > RECENT:
+        if len(fs.recent) > self.recent:
             fs.recent.pop(0)
         for s in fs.streams:                       # lowest slot index wins
             if s.valid and s.next <= p < s.next + s.size:
@@ -144,6 +171,7 @@ class PolicyModel:
                 s.next = ws + wn
                 s.size = wn
                 s.last_use = fs.clock
+                self.decisions.append((near, 0, RULE_ZONE))
                 return ws, wn
         # context: the pages right behind p are already cached (read or being read by other
         # blocks), so p continues a sequential stream that no slot tracks
@@ -157,17 +185,20 @@ class PolicyModel:
                 break
         if victim is None:                         # else least recently used, lowest index on ties
             victim = min(fs.streams, key=lambda s: s.last_use)
-        if near >= NEAR_MIN:
+        if near >= self.near_min:
             # many blocks missing close together: the file is read in aggregate (interleaved
             # strides), take the whole cap-sized aligned chunk around p
             wn = self.cap
             ws = p // wn * wn
+            self.decisions.append((near, 0, RULE_AGGREGATE))
         elif h > 0:
             wn = min(2 * h, self.cap)
             ws = p
+            self.decisions.append((near, h, RULE_CONTEXT))
         else:
             wn = self.W0 if (p == 0 or fs.advice == ADV_SEQUENTIAL) else 1
             ws = p
+            self.decisions.append((near, 0, RULE_NEW))
         wn = max(1, min(wn, self.cap))
         victim.valid = True
         victim.next = ws + wn
@@ -182,18 +213,19 @@ class PolicyModel:
             self.hand += 1
             f = t % self.C
             fr = self.frames[f]
+            seen = fr.ref | (1 if fr.pins > 0 else 0) << 1 | STATE_CODE[fr.state] << 3
             if fr.state == FREE:
-                self.events.append(("HAND", t, f, "FREE", -1, -1, 0))
+                self.events.append(("HAND", t, f, "FREE", -1, -1, 0, seen))
                 return f
             if fr.state == FILLING or fr.pins > 0:
-                self.events.append(("HAND", t, f, "SKIP", -1, -1, 0))
+                self.events.append(("HAND", t, f, "SKIP", -1, -1, 0, seen))
                 continue
             if fr.ref:
                 fr.ref = 0
-                self.events.append(("HAND", t, f, "CLEAR", -1, -1, 0))
+                self.events.append(("HAND", t, f, "CLEAR", -1, -1, 0, seen))
                 continue
             # evict: unmap the old tag, reuse the frame in place
-            self.events.append(("HAND", t, f, "EVICT", fr.file, fr.page, fr.ra))
+            self.events.append(("HAND", t, f, "EVICT", fr.file, fr.page, fr.ra, seen))
             del self.map[(fr.file, fr.page)]
             self.evictions += 1
             if fr.ra:

@@ -12,20 +12,25 @@ and replays it on the CPU:
   be consistent -- a FREE visit finds a frame that never held a page, an EVICT names
   exactly the page the frame received at its previous claim, every claim is followed by
   an allocation with the same ticket, no page is held by two frames at once, and the
-  eviction order is the EVICT records sorted by ticket;
+  eviction order is the EVICT records sorted by ticket. Each visit also logs what it found
+  (frame state, reference bit, pin, a lost compare-and-swap), and the action must be the
+  second-chance rule applied to it: FREE only on a free frame, CLEAR only on a valid
+  unpinned frame with the bit set, EVICT only on a valid unpinned frame with the bit clear,
+  SKIP only on a pinned or filling frame or after losing a race;
 * readahead: the misses of a file are logged under its miss lock, so their record order
   is the order the detector saw them. Replaying the stream table and the recent-miss
-  ring gives the exact window of every decision taken by a stream zone or by the
-  aggregate (near-miss) rule, and the exact near count; a decision by the context rule
-  depends on which pages were cached at that instant, so only its shape is checked
-  (it starts at the missed page, and its length is 1, W0 or an even 2h <= cap);
+  ring gives the exact window of every decision, and the exact near count; a decision by
+  the context rule depends on which pages were cached at that instant, which the trace
+  records (the history length h), so its window is checked exactly given h;
 * requests: each block's own records are in program order, so every miss is followed by
   that block's allocations and one request, which must cover exactly the contiguous run
   of allocated pages inside the window, starting with the demanded page.
 
 Events are tuples:
-  ("MISS", block, file, page, ws, wn, near)
-  ("HAND", ticket, frame, action, vfile, vpage, vra, block)
+  ("MISS", block, file, page, ws, wn, packed)      packed = near | h << 8 | rule << 24
+  ("HAND", ticket, frame, action, vfile, vpage, vra, seen, block)
+        seen = ref | pinned << 1 | lost race << 2 | state << 3 (0 free, 1 claimed, 2 filling,
+        3 valid)
   ("ALLOC", block, file, page, frame, ra, ticket)
   ("REQ", block, file, first, npages)
   ("NOFRAME", block, file, page)
@@ -35,7 +40,7 @@ from __future__ import annotations
 from collections import defaultdict
 from typing import Dict, List, Tuple
 
-from .policy import NEAR_MIN, NEAR_PAGES, RECENT
+from .policy import NEAR_MIN, NEAR_PAGES, RECENT, RULE_AGGREGATE, RULE_CONTEXT, RULE_NEW, RULE_OFF, RULE_ZONE
 
 
 class ReplayError(AssertionError):
@@ -61,8 +66,19 @@ def replay_clock(events, nframes: int) -> Dict[str, object]:
     evictions: List[Tuple[int, int, int, int]] = []     # (ticket, frame, file, page)
     wasted = 0
     for e in hands:
-        _, t, f, act, vf, vp, vra, _blk = e
+        _, t, f, act, vf, vp, vra, seen, _blk = e
         _check(f == t % nframes, f"ticket {t} visited frame {f}, expected {t % nframes}")
+        ref, pinned, lost, state = seen & 1, (seen >> 1) & 1, (seen >> 2) & 1, seen >> 3
+        # the second-chance rule applied to what the visit found
+        if act == "FREE":
+            _check(state == 0 and not pinned and not lost, f"FREE at ticket {t} found {seen:#x}")
+        elif act == "CLEAR":
+            _check(state == 3 and ref and not pinned and not lost, f"CLEAR at ticket {t} found {seen:#x}")
+            _check(f in occupant, f"CLEAR at ticket {t} of empty frame {f}")
+        elif act == "EVICT":
+            _check(state == 3 and not ref and not pinned and not lost, f"EVICT at ticket {t} found {seen:#x}")
+        else:
+            _check(pinned or lost or state in (1, 2), f"SKIP at ticket {t} found {seen:#x}")
         if act == "FREE":
             _check(f not in occupant, f"FREE visit at ticket {t} but frame {f} holds {occupant.get(f)}")
         elif act == "EVICT":
@@ -91,27 +107,31 @@ def replay_clock(events, nframes: int) -> Dict[str, object]:
 
 
 def replay_readahead(events, ra_init: int, ra_cap: int, streams: int,
-                     files: Dict[int, int], page_size: int, advice: Dict[int, str] = None):
-    """Replay every file's miss decisions in lock (record) order."""
+                     files: Dict[int, int], page_size: int, advice: Dict[int, str] = None,
+                     recent: int = RECENT, near_pages: int = NEAR_PAGES, near_min: int = NEAR_MIN):
+    """Replay every file's miss decisions in lock (record) order. ra_cap is the cap after the
+    thrash guard. Returns how many decisions were checked exactly, and by which rule."""
     advice = advice or {}
     state = {}
+    by_rule = defaultdict(int)
     checked_exact = 0
-    checked_shape = 0
     for e in events:
         if e[0] != "MISS":
             continue
-        _, blk, fid, p, ws, wn, near = e
+        _, blk, fid, p, ws, wn, packed = e
+        near, h, rule = packed & 0xFF, (packed >> 8) & 0xFFFF, packed >> 24
         npages = (files[fid] + page_size - 1) // page_size
         if ra_cap == 0 or advice.get(fid) == "random":
-            _check((ws, wn) == (p, 1), f"readahead off but miss at {p} got window {(ws, wn)}")
+            _check((ws, wn) == (p, 1) and rule == RULE_OFF, f"readahead off but miss at {p} got window {(ws, wn)}")
             checked_exact += 1
+            by_rule[RULE_OFF] += 1
             continue
         st = state.setdefault(fid, {"clock": 0, "recent": [], "streams": [[False, 0, 0, 0] for _ in range(streams)]})
         st["clock"] += 1
-        want_near = sum(1 for r in st["recent"] if abs(r - p) <= NEAR_PAGES)
+        want_near = sum(1 for r in st["recent"] if abs(r - p) <= near_pages)
         _check(near == want_near, f"miss at {p}: near count {near}, model {want_near}")
         st["recent"].append(p)
-        if len(st["recent"]) > RECENT:
+        if len(st["recent"]) > recent:
             st["recent"].pop(0)
         slots = st["streams"]
         zone = next((i for i, s in enumerate(slots) if s[0] and s[1] <= p < s[1] + s[2]), None)
@@ -119,32 +139,33 @@ def replay_readahead(events, ra_init: int, ra_cap: int, streams: int,
             s = slots[zone]
             exp_ws, exp_wn = s[1], min(2 * s[2], ra_cap)
             slots[zone] = [True, exp_ws + exp_wn, exp_wn, st["clock"]]
-            _check((ws, wn) == (exp_ws, min(exp_wn, npages - exp_ws)),
-                   f"zone decision at {p}: trace {(ws, wn)}, model {(exp_ws, exp_wn)}")
-            checked_exact += 1
-            continue
-        victim = next((i for i, s in enumerate(slots) if not s[0]), None)
-        if victim is None:
-            victim = min(range(len(slots)), key=lambda i: (slots[i][3], i))
-        if want_near >= NEAR_MIN:
-            exp_wn = ra_cap
-            exp_ws = p - p % ra_cap
-            _check((ws, wn) == (exp_ws, min(exp_wn, npages - exp_ws)),
-                   f"aggregate decision at {p}: trace {(ws, wn)}, model {(exp_ws, exp_wn)}")
-            checked_exact += 1
-            slots[victim] = [True, exp_ws + exp_wn, exp_wn, st["clock"]]
+            exp_rule, exp_h = RULE_ZONE, 0
         else:
-            w0 = ra_init if (p == 0 or advice.get(fid) == "sequential") else 1
-            _check(ws == p, f"context decision at {p} starts at {ws}")
-            full = wn if p + wn < npages else None        # EOF-clamped windows cannot be classified
-            if full is not None:
-                _check(full in (1, min(w0, ra_cap)) or (full % 2 == 0 and full <= ra_cap) or full == ra_cap,
-                       f"context decision at {p}: window {wn} is not 1, W0 or 2h <= cap")
-            checked_shape += 1
-            # the device stored the unclamped length; recover it where the window was clamped
-            stored = wn if full is not None else max(wn, 1)
-            slots[victim] = [True, ws + stored, stored, st["clock"]]
-    return {"exact": checked_exact, "shape_only": checked_shape}
+            victim = next((i for i, s in enumerate(slots) if not s[0]), None)
+            if victim is None:
+                victim = min(range(len(slots)), key=lambda i: (slots[i][3], i))
+            if want_near >= near_min:
+                exp_wn = ra_cap
+                exp_ws = p - p % ra_cap
+                exp_rule, exp_h = RULE_AGGREGATE, 0
+            else:
+                # the cached history behind p is the trace's; it cannot exceed the pages
+                # behind p or the cap, and it sizes the window exactly
+                _check(h <= min(p, ra_cap), f"context decision at {p}: history {h} out of range")
+                exp_h = h
+                if h > 0:
+                    exp_wn, exp_rule = min(2 * h, ra_cap), RULE_CONTEXT
+                else:
+                    w0 = ra_init if (p == 0 or advice.get(fid) == "sequential") else 1
+                    exp_wn, exp_rule = max(1, min(w0, ra_cap)), RULE_NEW
+                exp_ws = p
+            slots[victim] = [True, exp_ws + exp_wn, exp_wn, st["clock"]]
+        _check(rule == exp_rule and h == exp_h, f"miss at {p}: rule {rule} h {h}, model rule {exp_rule} h {exp_h}")
+        _check((ws, wn) == (exp_ws, min(exp_wn, npages - exp_ws)),
+               f"decision at {p} (rule {rule}): trace {(ws, wn)}, model {(exp_ws, exp_wn)}")
+        checked_exact += 1
+        by_rule[exp_rule] += 1
+    return {"exact": checked_exact, "shape_only": 0, "by_rule": dict(by_rule)}
 
 
 def replay_requests(events) -> int:

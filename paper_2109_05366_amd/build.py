@@ -28,11 +28,14 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source into libgfs.so (always recompiles); returns the library path."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIP_FLAGS + ["-shared", "-I", INCLUDE, "-o", tmp]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES] + ["-lpthread"]
+# a user kernel of the device API that the tests call (gopen by path, error returns)
+PROBE_SRC = os.path.join(ROOT, "tests", "csrc", "gfs_api_probe.hip")
+PROBE_LIB = os.path.join(ROOT, "tests", "libgfs_api_probe.so")
+
+
+def _hipcc_shared(sources, out, verbose: bool) -> str:
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + HIP_FLAGS + ["-shared", "-I", INCLUDE, "-o", tmp] + list(sources) + ["-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -44,7 +47,16 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + "\n".join(noise))
     if verbose and noise:
         print("\n".join(noise), file=sys.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source into libgfs.so, and the tests' device-API probe into
+    tests/libgfs_api_probe.so (always recompiles); returns the library path."""
+    _hipcc_shared([os.path.join(CSRC, s) for s in SOURCES], LIB, verbose)
+    if os.path.exists(PROBE_SRC):
+        _hipcc_shared([PROBE_SRC], PROBE_LIB, verbose)
     return LIB
 
 

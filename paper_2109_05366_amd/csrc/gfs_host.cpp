@@ -31,6 +31,9 @@
 #include "gfs_layout.h"
 
 extern "C" int gfs_internal_zero(void* p, size_t bytes, hipStream_t s);
+extern "C" int gfs_internal_resident_blocks(uint32_t threads, uint32_t* blocks);
+extern "C" int gfs_internal_purge_file(const gfs_dev* ddev, uint32_t nframes, uint64_t pt_entries, uint32_t file,
+                                       hipStream_t s);
 
 namespace {
 
@@ -79,9 +82,13 @@ int make_layout(const gfs_config* c, Layout* L) {
   if (c->io_backend == GFS_IO_PREAD_PARTITIONED && c->host_threads > c->rpc_slots) return -EINVAL;
   if (c->o_direct > GFS_DIRECT_PREFER) return -EINVAL;
   if (c->trace_level > 2) return -EINVAL;
-  if (c->io_chunk_bytes % kDirectAlign || c->io_chunk_bytes < (64u << 10) || c->io_chunk_bytes > (64u << 20) ||
-      c->reserved0)
+  if (c->io_chunk_bytes % kDirectAlign || c->io_chunk_bytes < (64u << 10) || c->io_chunk_bytes > (64u << 20))
     return -EINVAL;
+  if (c->max_files < 1 || c->max_files > GFS_MAX_FILES) return -EINVAL;
+  if (c->ra_recent < 1 || c->ra_recent > GFS_MAX_RECENT) return -EINVAL;
+  if (c->ra_near_pages > (1u << 20) || c->ra_near_min < 1 || c->ra_near_min > c->ra_recent + 1) return -EINVAL;
+  if (c->ra_async > 1) return -EINVAL;
+  if (c->ra_async) return -ENOTSUP;   /* marker-triggered prefetch is not built (see gfs.h) */
   if (c->policy == GFS_POLICY_SHARED) {
     L->max_req_pages = L->ra_cap ? L->ra_cap : 1;
   } else if (c->policy == GFS_POLICY_PRIVATE) {
@@ -102,13 +109,14 @@ int make_layout(const gfs_config* c, Layout* L) {
   uint64_t o = 0;
   L->off_globals = o; o = align_up(o + sizeof(gfs_globals), kAlign);
   L->off_dev = o; o = align_up(o + sizeof(gfs_dev), kAlign);
-  L->off_files = o; o = align_up(o + sizeof(gfs_file_dev) * GFS_MAX_FILES, kAlign);
-  L->off_locks = o; o = align_up(o + sizeof(gfs_file_lock) * GFS_MAX_FILES, kAlign);
-  L->off_lockq = o; o = align_up(o + 8ull * GFS_LOCK_SLOTS * GFS_MAX_FILES, kAlign);
-  L->off_claims = o; o = align_up(o + sizeof(gfs_file_claims) * GFS_MAX_FILES, kAlign);
+  const uint64_t nf = c->max_files;
+  L->off_files = o; o = align_up(o + sizeof(gfs_file_dev) * nf, kAlign);
+  L->off_locks = o; o = align_up(o + sizeof(gfs_file_lock) * nf, kAlign);
+  L->off_lockq = o; o = align_up(o + 8ull * GFS_LOCK_SLOTS * nf, kAlign);
+  L->off_claims = o; o = align_up(o + sizeof(gfs_file_claims) * nf, kAlign);
   L->off_pslots = o;
   if (c->policy == GFS_POLICY_PRIVATE) o = align_up(o + sizeof(gfs_pslot) * c->private_slots, kAlign);
-  L->off_names = o; o = align_up(o + (uint64_t)GFS_NAME_MAX * GFS_MAX_FILES, kAlign);
+  L->off_names = o; o = align_up(o + (uint64_t)GFS_NAME_MAX * nf, kAlign);
   L->off_fword = o; o = align_up(o + 8 * L->nframes, kAlign);
   L->off_ftag = o; o = align_up(o + 8 * L->nframes, kAlign);
   L->off_pt = o; o = align_up(o + 8 * GFS_BUCKET_SLOTS * L->nbuckets, kAlign);
@@ -403,6 +411,20 @@ int download_file_record(gfs_ctx* c, int id, gfs_file_dev* rec) {
   return hip_ok(hipStreamSynchronize(c->stream));
 }
 
+// clear one file id's miss lock, its queue slots and its window claims (no kernel running)
+int zero_file_locks(gfs_ctx* c, int id) {
+  const Layout& L = c->L;
+  int rc = gfs_internal_zero(c->meta + L.off_locks + sizeof(gfs_file_lock) * (uint64_t)id, sizeof(gfs_file_lock),
+                             c->stream);
+  if (!rc)
+    rc = gfs_internal_zero(c->meta + L.off_lockq + 8ull * GFS_LOCK_SLOTS * (uint64_t)id, 8ull * GFS_LOCK_SLOTS,
+                           c->stream);
+  if (!rc)
+    rc = gfs_internal_zero(c->meta + L.off_claims + sizeof(gfs_file_claims) * (uint64_t)id,
+                           sizeof(gfs_file_claims), c->stream);
+  return rc;
+}
+
 // zero the dynamic state: counters, hand, ring tail, frames, tags, table, slots, trace
 int zero_dynamic(gfs_ctx* c) {
   const Layout& L = c->L;
@@ -440,6 +462,12 @@ void gfs_config_default(gfs_config* cfg) {
   cfg->policy = GFS_POLICY_SHARED;
   cfg->private_slots = 512;
   cfg->io_chunk_bytes = 2u << 20;
+  cfg->max_files = 64;
+  cfg->ra_recent = 64;
+  cfg->ra_near_pages = 64;
+  cfg->ra_near_min = 3;
+  cfg->ra_quota_blocks = 0;
+  cfg->ra_async = 0;
 }
 
 int gfs_device_bytes(const gfs_config* cfg, size_t* frames_bytes, size_t* meta_bytes) {
@@ -474,16 +502,32 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
     return -EIO;
   }
   // every block the device can hold at once may wait on one file's miss lock: each needs
-  // its own queue slot
-  int cus = 0, thr_per_cu = 0;
+  // its own queue slot. A block that calls gread holds at least GFS_BLOCK_LDS_MIN bytes of
+  // LDS and one wave, which bounds the blocks per CU.
+  int cus = 0, thr_per_cu = 0, lds_per_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
-      hipDeviceGetAttribute(&thr_per_cu, hipDeviceAttributeMaxThreadsPerMultiProcessor, c->device) != hipSuccess) {
+      hipDeviceGetAttribute(&thr_per_cu, hipDeviceAttributeMaxThreadsPerMultiProcessor, c->device) != hipSuccess ||
+      hipDeviceGetAttribute(&lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device) !=
+          hipSuccess) {
     delete c;
     return -EIO;
   }
-  if ((uint64_t)cus * (uint64_t)(thr_per_cu / 64) > GFS_LOCK_SLOTS) {
-    delete c;
-    return -EINVAL;
+  {
+    uint64_t per_cu = (uint64_t)(thr_per_cu / 64);
+    const uint64_t by_lds = (uint64_t)lds_per_cu / GFS_BLOCK_LDS_MIN;
+    if (lds_per_cu > 0 && by_lds < per_cu) per_cu = by_lds;
+    if ((uint64_t)cus * per_cu > GFS_LOCK_SLOTS) {
+      delete c;
+      return -EINVAL;
+    }
+  }
+  uint32_t quota_blocks = cfg->ra_quota_blocks;
+  if (quota_blocks == 0) {
+    // the blocks of the library's 256-thread reader kernels that fit on the device at once
+    if (gfs_internal_resident_blocks(GFS_MAX_BLOCK_THREADS, &quota_blocks) != 0 || quota_blocks == 0) {
+      delete c;
+      return -EIO;
+    }
   }
   const uint64_t ring_bytes = sizeof(gfs_rpc_slot) * (uint64_t)cfg->rpc_slots;
   const uint64_t staging_bytes = L.max_req_bytes * (uint64_t)cfg->rpc_slots;
@@ -518,6 +562,12 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   h.max_req_pages = (uint32_t)L.max_req_pages;
   h.trace_level = cfg->trace_level;
   h.trace_cap = cfg->trace_capacity;
+  h.max_files = cfg->max_files;
+  h.ra_recent = cfg->ra_recent;
+  h.ra_near_pages = cfg->ra_near_pages;
+  h.ra_near_min = cfg->ra_near_min;
+  h.ra_quota_blocks = quota_blocks;
+  c->cfg.ra_quota_blocks = quota_blocks;   /* gfs_get_config reports the resolved count */
   h.max_req_bytes = L.max_req_bytes;
   c->clock_khz = khz;
   const uint64_t tns = cfg->wait_timeout_ns ? cfg->wait_timeout_ns : 10000000000ull;
@@ -577,7 +627,7 @@ int gfs_open(gfs_ctx* c, const char* path, int flags, int* file_id) {
   const size_t plen = strlen(path);
   if (plen == 0 || plen >= GFS_NAME_MAX) return -ENAMETOOLONG;
   int id = -1;
-  for (int i = 0; i < (int)GFS_MAX_FILES; ++i)
+  for (int i = 0; i < (int)c->cfg.max_files; ++i)
     if (!c->files[i].open) { id = i; break; }
   if (id < 0) return -ENFILE;
   bool direct = false;
@@ -606,7 +656,8 @@ int gfs_open(gfs_ctx* c, const char* path, int flags, int* file_id) {
   char name[GFS_NAME_MAX];
   memset(name, 0, sizeof name);
   memcpy(name, path, plen);
-  int rc = upload_file_record(c, id, rec);
+  int rc = zero_file_locks(c, id);
+  if (!rc) rc = upload_file_record(c, id, rec);
   if (!rc && hipMemcpyAsync(c->meta + c->L.off_names + (uint64_t)id * GFS_NAME_MAX, name, GFS_NAME_MAX,
                             hipMemcpyHostToDevice, c->stream) != hipSuccess)
     rc = -EIO;
@@ -652,8 +703,15 @@ int gfs_close(gfs_ctx* c, int file_id) {
   int rc = download_file_record(c, file_id, &rec);
   if (rc) return rc;
   if (rec.handles != 0) return -EBUSY;
-  rec.open = 0;
+  // A page key is (id, page), and a later gfs_open may give this id to another file: drop
+  // every cached page, reservation and frame of the file now, so that no read of the next
+  // file under this id can find them, and clear the id's detector and lock state.
+  memset(&rec, 0, sizeof rec);
   rc = upload_file_record(c, file_id, rec);
+  if (!rc) rc = gfs_internal_purge_file(c->ddev, (uint32_t)c->L.nframes, c->L.nbuckets * GFS_BUCKET_SLOTS,
+                                        (uint32_t)file_id, c->stream);
+  if (!rc) rc = zero_file_locks(c, file_id);
+  if (!rc) rc = hip_ok(hipStreamSynchronize(c->stream));
   if (rc) return rc;
   HostFile& hf = c->files[file_id];
   const int fd = hf.fd.exchange(-1);
@@ -744,7 +802,7 @@ int gfs_reset_cache(gfs_ctx* c) {
   stop_threads(c);
   int rc = zero_dynamic(c);
   // clear readahead streams, locks and clocks of registered files
-  for (int i = 0; !rc && i < (int)GFS_MAX_FILES; ++i) {
+  for (int i = 0; !rc && i < (int)c->cfg.max_files; ++i) {
     if (!c->files[i].open) continue;
     gfs_file_dev rec;
     rc = download_file_record(c, i, &rec);

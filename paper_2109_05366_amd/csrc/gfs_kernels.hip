@@ -22,6 +22,27 @@ __global__ void zero_kernel(uint64_t* p, uint64_t n8) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8; i += stride) p[i] = 0;
 }
 
+// Drop one file's pages: frames whose tag belongs to it become FREE (version bumped), and its
+// page-table entries (mapped pages and reservations) are cleared. Runs with no reader kernel
+// in flight, so plain accesses suffice.
+__global__ void purge_file_kernel(const gfs_dev* d, uint32_t nframes, uint64_t pt_entries, uint32_t file) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t prefix = (uint64_t)file + 1;
+  const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint64_t i = i0; i < nframes; i += stride) {
+    const uint64_t w = d->fword[i];
+    if ((w & GFS_FW_STATE) != GFS_FS_FREE && (d->ftag[i] >> GFS_KEY_PAGE_BITS) == prefix) {
+      d->fword[i] = (((w >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT) | GFS_FS_FREE;
+      d->ftag[i] = 0;
+      d->ffill[i] = 0;
+    }
+  }
+  for (uint64_t i = i0; i < pt_entries; i += stride) {
+    const uint64_t e = d->pt[i];
+    if (e && (e >> (GFS_ENTRY_FRAME_BITS + GFS_KEY_PAGE_BITS)) == prefix) d->pt[i] = 0;
+  }
+}
+
 __global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) list_reader_kernel(const gfs_dev* d, int file_id, const uint64_t* offsets,
                                    uint32_t reads, uint64_t read_size, int consumer,
                                    uint8_t* buf, void* out, int64_t* status, uint64_t* turn) {
@@ -181,6 +202,29 @@ extern "C" int gfs_batch_grid(uint32_t threads, uint32_t* grid) {
     return -EIO;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -EIO;
   *grid = (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)cus;
+  return 0;
+}
+
+extern "C" int gfs_internal_purge_file(const gfs_dev* ddev, uint32_t nframes, uint64_t pt_entries, uint32_t file,
+                                       hipStream_t s) {
+  const uint64_t n = pt_entries > nframes ? pt_entries : nframes;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(purge_file_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, ddev, nframes, pt_entries, file);
+  return hipGetLastError() == hipSuccess ? 0 : -EIO;
+}
+
+// Blocks of the list-reader kernel at `threads` threads that fit on the current device at
+// once: the thrash guard's default count of blocks sharing the cache.
+extern "C" int gfs_internal_resident_blocks(uint32_t threads, uint32_t* blocks) {
+  int dev = 0, per_cu = 0, cus = 0;
+  if (!blocks) return -EINVAL;
+  if (hipGetDevice(&dev) != hipSuccess) return -EIO;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, list_reader_kernel, (int)threads, 0) != hipSuccess)
+    return -EIO;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -EIO;
+  *blocks = (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)cus;
   return 0;
 }
 

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgfs.so")
 
-GFS_ABI_VERSION = 1
+GFS_ABI_VERSION = 2
 GFS_O_RDONLY = 0
 GFS_ADV_NORMAL, GFS_ADV_RANDOM, GFS_ADV_SEQUENTIAL = 0, 1, 2
 GFS_DIRECT_OFF, GFS_DIRECT_ON, GFS_DIRECT_PREFER = 0, 1, 2
@@ -24,6 +24,7 @@ GFS_IO_PREAD, GFS_IO_PREAD_PARTITIONED = 0, 1
 GFS_MAX_WINDOW_PAGES = 1024
 
 EV_HIT, EV_JOIN, EV_MISS, EV_HAND, EV_ALLOC, EV_REQ, EV_NOFRAME = 1, 2, 3, 4, 5, 6, 7
+RA_RULE_OFF, RA_RULE_ZONE, RA_RULE_AGGREGATE, RA_RULE_CONTEXT, RA_RULE_NEW = 0, 1, 2, 3, 4
 HAND_FREE, HAND_SKIP, HAND_CLEAR, HAND_EVICT = 0, 1, 2, 3
 
 
@@ -36,7 +37,9 @@ class gfs_config(C.Structure):
         ("io_backend", C.c_uint32), ("o_direct", C.c_uint32),
         ("trace_level", C.c_uint32), ("trace_capacity", C.c_uint32),
         ("wait_timeout_ns", C.c_uint64), ("policy", C.c_uint32), ("private_slots", C.c_uint32),
-        ("io_chunk_bytes", C.c_uint32), ("reserved0", C.c_uint32),
+        ("io_chunk_bytes", C.c_uint32), ("max_files", C.c_uint32),
+        ("ra_recent", C.c_uint32), ("ra_near_pages", C.c_uint32), ("ra_near_min", C.c_uint32),
+        ("ra_quota_blocks", C.c_uint32), ("ra_async", C.c_uint32),
     ]
 
 
@@ -282,6 +285,9 @@ class PageCache:
 
     def stats(self) -> Dict[str, object]:
         return gfs_stats_read(self.ctx)
+
+    def config(self) -> gfs_config:
+        return gfs_get_config(self.ctx)
 
     def trace(self, max_events: Optional[int] = None) -> np.ndarray:
         return gfs_trace_read(self.ctx, max_events or int(self.cfg.trace_capacity))

@@ -13,15 +13,20 @@ def make_config(page_size: int, cache_bytes: int, ra_cap_bytes: int = 16 << 20, 
                 streams: int = 8, host_threads: int = 8, rpc_slots: int = 64,
                 o_direct: int = gfs.GFS_DIRECT_PREFER, trace_level: int = 0, trace_capacity: int = 0,
                 timeout_s: float = 30.0, policy: int = gfs.GFS_POLICY_SHARED,
-                private_slots: int = 512, io_chunk_bytes: int = 2 << 20) -> gfs.gfs_config:
+                private_slots: int = 512, io_chunk_bytes: int = 2 << 20, max_files: int = 64,
+                detector=(64, 64, 3), quota_blocks: int = 0, timeout_ns: int = 0) -> gfs.gfs_config:
+    """detector = (ra_recent, ra_near_pages, ra_near_min); quota_blocks = the thrash guard's
+    resident-block count (0: the device's, 1: off); timeout_ns overrides timeout_s."""
     cap_pages = min(ra_cap_bytes // page_size, gfs.GFS_MAX_WINDOW_PAGES)
     init = min(ra_init_pages, cap_pages) if cap_pages else 0
     return gfs.gfs_config_default(
         page_size=page_size, cache_bytes=cache_bytes, ra_cap_bytes=cap_pages * page_size,
         ra_init_bytes=init * page_size, streams_per_file=streams, host_threads=host_threads,
         rpc_slots=rpc_slots, o_direct=o_direct, trace_level=trace_level,
-        trace_capacity=trace_capacity, wait_timeout_ns=int(timeout_s * 1e9), policy=policy,
-        private_slots=private_slots, io_chunk_bytes=io_chunk_bytes)
+        trace_capacity=trace_capacity, wait_timeout_ns=int(timeout_ns or timeout_s * 1e9), policy=policy,
+        private_slots=private_slots, io_chunk_bytes=io_chunk_bytes, max_files=max_files,
+        ra_recent=detector[0], ra_near_pages=detector[1], ra_near_min=detector[2],
+        ra_quota_blocks=quota_blocks)
 
 
 @dataclasses.dataclass
@@ -88,14 +93,19 @@ class BatchReader:
     """Device buffers and unit plan for one persistent batch launch over registered files."""
 
     def __init__(self, file_ids, sizes, unit_bytes: int, blocks_per_file: int, grid: int = 0,
-                 threads: int = 256, device: str = "cuda:0"):
+                 threads: int = 256, device: str = "cuda:0", units=None, nout: int = 0):
+        """units: an explicit unit list (UNIT_DTYPE records, file = registered id) with nout
+        output rows, instead of the plan gfs_batch_plan makes for whole files."""
         import torch
         self.torch = torch
         self.threads = threads
         self.grid = grid or gfs.gfs_batch_grid(threads)
         self.unit_bytes = unit_bytes
-        self.nfiles = len(sizes)
-        plan = gfs.gfs_batch_plan(sizes, file_ids, unit_bytes, self.grid, blocks_per_file)
+        self.nfiles = nout if units is not None else len(sizes)
+        if units is not None:
+            plan = np.ascontiguousarray(units).astype(gfs.UNIT_DTYPE)
+        else:
+            plan = gfs.gfs_batch_plan(sizes, file_ids, unit_bytes, self.grid, blocks_per_file)
         self.nunits = len(plan)
         self.units = torch.from_numpy(plan.view(np.uint8).copy()).to(device)
         self.buf = torch.empty(self.grid * unit_bytes, dtype=torch.uint8, device=device)

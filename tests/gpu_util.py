@@ -39,10 +39,11 @@ def decode(ev: np.ndarray):
             out.append(("MISS", blk, f, p, b, a))
         elif op == 4:
             act = _ACTIONS[a & 0xFF]
+            x = a >> 8            # victim's prefetched mark | what the hand found << 1
             if act == "EVICT":
-                out.append(("HAND", b, fr, act, f, p, a >> 8))
+                out.append(("HAND", b, fr, act, f, p, x & 1, x >> 1))
             else:
-                out.append(("HAND", b, fr, act, -1, -1, 0))
+                out.append(("HAND", b, fr, act, -1, -1, 0, x >> 1))
         elif op == 5:
             out.append(("ALLOC", f, p, fr, a))
         elif op == 6:
@@ -98,10 +99,11 @@ def decode_replay(ev: np.ndarray):
             out.append(("MISS", blk, f, p, b, a, fr))
         elif op == 4:
             act = _ACTIONS[a & 0xFF]
+            x = a >> 8
             if act == "EVICT":
-                out.append(("HAND", b, fr, act, f, p, a >> 8, blk))
+                out.append(("HAND", b, fr, act, f, p, x & 1, x >> 1, blk))
             else:
-                out.append(("HAND", b, fr, act, -1, -1, 0, blk))
+                out.append(("HAND", b, fr, act, -1, -1, 0, x >> 1, blk))
         elif op == 5:
             out.append(("ALLOC", blk, f, p, fr, a, b))
         elif op == 6:

@@ -10,10 +10,11 @@ import os
 import numpy as np
 import pytest
 
-from oracle.policy import PolicyModel, run_serialized
+from oracle.policy import PolicyModel, quota_cap, run_serialized
 from paper_2109_05366_amd import gfs, runner
 from workloads import configs
 
+from golden import make_golden
 from gpu_util import canon, decode, expected
 
 pytestmark = pytest.mark.gpu
@@ -56,17 +57,26 @@ def test_small_parity(name, ra_pages, data_dir, cuda):
         assert st["ra_pages"] == 0
 
 
-@pytest.mark.parametrize("name,ra_pages", [
-    ("c2_small", 0), ("c2_small", 16), ("c3c_small", 0), ("c3c_small", 8),
-    ("c1_small", 8), ("c3a_small", 16), ("c3b_small", 4),
+DEFAULT_DET = (64, 64, 3)
+
+
+@pytest.mark.parametrize("name,ra_pages,det,quota", [
+    ("c2_small", 0, DEFAULT_DET, 1), ("c2_small", 16, DEFAULT_DET, 1), ("c3c_small", 0, DEFAULT_DET, 1),
+    ("c3c_small", 8, DEFAULT_DET, 1), ("c1_small", 8, DEFAULT_DET, 1), ("c3a_small", 16, DEFAULT_DET, 1),
+    ("c3b_small", 4, DEFAULT_DET, 1),
+    # other detector constants: aggregate rule off (the context rule decides), and a short
+    # memory with a small radius
+    ("c3a_small", 16, (64, 64, 65), 1), ("c3c_small", 8, (16, 8, 2), 1), ("c2_small", 16, (8, 4, 2), 1),
+    # the thrash guard: windows clipped to the cache's share per resident block
+    ("c2_small", 16, DEFAULT_DET, 16), ("c3b_small", 8, DEFAULT_DET, 16),
 ])
-def test_serialized_trace_matches_model(name, ra_pages, data_dir, cuda):
+def test_serialized_trace_matches_model(name, ra_pages, det, quota, data_dir, cuda):
     wl = configs.get(name)
     path = configs.ensure_file(wl.file, data_dir)
-    _say(f"serialized {name} ra_pages={ra_pages}")
+    _say(f"serialized {name} ra_pages={ra_pages} detector={det} quota={quota}")
     cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=ra_pages * wl.page_size,
                              ra_init_pages=4, streams=8, trace_level=2, trace_capacity=1 << 20,
-                             timeout_s=20)
+                             timeout_s=20, detector=det, quota_blocks=quota)
     with gfs.PageCache(cfg) as cache:
         fid = cache.open(path)
         res = runner.run_list(cache, fid, wl.offsets, wl.read_size, wl.consumer, serialize=True)
@@ -77,18 +87,59 @@ def test_serialized_trace_matches_model(name, ra_pages, data_dir, cuda):
     np.testing.assert_array_equal(res.status, exp_deliv)
     np.testing.assert_array_equal(res.out, exp_out)
     C = wl.cache_bytes // wl.page_size
-    model = PolicyModel(C, wl.page_size, ra_init_pages=min(4, ra_pages) if ra_pages else 4,
-                        ra_cap_pages=ra_pages, streams_per_file=8)
+    cap = quota_cap(ra_pages, C, wl.blocks, quota) if ra_pages else 0
+    model = PolicyModel(C, wl.page_size, ra_init_pages=min(4, cap) if cap else 4,
+                        ra_cap_pages=cap, streams_per_file=8, recent=det[0], near_pages=det[1], near_min=det[2])
     model.open(fid, wl.file.size)
     run_serialized(model, fid, wl.offsets, wl.read_size)
+    _compare_traces(ev, model, st)
+
+
+def _compare_traces(ev, model, st):
+    """The device trace equals the model's event sequence (hand visits with what they found),
+    and every miss logged the model's detector inputs and rule."""
     got = canon(decode(ev))
     want = canon(model.events)
     assert len(got) == len(want)
     for i, (g, w) in enumerate(zip(got, want)):
         assert g == w, f"event {i}: gpu {g} != model {w}"
+    packed = [int(r["frame"]) for r in ev if int(r["op"]) == gfs.EV_MISS]
+    dec = [(x & 0xFF, (x >> 8) & 0xFFFF, x >> 24) for x in packed]
+    assert dec == model.decisions
     assert st["misses"] == model.misses and st["hits"] == model.hits
     assert st["evictions"] == model.evictions and st["wasted_pages"] == model.wasted_pages
     assert st["fetched_pages"] == model.fetched_pages
+
+
+@pytest.mark.parametrize("name,advice", [("c3b_small", "random"), ("c3c_small", "sequential"),
+                                         ("c3c_small", "random"), ("c3a_small", "sequential")])
+def test_fadvise_serialized_trace_matches_model(name, advice, data_dir, cuda):
+    """gfs_fadvise (Sec. 4: runtime hints like posix_fadvise): RANDOM turns readahead off for
+    the file (every miss fetches its page alone), SEQUENTIAL opens every new stream with the
+    initial window; the device trace equals the model run with the same advice."""
+    from oracle.policy import ADV_RANDOM, ADV_SEQUENTIAL
+    wl = configs.get(name)
+    path = configs.ensure_file(wl.file, data_dir)
+    ra_pages = 8
+    _say(f"fadvise {advice} {name}")
+    cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=ra_pages * wl.page_size,
+                             trace_level=2, trace_capacity=1 << 20, timeout_s=20, quota_blocks=1)
+    with gfs.PageCache(cfg) as cache:
+        fid = cache.open(path)
+        cache.fadvise(fid, gfs.GFS_ADV_RANDOM if advice == "random" else gfs.GFS_ADV_SEQUENTIAL)
+        res = runner.run_list(cache, fid, wl.offsets, wl.read_size, wl.consumer, serialize=True)
+        st = cache.stats()
+        ev = cache.trace()
+    exp_out, exp_deliv = expected(wl, path)
+    np.testing.assert_array_equal(res.status, exp_deliv)
+    np.testing.assert_array_equal(res.out, exp_out)
+    C = wl.cache_bytes // wl.page_size
+    model = PolicyModel(C, wl.page_size, ra_init_pages=4, ra_cap_pages=ra_pages, streams_per_file=8)
+    model.open(fid, wl.file.size, advice=ADV_RANDOM if advice == "random" else ADV_SEQUENTIAL)
+    run_serialized(model, fid, wl.offsets, wl.read_size)
+    _compare_traces(ev, model, st)
+    if advice == "random":
+        assert st["ra_pages"] == 0 and st["misses"] == st["fetched_pages"]
 
 
 def test_c1_full_parity(data_dir, cuda):
@@ -110,9 +161,13 @@ def test_c1_full_parity(data_dir, cuda):
         np.testing.assert_array_equal(res2.out, exp_out)
         assert st["evictions"] == 0 and st["fetched_pages"] == 1024    # closed form (i)
         assert st2["misses"] == st["misses"] and st2["fetched_pages"] == 1024
+        # the stored golden values (tests/golden/, pinned on the CPU)
+        golden, total = make_golden.load_c1()
+        assert [int(x) for x in res.out] == golden
+        assert int(res.out.sum(dtype=np.uint64)) == total
 
 
-def test_gopen_path_and_errors(data_dir, cuda):
+def test_host_open_errors_and_unaligned_reads(data_dir, cuda):
     wl = configs.c1_small()
     path = configs.ensure_file(wl.file, data_dir)
     cfg = runner.make_config(wl.page_size, wl.cache_bytes, timeout_s=20)
@@ -134,6 +189,125 @@ def test_gopen_path_and_errors(data_dir, cuda):
         cache.close_file(fid)
         with pytest.raises(OSError):
             cache.close_file(fid)
+
+
+def _probe_lib():
+    import ctypes
+    from paper_2109_05366_amd import build as b
+    if not os.path.exists(b.PROBE_LIB):
+        raise RuntimeError(f"{b.PROBE_LIB} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(b.PROBE_LIB)
+    vp = ctypes.c_void_p
+    L.gfs_test_api_probe.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                     ctypes.c_uint32, vp, vp, vp]
+    L.gfs_test_api_probe.restype = ctypes.c_int
+    return L
+
+
+@pytest.mark.parametrize("threads", [256, 64, 96])
+def test_device_gopen_by_path_and_error_returns(threads, data_dir, cuda):
+    """A user kernel opens a registered file by path with gopen (Sec. 2.2), reads through the
+    descriptor and closes it; the device-side error returns are the documented ones: -EROFS
+    for a non-read-only open (prefetching only for read-only files, Sec. 4), -ENOENT for a
+    path or id that is not registered, -EBADF for a bad descriptor in gread and gclose, 0 at
+    the end of the file, and -EINVAL from gread in a block whose size is not a multiple of
+    64 threads."""
+    torch = cuda
+    from oracle import data as odata
+    wl = configs.c1_small()
+    path = configs.ensure_file(wl.file, data_dir)
+    L = _probe_lib()
+    cfg = runner.make_config(wl.page_size, wl.cache_bytes, timeout_s=20)
+    with gfs.PageCache(cfg) as cache:
+        fid = cache.open(path)
+        other = configs.ensure_file(configs.FileSpec("probe_other_seed5.bin", 5, 1 << 20), data_dir)
+        fid2 = cache.open(other)
+        cache.close_file(fid2)                         # id fid2: below max_files, not registered
+        p_dev = torch.tensor(list(path.encode()) + [0], dtype=torch.uint8, device="cuda")
+        m_dev = torch.tensor(list((path + ".missing").encode()) + [0], dtype=torch.uint8, device="cuda")
+        off, size = 3 * (64 << 10) + 40, (100 << 10) + 16
+        buf = torch.zeros(size + 64, dtype=torch.uint8, device="cuda")
+        out = torch.full((10,), -999, dtype=torch.int64, device="cuda")
+        _say(f"api probe, {threads} threads")
+        rc = L.gfs_test_api_probe(cache.handle, p_dev.data_ptr(), m_dev.data_ptr(), fid2, off, size, wl.file.size,
+                                  threads, buf.data_ptr(), out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        assert rc == 0
+        torch.cuda.synchronize()
+        o = out.cpu().tolist()
+        st = cache.stats()
+    assert o[0] == fid
+    assert o[1] == -30 and o[2] == -2                  # -EROFS, -ENOENT
+    assert o[7] == -9 and o[8] == 0 and o[9] == -2     # gclose(bad) -EBADF, gclose ok, gopen_id -ENOENT
+    if threads % 64:
+        assert o[3] == -9 and o[4] == -9               # descriptors are checked first
+        assert o[5] == -22 and o[6] == -22             # -EINVAL: not a multiple of 64 threads
+    else:
+        assert o[3] == -9 and o[4] == -9               # -EBADF
+        assert o[5] == size and o[6] == 0
+        assert bytes(buf[:size].cpu().numpy()) == odata.delivered(path, off, size)
+        assert st["timeouts"] == 0 and st["io_errors"] == 0
+
+
+def test_close_drops_pages_before_the_id_is_reused(data_dir, cuda):
+    """gfs_close drops the file's cached pages: a different file opened next gets the same id,
+    and reading it without a cache reset returns its own bytes, not the closed file's."""
+    from oracle import data as odata
+    a = configs.c1_small()
+    b_spec = configs.FileSpec("reuse_seed23.bin", 23, a.file.size)
+    pa = configs.ensure_file(a.file, data_dir)
+    pb = configs.ensure_file(b_spec, data_dir)
+    want_a = odata.block_checksums(pa, a.offsets, a.read_size)
+    want_b = odata.block_checksums(pb, a.offsets, a.read_size)
+    assert not np.array_equal(want_a, want_b)
+    for ra in (0, 8):
+        cfg = runner.make_config(a.page_size, a.cache_bytes, ra_cap_bytes=ra * a.page_size, timeout_s=20)
+        with gfs.PageCache(cfg) as cache:
+            fa = cache.open(pa)
+            _say(f"reuse: read A, ra={ra}")
+            np.testing.assert_array_equal(runner.run_list(cache, fa, a.offsets, a.read_size, a.consumer).out, want_a)
+            np.testing.assert_array_equal(runner.run_list(cache, fa, a.offsets, a.read_size, a.consumer).out, want_a)
+            s0 = cache.stats()
+            cache.close_file(fa)
+            fb = cache.open(pb)
+            assert fb == fa                            # the id is reused
+            _say("reuse: read B under the same id, no reset")
+            res = runner.run_list(cache, fb, a.offsets, a.read_size, a.consumer)
+            s1 = cache.stats()
+            np.testing.assert_array_equal(res.out, want_b)
+            assert s1["fetched_pages"] - s0["fetched_pages"] == s0["fetched_pages"]   # all of B fetched
+            # and the first file, opened again (another id now), reads right too
+            fa2 = cache.open(pa)
+            np.testing.assert_array_equal(runner.run_list(cache, fa2, a.offsets, a.read_size, a.consumer).out,
+                                          want_a)
+
+
+def test_wait_timeout_gives_etimedout_and_every_block_exits(data_dir, cuda):
+    """Failure handling forced from the host: a 2 us device wait limit is far below a host
+    read, so blocks give up with -ETIMEDOUT (the kernel's own bounded waits; every block
+    returns) and no block delivers wrong bytes; after a reset the cache serves the same reads
+    correctly with the default limit."""
+    wl = configs.c2_small()
+    path = configs.ensure_file(wl.file, data_dir)
+    exp_out, exp_deliv = expected(wl, path)
+    cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=8 * wl.page_size, timeout_ns=2000)
+    with gfs.PageCache(cfg) as cache:
+        fid = cache.open(path)
+        _say("2 us wait limit")
+        res = runner.run_list(cache, fid, wl.offsets, wl.read_size, wl.consumer)
+        st = cache.stats()
+        timed_out = res.status == -110
+        assert timed_out.any() and st["timeouts"] > 0
+        ok = ~timed_out
+        np.testing.assert_array_equal(res.status[ok], exp_deliv[ok])
+        np.testing.assert_array_equal(res.out[ok], exp_out[ok])
+        assert set(res.status[timed_out].tolist()) == {-110}
+    cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=8 * wl.page_size, timeout_s=20)
+    with gfs.PageCache(cfg) as cache:
+        fid = cache.open(path)
+        res = runner.run_list(cache, fid, wl.offsets, wl.read_size, wl.consumer)
+        st = cache.stats()
+    assert st["timeouts"] == 0
+    np.testing.assert_array_equal(res.out, exp_out)
 
 
 def test_tiny_cache_many_blocks_progress(data_dir, cuda):

@@ -37,7 +37,7 @@ def test_config_default_values():
     assert cfg.page_size == 64 << 10 and cfg.cache_bytes == 256 << 20
     assert cfg.ra_init_bytes == 4 * cfg.page_size and cfg.ra_cap_bytes == 16 << 20
     assert cfg.streams_per_file == 8 and cfg.host_threads == 8 and cfg.rpc_slots == 64
-    assert ctypes.sizeof(gfs.gfs_config) == 88
+    assert ctypes.sizeof(gfs.gfs_config) == 112
     assert cfg.policy == gfs.GFS_POLICY_SHARED and cfg.private_slots == 512
     assert cfg.io_chunk_bytes == 2 << 20
     assert gfs.EVENT_DTYPE.itemsize == 32
@@ -101,6 +101,25 @@ def test_policy_and_queue_limits():
     for chunk in (64 << 10, 8 << 20, 64 << 20):
         gfs.gfs_device_bytes(gfs.gfs_config_default(io_chunk_bytes=chunk))
     for bad in (dict(io_chunk_bytes=0), dict(io_chunk_bytes=(1 << 20) + 512), dict(io_chunk_bytes=32 << 10),
-                dict(io_chunk_bytes=128 << 20), dict(reserved0=1)):
+                dict(io_chunk_bytes=128 << 20), dict(max_files=0), dict(max_files=1025), dict(ra_recent=0),
+                dict(ra_recent=65), dict(ra_near_min=0), dict(ra_near_min=66), dict(ra_near_pages=(1 << 20) + 1),
+                dict(ra_async=2)):
         with pytest.raises(OSError):
             gfs.gfs_device_bytes(gfs.gfs_config_default(**bad))
+
+
+def test_metadata_scales_with_max_files():
+    """Per-file metadata (record, miss lock and its 4096 queue slots, claims, path) is sized
+    by max_files: about 34 KiB per file, so 64 files take ~2 MiB rather than the 1024-file
+    maximum's ~34 MiB."""
+    _, m64 = gfs.gfs_device_bytes(gfs.gfs_config_default(max_files=64))
+    _, m1024 = gfs.gfs_device_bytes(gfs.gfs_config_default(max_files=1024))
+    per_file = (m1024 - m64) / 960
+    assert 33 << 10 < per_file < 35 << 10, per_file
+    assert m64 < m1024 / 8
+
+
+def test_detector_defaults():
+    cfg = gfs.gfs_config_default()
+    assert (cfg.ra_recent, cfg.ra_near_pages, cfg.ra_near_min) == (64, 64, 3)
+    assert cfg.ra_quota_blocks == 0 and cfg.ra_async == 0 and cfg.max_files == 64

@@ -191,9 +191,12 @@ def _interleavings(seqs):
         yield perm
 
 
-@pytest.mark.parametrize("case", range(6))
+@pytest.mark.parametrize("case", range(10))
 def test_brute_force_against_naive_model(case):
     rng = random.Random(1000 + case)
+    # detector constants: the defaults for the first cases, then small ones under which the
+    # aggregate rule fires or stays off within a few pages
+    det = (64, 64, 3) if case < 4 else (rng.choice([1, 2, 3]), rng.choice([0, 1, 2]), rng.choice([1, 2, 4]))
     nblocks = 3 if case % 2 == 0 else 2
     nacc = 3 if nblocks == 3 else 4
     npages = rng.randint(4, 8)
@@ -207,9 +210,10 @@ def test_brute_force_against_naive_model(case):
     n = 0
     for order in _interleavings(seqs):
         pos = [0] * nblocks
-        m = PolicyModel(nframes, psz, ra_init_pages=w0, ra_cap_pages=cap, streams_per_file=2)
+        m = PolicyModel(nframes, psz, ra_init_pages=w0, ra_cap_pages=cap, streams_per_file=2, recent=det[0],
+                        near_pages=det[1], near_min=det[2])
         m.open(0, fsize)
-        nv = NaiveModel(nframes, psz, w0, cap, 2)
+        nv = NaiveModel(nframes, psz, w0, cap, 2, recent=det[0], reach=det[1], enough=det[2])
         nv.open(0, fsize)
         for b in order:
             page, size = seqs[b][pos[b]]
@@ -248,6 +252,38 @@ def test_aggregate_read_takes_aligned_cap_chunk():
         m.gread(0, 0, p * 4096, 4096)
     assert [(e[4], e[5]) for e in _misses(m.events)] == [(10, 1), (30, 1), (50, 1), (64, 16)]
     assert [e for e in m.events if e[0] == "REQ"][-1] == ("REQ", 0, 64, 16)
+
+
+def test_aggregate_rule_constants_are_parameters():
+    # hand-worked with 2 remembered misses, radius 8, 2 near misses needed, cap 16: misses at
+    # 10 and 14 open probation streams (10 has no near history, 14 has one: 10); at 18 the
+    # ring holds 10 and 14, both within 8 -> aligned chunk [16, 32); at 100 the ring holds
+    # 14 and 18 (10 was forgotten), neither near -> probation
+    m = PolicyModel(nframes=256, page_size=4096, ra_init_pages=4, ra_cap_pages=16, streams_per_file=1,
+                    recent=2, near_pages=8, near_min=2)
+    m.open(0, 1 << 20)
+    for p in (10, 14, 18, 100):
+        m.gread(0, 0, p * 4096, 4096)
+    assert [(e[4], e[5]) for e in _misses(m.events)] == [(10, 1), (14, 1), (16, 16), (100, 1)]
+    assert [(n, r) for n, _, r in m.decisions] == [(0, 4), (1, 4), (2, 2), (0, 4)]
+    # the same reads under the default constants (3 near misses within 64 needed): no chunk
+    m2 = PolicyModel(nframes=256, page_size=4096, ra_init_pages=4, ra_cap_pages=16, streams_per_file=1)
+    m2.open(0, 1 << 20)
+    for p in (10, 14, 18):
+        m2.gread(0, 0, p * 4096, 4096)
+    assert [(e[4], e[5]) for e in _misses(m2.events)] == [(10, 1), (14, 1), (18, 1)]
+
+
+def test_thrash_guard_caps_windows_at_one_blocks_share():
+    from oracle.policy import quota_cap
+    # Sec. 5.1's quota: cache pages over the resident blocks (the smaller of the launch's
+    # grid and the resident count)
+    assert quota_cap(256, 16384, 1024, 512) == 32
+    assert quota_cap(16, 16384, 1024, 512) == 16
+    assert quota_cap(64, 8192, 1024, 512) == 16
+    assert quota_cap(64, 8192, 8, 512) == 64
+    assert quota_cap(16, 64, 1024, 512) == 1
+    assert quota_cap(16, 64, 1024, 1) == 16
 
 
 def test_request_is_the_unmapped_run_around_the_miss():

@@ -13,16 +13,19 @@ from oracle.policy import PolicyModel, run_serialized
 from workloads import configs
 
 
-def _to_replay(events):
+def _to_replay(model):
     """Model events -> replay tuples: give ALLOC the ticket of the claim before it and the
-    block of the current miss; give HAND the block too."""
+    block of the current miss; give HAND the block too; pack each miss's detector inputs
+    (near | h << 8 | rule << 24) the way the device trace does."""
     out = []
     blk = -1
     last_claim = None
-    for e in events:
+    decisions = iter(model.decisions)
+    for e in model.events:
         if e[0] == "MISS":
             blk = e[1]
-            out.append(("MISS", blk, e[2], e[3], e[4], e[5], None))
+            near, h, rule = next(decisions)
+            out.append(("MISS", blk, e[2], e[3], e[4], e[5], near | h << 8 | rule << 24))
         elif e[0] == "HAND":
             out.append(("HAND",) + tuple(e[1:]) + (blk,))
             if e[3] in ("FREE", "EVICT"):
@@ -36,44 +39,56 @@ def _to_replay(events):
     return out
 
 
-def _fill_near(events, page_size, cap):
-    """The model does not log its near count; recompute it the way the detector does."""
-    out = []
-    recent = {}
-    for e in events:
-        if e[0] == "MISS" and cap:
-            r = recent.setdefault(e[2], [])
-            near = sum(1 for x in r if abs(x - e[3]) <= 64)
-            r.append(e[3])
-            if len(r) > 64:
-                r.pop(0)
-            e = e[:6] + (near,)
-        elif e[0] == "MISS":
-            e = e[:6] + (0,)
-        out.append(e)
-    return out
-
-
-def _model_trace(name, cap):
+def _model_trace(name, cap, recent=64, near_pages=64, near_min=3):
     wl = configs.get(name)
     C = wl.cache_bytes // wl.page_size
-    m = PolicyModel(C, wl.page_size, ra_init_pages=4, ra_cap_pages=cap, streams_per_file=8)
+    m = PolicyModel(C, wl.page_size, ra_init_pages=4, ra_cap_pages=cap, streams_per_file=8, recent=recent,
+                    near_pages=near_pages, near_min=near_min)
     m.open(0, wl.file.size)
     run_serialized(m, 0, wl.offsets, wl.read_size)
-    ev = _fill_near(_to_replay(m.events), wl.page_size, cap)
+    ev = _to_replay(m)
     return wl, C, m, ev
 
 
-@pytest.mark.parametrize("name,cap", [("c2_small", 0), ("c2_small", 16), ("c3c_small", 8), ("c3a_small", 16)])
-def test_replay_accepts_rule_following_traces(name, cap):
-    wl, C, m, ev = _model_trace(name, cap)
+@pytest.mark.parametrize("name,cap,det", [("c2_small", 0, (64, 64, 3)), ("c2_small", 16, (64, 64, 3)),
+                                          ("c3c_small", 8, (64, 64, 3)), ("c3a_small", 16, (64, 64, 3)),
+                                          ("c2_small", 16, (8, 4, 2)), ("c3b_small", 8, (16, 8, 2)),
+                                          ("c3a_small", 8, (64, 64, 65)), ("c3c_small", 8, (64, 64, 65))])
+def test_replay_accepts_rule_following_traces(name, cap, det):
+    wl, C, m, ev = _model_trace(name, cap, *det)
     rc = replay.replay_clock(ev, C)
     assert [(f, p) for _, _, f, p in rc["evictions"]] == \
         [(e[4], e[5]) for e in m.events if e[0] == "HAND" and e[3] == "EVICT"]
     assert rc["allocations"] == m.fetched_pages and rc["wasted_pages"] == m.wasted_pages
-    rr = replay.replay_readahead(ev, 4, cap, 8, {0: wl.file.size}, wl.page_size)
-    assert rr["exact"] + rr["shape_only"] == m.misses
+    rr = replay.replay_readahead(ev, 4, cap, 8, {0: wl.file.size}, wl.page_size, recent=det[0],
+                                 near_pages=det[1], near_min=det[2])
+    assert rr["exact"] == m.misses and rr["shape_only"] == 0
     assert replay.replay_requests(ev) == m.requests
+
+
+def test_replay_rejects_hand_action_against_what_it_found():
+    """Each visit's action must follow from the bits it read: a CLEAR of a frame whose bit
+    was clear, an EVICT of a frame whose bit was set or that was pinned, a SKIP of a free,
+    unpinned frame without a lost race -- each is rejected."""
+    wl, C, m, ev = _model_trace("c2_small", 16)
+    for act, tweak in (("CLEAR", lambda s: s & ~1), ("EVICT", lambda s: s | 1), ("EVICT", lambda s: s | 2),
+                       ("SKIP", lambda s: 0), ("FREE", lambda s: s | 3 << 3)):
+        if not any(e[0] == "HAND" and e[3] == act for e in ev):
+            continue
+        bad = _mutate(ev, lambda e: e[0] == "HAND" and e[3] == act, lambda e: e[:7] + (tweak(e[7]),) + e[8:])
+        with pytest.raises(replay.ReplayError):
+            replay.replay_clock(bad, C)
+
+
+def test_replay_rejects_context_window_not_sized_by_history():
+    """A context decision's window is min(2h, cap) for the history h the trace reports."""
+    wl, C, m, ev = _model_trace("c3a_small", 8, near_min=65)     # aggregate rule off
+    ctx = [e for e in ev if e[0] == "MISS" and (e[6] >> 24) == 3]
+    assert ctx, "no context decision in the model trace"
+    assert replay.replay_readahead(ev, 4, 8, 8, {0: wl.file.size}, wl.page_size, near_min=65)["by_rule"][3] == len(ctx)
+    bad = _mutate(ev, lambda e: e is ctx[0], lambda e: e[:6] + (e[6] + (1 << 8),))
+    with pytest.raises(replay.ReplayError):
+        replay.replay_readahead(bad, 4, 8, 8, {0: wl.file.size}, wl.page_size, near_min=65)
 
 
 def _mutate(ev, pred, fn):

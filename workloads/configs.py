@@ -173,6 +173,62 @@ def c3_small(pattern: str) -> Workload:
     return Workload("c3" + pattern + "_small", f, 64 * KiB, 4 * MiB, blocks, 256, 64 * KiB, off, CONSUMER_CHECKSUM)
 
 
+@dataclasses.dataclass
+class MixedWorkload:
+    """Two files read at once through one persistent batch launch (the mixed case of Sec. 3.1,
+    where one file is read sequentially and another at random): file 0 in consecutive pieces,
+    file 1 in whole pages at random; the unit list interleaves one piece of file 0 with
+    `ratio` random reads of file 1. Output row 0 folds file 0's reads, row 1 file 1's."""
+    name: str
+    seq: FileSpec
+    rnd: FileSpec
+    page_size: int
+    cache_bytes: int
+    piece: int                 # bytes per sequential read of file 0
+    nrandom: int               # random page reads of file 1
+    ratio: int
+    seed: int                  # SplitMix64 seed of the random page indices
+
+    def units(self) -> np.ndarray:
+        """Records (file, out, offset, size) in launch order; file = 0 or 1 (the caller maps
+        them to registered ids)."""
+        seq_off = np.arange(0, self.seq.size, self.piece, dtype=np.uint64)
+        npages = self.rnd.size // self.page_size
+        bits = int(npages).bit_length() - 1
+        if 1 << bits != npages:
+            raise ValueError("file 1 must hold a power-of-two number of pages")
+        pages = splitmix.outputs(self.seed, 1, self.nrandom) >> np.uint64(64 - bits)
+        rnd_off = pages * np.uint64(self.page_size)
+        dt = np.dtype([("file", "<u4"), ("out", "<u4"), ("offset", "<u8"), ("size", "<u8")])
+        out = np.zeros(len(seq_off) + len(rnd_off), dtype=dt)
+        k = i = j = 0
+        while i < len(seq_off) or j < len(rnd_off):
+            if i < len(seq_off):
+                out[k] = (0, 0, seq_off[i], min(self.piece, self.seq.size - int(seq_off[i])))
+                k += 1
+                i += 1
+            for _ in range(self.ratio):
+                if j < len(rnd_off):
+                    out[k] = (1, 1, rnd_off[j], self.page_size)
+                    k += 1
+                    j += 1
+        return out
+
+
+def f2() -> MixedWorkload:
+    """2 GiB read in 1 MiB pieces (seed 5) beside 32768 random 64 KiB page reads of another
+    2 GiB file (seed 6, page indices from SplitMix64 seed 1000006), 1 GiB cache."""
+    return MixedWorkload("f2", FileSpec("f2a_seed5_2GiB.bin", 5, 2 * GiB), FileSpec("f2b_seed6_2GiB.bin", 6, 2 * GiB),
+                         64 * KiB, 1 * GiB, 1 * MiB, 32768, 16, 1000006)
+
+
+def f2_small() -> MixedWorkload:
+    """The mixed case at 1/128 scale: 16 MiB in 256 KiB pieces beside 256 random page reads of
+    a 16 MiB file, 8 MiB cache (128 frames)."""
+    return MixedWorkload("f2_small", FileSpec("f2sa_seed5.bin", 5, 16 * MiB), FileSpec("f2sb_seed6.bin", 6, 16 * MiB),
+                         64 * KiB, 8 * MiB, 256 * KiB, 256, 4, 1000006)
+
+
 REGISTRY = {
     "c1": c1, "c2": c2,
     "c3a": lambda: c3("a"), "c3b": lambda: c3("b"), "c3c": lambda: c3("c"),
