@@ -190,12 +190,171 @@ def hit_path(torch, gfs, runner, configs, ddir, host_threads):
     # algorithmic HBM bytes per delivered byte on a hit: frame read + user-buffer write
     # (+ the consumer's read of the user buffer, which is the benchmark, not the method)
     traffic, traffic_src = recorded_traffic(HIT_TRAFFIC_SUMMARY, "traffic_bytes_per_launch_1024x16")
+    # the method's own bytes on a hit: the frame read and the user-buffer write (2 B per delivered
+    # byte); the consumer's read of the user buffer (the third counted byte) is the benchmark's
+    method = 2 * hbytes / (hk * 1e-3) / 1e9
     return {"workload": "1 GiB file cached in a 2 GiB cache (64 KiB pages), 1024 blocks x 16 reads "
                         "of 64 KiB, all hits", "kernel_ms": hk,
             "delivered_GBps": hbytes / (hk * 1e-3) / 1e9,
             "hbm_GBps": 3 * hbytes / (hk * 1e-3) / 1e9,
-            "traffic": traffic, "traffic_source": traffic_src,
+            "roofline": {"bound": "hbm", "achieved": round(method, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(method / HBM_PEAK_GBS, 4), "bytes_per_launch": 2 * hbytes,
+                         "traffic": traffic, "traffic_source": traffic_src, "kernel": "list_reader_kernel",
+                         "note": "achieved counts 2 B per delivered byte (frame read + user-buffer write); "
+                                 "traffic is the counted HBM bytes, which include the consumer's read"},
             "misses_after_warm": s1["misses"] - s0["misses"]}
+
+
+def cpu_procs() -> int:
+    """Worker processes for the CPU legs: the CPUs this process may run on, at most 16 (one
+    GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_rows(args):
+    """One worker's share of the oracle: (kind, path, offsets rows, read size)."""
+    from oracle import data as odata
+    kind, path, offs, size = args
+    if kind == "hist":
+        return odata.block_histograms(path, offs, size)
+    return odata.block_checksums(path, offs, size)
+
+
+def _oracle_file(path):
+    from oracle import data as odata
+    return odata.file_digest(path)
+
+
+def _fork_pool(procs):
+    """A process pool made by fork: only used before this process touches the GPU."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    return ProcessPoolExecutor(max_workers=procs, mp_context=mp.get_context("fork"))
+
+
+def oracle_blocks(wl, path, procs: int):
+    """Every block's expected output of a list workload, split over `procs` processes."""
+    import numpy as np
+    kind = "hist" if wl.consumer == 1 else "csum"
+    if procs <= 1:
+        return _oracle_rows((kind, path, wl.offsets, wl.read_size))
+    cuts = np.linspace(0, wl.blocks, procs + 1).astype(int)
+    jobs = [(kind, path, wl.offsets[a:b], wl.read_size) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
+    with _fork_pool(procs) as ex:
+        parts = list(ex.map(_oracle_rows, jobs))
+    return np.concatenate(parts)
+
+
+def cpu_legs(wl, path):
+    """The CPU oracle timed on this host (run before the process touches the GPU): all
+    blocks with one thread, then with one process per available CPU (at most 16); returns
+    (cpu_baseline record, every block's expected output)."""
+    import numpy as np
+    t0 = time.perf_counter()
+    out1 = oracle_blocks(wl, path, 1)
+    dt1 = time.perf_counter() - t0
+    procs = cpu_procs()
+    t0 = time.perf_counter()
+    outn = oracle_blocks(wl, path, procs)
+    dtn = time.perf_counter() - t0
+    if not np.array_equal(out1, outn):
+        raise RuntimeError("oracle differs between one and several processes")
+    nbytes = wl.delivered_bytes
+    what = "histograms" if wl.consumer else "checksums"
+    rec = {"value": round(nbytes / dt1 / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+           "sample": f"all {wl.blocks} blocks ({nbytes >> 20} MiB): plain pread + numpy per-block {what}, "
+                     f"{dt1:.1f} s on one thread",
+           "parallel": {"value": round(nbytes / dtn / 1e9, 3), "unit": "GB/s", "cores": procs,
+                        "sample": f"the same {wl.blocks} blocks split over {procs} processes, {dtn:.1f} s"}}
+    log(f"cpu oracle: {rec['value']} GB/s on 1 core, {rec['parallel']['value']} GB/s on {procs}")
+    return rec, out1
+
+
+def cpu_io_comparator(torch, gfs, wl, path, want):
+    """The paper's CPU-I/O baseline (Sec. 6): one host thread reads the whole file (O_DIRECT,
+    4 MiB reads, into an aligned bounce buffer), copies it to the GPU, and the same
+    reads and consumers then run over the device copy (gfs_launch_buffer_reader). GB/s of
+    delivered bytes over the whole sequence; the outputs must equal the oracle's."""
+    import mmap
+
+    import numpy as np
+    chunk = 4 << 20
+    size = wl.file.size
+    dev = torch.empty(size, dtype=torch.uint8, device="cuda")
+    bounce = mmap.mmap(-1, chunk)                       # page-aligned
+    view = np.frombuffer(bounce, dtype=np.uint8)
+    offs = torch.from_numpy(np.ascontiguousarray(wl.offsets).view(np.int64)).to("cuda")
+    out = torch.zeros(wl.blocks * (256 if wl.consumer else 1), dtype=torch.int32 if wl.consumer else torch.int64,
+                      device="cuda")
+    status = torch.zeros(wl.blocks, dtype=torch.int64, device="cuda")
+    flags = os.O_RDONLY | getattr(os, "O_DIRECT", 0)
+    try:
+        fd = os.open(path, flags)
+    except OSError:
+        fd = os.open(path, os.O_RDONLY)
+    try:
+        os.posix_fadvise(fd, 0, 0, os.POSIX_FADV_DONTNEED)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        off = 0
+        while off < size:
+            n = os.preadv(fd, [bounce], off)
+            if n <= 0:
+                raise RuntimeError("short read in the CPU-I/O comparator")
+            dev[off:off + n].copy_(torch.from_numpy(view[:n]))
+            off += n
+        stream = torch.cuda.current_stream()
+        gfs.gfs_launch_buffer_reader(dev.data_ptr(), size, offs.data_ptr(), wl.blocks, wl.reads_per_block,
+                                     wl.read_size, wl.threads, wl.consumer, out.data_ptr(), status.data_ptr(),
+                                     stream.cuda_stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        os.close(fd)
+    got = out.cpu().numpy()
+    got = got.view(np.uint32).reshape(wl.blocks, 256) if wl.consumer else got.view(np.uint64)
+    if not np.array_equal(got, want):
+        raise RuntimeError("CPU-I/O comparator: outputs differ from the oracle")
+    del dev
+    return {"GBps": round(wl.delivered_bytes / dt / 1e9, 3), "host_threads": 1, "read_piece_MiB": chunk >> 20,
+            "what": "one host thread: O_DIRECT pread of the whole file + copy to the GPU, then the same consumer "
+                    "kernel over the device copy"}
+
+
+def list_passes(torch, gfs, runner, wl, path, cap_bytes, steps, warmup, host_threads, rpc_slots, io_chunk,
+                want=None, policy=None, private_slots=512, advice="normal"):
+    """Cold passes of a list workload with readahead at cap_bytes (0: off); every block's
+    output is compared with `want` when given. Returns a result dict (rates, kernel times,
+    counters, outputs)."""
+    import numpy as np
+    cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=cap_bytes, host_threads=host_threads,
+                             rpc_slots=rpc_slots, timeout_s=60, io_chunk_bytes=io_chunk,
+                             policy=gfs.GFS_POLICY_SHARED if policy is None else policy,
+                             private_slots=private_slots)
+    with gfs.PageCache(cfg) as cache:
+        fid = cache.open(path)
+        if advice != "normal":
+            cache.fadvise(fid, {"random": gfs.GFS_ADV_RANDOM, "sequential": gfs.GFS_ADV_SEQUENTIAL}[advice])
+        reader = runner.ListReader(wl.offsets, wl.read_size, wl.consumer, wl.threads)
+        wall, kms, st = run_steps(torch, cache, fid, reader, steps, warmup)
+        res = reader.result()
+    if st["timeouts"] or st["io_errors"]:
+        raise RuntimeError(f"{wl.name} cap {cap_bytes}: device errors {st}")
+    o = wl.offsets.astype(np.int64)
+    deliv = np.maximum(np.minimum(o + wl.read_size, wl.file.size) - o, 0).sum(axis=1)
+    if not np.array_equal(res.status, deliv):
+        raise RuntimeError(f"{wl.name} cap {cap_bytes}: wrong delivered byte counts")
+    if want is not None and not np.array_equal(res.out, want):
+        raise RuntimeError(f"{wl.name} cap {cap_bytes}: outputs differ from the oracle")
+    delivered = wl.delivered_bytes
+    per_step = [delivered / (k * 1e-3) / 1e9 for k in kms]
+    return {"wall_s": wall, "GBps": steps * delivered / wall / 1e9,
+            "kernel_GBps": delivered / (np.mean(kms) * 1e-3) / 1e9, "kernel_ms": float(np.mean(kms)),
+            "step_min_GBps": min(per_step), "step_max_GBps": max(per_step), "out": res.out, "stats": st}
 
 
 def _pool_files(m, ddir):
@@ -572,6 +731,8 @@ def main() -> int:
     ap.add_argument("--ra-cap-kib", type=int, default=0, help="readahead cap / prefetch size in KiB (overrides MiB)")
     ap.add_argument("--advice", default="normal", choices=["normal", "random", "sequential"],
                     help="fadvise-style hint for the file of c2/c3 (random switches readahead off)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default line without the extra records (c3a, c3b, c4, c5)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); "
@@ -579,11 +740,11 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
-    import numpy as np
-    import torch
+    pre = None
+    if args.workload == "c2":
+        pre = prepare_default(args)      # before this process touches the GPU (a fork pool runs)
 
-    from paper_2109_05366_amd import gfs, runner
-    from workloads import configs
+    import torch
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "c4":
@@ -596,116 +757,298 @@ def main() -> int:
         return bench_hits(args, torch)
     if args.workload == "f4":
         return bench_diagnostics(args, torch)
+    if args.workload != "c2":
+        return bench_list(args, torch)
+    return bench_default(args, torch, pre)
+
+
+def bench_list(args, torch) -> int:
+    """One list workload (c3a/c3b/c3c) on its own line: the same fields as the default line
+    without the extra records."""
+    import numpy as np
+
+    from paper_2109_05366_amd import gfs, runner
+    from workloads import configs
     wl = configs.get(args.workload)
     ddir = args.data_dir or os.environ.get("GFS_DATA_DIR") or configs.data_dir()
-    log(f"workload {wl.name}: file {wl.file.size >> 20} MiB, cache {wl.cache_bytes >> 20} MiB, "
-        f"page {wl.page_size >> 10} KiB, {wl.blocks} blocks x {wl.threads}, data dir {ddir}")
+    path = configs.ensure_file(wl.file, ddir)
+    nvme = storage_peak(path)
+    h2d = h2d_peak(torch)
+    cap = _cap_bytes(args, wl)
+    policy = gfs.GFS_POLICY_PRIVATE if args.policy == "private" else gfs.GFS_POLICY_SHARED
+    want = None
+    if not args.no_cpu_baseline:
+        from oracle import data as odata
+        want = (odata.block_histograms if wl.consumer else odata.block_checksums)(path, wl.offsets, wl.read_size)
+    ra = list_passes(torch, gfs, runner, wl, path, cap, args.steps, args.warmup, args.host_threads, args.rpc_slots,
+                     args.io_chunk_kib << 10, want, policy, args.private_slots, args.advice)
+    off = None if args.no_ra_off else list_passes(torch, gfs, runner, wl, path, 0, args.steps, args.warmup,
+                                                  args.host_threads, args.rpc_slots, args.io_chunk_kib << 10, want,
+                                                  policy, args.private_slots, args.advice)
+    value = ra["GBps"]
+    mp_ = min(nvme, h2d)
+    line = {
+        "metric": "delivered file-read GB/s (readahead vs none) + fraction of min(NVMe, H2D) peak",
+        "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ra["wall_s"] / args.steps * 1e3, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": _list_desc(wl), "ra_cap_KiB": cap >> 10, "policy": args.policy,
+                   "advice": args.advice, "host_threads": args.host_threads, "data_dir": ddir},
+        "readahead_off_GBps": round(off["GBps"], 3) if off else None,
+        "readahead_speedup": round(value / off["GBps"], 3) if off else None,
+        "storage_peak_GBps": round(nvme, 3), "h2d_peak_GBps": round(h2d, 3),
+        "io_bound": {"bound": "storage" if nvme < h2d else "h2d", "achieved": round(value, 3),
+                     "peak": round(mp_, 3), "unit": "GB/s", "frac": round(value / mp_, 3)},
+        "stats": {"ra": _stat_subset(ra["stats"]), "no_ra": _stat_subset(off["stats"]) if off else None},
+        "parity": "every block" if want is not None else "delivered byte counts only",
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def _cap_bytes(args, wl) -> int:
+    if args.ra_cap_kib:
+        return args.ra_cap_kib << 10
+    if args.ra_cap_mib is not None:
+        return args.ra_cap_mib << 20
+    return wl.ra_cap_bytes
+
+
+def _list_desc(wl) -> str:
+    size = f"{wl.file.size >> 30} GiB" if wl.file.size >= 1 << 30 else f"{wl.file.size >> 20} MiB"
+    cache = f"{wl.cache_bytes >> 30} GiB" if wl.cache_bytes >= 1 << 30 else f"{wl.cache_bytes >> 20} MiB"
+    return (f"{wl.name}: {size} splitmix64(seed={wl.file.seed}) file, {cache} cache, {wl.page_size >> 10} KiB "
+            f"pages, {wl.blocks} blocks x {wl.threads} threads, {wl.read_size >> 10} KiB reads, cold per step")
+
+
+_STAT_KEYS = ("hits", "joins", "misses", "ra_pages", "fetched_pages", "evictions", "wasted_pages", "requests",
+              "request_bytes", "host_bytes", "retries", "noframe", "host_read_ns", "t_lock_ns", "t_crit_ns",
+              "t_alloc_ns", "t_slot_ns", "t_host_ns", "t_pull_ns", "t_join_ns", "lock_acquired", "private_hits",
+              "private_wasted")
+
+
+def _stat_subset(st):
+    return {k: st[k] for k in _STAT_KEYS}
+
+
+def prepare_default(args):
+    """Everything the default line needs before the GPU is touched: the input files, the
+    CPU oracle timed on this host (one thread, then one process per CPU), and every expected
+    output of the extra records (computed by a process pool, which may only fork here)."""
+    import numpy as np
+
+    from workloads import configs, manifest
+    ddir = args.data_dir or os.environ.get("GFS_DATA_DIR") or configs.data_dir()
+    wl = configs.get("c2")
     t = time.perf_counter()
     path = configs.ensure_file(wl.file, ddir)
-    log(f"file ready ({time.perf_counter() - t:.1f} s): {path}")
+    log(f"workload c2: file {wl.file.size >> 20} MiB ready ({time.perf_counter() - t:.1f} s), data dir {ddir}")
+    pre = {"ddir": ddir, "wl": wl, "path": path}
+    if args.no_cpu_baseline:
+        pre["cpu"], pre["want"] = None, None
+    else:
+        pre["cpu"], pre["want"] = cpu_legs(wl, path)
+    pre["extra"] = {}
+    if args.no_extra:
+        return pre
+    procs = cpu_procs()
+    for name in ("c3a", "c3b"):
+        w = configs.get(name)
+        p = configs.ensure_file(w.file, ddir)
+        t = time.perf_counter()
+        pre["extra"][name] = {"wl": w, "path": p, "want": oracle_blocks(w, p, procs)}
+        log(f"{name}: oracle over every block ({time.perf_counter() - t:.1f} s, {procs} processes)")
+    m = manifest.load("batch")
+    paths = _pool_files(m, ddir)
+    t = time.perf_counter()
+    with _fork_pool(procs) as ex:
+        dig = list(ex.map(_oracle_file, paths))
+    pre["extra"]["c4"] = {"m": m, "paths": paths, "csum": np.array([d[0] for d in dig], dtype=np.uint64),
+                          "hist": np.stack([d[1] for d in dig])}
+    log(f"c4: oracle over every file ({time.perf_counter() - t:.1f} s)")
+    sm = manifest.load("serve")
+    sdir = _tmpfs_dir(sum(f["size"] for f in sm["files"]))
+    if sdir:
+        spaths = _pool_files(sm, sdir)
+        t = time.perf_counter()
+        with _fork_pool(procs) as ex:
+            sdig = list(ex.map(_oracle_file, spaths))
+        pre["extra"]["c5"] = {"m": sm, "paths": spaths, "dir": sdir,
+                              "csum": np.array([d[0] for d in sdig], dtype=np.uint64)}
+        log(f"c5: pool on tmpfs, oracle over every file ({time.perf_counter() - t:.1f} s)")
+    return pre
 
+
+def _tmpfs_dir(nbytes: int):
+    """A fresh directory on tmpfs with room for nbytes (and 2 GiB more), else None."""
+    import shutil
+    import tempfile
+    if not os.path.isdir("/dev/shm") or shutil.disk_usage("/dev/shm").free < nbytes + (2 << 30):
+        return None
+    return tempfile.mkdtemp(prefix="gfs_bench_pool_", dir="/dev/shm")
+
+
+def extra_list(torch, gfs, runner, args, name, e, passes: int = 3):
+    """A sub-record for another list workload: cold passes with readahead (the workload's cap,
+    the default thrash guard) and without, every block compared with the oracle, and the
+    fraction of the storage rate measured on the same file."""
+    wl, path = e["wl"], e["path"]
+    nvme = storage_peak(path)
+    ra = list_passes(torch, gfs, runner, wl, path, wl.ra_cap_bytes, passes, 1, args.host_threads,
+                     args.rpc_slots, args.io_chunk_kib << 10, e["want"])
+    off = list_passes(torch, gfs, runner, wl, path, 0, passes, 1, args.host_threads, args.rpc_slots,
+                      args.io_chunk_kib << 10, e["want"])
+    st = ra["stats"]
+    demand = st["fetched_pages"] - st["ra_pages"]
+    rec = {"workload": _list_desc(wl), "GBps": round(ra["GBps"], 3), "readahead_off_GBps": round(off["GBps"], 3),
+           "readahead_speedup": round(ra["GBps"] / off["GBps"], 3), "storage_peak_GBps": round(nvme, 3),
+           "frac_of_storage": round(ra["GBps"] / nvme, 3), "steps": passes, "ra_cap_KiB": wl.ra_cap_bytes >> 10,
+           "wasted_pages": st["wasted_pages"], "demand_pages": demand,
+           "wasted_frac_of_demand": round(st["wasted_pages"] / max(demand, 1), 4),
+           "fetched_pages": st["fetched_pages"], "requests": st["requests"], "parity": "every block"}
+    log(f"{name}: {rec}")
+    return rec
+
+
+def extra_batch(torch, args, e, passes: int = 3):
+    """C4: 64 lognormal files read whole by one persistent kernel: cold passes with the
+    autotuner's configuration, readahead off with the same plan, one launch per file;
+    every file's checksum and histogram compared with the oracle."""
+    import numpy as np
+
+    from paper_2109_05366_amd import autotune
+    m, paths = e["m"], e["paths"]
+    sizes = [f["size"] for f in m["files"]]
+    total = sum(sizes)
+    nvme = _multi_storage_peak(paths)
+    bb = autotune.BatchBench(paths, sizes, m["cache_bytes"], host_threads=args.host_threads, rpc_slots=args.rpc_slots)
+    best = (64 << 10, 1 << 20, 8)
+    bb.run(best)
+    runs = []
+    for _ in range(passes):
+        gbs, res, st = bb.run(best)
+        if st["timeouts"] or st["io_errors"] or int(res.status.sum()) != total:
+            raise RuntimeError(f"c4: device errors or short delivery {st}")
+        if not (np.array_equal(res.csum, e["csum"]) and np.array_equal(res.hist, e["hist"])):
+            raise RuntimeError("c4: outputs differ from the oracle")
+        runs.append(gbs)
+    off, res_off, _ = bb.run((best[0], 0, best[2]))
+    if not np.array_equal(res_off.csum, e["csum"]):
+        raise RuntimeError("c4 (readahead off): outputs differ from the oracle")
+    plain = bb.run_per_file(best)
+    value = float(np.mean(runs))
+    rec = {"workload": f"c4: {len(sizes)} lognormal files, {total / 2**30:.2f} GiB, {m['cache_bytes'] >> 30} GiB "
+                       f"cache, one persistent launch, cold per pass",
+           "GBps": round(value, 3), "runs_GBps": [round(x, 3) for x in runs], "readahead_off_GBps": round(off, 3),
+           "readahead_speedup": round(value / off, 3), "one_launch_per_file_GBps": round(plain, 3),
+           "batched_speedup": round(value / plain, 3), "storage_peak_GBps": round(nvme, 3),
+           "frac_of_storage": round(value / nvme, 3),
+           "config": {"page_KiB": best[0] >> 10, "ra_cap_MiB": best[1] >> 20, "blocks_per_file": best[2]},
+           "parity": "every file (checksum and histogram)"}
+    log(f"c4: {rec}")
+    return rec
+
+
+def extra_serve(torch, args, e, rate: int = 200):
+    """C5: the whole request stream (Poisson arrivals at `rate`/s) over the pool on tmpfs,
+    admitted by the cache budget; every request's checksum compared with the oracle's
+    checksum of its file."""
+    import numpy as np
+
+    from oracle import serve as oserve
+    from paper_2109_05366_amd import gfs, runner
+    from workloads import manifest
+    m, paths = e["m"], e["paths"]
+    sizes = np.array([f["size"] for f in m["files"]], dtype=np.int64)
+    files = np.array([r["file"] for r in m["requests"]])
+    budget = int(m["budget_bytes"])
+    page = 256 << 10
+    arrivals = manifest.scaled_arrivals(m, rate)
+    cfg = runner.make_config(page, budget, ra_cap_bytes=16 << 20, host_threads=8, rpc_slots=args.rpc_slots,
+                             timeout_s=60)
+    with gfs.PageCache(cfg) as cache:
+        ids = [cache.open(p) for p in paths]
+        recs, summ = runner.serve(cache, [ids[f] for f in files], arrivals, budget)
+        st = cache.stats()
+    if st["timeouts"] or st["io_errors"] or not np.array_equal(recs["result"], sizes[files]):
+        raise RuntimeError(f"c5: device errors or short delivery {st}")
+    if not np.array_equal(recs["csum"], e["csum"][files]):
+        raise RuntimeError("c5: a request's checksum differs from the oracle")
+    oserve.check_admission(recs["arrival_ns"], recs["admit_ns"], recs["done_ns"], recs["seq"], recs["reserved"],
+                           budget)
+    lat = runner.latency_ms(recs)
+    gbs = summ["delivered_bytes"] / summ["span_ns"]
+    offered = float(sizes[files].sum()) / (arrivals[-1] / 1e9) / 1e9
+    rec = {"workload": f"c5: {len(files)} Poisson requests at {rate}/s over a {len(sizes)}-file pool "
+                       f"({sizes.sum() / 2**30:.1f} GiB, tmpfs), {budget >> 30} GiB cache budget, 256 KiB pages",
+           "GBps": round(gbs, 3), "offered_GBps": round(offered, 3), "span_s": round(summ["span_ns"] / 1e9, 2),
+           **{k: round(v, 2) for k, v in lat.items()}, "requests": len(files),
+           "host_GB": round(st["host_bytes"] / 1e9, 2), "page_hits": st["hits"],
+           "peak_pending": summ["peak_pending"], "parity": "every request's checksum"}
+    log(f"c5: {rec}")
+    return rec
+
+
+def bench_default(args, torch, pre) -> int:
+    """The headline line: C2 from the box's storage, readahead on and off, with the extra
+    records (C3a, C3b, C4, C5) unless --no-extra."""
+    import numpy as np
+
+    from paper_2109_05366_amd import gfs, runner
+    wl, path, ddir = pre["wl"], pre["path"], pre["ddir"]
     # the disk's rate drifts by +-15 % within minutes: sample it before and after the timed
     # passes and take the mean as the bound
     nvme_samples = [storage_peak(path)]
     log(f"storage peak {nvme_samples[0]:.2f} GB/s")
     h2d = h2d_peak(torch)
     log(f"pinned H2D peak {h2d:.2f} GB/s")
-
     delivered = wl.delivered_bytes
-    results = {}
-    stats = {}
-    kernel_ms = {}
-    if args.ra_cap_kib:
-        cap_bytes = args.ra_cap_kib << 10
-    elif args.ra_cap_mib is not None:
-        cap_bytes = args.ra_cap_mib << 20
-    else:
-        cap_bytes = wl.ra_cap_bytes
+    cap_bytes = _cap_bytes(args, wl)
     policy = gfs.GFS_POLICY_PRIVATE if args.policy == "private" else gfs.GFS_POLICY_SHARED
+    results = {}
     for label, cap in (("ra", cap_bytes), ("no_ra", 0)):
         if label == "no_ra" and args.no_ra_off:
             continue
-        cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=cap,
-                                 host_threads=args.host_threads, rpc_slots=args.rpc_slots, timeout_s=60,
-                                 policy=policy, private_slots=args.private_slots,
-                                 io_chunk_bytes=args.io_chunk_kib << 10)
-        with gfs.PageCache(cfg) as cache:
-            fid = cache.open(path)
-            if args.advice != "normal":
-                cache.fadvise(fid, {"random": gfs.GFS_ADV_RANDOM, "sequential": gfs.GFS_ADV_SEQUENTIAL}[args.advice])
-            reader = runner.ListReader(wl.offsets, wl.read_size, wl.consumer, wl.threads)
-            log(f"{label}: cap {cap >> 10} KiB, policy {args.policy}")
-            wall, kms, st = run_steps(torch, cache, fid, reader, args.steps, args.warmup)
-            res = reader.result()
-        if st["timeouts"] or st["io_errors"]:
-            raise RuntimeError(f"{label}: device errors {st}")
-        if not np.array_equal(res.status, np.full(wl.blocks, delivered // wl.blocks)):
-            raise RuntimeError(f"{label}: wrong delivered byte counts")
-        per_step = [delivered / (k * 1e-3) / 1e9 for k in kms]
-        results[label] = {"wall_s": wall, "GBps": args.steps * delivered / wall / 1e9,
-                          "kernel_GBps": delivered / (np.mean(kms) * 1e-3) / 1e9,
-                          "step_min_GBps": min(per_step), "step_max_GBps": max(per_step),
-                          "out": res.out}
-        stats[label] = {k: st[k] for k in ("hits", "joins", "misses", "ra_pages", "fetched_pages",
-                                           "evictions", "wasted_pages", "requests", "request_bytes",
-                                           "host_bytes", "retries", "noframe", "host_read_ns",
-                                           "t_lock_ns", "t_crit_ns", "t_alloc_ns", "t_slot_ns",
-                                           "t_host_ns", "t_pull_ns", "t_join_ns", "private_hits",
-                                           "private_wasted")}
-        kernel_ms[label] = float(np.mean(kms))
+        log(f"{label}: cap {cap >> 10} KiB, policy {args.policy}")
+        results[label] = list_passes(torch, gfs, runner, wl, path, cap, args.steps, args.warmup, args.host_threads,
+                                     args.rpc_slots, args.io_chunk_kib << 10, pre["want"], policy,
+                                     args.private_slots, args.advice)
         log(f"{label}: {results[label]['GBps']:.2f} GB/s wall, {results[label]['kernel_GBps']:.2f} GB/s kernel")
-
     nvme_samples.append(storage_peak(path))
     nvme = float(np.mean(nvme_samples))
     log(f"storage peak after the passes {nvme_samples[1]:.2f} GB/s (mean {nvme:.2f})")
-
-    # parity on sampled blocks against the oracle (the full run's outputs)
-    from oracle import data as odata
-    rng = np.random.default_rng(0)
-    sample = sorted(set(int(x) for x in rng.integers(0, wl.blocks, size=4)) | {0, wl.blocks - 1})
-    if wl.consumer == configs.CONSUMER_HISTOGRAM:
-        want = odata.block_histograms(path, wl.offsets, wl.read_size, blocks=sample)
-    else:
-        want = odata.block_checksums(path, wl.offsets, wl.read_size, blocks=sample)
-    parity_ok = all(np.array_equal(r["out"][sample], want[sample]) for r in results.values())
-    if not parity_ok:
-        raise RuntimeError("parity failure on sampled blocks")
-
-    # all-hit pass: a 1 GiB file held entirely in a 2 GiB cache, read twice; the second pass
-    # is lookup + pin + copy-out + consumer only
+    cpu_io = None
+    if pre["want"] is not None:
+        cpu_io = cpu_io_comparator(torch, gfs, wl, path, pre["want"])
+        log(f"CPU-I/O comparator: {cpu_io['GBps']} GB/s")
     # calibration for HBM traffic counters: a plain 1 GiB device-to-device copy (known bytes)
     calib_src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
     calib_dst = torch.empty_like(calib_src)
     calib_dst.copy_(calib_src)
     torch.cuda.synchronize()
     del calib_src, calib_dst
-
-    hit = None if args.no_hit_path else hit_path(torch, gfs, runner, configs, ddir, args.host_threads)
+    hit = None if args.no_hit_path else hit_path(torch, gfs, runner, configs_mod(), ddir, args.host_threads)
     fast = None
     if not args.no_tmpfs and not ddir.startswith("/dev/shm"):
-        fast = fast_storage(torch, gfs, runner, configs, wl, cap_bytes, args, h2d)
+        fast = fast_storage(torch, gfs, runner, configs_mod(), wl, cap_bytes, args, h2d)
         if fast:
             log(f"tmpfs: {fast['GBps']:.2f} GB/s ({fast['frac_of_h2d_peak']:.3f} of pinned H2D), "
                 f"readahead off {fast['readahead_off_GBps']:.2f} GB/s")
     if hit:
-        log(f"hit path: {hit['delivered_GBps']:.1f} GB/s delivered, {hit['hbm_GBps']:.1f} GB/s HBM")
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        # a bounded sample: every block of the workload is about 10-30 s of single-core oracle
-        # work at the sizes here; larger workloads take every k-th block up to 1024 blocks
-        cblocks = list(range(0, wl.blocks, max(1, wl.blocks // 1024)))[:1024]
-        t0 = time.perf_counter()
-        if wl.consumer == configs.CONSUMER_HISTOGRAM:
-            odata.block_histograms(path, wl.offsets, wl.read_size, blocks=cblocks)
-        else:
-            odata.block_checksums(path, wl.offsets, wl.read_size, blocks=cblocks)
-        dt = time.perf_counter() - t0
-        cbytes = len(cblocks) * wl.reads_per_block * wl.read_size
-        cpu = {"value": cbytes / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(cblocks)} of {wl.blocks} blocks ({cbytes >> 20} MiB): plain pread + "
-                         f"numpy per-block {'histograms' if wl.consumer else 'checksums'}, {dt:.1f} s"}
-        log(f"cpu oracle: {cpu['value']:.2f} GB/s on {cbytes >> 20} MiB")
+        log(f"hit path: {hit['delivered_GBps']:.1f} GB/s delivered")
+    extra = {}
+    try:
+        for name in ("c3a", "c3b"):
+            if name in pre["extra"]:
+                extra[name] = extra_list(torch, gfs, runner, args, name, pre["extra"][name])
+        if "c4" in pre["extra"]:
+            extra["c4"] = extra_batch(torch, args, pre["extra"]["c4"])
+        if "c5" in pre["extra"]:
+            extra["c5"] = extra_serve(torch, args, pre["extra"]["c5"])
+    finally:
+        import shutil
+        if "c5" in pre["extra"]:
+            shutil.rmtree(pre["extra"]["c5"]["dir"], ignore_errors=True)
 
     ra = results["ra"]
     value = ra["GBps"]
@@ -713,7 +1056,7 @@ def main() -> int:
     min_peak = min(nvme, h2d)
     # dominant kernel: the list reader; algorithmic HBM bytes per delivered byte = 3
     # (frame fill write, copy-out read, user-buffer write)
-    kms_ra = kernel_ms["ra"]
+    kms_ra = ra["kernel_ms"]
     achieved = 3 * delivered / (kms_ra * 1e-3) / 1e9
     traffic, traffic_src = recorded_traffic()
     line = {
@@ -729,12 +1072,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {wl.file.size >> 30} GiB splitmix64(seed={wl.file.seed}) file, "
-                               f"{wl.cache_bytes >> 30} GiB cache, {wl.page_size >> 10} KiB pages, "
-                               f"{wl.blocks} blocks x {wl.threads} threads, {wl.read_size >> 10} KiB reads, "
-                               f"cold per step",
-                   "ra_cap_KiB": cap_bytes >> 10, "policy": args.policy, "advice": args.advice,
-                   "host_threads": args.host_threads, "io_chunk_KiB": args.io_chunk_kib,
+        "config": {"workload": _list_desc(wl), "ra_cap_KiB": cap_bytes >> 10, "policy": args.policy,
+                   "advice": args.advice, "host_threads": args.host_threads, "io_chunk_KiB": args.io_chunk_kib,
                    "rpc_slots": args.rpc_slots, "data_dir": ddir},
         "readahead_off_GBps": round(results["no_ra"]["GBps"], 3) if "no_ra" in results else None,
         "readahead_speedup": round(value / results["no_ra"]["GBps"], 3) if "no_ra" in results else None,
@@ -745,22 +1084,27 @@ def main() -> int:
         "io_bound": {"bound": bound_name, "achieved": round(value, 3), "peak": round(min_peak, 3),
                      "unit": "GB/s", "frac": round(value / min_peak, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": traffic if wl.name == "c2" else None,
-                     "traffic_source": traffic_src if wl.name == "c2" else "counters taken on c2 only",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "traffic_source": traffic_src,
                      "kernel": "list_reader_kernel", "kernel_ms": round(kms_ra, 2),
                      "bytes_per_launch": 3 * delivered},
         "hit_path": hit,
         "tmpfs": fast,
+        "cpu_io_comparator": cpu_io,
         "kernel_GBps": {k: round(v["kernel_GBps"], 3) for k, v in results.items()},
         "step_min_max_GBps": {k: [round(v["step_min_GBps"], 3), round(v["step_max_GBps"], 3)]
                               for k, v in results.items()},
-        "stats": stats,
-        "parity_sampled_blocks": sample,
-        "cpu_baseline": cpu,
+        "stats": {k: _stat_subset(v["stats"]) for k, v in results.items()},
+        "parity": "every block of every timed pass" if pre["want"] is not None else "delivered byte counts only",
+        "cpu_baseline": pre["cpu"],
+        "extra": extra,
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def configs_mod():
+    from workloads import configs
+    return configs
 
 
 if __name__ == "__main__":

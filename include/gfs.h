@@ -282,6 +282,16 @@ int gfs_launch_list_reader(gfs_ctx* ctx, int file_id, const uint64_t* offsets, u
                            void* buf, void* out, int64_t* status, uint64_t* turn,
                            void* hip_stream);
 
+/* gfs_launch_buffer_reader: the list reader's reads and consumers taken straight from a copy
+ * of the file in device memory (data_dev, data_size bytes) instead of through gread; reads at
+ * or past data_size deliver nothing, reads crossing it are cut short, exactly like gread at
+ * the end of a file. This is the GPU half of the paper's CPU-I/O baseline (Sec. 6: the CPU
+ * reads the file and copies it to the GPU, then the kernel runs). Arguments as for
+ * gfs_launch_list_reader (offsets need no alignment); no context. -EINVAL on bad shapes. */
+int gfs_launch_buffer_reader(const void* data_dev, uint64_t data_size, const uint64_t* offsets, uint32_t blocks,
+                             uint32_t reads, uint64_t read_size, uint32_t threads, int consumer, void* out,
+                             int64_t* status, void* hip_stream);
+
 /* ---- batched persistent launch (many files, one kernel) ----
  *
  * A unit is one gread of one file: bytes [offset, offset+size) of file `file`, folded into

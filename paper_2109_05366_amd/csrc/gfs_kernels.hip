@@ -110,6 +110,52 @@ __global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) list_reader_kernel(cons
   if (tid == 0) status[b] = err ? err : total;
 }
 
+// The same reads and consumers as list_reader_kernel, taken straight from a copy of the file
+// in device memory instead of through gread: the GPU half of the CPU-I/O comparator, where
+// host code reads the file and copies it to the GPU before the kernel runs (the paper's
+// "CPU I/O" baseline, Sec. 6).
+__global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) buffer_reader_kernel(const uint8_t* data, uint64_t size,
+                                                                              const uint64_t* offsets, uint32_t reads,
+                                                                              uint64_t read_size, int consumer,
+                                                                              void* out, int64_t* status) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t red[16];
+  const uint32_t b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  if (consumer == 1)
+    for (uint32_t i = tid; i < 256; i += nt) hist[i] = 0;
+  __syncthreads();
+  int64_t total = 0;
+  uint64_t csum = 0;
+  for (uint32_t k = 0; k < reads; ++k) {
+    const uint64_t off = offsets[(uint64_t)b * reads + k];
+    if (off >= size) continue;
+    const uint64_t n = read_size < size - off ? read_size : size - off;
+    const uint8_t* p = data + off;
+    total += (int64_t)n;
+    if ((((uintptr_t)p) & 15) == 0) {
+      if (consumer == 0) csum += checksum_part(p, n, tid, nt);
+      else histogram_part(p, n, tid, nt, hist);
+    } else if (consumer == 0) {
+      for (uint64_t w = 4ull * tid; w < n; w += 4ull * nt) {
+        uint32_t word = 0;
+        for (int i = 0; i < 4; ++i)
+          if (w + i < n) word |= (uint32_t)p[w + i] << (8 * i);
+        csum += word;
+      }
+    } else {
+      for (uint64_t j = tid; j < n; j += nt) atomicAdd(&hist[p[j]], 1u);
+    }
+  }
+  __syncthreads();
+  if (consumer == 0) {
+    const uint64_t s = block_sum_u64(csum, red, tid, nt);
+    if (tid == 0) ((uint64_t*)out)[b] = s;
+  } else {
+    for (uint32_t i = tid; i < 256; i += nt) ((uint32_t*)out)[(uint64_t)b * 256 + i] = hist[i];
+  }
+  if (tid == 0) status[b] = total;
+}
+
 // Persistent batch reader: blocks take units in order from one device counter; a block
 // keeps its descriptor and its partial checksum/histogram while consecutive units belong
 // to the same file, and adds them into that file's output row when it moves on.
@@ -191,6 +237,19 @@ extern "C" int gfs_launch_batch(gfs_ctx* ctx, const gfs_unit* units, uint64_t nu
   if (rc) return rc;
   hipLaunchKernelGGL(batch_reader_kernel, dim3(grid), dim3(threads), 0, s, gfs_device_handle(ctx), units,
                      nunits, counter, (uint8_t*)buf, unit_bytes, csum, hist, status);
+  return hipGetLastError() == hipSuccess ? 0 : -EIO;
+}
+
+extern "C" int gfs_launch_buffer_reader(const void* data_dev, uint64_t data_size, const uint64_t* offsets,
+                                        uint32_t blocks, uint32_t reads, uint64_t read_size, uint32_t threads,
+                                        int consumer, void* out, int64_t* status, void* hip_stream) {
+  if (!data_dev || !offsets || !out || !status) return -EINVAL;
+  if (blocks == 0 || blocks > (1u << 20) || reads == 0) return -EINVAL;
+  if (threads == 0 || threads % 64 || threads > GFS_MAX_BLOCK_THREADS) return -EINVAL;
+  if (read_size == 0 || (consumer != 0 && consumer != 1)) return -EINVAL;
+  if (((uintptr_t)out) & 15) return -EINVAL;
+  hipLaunchKernelGGL(buffer_reader_kernel, dim3(blocks), dim3(threads), 0, (hipStream_t)hip_stream,
+                     (const uint8_t*)data_dev, data_size, offsets, reads, read_size, consumer, out, status);
   return hipGetLastError() == hipSuccess ? 0 : -EIO;
 }
 

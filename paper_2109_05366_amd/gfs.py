@@ -103,6 +103,7 @@ def lib() -> C.CDLL:
     L.gfs_reset_cache.argtypes = [vp]
     L.gfs_shutdown.argtypes = [vp]
     L.gfs_launch_list_reader.argtypes = [vp, i32, vp, u32, u32, u64, u32, i32, vp, vp, vp, vp, vp]
+    L.gfs_launch_buffer_reader.argtypes = [vp, u64, vp, u32, u32, u64, u32, i32, vp, vp, vp]
     L.gfs_batch_plan.argtypes = [vp, vp, u32, u64, u32, u32, vp, u64, C.POINTER(u64)]
     L.gfs_launch_batch.argtypes = [vp, vp, u64, u32, u32, u64, vp, vp, vp, vp, vp, vp]
     L.gfs_batch_grid.argtypes = [u32, C.POINTER(u32)]
@@ -111,7 +112,8 @@ def lib() -> C.CDLL:
     L.gfs_serve_run.argtypes = [vp, vp, u32, C.POINTER(gfs_serve_params), vp, C.POINTER(gfs_serve_summary), vp]
     for name in ("gfs_device_bytes", "gfs_init", "gfs_open", "gfs_fadvise", "gfs_close",
                  "gfs_stats_read", "gfs_trace_read", "gfs_reset_cache", "gfs_shutdown",
-                 "gfs_launch_list_reader", "gfs_batch_plan", "gfs_launch_batch", "gfs_batch_grid",
+                 "gfs_launch_list_reader", "gfs_launch_buffer_reader", "gfs_batch_plan", "gfs_launch_batch",
+                 "gfs_batch_grid",
                  "gfs_file_size", "gfs_get_config", "gfs_serve_run"):
         getattr(L, name).restype = i32
     _lib = L
@@ -202,6 +204,14 @@ def gfs_launch_list_reader(ctx: int, file_id: int, offsets_dev: int, blocks: int
                                         C.c_void_p(out_dev), C.c_void_p(status_dev),
                                         C.c_void_p(turn_dev or 0), C.c_void_p(stream)),
            "gfs_launch_list_reader")
+
+
+def gfs_launch_buffer_reader(data_dev: int, data_size: int, offsets_dev: int, blocks: int, reads: int,
+                             read_size: int, threads: int, consumer: int, out_dev: int, status_dev: int,
+                             stream: int) -> None:
+    _check(lib().gfs_launch_buffer_reader(C.c_void_p(data_dev), data_size, C.c_void_p(offsets_dev), blocks, reads,
+                                          read_size, threads, consumer, C.c_void_p(out_dev), C.c_void_p(status_dev),
+                                          C.c_void_p(stream)), "gfs_launch_buffer_reader")
 
 
 def gfs_batch_plan(sizes, ids, unit_bytes: int, grid: int, blocks_per_file: int) -> np.ndarray:

@@ -424,3 +424,36 @@ def test_partitioned_host_queue(name, data_dir, cuda):
     np.testing.assert_array_equal(res.status, exp_deliv)
     np.testing.assert_array_equal(res.out, exp_out)
     assert sum(st["host_thread_requests"]) == st["requests"]
+
+
+@pytest.mark.parametrize("name", ["c1_small", "c2_small"])
+def test_buffer_reader_matches_oracle(name, data_dir, cuda):
+    """The CPU-I/O comparator's kernel (the same reads and consumers over a device copy of the
+    file) gives the oracle's outputs, including reads at and past the end of the file and an
+    unaligned read."""
+    torch = cuda
+    wl = configs.get(name)
+    path = configs.ensure_file(wl.file, data_dir)
+    offs = wl.offsets.copy()
+    offs[0, 0] += np.uint64(3)                          # an unaligned read
+    exp_out = (odata_mod().block_checksums if wl.consumer == 0 else odata_mod().block_histograms)(
+        path, offs, wl.read_size)
+    with open(path, "rb") as fh:
+        raw = np.frombuffer(fh.read(), dtype=np.uint8)
+    data = torch.from_numpy(raw.copy()).to("cuda")
+    o_dev = torch.from_numpy(offs.view(np.int64)).to("cuda")
+    out = torch.zeros(wl.blocks * (1 if wl.consumer == 0 else 256), dtype=torch.int64 if wl.consumer == 0
+                      else torch.int32, device="cuda")
+    status = torch.zeros(wl.blocks, dtype=torch.int64, device="cuda")
+    gfs.gfs_launch_buffer_reader(data.data_ptr(), len(raw), o_dev.data_ptr(), wl.blocks, wl.reads_per_block,
+                                 wl.read_size, 256, wl.consumer, out.data_ptr(), status.data_ptr(),
+                                 torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    got = got.view(np.uint64) if wl.consumer == 0 else got.view(np.uint32).reshape(wl.blocks, 256)
+    np.testing.assert_array_equal(got, exp_out)
+
+
+def odata_mod():
+    from oracle import data as odata
+    return odata

@@ -14,7 +14,7 @@ difference in floating-point libraries can never make them disagree.
   sigma = 1.2) clipped to [16 MiB, 4 GiB] from seed 1000005; the full 512-file pool (about
   138 GiB) does not fit the disk, so the first 64 draws of that stream form the pool (file
   j has contents seed 10000 + j) and the cache budget keeps the full design's ratio of a
-  quarter of the pool. Requests: Poisson arrivals at 200/s from SplitMix64(seed 7); request
+  quarter of the pool. Requests: 20 000 Poisson arrivals at 200/s from SplitMix64(seed 7); request
   i takes the uniforms of outputs 2i+1 and 2i+2: the gap since the previous arrival is
   -ln(1 - u) / rate (inverse CDF) and the file is floor(u' * pool). Times are integer ns.
   Other rates reuse the same draws with every time scaled by 200 / rate.
@@ -92,7 +92,7 @@ def build_serve(small: bool = False) -> Dict[str, object]:
     files = [{"name": f"c5_{j:03d}.bin", "seed": 10000 + j, "size": s} for j, s in enumerate(sizes)]
     budget = sum(sizes) // 4 // GiB * GiB
     return {"name": "serve", "budget_bytes": budget, "rate_per_s": 200,
-            "files": files, "requests": poisson_arrivals(7, 400, 200.0, len(files))}
+            "files": files, "requests": poisson_arrivals(7, 20000, 200.0, len(files))}
 
 
 def scaled_arrivals(m: Dict[str, object], rate_per_s: int) -> List[int]:
