@@ -509,7 +509,7 @@ def bench_serve(args, torch) -> int:
                 raise RuntimeError(f"c5 parity failure on file {f}")
     head = out[0]
     line = {
-        "metric": "delivered file-read GB/s of a request stream, p50/p99 time to first chunk and completion",
+        "metric": "delivered file-read GB/s of a request stream, p50/p99 time to first page and completion",
         "value": head["GBps"], "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": round(head["span_s"] * 1e3, 1), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",

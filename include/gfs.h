@@ -53,7 +53,7 @@ extern "C" {
 
 /* host read backends */
 #define GFS_IO_PREAD 0              /* any idle host thread takes the next request (ring order) */
-#define GFS_IO_PREAD_PARTITIONED 1  /* GPUfs's queue (Sec. 3.4): a block posts into the slot of its
+#define GFS_IO_PREAD_PARTITIONED 1  /* GPUfs's queue (Sec. 3.3): a block posts into the slot of its
                                        block id (mod rpc_slots); host thread i serves only its own
                                        contiguous range of slots, one request at a time */
 
@@ -110,9 +110,13 @@ typedef struct gfs_config {
                                     "Asynchronous operation"); 1 = marker-triggered (Sec. 2.3) */
 } gfs_config;
 
-/* Fill *cfg with defaults: 64 KiB pages, 256 MiB cache, readahead 4 pages growing to
- * 16 MiB, 8 streams per file, 8 host threads, 64 slots, 2 MiB host read pieces, O_DIRECT
- * preferred, trace off, shared policy (512 private slots if the private policy is chosen).
+/* Fill *cfg with defaults: 64 KiB pages (the best GPUfs page size for sequential reads,
+ * Sec. 3.1), 256 MiB cache, readahead 4 pages (the 16 KB first fetch of Sec. 3.2's example,
+ * at 4 KB pages) growing by doubling to 16 MiB (Linux's window growth, Sec. 2.3), 8 streams
+ * per file (Sec. 2.3: several streams per descriptor), 8 host threads, 64 slots, 2 MiB host
+ * read pieces, O_DIRECT preferred, trace off, shared policy (512 private slots if the
+ * private policy is chosen), 64 files, detector constants 64/64/3, the device's resident
+ * blocks for the thrash guard, synchronous prefetch (Sec. 4).
  *
  * GFS_POLICY_PRIVATE: a miss that the block's private buffer cannot serve asks the host for
  * the page plus ra_cap_bytes that follow it (PREFETCH_SIZE, static); the page goes into the
@@ -126,13 +130,16 @@ void gfs_config_default(gfs_config* cfg);
 typedef struct gfs_ctx gfs_ctx;
 struct gfs_dev;
 
-/* Device memory the caller must provide for a configuration: the frame pool
+/* Device memory the caller must provide for a configuration (Sec. 2.2: the page cache lives in
+ * GPU memory; Sec. 5.1: its frames are reused in place): the frame pool
  * (cache_bytes, plus the private buffers under GFS_POLICY_PRIVATE; 256-byte aligned) and
  * the metadata region (page table, frame words,
  * tags, per-file state, counters, trace ring). -EINVAL if the configuration is invalid. */
 int gfs_device_bytes(const gfs_config* cfg, size_t* frames_bytes, size_t* meta_bytes);
 
-/* Create a cache. frames_dev and meta_dev are device pointers (e.g. from PyTorch) of at
+/* Create a cache (Sec. 2.2: the GPU page cache, the shared CPU-GPU request queue, and the
+ * host threads that poll it and read files for the GPU). frames_dev and meta_dev are device
+ * pointers (e.g. from PyTorch) of at
  * least the sizes gfs_device_bytes reports; they stay owned by the caller and must
  * outlive the context. hip_stream is the hipStream_t the library uses for its own
  * set-up work (may be NULL for the null stream). The call initialises the metadata,
@@ -141,15 +148,17 @@ int gfs_device_bytes(const gfs_config* cfg, size_t* frames_bytes, size_t* meta_b
 int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_stream,
              gfs_ctx** out);
 
-/* Register a file for device reads. flags must be GFS_O_RDONLY (the paper enables
- * prefetching only for read-only files; there is no write path): anything else gives
+/* Register a file for device reads (the host half of Sec. 2.2's open). flags must be
+ * GFS_O_RDONLY (Sec. 4, page cache coherency: prefetching is enabled only for read-only
+ * files; there is no write path): anything else gives
  * -EROFS. The path is copied. *file_id receives the id that gopen resolves the same
  * path to, and that the workload launchers take. Must not run concurrently with
  * kernels using the context. Errors: -ENFILE (table full), -errno from open/fstat,
  * -EFBIG (more pages than the encoding holds). */
 int gfs_open(gfs_ctx* ctx, const char* path, int flags, int* file_id);
 
-/* Readahead hint for a registered file (Sec. 4, runtime hints like posix_fadvise):
+/* Readahead hint for a registered file (Sec. 4.1: for files not read in order the paper lets
+ * the user switch its prefetcher off with a posix_fadvise-style hint):
  * GFS_ADV_RANDOM switches readahead off for it, GFS_ADV_SEQUENTIAL opens every new
  * stream with the initial window, GFS_ADV_NORMAL restores the default. */
 int gfs_fadvise(gfs_ctx* ctx, int file_id, int advice);
@@ -161,7 +170,8 @@ int gfs_fadvise(gfs_ctx* ctx, int file_id, int advice);
  * open (gopen without gclose; the file stays registered), -EIO on a HIP error. */
 int gfs_close(gfs_ctx* ctx, int file_id);
 
-/* Device pointer to the cache handle; pass it to kernels that call gread. */
+/* Device pointer to the cache handle; pass it to kernels that call gopen/gread/gclose (Sec.
+ * 2.2: GPU threadblocks call the file API). NULL if ctx is NULL; valid until gfs_shutdown. */
 const struct gfs_dev* gfs_device_handle(gfs_ctx* ctx);
 
 typedef struct gfs_stats {
@@ -214,7 +224,10 @@ typedef struct gfs_stats {
   uint64_t host_thread_requests[64];   /* per host thread: requests it started serving */
 } gfs_stats;
 
-/* Snapshot the counters. Call when no kernel using the context is running. */
+/* Snapshot the counters (the quantities Sec. 3 and Sec. 6 measure: hits and misses of the GPU
+ * page cache, prefetched and wasted pages, host requests and bytes, each host thread's polls
+ * before its first request as in Sec. 3.3). Call when no kernel using the context is
+ * running; -EINVAL on NULL arguments, -EIO on a HIP error. */
 int gfs_stats_read(gfs_ctx* ctx, gfs_stats* out);
 
 /* Trace record (32 bytes), written by device code when trace_level > 0. */
@@ -250,19 +263,26 @@ enum { GFS_RA_RULE_OFF = 0, GFS_RA_RULE_ZONE = 1, GFS_RA_RULE_AGGREGATE = 2, GFS
        GFS_RA_RULE_NEW = 4 };
 enum { GFS_HAND_FREE = 0, GFS_HAND_SKIP = 1, GFS_HAND_CLEAR = 2, GFS_HAND_EVICT = 3 };
 
-/* Copy up to cap_bytes of recorded events (in record order) to host memory dst;
- * *n_bytes receives the bytes copied. Call when no kernel using the context runs. */
+/* Copy up to cap_bytes of recorded events (in record order) to host memory dst; *n_bytes
+ * receives the bytes copied (whole records). The trace is the GPU I/O trace that Sec. 3.3
+ * records and replays on the CPU; here it carries the policy's decisions for the CPU model
+ * to replay. Call when no kernel using the context runs. -EINVAL, -EIO. */
 int gfs_trace_read(gfs_ctx* ctx, void* dst, size_t cap_bytes, size_t* n_bytes);
 
-/* Drop every cached page, readahead stream, counter and trace record (cold start).
- * Registered files stay registered. Call when no kernel using the context runs. */
+/* Drop every cached page, readahead stream, counter and trace record (cold start: Sec. 6
+ * flushes the page cache before every run; file reads then use O_DIRECT or come after
+ * POSIX_FADV_DONTNEED). Registered files stay registered. Call when no kernel using the
+ * context runs. -EINVAL, -EIO. */
 int gfs_reset_cache(gfs_ctx* ctx);
 
-/* Stop the host threads, free the ring and staging, close files, free the context.
- * Kernels using the handle must have completed. */
+/* Stop the host threads (Sec. 2.2), free the ring and staging, close files, free the
+ * context. Kernels using the handle must have completed. -EINVAL if ctx is NULL. */
 int gfs_shutdown(gfs_ctx* ctx);
 
 /* ---- workload launchers (the benchmark consumers of gread; not part of the method) ----
+ *
+ * The workloads follow the paper's microbenchmark (Sec. 6.1): threadblocks each read their
+ * share of a file in fixed-size strides, in order.
  *
  * gfs_launch_list_reader: one kernel of `blocks` threadblocks x `threads` threads
  * (a multiple of 64, <= GFS_MAX_BLOCK_THREADS). Block b calls gread(file, offsets[b*reads + k],
@@ -303,7 +323,8 @@ typedef struct gfs_unit {
   uint64_t size;
 } gfs_unit;           /* 24 B */
 
-/* Plan the unit order of a batch (host only, no GPU): files in the given order are cut
+/* Plan the unit order of a batch (host only, no GPU; a launch shape of this library, which
+ * the paper, launching one kernel per application, does not have): files in the given order are cut
  * into units of at most unit_bytes; `grid / blocks_per_file` files are read at a time,
  * their units interleaved round-robin, and a finished file's place is taken by the next
  * one, so that a grid pulling units in order has about blocks_per_file blocks on each
@@ -314,7 +335,9 @@ int gfs_batch_plan(const uint64_t* sizes, const uint32_t* ids, uint32_t nfiles, 
                    uint32_t grid, uint32_t blocks_per_file, gfs_unit* out, uint64_t cap,
                    uint64_t* nout);
 
-/* gfs_launch_batch: one persistent kernel of `grid` blocks x `threads` threads (a multiple
+/* gfs_launch_batch (every unit is one block-level gread, Sec. 2.2; the persistent launch over
+ * many files is this library's own shape): one persistent kernel of `grid` blocks x `threads`
+ * threads (a multiple
  * of 64, <= GFS_MAX_BLOCK_THREADS); blocks take units from units[0..nunits) in order through the device
  * counter *counter (reset by the call), gread each into their own buf + b*unit_bytes, and
  * fold the bytes into csum[out] (wrapping u64 sum of LE u32 words) and hist[out*256 + v]
@@ -326,17 +349,26 @@ int gfs_launch_batch(gfs_ctx* ctx, const gfs_unit* units, uint64_t nunits, uint3
                      uint64_t* csum, uint32_t* hist, int64_t* status, void* hip_stream);
 
 /* Blocks of `threads` threads that fit on the device at once for the batch kernel (the grid
- * a persistent launch should use); -EIO on a HIP error. */
+ * a persistent launch should use; Sec. 3.3 shows why the resident count matters: blocks not
+ * yet resident leave their host threads idle); -EINVAL on a bad thread count, -EIO on a HIP
+ * error. */
 int gfs_batch_grid(uint32_t threads, uint32_t* grid);
 
-/* Size in bytes of a registered file (host only). -EBADF if file_id is not registered. */
+/* Size in bytes of a registered file (host only; the size gread clamps to, Sec. 2.2's POSIX
+ * read semantics). -EBADF if file_id is not registered, -EINVAL if size is NULL. */
 int gfs_file_size(gfs_ctx* ctx, int file_id, uint64_t* size);
 
 /* The configuration the context was created with (host only), with ra_quota_blocks resolved
- * to the count in use when it was 0. */
+ * to the count in use when it was 0 (the resident blocks of Sec. 5.1's quota). -EINVAL on
+ * NULL arguments. */
 int gfs_get_config(gfs_ctx* ctx, gfs_config* out);
 
 /* ---- serving loop (a stream of whole-file read requests, one persistent kernel) ----
+ *
+ * The paper has no serving loop; this one is built from its parts: every request is a
+ * stream of block-level greads (Sec. 2.2), admission keeps the bytes of unfinished requests
+ * within the cache (Sec. 5: files larger than the cache stream through frames reused in
+ * place), and the readahead detector serves each request's sequential stream (Sec. 4).
  *
  * Every request reads one registered file from start to end through gread, in chunks of
  * chunk_bytes, and yields the wrapping u64 sum of the file's little-endian u32 words (a
@@ -365,7 +397,8 @@ typedef struct gfs_serve_record {
   int64_t result;         /* bytes delivered, or -errno of the first failed gread */
   uint64_t arrival_ns;    /* times after the start of the run, host clock */
   uint64_t admit_ns;      /* the host handed the request to the kernel */
-  uint64_t first_ns;      /* first chunk delivered (device clock mapped to the host's) */
+  uint64_t first_ns;      /* the file's first page delivered (device clock mapped to the host's;
+                             0 if that read failed) */
   uint64_t done_ns;       /* the host saw the request complete */
   uint64_t seq;           /* admission order */
   uint64_t reserved;      /* cache bytes reserved for it */

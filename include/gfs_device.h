@@ -17,8 +17,9 @@
  *       Copy file bytes [offset, min(offset+size, file size)) to dst (device memory of
  *       at least that many bytes; 16-byte alignment of dst and offset takes the vector
  *       path). Returns the byte count (short only at EOF, 0 at or past it) or -EBADF,
- *       -EINVAL, -EIO (host read failed), -ENOSPC (page table full), -ETIMEDOUT (a wait
- *       exceeded the configured timeout; the cache must then be reset).
+ *       -EINVAL, -EIO (host read failed), -ENOSPC (the page's table buckets stayed full of
+ *       other misses' reservations until the wait limit), -ETIMEDOUT (a wait exceeded the
+ *       configured timeout; the cache must then be reset).
  *   int     gclose(const gfs_dev* d, int fd);
  *
  * How a read is served (Sec. 2.2 and Sec. 4.1): the request is divided into pages; each
@@ -992,6 +993,15 @@ __device__ int miss_private_wave(const gfs_dev* d, uint32_t file, uint64_t p, ui
   if (l == 0) bcount(bs, GFS_T_CRIT, wall_clock64() - tl1);
   if (present) return 1;
   if (slot < 0) {
+    /* both buckets of the key are full: reservations of misses in flight come and go, so
+       back off and look again; only a table still full at the wait limit is an error */
+    if (!expired(d, t0)) {
+      if (l == 0) {
+        bcount(bs, GFS_C_RETRIES, 1);
+        nap(naps);
+      }
+      return 1;
+    }
     if (l == 0) {
       bs->status = -kENOSPC;
       bs->pull = 0;
@@ -1330,7 +1340,8 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       }
       if (got == 0) {
         if (l == 0) bcount(bs, keep ? GFS_C_NOFRAME : GFS_C_RETRIES, 1);
-        if (keep == 0) {
+        if (keep == 0 && expired(d, t0)) {
+          /* the demanded page's buckets stayed full until the wait limit */
           if (l == 0) {
             bs->status = -kENOSPC;
             bs->pull = 0;
@@ -1340,7 +1351,8 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
         }
         if (expired(d, t0)) break;
         if (l == 0) nap(naps);
-        continue;   /* every frame pinned or filling: back off and retry the access */
+        continue;   /* buckets full of reservations in flight, or every frame pinned or
+                       filling: back off and retry the access */
       }
       if (got < n && l == 0)
         trace_ev(d, 1, GFS_EV_NOFRAME, bid, file, bs->list[got], GFS_NO_FRAME, 0, 0);

@@ -4,7 +4,7 @@
 // requested span, and the GPU side places every page of it in the cache).
 //
 // Differences from the paper's host side, on purpose: any idle host thread takes any posted
-// request (the paper's per-thread slot partition left threads idle, Sec. 3.4);
+// request (the paper's per-thread slot partition left threads idle, Sec. 3.3);
 // one read covers a whole readahead span instead of one page per read; the data is read
 // straight into pinned staging that the GPU pulls from, so the host issues no copy calls.
 #include <errno.h>
@@ -102,9 +102,11 @@ int make_layout(const gfs_config* c, Layout* L) {
     return -EINVAL;
   }
   L->max_req_bytes = L->max_req_pages * P;
-  // page table: 4 entries per frame, 16-entry buckets, power-of-two bucket count
+  // page table: 4 entries per frame, plus room for the reservations of misses in flight
+  // (a page is reserved before it gets a frame; with a small cache, blocks that miss at once
+  // can hold more reservations than there are frames), 16-entry buckets, power-of-two count
   uint64_t nb = 2;
-  while (nb * GFS_BUCKET_SLOTS < 4 * L->nframes) nb <<= 1;
+  while (nb * GFS_BUCKET_SLOTS < 4 * L->nframes + 2 * GFS_LOCK_SLOTS) nb <<= 1;
   L->nbuckets = nb;
   uint64_t o = 0;
   L->off_globals = o; o = align_up(o + sizeof(gfs_globals), kAlign);
@@ -263,7 +265,7 @@ bool pop_chunk(gfs_ctx* c, gfs_ctx::Chunk* out) {
   return true;
 }
 
-// Partitioned queue (GPUfs's, Sec. 3.4): thread idx serves only the slots
+// Partitioned queue (GPUfs's, Sec. 3.3): thread idx serves only the slots
 // [idx*S/N, (idx+1)*S/N), in turn, each request whole by itself.
 void io_thread_partitioned(gfs_ctx* c, int idx) {
   const uint32_t NS = c->cfg.rpc_slots, N = c->cfg.host_threads;

@@ -41,7 +41,7 @@ struct SrvEntry {
   uint64_t next;       /* chunks handed out */
   uint64_t done;       /* chunks finished */
   uint64_t csum;       /* wrapping sum over finished chunks */
-  uint64_t t_first;    /* wall_clock64 when the first chunk finished (0: none yet) */
+  uint64_t t_first;    /* wall_clock64 when the request's first page was delivered (0: not yet) */
   int64_t err;         /* -errno of the first failed chunk (0: none) */
 };
 static_assert(sizeof(SrvEntry) == 64, "entry is one 64-byte record");
@@ -242,7 +242,22 @@ __global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) serve_kernel(const gfs_
     }
     const uint64_t off = k * chunk;
     const uint64_t len = std::min<uint64_t>(chunk, size - off);
-    if (r == 0) r = gread(d, fd, off, len, mybuf);
+    if (r == 0 && k == 0) {
+      // the request's first page on its own, so that its delivery time is the time to
+      // first page; then the rest of the chunk
+      const uint64_t first = std::min<uint64_t>(len, d->page_size);
+      r = gread(d, fd, 0, first, mybuf);
+      if (r == (int64_t)first && tid == 0) {
+        uint64_t zero = 0;
+        gfsd::cas64(&tab[i].t_first, zero, wall_clock64());
+      }
+      if (r == (int64_t)first && first < len) {
+        const int64_t r2 = gread(d, fd, first, len - first, mybuf + first);
+        r = r2 < 0 ? r2 : r + r2;
+      }
+    } else if (r == 0) {
+      r = gread(d, fd, off, len, mybuf);
+    }
     const uint64_t part = r > 0 ? checksum_part(mybuf, (uint64_t)r, tid, nt) : 0;
     const uint64_t s = block_sum_u64(part, red, tid, nt);
     if (tid == 0) {
@@ -256,8 +271,6 @@ __global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) serve_kernel(const gfs_
         total += r;
       }
       const uint64_t now = wall_clock64();
-      uint64_t zero = 0;
-      gfsd::cas64(&e->t_first, zero, now);
       gfsd::st_rlx(&ctl->progress, now);
       const uint64_t prev = __hip_atomic_fetch_add(&e->done, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
       if (prev + 1 == e->nchunks) complete_entry(e, &done[i], gfsd::ld_acq(&e->t_first));

@@ -144,7 +144,7 @@ def serve(cache: gfs.PageCache, file_ids, arrival_ns, budget_bytes: int, chunk_b
 
 
 def latency_ms(records: np.ndarray) -> dict:
-    """p50/p99 of time to first chunk and of completion, from arrival, in milliseconds."""
+    """p50/p99 of time to first page and of completion, from arrival, in milliseconds."""
     ttfp = (records["first_ns"].astype(np.float64) - records["arrival_ns"]) / 1e6
     done = (records["done_ns"].astype(np.float64) - records["arrival_ns"]) / 1e6
     return {"ttfp_p50": float(np.percentile(ttfp, 50)), "ttfp_p99": float(np.percentile(ttfp, 99)),

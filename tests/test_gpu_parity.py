@@ -114,7 +114,7 @@ def _compare_traces(ev, model, st):
 @pytest.mark.parametrize("name,advice", [("c3b_small", "random"), ("c3c_small", "sequential"),
                                          ("c3c_small", "random"), ("c3a_small", "sequential")])
 def test_fadvise_serialized_trace_matches_model(name, advice, data_dir, cuda):
-    """gfs_fadvise (Sec. 4: runtime hints like posix_fadvise): RANDOM turns readahead off for
+    """gfs_fadvise (Sec. 4.1: a posix_fadvise-style hint switches prefetching off): RANDOM turns readahead off for
     the file (every miss fetches its page alone), SEQUENTIAL opens every new stream with the
     initial window; the device trace equals the model run with the same advice."""
     from oracle.policy import ADV_RANDOM, ADV_SEQUENTIAL

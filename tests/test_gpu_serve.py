@@ -48,7 +48,7 @@ def _check_records(recs, sizes, files, want, budget, page):
     assert list(recs["reserved"]) == reserved
     oserve.check_admission(recs["arrival_ns"], recs["admit_ns"], recs["done_ns"], recs["seq"], recs["reserved"],
                            budget)
-    # the first chunk lands between admission and completion (device clock mapped to the host's)
+    # the first page lands between admission and completion (device clock mapped to the host's)
     slack = 200_000
     assert np.all(recs["first_ns"].astype(np.int64) + slack >= recs["admit_ns"].astype(np.int64))
     assert np.all(recs["first_ns"] <= recs["done_ns"] + slack)

@@ -47,8 +47,10 @@ def test_device_bytes_layout_scales_with_frames():
     f1, m1 = gfs.gfs_device_bytes(gfs.gfs_config_default(cache_bytes=256 << 20))
     f2, m2 = gfs.gfs_device_bytes(gfs.gfs_config_default(cache_bytes=512 << 20))
     assert f1 == 256 << 20 and f2 == 512 << 20
-    # frame words, tags and fill tags (24 B) + table (4 entries x 8 B) per frame
-    assert m2 - m1 == (4096 * (8 + 8 + 8 + 32))
+    # frame words, tags and fill tags (24 B per frame) + the table: 8 B entries, at least 4
+    # per frame plus 8192 for reservations in flight, a power of two of 16-entry buckets
+    # (32768 entries for 4096 frames, 65536 for 8192)
+    assert m2 - m1 == 4096 * (8 + 8 + 8) + 8 * (65536 - 32768)
     f3, m3 = gfs.gfs_device_bytes(gfs.gfs_config_default(trace_level=1, trace_capacity=1000))
     assert m3 - m1 >= 1000 * 32
 
