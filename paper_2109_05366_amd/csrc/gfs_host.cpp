@@ -1,12 +1,8 @@
-// Host runtime of the GPU file page cache: context set-up, file registry, and the host
-// I/O threads that serve the device's request ring (Sec. 2.2: host threads poll the shared
-// CPU-GPU request queue and read the file for the GPU; Sec. 4.1: the host reads the whole
-// requested span, and the GPU side places every page of it in the cache).
-//
-// Differences from the paper's host side, on purpose: any idle host thread takes any posted
-// request (the paper's per-thread slot partition left threads idle, Sec. 3.3);
-// one read covers a whole readahead span instead of one page per read; the data is read
-// straight into pinned staging that the GPU pulls from, so the host issues no copy calls.
+// Host runtime of the GPU file page cache: context set-up (HBM metadata layout, pinned ring
+// and staging), the file registry, statistics, trace, reset and shutdown (Sec. 2.2: the
+// GPU page cache and the shared CPU-GPU request queue). The host I/O threads that serve the
+// ring are in gfs_hostio.h; the host issues no copy calls: the GPU pulls each request's
+// bytes from pinned staging itself.
 #include <errno.h>
 #include <fcntl.h>
 #include <sched.h>
@@ -28,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include "gfs.h"
+#include "gfs_hostio.h"
 #include "gfs_layout.h"
 
 extern "C" int gfs_internal_zero(void* p, size_t bytes, hipStream_t s);
@@ -38,14 +35,9 @@ extern "C" int gfs_internal_purge_file(const gfs_dev* ddev, uint32_t nframes, ui
 namespace {
 
 constexpr uint64_t kAlign = 256;
-constexpr uint64_t kDirectAlign = 4096;
 
-uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
-uint64_t now_ns() {
-  timespec t;
-  clock_gettime(CLOCK_MONOTONIC, &t);
-  return (uint64_t)t.tv_sec * 1000000000ull + (uint64_t)t.tv_nsec;
-}
+using gfs_hostio::align_up;
+using gfs_hostio::kDirectAlign;
 bool pow2(uint64_t v) { return v && !(v & (v - 1)); }
 uint32_t log2u(uint64_t v) {
   uint32_t s = 0;
@@ -131,14 +123,6 @@ int make_layout(const gfs_config* c, Layout* L) {
   return 0;
 }
 
-struct HostFile {
-  std::atomic<int> fd{-1};
-  bool open = false;
-  bool direct = false;
-  uint64_t size = 0;
-  std::string path;
-};
-
 }  // namespace
 
 struct gfs_ctx {
@@ -152,250 +136,13 @@ struct gfs_ctx {
   gfs_dev* ddev = nullptr;
   gfs_rpc_slot* ring = nullptr;   // host address (pinned, mapped)
   uint8_t* staging = nullptr;     // host address (pinned, mapped)
-  HostFile files[GFS_MAX_FILES];
-  std::vector<std::thread> threads;
-  std::unique_ptr<std::atomic<uint64_t>[]> claimed;   // per ring slot: last generation a thread took
-  std::atomic<bool> stop{false};
-  std::atomic<uint64_t> host_requests{0}, host_bytes{0}, host_read_ns{0}, host_errors{0};
-  std::atomic<int64_t> host_last_errno{0};
-  std::atomic<uint64_t> spins[64];
-  std::atomic<uint64_t> thread_requests[64];
+  gfs_hostio::HostFile files[GFS_MAX_FILES];
+  gfs_hostio::HostIo io;          // the host I/O threads serving the ring
   bool last_direct = false;
   int clock_khz = 100000;
-  /* a request larger than one chunk is split; any I/O thread may read any chunk */
-  struct Chunk {
-    uint32_t slot;
-    uint64_t gen;
-    uint64_t off;       /* file offset */
-    uint64_t len;
-    uint64_t dst;       /* byte offset in the slot's staging */
-  };
-  struct Track {
-    std::atomic<uint32_t> remaining{0};
-    std::atomic<int64_t> total{0};
-    std::atomic<int64_t> err{0};
-  };
-  std::mutex qmu;
-  std::deque<Chunk> queue;
-  std::atomic<uint32_t> queued{0};
-  std::unique_ptr<Track[]> track;
 };
 
 namespace {
-
-// Read file bytes [off, off+len) into dst (pinned staging). Returns bytes read (short only
-// at end of file) or -errno. Direct reads cannot target the GPU driver's pinned pages (the
-// kernel refuses to pin them for DMA, EFAULT), so they go through the thread's aligned
-// bounce buffer in chunks and are copied into staging; buffered reads go straight in.
-int64_t read_span(int fd, bool direct, uint8_t* dst, uint64_t off, uint64_t len, uint8_t* bounce,
-                  uint64_t chunk) {
-  uint64_t done = 0;
-  if (!direct) {
-    while (done < len) {
-      const ssize_t r = pread(fd, dst + done, len - done, (off_t)(off + done));
-      if (r < 0) {
-        if (errno == EINTR) continue;
-        return -(int64_t)errno;
-      }
-      if (r == 0) break;
-      done += (uint64_t)r;
-    }
-    return (int64_t)done;
-  }
-  while (done < len) {
-    const uint64_t want = len - done < chunk ? align_up(len - done, kDirectAlign) : chunk;
-    ssize_t r;
-    do {
-      r = pread(fd, bounce, want, (off_t)(off + done));
-    } while (r < 0 && errno == EINTR);
-    if (r < 0) return -(int64_t)errno;
-    if (r == 0) break;
-    uint64_t take = (uint64_t)r;
-    if (take > len - done) take = len - done;
-    memcpy(dst + done, bounce, take);
-    done += take;
-    if ((uint64_t)r < want) break;   // end of file
-  }
-  return (int64_t)done;
-}
-
-inline void cpu_relax() { __builtin_ia32_pause(); }
-
-// Read one chunk of a request into the slot's staging; the thread that finishes a
-// request's last chunk publishes its result to the device.
-void run_chunk(gfs_ctx* c, const gfs_ctx::Chunk& ch, uint8_t* bounce) {
-  gfs_rpc_slot* rs = &c->ring[ch.slot];
-  gfs_ctx::Track& tr = c->track[ch.slot];
-  const uint32_t fid = rs->file_id;
-  HostFile* hf = fid < GFS_MAX_FILES ? &c->files[fid] : nullptr;
-  const int fd = hf ? hf->fd.load(std::memory_order_acquire) : -1;
-  int64_t r;
-  if (fd < 0) {
-    r = -EBADF;
-  } else {
-    const uint64_t t0 = now_ns();
-    r = read_span(fd, hf->direct, c->staging + (uint64_t)ch.slot * c->L.max_req_bytes + ch.dst,
-                  ch.off, ch.len, bounce, c->cfg.io_chunk_bytes);
-    c->host_read_ns.fetch_add(now_ns() - t0, std::memory_order_relaxed);
-  }
-  if (r < 0) {
-    tr.err.store(r, std::memory_order_relaxed);
-    c->host_errors.fetch_add(1, std::memory_order_relaxed);
-    c->host_last_errno.store(-r, std::memory_order_relaxed);
-  } else {
-    tr.total.fetch_add(r, std::memory_order_relaxed);
-    c->host_bytes.fetch_add((uint64_t)r, std::memory_order_relaxed);
-  }
-  if (tr.remaining.fetch_sub(1, std::memory_order_acq_rel) == 1) {
-    const int64_t e = tr.err.load(std::memory_order_relaxed);
-    rs->result = e ? e : tr.total.load(std::memory_order_relaxed);
-    rs->t_done_ns = now_ns();
-    __atomic_store_n(&rs->done_seq, ch.gen, __ATOMIC_RELEASE);
-    c->host_requests.fetch_add(1, std::memory_order_relaxed);
-  }
-}
-
-bool pop_chunk(gfs_ctx* c, gfs_ctx::Chunk* out) {
-  if (c->queued.load(std::memory_order_relaxed) == 0) return false;
-  std::lock_guard<std::mutex> g(c->qmu);
-  if (c->queue.empty()) return false;
-  *out = c->queue.front();
-  c->queue.pop_front();
-  c->queued.fetch_sub(1, std::memory_order_relaxed);
-  return true;
-}
-
-// Partitioned queue (GPUfs's, Sec. 3.3): thread idx serves only the slots
-// [idx*S/N, (idx+1)*S/N), in turn, each request whole by itself.
-void io_thread_partitioned(gfs_ctx* c, int idx) {
-  const uint32_t NS = c->cfg.rpc_slots, N = c->cfg.host_threads;
-  const uint32_t lo = (uint32_t)((uint64_t)idx * NS / N), hi = (uint32_t)((uint64_t)(idx + 1) * NS / N);
-  std::vector<uint64_t> want(hi - lo, 1);   // next generation of each own slot
-  bool first = true;
-  uint64_t spins = 0;
-  const uint64_t chunk = c->cfg.io_chunk_bytes;
-  uint8_t* bounce = (uint8_t*)aligned_alloc(kDirectAlign, chunk);
-  if (!bounce) return;
-  while (!c->stop.load(std::memory_order_relaxed)) {
-    bool served = false;
-    for (uint32_t s = lo; s < hi; ++s) {
-      gfs_rpc_slot* rs = &c->ring[s];
-      const uint64_t gen = want[s - lo];
-      if (__atomic_load_n(&rs->req_seq, __ATOMIC_ACQUIRE) != gen) continue;
-      if (first) {
-        c->spins[idx].store(spins, std::memory_order_relaxed);
-        first = false;
-      }
-      c->thread_requests[idx].fetch_add(1, std::memory_order_relaxed);
-      rs->t_claim_ns = now_ns();
-      const uint64_t off = rs->offset, len = rs->length;
-      const uint64_t n = len > c->L.max_req_bytes ? 0 : (len + chunk - 1) / chunk;
-      gfs_ctx::Track& tr = c->track[s];
-      tr.total.store(0, std::memory_order_relaxed);
-      tr.err.store(n == 0 && len ? -EINVAL : 0, std::memory_order_relaxed);
-      tr.remaining.store(n ? (uint32_t)n : 1u, std::memory_order_release);
-      if (n == 0) {
-        run_chunk(c, {s, gen, off, 0, 0}, bounce);
-      } else {
-        for (uint64_t i = 0; i < n; ++i) {
-          const uint64_t o = i * chunk;
-          run_chunk(c, {s, gen, off + o, (len - o) < chunk ? (len - o) : chunk, o}, bounce);
-        }
-      }
-      want[s - lo] = gen + 1;
-      served = true;
-    }
-    if (!served) {
-      ++spins;
-      if (spins < (1u << 20)) cpu_relax();
-      else usleep(50);
-    }
-  }
-  free(bounce);
-}
-
-// One host I/O thread: read queued chunks when there are any; otherwise look over the ring
-// for a posted request that no thread has taken (starting after the slot it served last, so
-// every slot is visited in turn), take it with a compare-and-swap on the slot's claimed
-// generation, split it into chunks, queue all but the first, and read the first. Taking
-// any posted request, rather than waiting on the next ticket in ring order, keeps a thread
-// from idling behind a slot whose block has not posted yet.
-void io_thread(gfs_ctx* c, int idx) {
-  const uint32_t NS = c->cfg.rpc_slots;
-  bool first = true;
-  uint64_t spins = 0;
-  uint32_t pos = (uint32_t)((uint64_t)idx * NS / c->cfg.host_threads);
-  const uint64_t chunk = c->cfg.io_chunk_bytes;
-  uint8_t* bounce = (uint8_t*)aligned_alloc(kDirectAlign, chunk);
-  if (!bounce) return;
-  gfs_ctx::Chunk ch;
-  while (!c->stop.load(std::memory_order_relaxed)) {
-    if (pop_chunk(c, &ch)) {
-      run_chunk(c, ch, bounce);
-      continue;
-    }
-    int32_t got = -1;
-    uint64_t gen = 0;
-    for (uint32_t k = 0; k < NS && got < 0; ++k) {
-      const uint32_t s = pos + k < NS ? pos + k : pos + k - NS;
-      const uint64_t g = __atomic_load_n(&c->ring[s].req_seq, __ATOMIC_ACQUIRE);
-      uint64_t prev = g - 1;
-      if (g != 0 && c->claimed[s].load(std::memory_order_relaxed) == prev &&
-          c->claimed[s].compare_exchange_strong(prev, g, std::memory_order_acq_rel)) {
-        got = (int32_t)s;
-        gen = g;
-      }
-    }
-    if (got < 0) {
-      ++spins;
-      if (spins < (1u << 20)) cpu_relax();
-      else usleep(50);   // long idle: stop burning the core, at some wake-up latency
-      continue;
-    }
-    const uint32_t s = (uint32_t)got;
-    pos = s + 1 < NS ? s + 1 : 0;
-    if (first) {
-      c->spins[idx].store(spins, std::memory_order_relaxed);
-      first = false;
-    }
-    c->thread_requests[idx].fetch_add(1, std::memory_order_relaxed);
-    gfs_rpc_slot* rs = &c->ring[s];
-    rs->t_claim_ns = now_ns();
-    const uint64_t off = rs->offset, len = rs->length;
-    const uint64_t n = len > c->L.max_req_bytes ? 0 : (len + chunk - 1) / chunk;
-    gfs_ctx::Track& tr = c->track[s];
-    tr.total.store(0, std::memory_order_relaxed);
-    tr.err.store(n == 0 && len ? -EINVAL : 0, std::memory_order_relaxed);
-    tr.remaining.store(n ? (uint32_t)n : 1u, std::memory_order_release);
-    if (n > 1) {
-      std::lock_guard<std::mutex> g(c->qmu);
-      for (uint64_t i = 1; i < n; ++i) {
-        const uint64_t o = i * chunk;
-        c->queue.push_back({s, gen, off + o, (len - o) < chunk ? (len - o) : chunk, o});
-      }
-      c->queued.fetch_add((uint32_t)(n - 1), std::memory_order_relaxed);
-    }
-    run_chunk(c, {s, gen, off, n ? (len < chunk ? len : chunk) : 0, 0}, bounce);
-  }
-  free(bounce);
-}
-
-void start_threads(gfs_ctx* c) {
-  c->stop.store(false);
-  for (uint32_t i = 0; i < c->cfg.rpc_slots; ++i) c->claimed[i].store(0);
-  for (uint32_t i = 0; i < c->cfg.host_threads; ++i)
-    c->threads.emplace_back(c->cfg.io_backend == GFS_IO_PREAD_PARTITIONED ? io_thread_partitioned : io_thread, c,
-                            (int)i);
-}
-
-void stop_threads(gfs_ctx* c) {
-  c->stop.store(true);
-  for (auto& t : c->threads) t.join();
-  c->threads.clear();
-  std::lock_guard<std::mutex> g(c->qmu);
-  c->queue.clear();
-  c->queued.store(0);
-}
 
 int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : -EIO; }
 
@@ -490,8 +237,6 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   if (rc) return rc;
   gfs_ctx* c = new (std::nothrow) gfs_ctx();
   if (!c) return -ENOMEM;
-  for (auto& s : c->spins) s.store(0);
-  for (auto& s : c->thread_requests) s.store(0);
   c->cfg = *cfg;
   c->L = L;
   c->stream = (hipStream_t)hip_stream;
@@ -610,15 +355,22 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
     return rc;
   }
   memset(c->ring, 0, ring_bytes);
-  c->track.reset(new (std::nothrow) gfs_ctx::Track[cfg->rpc_slots]);
-  c->claimed.reset(new (std::nothrow) std::atomic<uint64_t>[cfg->rpc_slots]);
-  if (!c->track || !c->claimed) {
+  gfs_hostio::HostIo& io = c->io;
+  io.rpc_slots = cfg->rpc_slots;
+  io.host_threads = cfg->host_threads;
+  io.io_backend = cfg->io_backend;
+  io.io_chunk_bytes = cfg->io_chunk_bytes;
+  io.max_req_bytes = L.max_req_bytes;
+  io.ring = c->ring;
+  io.staging = c->staging;
+  io.files = c->files;
+  if (io.init() != 0) {
     (void)hipHostFree(c->staging);
     (void)hipHostFree(c->ring);
     delete c;
     return -ENOMEM;
   }
-  start_threads(c);
+  gfs_hostio::start_threads(&io);
   *out = c;
   return 0;
 }
@@ -665,7 +417,7 @@ int gfs_open(gfs_ctx* c, const char* path, int flags, int* file_id) {
     rc = -EIO;
   if (!rc) rc = hip_ok(hipStreamSynchronize(c->stream));
   if (rc) { close(fd); return rc; }
-  HostFile& hf = c->files[id];
+  gfs_hostio::HostFile& hf = c->files[id];
   hf.open = true;
   hf.direct = direct;
   hf.size = size;
@@ -715,7 +467,7 @@ int gfs_close(gfs_ctx* c, int file_id) {
   if (!rc) rc = zero_file_locks(c, file_id);
   if (!rc) rc = hip_ok(hipStreamSynchronize(c->stream));
   if (rc) return rc;
-  HostFile& hf = c->files[file_id];
+  gfs_hostio::HostFile& hf = c->files[file_id];
   const int fd = hf.fd.exchange(-1);
   if (fd >= 0) close(fd);
   hf.open = false;
@@ -749,9 +501,9 @@ int gfs_stats_read(gfs_ctx* c, gfs_stats* out) {
   s.timeouts = g.ctr[GFS_C_TIMEOUTS];
   s.io_errors = g.ctr[GFS_C_IOERR];
   s.trace_events = g.trace_n;
-  s.host_requests = c->host_requests.load();
-  s.host_bytes = c->host_bytes.load();
-  s.host_read_ns = c->host_read_ns.load();
+  s.host_requests = c->io.host_requests.load();
+  s.host_bytes = c->io.host_bytes.load();
+  s.host_read_ns = c->io.host_read_ns.load();
   const double ns_per_tick = 1e6 / (double)c->clock_khz;
   s.t_lock_ns = (uint64_t)(g.ctr[GFS_T_LOCK] * ns_per_tick);
   s.t_crit_ns = (uint64_t)(g.ctr[GFS_T_CRIT] * ns_per_tick);
@@ -770,10 +522,10 @@ int gfs_stats_read(gfs_ctx* c, gfs_stats* out) {
   s.t_unpin_ns = (uint64_t)(g.ctr[GFS_T_UNPIN] * ns_per_tick);
   s.private_hits = g.ctr[GFS_C_PB_HITS];
   s.private_wasted = g.ctr[GFS_C_PB_WASTED];
-  s.host_errors = c->host_errors.load();
-  s.host_last_errno = (uint64_t)c->host_last_errno.load();
-  for (uint32_t i = 0; i < 64; ++i) s.host_spins[i] = c->spins[i].load();
-  for (uint32_t i = 0; i < 64; ++i) s.host_thread_requests[i] = c->thread_requests[i].load();
+  s.host_errors = c->io.host_errors.load();
+  s.host_last_errno = (uint64_t)c->io.host_last_errno.load();
+  for (uint32_t i = 0; i < 64; ++i) s.host_spins[i] = c->io.spins[i].load();
+  for (uint32_t i = 0; i < 64; ++i) s.host_thread_requests[i] = c->io.thread_requests[i].load();
   s.host_threads = c->cfg.host_threads;
   s.direct_io = c->last_direct ? 1 : 0;
   *out = s;
@@ -801,7 +553,7 @@ int gfs_trace_read(gfs_ctx* c, void* dst, size_t cap_bytes, size_t* n_bytes) {
 
 int gfs_reset_cache(gfs_ctx* c) {
   if (!c) return -EINVAL;
-  stop_threads(c);
+  gfs_hostio::stop_threads(&c->io);
   int rc = zero_dynamic(c);
   // clear readahead streams, locks and clocks of registered files
   for (int i = 0; !rc && i < (int)c->cfg.max_files; ++i) {
@@ -820,19 +572,14 @@ int gfs_reset_cache(gfs_ctx* c) {
     rc = upload_file_record(c, i, rec);
     if (c->files[i].direct) posix_fadvise(c->files[i].fd.load(), 0, 0, POSIX_FADV_DONTNEED);
   }
-  c->host_requests = 0;
-  c->host_bytes = 0;
-  c->host_read_ns = 0;
-  c->host_errors = 0;
-  c->host_last_errno = 0;
-  for (auto& s : c->spins) s.store(0);
-  start_threads(c);
+  c->io.clear_counters();
+  gfs_hostio::start_threads(&c->io);
   return rc;
 }
 
 int gfs_shutdown(gfs_ctx* c) {
   if (!c) return -EINVAL;
-  stop_threads(c);
+  gfs_hostio::stop_threads(&c->io);
   for (auto& f : c->files) {
     const int fd = f.fd.exchange(-1);
     if (fd >= 0) close(fd);
