@@ -736,7 +736,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); "
-              "the path is per-GPU and would shard by file/chunk across GPUs, see DESIGN.md",
+              "the path is per-GPU: each GPU would get its own cache, ring and host threads and read its share of the files",
               file=sys.stderr)
         return 2
 

@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define GFS_ABI_VERSION 2u
+#define GFS_ABI_VERSION 3u
 
 /* limits of the encoding (page-table entry = file:11 | page:28 | frame:24 bits) */
 #define GFS_MAX_FILES 1024u
@@ -56,6 +56,9 @@ extern "C" {
 #define GFS_IO_PREAD_PARTITIONED 1  /* GPUfs's queue (Sec. 3.3): a block posts into the slot of its
                                        block id (mod rpc_slots); host thread i serves only its own
                                        contiguous range of slots, one request at a time */
+#define GFS_IO_URING 2              /* as GFS_IO_PREAD, but each host thread keeps io_depth reads in
+                                       flight on its own io_uring (Sec. 4.1 has the host read the
+                                       whole span; this overlaps its pieces on one thread) */
 
 /* cache policies */
 #define GFS_POLICY_SHARED 0    /* readahead windows into the shared page cache, global clock */
@@ -108,6 +111,8 @@ typedef struct gfs_config {
   uint32_t ra_quota_blocks;
   uint32_t ra_async;             /* 0 = synchronous prefetch (the paper's choice, Sec. 4
                                     "Asynchronous operation"); 1 = marker-triggered (Sec. 2.3) */
+  uint32_t io_depth;             /* GFS_IO_URING: reads each host thread keeps in flight, 1..256
+                                    (each holds an io_chunk_bytes bounce buffer for O_DIRECT) */
 } gfs_config;
 
 /* Fill *cfg with defaults: 64 KiB pages (the best GPUfs page size for sequential reads,

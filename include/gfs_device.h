@@ -79,6 +79,9 @@ struct BlockState {
   int32_t bframe[64];           /* batched hits: frame pinned for page base + i, or -1 */
 };
 
+/* the lock queue's size assumes every block that calls gread holds this much LDS */
+static_assert(sizeof(BlockState) >= GFS_BLOCK_LDS_MIN, "per-block state below the LDS bound the lock queue assumes");
+
 __device__ __forceinline__ BlockState* block_state() {
   __shared__ BlockState gfs_block_state;
   return &gfs_block_state;

@@ -70,7 +70,9 @@ int make_layout(const gfs_config* c, Layout* L) {
   if (L->ra_cap && (L->ra_init < 1 || L->ra_init > L->ra_cap)) return -EINVAL;
   if (c->host_threads < 1 || c->host_threads > 64) return -EINVAL;
   if (c->rpc_slots < 1 || c->rpc_slots > 4096) return -EINVAL;
-  if (c->io_backend != GFS_IO_PREAD && c->io_backend != GFS_IO_PREAD_PARTITIONED) return -EINVAL;
+  if (c->io_backend != GFS_IO_PREAD && c->io_backend != GFS_IO_PREAD_PARTITIONED && c->io_backend != GFS_IO_URING)
+    return -EINVAL;
+  if (c->io_depth < 1 || c->io_depth > 256) return -EINVAL;
   if (c->io_backend == GFS_IO_PREAD_PARTITIONED && c->host_threads > c->rpc_slots) return -EINVAL;
   if (c->o_direct > GFS_DIRECT_PREFER) return -EINVAL;
   if (c->trace_level > 2) return -EINVAL;
@@ -217,6 +219,7 @@ void gfs_config_default(gfs_config* cfg) {
   cfg->ra_near_min = 3;
   cfg->ra_quota_blocks = 0;
   cfg->ra_async = 0;
+  cfg->io_depth = 8;
 }
 
 int gfs_device_bytes(const gfs_config* cfg, size_t* frames_bytes, size_t* meta_bytes) {
@@ -266,6 +269,14 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
     if ((uint64_t)cus * per_cu > GFS_LOCK_SLOTS) {
       delete c;
       return -EINVAL;
+    }
+  }
+  // the io_uring backend needs the kernel's io_uring (a system can switch it off)
+  if (cfg->io_backend == GFS_IO_URING) {
+    const int rc = gfs_hostio::uring_available();
+    if (rc) {
+      delete c;
+      return rc == -EPERM || rc == -ENOSYS ? -ENOSYS : rc;
     }
   }
   uint32_t quota_blocks = cfg->ra_quota_blocks;
@@ -359,6 +370,7 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   io.rpc_slots = cfg->rpc_slots;
   io.host_threads = cfg->host_threads;
   io.io_backend = cfg->io_backend;
+  io.io_depth = cfg->io_depth;
   io.io_chunk_bytes = cfg->io_chunk_bytes;
   io.max_req_bytes = L.max_req_bytes;
   io.ring = c->ring;

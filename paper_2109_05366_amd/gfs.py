@@ -15,12 +15,12 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgfs.so")
 
-GFS_ABI_VERSION = 2
+GFS_ABI_VERSION = 3
 GFS_O_RDONLY = 0
 GFS_ADV_NORMAL, GFS_ADV_RANDOM, GFS_ADV_SEQUENTIAL = 0, 1, 2
 GFS_DIRECT_OFF, GFS_DIRECT_ON, GFS_DIRECT_PREFER = 0, 1, 2
 GFS_POLICY_SHARED, GFS_POLICY_PRIVATE = 0, 1
-GFS_IO_PREAD, GFS_IO_PREAD_PARTITIONED = 0, 1
+GFS_IO_PREAD, GFS_IO_PREAD_PARTITIONED, GFS_IO_URING = 0, 1, 2
 GFS_MAX_WINDOW_PAGES = 1024
 
 EV_HIT, EV_JOIN, EV_MISS, EV_HAND, EV_ALLOC, EV_REQ, EV_NOFRAME = 1, 2, 3, 4, 5, 6, 7
@@ -39,7 +39,7 @@ class gfs_config(C.Structure):
         ("wait_timeout_ns", C.c_uint64), ("policy", C.c_uint32), ("private_slots", C.c_uint32),
         ("io_chunk_bytes", C.c_uint32), ("max_files", C.c_uint32),
         ("ra_recent", C.c_uint32), ("ra_near_pages", C.c_uint32), ("ra_near_min", C.c_uint32),
-        ("ra_quota_blocks", C.c_uint32), ("ra_async", C.c_uint32),
+        ("ra_quota_blocks", C.c_uint32), ("ra_async", C.c_uint32), ("io_depth", C.c_uint32),
     ]
 
 

@@ -3,13 +3,15 @@
 // ring ABI (gfs_rpc_slot) the way the device does -- a ticket picks the slot and generation,
 // the slot is written and its generation published with a release store, the block waits
 // for done_seq with an acquire load and a deadline, checks the staged bytes, and frees the
-// slot. Both host queue disciplines are driven: the shared ring (any thread takes any posted
-// request) and the partitioned one (a block posts into its own slot, each host thread serves
-// its own range). Error paths: a request for an unregistered file gets -EBADF, reads that
-// cross the end of the file come back short.
+// slot. Every host read backend is driven: the shared ring (any thread takes any posted
+// request), the partitioned one (a block posts into its own slot, each host thread serves
+// its own range) and the io_uring one (the shared ring with DEPTH reads in flight per host
+// thread). Error paths: a request for an unregistered file gets -EBADF, reads that cross the
+// end of the file come back short.
 //
-// usage: hostio_check DIR BACKEND HOST_THREADS SLOTS PRODUCERS REQUESTS DIRECT
-// prints one summary line; exit status 0 when every check held.
+// usage: hostio_check DIR BACKEND HOST_THREADS SLOTS PRODUCERS REQUESTS DIRECT [DEPTH]
+// prints one summary line; exit status 0 when every check held, 5 when io_uring is asked for
+// and the kernel refuses to create one.
 #include <fcntl.h>
 #include <stdio.h>
 #include <sys/stat.h>
@@ -117,14 +119,19 @@ void producer(Shared* sh, int id, int nreq, bool partitioned) {
 }  // namespace
 
 int main(int argc, char** argv) {
-  if (argc != 8) {
-    fprintf(stderr, "usage: %s DIR BACKEND HOST_THREADS SLOTS PRODUCERS REQUESTS DIRECT\n", argv[0]);
+  if (argc != 8 && argc != 9) {
+    fprintf(stderr, "usage: %s DIR BACKEND HOST_THREADS SLOTS PRODUCERS REQUESTS DIRECT [DEPTH]\n", argv[0]);
     return 2;
   }
   const std::string dir = argv[1];
   const uint32_t backend = (uint32_t)atoi(argv[2]), threads = (uint32_t)atoi(argv[3]), slots = (uint32_t)atoi(argv[4]);
   const int producers = atoi(argv[5]), nreq = atoi(argv[6]);
   const bool direct = atoi(argv[7]) != 0;
+  const uint32_t depth = argc == 9 ? (uint32_t)atoi(argv[8]) : 4u;
+  if (backend == GFS_IO_URING && gfs_hostio::uring_available() != 0) {
+    printf("io_uring unavailable\n");
+    return 5;
+  }
   static gfs_hostio::HostFile files[GFS_MAX_FILES];
   for (int f = 0; f < 2; ++f) {
     const std::string path = dir + "/hostio_" + std::to_string(f) + ".bin";
@@ -141,6 +148,7 @@ int main(int argc, char** argv) {
   io.rpc_slots = slots;
   io.host_threads = threads;
   io.io_backend = backend;
+  io.io_depth = depth;
   io.io_chunk_bytes = 64 << 10;                 // pieces smaller than a request: several threads per request
   io.max_req_bytes = kMaxPages * kPage;
   io.ring = (gfs_rpc_slot*)aligned_alloc(128, sizeof(gfs_rpc_slot) * slots);

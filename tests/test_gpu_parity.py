@@ -57,6 +57,33 @@ def test_small_parity(name, ra_pages, data_dir, cuda):
         assert st["ra_pages"] == 0
 
 
+@pytest.mark.parametrize("name,ra_pages,depth", [("c2_small", 16, 8), ("c3a_small", 16, 4), ("c3c_small", 0, 2)])
+def test_io_uring_backend_parity(name, ra_pages, depth, data_dir, cuda):
+    """The io_uring host backend (several reads in flight per host thread) delivers the same
+    bytes as the pread one."""
+    wl = configs.get(name)
+    path = configs.ensure_file(wl.file, data_dir)
+    exp_out, exp_deliv = expected(wl, path)
+    _say(f"io_uring {name} ra_pages={ra_pages} depth={depth}")
+    cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=ra_pages * wl.page_size, timeout_s=20,
+                             host_threads=2, io_backend=gfs.GFS_IO_URING, io_depth=depth,
+                             io_chunk_bytes=256 << 10)
+    try:
+        cache = gfs.PageCache(cfg)
+    except OSError as e:
+        if e.errno == 38:   # ENOSYS: the box's kernel refuses io_uring
+            pytest.skip("io_uring unavailable")
+        raise
+    with cache:
+        fid = cache.open(path)
+        res = runner.run_list(cache, fid, wl.offsets, wl.read_size, wl.consumer)
+        st = cache.stats()
+    assert st["timeouts"] == 0 and st["io_errors"] == 0, st
+    np.testing.assert_array_equal(res.status, exp_deliv)
+    np.testing.assert_array_equal(res.out, exp_out)
+    assert st["host_bytes"] == st["request_bytes"] and st["host_requests"] == st["requests"]
+
+
 DEFAULT_DET = (64, 64, 3)
 
 

@@ -60,7 +60,8 @@ def test_device_bytes_layout_scales_with_frames():
     ("cache_bytes", 0), ("cache_bytes", 100 << 10), ("cache_bytes", (64 << 10) * 63),
     ("streams_per_file", 0), ("streams_per_file", 9), ("ra_cap_bytes", 100),
     ("ra_cap_bytes", (64 << 10) * 1025), ("host_threads", 0), ("host_threads", 65),
-    ("rpc_slots", 0), ("o_direct", 3), ("trace_level", 3), ("io_backend", 2), ("policy", 2),
+    ("rpc_slots", 0), ("o_direct", 3), ("trace_level", 3), ("io_backend", 3), ("policy", 2),
+    ("io_depth", 0), ("io_depth", 257),
 ])
 def test_invalid_configs_rejected(field, value):
     cfg = gfs.gfs_config_default()
