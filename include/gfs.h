@@ -429,6 +429,27 @@ typedef struct gfs_serve_summary {
 int gfs_serve_run(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32_t n, const gfs_serve_params* params,
                   gfs_serve_record* out, gfs_serve_summary* summary, void* hip_stream);
 
+/* ---- the serving loop without allocation ----
+ *
+ * For callers that cannot allocate memory during a run (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same run as gfs_serve_run, with the
+ * same arguments, results and errors, but the call allocates nothing. Its device state
+ * (request table, control words, block status, one chunk buffer per block) lives in a
+ * fixed array of GFS_SERVE_NOALLOC_SCRATCH_BYTES that every GPU the library runs on holds
+ * until the process ends; its pinned mailbox (submissions and completion records for up to
+ * GFS_SERVE_NOALLOC_MAX_REQUESTS requests) and host bookkeeping are allocated once, by
+ * gfs_init. The scratch array is shared by every call on that GPU and the mailbox by every
+ * call on that context: calls that overlap on one GPU race and must not be made. Each call
+ * clears what it needs zeroed. The context's device must be current (-EINVAL otherwise).
+ * -E2BIG if n exceeds GFS_SERVE_NOALLOC_MAX_REQUESTS, or if the run's device state,
+ * 64 B per request + 1 KiB + 8 B per block + chunk_bytes per block (each part rounded up to
+ * 256 B), exceeds GFS_SERVE_NOALLOC_SCRATCH_BYTES (e.g. 512 blocks fit chunks up to 120 KiB). */
+#define GFS_SERVE_NOALLOC_MAX_REQUESTS 16384u
+#define GFS_SERVE_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int gfs_serve_run_noalloc(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32_t n,
+                          const gfs_serve_params* params, gfs_serve_record* out, gfs_serve_summary* summary,
+                          void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

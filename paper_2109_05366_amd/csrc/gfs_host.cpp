@@ -29,6 +29,9 @@
 
 extern "C" int gfs_internal_zero(void* p, size_t bytes, hipStream_t s);
 extern "C" int gfs_internal_resident_blocks(uint32_t threads, uint32_t* blocks);
+struct gfs_serve_area;
+extern "C" int gfs_internal_serve_setup(int device, gfs_serve_area** out);
+extern "C" void gfs_internal_serve_teardown(gfs_serve_area* a);
 extern "C" int gfs_internal_purge_file(const gfs_dev* ddev, uint32_t nframes, uint64_t pt_entries, uint32_t file,
                                        hipStream_t s);
 
@@ -142,6 +145,7 @@ struct gfs_ctx {
   gfs_hostio::HostIo io;          // the host I/O threads serving the ring
   bool last_direct = false;
   int clock_khz = 100000;
+  gfs_serve_area* serve = nullptr;   // pinned mailbox of gfs_serve_run_noalloc
 };
 
 namespace {
@@ -366,6 +370,14 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
     return rc;
   }
   memset(c->ring, 0, ring_bytes);
+  // the no-alloc serving entry point: this device's scratch address and the context's mailbox
+  rc = gfs_internal_serve_setup(c->device, &c->serve);
+  if (rc) {
+    (void)hipHostFree(c->staging);
+    (void)hipHostFree(c->ring);
+    delete c;
+    return rc;
+  }
   gfs_hostio::HostIo& io = c->io;
   io.rpc_slots = cfg->rpc_slots;
   io.host_threads = cfg->host_threads;
@@ -377,6 +389,7 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   io.staging = c->staging;
   io.files = c->files;
   if (io.init() != 0) {
+    gfs_internal_serve_teardown(c->serve);
     (void)hipHostFree(c->staging);
     (void)hipHostFree(c->ring);
     delete c;
@@ -596,11 +609,14 @@ int gfs_shutdown(gfs_ctx* c) {
     const int fd = f.fd.exchange(-1);
     if (fd >= 0) close(fd);
   }
+  gfs_internal_serve_teardown(c->serve);
   (void)hipHostFree(c->staging);
   (void)hipHostFree(c->ring);
   delete c;
   return 0;
 }
+
+gfs_serve_area* gfs_internal_ctx_serve_area(gfs_ctx* c) { return c ? c->serve : nullptr; }
 
 }  // extern "C"
 

@@ -16,6 +16,8 @@
 
 #include <algorithm>
 #include <deque>
+#include <mutex>
+#include <new>
 #include <vector>
 
 #include <hip/hip_runtime.h>
@@ -294,35 +296,52 @@ void nap_ns(uint64_t ns) {
 
 uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
-/* buffers of one run; freed on every exit path */
-struct ServeBuffers {
-  uint8_t* dev = nullptr;    /* table, control, block status */
-  uint8_t* bufs = nullptr;   /* one chunk buffer per block */
-  uint8_t* pin = nullptr;    /* submissions, host control, completion records (pinned) */
-  ~ServeBuffers() {
-    if (dev) (void)hipFree(dev);
-    if (bufs) (void)hipFree(bufs);
-    if (pin) (void)hipHostFree(pin);
-  }
+/* Where one run keeps its state: device memory (request table, control words, block status,
+   one chunk buffer per block), pinned host memory (submissions, host control, completion
+   records; host and device addresses), and the host's per-request bookkeeping. */
+struct ServeMem {
+  SrvEntry* tab = nullptr;
+  SrvCtrl* ctl = nullptr;
+  int64_t* status = nullptr;
+  uint8_t* bufs = nullptr;
+  uint8_t* dev_clear = nullptr;      /* [tab, ctl, status]: zeroed before the launch */
+  uint64_t dev_clear_bytes = 0;
+  uint8_t* pin = nullptr;            /* host address of [subs | host control | completions] */
+  uint8_t* dpin = nullptr;           /* its device address */
+  uint64_t sub_bytes = 0, hc_bytes = 0, dn_bytes = 0;
+  uint64_t* size = nullptr;          /* per request: file size */
+  uint64_t* resv = nullptr;          /*   cache bytes it reserves */
+  uint32_t* seq_req = nullptr;       /* per admission: the request */
+  uint8_t* done_seen = nullptr;      /* per request: completion seen */
+  uint32_t* queue = nullptr;         /* arrived, not admitted (FIFO; each request once) */
+  uint32_t* inflight = nullptr;      /* admitted, not complete */
 };
 
-}  // namespace
+/* device and pinned bytes of a run of n requests on `grid` blocks */
+struct ServeSizes {
+  uint64_t tab, ctl, st, bufs, sub, hc, dn;
+};
+ServeSizes serve_sizes(uint32_t n, uint32_t grid, uint64_t chunk) {
+  ServeSizes z;
+  z.tab = round_up((uint64_t)n * sizeof(SrvEntry), 256);
+  z.ctl = round_up(sizeof(SrvCtrl), 256);
+  z.st = round_up((uint64_t)grid * 8, 256);
+  z.bufs = round_up((uint64_t)grid * chunk, 256);
+  z.sub = round_up((uint64_t)n * sizeof(SrvSub), 256);
+  z.hc = round_up(sizeof(SrvHost), 256);
+  z.dn = round_up((uint64_t)n * sizeof(SrvDone), 256);
+  return z;
+}
 
-extern "C" int gfs_serve_run(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32_t n,
-                             const gfs_serve_params* p, gfs_serve_record* out, gfs_serve_summary* summary,
-                             void* hip_stream) {
+/* Checks shared by both entry points; sets the grid, the device clock rate and the page size. */
+int serve_check(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32_t n, const gfs_serve_params* p,
+                gfs_serve_record* out, uint32_t* grid_out, int* khz_out, uint64_t* page_out) {
   if (!ctx || !reqs || !p || !out || n == 0 || n > (1u << 20)) return -EINVAL;
   if (p->budget_bytes == 0 || p->chunk_bytes == 0 || p->chunk_bytes % 16 || p->chunk_bytes > (64ull << 20))
     return -EINVAL;
   if (p->threads == 0 || p->threads % 64 || p->threads > GFS_MAX_BLOCK_THREADS) return -EINVAL;
   gfs_config cfg;
   if (gfs_get_config(ctx, &cfg)) return -EINVAL;
-  std::vector<uint64_t> size(n), resv(n);
-  for (uint32_t i = 0; i < n; ++i) {
-    if (i && reqs[i].arrival_ns < reqs[i - 1].arrival_ns) return -EINVAL;
-    if (gfs_file_size(ctx, (int)reqs[i].file_id, &size[i])) return -EBADF;
-    resv[i] = round_up(size[i], cfg.page_size);
-  }
   uint32_t grid = p->grid;
   int dev = 0, khz = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -EIO;
@@ -335,39 +354,34 @@ extern "C" int gfs_serve_run(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32
     grid = (uint32_t)std::max(per_cu, 1) * (uint32_t)cus;
   }
   if (grid > (1u << 16)) return -EINVAL;
+  *grid_out = grid;
+  *khz_out = khz;
+  *page_out = cfg.page_size;
+  return 0;
+}
 
-  // device: table | control | status ; pinned: submissions | host control | completions
-  const uint64_t tab_bytes = round_up((uint64_t)n * sizeof(SrvEntry), 256);
-  const uint64_t ctl_bytes = round_up(sizeof(SrvCtrl), 256);
-  const uint64_t st_bytes = round_up((uint64_t)grid * 8, 256);
-  const uint64_t sub_bytes = round_up((uint64_t)n * sizeof(SrvSub), 256);
-  const uint64_t hc_bytes = round_up(sizeof(SrvHost), 256);
-  const uint64_t dn_bytes = round_up((uint64_t)n * sizeof(SrvDone), 256);
-  ServeBuffers B;
-  if (hipMalloc((void**)&B.dev, tab_bytes + ctl_bytes + st_bytes) != hipSuccess) return -ENOMEM;
-  if (hipMalloc((void**)&B.bufs, (uint64_t)grid * p->chunk_bytes) != hipSuccess) return -ENOMEM;
-  if (hipHostMalloc((void**)&B.pin, sub_bytes + hc_bytes + dn_bytes, hipHostMallocMapped | hipHostMallocCoherent) !=
-      hipSuccess)
-    return -ENOMEM;
-  memset(B.pin, 0, sub_bytes + hc_bytes + dn_bytes);
-  void* dpin = nullptr;
-  if (hipHostGetDevicePointer(&dpin, B.pin, 0) != hipSuccess) return -EIO;
-  SrvSub* subs = (SrvSub*)B.pin;
-  SrvHost* hc = (SrvHost*)(B.pin + sub_bytes);
-  SrvDone* dn = (SrvDone*)(B.pin + sub_bytes + hc_bytes);
-  uint8_t* dp = (uint8_t*)dpin;
-  SrvEntry* tab = (SrvEntry*)B.dev;
-  SrvCtrl* ctl = (SrvCtrl*)(B.dev + tab_bytes);
-  int64_t* status = (int64_t*)(B.dev + tab_bytes + ctl_bytes);
-
-  hipStream_t s = (hipStream_t)hip_stream;
-  int rc = gfs_internal_zero(B.dev, tab_bytes + ctl_bytes + st_bytes, s);
+/* Run the stream with the state in m (sized for n requests and `grid` blocks). */
+int serve_core(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32_t n, const gfs_serve_params* p,
+               gfs_serve_record* out, gfs_serve_summary* summary, hipStream_t s, uint32_t grid, int khz,
+               uint64_t page, const ServeMem& m) {
+  uint64_t* size = m.size;
+  uint64_t* resv = m.resv;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (i && reqs[i].arrival_ns < reqs[i - 1].arrival_ns) return -EINVAL;
+    if (gfs_file_size(ctx, (int)reqs[i].file_id, &size[i])) return -EBADF;
+    resv[i] = round_up(size[i], page);
+  }
+  memset(m.pin, 0, m.sub_bytes + m.hc_bytes + m.dn_bytes);
+  SrvSub* subs = (SrvSub*)m.pin;
+  SrvHost* hc = (SrvHost*)(m.pin + m.sub_bytes);
+  SrvDone* dn = (SrvDone*)(m.pin + m.sub_bytes + m.hc_bytes);
+  int rc = gfs_internal_zero(m.dev_clear, m.dev_clear_bytes, s);
   if (rc) return rc;
   const uint64_t idle_ns = p->idle_timeout_ns ? p->idle_timeout_ns : 60000000000ull;
   const uint64_t idle_ticks = idle_ns / 1000 * (uint64_t)khz / 1000;
-  hipLaunchKernelGGL(serve_kernel, dim3(grid), dim3(p->threads), 0, s, gfs_device_handle(ctx), tab, n, ctl,
-                     (const SrvSub*)dp, (SrvHost*)(dp + sub_bytes), (SrvDone*)(dp + sub_bytes + hc_bytes),
-                     B.bufs, p->chunk_bytes, idle_ticks, status);
+  hipLaunchKernelGGL(serve_kernel, dim3(grid), dim3(p->threads), 0, s, gfs_device_handle(ctx), m.tab, n, m.ctl,
+                     (const SrvSub*)m.dpin, (SrvHost*)(m.dpin + m.sub_bytes),
+                     (SrvDone*)(m.dpin + m.sub_bytes + m.hc_bytes), m.bufs, p->chunk_bytes, idle_ticks, m.status);
   if (hipGetLastError() != hipSuccess) return -EIO;
 
   // the host must always let the kernel end: close (or abort) before waiting for it
@@ -400,21 +414,24 @@ extern "C" int gfs_serve_run(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32
     return v > 0 ? (uint64_t)v : 0;
   };
 
-  std::vector<uint32_t> seq_req(n);
-  std::vector<uint8_t> done_seen(n, 0);
-  std::deque<uint32_t> pending;
-  std::vector<uint32_t> inflight;   // admission numbers not yet complete
+  uint32_t* seq_req = m.seq_req;
+  uint8_t* done_seen = m.done_seen;
+  memset(done_seen, 0, n);
+  uint32_t* queue = m.queue;        // arrived requests waiting for admission: [qhead, qtail)
+  uint32_t qhead = 0, qtail = 0;
+  uint32_t* inflight = m.inflight;  // admission numbers not yet complete: [0, ninflight)
+  uint32_t ninflight = 0;
   uint64_t reserved = 0, peak_reserved = 0, delivered = 0, last_query = 0;
   uint32_t next = 0, admitted = 0, completed = 0, peak_pending = 0;
   int err = 0;
   for (uint32_t i = 0; i < n; ++i) out[i] = gfs_serve_record{};
   while (completed < n) {
     uint64_t now = host_ns() - t0;
-    while (next < n && reqs[next].arrival_ns <= now) pending.push_back(next++);
-    peak_pending = std::max<uint32_t>(peak_pending, (uint32_t)pending.size());
-    while (!pending.empty()) {
-      const uint32_t r = pending.front();
-      if (!inflight.empty() && reserved + resv[r] > p->budget_bytes) break;
+    while (next < n && reqs[next].arrival_ns <= now) queue[qtail++] = next++;
+    peak_pending = std::max<uint32_t>(peak_pending, qtail - qhead);
+    while (qhead < qtail) {
+      const uint32_t r = queue[qhead];
+      if (ninflight && reserved + resv[r] > p->budget_bytes) break;
       const uint32_t q = admitted++;
       subs[q].file = reqs[r].file_id;
       subs[q].size = size[r];
@@ -426,11 +443,11 @@ extern "C" int gfs_serve_run(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32
       __atomic_store_n(&hc->tail, (uint64_t)admitted, __ATOMIC_RELEASE);
       reserved += resv[r];
       peak_reserved = std::max(peak_reserved, reserved);
-      inflight.push_back(q);
-      pending.pop_front();
+      inflight[ninflight++] = q;
+      ++qhead;
     }
     bool progress = false;
-    for (size_t j = 0; j < inflight.size();) {
+    for (uint32_t j = 0; j < ninflight;) {
       const uint32_t q = inflight[j];
       if (!__atomic_load_n(&dn[q].flag, __ATOMIC_ACQUIRE)) {
         ++j;
@@ -445,8 +462,7 @@ extern "C" int gfs_serve_run(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32
       if (out[r].result > 0) delivered += (uint64_t)out[r].result;
       reserved -= resv[r];
       ++completed;
-      inflight[j] = inflight.back();
-      inflight.pop_back();
+      inflight[j] = inflight[--ninflight];
       progress = true;
     }
     if (progress) continue;
@@ -458,7 +474,7 @@ extern "C" int gfs_serve_run(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32
         break;
       }
     }
-    if (pending.empty() && next < n && reqs[next].arrival_ns > now + 100000ull)
+    if (qhead == qtail && next < n && reqs[next].arrival_ns > now + 100000ull)
       nap_ns(std::min<uint64_t>(reqs[next].arrival_ns - now - 50000ull, 200000ull));
     else
       nap_ns(2000);
@@ -478,4 +494,180 @@ extern "C" int gfs_serve_run(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32
     summary->clock_skew_ns = t0 - prev_poll;
   }
   return err;
+}
+
+/* buffers of one gfs_serve_run; freed on every exit path */
+struct ServeBuffers {
+  uint8_t* dev = nullptr;    /* table, control, block status */
+  uint8_t* bufs = nullptr;   /* one chunk buffer per block */
+  uint8_t* pin = nullptr;    /* submissions, host control, completion records (pinned) */
+  ~ServeBuffers() {
+    if (dev) (void)hipFree(dev);
+    if (bufs) (void)hipFree(bufs);
+    if (pin) (void)hipHostFree(pin);
+  }
+};
+
+/* ---- the entry point that allocates nothing ----
+ * Its device state lives in `scratch`, one array per GPU the library runs on, held until the
+ * process ends. Host code never passes the array's name to a kernel (in host code it is a
+ * stand-in, not a device address): the device address comes from hipGetSymbolAddress, taken
+ * once per device at gfs_init with that device current, and is used everywhere instead. */
+static __device__ __align__(256) uint8_t scratch[GFS_SERVE_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+}  // namespace
+
+/* The pinned mailbox and host bookkeeping of gfs_serve_run_noalloc, allocated once per
+   context at gfs_init for GFS_SERVE_NOALLOC_MAX_REQUESTS requests. */
+struct gfs_serve_area {
+  int device = -1;
+  uint8_t* pin = nullptr;    /* host address */
+  uint8_t* dpin = nullptr;   /* device address */
+  uint64_t* size = nullptr;
+  uint64_t* resv = nullptr;
+  uint32_t* seq_req = nullptr;
+  uint8_t* done_seen = nullptr;
+  uint32_t* queue = nullptr;
+  uint32_t* inflight = nullptr;
+};
+
+extern "C" void gfs_internal_serve_teardown(gfs_serve_area* a) {
+  if (!a) return;
+  if (a->pin) (void)hipHostFree(a->pin);
+  delete[] a->size;
+  delete[] a->resv;
+  delete[] a->seq_req;
+  delete[] a->done_seen;
+  delete[] a->queue;
+  delete[] a->inflight;
+  delete a;
+}
+
+/* Called by gfs_init with `device` current: look up this device's scratch address (once per
+   device), and allocate the context's mailbox. 0, -ENOMEM or -EIO. */
+extern "C" int gfs_internal_serve_setup(int device, gfs_serve_area** out) {
+  if (device < 0 || device >= kMaxDevices || !out) return -EINVAL;
+  {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+      void* ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return -EIO;
+      g_scratch_addr[device] = ptr;
+    }
+  }
+  const uint32_t n = GFS_SERVE_NOALLOC_MAX_REQUESTS;
+  const ServeSizes z = serve_sizes(n, 1, 16);
+  gfs_serve_area* a = new (std::nothrow) gfs_serve_area;
+  if (!a) return -ENOMEM;
+  a->device = device;
+  a->size = new (std::nothrow) uint64_t[n];
+  a->resv = new (std::nothrow) uint64_t[n];
+  a->seq_req = new (std::nothrow) uint32_t[n];
+  a->done_seen = new (std::nothrow) uint8_t[n];
+  a->queue = new (std::nothrow) uint32_t[n];
+  a->inflight = new (std::nothrow) uint32_t[n];
+  if (!a->size || !a->resv || !a->seq_req || !a->done_seen || !a->queue || !a->inflight ||
+      hipHostMalloc((void**)&a->pin, z.sub + z.hc + z.dn, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+    a->pin = nullptr;
+    gfs_internal_serve_teardown(a);
+    return -ENOMEM;
+  }
+  void* dp = nullptr;
+  if (hipHostGetDevicePointer(&dp, a->pin, 0) != hipSuccess) {
+    gfs_internal_serve_teardown(a);
+    return -EIO;
+  }
+  a->dpin = (uint8_t*)dp;
+  *out = a;
+  return 0;
+}
+
+extern "C" gfs_serve_area* gfs_internal_ctx_serve_area(gfs_ctx* ctx);
+
+extern "C" int gfs_serve_run(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32_t n,
+                             const gfs_serve_params* p, gfs_serve_record* out, gfs_serve_summary* summary,
+                             void* hip_stream) {
+  uint32_t grid = 0;
+  int khz = 0;
+  uint64_t page = 0;
+  int rc = serve_check(ctx, reqs, n, p, out, &grid, &khz, &page);
+  if (rc) return rc;
+  const ServeSizes z = serve_sizes(n, grid, p->chunk_bytes);
+  ServeBuffers B;
+  if (hipMalloc((void**)&B.dev, z.tab + z.ctl + z.st) != hipSuccess) return -ENOMEM;
+  if (hipMalloc((void**)&B.bufs, z.bufs) != hipSuccess) return -ENOMEM;
+  if (hipHostMalloc((void**)&B.pin, z.sub + z.hc + z.dn, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+    return -ENOMEM;
+  void* dpin = nullptr;
+  if (hipHostGetDevicePointer(&dpin, B.pin, 0) != hipSuccess) return -EIO;
+  std::vector<uint64_t> size(n), resv(n);
+  std::vector<uint32_t> seq_req(n), queue(n), inflight(n);
+  std::vector<uint8_t> done_seen(n);
+  ServeMem m;
+  m.tab = (SrvEntry*)B.dev;
+  m.ctl = (SrvCtrl*)(B.dev + z.tab);
+  m.status = (int64_t*)(B.dev + z.tab + z.ctl);
+  m.bufs = B.bufs;
+  m.dev_clear = B.dev;
+  m.dev_clear_bytes = z.tab + z.ctl + z.st;
+  m.pin = B.pin;
+  m.dpin = (uint8_t*)dpin;
+  m.sub_bytes = z.sub;
+  m.hc_bytes = z.hc;
+  m.dn_bytes = z.dn;
+  m.size = size.data();
+  m.resv = resv.data();
+  m.seq_req = seq_req.data();
+  m.done_seen = done_seen.data();
+  m.queue = queue.data();
+  m.inflight = inflight.data();
+  return serve_core(ctx, reqs, n, p, out, summary, (hipStream_t)hip_stream, grid, khz, page, m);
+}
+
+extern "C" int gfs_serve_run_noalloc(gfs_ctx* ctx, const gfs_serve_request* reqs, uint32_t n,
+                                     const gfs_serve_params* p, gfs_serve_record* out,
+                                     gfs_serve_summary* summary, void* hip_stream) {
+  uint32_t grid = 0;
+  int khz = 0;
+  uint64_t page = 0;
+  int rc = serve_check(ctx, reqs, n, p, out, &grid, &khz, &page);
+  if (rc) return rc;
+  gfs_serve_area* a = gfs_internal_ctx_serve_area(ctx);
+  int dev = -1;
+  if (!a || hipGetDevice(&dev) != hipSuccess) return -EIO;
+  if (dev != a->device) return -EINVAL;   /* the context's device must be current */
+  uint8_t* base = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    base = (uint8_t*)g_scratch_addr[dev];
+  }
+  if (!base) return -EIO;
+  if (n > GFS_SERVE_NOALLOC_MAX_REQUESTS) return -E2BIG;
+  const ServeSizes z = serve_sizes(n, grid, p->chunk_bytes);
+  if (z.tab + z.ctl + z.st + z.bufs > GFS_SERVE_NOALLOC_SCRATCH_BYTES) return -E2BIG;
+  const ServeSizes zmax = serve_sizes(GFS_SERVE_NOALLOC_MAX_REQUESTS, 1, 16);
+  ServeMem m;
+  m.tab = (SrvEntry*)base;
+  m.ctl = (SrvCtrl*)(base + z.tab);
+  m.status = (int64_t*)(base + z.tab + z.ctl);
+  m.bufs = base + z.tab + z.ctl + z.st;
+  m.dev_clear = base;
+  m.dev_clear_bytes = z.tab + z.ctl + z.st;
+  // the mailbox keeps its full-size layout; this run uses the first n entries of each part
+  m.pin = a->pin;
+  m.dpin = a->dpin;
+  m.sub_bytes = zmax.sub;
+  m.hc_bytes = zmax.hc;
+  m.dn_bytes = zmax.dn;
+  m.size = a->size;
+  m.resv = a->resv;
+  m.seq_req = a->seq_req;
+  m.done_seen = a->done_seen;
+  m.queue = a->queue;
+  m.inflight = a->inflight;
+  return serve_core(ctx, reqs, n, p, out, summary, (hipStream_t)hip_stream, grid, khz, page, m);
 }

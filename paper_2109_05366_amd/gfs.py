@@ -110,11 +110,12 @@ def lib() -> C.CDLL:
     L.gfs_file_size.argtypes = [vp, i32, C.POINTER(u64)]
     L.gfs_get_config.argtypes = [vp, C.POINTER(gfs_config)]
     L.gfs_serve_run.argtypes = [vp, vp, u32, C.POINTER(gfs_serve_params), vp, C.POINTER(gfs_serve_summary), vp]
+    L.gfs_serve_run_noalloc.argtypes = L.gfs_serve_run.argtypes
     for name in ("gfs_device_bytes", "gfs_init", "gfs_open", "gfs_fadvise", "gfs_close",
                  "gfs_stats_read", "gfs_trace_read", "gfs_reset_cache", "gfs_shutdown",
                  "gfs_launch_list_reader", "gfs_launch_buffer_reader", "gfs_batch_plan", "gfs_launch_batch",
                  "gfs_batch_grid",
-                 "gfs_file_size", "gfs_get_config", "gfs_serve_run"):
+                 "gfs_file_size", "gfs_get_config", "gfs_serve_run", "gfs_serve_run_noalloc"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -258,15 +259,31 @@ def gfs_get_config(ctx: int) -> gfs_config:
     return cfg
 
 
-def gfs_serve_run(ctx: int, requests: np.ndarray, params: gfs_serve_params,
-                  stream: int) -> Tuple[np.ndarray, Dict[str, int]]:
-    """requests: SERVE_REQUEST_DTYPE array; returns (SERVE_RECORD_DTYPE records, summary)."""
+def _serve(name: str, ctx: int, requests: np.ndarray, params: gfs_serve_params,
+           stream: int) -> Tuple[np.ndarray, Dict[str, int]]:
     reqs = np.ascontiguousarray(requests, dtype=SERVE_REQUEST_DTYPE)
     out = np.zeros(len(reqs), dtype=SERVE_RECORD_DTYPE)
     summ = gfs_serve_summary()
-    _check(lib().gfs_serve_run(C.c_void_p(ctx), C.c_void_p(reqs.ctypes.data), len(reqs), C.byref(params),
-                               C.c_void_p(out.ctypes.data), C.byref(summ), C.c_void_p(stream)), "gfs_serve_run")
+    _check(getattr(lib(), name)(C.c_void_p(ctx), C.c_void_p(reqs.ctypes.data), len(reqs), C.byref(params),
+                                C.c_void_p(out.ctypes.data), C.byref(summ), C.c_void_p(stream)), name)
     return out, {n: int(getattr(summ, n)) for n, _ in gfs_serve_summary._fields_}
+
+
+def gfs_serve_run(ctx: int, requests: np.ndarray, params: gfs_serve_params,
+                  stream: int) -> Tuple[np.ndarray, Dict[str, int]]:
+    """requests: SERVE_REQUEST_DTYPE array; returns (SERVE_RECORD_DTYPE records, summary)."""
+    return _serve("gfs_serve_run", ctx, requests, params, stream)
+
+
+def gfs_serve_run_noalloc(ctx: int, requests: np.ndarray, params: gfs_serve_params,
+                          stream: int) -> Tuple[np.ndarray, Dict[str, int]]:
+    """As gfs_serve_run, through the entry point that allocates nothing (state in the
+    library's fixed scratch array and the context's mailbox)."""
+    return _serve("gfs_serve_run_noalloc", ctx, requests, params, stream)
+
+
+GFS_SERVE_NOALLOC_MAX_REQUESTS = 16384
+GFS_SERVE_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 # ---- convenience: a cache over torch-allocated device memory ----------------------------

@@ -132,9 +132,10 @@ class BatchReader:
 
 
 def serve(cache: gfs.PageCache, file_ids, arrival_ns, budget_bytes: int, chunk_bytes: int = 1 << 20,
-          grid: int = 0, threads: int = 256, idle_timeout_s: float = 60.0, stream=None):
-    """Run a request stream through gfs_serve_run. file_ids[i] is request i's registered file,
-    arrival_ns[i] its arrival time. Returns (records, summary) as the binding gives them."""
+          grid: int = 0, threads: int = 256, idle_timeout_s: float = 60.0, stream=None, noalloc: bool = False):
+    """Run a request stream through gfs_serve_run (gfs_serve_run_noalloc if noalloc). file_ids[i]
+    is request i's registered file, arrival_ns[i] its arrival time. Returns (records, summary)
+    as the binding gives them."""
     import torch
     req = np.zeros(len(file_ids), dtype=gfs.SERVE_REQUEST_DTYPE)
     req["file_id"] = np.asarray(file_ids, dtype=np.uint32)
@@ -142,7 +143,8 @@ def serve(cache: gfs.PageCache, file_ids, arrival_ns, budget_bytes: int, chunk_b
     params = gfs.gfs_serve_params(budget_bytes=budget_bytes, chunk_bytes=chunk_bytes, grid=grid, threads=threads,
                                   idle_timeout_ns=int(idle_timeout_s * 1e9))
     s = stream if stream is not None else torch.cuda.current_stream()
-    return gfs.gfs_serve_run(cache.ctx, req, params, s.cuda_stream)
+    run = gfs.gfs_serve_run_noalloc if noalloc else gfs.gfs_serve_run
+    return run(cache.ctx, req, params, s.cuda_stream)
 
 
 def latency_ms(records: np.ndarray) -> dict:
