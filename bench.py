@@ -326,15 +326,15 @@ def cpu_io_comparator(torch, gfs, wl, path, want):
 
 
 def list_passes(torch, gfs, runner, wl, path, cap_bytes, steps, warmup, host_threads, rpc_slots, io_chunk,
-                want=None, policy=None, private_slots=512, advice="normal"):
-    """Cold passes of a list workload with readahead at cap_bytes (0: off); every block's
-    output is compared with `want` when given. Returns a result dict (rates, kernel times,
-    counters, outputs)."""
+                want=None, policy=None, private_slots=512, advice="normal", ra_async=0):
+    """Cold passes of a list workload with readahead at cap_bytes (0: off; ra_async 1: the
+    asynchronous, marker-triggered mode); every block's output is compared with `want` when
+    given. Returns a result dict (rates, kernel times, counters, outputs)."""
     import numpy as np
     cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=cap_bytes, host_threads=host_threads,
                              rpc_slots=rpc_slots, timeout_s=60, io_chunk_bytes=io_chunk,
                              policy=gfs.GFS_POLICY_SHARED if policy is None else policy,
-                             private_slots=private_slots)
+                             private_slots=private_slots, ra_async=ra_async)
     with gfs.PageCache(cfg) as cache:
         fid = cache.open(path)
         if advice != "normal":
@@ -719,6 +719,8 @@ def main() -> int:
     ap.add_argument("--io-chunk-kib", type=int, default=4096,
                     help="size of the pieces a host request is read in (one per free host thread)")
     ap.add_argument("--no-ra-off", action="store_true", help="skip the readahead-off comparison")
+    ap.add_argument("--no-ra-async", action="store_true",
+                    help="skip the asynchronous (marker-triggered) readahead comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3a", "c3b", "c3c", "c4", "c5", "f3", "f4", "hit"])
     ap.add_argument("--no-hit-path", action="store_true")
@@ -785,6 +787,11 @@ def bench_list(args, torch) -> int:
     off = None if args.no_ra_off else list_passes(torch, gfs, runner, wl, path, 0, args.steps, args.warmup,
                                                   args.host_threads, args.rpc_slots, args.io_chunk_kib << 10, want,
                                                   policy, args.private_slots, args.advice)
+    asy = None
+    if not args.no_ra_async and args.policy == "shared" and cap:
+        asy = list_passes(torch, gfs, runner, wl, path, cap, args.steps, args.warmup, args.host_threads,
+                          args.rpc_slots, args.io_chunk_kib << 10, want, policy, args.private_slots, args.advice,
+                          ra_async=1)
     value = ra["GBps"]
     mp_ = min(nvme, h2d)
     line = {
@@ -796,10 +803,13 @@ def bench_list(args, torch) -> int:
                    "advice": args.advice, "host_threads": args.host_threads, "data_dir": ddir},
         "readahead_off_GBps": round(off["GBps"], 3) if off else None,
         "readahead_speedup": round(value / off["GBps"], 3) if off else None,
+        "readahead_async_GBps": round(asy["GBps"], 3) if asy else None,
+        "async_vs_sync": round(asy["GBps"] / value, 3) if asy else None,
         "storage_peak_GBps": round(nvme, 3), "h2d_peak_GBps": round(h2d, 3),
         "io_bound": {"bound": "storage" if nvme < h2d else "h2d", "achieved": round(value, 3),
                      "peak": round(mp_, 3), "unit": "GB/s", "frac": round(value / mp_, 3)},
-        "stats": {"ra": _stat_subset(ra["stats"]), "no_ra": _stat_subset(off["stats"]) if off else None},
+        "stats": {"ra": _stat_subset(ra["stats"]), "no_ra": _stat_subset(off["stats"]) if off else None,
+                  "ra_async": _stat_subset(asy["stats"]) if asy else None},
         "parity": "every block" if want is not None else "delivered byte counts only",
     }
     print(json.dumps(line), flush=True)
@@ -824,7 +834,7 @@ def _list_desc(wl) -> str:
 _STAT_KEYS = ("hits", "joins", "misses", "ra_pages", "fetched_pages", "evictions", "wasted_pages", "requests",
               "request_bytes", "host_bytes", "retries", "noframe", "host_read_ns", "t_lock_ns", "t_crit_ns",
               "t_alloc_ns", "t_slot_ns", "t_host_ns", "t_pull_ns", "t_join_ns", "lock_acquired", "private_hits",
-              "private_wasted")
+              "private_wasted", "ra_async_windows")
 
 
 def _stat_subset(st):
@@ -898,11 +908,16 @@ def extra_list(torch, gfs, runner, args, name, e, passes: int = 3):
                      args.rpc_slots, args.io_chunk_kib << 10, e["want"])
     off = list_passes(torch, gfs, runner, wl, path, 0, passes, 1, args.host_threads, args.rpc_slots,
                       args.io_chunk_kib << 10, e["want"])
+    asy = list_passes(torch, gfs, runner, wl, path, wl.ra_cap_bytes, passes, 1, args.host_threads, args.rpc_slots,
+                      args.io_chunk_kib << 10, e["want"], ra_async=1)
     st = ra["stats"]
     demand = st["fetched_pages"] - st["ra_pages"]
     rec = {"workload": _list_desc(wl), "GBps": round(ra["GBps"], 3), "readahead_off_GBps": round(off["GBps"], 3),
            "readahead_speedup": round(ra["GBps"] / off["GBps"], 3), "storage_peak_GBps": round(nvme, 3),
-           "frac_of_storage": round(ra["GBps"] / nvme, 3), "steps": passes, "ra_cap_KiB": wl.ra_cap_bytes >> 10,
+           "frac_of_storage": round(ra["GBps"] / nvme, 3), "readahead_async_GBps": round(asy["GBps"], 3),
+           "async_vs_sync": round(asy["GBps"] / ra["GBps"], 3),
+           "async_wasted_pages": asy["stats"]["wasted_pages"], "async_windows": asy["stats"]["ra_async_windows"],
+           "steps": passes, "ra_cap_KiB": wl.ra_cap_bytes >> 10,
            "wasted_pages": st["wasted_pages"], "demand_pages": demand,
            "wasted_frac_of_demand": round(st["wasted_pages"] / max(demand, 1), 4),
            "fetched_pages": st["fetched_pages"], "requests": st["requests"], "parity": "every block"}
@@ -1006,13 +1021,15 @@ def bench_default(args, torch, pre) -> int:
     cap_bytes = _cap_bytes(args, wl)
     policy = gfs.GFS_POLICY_PRIVATE if args.policy == "private" else gfs.GFS_POLICY_SHARED
     results = {}
-    for label, cap in (("ra", cap_bytes), ("no_ra", 0)):
+    for label, cap, asy in (("ra", cap_bytes, 0), ("no_ra", 0, 0), ("ra_async", cap_bytes, 1)):
         if label == "no_ra" and args.no_ra_off:
+            continue
+        if label == "ra_async" and (args.no_ra_async or args.policy != "shared"):
             continue
         log(f"{label}: cap {cap >> 10} KiB, policy {args.policy}")
         results[label] = list_passes(torch, gfs, runner, wl, path, cap, args.steps, args.warmup, args.host_threads,
                                      args.rpc_slots, args.io_chunk_kib << 10, pre["want"], policy,
-                                     args.private_slots, args.advice)
+                                     args.private_slots, args.advice, ra_async=asy)
         log(f"{label}: {results[label]['GBps']:.2f} GB/s wall, {results[label]['kernel_GBps']:.2f} GB/s kernel")
     nvme_samples.append(storage_peak(path))
     nvme = float(np.mean(nvme_samples))
@@ -1077,6 +1094,8 @@ def bench_default(args, torch, pre) -> int:
                    "rpc_slots": args.rpc_slots, "data_dir": ddir},
         "readahead_off_GBps": round(results["no_ra"]["GBps"], 3) if "no_ra" in results else None,
         "readahead_speedup": round(value / results["no_ra"]["GBps"], 3) if "no_ra" in results else None,
+        "readahead_async_GBps": round(results["ra_async"]["GBps"], 3) if "ra_async" in results else None,
+        "async_vs_sync": round(results["ra_async"]["GBps"] / value, 3) if "ra_async" in results else None,
         "storage_peak_GBps": round(nvme, 3),
         "storage_peak_samples_GBps": [round(x, 3) for x in nvme_samples],
         "h2d_peak_GBps": round(h2d, 3),

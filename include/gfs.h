@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define GFS_ABI_VERSION 3u
+#define GFS_ABI_VERSION 4u
 
 /* limits of the encoding (page-table entry = file:11 | page:28 | frame:24 bits) */
 #define GFS_MAX_FILES 1024u
@@ -110,7 +110,15 @@ typedef struct gfs_config {
      gfs_init); 1 = no guard (R = 1). */
   uint32_t ra_quota_blocks;
   uint32_t ra_async;             /* 0 = synchronous prefetch (the paper's choice, Sec. 4
-                                    "Asynchronous operation"); 1 = marker-triggered (Sec. 2.3) */
+                                    "Asynchronous operation": a missing block waits for its whole
+                                    window); 1 = asynchronous, marker-triggered (Linux's way,
+                                    Sec. 2.3): the page after a demand miss, and the first page of
+                                    each asynchronous window, is its stream's marker; the first
+                                    block to reach it issues the stream's next window and does not
+                                    wait for it. Shared policy only (-EINVAL otherwise). A block
+                                    keeps at most one such window outstanding and pulls it in at
+                                    gclose at the latest, so kernels must gclose before they end
+                                    or gopen again. */
   uint32_t io_depth;             /* GFS_IO_URING: reads each host thread keeps in flight, 1..256
                                     (each holds an io_chunk_bytes bounce buffer for O_DIRECT) */
 } gfs_config;
@@ -227,6 +235,7 @@ typedef struct gfs_stats {
   uint32_t host_threads;
   uint32_t direct_io;         /* 1 if the last gfs_open used O_DIRECT */
   uint64_t host_thread_requests[64];   /* per host thread: requests it started serving */
+  uint64_t ra_async_windows;  /* asynchronous readahead: windows issued at a marker page */
 } gfs_stats;
 
 /* Snapshot the counters (the quantities Sec. 3 and Sec. 6 measure: hits and misses of the GPU
@@ -260,7 +269,9 @@ enum {
   GFS_EV_ALLOC = 5,  /* file,page,frame; a = ra (1 if prefetched), b = hand ticket */
   GFS_EV_REQ = 6,    /* file, page = first page, a = pages in span, b = ring ticket */
   GFS_EV_NOFRAME = 7, /* file,page: window cut short, no frame left             */
-  GFS_EV_PBHIT = 8    /* private policy: file,page,frame filled from the private buffer */
+  GFS_EV_PBHIT = 8,   /* private policy: file,page,frame filled from the private buffer */
+  GFS_EV_ADV = 9      /* asynchronous readahead: file, page = the marker page whose access
+                         advanced a stream; a = window length (EOF-clamped), b = window start */
 };
 /* readahead rules (GFS_EV_MISS): off (readahead off or RANDOM advice), a stream's zone,
    aggregate reading, context (cached history behind the page), a new stream (W0 or 1) */

@@ -77,6 +77,16 @@ struct BlockState {
   uint32_t help_page;           /* page of the frame a helping block pulls */
   int32_t pslot;                /* private policy: the block's slot (-1: none) */
   int32_t bframe[64];           /* batched hits: frame pinned for page base + i, or -1 */
+  uint32_t trig;                /* asynchronous readahead: this page access took a marker */
+  uint32_t a_pending;           /* 1: this block has an asynchronous request outstanding, whose
+                                   pages and frames are list[0..a_n) / lframe[0..a_n) */
+  uint32_t a_slot, a_n, a_file;
+  int32_t a_status;
+  uint64_t a_gen, a_first;
+  uint64_t tagkey;              /* nonzero: frame is pinned VALID and its tag is still to be
+                                   compared with this key (the hit's copy carries the check) */
+  uint64_t pinw;                /* the frame word the pin returned (for the hit's bit updates) */
+  int32_t tag_ok;               /* the check's outcome, for every thread of the block */
 };
 
 /* the lock queue's size assumes every block that calls gread holds this much LDS */
@@ -313,7 +323,7 @@ __device__ bool pt_delete_lane(const gfs_dev* d, uint64_t key, uint32_t frame) {
 }
 
 /* ------------------------------------------------------------------ frame words */
-enum { PIN_RETRY = 0, PIN_VALID = 1, PIN_FILLING = 2, PIN_ERROR = 3 };
+enum { PIN_RETRY = 0, PIN_VALID = 1, PIN_FILLING = 2, PIN_ERROR = 3, PIN_VALID_UNCHECKED = 4 };
 
 /* Pins are counted with fetch-and-add and fetch-and-subtract, so a pin costs one atomic
  * round trip and dropping one costs none (the wave does not wait for it). Every other change
@@ -332,9 +342,10 @@ __device__ __forceinline__ void frame_unpin(const gfs_dev* d, uint32_t f) {
  * clears the prefetched mark (the page has now been demanded). Acquire: a valid frame's
  * bytes, published with release by the block that filled it, are visible afterwards, and
  * the tag is read after the pin is in place (a frame cannot be claimed while pinned). */
-__device__ int frame_pin(const gfs_dev* d, uint32_t f, uint64_t key) {
+__device__ int frame_pin(const gfs_dev* d, uint32_t f, uint64_t key, uint64_t* w_out = nullptr) {
   uint64_t* fw = &d->fword[f];
   const uint64_t w = __hip_atomic_fetch_add(fw, GFS_FW_PIN_ONE, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  if (w_out) *w_out = w;
   const uint64_t st = w & GFS_FW_STATE;
   if ((st != GFS_FS_FILLING && st != GFS_FS_VALID) || ld_rlx(&d->ftag[f]) != key) {
     frame_unpin(d, f);
@@ -350,6 +361,47 @@ __device__ int frame_pin(const gfs_dev* d, uint32_t f, uint64_t key) {
   if (w & GFS_FW_RA)
     __hip_atomic_fetch_and(fw, ~GFS_FW_RA, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return st == GFS_FS_VALID ? PIN_VALID : PIN_FILLING;
+}
+
+/* The bit updates of a demand pin: set the reference bit, clear the prefetched mark (the page
+   has now been demanded). Idempotent; the wave does not wait for them. */
+__device__ __forceinline__ void frame_pin_bits(const gfs_dev* d, uint32_t f, uint64_t w) {
+  uint64_t* fw = &d->fword[f];
+  if (!(w & GFS_FW_REF))
+    __hip_atomic_fetch_or(fw, GFS_FW_REF, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (w & GFS_FW_RA)
+    __hip_atomic_fetch_and(fw, ~GFS_FW_RA, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+/* Pin frame f for a hit whose tag comparison travels with the copy: a VALID frame without
+ * the error bit is left pinned and reported PIN_VALID_UNCHECKED (w receives the word the pin
+ * returned); the caller loads the frame's tag together with the first loads of its copy and
+ * keeps the copy only if the tag is key (a pinned frame cannot be claimed, so the tag read
+ * after the pin is the one the bytes belong to), then applies frame_pin_bits. Any other state
+ * goes through frame_pin's checks. Saves frame_pin's dependent tag load on every hit. */
+__device__ int frame_pin_fast(const gfs_dev* d, uint32_t f, uint64_t key, uint64_t& w_out) {
+  uint64_t* fw = &d->fword[f];
+  const uint64_t w = __hip_atomic_fetch_add(fw, GFS_FW_PIN_ONE, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  w_out = w;
+  const uint64_t st = w & GFS_FW_STATE;
+  if (st == GFS_FS_VALID && !(w & GFS_FW_ERR)) return PIN_VALID_UNCHECKED;
+  if ((st != GFS_FS_FILLING && st != GFS_FS_VALID) || ld_rlx(&d->ftag[f]) != key) {
+    frame_unpin(d, f);
+    return PIN_RETRY;
+  }
+  if (st == GFS_FS_VALID) {
+    frame_unpin(d, f);   /* the host read of this page failed */
+    return PIN_ERROR;
+  }
+  frame_pin_bits(d, f, w);
+  return PIN_FILLING;
+}
+
+/* Lane: the pinned frame's word showed the marker bit; clear it. True for the one block whose
+   clearing took it (that block advances the stream). */
+__device__ __forceinline__ bool mark_take_lane(const gfs_dev* d, uint32_t f) {
+  const uint64_t old = __hip_atomic_fetch_and(&d->fword[f], ~GFS_FW_MARK, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return (old & GFS_FW_MARK) != 0;
 }
 
 /* One clock step at frame f (per lane). FREE or EVICT leave the frame CLAIMED by the
@@ -455,7 +507,7 @@ __device__ bool lock_try_leave_lane(const gfs_dev* d, uint32_t file, uint64_t t)
  * Returns LOCK_OWN (ticket set), LOCK_LEFT, LOCK_COVERED (the holder's window covers the
  * page) or LOCK_TIMEOUT (left the queue after the wait timeout). */
 __device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uint64_t page, uint64_t t0,
-                              uint64_t& ticket);
+                              uint64_t& ticket, bool may_leave = true);
 /* Wave-collective: pass the lock on; [lo, hi) is the window the holder has just claimed
    (lo == hi: none). */
 __device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket, uint64_t lo, uint64_t hi);
@@ -463,7 +515,7 @@ __device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticke
 __device__ int32_t pt_lookup_wave(const gfs_dev* d, uint64_t key);
 
 __device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uint64_t page, uint64_t t0,
-                              uint64_t& ticket) {
+                              uint64_t& ticket, bool may_leave) {
   uint64_t t = 0;
   if (lane() == 0)
     t = __hip_atomic_fetch_add(&d->locks[file].next, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -494,7 +546,7 @@ __device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uin
       st = __shfl(st, 0, 64);
       if (st < 0 && (n & 7) == 7) {
         /* the page may have been reserved by a window that covers it */
-        const bool present = pt_lookup_wave(d, key) >= 0;
+        const bool present = may_leave && pt_lookup_wave(d, key) >= 0;
         const bool late = expired(d, t0);
         if (present || late) {
           int out = 0;
@@ -579,7 +631,7 @@ __device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticke
 struct RaState {
   uint32_t advice, clk, rn;
   uint64_t r, s_next;
-  uint32_t s_size, s_last, s_valid;
+  uint32_t s_size, s_last, s_valid, s_marker;
 };
 __device__ __forceinline__ RaState ra_load_lane(const gfs_dev* d, uint32_t file) {
   gfs_file_dev* fe = &d->files[file];
@@ -595,6 +647,7 @@ __device__ __forceinline__ RaState ra_load_lane(const gfs_dev* d, uint32_t file)
     st.s_size = ld_rlx32(&sp->size);
     st.s_last = ld_rlx32(&sp->last_use);
     st.s_valid = ld_rlx32(&sp->valid);
+    st.s_marker = ld_rlx32(&sp->marker);
   }
   return st;
 }
@@ -616,7 +669,8 @@ __device__ __forceinline__ uint32_t ra_cap_eff(const gfs_dev* d) {
 }
 
 __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, const RaState& st, uint64_t& ws,
-                               uint32_t& wn, uint32_t& near_out, uint32_t& h_out, uint32_t& rule_out) {
+                               uint32_t& wn, uint32_t& near_out, uint32_t& h_out, uint32_t& rule_out,
+                               int& slot_out) {
   gfs_file_dev* fe = &d->files[file];
   const uint32_t advice = st.advice;
   ws = p;
@@ -624,6 +678,7 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, cons
   near_out = 0;
   h_out = 0;
   rule_out = RA_RULE_OFF;
+  slot_out = -1;
   if (d->ra_cap == 0 || advice == GFS_ADV_RANDOM) return;
   const uint32_t l = lane();
   const uint32_t cap = ra_cap_eff(d);
@@ -708,6 +763,7 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, cons
     st_rlx32(&s->last_use, clk);
     st_rlx32(&s->valid, 1u);
   }
+  slot_out = j;
 }
 
 /* ------------------------------------------------------------------ clock allocation
@@ -719,7 +775,7 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, cons
  * table entry is pointed at the frame. Returns how many pages got frames (a prefix of the
  * list); stops after 2 * nframes visits without enough frames. */
 __device__ uint32_t alloc_wave(const gfs_dev* d, uint32_t file, uint64_t demand, BlockState* bs,
-                               uint32_t n, uint32_t bid) {
+                               uint32_t n, uint32_t bid, uint64_t mark = ~0ull) {
   const uint32_t l = lane();
   uint32_t assigned = 0;
   uint64_t visits = 0;
@@ -760,7 +816,7 @@ __device__ uint32_t alloc_wave(const gfs_dev* d, uint32_t file, uint64_t demand,
       /* CLAIMED (no flags, no pins of ours) -> FILLING, version + 1, pinned for the demanded
          page, prefetched mark otherwise; an addition keeps pins other blocks hold briefly */
       const uint64_t delta = (GFS_FS_FILLING - GFS_FS_CLAIMED) + GFS_FW_VER_ONE +
-                             (q == demand ? GFS_FW_PIN_ONE : GFS_FW_RA);
+                             (q == demand ? GFS_FW_PIN_ONE : GFS_FW_RA) + (q == mark ? GFS_FW_MARK : 0ull);
       __hip_atomic_fetch_add(&d->fword[f], delta, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       st_rel(d->pt + bs->lslot[k], (key << GFS_ENTRY_FRAME_BITS) | f);
       bs->lframe[k] = f;
@@ -837,7 +893,27 @@ __device__ void join_or_help_lane(const gfs_dev* d, uint32_t f, uint64_t p, uint
     }
     if (!(w & GFS_FW_PULL)) {
       const uint64_t ff = ld_rlx(&d->ffill[f]);
-      if (ff) {
+      if (ff >> 63) {
+        /* an asynchronous request: nobody publishes it, so look at the host's completion in
+           the ring slot itself (the slot cannot be reused while this frame is filling) */
+        const uint32_t s = (uint32_t)((ff >> 40) & 0x7fffff) - 1;
+        const uint64_t gen = ff & ((1ull << 40) - 1);
+        gfs_rpc_slot* rs = &d->ring[s];
+        if (__hip_atomic_load(&rs->done_seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == gen) {
+          acquire_system();   /* the staged bytes and the result, written before done_seq */
+          if (cas64(fw, w, (w | GFS_FW_PULL) + GFS_FW_VER_ONE)) {
+            bs->status = 0;
+            bs->pull = 2;
+            bs->slot = s;
+            bs->gen = gen;
+            bs->first_page = rs->offset >> d->page_shift;
+            bs->result = rs->result;
+            bs->help_page = (uint32_t)p;
+            return;
+          }
+          continue;
+        }
+      } else if (ff) {
         const uint32_t s = (uint32_t)(ff >> 40) - 1;
         gfs_req_dev* rq = &d->reqd[s];
         const uint64_t ready = ld_rlx(&rq->ready);
@@ -1134,6 +1210,296 @@ __device__ int miss_private_wave(const gfs_dev* d, uint32_t file, uint64_t p, ui
   return 0;
 }
 
+/* Wave 0: the shared policy's miss path for page p of `file` (key), found absent from the
+ * table: take the file's miss lock, decide and claim the window, reserve and allocate its
+ * run, post the request and wait for the host. Out of line: it runs once per host request
+ * and holds most of the library's registers, which the hit path then does not have to share.
+ * Returns 0 when bs is filled in (status, frame, pull), 1 to look the page up again, 2 when
+ * the wait timed out. */
+__device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint32_t file, uint64_t p,
+                                                          uint64_t key, uint64_t fsize, BlockState* bs,
+                                                          uint32_t bid, uint64_t t0, uint32_t& naps) {
+  const uint32_t l = lane();
+  const uint64_t tl0 = wall_clock64();
+  uint64_t ticket;
+  const int lk = lock_file_wave(d, file, key, p, t0, ticket);
+  const uint64_t tl1 = wall_clock64();
+  if (l == 0) bcount(bs, GFS_T_LOCK, tl1 - tl0);
+  if (lk == LOCK_TIMEOUT) return 2;
+  if (lk == LOCK_LEFT) {
+    if (l == 0) bcount(bs, GFS_C_LOCK_LEFT, 1);
+    return 1;   /* the page was reserved while this block waited: go to the pin path */
+  }
+  if (lk == LOCK_COVERED) {
+    /* the holder's window covers the page: wait until its reservation shows in the
+       table or no running claim covers the page any more, then look again */
+    if (l == 0) bcount(bs, GFS_C_LOCK_LEFT, 1);
+    uint32_t nw = 0;
+    while (pt_lookup_wave(d, key) < 0 && !expired(d, t0)) {
+      uint64_t cl = 0;
+      if (l < GFS_CLAIMS) cl = ld_rlx(&d->claims[file].e[l]);
+      const uint64_t c_lo = cl >> 32, c_hi = (cl >> 32) + ((cl & 0xffffffffull) >> 1);
+      if (__ballot(l < GFS_CLAIMS && (cl & 1ull) && c_lo <= p && p < c_hi) == 0) break;
+      if (l == 0) nap_short(nw);
+    }
+    acquire_agent();   /* the reservations, published before the claim was cleared */
+    return 1;
+  }
+  if (l == 0) bcount(bs, GFS_C_LOCKS, 1);
+  /* every block waiting on this file's lock waits for this wave: let it issue first */
+  __builtin_amdgcn_s_setprio(3);
+  /* one round: the detector state and the file's window claims; then, ordered after the
+     claims, the table probe (a claim cleared after its reservations means they show) */
+  const RaState ras = ra_load_lane(d, file);
+  uint64_t cl = 0;
+  if (l < GFS_CLAIMS) cl = ld_rlx(&d->claims[file].e[l]);
+  const uint64_t npages = d->files[file].npages;
+  drain_atomics();   /* the table probe below goes out after the claims were read */
+  const bool cl_on = l < GFS_CLAIMS && (cl & 1ull);
+  const uint64_t cl_lo = cl >> 32, cl_hi = (cl >> 32) + ((cl & 0xffffffffull) >> 1);
+  const bool covered = __ballot(cl_on && cl_lo <= p && p < cl_hi) != 0;
+  const uint64_t free_cl = __ballot(l < GFS_CLAIMS && !cl_on);
+  const bool present = pt_lookup_wave(d, key) >= 0;
+  if (present || covered || free_cl == 0) {
+    /* filled, reserved, or about to be reserved by a window being claimed: go to the pin
+       path (after a nap if the claim is still running) */
+    unlock_file_wave(d, file, ticket, 0, 0);
+    __builtin_amdgcn_s_setprio(0);
+    if (l == 0) bcount(bs, GFS_T_CRIT, wall_clock64() - tl1);
+    if (!present) {
+      if (expired(d, t0)) return 2;
+      if (l == 0) nap(naps);
+    }
+    return 1;
+  }
+  /* miss: decide the window, clip it to stay out of running claims, claim it, unlock */
+  uint64_t ws;
+  uint32_t wn, near, hist, rule;
+  int rslot;
+  const uint64_t td0 = wall_clock64();
+  ra_decide_wave(d, file, p, ras, ws, wn, near, hist, rule, rslot);
+  const uint64_t td1 = wall_clock64();
+  if (l == 0) bcount(bs, GFS_T_DECIDE, td1 - td0);
+  if (ws + wn > npages) wn = (uint32_t)(npages - ws);
+  /* asynchronous readahead: the page after the demanded one is the stream's marker */
+  uint64_t mark = ~0ull;
+  if (d->ra_async && rslot >= 0) {
+    mark = p + 1 < ws + wn ? p + 1 : ~0ull;
+    if (l == 0) st_rlx32(&d->files[file].streams[rslot].marker, mark == ~0ull ? GFS_NO_MARKER : (uint32_t)mark);
+  }
+  if (l == 0)
+    trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, (near & 0xffu) | (hist << 8) | (rule << 24), wn, ws);
+  uint64_t cws = ws, cwe = ws + wn;
+  {
+    uint64_t lo_b = cl_on && cl_hi <= p ? cl_hi : 0;
+    uint64_t hi_b = cl_on && cl_lo > p ? cl_lo : ~0ull;
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint64_t a = __shfl_xor(lo_b, off, 64), b = __shfl_xor(hi_b, off, 64);
+      lo_b = a > lo_b ? a : lo_b;
+      hi_b = b < hi_b ? b : hi_b;
+    }
+    cws = cws > lo_b ? cws : lo_b;
+    cwe = cwe < hi_b ? cwe : hi_b;
+  }
+  const uint32_t cj = (uint32_t)__builtin_ctzll(free_cl);
+  uint64_t* claim = &d->claims[file].e[cj];
+  if (l == 0) st_rlx(claim, (cws << 32) | ((cwe - cws) << 1) | 1ull);
+  const uint64_t tu0 = wall_clock64();
+  unlock_file_wave(d, file, ticket, cws, cwe);
+  __builtin_amdgcn_s_setprio(0);
+  const uint64_t tl2 = wall_clock64();
+  if (l == 0) {
+    bcount(bs, GFS_T_CRIT, tl2 - tl1);
+    bcount(bs, GFS_T_UNLOCK, tl2 - tu0);
+  }
+  /* reserve the run of unmapped pages around p inside the claimed window */
+  const uint32_t cwn = (uint32_t)(cwe - cws);
+  uint32_t n = 0, failed = 0;
+  if (cwn <= 64) {
+    /* one round: lane i loads the buckets of window page cws + i, the run around p is
+       read off the ballot of present pages, and each run lane reserves its page from
+       the buckets it already holds */
+    n = reserve_run_small_wave(d, file, p, cws, cwn, bs, failed);
+  } else {
+    uint64_t a = p;
+    for (uint64_t base = p; base > cws;) {
+      const bool valid = (uint64_t)l < base - cws;
+      bool stop = !valid;
+      if (valid) stop = pt_present_lane(d, page_key(file, base - 1 - l));
+      const uint64_t sm = __ballot(stop);
+      const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
+      a = base - k;
+      if (k < 64) break;
+      base -= 64;
+    }
+    uint64_t b = p;
+    for (uint64_t base = p + 1; base < cwe;) {
+      const bool valid = (uint64_t)l < cwe - base;
+      bool stop = !valid;
+      if (valid) stop = pt_present_lane(d, page_key(file, base + l));
+      const uint64_t sm = __ballot(stop);
+      const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
+      b = base + k - 1;
+      if (k < 64) break;
+      base += 64;
+    }
+    n = (uint32_t)(b - a + 1);
+    /* allocation order: the demanded page first, then the rest of the run ascending */
+    for (uint32_t i = l; i < n; i += 64) {
+      uint64_t q;
+      if (i == 0) q = p;
+      else if (i <= p - a) q = a + i - 1;
+      else q = a + i;
+      const int64_t slot = pt_reserve_lane(d, page_key(file, q));
+      bs->list[i] = (uint32_t)q;
+      bs->lslot[i] = slot < 0 ? 0xffffffffu : (uint32_t)slot;
+      bs->lframe[i] = GFS_NO_FRAME;
+      failed |= slot < 0 ? 1u : 0u;
+    }
+  }
+  failed = (uint32_t)(__ballot(failed != 0) != 0);
+  /* the reservations are in the table: release the claim */
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (l == 0) st_rlx(claim, 0ull);
+  wave_sync_lds();
+  const uint64_t tl3 = wall_clock64();
+  if (l == 0) bcount(bs, GFS_T_RUN, tl3 - tl2);
+  /* a reservation can fail only if both buckets are full: keep the prefix before the
+     first failure (the demanded page comes first) and drop the rest */
+  uint32_t keep = n;
+  if (failed) {
+    uint32_t firstbad = n;
+    for (uint32_t i = l; i < n; i += 64)
+      if (bs->lslot[i] == 0xffffffffu) firstbad = i < firstbad ? i : firstbad;
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint32_t o = __shfl_xor(firstbad, off, 64);
+      firstbad = o < firstbad ? o : firstbad;
+    }
+    keep = firstbad;
+  }
+  const uint32_t got = keep ? alloc_wave(d, file, p, bs, keep, bid, mark) : 0;
+  if (l == 0) bcount(bs, GFS_T_ALLOC, wall_clock64() - tl3);
+  /* release reservations that got no frame (the table was full or no frame was free) */
+  for (uint32_t i = got + l; i < n; i += 64) {
+    if (bs->lslot[i] != 0xffffffffu)
+      st_rel(d->pt + bs->lslot[i], 0ull);
+  }
+  if (got == 0) {
+    if (l == 0) bcount(bs, keep ? GFS_C_NOFRAME : GFS_C_RETRIES, 1);
+    if (keep == 0 && expired(d, t0)) {
+      /* the demanded page's buckets stayed full until the wait limit */
+      if (l == 0) {
+        bs->status = -kENOSPC;
+        bs->pull = 0;
+        bs->frame = -1;
+      }
+      return 0;
+    }
+    if (expired(d, t0)) return 2;
+    if (l == 0) nap(naps);
+    return 1;   /* buckets full of reservations in flight, or every frame pinned or
+                   filling: back off and retry the access */
+  }
+  if (got < n && l == 0)
+    trace_ev(d, 1, GFS_EV_NOFRAME, bid, file, bs->list[got], GFS_NO_FRAME, 0, 0);
+  /* span of the pages that got frames: p and a contiguous piece of the run */
+  uint64_t lo = ~0ull, hi = 0;
+  for (uint32_t k = l; k < got; k += 64) {
+    const uint64_t q = bs->list[k];
+    lo = q < lo ? q : lo;
+    hi = q > hi ? q : hi;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t olo = __shfl_xor(lo, off, 64), ohi = __shfl_xor(hi, off, 64);
+    lo = olo < lo ? olo : lo;
+    hi = ohi > hi ? ohi : hi;
+  }
+  /* post the request for the span [lo, hi] and wait for the host */
+  const uint32_t span = (uint32_t)(hi - lo + 1);
+  const uint64_t off0 = lo << d->page_shift;
+  uint64_t len = (uint64_t)span << d->page_shift;
+  if (off0 + len > fsize) len = fsize - off0;
+  int64_t status = 0;
+  uint64_t tk = 0;
+  if (l == 0) {
+    ring_ticket_lane(d, bid, tk);
+    const uint32_t s = ring_slot(d, bid, tk);
+    const uint64_t gen = ring_gen(d, tk);
+    uint32_t nn = 0;
+    const uint64_t ts0 = wall_clock64();
+    while (ld_rlx(&d->slot_free[s]) != gen - 1) {
+      if (expired(d, t0)) {
+        status = -kETIMEDOUT;
+        break;
+      }
+      nap(nn);
+    }
+    acquire_agent();   /* the slot's last users are done with its staging */
+    bcount(bs, GFS_T_SLOT, wall_clock64() - ts0);
+    if (status == 0) {
+      gfs_rpc_slot* rs = &d->ring[s];
+      rs->file_id = file;
+      rs->npages = span;
+      rs->offset = off0;
+      rs->length = len;
+      rs->ticket = tk;
+      __hip_atomic_store(&rs->req_seq, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      trace_ev(d, 1, GFS_EV_REQ, bid, file, (uint32_t)lo, GFS_NO_FRAME, span, tk);
+      bcount(bs, GFS_C_MISSES, 1);
+      bcount(bs, GFS_C_REQUESTS, 1);
+      bcount(bs, GFS_C_REQ_BYTES, len);
+      bcount(bs, GFS_C_FETCHED, got);
+      bcount(bs, GFS_C_RA_PAGES, got - 1);
+    }
+  }
+  status = __shfl(status, 0, 64);
+  tk = __shfl(tk, 0, 64);
+  const uint32_t s = ring_slot(d, bid, tk);
+  const uint64_t gen = ring_gen(d, tk);
+  if (status == 0) {
+    /* tell waiting blocks which request fills each frame: (slot + 1) << 40 | gen */
+    const uint64_t fill = ((uint64_t)(s + 1) << 40) | (gen & ((1ull << 40) - 1));
+    for (uint32_t k = l; k < got; k += 64) st_rel(&d->ffill[bs->lframe[k]], fill);
+  }
+  if (l == 0) {
+    if (status == 0) {
+      gfs_rpc_slot* rs = &d->ring[s];
+      uint32_t nn = 0;
+      const uint64_t th0 = wall_clock64();
+      while (__hip_atomic_load(&rs->done_seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) !=
+             gen) {
+        if (expired(d, t0)) {
+          status = -kETIMEDOUT;
+          break;
+        }
+        nap(nn);
+      }
+      acquire_system();   /* the staged bytes, written by the host before done_seq */
+      bcount(bs, GFS_T_HOST, wall_clock64() - th0);
+      if (status == 0) {
+        bs->result = rs->result;
+        /* let blocks waiting on frames of this request pull their own pages */
+        gfs_req_dev* rq = &d->reqd[s];
+        rq->result = bs->result;
+        rq->first_page = lo;
+        rq->file = file;
+        __hip_atomic_store(&rq->remaining, got, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st_rel(&rq->ready, gen);
+      }
+    }
+    if (status) bcount(bs, GFS_C_TIMEOUTS, 1);
+    bs->status = status;
+    bs->frame = (int32_t)bs->lframe[0];
+    bs->pull = status == 0 ? 1 : 0;
+    bs->slot = s;
+    bs->gen = gen;
+    bs->first_page = lo;
+    bs->list_n = got;
+    bs->file = file;
+  }
+  return 0;
+}
+
 /* ------------------------------------------------------------------ one page, wave 0
  * Leaves in bs: status; on success the pinned frame, and pull = 1 when this block posted
  * the request and must pull it. */
@@ -1143,12 +1509,29 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
   const uint32_t l = lane();
   const uint64_t t0 = wall_clock64();
   uint32_t naps = 0;
+  /* untraced runs check a hit's tag with its copy (frame_pin_fast) */
+  const bool fast = d->trace_level == 0;
+  if (l == 0) {
+    bs->tagkey = 0;
+    bs->trig = 0;
+  }
   while (true) {
     int32_t f = pt_lookup_wave(d, key);
     if (f >= 0 && (uint32_t)f != kReserved) {
       int r = PIN_RETRY;
-      if (l == 0) r = frame_pin(d, (uint32_t)f, key);
+      uint64_t w = 0;
+      if (l == 0) r = fast ? frame_pin_fast(d, (uint32_t)f, key, w) : frame_pin(d, (uint32_t)f, key, &w);
       r = __shfl(r, 0, 64);
+      if (r == PIN_VALID_UNCHECKED) {
+        if (l == 0) {
+          bs->frame = f;
+          bs->status = 0;
+          bs->pull = 0;
+          bs->tagkey = key;
+          bs->pinw = w;
+        }
+        return;
+      }
       if (r == PIN_VALID) {
         if (l == 0) {
           bcount(bs, GFS_C_HITS, 1);
@@ -1156,6 +1539,7 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
           bs->frame = f;
           bs->status = 0;
           bs->pull = 0;
+          if (d->ra_async && (w & GFS_FW_MARK)) bs->trig = mark_take_lane(d, (uint32_t)f) ? 1u : 0u;
         }
         return;
       }
@@ -1163,6 +1547,7 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
         if (l == 0) {
           bcount(bs, GFS_C_JOINS, 1);
           trace_ev(d, 2, GFS_EV_JOIN, bid, file, (uint32_t)p, (uint32_t)f, 0, 0);
+          if (d->ra_async && (w & GFS_FW_MARK)) bs->trig = mark_take_lane(d, (uint32_t)f) ? 1u : 0u;
           const uint64_t tj0 = wall_clock64();
           join_or_help_lane(d, (uint32_t)f, p, t0, bs);
           bcount(bs, GFS_T_JOIN, wall_clock64() - tj0);
@@ -1183,278 +1568,21 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
       if (r == 0) return;
       if (r == 2) break;
       continue;
-    } else if (f < 0) {
-      const uint64_t tl0 = wall_clock64();
-      uint64_t ticket;
-      const int lk = lock_file_wave(d, file, key, p, t0, ticket);
-      const uint64_t tl1 = wall_clock64();
-      if (l == 0) bcount(bs, GFS_T_LOCK, tl1 - tl0);
-      if (lk == LOCK_TIMEOUT) break;
-      if (lk == LOCK_LEFT) {
-        if (l == 0) bcount(bs, GFS_C_LOCK_LEFT, 1);
-        continue;   /* the page was reserved while this block waited: go to the pin path */
-      }
-      if (lk == LOCK_COVERED) {
-        /* the holder's window covers the page: wait until its reservation shows in the
-           table or no running claim covers the page any more, then look again */
-        if (l == 0) bcount(bs, GFS_C_LOCK_LEFT, 1);
-        uint32_t nw = 0;
-        while (pt_lookup_wave(d, key) < 0 && !expired(d, t0)) {
-          uint64_t cl = 0;
-          if (l < GFS_CLAIMS) cl = ld_rlx(&d->claims[file].e[l]);
-          const uint64_t c_lo = cl >> 32, c_hi = (cl >> 32) + ((cl & 0xffffffffull) >> 1);
-          if (__ballot(l < GFS_CLAIMS && (cl & 1ull) && c_lo <= p && p < c_hi) == 0) break;
-          if (l == 0) nap_short(nw);
-        }
-        acquire_agent();   /* the reservations, published before the claim was cleared */
-        continue;
-      }
-      if (l == 0) bcount(bs, GFS_C_LOCKS, 1);
-      /* every block waiting on this file's lock waits for this wave: let it issue first */
-      __builtin_amdgcn_s_setprio(3);
-      /* one round: the detector state and the file's window claims; then, ordered after the
-         claims, the table probe (a claim cleared after its reservations means they show) */
-      const RaState ras = ra_load_lane(d, file);
-      uint64_t cl = 0;
-      if (l < GFS_CLAIMS) cl = ld_rlx(&d->claims[file].e[l]);
-      const uint64_t npages = d->files[file].npages;
-      drain_atomics();   /* the table probe below goes out after the claims were read */
-      const bool cl_on = l < GFS_CLAIMS && (cl & 1ull);
-      const uint64_t cl_lo = cl >> 32, cl_hi = (cl >> 32) + ((cl & 0xffffffffull) >> 1);
-      const bool covered = __ballot(cl_on && cl_lo <= p && p < cl_hi) != 0;
-      const uint64_t free_cl = __ballot(l < GFS_CLAIMS && !cl_on);
-      const bool present = pt_lookup_wave(d, key) >= 0;
-      if (present || covered || free_cl == 0) {
-        /* filled, reserved, or about to be reserved by a window being claimed: go to the pin
-           path (after a nap if the claim is still running) */
-        unlock_file_wave(d, file, ticket, 0, 0);
-        __builtin_amdgcn_s_setprio(0);
-        if (l == 0) bcount(bs, GFS_T_CRIT, wall_clock64() - tl1);
-        if (!present) {
-          if (expired(d, t0)) break;
-          if (l == 0) nap(naps);
-        }
-        continue;
-      }
-      /* miss: decide the window, clip it to stay out of running claims, claim it, unlock */
-      uint64_t ws;
-      uint32_t wn, near, hist, rule;
-      const uint64_t td0 = wall_clock64();
-      ra_decide_wave(d, file, p, ras, ws, wn, near, hist, rule);
-      const uint64_t td1 = wall_clock64();
-      if (l == 0) bcount(bs, GFS_T_DECIDE, td1 - td0);
-      if (ws + wn > npages) wn = (uint32_t)(npages - ws);
-      if (l == 0)
-        trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, (near & 0xffu) | (hist << 8) | (rule << 24), wn, ws);
-      uint64_t cws = ws, cwe = ws + wn;
-      {
-        uint64_t lo_b = cl_on && cl_hi <= p ? cl_hi : 0;
-        uint64_t hi_b = cl_on && cl_lo > p ? cl_lo : ~0ull;
-        for (int off = 32; off > 0; off >>= 1) {
-          const uint64_t a = __shfl_xor(lo_b, off, 64), b = __shfl_xor(hi_b, off, 64);
-          lo_b = a > lo_b ? a : lo_b;
-          hi_b = b < hi_b ? b : hi_b;
-        }
-        cws = cws > lo_b ? cws : lo_b;
-        cwe = cwe < hi_b ? cwe : hi_b;
-      }
-      const uint32_t cj = (uint32_t)__builtin_ctzll(free_cl);
-      uint64_t* claim = &d->claims[file].e[cj];
-      if (l == 0) st_rlx(claim, (cws << 32) | ((cwe - cws) << 1) | 1ull);
-      const uint64_t tu0 = wall_clock64();
-      unlock_file_wave(d, file, ticket, cws, cwe);
-      __builtin_amdgcn_s_setprio(0);
-      const uint64_t tl2 = wall_clock64();
+    } else if (f < 0 && bs->a_pending) {
+      /* a block posts a request only with no asynchronous request of its own outstanding (so
+         that no block waits for a ring slot that only it would free): the block finishes that
+         request first and then looks again */
       if (l == 0) {
-        bcount(bs, GFS_T_CRIT, tl2 - tl1);
-        bcount(bs, GFS_T_UNLOCK, tl2 - tu0);
-      }
-      /* reserve the run of unmapped pages around p inside the claimed window */
-      const uint32_t cwn = (uint32_t)(cwe - cws);
-      uint32_t n = 0, failed = 0;
-      if (cwn <= 64) {
-        /* one round: lane i loads the buckets of window page cws + i, the run around p is
-           read off the ballot of present pages, and each run lane reserves its page from
-           the buckets it already holds */
-        n = reserve_run_small_wave(d, file, p, cws, cwn, bs, failed);
-      } else {
-        uint64_t a = p;
-        for (uint64_t base = p; base > cws;) {
-          const bool valid = (uint64_t)l < base - cws;
-          bool stop = !valid;
-          if (valid) stop = pt_present_lane(d, page_key(file, base - 1 - l));
-          const uint64_t sm = __ballot(stop);
-          const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
-          a = base - k;
-          if (k < 64) break;
-          base -= 64;
-        }
-        uint64_t b = p;
-        for (uint64_t base = p + 1; base < cwe;) {
-          const bool valid = (uint64_t)l < cwe - base;
-          bool stop = !valid;
-          if (valid) stop = pt_present_lane(d, page_key(file, base + l));
-          const uint64_t sm = __ballot(stop);
-          const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
-          b = base + k - 1;
-          if (k < 64) break;
-          base += 64;
-        }
-        n = (uint32_t)(b - a + 1);
-        /* allocation order: the demanded page first, then the rest of the run ascending */
-        for (uint32_t i = l; i < n; i += 64) {
-          uint64_t q;
-          if (i == 0) q = p;
-          else if (i <= p - a) q = a + i - 1;
-          else q = a + i;
-          const int64_t slot = pt_reserve_lane(d, page_key(file, q));
-          bs->list[i] = (uint32_t)q;
-          bs->lslot[i] = slot < 0 ? 0xffffffffu : (uint32_t)slot;
-          bs->lframe[i] = GFS_NO_FRAME;
-          failed |= slot < 0 ? 1u : 0u;
-        }
-      }
-      failed = (uint32_t)(__ballot(failed != 0) != 0);
-      /* the reservations are in the table: release the claim */
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      if (l == 0) st_rlx(claim, 0ull);
-      wave_sync_lds();
-      const uint64_t tl3 = wall_clock64();
-      if (l == 0) bcount(bs, GFS_T_RUN, tl3 - tl2);
-      /* a reservation can fail only if both buckets are full: keep the prefix before the
-         first failure (the demanded page comes first) and drop the rest */
-      uint32_t keep = n;
-      if (failed) {
-        uint32_t firstbad = n;
-        for (uint32_t i = l; i < n; i += 64)
-          if (bs->lslot[i] == 0xffffffffu) firstbad = i < firstbad ? i : firstbad;
-        for (int off = 32; off > 0; off >>= 1) {
-          const uint32_t o = __shfl_xor(firstbad, off, 64);
-          firstbad = o < firstbad ? o : firstbad;
-        }
-        keep = firstbad;
-      }
-      const uint32_t got = keep ? alloc_wave(d, file, p, bs, keep, bid) : 0;
-      if (l == 0) bcount(bs, GFS_T_ALLOC, wall_clock64() - tl3);
-      /* release reservations that got no frame (the table was full or no frame was free) */
-      for (uint32_t i = got + l; i < n; i += 64) {
-        if (bs->lslot[i] != 0xffffffffu)
-          st_rel(d->pt + bs->lslot[i], 0ull);
-      }
-      if (got == 0) {
-        if (l == 0) bcount(bs, keep ? GFS_C_NOFRAME : GFS_C_RETRIES, 1);
-        if (keep == 0 && expired(d, t0)) {
-          /* the demanded page's buckets stayed full until the wait limit */
-          if (l == 0) {
-            bs->status = -kENOSPC;
-            bs->pull = 0;
-            bs->frame = -1;
-          }
-          return;
-        }
-        if (expired(d, t0)) break;
-        if (l == 0) nap(naps);
-        continue;   /* buckets full of reservations in flight, or every frame pinned or
-                       filling: back off and retry the access */
-      }
-      if (got < n && l == 0)
-        trace_ev(d, 1, GFS_EV_NOFRAME, bid, file, bs->list[got], GFS_NO_FRAME, 0, 0);
-      /* span of the pages that got frames: p and a contiguous piece of the run */
-      uint64_t lo = ~0ull, hi = 0;
-      for (uint32_t k = l; k < got; k += 64) {
-        const uint64_t q = bs->list[k];
-        lo = q < lo ? q : lo;
-        hi = q > hi ? q : hi;
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t olo = __shfl_xor(lo, off, 64), ohi = __shfl_xor(hi, off, 64);
-        lo = olo < lo ? olo : lo;
-        hi = ohi > hi ? ohi : hi;
-      }
-      /* post the request for the span [lo, hi] and wait for the host */
-      const uint32_t span = (uint32_t)(hi - lo + 1);
-      const uint64_t off0 = lo << d->page_shift;
-      uint64_t len = (uint64_t)span << d->page_shift;
-      if (off0 + len > fsize) len = fsize - off0;
-      int64_t status = 0;
-      uint64_t tk = 0;
-      if (l == 0) {
-        ring_ticket_lane(d, bid, tk);
-        const uint32_t s = ring_slot(d, bid, tk);
-        const uint64_t gen = ring_gen(d, tk);
-        uint32_t nn = 0;
-        const uint64_t ts0 = wall_clock64();
-        while (ld_rlx(&d->slot_free[s]) != gen - 1) {
-          if (expired(d, t0)) {
-            status = -kETIMEDOUT;
-            break;
-          }
-          nap(nn);
-        }
-        acquire_agent();   /* the slot's last users are done with its staging */
-        bcount(bs, GFS_T_SLOT, wall_clock64() - ts0);
-        if (status == 0) {
-          gfs_rpc_slot* rs = &d->ring[s];
-          rs->file_id = file;
-          rs->npages = span;
-          rs->offset = off0;
-          rs->length = len;
-          rs->ticket = tk;
-          __hip_atomic_store(&rs->req_seq, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-          trace_ev(d, 1, GFS_EV_REQ, bid, file, (uint32_t)lo, GFS_NO_FRAME, span, tk);
-          bcount(bs, GFS_C_MISSES, 1);
-          bcount(bs, GFS_C_REQUESTS, 1);
-          bcount(bs, GFS_C_REQ_BYTES, len);
-          bcount(bs, GFS_C_FETCHED, got);
-          bcount(bs, GFS_C_RA_PAGES, got - 1);
-        }
-      }
-      status = __shfl(status, 0, 64);
-      tk = __shfl(tk, 0, 64);
-      const uint32_t s = ring_slot(d, bid, tk);
-      const uint64_t gen = ring_gen(d, tk);
-      if (status == 0) {
-        /* tell waiting blocks which request fills each frame: (slot + 1) << 40 | gen */
-        const uint64_t fill = ((uint64_t)(s + 1) << 40) | (gen & ((1ull << 40) - 1));
-        for (uint32_t k = l; k < got; k += 64) st_rel(&d->ffill[bs->lframe[k]], fill);
-      }
-      if (l == 0) {
-        if (status == 0) {
-          gfs_rpc_slot* rs = &d->ring[s];
-          uint32_t nn = 0;
-          const uint64_t th0 = wall_clock64();
-          while (__hip_atomic_load(&rs->done_seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) !=
-                 gen) {
-            if (expired(d, t0)) {
-              status = -kETIMEDOUT;
-              break;
-            }
-            nap(nn);
-          }
-          acquire_system();   /* the staged bytes, written by the host before done_seq */
-          bcount(bs, GFS_T_HOST, wall_clock64() - th0);
-          if (status == 0) {
-            bs->result = rs->result;
-            /* let blocks waiting on frames of this request pull their own pages */
-            gfs_req_dev* rq = &d->reqd[s];
-            rq->result = bs->result;
-            rq->first_page = lo;
-            rq->file = file;
-            __hip_atomic_store(&rq->remaining, got, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            st_rel(&rq->ready, gen);
-          }
-        }
-        if (status) bcount(bs, GFS_C_TIMEOUTS, 1);
-        bs->status = status;
-        bs->frame = (int32_t)bs->lframe[0];
-        bs->pull = status == 0 ? 1 : 0;
-        bs->slot = s;
-        bs->gen = gen;
-        bs->first_page = lo;
-        bs->list_n = got;
-        bs->file = file;
+        bs->status = 0;
+        bs->pull = 5;
+        bs->frame = -1;
       }
       return;
+    } else if (f < 0) {
+      const int r = miss_shared_wave(d, file, p, key, fsize, bs, bid, t0, naps);
+      if (r == 0) return;
+      if (r == 2) break;
+      continue;
     }
     /* reserved by another block's miss, or a lost race: wait a little and look again */
     if (expired(d, t0)) break;
@@ -1584,9 +1712,12 @@ __device__ int64_t publish_pull_wave(const gfs_dev* d, BlockState* bs, uint64_t 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (l == 0) {
       request_done_lane(d, bs->slot, bs->gen, bs->nclaim);
-      /* the demanded page: pulled here, or by a helper that may still be copying it */
-      st = wait_valid_lane(d, (uint32_t)bs->frame, t0);
-      if (st == -kETIMEDOUT) bcount(bs, GFS_C_TIMEOUTS, 1);
+      /* the demanded page: pulled here, or by a helper that may still be copying it (an
+         asynchronous request has none: frame -1) */
+      if (bs->frame >= 0) {
+        st = wait_valid_lane(d, (uint32_t)bs->frame, t0);
+        if (st == -kETIMEDOUT) bcount(bs, GFS_C_TIMEOUTS, 1);
+      }
     }
   }
   for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off, 64);
@@ -1652,6 +1783,263 @@ __device__ int64_t private_publish_lane(const gfs_dev* d, BlockState* bs, uint64
   return 0;
 }
 
+/* ------------------------------------------------------------------ asynchronous readahead
+ * Sec. 2.3: Linux reads the next window while the reader still consumes the current one. A
+ * stream's marker page (the page after the demanded one in a demand window, the first page
+ * of an asynchronous window) carries GFS_FW_MARK from its allocation; the first block whose
+ * access finds it clears it and, after copying its own page, advances the stream: window
+ * [next, next + min(2 size, cap)), the run of unmapped pages from its start, posted to the
+ * host with nobody waiting. Blocks that need one of its pages join the frame and pull it from
+ * staging once the host is done (the ring slot says so); the block that posted the request
+ * pulls the rest when it next needs to post, reaches the next marker, or closes the file. */
+
+/* Wave-collective, outside the lock: reserve the run of unmapped pages that starts at ws,
+   within [ws, ws + n), ascending into bs->list/lslot/lframe; returns its length and sets
+   failed if a page found both buckets full. */
+__device__ uint32_t reserve_from_wave(const gfs_dev* d, uint32_t file, uint64_t ws, uint32_t n, BlockState* bs,
+                                      uint32_t& failed) {
+  const uint32_t l = lane();
+  uint32_t count = 0, bad = 0;
+  for (uint32_t base = 0; base < n; base += 64) {
+    const bool valid = base + l < n;
+    const uint64_t q = ws + base + l;
+    const uint64_t key = page_key(file, q);
+    uint32_t b1 = 0, b2 = 0;
+    uint64_t e[2 * GFS_BUCKET_SLOTS];
+    bool present = false;
+    if (valid) {
+      key_buckets(d, key, b1, b2);
+      pt_load_lane(d, b1, b2, e);
+#pragma unroll
+      for (int i = 0; i < 2 * GFS_BUCKET_SLOTS; ++i) present |= (e[i] >> GFS_ENTRY_FRAME_BITS) == key;
+    }
+    const uint64_t stop = __ballot(!valid || present);
+    const uint32_t k = stop ? (uint32_t)__builtin_ctzll(stop) : 64u;
+    if (l < k) {
+      int cnt1 = 0, cnt2 = 0, f1 = -1, f2 = -1;
+#pragma unroll
+      for (int i = 0; i < GFS_BUCKET_SLOTS; ++i) {
+        if (e[i]) ++cnt1;
+        else if (f1 < 0) f1 = i;
+        if (e[GFS_BUCKET_SLOTS + i]) ++cnt2;
+        else if (f2 < 0) f2 = GFS_BUCKET_SLOTS + i;
+      }
+      int pick = cnt2 < cnt1 ? f2 : f1;
+      if (pick < 0) pick = f1 >= 0 ? f1 : f2;
+      int64_t slot = -1;
+      if (pick >= 0) {
+        uint64_t expect = 0;
+        uint64_t* sp = slot_ptr(d, b1, b2, pick);
+        if (cas64_rlx(sp, expect, (key << GFS_ENTRY_FRAME_BITS) | kReserved)) slot = (int64_t)(sp - d->pt);
+        else slot = pt_reserve_lane(d, key);
+      }
+      bs->list[base + l] = (uint32_t)q;
+      bs->lslot[base + l] = slot < 0 ? 0xffffffffu : (uint32_t)slot;
+      bs->lframe[base + l] = GFS_NO_FRAME;
+      bad |= slot < 0 ? 1u : 0u;
+    }
+    count = base + k;
+    if (k < 64) break;
+  }
+  failed = (uint32_t)(__ballot(bad != 0) != 0);
+  return count;
+}
+
+/* Wave 0, with no asynchronous request of the block outstanding: the block's access found
+   marker page m of file `file`. Advance the stream whose marker m still is (lowest slot),
+   reserve and allocate the window's unmapped run, and post it to the host without waiting;
+   the request becomes the block's outstanding one. Gives up quietly when no stream names m,
+   the window is empty, a running claim holds its first page, or no frame is free. */
+__device__ __attribute__((noinline)) void async_issue_wave(const gfs_dev* d, uint32_t file, uint64_t m, uint64_t fsize, BlockState* bs,
+                                 uint32_t bid, uint64_t t0) {
+  const uint32_t l = lane();
+  uint64_t ticket;
+  /* the waiter announces no page of any window, so no holder marks it covered */
+  const int lk = lock_file_wave(d, file, 0, 0x7fffffffull, t0, ticket, false);
+  if (lk != LOCK_OWN) return;
+  __builtin_amdgcn_s_setprio(3);
+  const RaState ras = ra_load_lane(d, file);
+  uint64_t cl = 0;
+  if (l < GFS_CLAIMS) cl = ld_rlx(&d->claims[file].e[l]);
+  const uint64_t npages = d->files[file].npages;
+  drain_atomics();
+  const uint64_t sm = __ballot(l < d->streams && ras.s_valid && ras.s_marker == (uint32_t)m);
+  if (sm == 0) {
+    unlock_file_wave(d, file, ticket, 0, 0);
+    __builtin_amdgcn_s_setprio(0);
+    return;
+  }
+  const int j = __ffsll((unsigned long long)sm) - 1;
+  const uint32_t clk = __shfl(ras.clk, 0, 64) + 1;
+  const uint64_t ws = __shfl(ras.s_next, j, 64);
+  const uint32_t sz = __shfl(ras.s_size, j, 64);
+  const uint32_t cap = ra_cap_eff(d);
+  const uint32_t wn = 2 * sz < cap ? 2 * sz : cap;
+  gfs_file_dev* fe = &d->files[file];
+  if (l == 0) {
+    gfs_stream* st = &fe->streams[j];
+    st_rlx(&st->next, ws + wn);
+    st_rlx32(&st->size, wn);
+    st_rlx32(&st->last_use, clk);
+    st_rlx32(&st->marker, (uint32_t)ws);
+    st_rlx32(&fe->clock, clk);
+  }
+  const uint32_t wnc = ws < npages ? (uint32_t)((npages - ws) < wn ? (npages - ws) : wn) : 0u;
+  if (l == 0) {
+    trace_ev(d, 1, GFS_EV_ADV, bid, file, (uint32_t)m, 0, wnc, ws);
+    bcount(bs, GFS_C_ADVANCES, 1);
+  }
+  /* a running claim on the first page: that block is fetching it; else stop at the next claim */
+  const bool cl_on = l < GFS_CLAIMS && (cl & 1ull);
+  const uint64_t cl_lo = cl >> 32, cl_hi = (cl >> 32) + ((cl & 0xffffffffull) >> 1);
+  const bool held = __ballot(cl_on && cl_lo <= ws && ws < cl_hi) != 0;
+  const uint64_t free_cl = __ballot(l < GFS_CLAIMS && !cl_on);
+  uint64_t hi_b = cl_on && cl_lo > ws ? cl_lo : ~0ull;
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t b = __shfl_xor(hi_b, off, 64);
+    hi_b = b < hi_b ? b : hi_b;
+  }
+  const uint64_t cwe = ws + wnc < hi_b ? ws + wnc : hi_b;
+  if (wnc == 0 || held || free_cl == 0 || cwe <= ws) {
+    unlock_file_wave(d, file, ticket, 0, 0);
+    __builtin_amdgcn_s_setprio(0);
+    return;
+  }
+  const uint32_t cj = (uint32_t)__builtin_ctzll(free_cl);
+  uint64_t* claim = &d->claims[file].e[cj];
+  if (l == 0) st_rlx(claim, (ws << 32) | ((cwe - ws) << 1) | 1ull);
+  unlock_file_wave(d, file, ticket, ws, cwe);
+  __builtin_amdgcn_s_setprio(0);
+  uint32_t failed = 0;
+  const uint32_t n = reserve_from_wave(d, file, ws, (uint32_t)(cwe - ws), bs, failed);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (l == 0) st_rlx(claim, 0ull);
+  wave_sync_lds();
+  uint32_t keep = n;
+  if (failed) {
+    uint32_t firstbad = n;
+    for (uint32_t i = l; i < n; i += 64)
+      if (bs->lslot[i] == 0xffffffffu) firstbad = i < firstbad ? i : firstbad;
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint32_t o = __shfl_xor(firstbad, off, 64);
+      firstbad = o < firstbad ? o : firstbad;
+    }
+    keep = firstbad;
+  }
+  /* no demanded page: every page is prefetched; the window's first page is the new marker */
+  const uint32_t got = keep ? alloc_wave(d, file, ~0ull, bs, keep, bid, ws) : 0;
+  for (uint32_t i = got + l; i < n; i += 64)
+    if (bs->lslot[i] != 0xffffffffu) st_rel(d->pt + bs->lslot[i], 0ull);
+  if (got == 0) return;
+  if (got < n && l == 0) trace_ev(d, 1, GFS_EV_NOFRAME, bid, file, bs->list[got], GFS_NO_FRAME, 0, 0);
+  /* the pages that got frames are [ws, ws + got) */
+  const uint64_t off0 = ws << d->page_shift;
+  uint64_t len = (uint64_t)got << d->page_shift;
+  if (off0 + len > fsize) len = fsize - off0;
+  int status = 0;
+  uint64_t tk = 0;
+  if (l == 0) {
+    ring_ticket_lane(d, bid, tk);
+    const uint32_t s = ring_slot(d, bid, tk);
+    const uint64_t gen = ring_gen(d, tk);
+    uint32_t nn = 0;
+    const uint64_t ts0 = wall_clock64();
+    while (ld_rlx(&d->slot_free[s]) != gen - 1) {
+      if (expired(d, t0)) {
+        status = 1;
+        break;
+      }
+      nap(nn);
+    }
+    acquire_agent();   /* the slot's last users are done with its staging */
+    bcount(bs, GFS_T_SLOT, wall_clock64() - ts0);
+    if (status == 0) {
+      /* frames count themselves off the request as they are published */
+      __hip_atomic_store(&d->reqd[s].remaining, got, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      bcount(bs, GFS_C_TIMEOUTS, 1);
+    }
+  }
+  status = __shfl(status, 0, 64);
+  tk = __shfl(tk, 0, 64);
+  if (status) return;   /* the frames stay filling; the cache must be reset after a timeout */
+  const uint32_t s = ring_slot(d, bid, tk);
+  const uint64_t gen = ring_gen(d, tk);
+  const uint64_t fill = (1ull << 63) | ((uint64_t)(s + 1) << 40) | (gen & ((1ull << 40) - 1));
+  for (uint32_t k = l; k < got; k += 64) st_rel(&d->ffill[bs->lframe[k]], fill);
+  if (l == 0) {
+    gfs_rpc_slot* rs = &d->ring[s];
+    rs->file_id = file;
+    rs->npages = got;
+    rs->offset = off0;
+    rs->length = len;
+    rs->ticket = tk;
+    __hip_atomic_store(&rs->req_seq, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    trace_ev(d, 1, GFS_EV_REQ, bid, file, (uint32_t)ws, GFS_NO_FRAME, got, tk);
+    bcount(bs, GFS_C_REQUESTS, 1);
+    bcount(bs, GFS_C_REQ_BYTES, len);
+    bcount(bs, GFS_C_FETCHED, got);
+    bcount(bs, GFS_C_RA_PAGES, got);
+    bs->a_pending = 1;
+    bs->a_slot = s;
+    bs->a_gen = gen;
+    bs->a_first = ws;
+    bs->a_n = got;
+    bs->a_file = file;
+  }
+}
+
+/* Block-collective: finish the block's outstanding asynchronous request, if any: wait for the
+   host, pull every frame no other block has claimed, publish them. 0 or -ETIMEDOUT. */
+__device__ __attribute__((noinline)) int64_t async_finish_block(const gfs_dev* d, BlockState* bs) {
+  const uint32_t tid = thread_id();
+  __syncthreads();
+  if (!bs->a_pending) return 0;
+  const uint64_t t0 = wall_clock64();
+  if (tid == 0) {
+    gfs_rpc_slot* rs = &d->ring[bs->a_slot];
+    uint32_t nn = 0;
+    int st = 0;
+    const uint64_t th0 = wall_clock64();
+    while (__hip_atomic_load(&rs->done_seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != bs->a_gen) {
+      if (expired(d, t0)) {
+        st = -kETIMEDOUT;
+        break;
+      }
+      nap(nn);
+    }
+    acquire_system();   /* the staged bytes, written by the host before done_seq */
+    bcount(bs, GFS_T_HOST, wall_clock64() - th0);
+    if (st) bcount(bs, GFS_C_TIMEOUTS, 1);
+    bs->a_status = st;
+    bs->result = rs->result;
+    bs->slot = bs->a_slot;
+    bs->gen = bs->a_gen;
+    bs->first_page = bs->a_first;
+    bs->list_n = bs->a_n;
+    bs->frame = -1;
+    bs->pull = 1;
+  }
+  __syncthreads();
+  const int64_t st = bs->a_status;
+  if (st == 0) {
+    const uint64_t fsize = d->files[bs->a_file].size;
+    if (tid < 64) claim_pulls_wave(d, bs);
+    __syncthreads();
+    block_pull(d, bs, fsize);
+    __threadfence();
+    __syncthreads();
+    if (tid < 64) (void)publish_pull_wave(d, bs, fsize, t0);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    bs->a_pending = 0;
+    bs->pull = 0;
+  }
+  __syncthreads();
+  return st;
+}
+
 }  // namespace gfsd
 
 /* ====================================================================== public API */
@@ -1698,6 +2086,8 @@ __device__ int gopen_id(const gfs_dev* d, int file_id, int flags) {
     }
     for (int c = 0; c < GFS_C_COUNT; ++c) bs->ctr[c] = 0;
     bs->pull = 0;
+    bs->trig = 0;
+    bs->a_pending = 0;   /* an asynchronous request is finished by gclose, before the next gopen */
     bs->open_result = v;
   }
   __syncthreads();
@@ -1730,6 +2120,8 @@ __device__ int gopen(const gfs_dev* d, const char* path, int flags) {
 __device__ int gclose(const gfs_dev* d, int fd) {
   if (fd < 0 || (uint32_t)fd >= d->max_files) return -gfsd::kEBADF;
   gfsd::BlockState* bs = gfsd::block_state();
+  /* an asynchronous request still outstanding is pulled in before the block lets go */
+  (void)gfsd::async_finish_block(d, bs);
   __syncthreads();
   if (gfsd::thread_id() == 0) {
     __hip_atomic_fetch_sub(&d->files[fd].handles, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1783,9 +2175,11 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
         const uint64_t key = page_key((uint32_t)fd, pfirst + tid);
         f = pt_find_lane(d, key);
         if (f >= 0 && (uint32_t)f != kReserved) {
-          const int r = frame_pin(d, (uint32_t)f, key);
-          if (r != PIN_VALID) {
-            if (r == PIN_FILLING) frame_unpin(d, (uint32_t)f);   /* the one-page path joins it */
+          uint64_t w = 0;
+          const int r = frame_pin(d, (uint32_t)f, key, &w);
+          if (r != PIN_VALID || (d->ra_async && (w & GFS_FW_MARK))) {
+            /* the one-page path joins a filling frame, and takes a marker page's mark */
+            if (r == PIN_FILLING || r == PIN_VALID) frame_unpin(d, (uint32_t)f);
             f = -1;
           }
         } else {
@@ -1850,6 +2244,16 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
     const uint64_t ta0 = wall_clock64();
     if (tid < 64) acquire_page_wave(d, (uint32_t)fd, p, fsize, bs, bid);
     __syncthreads();
+    if (bs->pull == 5) {
+      /* a miss while this block's asynchronous request is outstanding: finish it, look again */
+      const int64_t e = async_finish_block(d, bs);
+      if (e < 0) {
+        err = e;
+        break;
+      }
+      --p;   /* the same page again (unsigned wrap at 0 is undone by the loop's ++p) */
+      continue;
+    }
     if (bs->pull >= 3) {
       const uint64_t tp0 = wall_clock64();
       private_pull(d, bs, fsize);
@@ -1893,15 +2297,52 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
     const uint64_t pbase = p << sh_bits;
     const uint64_t lo = offset > pbase ? offset : pbase;
     const uint64_t hi = end < pbase + P ? end : pbase + P;
+    /* a hit pinned with its tag unchecked: thread 0's tag load goes out just before its share
+       of the copy, so the check costs no round trip of its own; if the frame turns out to hold
+       another page (reused between the lookup and the pin), the bytes copied to dst are
+       overwritten by the next look (gread has not returned, so nobody may read dst yet) */
+    const uint64_t tk = bs->tagkey;
+    uint64_t tag = 0;
+    if (tk && tid == 0) tag = ld_rlx(&d->ftag[f]);
     copy_block((uint8_t*)dst + (lo - offset), d->frames + (uint64_t)f * P + (lo - pbase), hi - lo,
                tid, nt);
+    if (tk && tid == 0) {
+      const bool ok = tag == tk;
+      bs->tag_ok = ok ? 1 : 0;
+      if (ok && d->ra_async && (bs->pinw & GFS_FW_MARK)) bs->trig = mark_take_lane(d, (uint32_t)f) ? 1u : 0u;
+    }
     __syncthreads();
+    const bool trig = bs->trig != 0;
+    if (tk && !bs->tag_ok) {
+      __syncthreads();
+      if (tid == 0) {
+        frame_unpin(d, (uint32_t)f);
+        bcount(bs, GFS_C_RETRIES, 1);
+      }
+      --p;   /* look the same page up again (unsigned wrap at 0 is undone by the loop's ++p) */
+      continue;
+    }
     if (tid == 0) {
+      if (tk) {
+        frame_pin_bits(d, (uint32_t)f, bs->pinw);
+        bcount(bs, GFS_C_HITS, 1);
+      }
       const uint64_t ta2 = wall_clock64();
       frame_unpin(d, (uint32_t)f);
       bcount(bs, GFS_T_ACQUIRE, ta1 - ta0);
       bcount(bs, GFS_T_COPY, ta2 - ta1);
       bcount(bs, GFS_T_UNPIN, wall_clock64() - ta2);
+    }
+    if (trig) {
+      /* this access took its stream's marker: finish the block's previous asynchronous
+         request, then issue the stream's next window without waiting for it */
+      const int64_t e = async_finish_block(d, bs);
+      if (e < 0) {
+        err = e;
+        break;
+      }
+      if (tid < 64) async_issue_wave(d, (uint32_t)fd, p, fsize, bs, bid, wall_clock64());
+      __syncthreads();
     }
   }
   if (err) return err;

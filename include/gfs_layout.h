@@ -5,7 +5,7 @@
  * word and page-table entry encodings, and the request-ring slot in pinned host memory.
  *
  * HBM layout of the metadata region (offsets computed by the host, stored in gfs_dev):
- *   gfs_globals                      320 B
+ *   gfs_globals                      384 B
  *   gfs_dev (the handle)             512 B
  *   files[max_files]                 768 B each
  *   locks[max_files]                 128 B each (miss ticket locks)
@@ -39,6 +39,8 @@
 #define GFS_FW_RA (1ull << 3)    /* prefetched, not yet demanded */
 #define GFS_FW_ERR (1ull << 4)   /* the host read for this page failed */
 #define GFS_FW_PULL (1ull << 5)  /* filling, and a block is copying the bytes into the frame */
+#define GFS_FW_MARK (1ull << 6)  /* asynchronous readahead: the page is its stream's marker; the
+                                    first block to find it advances the stream */
 #define GFS_FW_PIN_SHIFT 8
 #define GFS_FW_PIN_ONE (1ull << GFS_FW_PIN_SHIFT)
 #define GFS_FW_PINS (0xffffull << GFS_FW_PIN_SHIFT)
@@ -58,7 +60,7 @@ typedef struct gfs_globals {
   uint64_t ring_tail;     /* request ring ticket counter */
   uint64_t trace_n;       /* trace records appended (including dropped) */
   uint64_t pad0[5];
-  uint64_t ctr[32];       /* device counters, GFS_C_* */
+  uint64_t ctr[40];       /* device counters, GFS_C_* */
 } gfs_globals;
 
 enum {
@@ -77,9 +79,10 @@ enum {
   GFS_T_ACQUIRE, GFS_T_COPY, GFS_T_UNPIN,
   GFS_C_PB_HITS,     /* private policy: misses filled from the private buffer */
   GFS_C_PB_WASTED,   /* private policy: private-buffer pages dropped unused */
+  GFS_C_ADVANCES,    /* asynchronous readahead: windows issued at a marker page */
   GFS_C_COUNT
 };
-typedef char gfs_counters_fit[(GFS_C_COUNT <= 32) ? 1 : -1];   /* gfs_globals.ctr */
+typedef char gfs_counters_fit[(GFS_C_COUNT <= 40) ? 1 : -1];   /* gfs_globals.ctr */
 
 /* room for the readahead detector's recent misses (the configured count, ra_recent, is at
    most this: one per lane of the deciding wave) */
@@ -90,8 +93,10 @@ typedef struct gfs_stream {
   uint32_t size;          /* last window length (pages) */
   uint32_t last_use;      /* per-file decision clock at last use */
   uint32_t valid;
-  uint32_t pad;
+  uint32_t marker;        /* asynchronous readahead: the page whose first access advances the
+                             stream (GFS_NO_MARKER: none) */
 } gfs_stream;             /* 24 B */
+#define GFS_NO_MARKER 0xffffffffu
 
 typedef struct gfs_file_dev {
   uint64_t size;          /* bytes */
@@ -189,7 +194,7 @@ typedef struct gfs_dev {
   uint32_t ra_near_pages;       /* detector: "near" radius */
   uint32_t ra_near_min;         /* detector: near misses that mark aggregate reading */
   uint32_t ra_quota_blocks;     /* thrash guard: resident blocks the cache is shared by */
-  uint32_t pad_dev0;
+  uint32_t ra_async;            /* 1: marker-triggered (asynchronous) readahead */
   uint64_t max_req_bytes;
   uint64_t timeout_ticks;       /* wall_clock64 ticks */
   uint8_t* frames;
@@ -209,7 +214,8 @@ typedef struct gfs_dev {
   uint32_t partitioned;         /* 1: a block posts into the slot of its block id */
   uint64_t* slot_free;
   uint64_t* slot_tail;          /* partitioned queue: requests posted into each slot so far */
-  uint64_t* ffill;
+  uint64_t* ffill;              /* per frame: (slot + 1) << 40 | generation of the request filling
+                                   it, bit 63 set for an asynchronous request (0: not yet known) */
   gfs_req_dev* reqd;
   uint32_t* req_frames;
   void* trace;                  /* gfs_event[trace_cap] */

@@ -41,9 +41,25 @@ whole window); a filled frame gets its reference bit set; a pin sets it and
 clears the unconsumed-prefetch mark; the hand starts at frame 0, skips frames
 that are filling or pinned, clears a set reference bit, and otherwise evicts.
 
+Asynchronous readahead (``ra_async``; Sec. 2.3: Linux issues the next window while the
+reader is still consuming the current one). Each decided window sets its stream's marker:
+after a demand miss at p, the page p + 1 when the window fetched it; after an
+asynchronous window, the window's first page. The marker page's frame carries a mark from
+its allocation. A block whose access finds a marked frame (hit or join) clears the mark and,
+if a stream's marker still names that page (lowest slot), advances that stream: window
+[s.next, s.next + min(2 s.size, cap)), the unmapped run from its first page, allocated
+ascending and requested from the host, with no page demanded and nobody waiting for it.
+A block keeps at most one such request outstanding: it completes the previous one first,
+when it reaches a marked page. In serialized runs every request completes by the end of
+the read that issued it (the test harness waits for it there). An access that finds a page
+still being filled (a later page of the same read, inside the block's own outstanding
+request) joins it: the page is filled then.
+
 Events produced (tuples; the GPU trace is decoded into the same vocabulary):
 
   ("HIT",  block, file, page, frame)
+  ("JOIN", block, file, page, frame)          the frame was still being filled
+  ("ADV",  block, file, page, ws, wn)         an asynchronous window, triggered at page
   ("MISS", block, file, page, ws, wn)          wn already clamped to EOF
   ("HAND", ticket, frame, action, vfile, vpage, vra, seen)
         action in FREE / SKIP / CLEAR / EVICT; victim fields are -1, -1, 0 unless EVICT;
@@ -87,6 +103,7 @@ class Frame:
     pins: int = 0
     ref: int = 0
     ra: int = 0
+    mark: int = 0          # asynchronous readahead: the page is its stream's marker
 
 
 @dataclasses.dataclass
@@ -95,6 +112,7 @@ class Stream:
     next: int = 0
     size: int = 0
     last_use: int = 0
+    marker: int = -1       # asynchronous readahead: the page whose access advances the stream
 
 
 @dataclasses.dataclass
@@ -110,7 +128,7 @@ class FileState:
 class PolicyModel:
     def __init__(self, nframes: int, page_size: int, ra_init_pages: int = 4,
                  ra_cap_pages: int = 0, streams_per_file: int = 8, recent: int = RECENT,
-                 near_pages: int = NEAR_PAGES, near_min: int = NEAR_MIN):
+                 near_pages: int = NEAR_PAGES, near_min: int = NEAR_MIN, ra_async: bool = False):
         """ra_cap_pages is the cap after the thrash guard (see ``quota_cap``)."""
         if nframes <= 0 or page_size <= 0:
             raise ValueError("nframes and page_size must be positive")
@@ -122,6 +140,8 @@ class PolicyModel:
         self.recent = recent
         self.near_pages = near_pages
         self.near_min = near_min
+        self.ra_async = ra_async
+        self.pending: Dict[int, List[int]] = {}   # block -> frames of its outstanding request
         self.frames = [Frame() for _ in range(nframes)]
         self.map: Dict[Tuple[int, int], int] = {}
         self.hand = 0
@@ -131,6 +151,8 @@ class PolicyModel:
         self.decisions: List[Tuple[int, int, int]] = []
         # counters
         self.hits = 0
+        self.joins = 0
+        self.advances = 0
         self.misses = 0
         self.evictions = 0
         self.fetched_pages = 0
@@ -155,7 +177,10 @@ class PolicyModel:
 
     # ---- readahead decision (one per miss) -----------------------------------------------
     def ra_decide(self, file_id: int, p: int) -> Tuple[int, int]:
+        """The window for a demand miss at p; the stream it set is left in self.last_stream
+        (None when readahead is off)."""
         fs = self.files[file_id]
+        self.last_stream = None
         if self.cap == 0 or fs.advice == ADV_RANDOM or not fs.read_only:
             self.decisions.append((0, 0, RULE_OFF))
             return p, 1
@@ -171,6 +196,7 @@ class PolicyModel:
                 s.next = ws + wn
                 s.size = wn
                 s.last_use = fs.clock
+                self.last_stream = s
                 self.decisions.append((near, 0, RULE_ZONE))
                 return ws, wn
         # context: the pages right behind p are already cached (read or being read by other
@@ -204,6 +230,7 @@ class PolicyModel:
         victim.next = ws + wn
         victim.size = wn
         victim.last_use = fs.clock
+        self.last_stream = victim
         return ws, wn
 
     # ---- clock ----------------------------------------------------------------------------
@@ -241,17 +268,31 @@ class PolicyModel:
         f = self.map.get((file_id, p))
         if f is not None:
             fr = self.frames[f]
+            if fr.state == FILLING:
+                # a page of the block's own outstanding request: wait for it, fill it
+                self.joins += 1
+                self.events.append(("JOIN", block, file_id, p, f))
+                fr.state = VALID
+                self.pending[block].remove(f)
+            else:
+                self.hits += 1
+                self.events.append(("HIT", block, file_id, p, f))
             fr.pins += 1
             fr.ref = 1
             fr.ra = 0
-            self.hits += 1
-            self.events.append(("HIT", block, file_id, p, f))
             fr.pins -= 1
+            if self.ra_async and fr.mark:
+                fr.mark = 0
+                self.advance(block, file_id, p)
             return f
         self.misses += 1
         ws, wn = self.ra_decide(file_id, p)
         wn = min(wn, self.npages(file_id) - ws)
         self.events.append(("MISS", block, file_id, p, ws, wn))
+        marker = -1
+        if self.ra_async and self.last_stream is not None:
+            marker = p + 1 if p + 1 < ws + wn else -1
+            self.last_stream.marker = marker
         # fetch the run of unmapped window pages that contains p (no holes in a request)
         a = p
         while a - 1 >= ws and (file_id, a - 1) not in self.map:
@@ -274,6 +315,7 @@ class PolicyModel:
             fr.pins = 1 if q == p else 0
             fr.ref = 0
             fr.ra = 0 if q == p else 1
+            fr.mark = 1 if q == marker else 0
             self.map[(file_id, q)] = g
             self.events.append(("ALLOC", file_id, q, g, fr.ra))
             allocated.append((q, g))
@@ -295,15 +337,70 @@ class PolicyModel:
         self.frames[fp].pins -= 1
         return fp
 
+    # ---- asynchronous readahead ---------------------------------------------------------------
+    def complete(self, block: int) -> None:
+        """The block's outstanding asynchronous request arrives: its frames become valid."""
+        for g in self.pending.pop(block, []):
+            fr = self.frames[g]
+            fr.state = VALID
+            fr.ref = 1
+
+    def advance(self, block: int, file_id: int, p: int) -> None:
+        """A block reached marked page p: finish its own outstanding request, then, if a
+        stream's marker still names p (lowest slot), issue that stream's next window."""
+        self.complete(block)
+        fs = self.files[file_id]
+        s = next((t for t in fs.streams if t.valid and t.marker == p), None)
+        if s is None:
+            return
+        fs.clock += 1
+        ws = s.next
+        wn = min(2 * s.size, self.cap)
+        s.next = ws + wn
+        s.size = wn
+        s.last_use = fs.clock
+        s.marker = ws
+        wn = max(0, min(wn, self.npages(file_id) - ws))
+        self.advances += 1
+        self.events.append(("ADV", block, file_id, p, ws, wn))
+        allocated = []
+        q = ws
+        while q < ws + wn and (file_id, q) not in self.map:
+            g = self.alloc()
+            if g is None:
+                self.events.append(("NOFRAME", block, file_id, q))
+                break
+            fr = self.frames[g]
+            fr.state = FILLING
+            fr.file, fr.page = file_id, q
+            fr.pins = 0
+            fr.ref = 0
+            fr.ra = 1
+            fr.mark = 1 if q == ws else 0
+            self.map[(file_id, q)] = g
+            self.events.append(("ALLOC", file_id, q, g, 1))
+            allocated.append(g)
+            self.fetched_pages += 1
+            self.fetched_bytes += self.page_bytes(file_id, q)
+            self.ra_pages += 1
+            q += 1
+        if allocated:
+            self.events.append(("REQ", file_id, ws, len(allocated)))
+            self.requests += 1
+            self.request_bytes += sum(self.page_bytes(file_id, r) for r in range(ws, ws + len(allocated)))
+            self.pending[block] = allocated
+
     # ---- one block-collective read ------------------------------------------------------------
     def gread(self, block: int, file_id: int, offset: int, size: int) -> int:
-        """Split [offset, offset+size) into pages (ascending) and access each; returns bytes."""
+        """Split [offset, offset+size) into pages (ascending) and access each; returns bytes.
+        An asynchronous request the read issued completes when it ends (serialized runs)."""
         fsize = self.files[file_id].size
         if size <= 0 or offset >= fsize:
             return 0
         end = min(offset + size, fsize)
         for p in range(offset // self.P, (end - 1) // self.P + 1):
             self.access(block, file_id, p)
+        self.complete(block)
         self.delivered_bytes += end - offset
         return end - offset
 

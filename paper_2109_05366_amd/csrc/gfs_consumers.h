@@ -18,6 +18,13 @@ __device__ __forceinline__ uint64_t checksum_part(const uint8_t* buf, uint64_t n
   const uint64_t n16 = n >> 4;
   const gfsd::gv4u* v = (const gfsd::gv4u*)buf;   /* user buffers are global memory */
   uint64_t i = tid;
+  for (; i + 7ull * nt < n16; i += 8ull * nt) {
+    gfsd::v4u x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = v[i + (uint64_t)k * nt];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += (uint64_t)x[k].x + x[k].y + x[k].z + x[k].w;
+  }
   for (; i + 3ull * nt < n16; i += 4ull * nt) {
     gfsd::v4u x[4];
 #pragma unroll

@@ -85,7 +85,7 @@ int make_layout(const gfs_config* c, Layout* L) {
   if (c->ra_recent < 1 || c->ra_recent > GFS_MAX_RECENT) return -EINVAL;
   if (c->ra_near_pages > (1u << 20) || c->ra_near_min < 1 || c->ra_near_min > c->ra_recent + 1) return -EINVAL;
   if (c->ra_async > 1) return -EINVAL;
-  if (c->ra_async) return -ENOTSUP;   /* marker-triggered prefetch is not built (see gfs.h) */
+  if (c->ra_async && c->policy != GFS_POLICY_SHARED) return -EINVAL;   /* markers live in the shared cache */
   if (c->policy == GFS_POLICY_SHARED) {
     L->max_req_pages = L->ra_cap ? L->ra_cap : 1;
   } else if (c->policy == GFS_POLICY_PRIVATE) {
@@ -329,6 +329,7 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   h.ra_near_pages = cfg->ra_near_pages;
   h.ra_near_min = cfg->ra_near_min;
   h.ra_quota_blocks = quota_blocks;
+  h.ra_async = cfg->ra_async;
   c->cfg.ra_quota_blocks = quota_blocks;   /* gfs_get_config reports the resolved count */
   h.max_req_bytes = L.max_req_bytes;
   c->clock_khz = khz;
@@ -547,6 +548,7 @@ int gfs_stats_read(gfs_ctx* c, gfs_stats* out) {
   s.t_unpin_ns = (uint64_t)(g.ctr[GFS_T_UNPIN] * ns_per_tick);
   s.private_hits = g.ctr[GFS_C_PB_HITS];
   s.private_wasted = g.ctr[GFS_C_PB_WASTED];
+  s.ra_async_windows = g.ctr[GFS_C_ADVANCES];
   s.host_errors = c->io.host_errors.load();
   s.host_last_errno = (uint64_t)c->io.host_last_errno.load();
   for (uint32_t i = 0; i < 64; ++i) s.host_spins[i] = c->io.spins[i].load();

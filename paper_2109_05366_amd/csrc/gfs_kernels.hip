@@ -43,7 +43,7 @@ __global__ void purge_file_kernel(const gfs_dev* d, uint32_t nframes, uint64_t p
   }
 }
 
-__global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) list_reader_kernel(const gfs_dev* d, int file_id, const uint64_t* offsets,
+__global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS, 2) list_reader_kernel(const gfs_dev* d, int file_id, const uint64_t* offsets,
                                    uint32_t reads, uint64_t read_size, int consumer,
                                    uint8_t* buf, void* out, int64_t* status, uint64_t* turn) {
   __shared__ uint32_t hist[256];
@@ -81,6 +81,9 @@ __global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) list_reader_kernel(cons
       }
     }
     const int64_t r = gread(d, fd, offsets[(uint64_t)b * reads + k], read_size, mybuf);
+    // serialized runs: an asynchronous window this read issued is in place before the next
+    // block's turn, so that every access sees the cache the one-at-a-time order implies
+    if (turn) (void)gfsd::async_finish_block(d, gfsd::block_state());
     if (turn && tid == 0)
       __hip_atomic_store(turn, my_turn + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     if (r < 0) {
@@ -114,7 +117,7 @@ __global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) list_reader_kernel(cons
 // in device memory instead of through gread: the GPU half of the CPU-I/O comparator, where
 // host code reads the file and copies it to the GPU before the kernel runs (the paper's
 // "CPU I/O" baseline, Sec. 6).
-__global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) buffer_reader_kernel(const uint8_t* data, uint64_t size,
+__global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS, 2) buffer_reader_kernel(const uint8_t* data, uint64_t size,
                                                                               const uint64_t* offsets, uint32_t reads,
                                                                               uint64_t read_size, int consumer,
                                                                               void* out, int64_t* status) {
@@ -159,7 +162,7 @@ __global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) buffer_reader_kernel(co
 // Persistent batch reader: blocks take units in order from one device counter; a block
 // keeps its descriptor and its partial checksum/histogram while consecutive units belong
 // to the same file, and adds them into that file's output row when it moves on.
-__global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) batch_reader_kernel(const gfs_dev* d, const gfs_unit* units, uint64_t nunits,
+__global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS, 2) batch_reader_kernel(const gfs_dev* d, const gfs_unit* units, uint64_t nunits,
                                     uint64_t* counter, uint8_t* buf, uint64_t unit_bytes,
                                     uint64_t* csum, uint32_t* hist, int64_t* status) {
   __shared__ uint32_t lhist[256];

@@ -203,7 +203,7 @@ __device__ int pick_unit(SrvCtrl* ctl, SrvEntry* tab, uint32_t cap, const SrvSub
   }
 }
 
-__global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS) serve_kernel(const gfs_dev* d, SrvEntry* tab, uint32_t cap, SrvCtrl* ctl, const SrvSub* subs,
+__global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS, 2) serve_kernel(const gfs_dev* d, SrvEntry* tab, uint32_t cap, SrvCtrl* ctl, const SrvSub* subs,
                              SrvHost* host, SrvDone* done, uint8_t* buf, uint64_t chunk, uint64_t idle_ticks,
                              int64_t* status) {
   __shared__ uint64_t red[16];

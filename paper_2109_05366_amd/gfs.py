@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgfs.so")
 
-GFS_ABI_VERSION = 3
+GFS_ABI_VERSION = 4
 GFS_O_RDONLY = 0
 GFS_ADV_NORMAL, GFS_ADV_RANDOM, GFS_ADV_SEQUENTIAL = 0, 1, 2
 GFS_DIRECT_OFF, GFS_DIRECT_ON, GFS_DIRECT_PREFER = 0, 1, 2
@@ -55,7 +55,7 @@ _STAT_U64 = ["hits", "joins", "misses", "ra_pages", "fetched_pages", "evictions"
 class gfs_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in _STAT_U64] + [
         ("host_spins", C.c_uint64 * 64), ("host_threads", C.c_uint32), ("direct_io", C.c_uint32),
-        ("host_thread_requests", C.c_uint64 * 64)]
+        ("host_thread_requests", C.c_uint64 * 64), ("ra_async_windows", C.c_uint64)]
 
 
 UNIT_DTYPE = np.dtype([("file", "<u4"), ("out", "<u4"), ("offset", "<u8"), ("size", "<u8")])
@@ -178,6 +178,7 @@ def gfs_stats_read(ctx: int) -> Dict[str, object]:
     out["host_spins"] = [int(x) for x in s.host_spins[: s.host_threads]]
     out["host_thread_requests"] = [int(x) for x in s.host_thread_requests[: s.host_threads]]
     out["direct_io"] = int(s.direct_io)
+    out["ra_async_windows"] = int(s.ra_async_windows)
     return out
 
 

@@ -50,13 +50,16 @@ def decode(ev: np.ndarray):
             out.append(("REQ", f, p, a))
         elif op == 7:
             out.append(("NOFRAME", blk, f, p))
+        elif op == 9:
+            out.append(("ADV", blk, f, p, b, a))
         else:
             raise ValueError(f"unknown trace op {op}")
     return out
 
 
 def canon(events):
-    """Order-insensitive within one miss: hand visits by ticket, allocations by page."""
+    """Order-insensitive within one miss (or asynchronous window): hand visits by ticket,
+    allocations by page."""
     out = []
     seg = None
 
@@ -72,7 +75,7 @@ def canon(events):
         if k in ("HIT", "JOIN"):
             flush()
             out.append(e)
-        elif k == "MISS":
+        elif k in ("MISS", "ADV"):
             flush()
             seg = [e, [], [], [], None]
         elif k == "HAND":

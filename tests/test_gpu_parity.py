@@ -122,6 +122,62 @@ def test_serialized_trace_matches_model(name, ra_pages, det, quota, data_dir, cu
     _compare_traces(ev, model, st)
 
 
+@pytest.mark.parametrize("name,ra_pages", [
+    ("c1_small", 8), ("c3a_small", 16), ("c3b_small", 8), ("c2_small", 16), ("c3c_small", 8),
+])
+def test_async_serialized_trace_matches_model(name, ra_pages, data_dir, cuda):
+    """Asynchronous (marker-triggered) readahead, one access at a time: every marker taken,
+    every window the stream advances to, and the rest of the trace equal the model's."""
+    wl = configs.get(name)
+    path = configs.ensure_file(wl.file, data_dir)
+    _say(f"serialized async {name} ra_pages={ra_pages}")
+    cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=ra_pages * wl.page_size,
+                             ra_init_pages=4, streams=8, trace_level=2, trace_capacity=1 << 20,
+                             timeout_s=20, quota_blocks=1, ra_async=1)
+    with gfs.PageCache(cfg) as cache:
+        fid = cache.open(path)
+        res = runner.run_list(cache, fid, wl.offsets, wl.read_size, wl.consumer, serialize=True)
+        st = cache.stats()
+        ev = cache.trace()
+    assert st["trace_events"] == len(ev) < (1 << 20)
+    exp_out, exp_deliv = expected(wl, path)
+    np.testing.assert_array_equal(res.status, exp_deliv)
+    np.testing.assert_array_equal(res.out, exp_out)
+    C = wl.cache_bytes // wl.page_size
+    model = PolicyModel(C, wl.page_size, ra_init_pages=min(4, ra_pages), ra_cap_pages=ra_pages,
+                        streams_per_file=8, ra_async=True)
+    model.open(fid, wl.file.size)
+    run_serialized(model, fid, wl.offsets, wl.read_size)
+    _compare_traces(ev, model, st)
+    assert st["ra_async_windows"] == model.advances
+    assert st["joins"] == model.joins
+
+
+@pytest.mark.parametrize("name,ra_pages", [("c2_small", 16), ("c3a_small", 16), ("c3b_small", 8),
+                                           ("c3c_small", 8), ("c1_small", 8)])
+def test_async_readahead_data(name, ra_pages, data_dir, cuda):
+    """Asynchronous readahead with every block running at once: the delivered data equal the
+    oracle's, windows were issued at markers, and every block finished its last one."""
+    wl = configs.get(name)
+    path = configs.ensure_file(wl.file, data_dir)
+    exp_out, exp_deliv = expected(wl, path)
+    _say(f"async data {name} ra_pages={ra_pages}")
+    cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=ra_pages * wl.page_size, timeout_s=20,
+                             ra_async=1)
+    with gfs.PageCache(cfg) as cache:
+        fid = cache.open(path)
+        for rep in range(2):   # cold, then with whatever the first pass left cached
+            res = runner.run_list(cache, fid, wl.offsets, wl.read_size, wl.consumer)
+            st = cache.stats()
+            assert st["timeouts"] == 0 and st["io_errors"] == 0, st
+            np.testing.assert_array_equal(res.status, exp_deliv)
+            np.testing.assert_array_equal(res.out, exp_out)
+        # every request was read by the host and every frame published: nothing is left filling
+        assert st["host_requests"] == st["requests"]
+    if name in ("c3a_small", "c1_small"):
+        assert st["ra_async_windows"] > 0
+
+
 def _compare_traces(ev, model, st):
     """The device trace equals the model's event sequence (hand visits with what they found),
     and every miss logged the model's detector inputs and rule."""

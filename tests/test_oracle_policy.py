@@ -293,3 +293,94 @@ def test_request_is_the_unmapped_run_around_the_miss():
     m.gread(0, 0, 5 * 4096, 4096)                  # page 5: probation window of 1
     m.gread(0, 0, 0, 4096)                         # page 0: W0 = 8 -> [0, 8), run stops at 5
     assert [e for e in m.events if e[0] == "REQ"][-1] == ("REQ", 0, 0, 5)
+
+
+# ---- asynchronous (marker-triggered) readahead ---------------------------------------------------
+
+def _async_closed_form(npages, W0, cap):
+    """Linux-style asynchronous readahead on one stream read page by page from offset 0, in
+    closed form (Sec. 2.3): the demand miss at page 0 fetches [0, W0) and marks page 1; each
+    marker triggers the next window, twice the last one up to the cap, starting where the last
+    one ended, whose first page is the next marker. Returns the (trigger page, start, length)
+    of every asynchronous window, lengths cut at the end of the file. (W0 >= 2: a first
+    window of one page has no page after the demanded one to mark.)"""
+    out = []
+    start, size, trigger = W0, min(2 * W0, cap), 1
+    while True:
+        out.append((trigger, start, max(0, min(size, npages - start))))
+        if start >= npages:
+            return out
+        trigger, start, size = start, start + size, min(2 * size, cap)
+
+
+@pytest.mark.parametrize("npages,W0,cap", [(100, 4, 16), (37, 2, 8), (5, 4, 4), (64, 2, 64)])
+def test_async_single_stream_closed_form(npages, W0, cap):
+    m = PolicyModel(nframes=256, page_size=1 << 16, ra_init_pages=W0, ra_cap_pages=cap, ra_async=True)
+    m.open(0, npages << 16)
+    for p in range(npages):
+        m.gread(0, 0, p << 16, 1 << 16)
+    adv = [(e[3], e[4], e[5]) for e in m.events if e[0] == "ADV"]
+    assert adv == _async_closed_form(npages, W0, cap)
+    # one demand miss; every later page was fetched ahead of its reader and hit
+    assert m.misses == 1 and m.hits == npages - 1 and m.joins == 0
+    assert m.fetched_pages == npages and m.wasted_pages == 0
+    reqs = [e for e in m.events if e[0] == "REQ"]
+    assert reqs[0] == ("REQ", 0, 0, min(W0, npages))
+    assert [(e[2], e[3]) for e in reqs[1:]] == [(s, n) for _, s, n in adv if n > 0]
+    m.check_invariants()
+
+
+def test_async_window_runs_ahead_of_synchronous():
+    # the same stream: synchronous readahead waits at the start of every window (a miss
+    # each), asynchronous readahead only at page 0
+    npages, W0, cap = 200, 4, 16
+    counts = {}
+    for mode in (False, True):
+        m = PolicyModel(nframes=512, page_size=4096, ra_init_pages=W0, ra_cap_pages=cap, ra_async=mode)
+        m.open(0, npages * 4096)
+        for p in range(npages):
+            m.gread(0, 0, p * 4096, 4096)
+        counts[mode] = (m.misses, m.requests, m.fetched_pages)
+    sync_windows = 1 + (npages - W0 - 8 - 16 + 15) // 16 + 2   # 4, 8, 16, 16, ...
+    assert counts[False][0] == counts[False][1] == sync_windows
+    assert counts[True][0] == 1 and counts[True][2] == counts[False][2] == npages
+
+
+def test_async_large_read_joins_its_own_window():
+    # one block reading 32 pages at a time: a read reaches the window it triggered earlier in
+    # the same read, joins its frames (they are still being filled) and triggers the next
+    m = PolicyModel(nframes=512, page_size=1 << 16, ra_init_pages=4, ra_cap_pages=16, ra_async=True)
+    m.open(0, 96 << 16)
+    for k in range(3):
+        m.gread(0, 0, (32 * k) << 16, 32 << 16)
+    ev = [e for e in m.events if e[0] in ("MISS", "ADV", "JOIN")]
+    assert ev[:4] == [("MISS", 0, 0, 0, 0, 4), ("ADV", 0, 0, 1, 4, 8), ("JOIN", 0, 0, 4, ev[2][4]),
+                      ("ADV", 0, 0, 4, 12, 16)]
+    # a read joins only the first page of a window it triggered itself (4, 12, 28 in the first
+    # read, whose last window [44, 60) arrives when it ends; 60 and 92 in the later reads);
+    # all 96 pages delivered, none wasted
+    joins = [e[3] for e in m.events if e[0] == "JOIN"]
+    assert joins == [4, 12, 28, 60, 92]
+    assert m.misses == 1 and m.fetched_pages == 96 and m.wasted_pages == 0
+    m.check_invariants()
+
+
+def test_async_marker_dropped_with_its_stream():
+    # one stream slot: a second reader's miss takes the slot, so the first stream's marker page
+    # no longer names any stream and its access advances nothing
+    m = PolicyModel(nframes=256, page_size=4096, ra_init_pages=4, ra_cap_pages=8, streams_per_file=1,
+                    ra_async=True)
+    m.open(0, 1000 * 4096)
+    m.gread(0, 0, 0, 4096)              # stream at 0: window [0, 4), marker 1
+    m.gread(1, 0, 500 * 4096, 4096)     # new stream at 500 takes the only slot
+    m.gread(0, 0, 4096, 4096)           # page 1: marked, but no stream names it
+    assert [e for e in m.events if e[0] == "ADV"] == []
+    assert m.frames[m.map[(0, 1)]].mark == 0
+
+
+def test_async_off_by_default_and_random_advice():
+    m = PolicyModel(nframes=256, page_size=4096, ra_init_pages=4, ra_cap_pages=8, ra_async=True)
+    m.open(0, 100 * 4096, advice="random")
+    for p in range(20):
+        m.gread(0, 0, p * 4096, 4096)
+    assert m.advances == 0 and m.misses == 20 and m.fetched_pages == 20
