@@ -650,7 +650,7 @@ def bench_hits(args, torch) -> int:
 def bench_small_pages(args, torch) -> int:
     """Small-page regime: the same strided reads of a 1 GiB file with 4 KiB pages and a
     64 KiB readahead window (growing from 4 pages, or opened at 64 KiB like the paper's
-    static prefetch), 4 KiB pages with a 256 KiB window, 4 KiB pages without readahead,
+    static prefetch, or asynchronous), 4 KiB pages with a 256 KiB window, 4 KiB pages without readahead,
     64 KiB pages without readahead, and 64 KiB pages with a 16 MiB window; cold per
     pass."""
     import numpy as np
@@ -666,6 +666,7 @@ def bench_small_pages(args, torch) -> int:
     # (name, page, cap, first window in pages); "static" opens every window at the cap,
     # as the paper's fixed PREFETCH_SIZE does (Sec. 4.1)
     variants = [("p4k_ra64k", 4 << 10, 64 << 10, 4), ("p4k_ra64k_static", 4 << 10, 64 << 10, 16),
+                ("p4k_ra64k_async", 4 << 10, 64 << 10, 4),
                 ("p4k_ra256k", 4 << 10, 256 << 10, 4), ("p4k_none", 4 << 10, 0, 4),
                 ("p64k_none", 64 << 10, 0, 4), ("p64k_ra16m", 64 << 10, 16 << 20, 4)]
     out = {}
@@ -673,7 +674,8 @@ def bench_small_pages(args, torch) -> int:
     want = odata.block_checksums(path, wl.offsets, wl.read_size, blocks=sample)
     for name, page, cap, w0 in variants:
         cfg = runner.make_config(page, wl.cache_bytes, ra_cap_bytes=cap, ra_init_pages=w0,
-                                 host_threads=args.host_threads, rpc_slots=args.rpc_slots, timeout_s=60)
+                                 host_threads=args.host_threads, rpc_slots=args.rpc_slots, timeout_s=60,
+                                 ra_async=1 if name.endswith("_async") else 0)
         with gfs.PageCache(cfg) as cache:
             fid = cache.open(path)
             reader = runner.ListReader(wl.offsets, wl.read_size, wl.consumer, wl.threads)

@@ -68,6 +68,9 @@ struct BlockState {
   uint32_t list_n;          /* pages in list[] that got frames (a prefix) */
   uint32_t file;
   int32_t open_result;
+  int32_t open_fd;          /* the descriptor gopen returned last (-1: none), and its file's */
+  uint64_t open_size;       /* size, read once: a registered file cannot be closed while a
+                               kernel holds it open, so gread need not read them again */
   uint64_t ctr[GFS_C_COUNT];    /* block-local statistics, added to the globals by gclose */
   uint32_t list[kMaxWindow];    /* run pages: the demanded page, then the rest ascending */
   uint32_t lframe[kMaxWindow];  /* frame given to list[k], or GFS_NO_FRAME */
@@ -1210,6 +1213,207 @@ __device__ int miss_private_wave(const gfs_dev* d, uint32_t file, uint64_t p, ui
   return 0;
 }
 
+/* Wave 0, after the run's pages got frames (bs->list/lframe[0..got), the demanded page first):
+ * post one request for the span of those pages, tell blocks waiting on its frames which request
+ * fills them, wait for the host, and publish the finished read for the helpers. Leaves in bs:
+ * status, the demanded page's frame, pull = 1 (this block pulls the request). Returns 0. */
+__device__ int post_wait_wave(const gfs_dev* d, uint32_t file, uint64_t fsize, BlockState* bs, uint32_t bid,
+                              uint64_t t0, uint32_t got) {
+  const uint32_t l = lane();
+  /* span of the pages that got frames: p and a contiguous piece of the run */
+  uint64_t lo = ~0ull, hi = 0;
+  for (uint32_t k = l; k < got; k += 64) {
+    const uint64_t q = bs->list[k];
+    lo = q < lo ? q : lo;
+    hi = q > hi ? q : hi;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t olo = __shfl_xor(lo, off, 64), ohi = __shfl_xor(hi, off, 64);
+    lo = olo < lo ? olo : lo;
+    hi = ohi > hi ? ohi : hi;
+  }
+  /* post the request for the span [lo, hi] and wait for the host */
+  const uint32_t span = (uint32_t)(hi - lo + 1);
+  const uint64_t off0 = lo << d->page_shift;
+  uint64_t len = (uint64_t)span << d->page_shift;
+  if (off0 + len > fsize) len = fsize - off0;
+  int64_t status = 0;
+  uint64_t tk = 0;
+  if (l == 0) {
+    ring_ticket_lane(d, bid, tk);
+    const uint32_t s = ring_slot(d, bid, tk);
+    const uint64_t gen = ring_gen(d, tk);
+    uint32_t nn = 0;
+    const uint64_t ts0 = wall_clock64();
+    while (ld_rlx(&d->slot_free[s]) != gen - 1) {
+      if (expired(d, t0)) {
+        status = -kETIMEDOUT;
+        break;
+      }
+      nap(nn);
+    }
+    acquire_agent();   /* the slot's last users are done with its staging */
+    bcount(bs, GFS_T_SLOT, wall_clock64() - ts0);
+    if (status == 0) {
+      gfs_rpc_slot* rs = &d->ring[s];
+      rs->file_id = file;
+      rs->npages = span;
+      rs->offset = off0;
+      rs->length = len;
+      rs->ticket = tk;
+      __hip_atomic_store(&rs->req_seq, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      trace_ev(d, 1, GFS_EV_REQ, bid, file, (uint32_t)lo, GFS_NO_FRAME, span, tk);
+      bcount(bs, GFS_C_MISSES, 1);
+      bcount(bs, GFS_C_REQUESTS, 1);
+      bcount(bs, GFS_C_REQ_BYTES, len);
+      bcount(bs, GFS_C_FETCHED, got);
+      bcount(bs, GFS_C_RA_PAGES, got - 1);
+    }
+  }
+  status = __shfl(status, 0, 64);
+  tk = __shfl(tk, 0, 64);
+  const uint32_t s = ring_slot(d, bid, tk);
+  const uint64_t gen = ring_gen(d, tk);
+  if (status == 0) {
+    /* tell waiting blocks which request fills each frame: (slot + 1) << 40 | gen */
+    const uint64_t fill = ((uint64_t)(s + 1) << 40) | (gen & ((1ull << 40) - 1));
+    for (uint32_t k = l; k < got; k += 64) st_rel(&d->ffill[bs->lframe[k]], fill);
+  }
+  if (l == 0) {
+    if (status == 0) {
+      gfs_rpc_slot* rs = &d->ring[s];
+      uint32_t nn = 0;
+      const uint64_t th0 = wall_clock64();
+      while (__hip_atomic_load(&rs->done_seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) !=
+             gen) {
+        if (expired(d, t0)) {
+          status = -kETIMEDOUT;
+          break;
+        }
+        nap(nn);
+      }
+      acquire_system();   /* the staged bytes, written by the host before done_seq */
+      bcount(bs, GFS_T_HOST, wall_clock64() - th0);
+      if (status == 0) {
+        bs->result = rs->result;
+        /* let blocks waiting on frames of this request pull their own pages */
+        gfs_req_dev* rq = &d->reqd[s];
+        rq->result = bs->result;
+        rq->first_page = lo;
+        rq->file = file;
+        __hip_atomic_store(&rq->remaining, got, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st_rel(&rq->ready, gen);
+      }
+    }
+    if (status) bcount(bs, GFS_C_TIMEOUTS, 1);
+    bs->status = status;
+    bs->frame = (int32_t)bs->lframe[0];
+    bs->pull = status == 0 ? 1 : 0;
+    bs->slot = s;
+    bs->gen = gen;
+    bs->first_page = lo;
+    bs->list_n = got;
+    bs->file = file;
+  }
+  return 0;
+}
+
+/* Wave-collective, without the miss lock: reserve the table entry of key if no entry for it
+ * exists, so that one block alone fetches the page. Lanes 0-31 load the key's two buckets; lane
+ * 0 takes a free entry of the less loaded bucket by compare-and-swap; once that swap has been
+ * performed the lanes look again, and if another block's entry for the same key is there the
+ * reservation is withdrawn. Of two blocks that reserve one key at once, the later swap sees the
+ * earlier one, so at most one reservation stays (both may withdraw; both then look again).
+ * Returns the entry's index, -1 when the key has (or just got) another entry, -2 when both
+ * buckets stayed full. */
+__device__ int64_t reserve_unique_wave(const gfs_dev* d, uint64_t key) {
+  uint32_t b1, b2;
+  key_buckets(d, key, b1, b2);
+  const uint32_t l = lane();
+  const uint64_t ent = (key << GFS_ENTRY_FRAME_BITS) | kReserved;
+  for (int attempt = 0; attempt < 64; ++attempt) {
+    uint64_t e = 0;
+    if (l < 32) e = ld_rlx(slot_ptr(d, b1, b2, (int)l));
+    if (__ballot(l < 32 && (e >> GFS_ENTRY_FRAME_BITS) == key)) return -1;
+    const uint64_t free1 = __ballot(l < 16 && e == 0), free2 = __ballot(l >= 16 && l < 32 && e == 0);
+    const uint32_t used1 = 16u - (uint32_t)__popcll(free1), used2 = 16u - (uint32_t)__popcll(free2);
+    uint64_t fm = used2 < used1 ? free2 : free1;   /* less loaded bucket, ties to the first */
+    if (fm == 0) fm = free1 ? free1 : free2;
+    if (fm == 0) return -2;
+    const int pick = __builtin_ctzll(fm);
+    uint64_t* sp = slot_ptr(d, b1, b2, pick);
+    int won = 0;
+    if (l == 0) {
+      uint64_t z = 0;
+      won = cas64_rlx(sp, z, ent) ? 1 : 0;
+    }
+    won = __shfl(won, 0, 64);
+    if (!won) continue;   /* the entry was taken meanwhile: look again */
+    drain_atomics();      /* the swap is performed before the second look goes out */
+    uint64_t e2 = 0;
+    if (l < 32 && (int)l != pick) e2 = ld_rlx(slot_ptr(d, b1, b2, (int)l));
+    if (__ballot(l < 32 && (int)l != pick && (e2 >> GFS_ENTRY_FRAME_BITS) == key)) {
+      if (l == 0) {
+        uint64_t x = ent;
+        (void)cas64_rlx(sp, x, 0ull);
+      }
+      return -1;
+    }
+    return (int64_t)(sp - d->pt);
+  }
+  return -2;
+}
+
+/* Wave 0: the miss path of a file whose windows are one page (readahead off, or RANDOM advice):
+ * no detector decision to make, so no miss lock; the page's reservation is made unique by
+ * reserve_unique_wave. Same results and trace events as the locked path for such a file.
+ * Returns as miss_shared_wave. */
+__device__ int miss_one_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint64_t key, uint64_t fsize,
+                                  BlockState* bs, uint32_t bid, uint64_t t0, uint32_t& naps) {
+  const uint32_t l = lane();
+  const uint64_t tr0 = wall_clock64();
+  const int64_t slot = reserve_unique_wave(d, key);
+  if (slot == -1) return 1;   /* another block's entry: go to the pin path */
+  if (slot < 0) {
+    /* both buckets full of other misses' reservations: back off; -ENOSPC at the wait limit */
+    if (!expired(d, t0)) {
+      if (l == 0) {
+        bcount(bs, GFS_C_RETRIES, 1);
+        nap(naps);
+      }
+      return 1;
+    }
+    if (l == 0) {
+      bs->status = -kENOSPC;
+      bs->pull = 0;
+      bs->frame = -1;
+    }
+    return 0;
+  }
+  if (l == 0) {
+    trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, (uint32_t)RA_RULE_OFF << 24, 1, p);
+    bs->list[0] = (uint32_t)p;
+    bs->lslot[0] = (uint32_t)slot;
+    bs->lframe[0] = GFS_NO_FRAME;
+  }
+  wave_sync_lds();
+  const uint64_t tl3 = wall_clock64();
+  if (l == 0) bcount(bs, GFS_T_RUN, tl3 - tr0);
+  const uint32_t got = alloc_wave(d, file, p, bs, 1, bid);
+  if (l == 0) bcount(bs, GFS_T_ALLOC, wall_clock64() - tl3);
+  if (got == 0) {
+    /* every frame pinned or filling: give the page back and retry the access */
+    if (l == 0) {
+      st_rel(d->pt + slot, 0ull);
+      bcount(bs, GFS_C_NOFRAME, 1);
+    }
+    if (expired(d, t0)) return 2;
+    if (l == 0) nap(naps);
+    return 1;
+  }
+  return post_wait_wave(d, file, fsize, bs, bid, t0, 1);
+}
+
 /* Wave 0: the shared policy's miss path for page p of `file` (key), found absent from the
  * table: take the file's miss lock, decide and claim the window, reserve and allocate its
  * run, post the request and wait for the host. Out of line: it runs once per host request
@@ -1219,6 +1423,8 @@ __device__ int miss_private_wave(const gfs_dev* d, uint32_t file, uint64_t p, ui
 __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint32_t file, uint64_t p,
                                                           uint64_t key, uint64_t fsize, BlockState* bs,
                                                           uint32_t bid, uint64_t t0, uint32_t& naps) {
+  if (d->ra_cap == 0 || ld_rlx32(&d->files[file].advice) == GFS_ADV_RANDOM)
+    return miss_one_page_wave(d, file, p, key, fsize, bs, bid, t0, naps);
   const uint32_t l = lane();
   const uint64_t tl0 = wall_clock64();
   uint64_t ticket;
@@ -1402,102 +1608,7 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
   }
   if (got < n && l == 0)
     trace_ev(d, 1, GFS_EV_NOFRAME, bid, file, bs->list[got], GFS_NO_FRAME, 0, 0);
-  /* span of the pages that got frames: p and a contiguous piece of the run */
-  uint64_t lo = ~0ull, hi = 0;
-  for (uint32_t k = l; k < got; k += 64) {
-    const uint64_t q = bs->list[k];
-    lo = q < lo ? q : lo;
-    hi = q > hi ? q : hi;
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint64_t olo = __shfl_xor(lo, off, 64), ohi = __shfl_xor(hi, off, 64);
-    lo = olo < lo ? olo : lo;
-    hi = ohi > hi ? ohi : hi;
-  }
-  /* post the request for the span [lo, hi] and wait for the host */
-  const uint32_t span = (uint32_t)(hi - lo + 1);
-  const uint64_t off0 = lo << d->page_shift;
-  uint64_t len = (uint64_t)span << d->page_shift;
-  if (off0 + len > fsize) len = fsize - off0;
-  int64_t status = 0;
-  uint64_t tk = 0;
-  if (l == 0) {
-    ring_ticket_lane(d, bid, tk);
-    const uint32_t s = ring_slot(d, bid, tk);
-    const uint64_t gen = ring_gen(d, tk);
-    uint32_t nn = 0;
-    const uint64_t ts0 = wall_clock64();
-    while (ld_rlx(&d->slot_free[s]) != gen - 1) {
-      if (expired(d, t0)) {
-        status = -kETIMEDOUT;
-        break;
-      }
-      nap(nn);
-    }
-    acquire_agent();   /* the slot's last users are done with its staging */
-    bcount(bs, GFS_T_SLOT, wall_clock64() - ts0);
-    if (status == 0) {
-      gfs_rpc_slot* rs = &d->ring[s];
-      rs->file_id = file;
-      rs->npages = span;
-      rs->offset = off0;
-      rs->length = len;
-      rs->ticket = tk;
-      __hip_atomic_store(&rs->req_seq, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-      trace_ev(d, 1, GFS_EV_REQ, bid, file, (uint32_t)lo, GFS_NO_FRAME, span, tk);
-      bcount(bs, GFS_C_MISSES, 1);
-      bcount(bs, GFS_C_REQUESTS, 1);
-      bcount(bs, GFS_C_REQ_BYTES, len);
-      bcount(bs, GFS_C_FETCHED, got);
-      bcount(bs, GFS_C_RA_PAGES, got - 1);
-    }
-  }
-  status = __shfl(status, 0, 64);
-  tk = __shfl(tk, 0, 64);
-  const uint32_t s = ring_slot(d, bid, tk);
-  const uint64_t gen = ring_gen(d, tk);
-  if (status == 0) {
-    /* tell waiting blocks which request fills each frame: (slot + 1) << 40 | gen */
-    const uint64_t fill = ((uint64_t)(s + 1) << 40) | (gen & ((1ull << 40) - 1));
-    for (uint32_t k = l; k < got; k += 64) st_rel(&d->ffill[bs->lframe[k]], fill);
-  }
-  if (l == 0) {
-    if (status == 0) {
-      gfs_rpc_slot* rs = &d->ring[s];
-      uint32_t nn = 0;
-      const uint64_t th0 = wall_clock64();
-      while (__hip_atomic_load(&rs->done_seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) !=
-             gen) {
-        if (expired(d, t0)) {
-          status = -kETIMEDOUT;
-          break;
-        }
-        nap(nn);
-      }
-      acquire_system();   /* the staged bytes, written by the host before done_seq */
-      bcount(bs, GFS_T_HOST, wall_clock64() - th0);
-      if (status == 0) {
-        bs->result = rs->result;
-        /* let blocks waiting on frames of this request pull their own pages */
-        gfs_req_dev* rq = &d->reqd[s];
-        rq->result = bs->result;
-        rq->first_page = lo;
-        rq->file = file;
-        __hip_atomic_store(&rq->remaining, got, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        st_rel(&rq->ready, gen);
-      }
-    }
-    if (status) bcount(bs, GFS_C_TIMEOUTS, 1);
-    bs->status = status;
-    bs->frame = (int32_t)bs->lframe[0];
-    bs->pull = status == 0 ? 1 : 0;
-    bs->slot = s;
-    bs->gen = gen;
-    bs->first_page = lo;
-    bs->list_n = got;
-    bs->file = file;
-  }
-  return 0;
+  return post_wait_wave(d, file, fsize, bs, bid, t0, got);
 }
 
 /* ------------------------------------------------------------------ one page, wave 0
@@ -2089,6 +2200,8 @@ __device__ int gopen_id(const gfs_dev* d, int file_id, int flags) {
     bs->trig = 0;
     bs->a_pending = 0;   /* an asynchronous request is finished by gclose, before the next gopen */
     bs->open_result = v;
+    bs->open_fd = v;
+    bs->open_size = v >= 0 ? d->files[v].size : 0;
   }
   __syncthreads();
   const int v = bs->open_result;
@@ -2137,6 +2250,7 @@ __device__ int gclose(const gfs_dev* d, int fd) {
       if (bs->ctr[c]) gfsd::fadd64(&d->g->ctr[c], bs->ctr[c]);
       bs->ctr[c] = 0;
     }
+    bs->open_fd = -1;
   }
   __syncthreads();
   return 0;
@@ -2147,11 +2261,16 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
   using namespace gfsd;
   BlockState* bs = block_state();
   if (fd < 0 || (uint32_t)fd >= d->max_files) return -kEBADF;
-  gfs_file_dev* fe = &d->files[fd];
-  if (ld_rlx32(&fe->open) == 0) return -kEBADF;
+  uint64_t fsize;
+  if (fd == bs->open_fd) {
+    fsize = bs->open_size;   /* checked by gopen */
+  } else {
+    gfs_file_dev* fe = &d->files[fd];
+    if (ld_rlx32(&fe->open) == 0) return -kEBADF;
+    fsize = fe->size;
+  }
   const uint32_t nt = block_threads();
   if (nt & 63u) return -kEINVAL;
-  const uint64_t fsize = fe->size;
   if (size == 0 || offset >= fsize) return 0;
   const uint64_t end = (size > fsize - offset) ? fsize : offset + size;
   const uint32_t tid = thread_id();

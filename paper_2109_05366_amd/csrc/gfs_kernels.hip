@@ -49,6 +49,7 @@ __global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS, 2) list_reader_kernel(c
   __shared__ uint32_t hist[256];
   __shared__ uint64_t red[16];
   __shared__ int gate_err;
+  __shared__ uint64_t offs[64];   /* the block's next read offsets, fetched 64 at a time */
   const uint32_t b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   uint8_t* mybuf = buf + (uint64_t)b * read_size;
   if (consumer == 1)
@@ -60,6 +61,12 @@ __global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS, 2) list_reader_kernel(c
   uint64_t csum = 0;
   const uint64_t t0 = wall_clock64();
   for (uint32_t k = 0; k < reads && err == 0; ++k) {
+    if ((k & 63) == 0) {
+      // one round trip for the next 64 offsets instead of one before every read (every thread
+      // has passed gread's barriers since it read the previous ones)
+      if (tid < 64 && k + tid < reads) offs[tid] = offsets[(uint64_t)b * reads + k + tid];
+      __syncthreads();
+    }
     const uint64_t my_turn = (uint64_t)k * gridDim.x + b;
     if (turn) {
       if (tid == 0) {
@@ -80,7 +87,7 @@ __global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS, 2) list_reader_kernel(c
         break;
       }
     }
-    const int64_t r = gread(d, fd, offsets[(uint64_t)b * reads + k], read_size, mybuf);
+    const int64_t r = gread(d, fd, offs[k & 63], read_size, mybuf);
     // serialized runs: an asynchronous window this read issued is in place before the next
     // block's turn, so that every access sees the cache the one-at-a-time order implies
     if (turn) (void)gfsd::async_finish_block(d, gfsd::block_state());
