@@ -325,6 +325,10 @@ def cpu_io_comparator(torch, gfs, wl, path, want):
                     "kernel over the device copy"}
 
 
+# the thrash guard's resident-block count for every list pass (--quota-blocks; 0: the device's)
+QUOTA_BLOCKS = 0
+
+
 def list_passes(torch, gfs, runner, wl, path, cap_bytes, steps, warmup, host_threads, rpc_slots, io_chunk,
                 want=None, policy=None, private_slots=512, advice="normal", ra_async=0):
     """Cold passes of a list workload with readahead at cap_bytes (0: off; ra_async 1: the
@@ -334,7 +338,7 @@ def list_passes(torch, gfs, runner, wl, path, cap_bytes, steps, warmup, host_thr
     cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=cap_bytes, host_threads=host_threads,
                              rpc_slots=rpc_slots, timeout_s=60, io_chunk_bytes=io_chunk,
                              policy=gfs.GFS_POLICY_SHARED if policy is None else policy,
-                             private_slots=private_slots, ra_async=ra_async)
+                             private_slots=private_slots, ra_async=ra_async, quota_blocks=QUOTA_BLOCKS)
     with gfs.PageCache(cfg) as cache:
         fid = cache.open(path)
         if advice != "normal":
@@ -647,6 +651,76 @@ def bench_hits(args, torch) -> int:
     return 0
 
 
+def bench_mixed(args, torch) -> int:
+    """f2, the mixed case (Sec. 3.1: one file read in order, another at random) through one
+    persistent launch: 2 GiB in 1 MiB pieces beside 32768 random 64 KiB page reads of another
+    2 GiB file, 1 GiB cache; cold passes with readahead and no hints, with the paper's remedy
+    (Sec. 4.1: SEQUENTIAL for the first file, RANDOM for the second), with RANDOM on the random
+    file only, and with readahead off; both output rows compared with the oracle each pass."""
+    import numpy as np
+
+    from oracle import data as odata
+    from paper_2109_05366_amd import gfs, runner
+    from workloads import configs
+    wl = configs.f2()
+    ddir = args.data_dir or os.environ.get("GFS_DATA_DIR") or configs.data_dir()
+    pa, pb = configs.ensure_file(wl.seq, ddir), configs.ensure_file(wl.rnd, ddir)
+    units = wl.units()
+    t = time.perf_counter()
+    want_c, want_h = odata.unit_outputs({0: pa, 1: pb}, units, 2)
+    log(f"f2: oracle over {len(units)} reads ({time.perf_counter() - t:.1f} s)")
+    delivered = int(units["size"].sum())
+    adv = {"normal": gfs.GFS_ADV_NORMAL, "sequential": gfs.GFS_ADV_SEQUENTIAL, "random": gfs.GFS_ADV_RANDOM}
+    variants = [("no_hints", 16 << 20, ("normal", "normal")), ("hints", 16 << 20, ("sequential", "random")),
+                ("random_hint", 16 << 20, ("normal", "random")), ("readahead_off", 0, ("normal", "normal"))]
+    out = {}
+    for name, cap, advice in variants:
+        cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=cap, host_threads=args.host_threads,
+                                 rpc_slots=args.rpc_slots, timeout_s=60, io_chunk_bytes=args.io_chunk_kib << 10)
+        rates = []
+        with gfs.PageCache(cfg) as cache:
+            ids = [cache.open(pa), cache.open(pb)]
+            for i, a in enumerate(advice):
+                cache.fadvise(ids[i], adv[a])
+            u = units.copy()
+            u["file"] = np.array(ids, dtype=np.uint32)[units["file"]]
+            rd = runner.BatchReader(None, None, wl.piece, 1, units=u, nout=2)
+            for step in range(args.warmup + args.steps):
+                cache.reset()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rd.launch(cache)
+                res = rd.result()
+                wall = time.perf_counter() - t0
+                st = cache.stats()
+                if st["timeouts"] or st["io_errors"] or int(res.status.sum()) != delivered:
+                    raise RuntimeError(f"f2 {name}: device errors or short delivery {st}")
+                if not (np.array_equal(res.csum, want_c) and np.array_equal(res.hist, want_h)):
+                    raise RuntimeError(f"f2 {name}: outputs differ from the oracle")
+                if step >= args.warmup:
+                    rates.append(delivered / wall / 1e9)
+        out[name] = {"GBps": round(float(np.mean(rates)), 3), "requests": st["requests"],
+                     "request_bytes": st["request_bytes"], "ra_pages": st["ra_pages"],
+                     "wasted_pages": st["wasted_pages"], "advice": list(advice), "ra_cap_MiB": cap >> 20}
+        log(f"f2 {name}: {out[name]}")
+    value = out["hints"]["GBps"]
+    line = {
+        "metric": "delivered file-read GB/s (readahead vs none) + fraction of min(NVMe, H2D) peak",
+        "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(delivered / value / 1e6, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "f2: 2 GiB splitmix64(seed=5) file in 1 MiB pieces beside 32768 random 64 KiB "
+                               "page reads of a 2 GiB file (seed 6), 1 GiB cache, one persistent launch; "
+                               "value = SEQUENTIAL + RANDOM hints", "data_dir": ddir},
+        "variants": out,
+        "hints_vs_no_hints": round(value / out["no_hints"]["GBps"], 3),
+        "hints_vs_readahead_off": round(value / out["readahead_off"]["GBps"], 3),
+        "parity": "both output rows (checksum and histogram) every pass",
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def bench_small_pages(args, torch) -> int:
     """Small-page regime: the same strided reads of a 1 GiB file with 4 KiB pages and a
     64 KiB readahead window (growing from 4 pages, or opened at 64 KiB like the paper's
@@ -721,10 +795,13 @@ def main() -> int:
     ap.add_argument("--io-chunk-kib", type=int, default=4096,
                     help="size of the pieces a host request is read in (one per free host thread)")
     ap.add_argument("--no-ra-off", action="store_true", help="skip the readahead-off comparison")
+    ap.add_argument("--quota-blocks", type=int, default=0,
+                    help="thrash guard: resident blocks the cache is shared by (0: the device's, 1: no guard)")
     ap.add_argument("--no-ra-async", action="store_true",
                     help="skip the asynchronous (marker-triggered) readahead comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3a", "c3b", "c3c", "c4", "c5", "f3", "f4", "hit"])
+    ap.add_argument("--workload", default="c2",
+                    choices=["c2", "c3a", "c3b", "c3c", "c4", "c5", "f2", "f3", "f4", "hit"])
     ap.add_argument("--no-hit-path", action="store_true")
     ap.add_argument("--no-tmpfs", action="store_true", help="skip the same passes from a tmpfs copy of the file")
     ap.add_argument("--autotune", action="store_true", help="c4: search page size, cap and blocks per file")
@@ -738,6 +815,8 @@ def main() -> int:
     ap.add_argument("--no-extra", action="store_true",
                     help="default line without the extra records (c3a, c3b, c4, c5)")
     args = ap.parse_args()
+    global QUOTA_BLOCKS
+    QUOTA_BLOCKS = args.quota_blocks
     if args.gpus != 1:
         print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); "
               "the path is per-GPU: each GPU would get its own cache, ring and host threads and read its share of the files",
@@ -755,6 +834,8 @@ def main() -> int:
         return bench_batch(args, torch)
     if args.workload == "c5":
         return bench_serve(args, torch)
+    if args.workload == "f2":
+        return bench_mixed(args, torch)
     if args.workload == "f3":
         return bench_small_pages(args, torch)
     if args.workload == "hit":
