@@ -1728,17 +1728,22 @@ __device__ __forceinline__ bool staged_short(const gfs_dev* d, uint64_t q, uint6
 }
 
 /* Wave 0: claim the request's frames that no helping block has taken (PULL bit); their
- * indices go to bs->lslot[0..nclaim). */
-__device__ void claim_pulls_wave(const gfs_dev* d, BlockState* bs) {
+ * indices go to bs->lslot[0..nclaim). A frame counts as the request's only while its fill word
+ * names the request (fill): once helpers have published it, the clock may have given it to
+ * another request, which the caller must not touch. The word is read first (acquire) and the
+ * fill word after it, and the claim is a compare-and-swap against that word, so a frame that
+ * changed hands in between is not claimed. */
+__device__ void claim_pulls_wave(const gfs_dev* d, BlockState* bs, uint64_t fill) {
   const uint32_t l = lane();
   uint32_t nclaim = 0;
   for (uint32_t base = 0; base < bs->list_n; base += 64) {
     const uint32_t k = base + l;
     bool won = false;
     if (k < bs->list_n) {
-      uint64_t* fw = &d->fword[bs->lframe[k]];
-      uint64_t w = ld_rlx(fw);
-      while ((w & GFS_FW_STATE) == GFS_FS_FILLING && !(w & GFS_FW_PULL)) {
+      const uint32_t f = bs->lframe[k];
+      uint64_t* fw = &d->fword[f];
+      uint64_t w = ld_acq(fw);
+      while ((w & GFS_FW_STATE) == GFS_FS_FILLING && !(w & GFS_FW_PULL) && ld_rlx(&d->ffill[f]) == fill) {
         if (cas64(fw, w, (w | GFS_FW_PULL) + GFS_FW_VER_ONE)) {
           won = true;
           break;
@@ -2112,7 +2117,12 @@ __device__ __attribute__((noinline)) int64_t async_finish_block(const gfs_dev* d
     uint32_t nn = 0;
     int st = 0;
     const uint64_t th0 = wall_clock64();
-    while (__hip_atomic_load(&rs->done_seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != bs->a_gen) {
+    /* the slot's generations only grow: one past a_gen means the host finished this request,
+       blocks that joined its frames pulled and published every one of them, and the slot went
+       to a later request (nothing is left to claim: no frame's fill word names this one) */
+    uint64_t ds;
+    while ((int64_t)((ds = __hip_atomic_load(&rs->done_seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) -
+                     bs->a_gen) < 0) {
       if (expired(d, t0)) {
         st = -kETIMEDOUT;
         break;
@@ -2122,6 +2132,7 @@ __device__ __attribute__((noinline)) int64_t async_finish_block(const gfs_dev* d
     acquire_system();   /* the staged bytes, written by the host before done_seq */
     bcount(bs, GFS_T_HOST, wall_clock64() - th0);
     if (st) bcount(bs, GFS_C_TIMEOUTS, 1);
+    if (st == 0 && ds != bs->a_gen) st = 1;   /* done, and nothing left to pull */
     bs->a_status = st;
     bs->result = rs->result;
     bs->slot = bs->a_slot;
@@ -2132,10 +2143,11 @@ __device__ __attribute__((noinline)) int64_t async_finish_block(const gfs_dev* d
     bs->pull = 1;
   }
   __syncthreads();
-  const int64_t st = bs->a_status;
+  int64_t st = bs->a_status;
   if (st == 0) {
     const uint64_t fsize = d->files[bs->a_file].size;
-    if (tid < 64) claim_pulls_wave(d, bs);
+    if (tid < 64)
+      claim_pulls_wave(d, bs, (1ull << 63) | ((uint64_t)(bs->a_slot + 1) << 40) | (bs->a_gen & ((1ull << 40) - 1)));
     __syncthreads();
     block_pull(d, bs, fsize);
     __threadfence();
@@ -2148,7 +2160,7 @@ __device__ __attribute__((noinline)) int64_t async_finish_block(const gfs_dev* d
     bs->pull = 0;
   }
   __syncthreads();
-  return st;
+  return st < 0 ? st : 0;
 }
 
 }  // namespace gfsd
@@ -2388,7 +2400,8 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
     } else if (bs->pull) {
       const uint64_t tp0 = wall_clock64();
       if (bs->pull == 1) {
-        if (tid < 64) claim_pulls_wave(d, bs);
+        if (tid < 64)
+          claim_pulls_wave(d, bs, ((uint64_t)(bs->slot + 1) << 40) | (bs->gen & ((1ull << 40) - 1)));
         __syncthreads();
       }
       block_pull(d, bs, fsize);

@@ -19,6 +19,10 @@
 //   async-unfinished  the asynchronous path with a planted mistake: a block posts again before
 //           it has finished its previous request; blocks then wait for ring slots that only
 //           they would free, and the run must fail its deadlines.
+//   async-exact-gen   another planted mistake: the poster waits for the slot's completion to
+//           equal its request's generation; when helpers have published every frame the slot
+//           moves on to a later request and that wait never ends (the device's fix accepts any
+//           later generation and then claims nothing).
 //   reserve the lock-free reservation of a page-table entry for a one-page miss: many blocks
 //           race to reserve one key in its two 16-entry buckets; after every round exactly one
 //           reservation is left.
@@ -48,6 +52,7 @@ namespace {
 constexpr uint64_t kPage = 4096;
 double kDeadlineS = 60.0;   // FPM_DEADLINE_S overrides
 bool g_planted_no_finish = false;   // mode "async-unfinished": a planted protocol mistake
+bool g_planted_exact_gen = false;   // mode "async-exact-gen": another one
 
 // ---- atomics with the device's orderings (agent scope -> plain C++ atomics here). The
 // device polls with relaxed loads and takes one acquire fence when it sees the awaited value;
@@ -211,17 +216,23 @@ struct Posted {
   uint32_t frames[64];
 };
 
-// the poster's part after the host is done: publish (sync), claim the rest, copy, publish
+// the poster's part after the host is done: publish (sync), claim the rest, copy, publish.
+// The slot's generations only grow: done_seq past the request's generation means helpers
+// published every frame and the slot went to a later request, so nothing is left to claim.
 void finish(Model* M, Posted& q, bool publish_record) {
   gfs_rpc_slot* rs = &M->ring[q.slot];
   const double t0 = now_s();
-  while (__atomic_load_n(&rs->done_seq, __ATOMIC_ACQUIRE) != q.gen) {
+  uint64_t ds;
+  while (true) {
+    ds = __atomic_load_n(&rs->done_seq, __ATOMIC_ACQUIRE);
+    if (g_planted_exact_gen ? ds == q.gen : (int64_t)(ds - q.gen) >= 0) break;
     if (now_s() - t0 > kDeadlineS) {
       fail("poster: host deadline");
       return;
     }
     nap();
   }
+  if (ds != q.gen) return;   /* moved on: every frame was published by helpers */
   if (publish_record) {
     gfs_req_dev* r = &M->reqd[q.slot];
     r->result = rs->result;
@@ -229,11 +240,13 @@ void finish(Model* M, Posted& q, bool publish_record) {
     __atomic_store_n(&r->remaining, q.n, __ATOMIC_RELAXED);
     st_rel(&r->ready, q.gen);
   }
+  const uint64_t fill = (M->async ? (1ull << 63) : 0ull) | ((uint64_t)(q.slot + 1) << 40) |
+                        (q.gen & ((1ull << 40) - 1));
   uint32_t claimed[64], nc = 0;
   for (uint32_t k = 0; k < q.n; ++k) {
     const uint32_t f = q.frames[k];
-    uint64_t w = ld_rlx(&M->fword[f]);
-    while ((w & GFS_FW_STATE) == GFS_FS_FILLING && !(w & GFS_FW_PULL))
+    uint64_t w = ld_acq(&M->fword[f]);
+    while ((w & GFS_FW_STATE) == GFS_FS_FILLING && !(w & GFS_FW_PULL) && ld_rlx(&M->ffill[f]) == fill)
       if (cas(&M->fword[f], w, (w | GFS_FW_PULL) + GFS_FW_VER_ONE)) {
         claimed[nc++] = k;
         break;
@@ -252,6 +265,22 @@ void join_some(Model* M, std::mt19937_64& rng, std::vector<std::atomic<uint64_t>
     if (!(v & 1)) continue;
     const uint32_t k = (uint32_t)((v >> 1) & 0xff), f = (uint32_t)((v >> 9) & 0xfffff);
     const uint64_t tk = v >> 29;
+    uint64_t w = __atomic_fetch_add(&M->fword[f], GFS_FW_PIN_ONE, __ATOMIC_ACQUIRE);
+    const uint64_t st = w & GFS_FW_STATE;
+    if ((st == GFS_FS_FILLING || st == GFS_FS_VALID) && ld_rlx(&M->ticket_of_frame[f]) == tk) {
+      M->joined++;
+      join_or_help(M, f, k, tk);
+    }
+    __atomic_fetch_sub(&M->fword[f], GFS_FW_PIN_ONE, __ATOMIC_RELAXED);
+  }
+}
+
+// join every frame of the request with ticket tk that the board still shows
+void join_ticket(Model* M, uint64_t tk, std::vector<std::atomic<uint64_t>>* board) {
+  for (uint32_t k = 0; k < M->pages; ++k) {
+    const uint64_t v = (*board)[(tk * M->pages + k) % board->size()].load(std::memory_order_acquire);
+    if (!(v & 1) || (v >> 29) != tk) continue;
+    const uint32_t f = (uint32_t)((v >> 9) & 0xfffff);
     uint64_t w = __atomic_fetch_add(&M->fword[f], GFS_FW_PIN_ONE, __ATOMIC_ACQUIRE);
     const uint64_t st = w & GFS_FW_STATE;
     if ((st == GFS_FS_FILLING || st == GFS_FS_VALID) && ld_rlx(&M->ticket_of_frame[f]) == tk) {
@@ -339,8 +368,13 @@ void block_thread(Model* M, uint32_t b, uint32_t nreq, std::vector<std::atomic<u
     rs->npages = q.n;
     rs->ticket = q.tk;
     __atomic_store_n(&rs->req_seq, q.gen, __ATOMIC_RELEASE);
-    // a block with an asynchronous request outstanding reads on: it joins frames of others
-    if (M->async) join_some(M, rng, board);
+    // a block with an asynchronous request outstanding reads on: it joins frames of others,
+    // every frame of the request posted just before its own among them (so that helpers often
+    // publish a whole request before its poster comes back to it)
+    if (M->async) {
+      join_some(M, rng, board);
+      if (q.tk > 0) join_ticket(M, q.tk - 1, board);
+    }
     if (M->async) {
       pend = q;
       has_pend = true;
@@ -503,6 +537,10 @@ int main(int argc, char** argv) {
   if (mode == "async") return run_fill(true, blocks, nreq, frames, slots, pages);
   if (mode == "async-unfinished") {
     g_planted_no_finish = true;
+    return run_fill(true, blocks, nreq, frames, slots, pages);
+  }
+  if (mode == "async-exact-gen") {
+    g_planted_exact_gen = true;
     return run_fill(true, blocks, nreq, frames, slots, pages);
   }
   if (mode == "reserve") return run_reserve(blocks, nreq);

@@ -10,7 +10,9 @@ bytes are staged. The frame pool is small, so requesters wait for frames other r
 Every frame must be published once with the right bytes, every slot generation freed in order,
 no wait may pass its deadline, and ThreadSanitizer must see no race. A planted mistake (an
 asynchronous poster that posts again before finishing its previous request) must be caught by
-the deadlines. The lock-free one-page reservation must leave exactly one entry per key.
+the deadlines, and so must a poster that waits for its slot's completion to equal its own
+generation after helpers have published the whole window (the slot has moved on by then).
+The lock-free one-page reservation must leave exactly one entry per key.
 """
 import os
 import shutil
@@ -50,6 +52,15 @@ def test_protocol_model_holds(model, args):
     assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
     assert r.returncode == 0, (r.stdout, r.stderr[-2000:])
     assert r.stdout.strip().endswith("-> ok")
+
+
+def test_planted_exact_generation_wait_is_caught(model):
+    # the poster of an asynchronous window that waits for the slot's completion to equal its
+    # request's generation never returns once helpers have published every frame and the slot
+    # has gone to a later request (the device accepts any later generation)
+    r = _run(model, ("async-exact-gen", 16, 40, 128, 8, 4), deadline_s=5)
+    assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
+    assert r.returncode == 1 and "poster: host deadline" in r.stderr, (r.stdout, r.stderr[-2000:])
 
 
 def test_planted_unfinished_async_request_is_caught(model):
