@@ -994,7 +994,9 @@ def extra_list(torch, gfs, runner, args, name, e, passes: int = 3):
     asy = list_passes(torch, gfs, runner, wl, path, wl.ra_cap_bytes, passes, 1, args.host_threads, args.rpc_slots,
                       args.io_chunk_kib << 10, e["want"], ra_async=1)
     st = ra["stats"]
-    demand = st["fetched_pages"] - st["ra_pages"]
+    # the pages the readers asked for (each read once per pass): what a fetch beyond them,
+    # and a prefetched page evicted unread, are measured against
+    demand = -(-wl.delivered_bytes // wl.page_size)
     rec = {"workload": _list_desc(wl), "GBps": round(ra["GBps"], 3), "readahead_off_GBps": round(off["GBps"], 3),
            "readahead_speedup": round(ra["GBps"] / off["GBps"], 3), "storage_peak_GBps": round(nvme, 3),
            "frac_of_storage": round(ra["GBps"] / nvme, 3), "readahead_async_GBps": round(asy["GBps"], 3),
@@ -1003,7 +1005,8 @@ def extra_list(torch, gfs, runner, args, name, e, passes: int = 3):
            "steps": passes, "ra_cap_KiB": wl.ra_cap_bytes >> 10,
            "wasted_pages": st["wasted_pages"], "demand_pages": demand,
            "wasted_frac_of_demand": round(st["wasted_pages"] / max(demand, 1), 4),
-           "fetched_pages": st["fetched_pages"], "requests": st["requests"], "parity": "every block"}
+           "fetched_pages": st["fetched_pages"], "fetched_over_demand": round(st["fetched_pages"] / max(demand, 1), 4),
+           "requests": st["requests"], "parity": "every block"}
     log(f"{name}: {rec}")
     return rec
 

@@ -115,7 +115,10 @@ typedef struct gfs_config {
                                     Sec. 2.3): the page after a demand miss, and the first page of
                                     each asynchronous window, is its stream's marker; the first
                                     block to reach it issues the stream's next window and does not
-                                    wait for it. Shared policy only (-EINVAL otherwise). A block
+                                    wait for it. Such windows use a quarter of the ring slots
+                                    (at least one) of their own and are skipped while all of
+                                    those are held. Shared policy only, rpc_slots >= 2 (-EINVAL
+                                    otherwise). A block
                                     keeps at most one such window outstanding and pulls it in at
                                     gclose at the latest, so kernels must gclose before they end
                                     or gopen again. */

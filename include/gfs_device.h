@@ -1007,29 +1007,49 @@ __device__ uint32_t reserve_run_small_wave(const gfs_dev* d, uint32_t file, uint
 }
 
 /* ------------------------------------------------------------------ ring slots
- * Shared ring (default): one ticket counter for the whole ring, ticket t uses slot t mod S in
- * generation t / S + 1. Partitioned (GPUfs's queue): block b always posts into slot b mod S,
- * whose own counter gives the generation; the ticket is then (generation - 1) * S + slot, so
- * the same two helpers recover slot and generation. */
+ * Ticketed requests use the first S = sync_slots slots. Shared ring (default): one ticket
+ * counter, ticket t uses slot t mod S in generation t / S + 1. Partitioned (GPUfs's queue):
+ * block b always posts into slot b mod S, whose own counter gives the generation; the ticket
+ * is then (generation - 1) * S + slot, so the same two helpers recover slot and generation.
+ * The remaining slots belong to asynchronous windows: a window takes a free one without
+ * waiting (or is not issued), because its pages are pulled only when readers reach them, and a
+ * ticketed request queued behind such a slot could wait for readers that wait for it. */
 __device__ __forceinline__ void ring_ticket_lane(const gfs_dev* d, uint32_t bid, uint64_t& tk) {
+  const uint32_t S = d->sync_slots;
   if (d->partitioned) {
-    const uint32_t s = bid % d->rpc_slots;
-    tk = fadd64(&d->slot_tail[s], 1) * d->rpc_slots + s;
+    const uint32_t s = bid % S;
+    tk = fadd64(&d->slot_tail[s], 1) * S + s;
   } else {
     tk = fadd64(&d->g->ring_tail, 1);
   }
 }
 __device__ __forceinline__ uint32_t ring_slot(const gfs_dev* d, uint32_t, uint64_t tk) {
-  return (uint32_t)(tk % d->rpc_slots);
+  return (uint32_t)(tk % d->sync_slots);
 }
-__device__ __forceinline__ uint64_t ring_gen(const gfs_dev* d, uint64_t tk) { return tk / d->rpc_slots + 1; }
+__device__ __forceinline__ uint64_t ring_gen(const gfs_dev* d, uint64_t tk) { return tk / d->sync_slots + 1; }
+
+/* Lane: take a free slot of the asynchronous windows (busy 0 -> 1), starting at the block's
+   own; -1 if every one is held. The slot's next generation is one past its last completed. */
+__device__ int32_t async_slot_take_lane(const gfs_dev* d, uint32_t bid) {
+  const uint32_t A = d->rpc_slots - d->sync_slots;
+  for (uint32_t i = 0; i < A; ++i) {
+    const uint32_t s = d->sync_slots + (bid + i) % A;
+    uint64_t* b = &d->reqd[s].busy;
+    uint64_t z = 0;
+    if (ld_rlx(b) == 0 && cas64(b, z, 1ull)) return (int32_t)s;
+  }
+  return -1;
+}
 
 /* ------------------------------------------------------------------ private policy
- * The paper's design (Sec. 4.1 and Sec. 5.1). A miss takes the file's lock only to reserve
- * the one page in the table; the frame comes from the block's own share of the frames,
+ * The paper's design (Sec. 4.1 and Sec. 5.1). A miss reserves the one page in the table
+ * without the file's lock (reserve_unique_wave); the frame comes from the block's own share
+ * of the frames,
  * least recently allocated first (a frame another block has pinned is passed over); the
  * bytes come from the block's private buffer if it holds the page, else from a host read of
  * the page plus the static prefetch size, whose tail becomes the new private buffer. */
+
+__device__ int64_t reserve_unique_wave(const gfs_dev* d, uint64_t key);
 
 /* Lane: claim frame f of the block's share: FREE, or VALID with no pins (its page is
    evicted; the reference bit plays no part). CLAIMED on success. */
@@ -1054,26 +1074,12 @@ __device__ int lra_visit(const gfs_dev* d, uint32_t f, uint64_t& vkey, uint32_t&
 __device__ int miss_private_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint64_t key, uint64_t fsize,
                                  BlockState* bs, uint32_t bid, uint64_t t0, uint32_t& naps) {
   const uint32_t l = lane();
-  const uint64_t tl0 = wall_clock64();
-  uint64_t ticket;
-  const int lk = lock_file_wave(d, file, key, p, t0, ticket);
-  const uint64_t tl1 = wall_clock64();
-  if (l == 0) bcount(bs, GFS_T_LOCK, tl1 - tl0);
-  if (lk == LOCK_TIMEOUT) return 2;
-  if (lk == LOCK_LEFT || lk == LOCK_COVERED) {
-    if (l == 0) bcount(bs, GFS_C_LOCK_LEFT, 1);
-    return 1;
-  }
-  if (l == 0) bcount(bs, GFS_C_LOCKS, 1);
-  __builtin_amdgcn_s_setprio(3);
-  const bool present = pt_lookup_wave(d, key) >= 0;
-  int64_t slot = -1;
-  if (!present && l == 0) slot = pt_reserve_lane(d, key);
-  slot = __shfl(slot, 0, 64);
-  unlock_file_wave(d, file, ticket, 0, 0);
-  __builtin_amdgcn_s_setprio(0);
-  if (l == 0) bcount(bs, GFS_T_CRIT, wall_clock64() - tl1);
-  if (present) return 1;
+  /* the page's table entry, made unique without the file's lock (the policy decides nothing
+     under it: the window is the static prefetch after p, into the block's own buffer) */
+  const uint64_t tr0 = wall_clock64();
+  const int64_t slot = reserve_unique_wave(d, key);
+  if (l == 0) bcount(bs, GFS_T_RUN, wall_clock64() - tr0);
+  if (slot == -1) return 1;   /* another block's entry: go to the pin path */
   if (slot < 0) {
     /* both buckets of the key are full: reservations of misses in flight come and go, so
        back off and look again; only a table still full at the wait limit is an error */
@@ -1796,7 +1802,10 @@ __device__ __forceinline__ void request_done_lane(const gfs_dev* d, uint32_t s, 
   if (cnt == 0) return;
   const uint32_t before = __hip_atomic_fetch_sub(&d->reqd[s].remaining, cnt, __ATOMIC_ACQ_REL,
                                                  __HIP_MEMORY_SCOPE_AGENT);
-  if (before == cnt) st_rel(&d->slot_free[s], gen);
+  if (before == cnt) {
+    st_rel(&d->slot_free[s], gen);
+    if (s >= d->sync_slots) st_rel(&d->reqd[s].busy, 0ull);   /* an asynchronous window's slot */
+  }
 }
 
 /* Wave 0, after the block's pull, a fence by every thread and a barrier: publish the frames
@@ -1969,10 +1978,20 @@ __device__ uint32_t reserve_from_wave(const gfs_dev* d, uint32_t file, uint64_t 
 __device__ __attribute__((noinline)) void async_issue_wave(const gfs_dev* d, uint32_t file, uint64_t m, uint64_t fsize, BlockState* bs,
                                  uint32_t bid, uint64_t t0) {
   const uint32_t l = lane();
+  /* a slot of its own first: with none free the window is not issued (readers then miss at
+     its first page and the stream goes on synchronously) */
+  int32_t aslot = -1;
+  if (l == 0) aslot = async_slot_take_lane(d, bid);
+  aslot = __shfl(aslot, 0, 64);
+  if (aslot < 0) return;
+  const uint32_t s = (uint32_t)aslot;
   uint64_t ticket;
   /* the waiter announces no page of any window, so no holder marks it covered */
   const int lk = lock_file_wave(d, file, 0, 0x7fffffffull, t0, ticket, false);
-  if (lk != LOCK_OWN) return;
+  if (lk != LOCK_OWN) {
+    if (l == 0) st_rel(&d->reqd[s].busy, 0ull);
+    return;
+  }
   __builtin_amdgcn_s_setprio(3);
   const RaState ras = ra_load_lane(d, file);
   uint64_t cl = 0;
@@ -1983,6 +2002,7 @@ __device__ __attribute__((noinline)) void async_issue_wave(const gfs_dev* d, uin
   if (sm == 0) {
     unlock_file_wave(d, file, ticket, 0, 0);
     __builtin_amdgcn_s_setprio(0);
+    if (l == 0) st_rel(&d->reqd[s].busy, 0ull);
     return;
   }
   const int j = __ffsll((unsigned long long)sm) - 1;
@@ -2019,6 +2039,7 @@ __device__ __attribute__((noinline)) void async_issue_wave(const gfs_dev* d, uin
   if (wnc == 0 || held || free_cl == 0 || cwe <= ws) {
     unlock_file_wave(d, file, ticket, 0, 0);
     __builtin_amdgcn_s_setprio(0);
+    if (l == 0) st_rel(&d->reqd[s].busy, 0ull);
     return;
   }
   const uint32_t cj = (uint32_t)__builtin_ctzll(free_cl);
@@ -2046,41 +2067,22 @@ __device__ __attribute__((noinline)) void async_issue_wave(const gfs_dev* d, uin
   const uint32_t got = keep ? alloc_wave(d, file, ~0ull, bs, keep, bid, ws) : 0;
   for (uint32_t i = got + l; i < n; i += 64)
     if (bs->lslot[i] != 0xffffffffu) st_rel(d->pt + bs->lslot[i], 0ull);
-  if (got == 0) return;
+  if (got == 0) {
+    if (l == 0) st_rel(&d->reqd[s].busy, 0ull);
+    return;
+  }
   if (got < n && l == 0) trace_ev(d, 1, GFS_EV_NOFRAME, bid, file, bs->list[got], GFS_NO_FRAME, 0, 0);
   /* the pages that got frames are [ws, ws + got) */
   const uint64_t off0 = ws << d->page_shift;
   uint64_t len = (uint64_t)got << d->page_shift;
   if (off0 + len > fsize) len = fsize - off0;
-  int status = 0;
-  uint64_t tk = 0;
-  if (l == 0) {
-    ring_ticket_lane(d, bid, tk);
-    const uint32_t s = ring_slot(d, bid, tk);
-    const uint64_t gen = ring_gen(d, tk);
-    uint32_t nn = 0;
-    const uint64_t ts0 = wall_clock64();
-    while (ld_rlx(&d->slot_free[s]) != gen - 1) {
-      if (expired(d, t0)) {
-        status = 1;
-        break;
-      }
-      nap(nn);
-    }
-    acquire_agent();   /* the slot's last users are done with its staging */
-    bcount(bs, GFS_T_SLOT, wall_clock64() - ts0);
-    if (status == 0) {
-      /* frames count themselves off the request as they are published */
-      __hip_atomic_store(&d->reqd[s].remaining, got, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      bcount(bs, GFS_C_TIMEOUTS, 1);
-    }
-  }
-  status = __shfl(status, 0, 64);
-  tk = __shfl(tk, 0, 64);
-  if (status) return;   /* the frames stay filling; the cache must be reset after a timeout */
-  const uint32_t s = ring_slot(d, bid, tk);
-  const uint64_t gen = ring_gen(d, tk);
+  /* the slot is this window's alone: its staging is free once its last request was counted
+     off (that cleared busy), and its next generation is one past the last completed */
+  acquire_agent();
+  const uint64_t gen = ld_rlx(&d->slot_free[s]) + 1;
+  const uint64_t tk = (gen - 1) * d->rpc_slots + s;   /* for the trace only */
+  if (l == 0)   /* frames count themselves off the request as they are published */
+    __hip_atomic_store(&d->reqd[s].remaining, got, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const uint64_t fill = (1ull << 63) | ((uint64_t)(s + 1) << 40) | (gen & ((1ull << 40) - 1));
   for (uint32_t k = l; k < got; k += 64) st_rel(&d->ffill[bs->lframe[k]], fill);
   if (l == 0) {

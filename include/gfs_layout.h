@@ -174,7 +174,8 @@ typedef struct gfs_req_dev {
   uint64_t first_page;    /* first page of the span */
   uint32_t remaining;     /* frames of the request not yet published */
   uint32_t file;
-  uint64_t pad[4];
+  uint64_t busy;          /* slots of asynchronous windows: 1 while a window holds the slot */
+  uint64_t pad[3];
 } gfs_req_dev;            /* 64 B */
 
 typedef struct gfs_dev {
@@ -195,6 +196,9 @@ typedef struct gfs_dev {
   uint32_t ra_near_min;         /* detector: near misses that mark aggregate reading */
   uint32_t ra_quota_blocks;     /* thrash guard: resident blocks the cache is shared by */
   uint32_t ra_async;            /* 1: marker-triggered (asynchronous) readahead */
+  uint32_t sync_slots;          /* ring slots [0, sync_slots) take ticketed requests; the rest are
+                                   the asynchronous windows' own (taken without waiting) */
+  uint32_t pad_dev1;
   uint64_t max_req_bytes;
   uint64_t timeout_ticks;       /* wall_clock64 ticks */
   uint8_t* frames;

@@ -12,6 +12,7 @@
 #include <time.h>
 #include <unistd.h>
 
+#include <algorithm>
 #include <atomic>
 #include <deque>
 #include <memory>
@@ -86,6 +87,7 @@ int make_layout(const gfs_config* c, Layout* L) {
   if (c->ra_near_pages > (1u << 20) || c->ra_near_min < 1 || c->ra_near_min > c->ra_recent + 1) return -EINVAL;
   if (c->ra_async > 1) return -EINVAL;
   if (c->ra_async && c->policy != GFS_POLICY_SHARED) return -EINVAL;   /* markers live in the shared cache */
+  if (c->ra_async && c->rpc_slots < 2) return -EINVAL;   /* asynchronous windows need slots of their own */
   if (c->policy == GFS_POLICY_SHARED) {
     L->max_req_pages = L->ra_cap ? L->ra_cap : 1;
   } else if (c->policy == GFS_POLICY_PRIVATE) {
@@ -321,6 +323,8 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   h.ra_init = (uint32_t)L.ra_init;
   h.ra_cap = (uint32_t)L.ra_cap;
   h.rpc_slots = cfg->rpc_slots;
+  // asynchronous windows get a quarter of the ring (at least one slot) to themselves
+  h.sync_slots = cfg->ra_async ? cfg->rpc_slots - std::max(1u, cfg->rpc_slots / 4) : cfg->rpc_slots;
   h.max_req_pages = (uint32_t)L.max_req_pages;
   h.trace_level = cfg->trace_level;
   h.trace_cap = cfg->trace_capacity;

@@ -8,24 +8,29 @@
 //
 // Modes:
 //   sync    the synchronous path: a requester takes frames (FILLING, pinned for its demanded
-//           page), posts the request into a ring slot (after the slot's previous generation is
-//           free), waits for the host, publishes the request record, claims the frames no helper
-//           has claimed (PULL bit), copies them from staging, publishes them VALID and counts
-//           them off; the block that counts off the last frame frees the slot. Other blocks
-//           join frames of the request and, once the record is ready, claim and copy their own.
-//   async   the asynchronous path: the poster does not wait; joiners see the host's completion
-//           in the ring slot itself and copy their own frames; the poster claims the rest later
-//           (before it posts again, as the device does).
-//   async-unfinished  the asynchronous path with a planted mistake: a block posts again before
-//           it has finished its previous request; blocks then wait for ring slots that only
-//           they would free, and the run must fail its deadlines.
-//   async-exact-gen   another planted mistake: the poster waits for the slot's completion to
-//           equal its request's generation; when helpers have published every frame the slot
-//           moves on to a later request and that wait never ends (the device's fix accepts any
-//           later generation and then claims nothing).
+//           page) and shows them to readers, waits for its ring slot's previous generation to
+//           be free, posts, waits for the host, publishes the request record, claims the frames
+//           no helper has claimed (PULL bit, only while the frame's fill word names the
+//           request), copies them from staging, publishes them VALID and counts them off; the
+//           block that counts off the last frame frees the slot. Other blocks join frames of
+//           the request and, once the record is ready, claim and copy their own.
+//   async   mixed: every other request of a block is an asynchronous window. A window takes one
+//           of the slots kept for windows without waiting (or is dropped), and its poster does
+//           not wait: joiners see the host's completion in the ring slot itself and copy their
+//           own frames; some windows lie ahead of every reader (nobody joins them); the poster
+//           finishes its window before it posts again, accepting any later generation of the
+//           slot (helpers may have published the whole window, and the slot moved on).
 //   reserve the lock-free reservation of a page-table entry for a one-page miss: many blocks
 //           race to reserve one key in its two 16-entry buckets; after every round exactly one
 //           reservation is left.
+// Planted mistakes, each of which the deadlines must catch:
+//   async-shared-slots  windows take ticketed slots of the shared ring: a requester waits for
+//           a slot held by a window that lies ahead of the readers while its poster waits on the
+//           requester's own page (the stall seen on the GPU before windows got slots of their
+//           own).
+//   async-exact-gen     the poster waits for its slot's completion to equal its window's
+//           generation; once helpers have published the whole window the slot has moved on and
+//           that wait never ends.
 // Frame pressure: the frame pool is small, so requesters wait for frames that other requests'
 // readers must first let go of.
 //
@@ -37,6 +42,7 @@
 #include <string.h>
 #include <time.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <mutex>
@@ -51,7 +57,7 @@ namespace {
 
 constexpr uint64_t kPage = 4096;
 double kDeadlineS = 60.0;   // FPM_DEADLINE_S overrides
-bool g_planted_no_finish = false;   // mode "async-unfinished": a planted protocol mistake
+bool g_planted_shared = false;      // mode "async-shared-slots": a planted protocol mistake
 bool g_planted_exact_gen = false;   // mode "async-exact-gen": another one
 
 // ---- atomics with the device's orderings (agent scope -> plain C++ atomics here). The
@@ -92,7 +98,11 @@ struct Model {
   uint64_t ring_tail = 0;
   std::vector<uint64_t> free_frames;       // frame pool (a stack under a lock: the clock's role)
   std::mutex pool_mu;
-  std::atomic<uint64_t> published{0}, freed_slots{0}, joined{0}, helped{0};
+  std::atomic<uint64_t> published{0}, freed_slots{0}, joined{0}, helped{0}, posted{0}, dropped{0};
+  std::atomic<bool> stop{false};
+  uint64_t next_id = 0;            // request ids (the frames' tags)
+  uint64_t async_base = 0, async_next = 0;   // frames of asynchronous windows
+  uint32_t nsync = 0;              // slots [0, nsync) take ticketed requests
   bool async = false;
 
   Model(uint32_t b, uint32_t f, uint32_t s, uint32_t p)
@@ -108,11 +118,10 @@ struct Model {
 };
 
 // ---- the host: serve posted requests in ring order (any slot), fill staging, publish done
-void host_thread(Model* M, uint64_t total) {
-  uint64_t served = 0;
+void host_thread(Model* M) {
   std::vector<uint64_t> seen(M->nslots, 0);
   const double t0 = now_s();
-  while (served < total) {
+  while (!M->stop.load()) {
     bool any = false;
     for (uint32_t s = 0; s < M->nslots; ++s) {
       gfs_rpc_slot* rs = &M->ring[s];
@@ -124,11 +133,10 @@ void host_thread(Model* M, uint64_t total) {
         for (uint64_t i = 0; i < kPage; ++i) st[k * kPage + i] = Model::byte(rs->ticket, k, i);
       rs->result = (int64_t)(rs->npages * kPage);
       __atomic_store_n(&rs->done_seq, g, __ATOMIC_RELEASE);
-      ++served;
       any = true;
     }
     if (!any) nap();
-    if (now_s() - t0 > kDeadlineS) {
+    if (now_s() - t0 > 4 * kDeadlineS) {
       fail("host: deadline");
       return;
     }
@@ -151,6 +159,7 @@ void request_done(Model* M, uint32_t s, uint64_t gen, uint32_t cnt) {
   if (before == cnt) {
     if (ld_rlx(&M->slot_free[s]) != gen - 1) fail("slot freed out of order");
     st_rel(&M->slot_free[s], gen);
+    if (s >= M->nsync) st_rel(&M->reqd[s].busy, 0ull);   /* a window's slot */
     M->freed_slots++;
   }
 }
@@ -212,9 +221,14 @@ bool join_or_help(Model* M, uint32_t f, uint32_t k, uint64_t tk) {
 
 struct Posted {
   uint32_t slot = 0, n = 0;
-  uint64_t gen = 0, tk = 0;
+  uint64_t gen = 0, tk = 0;   // tk: the request's id (the frames' tag)
+  bool async = false;
   uint32_t frames[64];
 };
+
+uint64_t fill_of(const Posted& q) {
+  return (q.async ? (1ull << 63) : 0ull) | ((uint64_t)(q.slot + 1) << 40) | (q.gen & ((1ull << 40) - 1));
+}
 
 // the poster's part after the host is done: publish (sync), claim the rest, copy, publish.
 // The slot's generations only grow: done_seq past the request's generation means helpers
@@ -240,8 +254,7 @@ void finish(Model* M, Posted& q, bool publish_record) {
     __atomic_store_n(&r->remaining, q.n, __ATOMIC_RELAXED);
     st_rel(&r->ready, q.gen);
   }
-  const uint64_t fill = (M->async ? (1ull << 63) : 0ull) | ((uint64_t)(q.slot + 1) << 40) |
-                        (q.gen & ((1ull << 40) - 1));
+  const uint64_t fill = fill_of(q);
   uint32_t claimed[64], nc = 0;
   for (uint32_t k = 0; k < q.n; ++k) {
     const uint32_t f = q.frames[k];
@@ -257,155 +270,177 @@ void finish(Model* M, Posted& q, bool publish_record) {
   request_done(M, q.slot, q.gen, nc);
 }
 
-// join a few frames of other blocks' requests on the board (pin, check the tag, wait or help,
-// unpin), as a block whose access finds a frame being filled does
+// board entry of page k of request tk: ((tk << 20 | frame) << 8 | k) << 1 | 1
+void advertise(Model* M, const Posted& q, std::vector<std::atomic<uint64_t>>* board) {
+  for (uint32_t k = 0; k < q.n; ++k)
+    (*board)[(q.tk * M->pages + k) % board->size()].store(((q.tk << 20 | q.frames[k]) << 8 | k) << 1 | 1,
+                                                            std::memory_order_release);
+}
+
+// pin frame f if it still holds page k of request tk, wait for it (helping), unpin
+void join_frame(Model* M, uint32_t f, uint32_t k, uint64_t tk) {
+  uint64_t w = __atomic_fetch_add(&M->fword[f], GFS_FW_PIN_ONE, __ATOMIC_ACQUIRE);
+  const uint64_t st = w & GFS_FW_STATE;
+  if ((st == GFS_FS_FILLING || st == GFS_FS_VALID) && ld_rlx(&M->ticket_of_frame[f]) == tk) {
+    M->joined++;
+    join_or_help(M, f, k, tk);
+  }
+  __atomic_fetch_sub(&M->fword[f], GFS_FW_PIN_ONE, __ATOMIC_RELAXED);
+}
+
+// join a few frames of other blocks' requests on the board, as a block whose access finds a
+// frame being filled does
 void join_some(Model* M, std::mt19937_64& rng, std::vector<std::atomic<uint64_t>>* board) {
   for (int j = 0; j < 3; ++j) {
     const uint64_t v = (*board)[rng() % board->size()].load(std::memory_order_acquire);
-    if (!(v & 1)) continue;
-    const uint32_t k = (uint32_t)((v >> 1) & 0xff), f = (uint32_t)((v >> 9) & 0xfffff);
-    const uint64_t tk = v >> 29;
-    uint64_t w = __atomic_fetch_add(&M->fword[f], GFS_FW_PIN_ONE, __ATOMIC_ACQUIRE);
-    const uint64_t st = w & GFS_FW_STATE;
-    if ((st == GFS_FS_FILLING || st == GFS_FS_VALID) && ld_rlx(&M->ticket_of_frame[f]) == tk) {
-      M->joined++;
-      join_or_help(M, f, k, tk);
-    }
-    __atomic_fetch_sub(&M->fword[f], GFS_FW_PIN_ONE, __ATOMIC_RELAXED);
+    if (v & 1) join_frame(M, (uint32_t)((v >> 9) & 0xfffff), (uint32_t)((v >> 1) & 0xff), v >> 29);
   }
 }
 
-// join every frame of the request with ticket tk that the board still shows
+// join every frame of request tk that the board still shows
 void join_ticket(Model* M, uint64_t tk, std::vector<std::atomic<uint64_t>>* board) {
   for (uint32_t k = 0; k < M->pages; ++k) {
     const uint64_t v = (*board)[(tk * M->pages + k) % board->size()].load(std::memory_order_acquire);
-    if (!(v & 1) || (v >> 29) != tk) continue;
-    const uint32_t f = (uint32_t)((v >> 9) & 0xfffff);
-    uint64_t w = __atomic_fetch_add(&M->fword[f], GFS_FW_PIN_ONE, __ATOMIC_ACQUIRE);
-    const uint64_t st = w & GFS_FW_STATE;
-    if ((st == GFS_FS_FILLING || st == GFS_FS_VALID) && ld_rlx(&M->ticket_of_frame[f]) == tk) {
-      M->joined++;
-      join_or_help(M, f, k, tk);
-    }
-    __atomic_fetch_sub(&M->fword[f], GFS_FW_PIN_ONE, __ATOMIC_RELAXED);
+    if ((v & 1) && (v >> 29) == tk) join_frame(M, (uint32_t)((v >> 9) & 0xfffff), k, tk);
   }
 }
 
-// one block: REQUESTS requests of PAGES pages each; joins frames of other blocks' requests
+// one block: REQUESTS requests of PAGES pages each. Mode sync: every request synchronous.
+// Mixed modes: every other request is an asynchronous window. Synchronous requests take
+// frames from the small pool and show them to readers before they get a slot (as the device
+// reserves pages before posting); asynchronous windows take frames of their own.
 void block_thread(Model* M, uint32_t b, uint32_t nreq, std::vector<std::atomic<uint64_t>>* board) {
   std::mt19937_64 rng(1000 + b);
   Posted pend;
   bool has_pend = false;
   for (uint32_t r = 0; r < nreq && !g_fail.load(); ++r) {
+    const bool do_async = M->async && (r & 1);
     // a block that waits for its own synchronous request joins nothing meanwhile; between
     // requests it reads other blocks' pages like any reader
     if (!M->async) join_some(M, rng, board);
-    // an asynchronous poster finishes its previous request before it posts again
-    if (has_pend && g_planted_no_finish) {
-      // the planted mistake: post again with the previous request unfinished (its frames are
-      // pulled only at the very end)
-      static thread_local std::vector<Posted> later;
-      later.push_back(pend);
-      has_pend = false;
-      if (r + 1 == nreq)
-        for (auto& x : later) finish(M, x, false);
-    } else if (has_pend) {
+    // a poster finishes its outstanding asynchronous window before it posts again
+    if (has_pend) {
       finish(M, pend, false);
       has_pend = false;
     }
-    // frames (pool under pressure: wait for readers of older requests to let go)
     Posted q;
     q.n = M->pages;
-    const double tf = now_s();
-    while (true) {
-      {
-        std::lock_guard<std::mutex> g(M->pool_mu);
-        if (M->free_frames.size() >= q.n) {
-          for (uint32_t k = 0; k < q.n; ++k) {
-            q.frames[k] = (uint32_t)M->free_frames.back();
-            M->free_frames.pop_back();
+    q.async = do_async;
+    q.tk = __atomic_fetch_add(&M->next_id, 1, __ATOMIC_RELAXED);
+    if (do_async) {
+      const uint64_t base = M->async_base + __atomic_fetch_add(&M->async_next, q.n, __ATOMIC_RELAXED);
+      for (uint32_t k = 0; k < q.n; ++k) q.frames[k] = (uint32_t)(base + k);
+    } else {
+      const double tf = now_s();
+      while (true) {
+        {
+          std::lock_guard<std::mutex> g(M->pool_mu);
+          if (M->free_frames.size() >= q.n) {
+            for (uint32_t k = 0; k < q.n; ++k) {
+              q.frames[k] = (uint32_t)M->free_frames.back();
+              M->free_frames.pop_back();
+            }
+            break;
           }
-          break;
         }
+        if (now_s() - tf > kDeadlineS) {
+          fail("no frames: deadline");
+          return;
+        }
+        nap();
       }
-      if (now_s() - tf > kDeadlineS) {
-        fail("no frames: deadline");
-        return;
-      }
-      nap();
     }
-    // ticket -> slot and generation; wait for the slot's previous generation to be free
-    q.tk = __atomic_fetch_add(&M->ring_tail, 1, __ATOMIC_RELAXED);
-    q.slot = (uint32_t)(q.tk % M->nslots);
-    q.gen = q.tk / M->nslots + 1;
-    const double ts = now_s();
-    while (ld_acq(&M->slot_free[q.slot]) != q.gen - 1) {
-      if (now_s() - ts > kDeadlineS) {
-        fail("slot: deadline");
-        return;
-      }
-      nap();
-    }
+    // CLAIMED -> FILLING, version + 1, the tag (a synchronous request's demanded page, k = 0,
+    // pinned by its poster); the fill word is not known yet. An addition, as on the device:
+    // a reader holding a stale pin on the frame keeps it (it drops the pin after seeing that
+    // the tag is not its page)
     for (uint32_t k = 0; k < q.n; ++k) {
       const uint32_t f = q.frames[k];
-      // CLAIMED -> FILLING, version + 1 (the demanded page, k = 0, pinned by the poster in the
-      // synchronous path)
-      uint64_t w = ld_rlx(&M->fword[f]);
-      const uint64_t nw = ((((w >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT) | GFS_FS_FILLING) +
-                          ((!M->async && k == 0) ? GFS_FW_PIN_ONE : 0);
-      st_rel(&M->fword[f], nw);
-      st_rlx(&M->ticket_of_frame[f], q.tk);   /* the tag, stored as the device stores ftag */
+      st_rlx(&M->ffill[f], 0ull);
+      st_rlx(&M->ticket_of_frame[f], q.tk);
+      const uint64_t delta = (GFS_FS_FILLING - GFS_FS_CLAIMED) + GFS_FW_VER_ONE +
+                             ((!do_async && k == 0) ? GFS_FW_PIN_ONE : 0);
+      __atomic_fetch_add(&M->fword[f], delta, __ATOMIC_RELEASE);
     }
-    if (M->async) __atomic_store_n(&M->reqd[q.slot].remaining, q.n, __ATOMIC_RELAXED);
-    const uint64_t fill = (M->async ? (1ull << 63) : 0ull) | ((uint64_t)(q.slot + 1) << 40) |
-                          (q.gen & ((1ull << 40) - 1));
+    if (!do_async) advertise(M, q, board);
+    if (do_async && !g_planted_shared) {
+      // a slot of the windows' own, taken without waiting; none free: the window is dropped
+      int32_t s = -1;
+      const uint32_t A = M->nslots - M->nsync;
+      for (uint32_t i = 0; i < A && s < 0; ++i) {
+        const uint32_t c = M->nsync + (b + i) % A;
+        uint64_t z = 0;
+        if (ld_rlx(&M->reqd[c].busy) == 0 && cas(&M->reqd[c].busy, z, 1ull)) s = (int32_t)c;
+      }
+      if (s < 0) {
+        M->dropped++;
+        continue;   /* its frames were never shown to anyone */
+      }
+      q.slot = (uint32_t)s;
+      q.gen = ld_acq(&M->slot_free[q.slot]) + 1;
+    } else {
+      // ticketed: wait for the slot's previous generation to be free
+      const uint64_t t = __atomic_fetch_add(&M->ring_tail, 1, __ATOMIC_RELAXED);
+      q.slot = (uint32_t)(t % M->nsync);
+      q.gen = t / M->nsync + 1;
+      const double ts = now_s();
+      while (ld_acq(&M->slot_free[q.slot]) != q.gen - 1) {
+        if (now_s() - ts > kDeadlineS) {
+          fail("slot: deadline");
+          return;
+        }
+        nap();
+      }
+    }
+    if (do_async) __atomic_store_n(&M->reqd[q.slot].remaining, q.n, __ATOMIC_RELAXED);
+    const uint64_t fill = fill_of(q);
     for (uint32_t k = 0; k < q.n; ++k) st_rel(&M->ffill[q.frames[k]], fill);
-    // advertise the frames for joiners: (frame << 20 | page) << 1 | 1, tagged by ticket
-    for (uint32_t k = 0; k < q.n; ++k)
-      (*board)[(q.tk * M->pages + k) % board->size()].store(((q.tk << 20 | q.frames[k]) << 8 | k) << 1 | 1,
-                                                              std::memory_order_release);
+    // windows that readers reach soon are shown to them (in the mode with adversarial readers,
+    // all of them); the rest lie ahead of every reader, like a readahead window
+    if (do_async && (g_planted_exact_gen || (rng() & 1))) advertise(M, q, board);
     gfs_rpc_slot* rs = &M->ring[q.slot];
     rs->npages = q.n;
     rs->ticket = q.tk;
     __atomic_store_n(&rs->req_seq, q.gen, __ATOMIC_RELEASE);
-    // a block with an asynchronous request outstanding reads on: it joins frames of others,
-    // every frame of the request posted just before its own among them (so that helpers often
-    // publish a whole request before its poster comes back to it)
-    if (M->async) {
-      join_some(M, rng, board);
-      if (q.tk > 0) join_ticket(M, q.tk - 1, board);
-    }
-    if (M->async) {
+    M->posted++;
+    if (do_async) {
       pend = q;
       has_pend = true;
-    } else {
-      finish(M, q, true);
-      // the demanded page: pulled here or by a helper; wait for it, read it, unpin
-      if (join_or_help(M, q.frames[0], 0, q.tk))
-        __atomic_fetch_sub(&M->fword[q.frames[0]], GFS_FW_PIN_ONE, __ATOMIC_RELAXED);
+      // a block with a window outstanding reads on: it joins frames of others, and in the
+      // adversarial mode every frame of the request before its own
+      join_some(M, rng, board);
+      if (g_planted_exact_gen) {
+        // adversarial readers: the poster's own reads reach the whole window, and other
+        // windows take its slot before the poster comes back to it
+        join_ticket(M, q.tk, board);
+        std::this_thread::sleep_for(std::chrono::milliseconds(2));
+      }
+      continue;
     }
+    finish(M, q, true);
+    // the demanded page: pulled here or by a helper; wait for it, read it, unpin
+    if (join_or_help(M, q.frames[0], 0, q.tk))
+      __atomic_fetch_sub(&M->fword[q.frames[0]], GFS_FW_PIN_ONE, __ATOMIC_RELAXED);
     // give back the frames of this block's completed request once nobody pins them (the clock
     // reclaims only unpinned VALID frames)
-    if (!M->async) {
-      for (uint32_t k = 0; k < q.n; ++k) {
-        const uint32_t f = q.frames[k];
-        const double tr = now_s();
-        while (true) {
-          uint64_t w = ld_rlx(&M->fword[f]);
-          if ((w & GFS_FW_STATE) == GFS_FS_VALID && !(w & GFS_FW_PINS)) {
-            const uint64_t claimed = (((w >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT) | GFS_FS_CLAIMED;
-            if (cas(&M->fword[f], w, claimed)) break;
-            continue;
-          }
-          if (now_s() - tr > kDeadlineS) {
-            fail("reclaim: deadline");
-            return;
-          }
-          nap();
+    for (uint32_t k = 0; k < q.n; ++k) {
+      const uint32_t f = q.frames[k];
+      const double tr = now_s();
+      while (true) {
+        uint64_t w = ld_rlx(&M->fword[f]);
+        if ((w & GFS_FW_STATE) == GFS_FS_VALID && !(w & GFS_FW_PINS)) {
+          const uint64_t claimed = (((w >> GFS_FW_VER_SHIFT) + 1) << GFS_FW_VER_SHIFT) | GFS_FS_CLAIMED;
+          if (cas(&M->fword[f], w, claimed)) break;
+          continue;
         }
-        std::lock_guard<std::mutex> g(M->pool_mu);
-        M->free_frames.push_back(f);
+        if (now_s() - tr > kDeadlineS) {
+          fail("reclaim: deadline (frame word " + std::to_string(w) + ")");
+          return;
+        }
+        nap();
       }
+      std::lock_guard<std::mutex> g(M->pool_mu);
+      M->free_frames.push_back(f);
     }
   }
   if (has_pend) finish(M, pend, false);
@@ -414,34 +449,40 @@ void block_thread(Model* M, uint32_t b, uint32_t nreq, std::vector<std::atomic<u
 int run_fill(bool async, uint32_t blocks, uint32_t nreq, uint32_t nframes, uint32_t nslots, uint32_t pages) {
   Model M(blocks, nframes, nslots, pages);
   M.async = async;
-  if (async) {
-    // frames of asynchronous requests are never given back in this model: size the pool
-    M.frames.assign((uint64_t)blocks * nreq * pages * kPage, 0);
-    M.fword.assign((size_t)blocks * nreq * pages, 0);
-    M.ffill.assign(M.fword.size(), 0);
-    M.ticket_of_frame.assign(M.fword.size(), 0);
-    M.free_frames.clear();
-    for (uint64_t i = 0; i < M.fword.size(); ++i) M.free_frames.push_back(i);
-  }
+  // asynchronous windows: a quarter of the slots (at least one) of their own, and frames past
+  // the pool (never given back in this model)
+  M.nsync = async && !g_planted_shared ? nslots - std::max(1u, nslots / 4) : nslots;
+  M.async_base = nframes;
+  const uint64_t extra = async ? (uint64_t)blocks * nreq * pages : 0;
+  M.frames.assign((nframes + extra) * kPage, 0);
+  M.fword.assign(nframes + extra, GFS_FS_CLAIMED);   // every frame starts owned by the pool
+  M.ffill.assign(nframes + extra, 0);
+  M.ticket_of_frame.assign(nframes + extra, 0);
   std::vector<std::atomic<uint64_t>> board(256);
   for (auto& x : board) x.store(0);
   const uint64_t total = (uint64_t)blocks * nreq;
-  std::thread host(host_thread, &M, total);
+  std::thread host(host_thread, &M);
   std::vector<std::thread> ts;
   for (uint32_t b = 0; b < blocks; ++b) ts.emplace_back(block_thread, &M, b, nreq, &board);
   for (auto& t : ts) t.join();
+  M.stop.store(true);
   host.join();
-  // every frame of every request published exactly once, every slot generation freed
-  if (M.published.load() != total * pages) fail("published " + std::to_string(M.published.load()) + " frames, want " +
-                                                std::to_string(total * pages));
-  if (M.freed_slots.load() != total) fail("slots freed " + std::to_string(M.freed_slots.load()));
+  // every posted request's frames published exactly once, every slot generation freed
+  const uint64_t posted = M.posted.load();
+  if (posted + M.dropped.load() != total) fail("requests posted " + std::to_string(posted));
+  if (M.published.load() != posted * pages)
+    fail("published " + std::to_string(M.published.load()) + " frames, want " + std::to_string(posted * pages));
+  if (M.freed_slots.load() != posted) fail("slots freed " + std::to_string(M.freed_slots.load()));
+  uint64_t gens = 0;
   for (uint32_t s = 0; s < nslots; ++s) {
-    const uint64_t gens = total / nslots + (s < total % nslots ? 1 : 0);
-    if (M.slot_free[s] != gens) fail("slot " + std::to_string(s) + " ends at generation " + std::to_string(M.slot_free[s]));
+    gens += M.slot_free[s];
+    if (s >= M.nsync && M.reqd[s].busy) fail("a window's slot is still held");
   }
-  printf("%s blocks=%u requests=%u frames=%u slots=%u pages=%u joined=%llu helped=%llu -> %s\n",
-         async ? "async" : "sync", blocks, nreq, nframes, nslots, pages, (unsigned long long)M.joined.load(),
-         (unsigned long long)M.helped.load(), g_fail.load() ? "FAILED" : "ok");
+  if (gens != posted) fail("slot generations " + std::to_string(gens) + " for " + std::to_string(posted) + " requests");
+  printf("%s blocks=%u requests=%u frames=%u slots=%u pages=%u posted=%llu dropped=%llu joined=%llu helped=%llu -> %s\n",
+         async ? "mixed" : "sync", blocks, nreq, nframes, nslots, pages, (unsigned long long)posted,
+         (unsigned long long)M.dropped.load(), (unsigned long long)M.joined.load(), (unsigned long long)M.helped.load(),
+         g_fail.load() ? "FAILED" : "ok");
   return g_fail.load() ? 1 : 0;
 }
 
@@ -535,8 +576,8 @@ int main(int argc, char** argv) {
   if (mode == "sync") return run_fill(false, blocks, nreq, frames, slots, pages);
   if (const char* e = getenv("FPM_DEADLINE_S")) kDeadlineS = atof(e);
   if (mode == "async") return run_fill(true, blocks, nreq, frames, slots, pages);
-  if (mode == "async-unfinished") {
-    g_planted_no_finish = true;
+  if (mode == "async-shared-slots") {
+    g_planted_shared = true;
     return run_fill(true, blocks, nreq, frames, slots, pages);
   }
   if (mode == "async-exact-gen") {
