@@ -160,49 +160,96 @@ def fast_storage(torch, gfs, runner, configs, wl, cap_bytes, args, h2d):
         shutil.rmtree(ddir, ignore_errors=True)
 
 
+HIT_FILE_BYTES = 1 << 30
+
+
+def _hit_passes(torch, gfs, runner, configs, cache, fid, blocks, reads, consumer, steps):
+    """Timed all-hit launches of the list reader over the cached 1 GiB file (strided 64 KiB
+    reads, one page each), on the launch stream with HIP events: (median kernel ms, per-page
+    timer split in us, misses during the passes)."""
+    import numpy as np
+    off = configs.strided_offsets(blocks, reads, 64 << 10)
+    r = runner.ListReader(off, 64 << 10, consumer, 256)
+    r.launch(cache, fid)   # warm-up launch of this shape
+    torch.cuda.synchronize()
+    s0 = cache.stats()
+    ms = []
+    stream = torch.cuda.current_stream()
+    for _ in range(max(steps, 1)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        r.launch(cache, fid, stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    s1 = cache.stats()
+    if int((r.status != reads * (64 << 10)).sum()):
+        raise RuntimeError("an all-hit pass delivered short or failed")
+    n = len(ms) * blocks * reads
+    split = {k.split("_")[1]: round((s1[k] - s0[k]) / n / 1e3, 2) for k in ("t_acquire_ns", "t_copy_ns", "t_unpin_ns")}
+    return float(np.median(ms)), split, s1["misses"] - s0["misses"]
+
+
+def _device_copy_GBps(torch, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """HBM bytes moved per second (read + write) by a plain device-to-device copy of nbytes:
+    the rate an ordinary streaming kernel reaches on this GPU, beside the published peak."""
+    import numpy as np
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    stream = torch.cuda.current_stream()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.copy_(a)
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del a, b
+    return 2 * nbytes / (float(np.median(ms)) * 1e-3) / 1e9
+
+
+def _hit_roofline(kernel_ms: float, blocks: int, reads: int) -> dict:
+    """The method's own bytes on a hit, measured on the reads-only launch: the frame read and
+    the user-buffer write, 2 B per delivered byte."""
+    traffic, traffic_src = recorded_traffic(HIT_TRAFFIC_SUMMARY, f"traffic_bytes_per_launch_none_{blocks}x{reads}")
+    method = 2 * HIT_FILE_BYTES / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(method, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(method / HBM_PEAK_GBS, 4), "bytes_per_launch": 2 * HIT_FILE_BYTES,
+            "traffic": traffic, "traffic_source": traffic_src, "kernel": "list_reader_kernel",
+            "launch": f"{blocks} x {reads} reads of 64 KiB, reads only (consumer 2)",
+            "note": "achieved counts 2 B per delivered byte (frame read + user-buffer write)"}
+
+
 def hit_path(torch, gfs, runner, configs, ddir, host_threads):
     """All-hit passes: a 1 GiB file held entirely in a 2 GiB cache, read after one cold pass;
-    each later pass is lookup + pin + copy-out + consumer only."""
-    import numpy as np
-    hf = configs.FileSpec("hit_seed9_1GiB.bin", 9, 1 << 30)
+    each later pass is lookup + pin + copy-out + unpin, with the checksum consumer and with
+    the reads alone."""
+    hf = configs.FileSpec("hit_seed9_1GiB.bin", 9, HIT_FILE_BYTES)
     hpath = configs.ensure_file(hf, ddir)
-    hoff = configs.strided_offsets(1024, 16, 64 << 10)
     hcfg = runner.make_config(64 << 10, 2 << 30, ra_cap_bytes=16 << 20, host_threads=host_threads,
                               timeout_s=60)
+    blocks, reads = 512, 32
     with gfs.PageCache(hcfg) as cache:
         fid = cache.open(hpath)
-        reader = runner.ListReader(hoff, 64 << 10, configs.CONSUMER_CHECKSUM, 256)
-        reader.launch(cache, fid)
+        runner.ListReader(configs.strided_offsets(blocks, reads, 64 << 10), 64 << 10,
+                          configs.CONSUMER_NONE, 256).launch(cache, fid)   # the cold pass
         torch.cuda.synchronize()
-        s0 = cache.stats()
-        hms = []
-        stream = torch.cuda.current_stream()
-        for _ in range(5):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            reader.launch(cache, fid, stream)
-            e1.record(stream)
-            e1.synchronize()
-            hms.append(e0.elapsed_time(e1))
-        s1 = cache.stats()
-    hbytes = 1 << 30
-    hk = float(np.median(hms))
-    # algorithmic HBM bytes per delivered byte on a hit: frame read + user-buffer write
-    # (+ the consumer's read of the user buffer, which is the benchmark, not the method)
-    traffic, traffic_src = recorded_traffic(HIT_TRAFFIC_SUMMARY, "traffic_bytes_per_launch_1024x16")
-    # the method's own bytes on a hit: the frame read and the user-buffer write (2 B per delivered
-    # byte); the consumer's read of the user buffer (the third counted byte) is the benchmark's
-    method = 2 * hbytes / (hk * 1e-3) / 1e9
-    return {"workload": "1 GiB file cached in a 2 GiB cache (64 KiB pages), 1024 blocks x 16 reads "
-                        "of 64 KiB, all hits", "kernel_ms": hk,
-            "delivered_GBps": hbytes / (hk * 1e-3) / 1e9,
-            "hbm_GBps": 3 * hbytes / (hk * 1e-3) / 1e9,
-            "roofline": {"bound": "hbm", "achieved": round(method, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(method / HBM_PEAK_GBS, 4), "bytes_per_launch": 2 * hbytes,
-                         "traffic": traffic, "traffic_source": traffic_src, "kernel": "list_reader_kernel",
-                         "note": "achieved counts 2 B per delivered byte (frame read + user-buffer write); "
-                                 "traffic is the counted HBM bytes, which include the consumer's read"},
-            "misses_after_warm": s1["misses"] - s0["misses"]}
+        k_sum, _, m1 = _hit_passes(torch, gfs, runner, configs, cache, fid, blocks, reads,
+                                   configs.CONSUMER_CHECKSUM, 5)
+        k_none, split, m2 = _hit_passes(torch, gfs, runner, configs, cache, fid, blocks, reads,
+                                        configs.CONSUMER_NONE, 5)
+    return {"workload": f"1 GiB file cached in a 2 GiB cache (64 KiB pages), {blocks} blocks x {reads} reads "
+                        "of 64 KiB, all hits", "kernel_ms": round(k_none, 4),
+            "delivered_GBps": round(HIT_FILE_BYTES / (k_none * 1e-3) / 1e9, 1),
+            "per_page_us": split,
+            "with_checksum": {"kernel_ms": round(k_sum, 4),
+                              "delivered_GBps": round(HIT_FILE_BYTES / (k_sum * 1e-3) / 1e9, 1),
+                              "hbm_GBps_at_3B_per_B": round(3 * HIT_FILE_BYTES / (k_sum * 1e-3) / 1e9, 1)},
+            "device_copy_GBps": round(_device_copy_GBps(torch), 1),
+            "roofline": _hit_roofline(k_none, blocks, reads),
+            "misses_after_warm": m1 + m2}
 
 
 def cpu_procs() -> int:
@@ -587,64 +634,44 @@ def bench_diagnostics(args, torch) -> int:
 
 def bench_hits(args, torch) -> int:
     """The kernel's own HBM-bound path: a 1 GiB file held in a 2 GiB cache of 64 KiB pages,
-    read in 64 KiB pieces after one cold pass, every read a hit (lookup, pin, copy-out, unpin,
-    checksum), at three launch shapes; per-page time split from the library's timers."""
-    import numpy as np
-
+    read in 64 KiB pieces after one cold pass, every read a hit (lookup, pin, copy-out, unpin),
+    at three launch shapes, with the reads alone and with the checksum consumer; per-page time
+    split from the library's timers; a plain device copy beside it."""
     from paper_2109_05366_amd import gfs, runner
     from workloads import configs
     ddir = args.data_dir or os.environ.get("GFS_DATA_DIR") or configs.data_dir()
-    path = configs.ensure_file(configs.FileSpec("hit_seed9_1GiB.bin", 9, 1 << 30), ddir)
+    path = configs.ensure_file(configs.FileSpec("hit_seed9_1GiB.bin", 9, HIT_FILE_BYTES), ddir)
     shapes = []
-    for blocks, reads in ((1024, 16), (512, 32), (256, 64)):
-        off = configs.strided_offsets(blocks, reads, 64 << 10)
-        cfg = runner.make_config(64 << 10, 2 << 30, ra_cap_bytes=16 << 20, timeout_s=60)
-        with gfs.PageCache(cfg) as cache:
-            fid = cache.open(path)
-            r = runner.ListReader(off, 64 << 10, configs.CONSUMER_CHECKSUM, 256)
-            r.launch(cache, fid)
-            torch.cuda.synchronize()
-            s0 = cache.stats()
-            ms = []
-            stream = torch.cuda.current_stream()
-            for _ in range(max(args.steps, 1)):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                r.launch(cache, fid, stream)
-                e1.record(stream)
-                e1.synchronize()
-                ms.append(e0.elapsed_time(e1))
-            s1 = cache.stats()
-        n = len(ms) * blocks * reads
-        d = {k: (s1[k] - s0[k]) / n / 1e3 for k in ("t_acquire_ns", "t_copy_ns", "t_unpin_ns")}
-        if s1["misses"] != s0["misses"]:
-            raise RuntimeError("the warm passes missed")
-        k = float(np.median(ms))
-        shapes.append({"blocks": blocks, "reads": reads, "kernel_ms": round(k, 4),
-                       "delivered_GBps": round((1 << 30) / (k * 1e-3) / 1e9, 1),
-                       "per_page_us": {"acquire": round(d["t_acquire_ns"], 2), "copy": round(d["t_copy_ns"], 2),
-                                       "unpin": round(d["t_unpin_ns"], 2)}})
-        log(f"hits {blocks} x {reads}: {shapes[-1]}")
-    # calibration for HBM traffic counters: a plain 1 GiB device-to-device copy (known bytes)
-    calib_src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-    torch.empty_like(calib_src).copy_(calib_src)
-    torch.cuda.synchronize()
-    del calib_src
-    best = max(shapes, key=lambda x: x["delivered_GBps"])
-    # algorithmic HBM bytes per delivered byte: frame read + user-buffer write + checksum read
-    achieved = 3 * best["delivered_GBps"]
-    traffic, traffic_src = recorded_traffic(HIT_TRAFFIC_SUMMARY,
-                                            f"traffic_bytes_per_launch_{best['blocks']}x{best['reads']}")
+    cfg = runner.make_config(64 << 10, 2 << 30, ra_cap_bytes=16 << 20, timeout_s=60)
+    with gfs.PageCache(cfg) as cache:
+        fid = cache.open(path)
+        runner.ListReader(configs.strided_offsets(512, 32, 64 << 10), 64 << 10,
+                          configs.CONSUMER_NONE, 256).launch(cache, fid)   # the cold pass
+        torch.cuda.synchronize()
+        for blocks, reads in ((1024, 16), (512, 32), (256, 64)):
+            row = {"blocks": blocks, "reads": reads}
+            for name, consumer in (("reads_only", configs.CONSUMER_NONE), ("checksum", configs.CONSUMER_CHECKSUM)):
+                k, split, missed = _hit_passes(torch, gfs, runner, configs, cache, fid, blocks, reads, consumer,
+                                               args.steps)
+                if missed:
+                    raise RuntimeError("the warm passes missed")
+                row[name] = {"kernel_ms": round(k, 4), "delivered_GBps": round(HIT_FILE_BYTES / (k * 1e-3) / 1e9, 1),
+                             "per_page_us": split}
+            shapes.append(row)
+            log(f"hits {blocks} x {reads}: {row}")
+    copy_gbps = _device_copy_GBps(torch)
+    best = max(shapes, key=lambda x: x["reads_only"]["delivered_GBps"])
+    k = best["reads_only"]["kernel_ms"]
     line = {
         "metric": "delivered GB/s of all-hit reads (the cache's HBM-bound path)",
-        "value": best["delivered_GBps"], "unit": "GB/s", "n_gpus": 1, "steps": max(args.steps, 1), "warmup": 1,
-        "ms_per_step": best["kernel_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "value": best["reads_only"]["delivered_GBps"], "unit": "GB/s", "n_gpus": 1, "steps": max(args.steps, 1),
+        "warmup": 1, "ms_per_step": k, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u8", "data": "synthetic",
-        "config": {"workload": "hit: 1 GiB splitmix64(seed=9) file in a 2 GiB cache of 64 KiB pages, 64 KiB reads"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 3), "traffic": traffic,
-                     "traffic_source": traffic_src, "kernel": "list_reader_kernel",
-                     "bytes_per_launch": 3 << 30},
+        "config": {"workload": "hit: 1 GiB splitmix64(seed=9) file in a 2 GiB cache of 64 KiB pages, 64 KiB reads, "
+                               f"reads only, {best['blocks']} x {best['reads']}"},
+        "roofline": _hit_roofline(k, best["blocks"], best["reads"]),
+        "device_copy_GBps": round(copy_gbps, 1),
+        "frac_of_device_copy": round(2 * HIT_FILE_BYTES / (k * 1e-3) / 1e9 / copy_gbps, 3),
         "shapes": shapes,
     }
     print(json.dumps(line), flush=True)

@@ -309,7 +309,9 @@ int gfs_shutdown(gfs_ctx* ctx);
  * buffer into its consumer output:
  *   consumer 0 (checksum): out is uint64[blocks]; wrapping sum of the delivered
  *     little-endian uint32 words, a trailing partial word zero-padded;
- *   consumer 1 (histogram): out is uint32[blocks*256]; count of each byte value.
+ *   consumer 1 (histogram): out is uint32[blocks*256]; count of each byte value;
+ *   consumer 2 (none): the reads only; out is not touched (may be NULL), and buf + b*read_size
+ *     holds what block b's last read delivered.
  * status (int64[blocks]) receives the total bytes delivered to the block, or the first
  * negative errno gread returned. turn, if not NULL, serialises the reads: read k of
  * block b waits until *turn == k*blocks + b and then increments it (test-only; every
@@ -326,7 +328,8 @@ int gfs_launch_list_reader(gfs_ctx* ctx, int file_id, const uint64_t* offsets, u
  * or past data_size deliver nothing, reads crossing it are cut short, exactly like gread at
  * the end of a file. This is the GPU half of the paper's CPU-I/O baseline (Sec. 6: the CPU
  * reads the file and copies it to the GPU, then the kernel runs). Arguments as for
- * gfs_launch_list_reader (offsets need no alignment); no context. -EINVAL on bad shapes. */
+ * gfs_launch_list_reader (offsets need no alignment; consumers 0 and 1 only); no context.
+ * -EINVAL on bad shapes. */
 int gfs_launch_buffer_reader(const void* data_dev, uint64_t data_size, const uint64_t* offsets, uint32_t blocks,
                              uint32_t reads, uint64_t read_size, uint32_t threads, int consumer, void* out,
                              int64_t* status, void* hip_stream);

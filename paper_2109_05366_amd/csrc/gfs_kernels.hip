@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS, 2) list_reader_kernel(c
     }
     total += r;
     if (consumer == 0) csum += checksum_part(mybuf, (uint64_t)r, tid, nt);
-    else histogram_part(mybuf, (uint64_t)r, tid, nt, hist);
+    else if (consumer == 1) histogram_part(mybuf, (uint64_t)r, tid, nt, hist);
     __syncthreads();
   }
   if (fd >= 0) gclose(d, fd);
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(GFS_MAX_BLOCK_THREADS, 2) list_reader_kernel(c
       for (uint32_t w = 0; w < (nt + 63) / 64; ++w) s += red[w];
       ((uint64_t*)out)[b] = s;
     }
-  } else {
+  } else if (consumer == 1) {
     __syncthreads();
     for (uint32_t i = tid; i < 256; i += nt) ((uint32_t*)out)[(uint64_t)b * 256 + i] = hist[i];
   }
@@ -311,11 +311,11 @@ extern "C" int gfs_launch_list_reader(gfs_ctx* ctx, int file_id, const uint64_t*
                                       uint32_t blocks, uint32_t reads, uint64_t read_size,
                                       uint32_t threads, int consumer, void* buf, void* out,
                                       int64_t* status, uint64_t* turn, void* hip_stream) {
-  if (!ctx || !offsets || !buf || !out || !status) return -EINVAL;
+  if (!ctx || !offsets || !buf || (!out && consumer != 2) || !status) return -EINVAL;
   if (blocks == 0 || blocks > (1u << 20) || reads == 0) return -EINVAL;
   if (threads == 0 || threads % 64 || threads > GFS_MAX_BLOCK_THREADS) return -EINVAL;
   if (read_size == 0 || read_size % 16) return -EINVAL;
-  if (consumer != 0 && consumer != 1) return -EINVAL;
+  if (consumer < 0 || consumer > 2) return -EINVAL;
   if (((uintptr_t)buf | (uintptr_t)out) & 15) return -EINVAL;
   if (turn) {
     // the serialising gate waits on other blocks: every block must be resident at once

@@ -53,8 +53,10 @@ class ListReader:
         self.buf = torch.empty(self.blocks * read_size, dtype=torch.uint8, device=device)
         if consumer == 0:
             self.out = torch.zeros(self.blocks, dtype=torch.int64, device=device)
-        else:
+        elif consumer == 1:
             self.out = torch.zeros(self.blocks * 256, dtype=torch.int32, device=device)
+        else:
+            self.out = None   # consumer 2: the reads only; the buffers hold each block's last read
         self.status = torch.zeros(self.blocks, dtype=torch.int64, device=device)
         self.turn = torch.zeros(1, dtype=torch.int64, device=device)
 
@@ -64,7 +66,7 @@ class ListReader:
             self.turn.zero_()
         gfs.gfs_launch_list_reader(cache.ctx, file_id, self.offsets.data_ptr(), self.blocks, self.reads,
                                    self.read_size, self.threads, self.consumer, self.buf.data_ptr(),
-                                   self.out.data_ptr(), self.status.data_ptr(),
+                                   self.out.data_ptr() if self.out is not None else 0, self.status.data_ptr(),
                                    self.turn.data_ptr() if serialize else 0, s.cuda_stream)
 
     def result(self) -> ListResult:
@@ -72,8 +74,10 @@ class ListReader:
         st = self.status.cpu().numpy()
         if self.consumer == 0:
             out = self.out.cpu().numpy().view(np.uint64).copy()
-        else:
+        elif self.consumer == 1:
             out = self.out.cpu().numpy().view(np.uint32).reshape(self.blocks, 256).copy()
+        else:
+            out = self.buf.cpu().numpy().reshape(self.blocks, self.read_size).copy()
         return ListResult(out=out, status=st)
 
 

@@ -537,6 +537,36 @@ def test_buffer_reader_matches_oracle(name, data_dir, cuda):
     np.testing.assert_array_equal(got, exp_out)
 
 
+@pytest.mark.parametrize("ra_pages", [0, 16])
+def test_reads_only_consumer_leaves_each_blocks_last_read(ra_pages, data_dir, cuda):
+    """Consumer 2 (the reads alone, as the all-hit benchmark times them): every block's buffer
+    ends holding what its reads put there in order (a short read at the end of the file
+    overwrites only its prefix, a read past it nothing), cold and then all hits."""
+    wl = configs.get("c1_small")
+    path = configs.ensure_file(wl.file, data_dir)
+    _, exp_deliv = expected(wl, path)
+    fill = 0xA5
+    want = np.full((wl.blocks, wl.read_size), fill, dtype=np.uint8)
+    for b in range(wl.blocks):
+        for off in wl.offsets[b]:
+            got = odata_mod().delivered(path, int(off), wl.read_size)
+            want[b, :len(got)] = np.frombuffer(got, dtype=np.uint8)
+    cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=ra_pages * wl.page_size, timeout_s=20)
+    with gfs.PageCache(cfg) as cache:
+        fid = cache.open(path)
+        r = runner.ListReader(wl.offsets, wl.read_size, configs.CONSUMER_NONE)
+        for label in ("cold", "warm"):
+            _say(f"reads only, {label}, ra_pages={ra_pages}")
+            r.buf.fill_(fill)
+            r.launch(cache, fid)
+            res = r.result()
+            np.testing.assert_array_equal(res.status, exp_deliv)
+            np.testing.assert_array_equal(res.out, want)
+        st = cache.stats()
+    assert st["timeouts"] == 0 and st["io_errors"] == 0, st
+    assert st["delivered_bytes"] == 2 * int(exp_deliv.sum())
+
+
 def odata_mod():
     from oracle import data as odata
     return odata

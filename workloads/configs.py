@@ -40,6 +40,7 @@ GiB = 1 << 30
 
 CONSUMER_CHECKSUM = 0
 CONSUMER_HISTOGRAM = 1
+CONSUMER_NONE = 2          # the reads only: each block's buffer ends holding its last read
 
 
 @dataclasses.dataclass(frozen=True)
