@@ -842,9 +842,14 @@ typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
 /* Block-cooperative copy of n bytes; both pointers 16-byte aligned and in global memory
  * (frames, user buffers). Global rather than generic accesses let loads and stores be
- * waited on separately, so eight 16-byte loads per lane are in flight per round. */
+ * waited on separately, so eight 16-byte loads per lane are in flight per round.
+ * kStream: the source is read with nontemporal loads, which do not keep its lines in the
+ * caches; the copy-out of a frame uses it, so that streaming page bytes through does not
+ * push the page table and frame words out of L2 (all-hit pass: +3 % with the reads alone,
+ * +6 % with a consumer reading the user buffer back, lookup and pin 0.3 us shorter). */
 typedef __attribute__((address_space(1))) v4u gv4u;
 
+template <bool kStream = false>
 __device__ __forceinline__ void copy_block_aligned(uint8_t* dst, const uint8_t* src, uint64_t n,
                                                    uint32_t tid, uint32_t nt) {
   const uint64_t n16 = n >> 4;
@@ -854,7 +859,10 @@ __device__ __forceinline__ void copy_block_aligned(uint8_t* dst, const uint8_t* 
   for (; i + 7ull * nt < n16; i += 8ull * nt) {
     v4u a[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) a[k] = s[i + (uint64_t)k * nt];
+    for (int k = 0; k < 8; ++k) {
+      if (kStream) a[k] = __builtin_nontemporal_load(&s[i + (uint64_t)k * nt]);
+      else a[k] = s[i + (uint64_t)k * nt];
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) o[i + (uint64_t)k * nt] = a[k];
   }
@@ -862,10 +870,11 @@ __device__ __forceinline__ void copy_block_aligned(uint8_t* dst, const uint8_t* 
   for (uint64_t j = (n16 << 4) + tid; j < n; j += nt) dst[j] = src[j];
 }
 
+/* The copy-out of a frame's bytes to a user buffer (any alignment). */
 __device__ __forceinline__ void copy_block(uint8_t* dst, const uint8_t* src, uint64_t n,
                                            uint32_t tid, uint32_t nt) {
   if ((((uintptr_t)dst | (uintptr_t)src) & 15) == 0) {
-    copy_block_aligned(dst, src, n, tid, nt);
+    copy_block_aligned<true>(dst, src, n, tid, nt);
   } else {
     for (uint64_t j = tid; j < n; j += nt) dst[j] = src[j];
   }
