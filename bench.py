@@ -139,10 +139,14 @@ def fast_storage(torch, gfs, runner, configs, wl, cap_bytes, args, h2d):
     try:
         path = configs.ensure_file(wl.file, ddir)
         out = {}
-        for label, cap in (("ra", cap_bytes), ("no_ra", 0)):
+        modes = [("ra", cap_bytes, 0), ("no_ra", 0, 0)]
+        if not args.no_ra_async and cap_bytes:
+            modes.append(("ra_async", cap_bytes, 1))
+        for label, cap, ra_async in modes:
             # reads from memory need few host threads; more only compete for the CPUs
             cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=cap, host_threads=8,
-                                     rpc_slots=args.rpc_slots, timeout_s=60, io_chunk_bytes=2 << 20)
+                                     rpc_slots=args.rpc_slots, timeout_s=60, io_chunk_bytes=2 << 20,
+                                     ra_async=ra_async, quota_blocks=QUOTA_BLOCKS)
             with gfs.PageCache(cfg) as cache:
                 fid = cache.open(path)
                 reader = runner.ListReader(wl.offsets, wl.read_size, wl.consumer, wl.threads)
@@ -154,7 +158,9 @@ def fast_storage(torch, gfs, runner, configs, wl, cap_bytes, args, h2d):
                 raise RuntimeError(f"tmpfs {label}: wrong delivered byte counts")
             out[label] = wl.delivered_bytes * 3 / wall / 1e9
         return {"data_dir": "tmpfs", "GBps": round(out["ra"], 3), "readahead_off_GBps": round(out["no_ra"], 3),
-                "readahead_speedup": round(out["ra"] / out["no_ra"], 3), "h2d_peak_GBps": round(h2d, 3),
+                "readahead_speedup": round(out["ra"] / out["no_ra"], 3),
+                "readahead_async_GBps": round(out["ra_async"], 3) if "ra_async" in out else None,
+                "h2d_peak_GBps": round(h2d, 3),
                 "frac_of_h2d_peak": round(out["ra"] / h2d, 3), "steps": 3, "host_threads": 8}
     finally:
         shutil.rmtree(ddir, ignore_errors=True)
