@@ -7,9 +7,10 @@ import bench
 
 def test_committed_summaries_parse():
     for summary, key in ((bench.TRAFFIC_SUMMARY, "traffic_bytes_per_launch"),
-                         (bench.HIT_TRAFFIC_SUMMARY, "traffic_bytes_per_launch_1024x16"),
-                         (bench.HIT_TRAFFIC_SUMMARY, "traffic_bytes_per_launch_512x32"),
-                         (bench.HIT_TRAFFIC_SUMMARY, "traffic_bytes_per_launch_256x64")):
+                         (bench.HIT_TRAFFIC_SUMMARY, "traffic_bytes_per_launch_none_1024x16"),
+                         (bench.HIT_TRAFFIC_SUMMARY, "traffic_bytes_per_launch_none_512x32"),
+                         (bench.HIT_TRAFFIC_SUMMARY, "traffic_bytes_per_launch_none_256x64"),
+                         (bench.HIT_TRAFFIC_SUMMARY, "traffic_bytes_per_launch_checksum_512x32")):
         assert os.path.exists(os.path.join(bench.ROOT, summary))
         value, src = bench.recorded_traffic(summary, key)
         if value is None:   # the kernel changed since the counters were taken
