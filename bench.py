@@ -382,36 +382,74 @@ def cpu_io_comparator(torch, gfs, wl, path, want):
 QUOTA_BLOCKS = 0
 
 
-def list_passes(torch, gfs, runner, wl, path, cap_bytes, steps, warmup, host_threads, rpc_slots, io_chunk,
-                want=None, policy=None, private_slots=512, advice="normal", ra_async=0):
-    """Cold passes of a list workload with readahead at cap_bytes (0: off; ra_async 1: the
-    asynchronous, marker-triggered mode); every block's output is compared with `want` when
-    given. Returns a result dict (rates, kernel times, counters, outputs)."""
+def mode_passes(torch, gfs, runner, wl, path, modes, steps, warmup, host_threads, rpc_slots, io_chunk,
+                want=None, policy=None, private_slots=512, advice="normal"):
+    """Cold passes of a list workload in several modes, `modes` = [(label, cap_bytes, ra_async)]
+    (cap 0: readahead off; ra_async 1: the asynchronous, marker-triggered mode). The modes take
+    turns, pass by pass (mode 1, mode 2, ..., mode 1, ...), each pass on a fresh context, so
+    that a storage rate that drifts during the run weighs on every mode alike. A pass is timed
+    from its launch to its completion (synchronized on both sides); `warmup` untimed passes
+    per mode go first. Every block's output is compared with `want` when given. Returns
+    {label: result dict (rates, kernel times, counters of the last pass, outputs)}."""
     import numpy as np
-    cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=cap_bytes, host_threads=host_threads,
-                             rpc_slots=rpc_slots, timeout_s=60, io_chunk_bytes=io_chunk,
-                             policy=gfs.GFS_POLICY_SHARED if policy is None else policy,
-                             private_slots=private_slots, ra_async=ra_async, quota_blocks=QUOTA_BLOCKS)
-    with gfs.PageCache(cfg) as cache:
-        fid = cache.open(path)
-        if advice != "normal":
-            cache.fadvise(fid, {"random": gfs.GFS_ADV_RANDOM, "sequential": gfs.GFS_ADV_SEQUENTIAL}[advice])
-        reader = runner.ListReader(wl.offsets, wl.read_size, wl.consumer, wl.threads)
-        wall, kms, st = run_steps(torch, cache, fid, reader, steps, warmup)
-        res = reader.result()
-    if st["timeouts"] or st["io_errors"]:
-        raise RuntimeError(f"{wl.name} cap {cap_bytes}: device errors {st}")
     o = wl.offsets.astype(np.int64)
     deliv = np.maximum(np.minimum(o + wl.read_size, wl.file.size) - o, 0).sum(axis=1)
-    if not np.array_equal(res.status, deliv):
-        raise RuntimeError(f"{wl.name} cap {cap_bytes}: wrong delivered byte counts")
-    if want is not None and not np.array_equal(res.out, want):
-        raise RuntimeError(f"{wl.name} cap {cap_bytes}: outputs differ from the oracle")
     delivered = wl.delivered_bytes
-    per_step = [delivered / (k * 1e-3) / 1e9 for k in kms]
-    return {"wall_s": wall, "GBps": steps * delivered / wall / 1e9,
-            "kernel_GBps": delivered / (np.mean(kms) * 1e-3) / 1e9, "kernel_ms": float(np.mean(kms)),
-            "step_min_GBps": min(per_step), "step_max_GBps": max(per_step), "out": res.out, "stats": st}
+    readers = {label: runner.ListReader(wl.offsets, wl.read_size, wl.consumer, wl.threads) for label, _, _ in modes}
+    acc = {label: {"wall": 0.0, "kms": [], "st": None, "out": None} for label, _, _ in modes}
+    stream = torch.cuda.current_stream()
+    for it in range(warmup + steps):
+        for label, cap, ra_async in modes:
+            cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=cap, host_threads=host_threads,
+                                     rpc_slots=rpc_slots, timeout_s=60, io_chunk_bytes=io_chunk,
+                                     policy=gfs.GFS_POLICY_SHARED if policy is None else policy,
+                                     private_slots=private_slots, ra_async=ra_async, quota_blocks=QUOTA_BLOCKS)
+            reader = readers[label]
+            with gfs.PageCache(cfg) as cache:
+                fid = cache.open(path)
+                if advice != "normal":
+                    cache.fadvise(fid, {"random": gfs.GFS_ADV_RANDOM, "sequential": gfs.GFS_ADV_SEQUENTIAL}[advice])
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                t0 = time.perf_counter()
+                e0.record(stream)
+                reader.launch(cache, fid, stream)
+                e1.record(stream)
+                e1.synchronize()
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                st = cache.stats()
+            res = reader.result()
+            if st["timeouts"] or st["io_errors"]:
+                raise RuntimeError(f"{wl.name} {label}: device errors {st}")
+            if not np.array_equal(res.status, deliv):
+                raise RuntimeError(f"{wl.name} {label}: wrong delivered byte counts")
+            if want is not None and not np.array_equal(res.out, want):
+                raise RuntimeError(f"{wl.name} {label}: outputs differ from the oracle")
+            if it < warmup:
+                log(f"  {label} warmup {it} done")
+                continue
+            a = acc[label]
+            a["wall"] += wall
+            a["kms"].append(e0.elapsed_time(e1))
+            a["st"], a["out"] = st, res.out
+            log(f"  {label} step {it - warmup}: kernel {a['kms'][-1]:.1f} ms, {delivered / wall / 1e9:.2f} GB/s")
+    out = {}
+    for label, a in acc.items():
+        kms = a["kms"]
+        per_step = [delivered / (k * 1e-3) / 1e9 for k in kms]
+        out[label] = {"wall_s": a["wall"], "GBps": steps * delivered / a["wall"] / 1e9,
+                      "kernel_GBps": delivered / (np.mean(kms) * 1e-3) / 1e9, "kernel_ms": float(np.mean(kms)),
+                      "step_min_GBps": min(per_step), "step_max_GBps": max(per_step), "out": a["out"],
+                      "stats": a["st"]}
+    return out
+
+
+def list_passes(torch, gfs, runner, wl, path, cap_bytes, steps, warmup, host_threads, rpc_slots, io_chunk,
+                want=None, policy=None, private_slots=512, advice="normal", ra_async=0):
+    """Cold passes of a list workload in one mode (see mode_passes)."""
+    return mode_passes(torch, gfs, runner, wl, path, [("x", cap_bytes, ra_async)], steps, warmup, host_threads,
+                       rpc_slots, io_chunk, want, policy, private_slots, advice)["x"]
 
 
 def _pool_files(m, ddir):
@@ -898,16 +936,14 @@ def bench_list(args, torch) -> int:
     if not args.no_cpu_baseline:
         from oracle import data as odata
         want = (odata.block_histograms if wl.consumer else odata.block_checksums)(path, wl.offsets, wl.read_size)
-    ra = list_passes(torch, gfs, runner, wl, path, cap, args.steps, args.warmup, args.host_threads, args.rpc_slots,
-                     args.io_chunk_kib << 10, want, policy, args.private_slots, args.advice)
-    off = None if args.no_ra_off else list_passes(torch, gfs, runner, wl, path, 0, args.steps, args.warmup,
-                                                  args.host_threads, args.rpc_slots, args.io_chunk_kib << 10, want,
-                                                  policy, args.private_slots, args.advice)
-    asy = None
+    modes = [("ra", cap, 0)]
+    if not args.no_ra_off:
+        modes.append(("no_ra", 0, 0))
     if not args.no_ra_async and args.policy == "shared" and cap:
-        asy = list_passes(torch, gfs, runner, wl, path, cap, args.steps, args.warmup, args.host_threads,
-                          args.rpc_slots, args.io_chunk_kib << 10, want, policy, args.private_slots, args.advice,
-                          ra_async=1)
+        modes.append(("ra_async", cap, 1))
+    res = mode_passes(torch, gfs, runner, wl, path, modes, args.steps, args.warmup, args.host_threads, args.rpc_slots,
+                      args.io_chunk_kib << 10, want, policy, args.private_slots, args.advice)
+    ra, off, asy = res["ra"], res.get("no_ra"), res.get("ra_async")
     value = ra["GBps"]
     mp_ = min(nvme, h2d)
     line = {
@@ -1020,12 +1056,10 @@ def extra_list(torch, gfs, runner, args, name, e, passes: int = 3):
     fraction of the storage rate measured on the same file."""
     wl, path = e["wl"], e["path"]
     nvme = storage_peak(path)
-    ra = list_passes(torch, gfs, runner, wl, path, wl.ra_cap_bytes, passes, 1, args.host_threads,
-                     args.rpc_slots, args.io_chunk_kib << 10, e["want"])
-    off = list_passes(torch, gfs, runner, wl, path, 0, passes, 1, args.host_threads, args.rpc_slots,
-                      args.io_chunk_kib << 10, e["want"])
-    asy = list_passes(torch, gfs, runner, wl, path, wl.ra_cap_bytes, passes, 1, args.host_threads, args.rpc_slots,
-                      args.io_chunk_kib << 10, e["want"], ra_async=1)
+    res = mode_passes(torch, gfs, runner, wl, path,
+                      [("ra", wl.ra_cap_bytes, 0), ("no_ra", 0, 0), ("ra_async", wl.ra_cap_bytes, 1)], passes, 1,
+                      args.host_threads, args.rpc_slots, args.io_chunk_kib << 10, e["want"])
+    ra, off, asy = res["ra"], res["no_ra"], res["ra_async"]
     st = ra["stats"]
     # the pages the readers asked for (each read once per pass): what a fetch beyond them,
     # and a prefetched page evicted unread, are measured against
@@ -1139,17 +1173,16 @@ def bench_default(args, torch, pre) -> int:
     delivered = wl.delivered_bytes
     cap_bytes = _cap_bytes(args, wl)
     policy = gfs.GFS_POLICY_PRIVATE if args.policy == "private" else gfs.GFS_POLICY_SHARED
-    results = {}
-    for label, cap, asy in (("ra", cap_bytes, 0), ("no_ra", 0, 0), ("ra_async", cap_bytes, 1)):
-        if label == "no_ra" and args.no_ra_off:
-            continue
-        if label == "ra_async" and (args.no_ra_async or args.policy != "shared"):
-            continue
-        log(f"{label}: cap {cap >> 10} KiB, policy {args.policy}")
-        results[label] = list_passes(torch, gfs, runner, wl, path, cap, args.steps, args.warmup, args.host_threads,
-                                     args.rpc_slots, args.io_chunk_kib << 10, pre["want"], policy,
-                                     args.private_slots, args.advice, ra_async=asy)
-        log(f"{label}: {results[label]['GBps']:.2f} GB/s wall, {results[label]['kernel_GBps']:.2f} GB/s kernel")
+    modes = [("ra", cap_bytes, 0)]
+    if not args.no_ra_off:
+        modes.append(("no_ra", 0, 0))
+    if not args.no_ra_async and args.policy == "shared" and cap_bytes:
+        modes.append(("ra_async", cap_bytes, 1))
+    log(f"modes {[m[0] for m in modes]} in turn: cap {cap_bytes >> 10} KiB, policy {args.policy}")
+    results = mode_passes(torch, gfs, runner, wl, path, modes, args.steps, args.warmup, args.host_threads,
+                          args.rpc_slots, args.io_chunk_kib << 10, pre["want"], policy, args.private_slots, args.advice)
+    for label, r in results.items():
+        log(f"{label}: {r['GBps']:.2f} GB/s wall, {r['kernel_GBps']:.2f} GB/s kernel")
     nvme_samples.append(storage_peak(path))
     nvme = float(np.mean(nvme_samples))
     log(f"storage peak after the passes {nvme_samples[1]:.2f} GB/s (mean {nvme:.2f})")

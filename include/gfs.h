@@ -261,7 +261,8 @@ typedef struct gfs_event {
 enum {
   GFS_EV_HIT = 1,    /* file,page,frame                                         */
   GFS_EV_JOIN = 2,   /* file,page,frame                                         */
-  GFS_EV_MISS = 3,   /* file,page; a = window length (EOF-clamped), b = window start;
+  GFS_EV_MISS = 3,   /* file,page; a = window length (EOF-clamped), b = window start |
+                        req << 32, req = pages of the read from page on (readahead on);
                         frame = near | h << 8 | rule << 24: the detector's inputs and choice --
                         near = the file's recent misses near page, h = cached pages right
                         behind page (counted only when no stream zone or the aggregate rule

@@ -90,6 +90,8 @@ struct BlockState {
                                    compared with this key (the hit's copy carries the check) */
   uint64_t pinw;                /* the frame word the pin returned (for the hit's bit updates) */
   int32_t tag_ok;               /* the check's outcome, for every thread of the block */
+  uint64_t read_last;           /* last page of the gread in progress: a readahead window
+                                   opened by a miss covers the read up to it */
 };
 
 /* the lock queue's size assumes every block that calls gread holds this much LDS */
@@ -512,8 +514,10 @@ __device__ bool lock_try_leave_lane(const gfs_dev* d, uint32_t file, uint64_t t)
 __device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uint64_t page, uint64_t t0,
                               uint64_t& ticket, bool may_leave = true);
 /* Wave-collective: pass the lock on; [lo, hi) is the window the holder has just claimed
-   (lo == hi: none). */
-__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket, uint64_t lo, uint64_t hi);
+   (lo == hi: none). has_pre: lane l's `pre` is the value of the slot of ticket + 1 + l, read
+   earlier under the lock, and the first look uses it instead of reading the slots again. */
+__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket, uint64_t lo, uint64_t hi,
+                                 bool has_pre = false, uint64_t pre = 0);
 
 __device__ int32_t pt_lookup_wave(const gfs_dev* d, uint64_t key);
 
@@ -581,7 +585,8 @@ __device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uin
  * loses only to the waiter leaving), and the first other ticket gets the grant; if that
  * waiter left just before the exchange, the scan goes on after it. A ticket that has not
  * announced its page yet is granted the lock like any other. */
-__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket, uint64_t lo, uint64_t hi) {
+__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket, uint64_t lo, uint64_t hi,
+                                 bool has_pre, uint64_t pre) {
   drain_atomics();
   const uint32_t l = lane();
   uint64_t n = ticket + 1;
@@ -590,7 +595,7 @@ __device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticke
     if (look) {
       const uint64_t nl = n + l;
       uint64_t* sl = lock_slot(d, file, nl);
-      uint64_t v = ld_rlx(sl);
+      uint64_t v = has_pre && n == ticket + 1 ? pre : ld_rlx(sl);
       const uint64_t pg = (v >> 32) & 0x7fffffffull;
       const bool gone = v == lock_left(nl) || v == lock_covered(nl);
       const bool cov = hi > lo && (v >> 63) && (uint32_t)v == ((uint32_t)nl << 2) && pg >= lo && pg < hi;
@@ -628,7 +633,9 @@ __device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticke
  * file is being read in aggregate by many blocks and the window is the cap-sized aligned
  * chunk around p; else the history of cached pages right behind p sizes it (context
  * readahead); with neither, it opens with the initial window at offset 0 or under
- * SEQUENTIAL advice, else with one page. */
+ * SEQUENTIAL advice, else with one page. A context or new window covers at least the req
+ * pages from p to the end of the read that missed (Sec. 2.3: the prefetcher reads at least
+ * what the caller asked for), up to the cap. */
 /* Per lane: the file's detector state, loaded together (lane i: recent miss i, stream
    slot i); the decision below uses it after the caller's acquire fence. */
 struct RaState {
@@ -671,9 +678,9 @@ __device__ __forceinline__ uint32_t ra_cap_eff(const gfs_dev* d) {
   return d->ra_cap < q ? d->ra_cap : (uint32_t)q;
 }
 
-__device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, const RaState& st, uint64_t& ws,
-                               uint32_t& wn, uint32_t& near_out, uint32_t& h_out, uint32_t& rule_out,
-                               int& slot_out) {
+__device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint32_t req, const RaState& st,
+                               uint64_t& ws, uint32_t& wn, uint32_t& near_out, uint32_t& h_out,
+                               uint32_t& rule_out, int& slot_out) {
   gfs_file_dev* fe = &d->files[file];
   const uint32_t advice = st.advice;
   ws = p;
@@ -732,18 +739,22 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, cons
       ws = p - p % cap;
       rule_out = RA_RULE_AGGREGATE;
     } else {
-      /* context: count the consecutive cached pages right behind p (64 per round); a
-         stream that no slot tracks shows up as that history */
+      /* context: count the consecutive cached pages right behind p (64 per round), up to
+         ceil(cap / 2), the most that can change the window min(2h, cap); a stream that no
+         slot tracks shows up as that history */
+      const uint32_t hmax = (cap + 1) / 2;
       uint32_t h = 0;
-      while (h < cap) {
+      while (h < hmax) {
         const uint64_t back = (uint64_t)h + 1 + l;
         bool mapped = false;
-        if (back <= p && h + l < cap) mapped = pt_present_lane(d, page_key(file, p - back));
+        if (back <= p && h + l < hmax) mapped = pt_present_lane(d, page_key(file, p - back));
         const uint64_t m = __ballot(mapped);
         const uint32_t run = (~m == 0ull) ? 64u : (uint32_t)__builtin_ctzll(~m);
         h += run;
         if (run < 64) break;
       }
+      /* either way the window covers at least the rest of the read that missed (req pages
+         from p), as a read larger than a page asks for them all */
       uint32_t w0;
       if (h > 0) {
         w0 = 2 * h;
@@ -752,6 +763,7 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, cons
         w0 = (p == 0 || advice == GFS_ADV_SEQUENTIAL) ? d->ra_init : 1u;
         rule_out = RA_RULE_NEW;
       }
+      if (w0 < req) w0 = req;
       if (w0 > cap) w0 = cap;
       if (w0 < 1) w0 = 1;
       ws = p;
@@ -1472,8 +1484,15 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
   /* one round: the detector state and the file's window claims; then, ordered after the
      claims, the table probe (a claim cleared after its reservations means they show) */
   const RaState ras = ra_load_lane(d, file);
+  /* the pages of the read that missed, from p on */
+  const uint64_t rl = bs->read_last;
+  const uint32_t req = rl >= p ? (rl - p + 1 < 0xffffffffull ? (uint32_t)(rl - p + 1) : 0xffffffffu) : 1u;
   uint64_t cl = 0;
   if (l < GFS_CLAIMS) cl = ld_rlx(&d->claims[file].e[l]);
+  /* the queue slots behind this ticket, read now for the hand-off: a waiter that arrives or
+     leaves after this read is handled by the grant's exchange (it returns what the slot
+     holds), and a stale "waiting" value only makes the covered mark's compare-and-swap fail */
+  const uint64_t qv = ld_rlx(lock_slot(d, file, ticket + 1 + l));
   const uint64_t npages = d->files[file].npages;
   drain_atomics();   /* the table probe below goes out after the claims were read */
   const bool cl_on = l < GFS_CLAIMS && (cl & 1ull);
@@ -1498,7 +1517,7 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
   uint32_t wn, near, hist, rule;
   int rslot;
   const uint64_t td0 = wall_clock64();
-  ra_decide_wave(d, file, p, ras, ws, wn, near, hist, rule, rslot);
+  ra_decide_wave(d, file, p, req, ras, ws, wn, near, hist, rule, rslot);
   const uint64_t td1 = wall_clock64();
   if (l == 0) bcount(bs, GFS_T_DECIDE, td1 - td0);
   if (ws + wn > npages) wn = (uint32_t)(npages - ws);
@@ -1509,7 +1528,8 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
     if (l == 0) st_rlx32(&d->files[file].streams[rslot].marker, mark == ~0ull ? GFS_NO_MARKER : (uint32_t)mark);
   }
   if (l == 0)
-    trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, (near & 0xffu) | (hist << 8) | (rule << 24), wn, ws);
+    trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, (near & 0xffu) | (hist << 8) | (rule << 24), wn,
+             ws | ((uint64_t)req << 32));
   uint64_t cws = ws, cwe = ws + wn;
   {
     uint64_t lo_b = cl_on && cl_hi <= p ? cl_hi : 0;
@@ -1526,7 +1546,7 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
   uint64_t* claim = &d->claims[file].e[cj];
   if (l == 0) st_rlx(claim, (cws << 32) | ((cwe - cws) << 1) | 1ull);
   const uint64_t tu0 = wall_clock64();
-  unlock_file_wave(d, file, ticket, cws, cwe);
+  unlock_file_wave(d, file, ticket, cws, cwe, true, qv);
   __builtin_amdgcn_s_setprio(0);
   const uint64_t tl2 = wall_clock64();
   if (l == 0) {
@@ -2381,6 +2401,7 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
     if (tid == 0) bcount(bs, GFS_T_COPY, wall_clock64() - tb0);
     __syncthreads();
   }
+  if (tid == 0) bs->read_last = plast;   /* read by wave 0's miss path, after this store */
   for (uint64_t p = pfirst; p <= plast; ++p) {
     if (batched && p - pfirst < 64 && bs->bframe[p - pfirst] >= 0) continue;
     const uint64_t ta0 = wall_clock64();

@@ -44,7 +44,7 @@ class NaiveModel:
         self.tick[file_id] = 0
         self.last_misses[file_id] = []
 
-    def _window(self, file_id, p):
+    def _window(self, file_id, p, want):
         if self.cap == 0 or self.advice[file_id] == "random":
             return p, 1
         self.tick[file_id] = self.tick[file_id] + 1
@@ -91,10 +91,14 @@ class NaiveModel:
             start = p - p % n
         elif behind > 0:
             n = 2 * behind
+            if n < want:          # never less than the rest of the read that missed
+                n = want
         elif p == 0 or self.advice[file_id] == "sequential":
             n = self.w0
+            if n < want:
+                n = want
         else:
-            n = 1
+            n = want              # a new stream reads what was asked for, at least one page
         if n > self.cap:
             n = self.cap
         if n < 1:
@@ -146,7 +150,9 @@ class NaiveModel:
                 self.frames[i][5] = 0
                 self.log.append(("HIT", block, file_id, page, i))
             else:
-                start, n = self._window(file_id, page)
+                # pages of this read from `page` to its end
+                want = (last_byte - 1) // P - page + 1
+                start, n = self._window(file_id, page, want)
                 if start + n > npages:
                     n = npages - start
                 self.log.append(("MISS", block, file_id, page, start, n))

@@ -29,10 +29,13 @@ new stream replaces an empty slot or the least recently used one (lowest index
 on ties): if at least ``near_min`` of the file's last ``recent`` misses lie within
 ``near_pages`` pages of p (defaults 3, 64, 64), many blocks are reading the file in aggregate
 (interleaved strides) and the
-window is the cap-sized chunk aligned around p; else [p, p + w) with w = min(2 h,
-cap) if the h >= 1 pages right before p are already cached (context readahead:
+window is the cap-sized chunk aligned around p; else [p, p + w) with w = min(max(2 h,
+r), cap) if the h >= 1 pages right before p are already cached (h counted up to
+ceil(cap / 2), beyond which the window no longer changes; context readahead:
 Linux's way of following readers that interleave on one descriptor, Sec. 2.3); else
-w = W0 if p == 0 or the file is SEQUENTIAL, else 1. Windows are clamped to EOF; the
+w = min(max(W0 if p == 0 or the file is SEQUENTIAL else 1, r), cap); r is the number
+of pages of the missing read from p to its end (a prefetcher reads at least what the
+caller asked for, Sec. 2.3). Windows are clamped to EOF; the
 block fetches the run of unmapped window pages that contains p (pages beyond a
 mapped page are left for later demand, so a request has no holes); the demanded
 page is allocated first, then the rest of the run in ascending order; one host
@@ -176,9 +179,9 @@ class PolicyModel:
         return max(0, min(self.P, self.files[file_id].size - page * self.P))
 
     # ---- readahead decision (one per miss) -----------------------------------------------
-    def ra_decide(self, file_id: int, p: int) -> Tuple[int, int]:
-        """The window for a demand miss at p; the stream it set is left in self.last_stream
-        (None when readahead is off)."""
+    def ra_decide(self, file_id: int, p: int, req: int = 1) -> Tuple[int, int]:
+        """The window for a demand miss at p, made by a read whose pages from p on are `req`;
+        the stream it set is left in self.last_stream (None when readahead is off)."""
         fs = self.files[file_id]
         self.last_stream = None
         if self.cap == 0 or fs.advice == ADV_RANDOM or not fs.read_only:
@@ -200,9 +203,10 @@ class PolicyModel:
                 self.decisions.append((near, 0, RULE_ZONE))
                 return ws, wn
         # context: the pages right behind p are already cached (read or being read by other
-        # blocks), so p continues a sequential stream that no slot tracks
+        # blocks), so p continues a sequential stream that no slot tracks; counted up to
+        # ceil(cap / 2), the most that can change the window min(2 h, cap)
         h = 0
-        while h < self.cap and p - 1 - h >= 0 and (file_id, p - 1 - h) in self.map:
+        while h < (self.cap + 1) // 2 and p - 1 - h >= 0 and (file_id, p - 1 - h) in self.map:
             h += 1
         victim = None
         for s in fs.streams:                       # an empty slot first (lowest index)
@@ -218,11 +222,13 @@ class PolicyModel:
             ws = p // wn * wn
             self.decisions.append((near, 0, RULE_AGGREGATE))
         elif h > 0:
-            wn = min(2 * h, self.cap)
+            # at least the rest of the read that missed (Sec. 2.3: the prefetcher reads more
+            # than the caller asked for, never less)
+            wn = min(max(2 * h, req), self.cap)
             ws = p
             self.decisions.append((near, h, RULE_CONTEXT))
         else:
-            wn = self.W0 if (p == 0 or fs.advice == ADV_SEQUENTIAL) else 1
+            wn = max(self.W0 if (p == 0 or fs.advice == ADV_SEQUENTIAL) else 1, req)
             ws = p
             self.decisions.append((near, 0, RULE_NEW))
         wn = max(1, min(wn, self.cap))
@@ -263,8 +269,9 @@ class PolicyModel:
         return None
 
     # ---- one page access ------------------------------------------------------------------
-    def access(self, block: int, file_id: int, p: int) -> int:
-        """Serve page p of file_id for a block; returns the frame (pinned, then unpinned)."""
+    def access(self, block: int, file_id: int, p: int, req: int = 1) -> int:
+        """Serve page p of file_id for a block, as page 1 of the `req` pages from p to the end
+        of the block's read; returns the frame (pinned, then unpinned)."""
         f = self.map.get((file_id, p))
         if f is not None:
             fr = self.frames[f]
@@ -286,7 +293,7 @@ class PolicyModel:
                 self.advance(block, file_id, p)
             return f
         self.misses += 1
-        ws, wn = self.ra_decide(file_id, p)
+        ws, wn = self.ra_decide(file_id, p, req)
         wn = min(wn, self.npages(file_id) - ws)
         self.events.append(("MISS", block, file_id, p, ws, wn))
         marker = -1
@@ -398,8 +405,9 @@ class PolicyModel:
         if size <= 0 or offset >= fsize:
             return 0
         end = min(offset + size, fsize)
-        for p in range(offset // self.P, (end - 1) // self.P + 1):
-            self.access(block, file_id, p)
+        last = (end - 1) // self.P
+        for p in range(offset // self.P, last + 1):
+            self.access(block, file_id, p, last - p + 1)
         self.complete(block)
         self.delivered_bytes += end - offset
         return end - offset

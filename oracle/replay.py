@@ -27,7 +27,8 @@ and replays it on the CPU:
   of allocated pages inside the window, starting with the demanded page.
 
 Events are tuples:
-  ("MISS", block, file, page, ws, wn, packed)      packed = near | h << 8 | rule << 24
+  ("MISS", block, file, page, ws, wn, packed[, req])   packed = near | h << 8 | rule << 24,
+        req = pages of the missing read from page on (1 when absent)
   ("HAND", ticket, frame, action, vfile, vpage, vra, seen, block)
         seen = ref | pinned << 1 | lost race << 2 | state << 3 (0 free, 1 claimed, 2 filling,
         3 valid)
@@ -118,7 +119,8 @@ def replay_readahead(events, ra_init: int, ra_cap: int, streams: int,
     for e in events:
         if e[0] != "MISS":
             continue
-        _, blk, fid, p, ws, wn, packed = e
+        blk, fid, p, ws, wn, packed = e[1:7]
+        req = e[7] if len(e) > 7 else 1
         near, h, rule = packed & 0xFF, (packed >> 8) & 0xFFFF, packed >> 24
         npages = (files[fid] + page_size - 1) // page_size
         if ra_cap == 0 or advice.get(fid) == "random":
@@ -150,14 +152,15 @@ def replay_readahead(events, ra_init: int, ra_cap: int, streams: int,
                 exp_rule, exp_h = RULE_AGGREGATE, 0
             else:
                 # the cached history behind p is the trace's; it cannot exceed the pages
-                # behind p or the cap, and it sizes the window exactly
-                _check(h <= min(p, ra_cap), f"context decision at {p}: history {h} out of range")
+                # behind p or ceil(cap / 2) (where the count stops), and it sizes the window
+                _check(h <= min(p, (ra_cap + 1) // 2), f"context decision at {p}: history {h} out of range")
                 exp_h = h
+                # either window covers at least the rest of the read that missed
                 if h > 0:
-                    exp_wn, exp_rule = min(2 * h, ra_cap), RULE_CONTEXT
+                    exp_wn, exp_rule = min(max(2 * h, req), ra_cap), RULE_CONTEXT
                 else:
                     w0 = ra_init if (p == 0 or advice.get(fid) == "sequential") else 1
-                    exp_wn, exp_rule = max(1, min(w0, ra_cap)), RULE_NEW
+                    exp_wn, exp_rule = max(1, min(max(w0, req), ra_cap)), RULE_NEW
                 exp_ws = p
             slots[victim] = [True, exp_ws + exp_wn, exp_wn, st["clock"]]
         _check(rule == exp_rule and h == exp_h, f"miss at {p}: rule {rule} h {h}, model rule {exp_rule} h {exp_h}")
@@ -193,7 +196,7 @@ def replay_requests(events) -> int:
                 allocs.append((e[6], e[3]))
             elif e[0] == "REQ":
                 _check(cur is not None, f"block {blk}: request without a miss")
-                _, _b, fid, p, ws, wn, _near = cur
+                fid, p, ws, wn = cur[2:6]
                 # the lanes of one wave append their records in no fixed order; the hand
                 # tickets fix the order in which the run's pages were given frames
                 pages = [q for _, q in sorted(allocs)]

@@ -36,7 +36,7 @@ def decode(ev: np.ndarray):
         elif op == 2:
             out.append(("JOIN", blk, f, p, fr))
         elif op == 3:
-            out.append(("MISS", blk, f, p, b, a))
+            out.append(("MISS", blk, f, p, b & 0xFFFFFFFF, a))   # b: window start | req << 32
         elif op == 4:
             act = _ACTIONS[a & 0xFF]
             x = a >> 8            # victim's prefetched mark | what the hand found << 1
@@ -99,7 +99,7 @@ def decode_replay(ev: np.ndarray):
         blk, f, p, fr, a, b = (int(r["block"]), int(r["file"]), int(r["page"]), int(r["frame"]),
                               int(r["a"]), int(r["b"]))
         if op == 3:
-            out.append(("MISS", blk, f, p, b, a, fr))
+            out.append(("MISS", blk, f, p, b & 0xFFFFFFFF, a, fr, max(1, b >> 32)))
         elif op == 4:
             act = _ACTIONS[a & 0xFF]
             x = a >> 8

@@ -122,6 +122,43 @@ def test_serialized_trace_matches_model(name, ra_pages, det, quota, data_dir, cu
     _compare_traces(ev, model, st)
 
 
+@pytest.mark.parametrize("pattern,ra_pages,det", [
+    ("strided", 16, DEFAULT_DET), ("random", 16, DEFAULT_DET), ("random", 16, (64, 64, 65)),
+    ("random", 8, (8, 4, 2)),
+])
+def test_multipage_serialized_trace_matches_model(pattern, ra_pages, det, data_dir, cuda):
+    """Reads of 8 pages of 4 KiB (32 KiB, unaligned to the read size in the random pattern,
+    some past the end of the file): a window opened by a new stream or by the context rule
+    covers at least the rest of the read that missed, on the device as in the model, miss
+    for miss, hand visit for hand visit."""
+    import dataclasses
+    wl = configs.get("f3_small")
+    if pattern == "random":
+        wl = dataclasses.replace(wl, offsets=configs.random_page_offsets(wl.blocks, wl.blocks * 13, 10, 4096, 777))
+    path = configs.ensure_file(wl.file, data_dir)
+    _say(f"serialized multi-page {pattern} ra_pages={ra_pages} detector={det}")
+    cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=ra_pages * wl.page_size,
+                             ra_init_pages=4, streams=8, trace_level=2, trace_capacity=1 << 20,
+                             timeout_s=20, detector=det, quota_blocks=1)
+    with gfs.PageCache(cfg) as cache:
+        fid = cache.open(path)
+        res = runner.run_list(cache, fid, wl.offsets, wl.read_size, wl.consumer, serialize=True)
+        st = cache.stats()
+        ev = cache.trace()
+    exp_out, exp_deliv = expected(wl, path)
+    np.testing.assert_array_equal(res.status, exp_deliv)
+    np.testing.assert_array_equal(res.out, exp_out)
+    C = wl.cache_bytes // wl.page_size
+    model = PolicyModel(C, wl.page_size, ra_init_pages=4, ra_cap_pages=ra_pages, streams_per_file=8,
+                        recent=det[0], near_pages=det[1], near_min=det[2])
+    model.open(fid, wl.file.size)
+    run_serialized(model, fid, wl.offsets, wl.read_size)
+    _compare_traces(ev, model, st)
+    # the device logged each miss's read length (pages from the missed page on)
+    reqs = [int(r["b"]) >> 32 for r in ev if int(r["op"]) == gfs.EV_MISS]
+    assert max(reqs) > 1
+
+
 @pytest.mark.parametrize("name,ra_pages", [
     ("c1_small", 8), ("c3a_small", 16), ("c3b_small", 8), ("c2_small", 16), ("c3c_small", 8),
 ])

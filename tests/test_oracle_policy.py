@@ -242,6 +242,40 @@ def test_context_readahead_follows_a_stream_no_slot_tracks():
     assert _misses(m.events)[-1][4:] == (200, 1)
 
 
+def test_a_read_of_several_pages_gets_them_in_one_window():
+    # hand-worked, one stream slot, cap 16 (Sec. 2.3: the prefetcher reads at least what the
+    # caller asked for): an 8-page read at page 100 opens a new stream with the 8 pages
+    # [100, 108) instead of one page on probation, and its other 7 pages are hits (the
+    # prefetch is synchronous); the next 8-page read at 108 is in the stream's zone and doubles it to
+    # [108, 124); a 40-page read at 300 asks for more than the cap: [300, 316), then the
+    # zone takes it on, [316, 332) and [332, 348), three requests for the 40 pages
+    m = PolicyModel(nframes=256, page_size=4096, ra_init_pages=4, ra_cap_pages=16, streams_per_file=1)
+    m.open(0, 1 << 22)
+    m.gread(0, 0, 100 * 4096, 8 * 4096)
+    assert [(e[4], e[5]) for e in _misses(m.events)] == [(100, 8)]
+    assert [e for e in m.events if e[0] == "REQ"] == [("REQ", 0, 100, 8)]
+    assert sum(1 for e in m.events if e[0] == "HIT") == 7
+    m.gread(0, 0, 108 * 4096, 8 * 4096)
+    assert [(e[4], e[5]) for e in _misses(m.events)][-1] == (108, 16)
+    m.gread(0, 0, 300 * 4096, 40 * 4096)
+    assert [(e[4], e[5]) for e in _misses(m.events)][-3:] == [(300, 16), (316, 16), (332, 16)]
+    assert [r for _, _, r in m.decisions] == [4, 1, 4, 1, 1]   # new, zone, new, zone, zone
+
+
+def test_context_window_covers_the_rest_of_the_read():
+    # hand-worked, one slot, cap 16: a 4-page read at 0 opens [0, 4) (W0 = 4 = the read);
+    # a 1-page read at 100 takes the only slot; a 12-page read at 4 is outside every zone
+    # with history 4 behind it: 2h = 8 pages would not cover the read, so the window is
+    # [4, 16), the 12 pages asked for
+    m = PolicyModel(nframes=256, page_size=4096, ra_init_pages=4, ra_cap_pages=16, streams_per_file=1)
+    m.open(0, 1 << 22)
+    m.gread(0, 0, 0, 4 * 4096)
+    m.gread(0, 0, 100 * 4096, 4096)
+    m.gread(0, 0, 4 * 4096, 12 * 4096)
+    assert [(e[4], e[5]) for e in _misses(m.events)] == [(0, 4), (100, 1), (4, 12)]
+    assert m.decisions[-1] == (1, 4, 3)   # one near miss (page 0), history 4, the context rule
+
+
 def test_aggregate_read_takes_aligned_cap_chunk():
     # hand-worked, one slot, cap 16 (near = within 64 pages): misses at 10, 30, 50 each start a
     # probation stream; at 70 three of the last misses are near, so the block takes the aligned
@@ -347,20 +381,22 @@ def test_async_window_runs_ahead_of_synchronous():
 
 
 def test_async_large_read_joins_its_own_window():
-    # one block reading 32 pages at a time: a read reaches the window it triggered earlier in
-    # the same read, joins its frames (they are still being filled) and triggers the next
+    # one block reading 32 pages at a time (cap 16): the first read's miss at 0 takes the cap,
+    # [0, 16) (the read asks for 32); its marker page 1 issues [16, 32); the read reaches that
+    # window while it is still being filled, joins its first page, whose mark issues [32, 48)
     m = PolicyModel(nframes=512, page_size=1 << 16, ra_init_pages=4, ra_cap_pages=16, ra_async=True)
     m.open(0, 96 << 16)
     for k in range(3):
         m.gread(0, 0, (32 * k) << 16, 32 << 16)
     ev = [e for e in m.events if e[0] in ("MISS", "ADV", "JOIN")]
-    assert ev[:4] == [("MISS", 0, 0, 0, 0, 4), ("ADV", 0, 0, 1, 4, 8), ("JOIN", 0, 0, 4, ev[2][4]),
-                      ("ADV", 0, 0, 4, 12, 16)]
-    # a read joins only the first page of a window it triggered itself (4, 12, 28 in the first
-    # read, whose last window [44, 60) arrives when it ends; 60 and 92 in the later reads);
-    # all 96 pages delivered, none wasted
+    assert ev[:4] == [("MISS", 0, 0, 0, 0, 16), ("ADV", 0, 0, 1, 16, 16), ("JOIN", 0, 0, 16, ev[2][4]),
+                      ("ADV", 0, 0, 16, 32, 16)]
+    # a read joins only the first page of a window it triggered itself (16 in the first read,
+    # whose last window [32, 48) arrives when it ends; 48 and 80 in the later reads, each
+    # started by the marker of the window the previous read left behind); all 96 pages
+    # delivered, none wasted
     joins = [e[3] for e in m.events if e[0] == "JOIN"]
-    assert joins == [4, 12, 28, 60, 92]
+    assert joins == [16, 48, 80]
     assert m.misses == 1 and m.fetched_pages == 96 and m.wasted_pages == 0
     m.check_invariants()
 

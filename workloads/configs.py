@@ -122,6 +122,21 @@ def f3() -> Workload:
                     strided_offsets(1024, 8, 128 * KiB), CONSUMER_CHECKSUM)
 
 
+def f3_small() -> Workload:
+    """The small-page shape at a size the oracle finishes in seconds: a 3 MiB + 12 KiB + 40 B
+    file (seed 4, a ragged last page) through a 512 KiB cache of 4 KiB pages (128 frames),
+    8 blocks reading 32 KiB strides b + 8 k (8 pages per read, 13 reads each; the last
+    stride is partial and some reads land past the end), per-block checksums."""
+    size = 3 * MiB + 12 * KiB + 40
+    f = FileSpec("f3s_seed4.bin", 4, size)
+    stride = 32 * KiB
+    nstrides = (size + stride - 1) // stride
+    blocks = 8
+    reads = (nstrides + blocks - 1) // blocks
+    return Workload("f3_small", f, 4 * KiB, 512 * KiB, blocks, 256, stride,
+                    strided_offsets(blocks, reads, stride), CONSUMER_CHECKSUM)
+
+
 def _c3_file() -> FileSpec:
     return FileSpec("c3_seed3_4GiB.bin", 3, 4 * GiB)
 
@@ -235,7 +250,7 @@ REGISTRY = {
     "c3a": lambda: c3("a"), "c3b": lambda: c3("b"), "c3c": lambda: c3("c"),
     "c1_small": c1_small, "c2_small": c2_small,
     "c3a_small": lambda: c3_small("a"), "c3b_small": lambda: c3_small("b"),
-    "c3c_small": lambda: c3_small("c"), "f3": f3,
+    "c3c_small": lambda: c3_small("c"), "f3": f3, "f3_small": f3_small,
 }
 
 
