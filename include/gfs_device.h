@@ -1653,7 +1653,7 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
                                   BlockState* bs, uint32_t bid) {
   const uint64_t key = page_key(file, p);
   const uint32_t l = lane();
-  const uint64_t t0 = wall_clock64();
+  uint64_t t0 = 0;   /* the wait deadline's start: read at the first step that may wait */
   uint32_t naps = 0;
   /* untraced runs check a hit's tag with its copy (frame_pin_fast) */
   const bool fast = d->trace_level == 0;
@@ -1678,6 +1678,7 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
         }
         return;
       }
+      if (t0 == 0) t0 = wall_clock64();
       if (r == PIN_VALID) {
         if (l == 0) {
           bcount(bs, GFS_C_HITS, 1);
@@ -1709,6 +1710,10 @@ __device__ void acquire_page_wave(const gfs_dev* d, uint32_t file, uint64_t p, u
         return;
       }
       if (l == 0) bcount(bs, GFS_C_RETRIES, 1);
+    }
+    if (t0 == 0) t0 = wall_clock64();
+    if (f >= 0 && (uint32_t)f != kReserved) {
+      /* the pin lost a race (the frame changed under it): wait a little and look again */
     } else if (f < 0 && d->policy == GFS_POLICY_PRIVATE) {
       const int r = miss_private_wave(d, file, p, key, fsize, bs, bid, t0, naps);
       if (r == 0) return;
@@ -2330,7 +2335,7 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
   const bool batched = plast > pfirst && d->trace_level == 0;
   if (batched) {
     const uint32_t cnt = (uint32_t)((plast - pfirst + 1) < 64 ? (plast - pfirst + 1) : 64);
-    const uint64_t tb0 = wall_clock64();
+    const uint64_t tb0 = d->page_timers ? wall_clock64() : 0;
     if (tid < 64) {
       int32_t f = -1;
       if (tid < cnt) {
@@ -2398,13 +2403,14 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
     }
     __syncthreads();
     if (tid < cnt && bs->bframe[tid] >= 0) frame_unpin(d, (uint32_t)bs->bframe[tid]);
-    if (tid == 0) bcount(bs, GFS_T_COPY, wall_clock64() - tb0);
+    if (tid == 0 && d->page_timers) bcount(bs, GFS_T_COPY, wall_clock64() - tb0);
     __syncthreads();
   }
   if (tid == 0) bs->read_last = plast;   /* read by wave 0's miss path, after this store */
   for (uint64_t p = pfirst; p <= plast; ++p) {
     if (batched && p - pfirst < 64 && bs->bframe[p - pfirst] >= 0) continue;
-    const uint64_t ta0 = wall_clock64();
+    const bool ptm = d->page_timers != 0;
+    const uint64_t ta0 = ptm ? wall_clock64() : 0;
     if (tid < 64) acquire_page_wave(d, (uint32_t)fd, p, fsize, bs, bid);
     __syncthreads();
     if (bs->pull == 5) {
@@ -2457,7 +2463,7 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
       __syncthreads();
       break;
     }
-    const uint64_t ta1 = wall_clock64();
+    const uint64_t ta1 = ptm ? wall_clock64() : 0;
     const uint64_t pbase = p << sh_bits;
     const uint64_t lo = offset > pbase ? offset : pbase;
     const uint64_t hi = end < pbase + P ? end : pbase + P;
@@ -2491,11 +2497,15 @@ __device__ __attribute__((always_inline)) int64_t gread(const gfs_dev* d, int fd
         frame_pin_bits(d, (uint32_t)f, bs->pinw);
         bcount(bs, GFS_C_HITS, 1);
       }
-      const uint64_t ta2 = wall_clock64();
-      frame_unpin(d, (uint32_t)f);
-      bcount(bs, GFS_T_ACQUIRE, ta1 - ta0);
-      bcount(bs, GFS_T_COPY, ta2 - ta1);
-      bcount(bs, GFS_T_UNPIN, wall_clock64() - ta2);
+      if (ptm) {
+        const uint64_t ta2 = wall_clock64();
+        frame_unpin(d, (uint32_t)f);
+        bcount(bs, GFS_T_ACQUIRE, ta1 - ta0);
+        bcount(bs, GFS_T_COPY, ta2 - ta1);
+        bcount(bs, GFS_T_UNPIN, wall_clock64() - ta2);
+      } else {
+        frame_unpin(d, (uint32_t)f);
+      }
     }
     if (trig) {
       /* this access took its stream's marker: finish the block's previous asynchronous

@@ -198,7 +198,7 @@ typedef struct gfs_dev {
   uint32_t ra_async;            /* 1: marker-triggered (asynchronous) readahead */
   uint32_t sync_slots;          /* ring slots [0, sync_slots) take ticketed requests; the rest are
                                    the asynchronous windows' own (taken without waiting) */
-  uint32_t pad_dev1;
+  uint32_t page_timers;         /* gfs_config.page_timers */
   uint64_t max_req_bytes;
   uint64_t timeout_ticks;       /* wall_clock64 ticks */
   uint8_t* frames;

@@ -334,6 +334,7 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   h.ra_near_min = cfg->ra_near_min;
   h.ra_quota_blocks = quota_blocks;
   h.ra_async = cfg->ra_async;
+  h.page_timers = cfg->page_timers ? 1u : 0u;
   c->cfg.ra_quota_blocks = quota_blocks;   /* gfs_get_config reports the resolved count */
   h.max_req_bytes = L.max_req_bytes;
   c->clock_khz = khz;

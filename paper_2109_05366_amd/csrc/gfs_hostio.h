@@ -77,6 +77,9 @@ struct HostIo {
   uint32_t io_backend = GFS_IO_PREAD;
   uint32_t io_depth = 1;            /* GFS_IO_URING: reads in flight per thread, 1..256 */
   uint64_t io_chunk_bytes = 0;      /* piece size, a multiple of kDirectAlign */
+  uint64_t min_piece_bytes = 256 << 10;   /* GFS_IO_PREAD: the smallest piece a request is cut
+                                             into when threads would otherwise sit idle (a
+                                             multiple of kDirectAlign) */
   uint64_t max_req_bytes = 0;       /* staging bytes per slot */
   gfs_rpc_slot* ring = nullptr;     /* rpc_slots slots */
   uint8_t* staging = nullptr;       /* rpc_slots * max_req_bytes */
@@ -93,6 +96,8 @@ struct HostIo {
   std::mutex qmu;
   std::deque<Chunk> queue;
   std::atomic<uint32_t> queued{0};
+  std::atomic<uint32_t> busy{0};    /* GFS_IO_PREAD threads reading a piece right now */
+  std::atomic<uint64_t> host_pieces{0};   /* pieces read (a request is one or more) */
 
   /* per-slot state; -ENOMEM if it cannot be allocated */
   int init() {
@@ -192,6 +197,7 @@ inline void run_chunk(HostIo* c, const Chunk& ch, uint8_t* bounce) {
     r = read_span(fd, hf->direct, c->staging + (uint64_t)ch.slot * c->max_req_bytes + ch.dst,
                   ch.off, ch.len, bounce, c->io_chunk_bytes);
     c->host_read_ns.fetch_add(now_ns() - t0, std::memory_order_relaxed);
+    c->host_pieces.fetch_add(1, std::memory_order_relaxed);
   }
   finish_chunk(c, ch, r);
 }
@@ -287,7 +293,22 @@ inline bool claim_request(HostIo* c, int idx, uint32_t* pos, Chunk* first_chunk)
   gfs_rpc_slot* rs = &c->ring[s];
   rs->t_claim_ns = now_ns();
   const uint64_t off = rs->offset, len = rs->length;
-  const uint64_t n = len > c->max_req_bytes ? 0 : (len + chunk - 1) / chunk;
+  /* pieces of io_chunk_bytes; but when fewer pieces than idle threads (this one included)
+     would result, smaller ones, down to min_piece_bytes, so that every idle thread reads a
+     share: a storage device serves more reads in flight faster, and a readahead window is
+     otherwise read by one thread while others wait for work */
+  uint64_t piece = chunk;
+  if (c->io_backend == GFS_IO_PREAD && len > c->min_piece_bytes) {
+    const uint32_t nt = c->host_threads;
+    const uint32_t taken = c->busy.load(std::memory_order_relaxed) + c->queued.load(std::memory_order_relaxed);
+    const uint32_t idle = nt > taken ? nt - taken : 1u;
+    if (idle > 1) {
+      uint64_t share = (len + idle - 1) / idle;
+      share = (share + c->min_piece_bytes - 1) / c->min_piece_bytes * c->min_piece_bytes;
+      if (share < piece) piece = share;
+    }
+  }
+  const uint64_t n = len > c->max_req_bytes ? 0 : (len + piece - 1) / piece;
   Track& tr = c->track[s];
   tr.total.store(0, std::memory_order_relaxed);
   tr.err.store(n == 0 && len ? -EINVAL : 0, std::memory_order_relaxed);
@@ -295,12 +316,12 @@ inline bool claim_request(HostIo* c, int idx, uint32_t* pos, Chunk* first_chunk)
   if (n > 1) {
     std::lock_guard<std::mutex> g(c->qmu);
     for (uint64_t i = 1; i < n; ++i) {
-      const uint64_t o = i * chunk;
-      c->queue.push_back({s, gen, off + o, (len - o) < chunk ? (len - o) : chunk, o});
+      const uint64_t o = i * piece;
+      c->queue.push_back({s, gen, off + o, (len - o) < piece ? (len - o) : piece, o});
     }
     c->queued.fetch_add((uint32_t)(n - 1), std::memory_order_relaxed);
   }
-  *first_chunk = {s, gen, off, n ? (len < chunk ? len : chunk) : 0, 0};
+  *first_chunk = {s, gen, off, n ? (len < piece ? len : piece) : 0, 0};
   return true;
 }
 
@@ -319,7 +340,9 @@ inline void io_thread(HostIo* c, int idx) {
   Chunk ch;
   while (!c->stop.load(std::memory_order_relaxed)) {
     if (pop_chunk(c, &ch)) {
+      c->busy.fetch_add(1, std::memory_order_relaxed);
       run_chunk(c, ch, bounce);
+      c->busy.fetch_sub(1, std::memory_order_relaxed);
       continue;
     }
     if (!claim_request(c, idx, &pos, &ch)) {
@@ -330,7 +353,9 @@ inline void io_thread(HostIo* c, int idx) {
       c->spins[idx].store(spins, std::memory_order_relaxed);
       first = false;
     }
+    c->busy.fetch_add(1, std::memory_order_relaxed);
     run_chunk(c, ch, bounce);
+    c->busy.fetch_sub(1, std::memory_order_relaxed);
   }
   free(bounce);
 }

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgfs.so")
 
-GFS_ABI_VERSION = 4
+GFS_ABI_VERSION = 5
 GFS_O_RDONLY = 0
 GFS_ADV_NORMAL, GFS_ADV_RANDOM, GFS_ADV_SEQUENTIAL = 0, 1, 2
 GFS_DIRECT_OFF, GFS_DIRECT_ON, GFS_DIRECT_PREFER = 0, 1, 2
@@ -40,6 +40,7 @@ class gfs_config(C.Structure):
         ("io_chunk_bytes", C.c_uint32), ("max_files", C.c_uint32),
         ("ra_recent", C.c_uint32), ("ra_near_pages", C.c_uint32), ("ra_near_min", C.c_uint32),
         ("ra_quota_blocks", C.c_uint32), ("ra_async", C.c_uint32), ("io_depth", C.c_uint32),
+        ("page_timers", C.c_uint32),
     ]
 
 

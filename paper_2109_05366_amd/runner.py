@@ -15,7 +15,8 @@ def make_config(page_size: int, cache_bytes: int, ra_cap_bytes: int = 16 << 20, 
                 timeout_s: float = 30.0, policy: int = gfs.GFS_POLICY_SHARED,
                 private_slots: int = 512, io_chunk_bytes: int = 2 << 20, max_files: int = 64,
                 detector=(64, 64, 3), quota_blocks: int = 0, timeout_ns: int = 0,
-                io_backend: int = gfs.GFS_IO_PREAD, io_depth: int = 8, ra_async: int = 0) -> gfs.gfs_config:
+                io_backend: int = gfs.GFS_IO_PREAD, io_depth: int = 8, ra_async: int = 0,
+                page_timers: int = 0) -> gfs.gfs_config:
     """detector = (ra_recent, ra_near_pages, ra_near_min); quota_blocks = the thrash guard's
     resident-block count (0: the device's, 1: off); timeout_ns overrides timeout_s; io_depth =
     reads in flight per host thread with the io_uring backend; ra_async = 1 for marker-triggered
@@ -29,7 +30,8 @@ def make_config(page_size: int, cache_bytes: int, ra_cap_bytes: int = 16 << 20, 
         trace_capacity=trace_capacity, wait_timeout_ns=int(timeout_ns or timeout_s * 1e9), policy=policy,
         private_slots=private_slots, io_chunk_bytes=io_chunk_bytes, max_files=max_files,
         ra_recent=detector[0], ra_near_pages=detector[1], ra_near_min=detector[2],
-        ra_quota_blocks=quota_blocks, io_backend=io_backend, io_depth=io_depth, ra_async=ra_async)
+        ra_quota_blocks=quota_blocks, io_backend=io_backend, io_depth=io_depth, ra_async=ra_async,
+        page_timers=page_timers)
 
 
 @dataclasses.dataclass

@@ -9,7 +9,7 @@
 // thread). Error paths: a request for an unregistered file gets -EBADF, reads that cross the
 // end of the file come back short.
 //
-// usage: hostio_check DIR BACKEND HOST_THREADS SLOTS PRODUCERS REQUESTS DIRECT [DEPTH]
+// usage: hostio_check DIR BACKEND HOST_THREADS SLOTS PRODUCERS REQUESTS DIRECT [DEPTH [CHUNK_KIB MIN_PIECE_KIB]]
 // prints one summary line; exit status 0 when every check held, 5 when io_uring is asked for
 // and the kernel refuses to create one.
 #include <fcntl.h>
@@ -119,15 +119,19 @@ void producer(Shared* sh, int id, int nreq, bool partitioned) {
 }  // namespace
 
 int main(int argc, char** argv) {
-  if (argc != 8 && argc != 9) {
-    fprintf(stderr, "usage: %s DIR BACKEND HOST_THREADS SLOTS PRODUCERS REQUESTS DIRECT [DEPTH]\n", argv[0]);
+  if (argc != 8 && argc != 9 && argc != 11) {
+    fprintf(stderr, "usage: %s DIR BACKEND HOST_THREADS SLOTS PRODUCERS REQUESTS DIRECT [DEPTH [CHUNK_KIB MIN_PIECE_KIB]]\n", argv[0]);
     return 2;
   }
   const std::string dir = argv[1];
   const uint32_t backend = (uint32_t)atoi(argv[2]), threads = (uint32_t)atoi(argv[3]), slots = (uint32_t)atoi(argv[4]);
   const int producers = atoi(argv[5]), nreq = atoi(argv[6]);
   const bool direct = atoi(argv[7]) != 0;
-  const uint32_t depth = argc == 9 ? (uint32_t)atoi(argv[8]) : 4u;
+  const uint32_t depth = argc >= 9 ? (uint32_t)atoi(argv[8]) : 4u;
+  /* optional: piece size and smallest piece in KiB (default 64 and the library's 256: no
+     request is then cut finer than its 64 KiB pieces) */
+  const uint64_t chunk_kib = argc >= 10 ? (uint64_t)atoi(argv[9]) : 64u;
+  const uint64_t min_piece_kib = argc >= 11 ? (uint64_t)atoi(argv[10]) : 256u;
   if (backend == GFS_IO_URING && gfs_hostio::uring_available() != 0) {
     printf("io_uring unavailable\n");
     return 5;
@@ -149,7 +153,8 @@ int main(int argc, char** argv) {
   io.host_threads = threads;
   io.io_backend = backend;
   io.io_depth = depth;
-  io.io_chunk_bytes = 64 << 10;                 // pieces smaller than a request: several threads per request
+  io.io_chunk_bytes = chunk_kib << 10;          // pieces smaller than a request: several threads per request
+  io.min_piece_bytes = min_piece_kib << 10;
   io.max_req_bytes = kMaxPages * kPage;
   io.ring = (gfs_rpc_slot*)aligned_alloc(128, sizeof(gfs_rpc_slot) * slots);
   io.staging = (uint8_t*)aligned_alloc(4096, io.max_req_bytes * slots);
@@ -173,11 +178,12 @@ int main(int argc, char** argv) {
                   io.host_bytes.load() == sh.bytes.load() && io.host_errors.load() >= sh.ebadf.load() &&
                   (sh.ebadf == 0 || io.host_last_errno.load() == EBADF);
   printf("requests %llu of %llu, bytes %llu, ebadf %llu, short %llu, failures %llu, host_requests %llu, "
-         "host_errors %llu, direct %d -> %s\n",
+         "host_errors %llu, pieces %llu, direct %d -> %s\n",
          (unsigned long long)sh.requests.load(), (unsigned long long)want, (unsigned long long)sh.bytes.load(),
          (unsigned long long)sh.ebadf.load(), (unsigned long long)sh.short_reads.load(),
          (unsigned long long)sh.failures.load(), (unsigned long long)io.host_requests.load(),
-         (unsigned long long)io.host_errors.load(), files[0].direct ? 1 : 0, ok ? "ok" : "FAILED");
+         (unsigned long long)io.host_errors.load(), (unsigned long long)io.host_pieces.load(),
+         files[0].direct ? 1 : 0, ok ? "ok" : "FAILED");
   for (int f = 0; f < 2; ++f) close(files[f].fd.load());
   free(io.ring);
   free(io.staging);

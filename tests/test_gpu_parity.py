@@ -604,6 +604,29 @@ def test_reads_only_consumer_leaves_each_blocks_last_read(ra_pages, data_dir, cu
     assert st["delivered_bytes"] == 2 * int(exp_deliv.sum())
 
 
+@pytest.mark.parametrize("timers", [0, 1])
+def test_page_timers_only_when_asked(timers, data_dir, cuda):
+    """The per-page split of gread's time (acquire, copy-out, unpin) is measured only in a
+    context created with page_timers; the data are the same either way."""
+    wl = configs.get("c1_small")
+    path = configs.ensure_file(wl.file, data_dir)
+    exp_out, exp_deliv = expected(wl, path)
+    cfg = runner.make_config(wl.page_size, wl.cache_bytes, ra_cap_bytes=16 * wl.page_size, timeout_s=20,
+                             page_timers=timers)
+    with gfs.PageCache(cfg) as cache:
+        fid = cache.open(path)
+        for _ in range(2):   # cold, then all hits
+            res = runner.run_list(cache, fid, wl.offsets, wl.read_size, wl.consumer)
+            np.testing.assert_array_equal(res.status, exp_deliv)
+            np.testing.assert_array_equal(res.out, exp_out)
+        st = cache.stats()
+    split = [st["t_acquire_ns"], st["t_copy_ns"], st["t_unpin_ns"]]
+    if timers:
+        assert min(split) > 0, split
+    else:
+        assert split == [0, 0, 0], split
+
+
 def odata_mod():
     from oracle import data as odata
     return odata

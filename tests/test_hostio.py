@@ -28,23 +28,30 @@ def checker(tmp_path_factory):
     return out
 
 
-@pytest.mark.parametrize("backend,threads,slots,producers,requests,direct,depth", [
-    (0, 4, 8, 16, 150, 1, 1),      # shared ring, more blocks than slots, O_DIRECT where allowed
-    (0, 8, 64, 32, 60, 0, 1),      # shared ring, buffered reads
-    (1, 4, 8, 16, 150, 0, 1),      # the partitioned queue (a block's own slot, one thread per range)
-    (1, 2, 2, 8, 60, 1, 1),
-    (2, 2, 16, 16, 120, 1, 8),     # io_uring: 8 reads in flight per thread, O_DIRECT where allowed
-    (2, 4, 64, 32, 60, 0, 4),      # io_uring, buffered reads
-    (2, 1, 4, 8, 60, 1, 1),        # io_uring, one thread, one read at a time
+@pytest.mark.parametrize("backend,threads,slots,producers,requests,direct,depth,pieces", [
+    (0, 4, 8, 16, 150, 1, 1, ()),  # shared ring, more blocks than slots, O_DIRECT where allowed
+    (0, 8, 64, 32, 60, 0, 1, ()),  # shared ring, buffered reads
+    # whole requests in one piece, cut into 64 KiB shares when threads are idle
+    (0, 8, 8, 4, 120, 1, 1, (512, 64)),
+    (0, 6, 16, 3, 120, 0, 1, (512, 128)),
+    (1, 4, 8, 16, 150, 0, 1, ()),  # the partitioned queue (a block's own slot, one thread per range)
+    (1, 2, 2, 8, 60, 1, 1, ()),
+    (2, 2, 16, 16, 120, 1, 8, ()), # io_uring: 8 reads in flight per thread, O_DIRECT where allowed
+    (2, 4, 64, 32, 60, 0, 4, ()),  # io_uring, buffered reads
+    (2, 1, 4, 8, 60, 1, 1, ()),    # io_uring, one thread, one read at a time
 ])
 def test_ring_engine_serves_every_request_without_races(checker, tmp_path, backend, threads, slots, producers,
-                                                         requests, direct, depth):
+                                                         requests, direct, depth, pieces):
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66")
     r = subprocess.run([checker, str(tmp_path), str(backend), str(threads), str(slots), str(producers),
-                        str(requests), str(direct), str(depth)], capture_output=True, text=True, timeout=300,
-                       env=env)
+                        str(requests), str(direct), str(depth)] + [str(x) for x in pieces],
+                       capture_output=True, text=True, timeout=300, env=env)
     if r.returncode == 5 and "io_uring unavailable" in r.stdout:
         pytest.skip("the kernel refuses io_uring here")
     assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
     assert r.returncode == 0, (r.stdout, r.stderr[-2000:])
     assert r.stdout.strip().endswith("-> ok")
+    if pieces:
+        # requests fit one piece of pieces[0] KiB, yet idle threads cut some into smaller shares
+        got = dict(kv.split(" ", 1) for kv in r.stdout.split(" -> ")[0].split(", "))
+        assert int(got["pieces"]) > int(got["host_requests"]), r.stdout

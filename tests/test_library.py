@@ -37,7 +37,7 @@ def test_config_default_values():
     assert cfg.page_size == 64 << 10 and cfg.cache_bytes == 256 << 20
     assert cfg.ra_init_bytes == 4 * cfg.page_size and cfg.ra_cap_bytes == 16 << 20
     assert cfg.streams_per_file == 8 and cfg.host_threads == 8 and cfg.rpc_slots == 64
-    assert ctypes.sizeof(gfs.gfs_config) == 112
+    assert ctypes.sizeof(gfs.gfs_config) == 120
     assert cfg.policy == gfs.GFS_POLICY_SHARED and cfg.private_slots == 512
     assert cfg.io_chunk_bytes == 2 << 20
     assert gfs.EVENT_DTYPE.itemsize == 32
@@ -125,4 +125,4 @@ def test_metadata_scales_with_max_files():
 def test_detector_defaults():
     cfg = gfs.gfs_config_default()
     assert (cfg.ra_recent, cfg.ra_near_pages, cfg.ra_near_min) == (64, 64, 3)
-    assert cfg.ra_quota_blocks == 0 and cfg.ra_async == 0 and cfg.max_files == 64
+    assert cfg.ra_quota_blocks == 0 and cfg.ra_async == 0 and cfg.max_files == 64 and cfg.page_timers == 0
