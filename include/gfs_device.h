@@ -678,9 +678,31 @@ __device__ __forceinline__ uint32_t ra_cap_eff(const gfs_dev* d) {
   return d->ra_cap < q ? d->ra_cap : (uint32_t)q;
 }
 
-__device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint32_t req, const RaState& st,
-                               uint64_t& ws, uint32_t& wn, uint32_t& near_out, uint32_t& h_out,
-                               uint32_t& rule_out, int& slot_out) {
+/* Wave-collective: how many consecutive pages right behind p are in the table (64 per round),
+ * up to ceil(cap / 2), the most that can change a context window min(2h, cap). The miss path
+ * counts them before it takes the file's miss lock, while it would wait anyway, so the lock's
+ * holder probes no table entries for this: the count is the table as the block saw it when
+ * it missed (with accesses made one at a time, the same as under the lock), and a context
+ * window is sized from it alone. */
+__device__ uint32_t ra_history_wave(const gfs_dev* d, uint32_t file, uint64_t p) {
+  const uint32_t l = lane();
+  const uint32_t hmax = (ra_cap_eff(d) + 1) / 2;
+  uint32_t h = 0;
+  while (h < hmax) {
+    const uint64_t back = (uint64_t)h + 1 + l;
+    bool mapped = false;
+    if (back <= p && h + l < hmax) mapped = pt_present_lane(d, page_key(file, p - back));
+    const uint64_t m = __ballot(mapped);
+    const uint32_t run = (~m == 0ull) ? 64u : (uint32_t)__builtin_ctzll(~m);
+    h += run;
+    if (run < 64) break;
+  }
+  return h < hmax ? h : hmax;
+}
+
+__device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint32_t req, uint32_t hist,
+                               const RaState& st, uint64_t& ws, uint32_t& wn, uint32_t& near_out,
+                               uint32_t& h_out, uint32_t& rule_out, int& slot_out) {
   gfs_file_dev* fe = &d->files[file];
   const uint32_t advice = st.advice;
   ws = p;
@@ -739,20 +761,9 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint
       ws = p - p % cap;
       rule_out = RA_RULE_AGGREGATE;
     } else {
-      /* context: count the consecutive cached pages right behind p (64 per round), up to
-         ceil(cap / 2), the most that can change the window min(2h, cap); a stream that no
-         slot tracks shows up as that history */
-      const uint32_t hmax = (cap + 1) / 2;
-      uint32_t h = 0;
-      while (h < hmax) {
-        const uint64_t back = (uint64_t)h + 1 + l;
-        bool mapped = false;
-        if (back <= p && h + l < hmax) mapped = pt_present_lane(d, page_key(file, p - back));
-        const uint64_t m = __ballot(mapped);
-        const uint32_t run = (~m == 0ull) ? 64u : (uint32_t)__builtin_ctzll(~m);
-        h += run;
-        if (run < 64) break;
-      }
+      /* context: the consecutive cached pages right behind p (hist, counted by
+         ra_history_wave); a stream that no slot tracks shows up as that history */
+      const uint32_t h = hist;
       /* either way the window covers at least the rest of the read that missed (req pages
          from p), as a read larger than a page asks for them all */
       uint32_t w0;
@@ -1453,6 +1464,8 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
   if (d->ra_cap == 0 || ld_rlx32(&d->files[file].advice) == GFS_ADV_RANDOM)
     return miss_one_page_wave(d, file, p, key, fsize, bs, bid, t0, naps);
   const uint32_t l = lane();
+  /* the cached history behind p, counted before the lock (see ra_history_wave) */
+  const uint32_t hist_pre = ra_history_wave(d, file, p);
   const uint64_t tl0 = wall_clock64();
   uint64_t ticket;
   const int lk = lock_file_wave(d, file, key, p, t0, ticket);
@@ -1517,7 +1530,7 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
   uint32_t wn, near, hist, rule;
   int rslot;
   const uint64_t td0 = wall_clock64();
-  ra_decide_wave(d, file, p, req, ras, ws, wn, near, hist, rule, rslot);
+  ra_decide_wave(d, file, p, req, hist_pre, ras, ws, wn, near, hist, rule, rslot);
   const uint64_t td1 = wall_clock64();
   if (l == 0) bcount(bs, GFS_T_DECIDE, td1 - td0);
   if (ws + wn > npages) wn = (uint32_t)(npages - ws);
