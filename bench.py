@@ -333,11 +333,27 @@ def cpu_legs(wl, path):
         raise RuntimeError("oracle differs between one and several processes")
     nbytes = wl.delivered_bytes
     what = "histograms" if wl.consumer else "checksums"
+    # the oracle's policy model (page table, detector, clock) replaying every page access of
+    # the workload in (round, block) order, one thread
+    from oracle.policy import PolicyModel, quota_cap, run_serialized
+    C = wl.cache_bytes // wl.page_size
+    cap = quota_cap(min(wl.ra_cap_bytes // wl.page_size, 1024), C, wl.blocks, 512)
+    model = PolicyModel(C, wl.page_size, ra_init_pages=min(4, cap), ra_cap_pages=cap, streams_per_file=8)
+    model.open(0, wl.file.size)
+    t0 = time.perf_counter()
+    run_serialized(model, 0, wl.offsets, wl.read_size)
+    dtm = time.perf_counter() - t0
+    accesses = model.hits + model.misses + model.joins
     rec = {"value": round(nbytes / dt1 / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
            "sample": f"all {wl.blocks} blocks ({nbytes >> 20} MiB): plain pread + numpy per-block {what}, "
                      f"{dt1:.1f} s on one thread",
            "parallel": {"value": round(nbytes / dtn / 1e9, 3), "unit": "GB/s", "cores": procs,
-                        "sample": f"the same {wl.blocks} blocks split over {procs} processes, {dtn:.1f} s"}}
+                        "sample": f"the same {wl.blocks} blocks split over {procs} processes, {dtn:.1f} s"},
+           "policy_model": {"value": round(len(model.events) / dtm), "unit": "events/s", "cores": 1,
+                            "page_accesses_per_s": round(accesses / dtm),
+                            "sample": f"the oracle's policy model over all {accesses} page accesses of the "
+                                      f"workload in (round, block) order: {len(model.events)} events, "
+                                      f"{model.misses} misses, {dtm:.2f} s"}}
     log(f"cpu oracle: {rec['value']} GB/s on 1 core, {rec['parallel']['value']} GB/s on {procs}")
     return rec, out1
 
