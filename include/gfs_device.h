@@ -633,9 +633,10 @@ __device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticke
  * file is being read in aggregate by many blocks and the window is the cap-sized aligned
  * chunk around p; else the history of cached pages right behind p sizes it (context
  * readahead); with neither, it opens with the initial window at offset 0 or under
- * SEQUENTIAL advice, else with one page. A context or new window covers at least the req
- * pages from p to the end of the read that missed (Sec. 2.3: the prefetcher reads at least
- * what the caller asked for), up to the cap. */
+ * SEQUENTIAL advice, else with one page. The context rule needs more cached history than
+ * the req pages from p to the end of the read that missed (a shorter one may be a random
+ * read next to cached pages), and a context or new window covers at least those req pages
+ * (Sec. 2.3: the prefetcher reads at least what the caller asked for), up to the cap. */
 /* Per lane: the file's detector state, loaded together (lane i: recent miss i, stream
    slot i); the decision below uses it after the caller's acquire fence. */
 struct RaState {
@@ -679,14 +680,17 @@ __device__ __forceinline__ uint32_t ra_cap_eff(const gfs_dev* d) {
 }
 
 /* Wave-collective: how many consecutive pages right behind p are in the table (64 per round),
- * up to ceil(cap / 2), the most that can change a context window min(2h, cap). The miss path
- * counts them before it takes the file's miss lock, while it would wait anyway, so the lock's
- * holder probes no table entries for this: the count is the table as the block saw it when
- * it missed (with accesses made one at a time, the same as under the lock), and a context
- * window is sized from it alone. */
-__device__ uint32_t ra_history_wave(const gfs_dev* d, uint32_t file, uint64_t p) {
+ * up to max(ceil(cap / 2), min(req, cap) + 1): enough to tell whether the history is longer
+ * than the read that missed (req pages from p), and to size a context window min(2h, cap).
+ * The miss path counts them before it takes the file's miss lock, while it would wait
+ * anyway, so the lock's holder probes no table entries for this: the count is the table as
+ * the block saw it when it missed (with accesses made one at a time, the same as under the
+ * lock), and the decision uses it alone. */
+__device__ uint32_t ra_history_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint32_t req) {
   const uint32_t l = lane();
-  const uint32_t hmax = (ra_cap_eff(d) + 1) / 2;
+  const uint32_t cap = ra_cap_eff(d);
+  const uint32_t r = req < cap ? req : cap;
+  const uint32_t hmax = (cap + 1) / 2 > r + 1 ? (cap + 1) / 2 : r + 1;
   uint32_t h = 0;
   while (h < hmax) {
     const uint64_t back = (uint64_t)h + 1 + l;
@@ -764,17 +768,20 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint
       /* context: the consecutive cached pages right behind p (hist, counted by
          ra_history_wave); a stream that no slot tracks shows up as that history */
       const uint32_t h = hist;
-      /* either way the window covers at least the rest of the read that missed (req pages
-         from p), as a read larger than a page asks for them all */
+      /* a history no longer than the read itself may be chance (a random read next to
+         cached pages): only a longer one makes p a stream's continuation. Either way the
+         window covers at least the rest of the read that missed (req pages from p), as a
+         read larger than a page asks for them all */
+      const uint32_t r = req < cap ? req : cap;
       uint32_t w0;
-      if (h > 0) {
+      if (h > r) {
         w0 = 2 * h;
         rule_out = RA_RULE_CONTEXT;
       } else {
         w0 = (p == 0 || advice == GFS_ADV_SEQUENTIAL) ? d->ra_init : 1u;
         rule_out = RA_RULE_NEW;
       }
-      if (w0 < req) w0 = req;
+      if (w0 < r) w0 = r;
       if (w0 > cap) w0 = cap;
       if (w0 < 1) w0 = 1;
       ws = p;
@@ -1464,8 +1471,11 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
   if (d->ra_cap == 0 || ld_rlx32(&d->files[file].advice) == GFS_ADV_RANDOM)
     return miss_one_page_wave(d, file, p, key, fsize, bs, bid, t0, naps);
   const uint32_t l = lane();
+  /* the pages of the read that missed, from p on */
+  const uint64_t rl = bs->read_last;
+  const uint32_t req = rl >= p ? (rl - p + 1 < 0xffffffffull ? (uint32_t)(rl - p + 1) : 0xffffffffu) : 1u;
   /* the cached history behind p, counted before the lock (see ra_history_wave) */
-  const uint32_t hist_pre = ra_history_wave(d, file, p);
+  const uint32_t hist_pre = ra_history_wave(d, file, p, req);
   const uint64_t tl0 = wall_clock64();
   uint64_t ticket;
   const int lk = lock_file_wave(d, file, key, p, t0, ticket);
@@ -1497,9 +1507,6 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
   /* one round: the detector state and the file's window claims; then, ordered after the
      claims, the table probe (a claim cleared after its reservations means they show) */
   const RaState ras = ra_load_lane(d, file);
-  /* the pages of the read that missed, from p on */
-  const uint64_t rl = bs->read_last;
-  const uint32_t req = rl >= p ? (rl - p + 1 < 0xffffffffull ? (uint32_t)(rl - p + 1) : 0xffffffffu) : 1u;
   uint64_t cl = 0;
   if (l < GFS_CLAIMS) cl = ld_rlx(&d->claims[file].e[l]);
   /* the queue slots behind this ticket, read now for the hand-off: a waiter that arrives or

@@ -70,11 +70,14 @@ class NaiveModel:
                 table[i] = [True, start + n, n, now]
                 return start, n
             i += 1
+        # the cached pages right behind p, counted up to one past the cap (enough to compare
+        # them with a read of up to cap pages and to size the window)
         behind = 0
         q = p - 1
-        while q >= 0 and behind < self.cap and _find(self.frames, file_id, q) >= 0:
+        while q >= 0 and behind <= self.cap and _find(self.frames, file_id, q) >= 0:
             behind += 1
             q -= 1
+        asked = want if want < self.cap else self.cap
         slot = -1
         for i in range(len(table)):
             if not table[i][0]:
@@ -89,16 +92,16 @@ class NaiveModel:
         if close >= self.enough:
             n = self.cap
             start = p - p % n
-        elif behind > 0:
+        elif behind > asked:      # more cached history than the read itself: a stream
             n = 2 * behind
-            if n < want:          # never less than the rest of the read that missed
-                n = want
+            if n < asked:         # never less than the rest of the read that missed
+                n = asked
         elif p == 0 or self.advice[file_id] == "sequential":
             n = self.w0
-            if n < want:
-                n = want
+            if n < asked:
+                n = asked
         else:
-            n = want              # a new stream reads what was asked for, at least one page
+            n = asked             # a new stream reads what was asked for, at least one page
         if n > self.cap:
             n = self.cap
         if n < 1:

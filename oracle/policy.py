@@ -30,12 +30,13 @@ on ties): if at least ``near_min`` of the file's last ``recent`` misses lie with
 ``near_pages`` pages of p (defaults 3, 64, 64), many blocks are reading the file in aggregate
 (interleaved strides) and the
 window is the cap-sized chunk aligned around p; else [p, p + w) with w = min(max(2 h,
-r), cap) if the h >= 1 pages right before p are already cached (h counted up to
-ceil(cap / 2), beyond which the window no longer changes; context readahead:
-Linux's way of following readers that interleave on one descriptor, Sec. 2.3); else
-w = min(max(W0 if p == 0 or the file is SEQUENTIAL else 1, r), cap); r is the number
-of pages of the missing read from p to its end (a prefetcher reads at least what the
-caller asked for, Sec. 2.3). Windows are clamped to EOF; the
+r), cap) if the h > r pages right before p are already cached (a history no longer
+than the read may be chance next to a random read; h counted up to
+max(ceil(cap / 2), r + 1), which decides the comparison and the window exactly; context
+readahead: Linux's way of following readers that interleave on one descriptor, Sec.
+2.3); else w = min(max(W0 if p == 0 or the file is SEQUENTIAL else 1, r), cap); r is
+min(cap, the number of pages of the missing read from p to its end) (a prefetcher reads
+at least what the caller asked for, Sec. 2.3). Windows are clamped to EOF; the
 block fetches the run of unmapped window pages that contains p (pages beyond a
 mapped page are left for later demand, so a request has no holes); the demanded
 page is allocated first, then the rest of the run in ascending order; one host
@@ -204,9 +205,12 @@ class PolicyModel:
                 return ws, wn
         # context: the pages right behind p are already cached (read or being read by other
         # blocks), so p continues a sequential stream that no slot tracks; counted up to
-        # ceil(cap / 2), the most that can change the window min(2 h, cap)
+        # max(ceil(cap / 2), r + 1), enough to compare with the read's r pages and to size
+        # the window min(2 h, cap)
+        r = min(req, self.cap)
+        hmax = max((self.cap + 1) // 2, r + 1)
         h = 0
-        while h < (self.cap + 1) // 2 and p - 1 - h >= 0 and (file_id, p - 1 - h) in self.map:
+        while h < hmax and p - 1 - h >= 0 and (file_id, p - 1 - h) in self.map:
             h += 1
         victim = None
         for s in fs.streams:                       # an empty slot first (lowest index)
@@ -221,16 +225,17 @@ class PolicyModel:
             wn = self.cap
             ws = p // wn * wn
             self.decisions.append((near, 0, RULE_AGGREGATE))
-        elif h > 0:
-            # at least the rest of the read that missed (Sec. 2.3: the prefetcher reads more
-            # than the caller asked for, never less)
-            wn = min(max(2 * h, req), self.cap)
+        elif h > r:
+            # a history longer than the read itself (a shorter one may be a random read next
+            # to cached pages); at least the rest of the read that missed (Sec. 2.3: the
+            # prefetcher reads more than the caller asked for, never less)
+            wn = min(max(2 * h, r), self.cap)
             ws = p
             self.decisions.append((near, h, RULE_CONTEXT))
         else:
-            wn = max(self.W0 if (p == 0 or fs.advice == ADV_SEQUENTIAL) else 1, req)
+            wn = max(self.W0 if (p == 0 or fs.advice == ADV_SEQUENTIAL) else 1, r)
             ws = p
-            self.decisions.append((near, 0, RULE_NEW))
+            self.decisions.append((near, h, RULE_NEW))
         wn = max(1, min(wn, self.cap))
         victim.valid = True
         victim.next = ws + wn

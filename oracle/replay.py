@@ -152,15 +152,18 @@ def replay_readahead(events, ra_init: int, ra_cap: int, streams: int,
                 exp_rule, exp_h = RULE_AGGREGATE, 0
             else:
                 # the cached history behind p is the trace's; it cannot exceed the pages
-                # behind p or ceil(cap / 2) (where the count stops), and it sizes the window
-                _check(h <= min(p, (ra_cap + 1) // 2), f"context decision at {p}: history {h} out of range")
+                # behind p or max(ceil(cap / 2), r + 1) (where the count stops), and it
+                # decides the rule and sizes the window
+                r = min(req, ra_cap)
+                _check(h <= min(p, max((ra_cap + 1) // 2, r + 1)), f"decision at {p}: history {h} out of range")
                 exp_h = h
-                # either window covers at least the rest of the read that missed
-                if h > 0:
-                    exp_wn, exp_rule = min(max(2 * h, req), ra_cap), RULE_CONTEXT
+                # the context rule needs more history than the read; either window covers
+                # at least the rest of the read that missed
+                if h > r:
+                    exp_wn, exp_rule = min(max(2 * h, r), ra_cap), RULE_CONTEXT
                 else:
                     w0 = ra_init if (p == 0 or advice.get(fid) == "sequential") else 1
-                    exp_wn, exp_rule = max(1, min(max(w0, req), ra_cap)), RULE_NEW
+                    exp_wn, exp_rule = max(1, min(max(w0, r), ra_cap)), RULE_NEW
                 exp_ws = p
             slots[victim] = [True, exp_ws + exp_wn, exp_wn, st["clock"]]
         _check(rule == exp_rule and h == exp_h, f"miss at {p}: rule {rule} h {h}, model rule {exp_rule} h {exp_h}")

@@ -262,18 +262,33 @@ def test_a_read_of_several_pages_gets_them_in_one_window():
     assert [r for _, _, r in m.decisions] == [4, 1, 4, 1, 1]   # new, zone, new, zone, zone
 
 
-def test_context_window_covers_the_rest_of_the_read():
-    # hand-worked, one slot, cap 16: a 4-page read at 0 opens [0, 4) (W0 = 4 = the read);
-    # a 1-page read at 100 takes the only slot; a 12-page read at 4 is outside every zone
-    # with history 4 behind it: 2h = 8 pages would not cover the read, so the window is
-    # [4, 16), the 12 pages asked for
+def test_context_rule_needs_more_history_than_the_read():
+    # hand-worked, one slot, cap 16 (Sec. 2.3; Linux's context readahead): a 4-page read at 0
+    # opens [0, 4) (W0 = 4 = the read); a 1-page read at 100 takes the only slot.
+    # (a) a 2-page read at 4: history 4 behind it, longer than the read -> context, window
+    #     2h = 8: [4, 12)
+    # (b) after a 1-page read at 200 takes the slot again, a 12-page read at 12: history 12
+    #     (pages 0..11), not longer than the read -> a new stream with the 12 pages asked
+    #     for, [12, 24) (the window the context rule would give as well)
+    # (c) a 1-page read at 301 with only page 300 cached behind it (read before, its stream
+    #     then replaced by a read at 500): a history of 1 is no longer than the read, as
+    #     likely a random read as a stream -> one page on probation
     m = PolicyModel(nframes=256, page_size=4096, ra_init_pages=4, ra_cap_pages=16, streams_per_file=1)
     m.open(0, 1 << 22)
     m.gread(0, 0, 0, 4 * 4096)
     m.gread(0, 0, 100 * 4096, 4096)
-    m.gread(0, 0, 4 * 4096, 12 * 4096)
-    assert [(e[4], e[5]) for e in _misses(m.events)] == [(0, 4), (100, 1), (4, 12)]
+    m.gread(0, 0, 4 * 4096, 2 * 4096)
+    assert [(e[4], e[5]) for e in _misses(m.events)] == [(0, 4), (100, 1), (4, 8)]
     assert m.decisions[-1] == (1, 4, 3)   # one near miss (page 0), history 4, the context rule
+    m.gread(0, 0, 200 * 4096, 4096)
+    m.gread(0, 0, 12 * 4096, 12 * 4096)
+    assert [(e[4], e[5]) for e in _misses(m.events)][-1] == (12, 12)
+    assert m.decisions[-1] == (2, 12, 4)   # near misses 0 and 4, history 12, a new stream
+    m.gread(0, 0, 300 * 4096, 4096)
+    m.gread(0, 0, 500 * 4096, 4096)
+    m.gread(0, 0, 301 * 4096, 4096)
+    assert [(e[4], e[5]) for e in _misses(m.events)][-1] == (301, 1)
+    assert m.decisions[-1][1:] == (1, 4)
 
 
 def test_aggregate_read_takes_aligned_cap_chunk():
