@@ -36,6 +36,7 @@ class NaiveModel:
         self.tick = {}
         self.last_misses = {}
         self.log = []
+        self.gone = []            # (file, page) evicted after being read, in eviction order
 
     def open(self, file_id, size, advice="normal"):
         self.size[file_id] = size
@@ -132,6 +133,8 @@ class NaiveModel:
                 self.log.append(("HAND", t, i, "CLEAR", -1, -1, 0, found))
                 continue
             self.log.append(("HAND", t, i, "EVICT", fr[1], fr[2], fr[5], found))
+            if fr[5] == 0:
+                self.gone.append((fr[1], fr[2]))
             self.frames[i] = [0, -1, -1, 0, 0, 0]
             return i
         return -1
@@ -159,11 +162,16 @@ class NaiveModel:
                 if start + n > npages:
                     n = npages - start
                 self.log.append(("MISS", block, file_id, page, start, n))
+                # a page read earlier and evicted since is not fetched again for a window,
+                # unless the missing page is such a page too (the file is read again)
+                again = (file_id, page) in self.gone
                 lo = page
-                while lo > start and _find(self.frames, file_id, lo - 1) < 0:
+                while (lo > start and _find(self.frames, file_id, lo - 1) < 0
+                       and (again or (file_id, lo - 1) not in self.gone)):
                     lo -= 1
                 hi = page
-                while hi < start + n - 1 and _find(self.frames, file_id, hi + 1) < 0:
+                while (hi < start + n - 1 and _find(self.frames, file_id, hi + 1) < 0
+                       and (again or (file_id, hi + 1) not in self.gone)):
                     hi += 1
                 todo = [page]
                 for q in range(lo, hi + 1):

@@ -38,7 +38,12 @@ readahead: Linux's way of following readers that interleave on one descriptor, S
 min(cap, the number of pages of the missing read from p to its end) (a prefetcher reads
 at least what the caller asked for, Sec. 2.3). Windows are clamped to EOF; the
 block fetches the run of unmapped window pages that contains p (pages beyond a
-mapped page are left for later demand, so a request has no holes); the demanded
+mapped page are left for later demand, so a request has no holes, and so are pages that
+were consumed and then evicted since the cache was set up, unless the demanded page is
+one of them: such a page lies behind a reader that has passed it, which is how a stream's
+last window reaches into a neighbour's chunk, and a demanded page that is one of them
+means the file is being read again; Sec. 5.1 counts prefetched pages evicted unused as
+the waste to avoid); the demanded
 page is allocated first, then the rest of the run in ascending order; one host
 request covers the run; the prefetch is synchronous (the requester waits for the
 whole window); a filled frame gets its reference bit set; a pin sets it and
@@ -51,7 +56,8 @@ after a demand miss at p, the page p + 1 when the window fetched it; after an
 asynchronous window, the window's first page. The marker page's frame carries a mark from
 its allocation. A block whose access finds a marked frame (hit or join) clears the mark and,
 if a stream's marker still names that page (lowest slot), advances that stream: window
-[s.next, s.next + min(2 s.size, cap)), the unmapped run from its first page, allocated
+[s.next, s.next + min(2 s.size, cap)), the run from its first page of pages that are
+unmapped and, unless the marker page itself was, not consumed and evicted, allocated
 ascending and requested from the host, with no page demanded and nobody waiting for it.
 A block keeps at most one such request outstanding: it completes the previous one first,
 when it reaches a marked page. In serialized runs every request completes by the end of
@@ -148,6 +154,9 @@ class PolicyModel:
         self.pending: Dict[int, List[int]] = {}   # block -> frames of its outstanding request
         self.frames = [Frame() for _ in range(nframes)]
         self.map: Dict[Tuple[int, int], int] = {}
+        # (file, page) of every page evicted after it was consumed (a pin cleared its
+        # prefetch mark, or it was demanded), since the cache was set up
+        self.shadow = set()
         self.hand = 0
         self.files: Dict[int, FileState] = {}
         self.events: List[tuple] = []
@@ -269,9 +278,18 @@ class PolicyModel:
             if fr.ra:
                 self.wasted_pages += 1
                 self.wasted_bytes += self.page_bytes(fr.file, fr.page)
+            else:
+                self.shadow.add((fr.file, fr.page))
             self.frames[f] = Frame()
             return f
         return None
+
+    def _fetchable(self, file_id: int, q: int, p: int) -> bool:
+        """May a window that page p opened fetch page q: q is not cached, and it was not
+        consumed and then evicted, unless p was."""
+        if (file_id, q) in self.map:
+            return False
+        return (file_id, q) not in self.shadow or (file_id, p) in self.shadow
 
     # ---- one page access ------------------------------------------------------------------
     def access(self, block: int, file_id: int, p: int, req: int = 1) -> int:
@@ -305,12 +323,13 @@ class PolicyModel:
         if self.ra_async and self.last_stream is not None:
             marker = p + 1 if p + 1 < ws + wn else -1
             self.last_stream.marker = marker
-        # fetch the run of unmapped window pages that contains p (no holes in a request)
+        # fetch the run of unmapped window pages that contains p (no holes in a request);
+        # consumed-then-evicted pages end it too, unless p is one of them
         a = p
-        while a - 1 >= ws and (file_id, a - 1) not in self.map:
+        while a - 1 >= ws and self._fetchable(file_id, a - 1, p):
             a -= 1
         b = p
-        while b + 1 < ws + wn and (file_id, b + 1) not in self.map:
+        while b + 1 < ws + wn and self._fetchable(file_id, b + 1, p):
             b += 1
         order = [p] + [q for q in range(a, b + 1) if q != p]
         allocated = []
@@ -377,7 +396,7 @@ class PolicyModel:
         self.events.append(("ADV", block, file_id, p, ws, wn))
         allocated = []
         q = ws
-        while q < ws + wn and (file_id, q) not in self.map:
+        while q < ws + wn and self._fetchable(file_id, q, p):
             g = self.alloc()
             if g is None:
                 self.events.append(("NOFRAME", block, file_id, q))

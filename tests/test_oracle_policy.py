@@ -228,6 +228,47 @@ def test_brute_force_against_naive_model(case):
     assert n > 1 and len(outcomes) >= 1
 
 
+def test_a_window_does_not_fetch_again_what_a_reader_consumed_and_the_cache_dropped():
+    # hand-worked, 2 frames, one stream slot, aggregate rule off. 5 and 50 are read; 51's
+    # window [51, 53) evicts both (consumed, so they leave shadows), then 3 evicts 51 and 4
+    # evicts 52, which was prefetched and never read (no shadow). 4 is in 3's zone: window
+    # [4, 6), but 5 was consumed and dropped, so only 4 is requested (Sec. 5.1: prefetched
+    # pages evicted unused are the waste to avoid; 5 lies behind the reader that read it)
+    P = 4096
+    m = PolicyModel(nframes=2, page_size=P, ra_init_pages=1, ra_cap_pages=4, streams_per_file=1, near_min=100)
+    m.open(0, 64 * P)
+    for p in (5, 50, 51, 3, 4):
+        m.gread(0, 0, p * P, P)
+    assert [(e[4], e[5]) for e in _misses(m.events)] == [(5, 1), (50, 1), (51, 2), (3, 1), (4, 2)]
+    assert [e[2:] for e in m.events if e[0] == "REQ"] == [(5, 1), (50, 1), (51, 2), (3, 1), (4, 1)]
+    assert [(e[5], e[6]) for e in m.events if e[0] == "HAND" and e[3] == "EVICT"] == \
+        [(5, 0), (50, 0), (51, 0), (52, 1)]
+    # the same accesses, with 5 never read before: the window fetches both pages
+    m2 = PolicyModel(nframes=2, page_size=P, ra_init_pages=1, ra_cap_pages=4, streams_per_file=1, near_min=100)
+    m2.open(0, 64 * P)
+    for p in (6, 50, 51, 3, 4):
+        m2.gread(0, 0, p * P, P)
+    assert [e[2:] for e in m2.events if e[0] == "REQ"][-1] == (4, 2)
+
+
+def test_a_file_read_again_gets_full_windows():
+    # a single reader passes twice over a 40-page file through 8 frames: in the second pass
+    # every page it misses was consumed and dropped, so the shadows do not cut its windows,
+    # and it fetches with the same 4-page requests as the first pass
+    P = 4096
+    m = PolicyModel(nframes=8, page_size=P, ra_init_pages=4, ra_cap_pages=4, streams_per_file=1)
+    m.open(0, 40 * P)
+    reqs = []
+    for _ in range(2):
+        n0 = len(m.events)
+        for p in range(40):
+            m.gread(0, 0, p * P, P)
+        reqs.append([e[2:] for e in m.events[n0:] if e[0] == "REQ"])
+    assert reqs[0] == [(q, 4) for q in range(0, 40, 4)]
+    assert reqs[1] == reqs[0]
+    assert m.fetched_pages == 80 and m.wasted_pages == 0
+
+
 def test_context_readahead_follows_a_stream_no_slot_tracks():
     # hand-worked, one stream slot: 0 opens [0,4); 100 takes the only slot; 4 is outside every
     # zone, but pages 0..3 right behind it are cached, so it is sequential with history 4:
