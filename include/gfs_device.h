@@ -339,6 +339,24 @@ enum { PIN_RETRY = 0, PIN_VALID = 1, PIN_FILLING = 2, PIN_ERROR = 3, PIN_VALID_U
 
 /* Drop a pin. Relaxed: the caller's reads of the frame have completed (a block barrier
  * waits for them) before this is issued, and unpinning publishes nothing. */
+/* ------------------------------------------------------------------ evicted-after-use bits
+ * One bit per page of a file: set when the clock evicts the page after it was consumed (its
+ * prefetch mark cleared by a pin, or it was the demanded page). A window leaves such pages
+ * out of its run, unless the demanded page (the marker page, for an asynchronous window) is
+ * one of them: a page a reader consumed and the cache dropped lies behind that reader, and a
+ * demanded one means the file is being read again. */
+__device__ __forceinline__ uint64_t* shadow_word(const gfs_dev* d, uint32_t file, uint64_t q) {
+  return d->shadow + (uint64_t)file * (GFS_SHADOW_PAGES / 64) + (q >> 6);
+}
+__device__ __forceinline__ bool shadow_lane(const gfs_dev* d, uint32_t file, uint64_t q) {
+  if (q >= GFS_SHADOW_PAGES) return false;
+  return ((ld_rlx(shadow_word(d, file, q)) >> (q & 63)) & 1ull) != 0;
+}
+__device__ __forceinline__ void shadow_set_lane(const gfs_dev* d, uint32_t file, uint64_t q) {
+  if (q < GFS_SHADOW_PAGES)
+    __hip_atomic_fetch_or(shadow_word(d, file, q), 1ull << (q & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void frame_unpin(const gfs_dev* d, uint32_t f) {
   __hip_atomic_fetch_sub(&d->fword[f], GFS_FW_PIN_ONE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -842,7 +860,11 @@ __device__ uint32_t alloc_wave(const gfs_dev* d, uint32_t file, uint64_t demand,
     if (ok) {
       const uint32_t k = assigned + (uint32_t)__popcll(sm & lanemask_lt());
       const uint64_t q = bs->list[k];
-      if (act == GFS_HAND_EVICT) pt_delete_lane(d, vkey, f);
+      if (act == GFS_HAND_EVICT) {
+        pt_delete_lane(d, vkey, f);
+        if (!vra)
+          shadow_set_lane(d, (uint32_t)(vkey >> GFS_KEY_PAGE_BITS) - 1u, vkey & ((1ull << GFS_KEY_PAGE_BITS) - 1));
+      }
       const uint64_t key = page_key(file, q);
       st_rlx(&d->ftag[f], key);
       st_rlx(&d->ffill[f], 0ull);   /* the request that fills it is not known yet */
@@ -1000,15 +1022,18 @@ __device__ uint32_t reserve_run_small_wave(const gfs_dev* d, uint32_t file, uint
   const uint64_t ent = (key << GFS_ENTRY_FRAME_BITS) | kReserved;
   uint32_t b1 = 0, b2 = 0;
   uint64_t e[2 * GFS_BUCKET_SLOTS];
-  bool present = false;
+  bool present = false, gone = false;
   if (l < wn) {
     key_buckets(d, key, b1, b2);
     pt_load_lane(d, b1, b2, e);
+    gone = shadow_lane(d, file, q);
 #pragma unroll
     for (int i = 0; i < 2 * GFS_BUCKET_SLOTS; ++i) present |= (e[i] >> GFS_ENTRY_FRAME_BITS) == key;
   }
   const uint32_t pi = (uint32_t)(p - ws);
   uint64_t pm = __ballot(l < wn && present);
+  const uint64_t gm = __ballot(gone);
+  if (((gm >> pi) & 1ull) == 0) pm |= gm;     /* pages evicted after use stop it, unless p is one */
   if (wn < 64) pm |= ~0ull << wn;             /* pages outside the window stop the run */
   pm &= ~(1ull << pi);                         /* p itself is absent (probed under the lock) */
   const uint64_t below = pm & ((1ull << pi) - 1);
@@ -1582,11 +1607,14 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
        the buckets it already holds */
     n = reserve_run_small_wave(d, file, p, cws, cwn, bs, failed);
   } else {
+    /* pages evicted after use end the run too, unless p is one */
+    const bool clip = !shadow_lane(d, file, p);
     uint64_t a = p;
     for (uint64_t base = p; base > cws;) {
       const bool valid = (uint64_t)l < base - cws;
       bool stop = !valid;
-      if (valid) stop = pt_present_lane(d, page_key(file, base - 1 - l));
+      if (valid)
+        stop = pt_present_lane(d, page_key(file, base - 1 - l)) | (clip && shadow_lane(d, file, base - 1 - l));
       const uint64_t sm = __ballot(stop);
       const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
       a = base - k;
@@ -1597,7 +1625,7 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
     for (uint64_t base = p + 1; base < cwe;) {
       const bool valid = (uint64_t)l < cwe - base;
       bool stop = !valid;
-      if (valid) stop = pt_present_lane(d, page_key(file, base + l));
+      if (valid) stop = pt_present_lane(d, page_key(file, base + l)) | (clip && shadow_lane(d, file, base + l));
       const uint64_t sm = __ballot(stop);
       const uint32_t k = sm ? (uint32_t)__builtin_ctzll(sm) : 64u;
       b = base + k - 1;
@@ -1975,8 +2003,8 @@ __device__ int64_t private_publish_lane(const gfs_dev* d, BlockState* bs, uint64
 /* Wave-collective, outside the lock: reserve the run of unmapped pages that starts at ws,
    within [ws, ws + n), ascending into bs->list/lslot/lframe; returns its length and sets
    failed if a page found both buckets full. */
-__device__ uint32_t reserve_from_wave(const gfs_dev* d, uint32_t file, uint64_t ws, uint32_t n, BlockState* bs,
-                                      uint32_t& failed) {
+__device__ uint32_t reserve_from_wave(const gfs_dev* d, uint32_t file, uint64_t ws, uint32_t n, bool clip,
+                                      BlockState* bs, uint32_t& failed) {
   const uint32_t l = lane();
   uint32_t count = 0, bad = 0;
   for (uint32_t base = 0; base < n; base += 64) {
@@ -1985,14 +2013,15 @@ __device__ uint32_t reserve_from_wave(const gfs_dev* d, uint32_t file, uint64_t 
     const uint64_t key = page_key(file, q);
     uint32_t b1 = 0, b2 = 0;
     uint64_t e[2 * GFS_BUCKET_SLOTS];
-    bool present = false;
+    bool present = false, gone = false;
     if (valid) {
       key_buckets(d, key, b1, b2);
       pt_load_lane(d, b1, b2, e);
+      gone = clip && shadow_lane(d, file, q);
 #pragma unroll
       for (int i = 0; i < 2 * GFS_BUCKET_SLOTS; ++i) present |= (e[i] >> GFS_ENTRY_FRAME_BITS) == key;
     }
-    const uint64_t stop = __ballot(!valid || present);
+    const uint64_t stop = __ballot(!valid || present || gone);
     const uint32_t k = stop ? (uint32_t)__builtin_ctzll(stop) : 64u;
     if (l < k) {
       int cnt1 = 0, cnt2 = 0, f1 = -1, f2 = -1;
@@ -2051,6 +2080,8 @@ __device__ __attribute__((noinline)) void async_issue_wave(const gfs_dev* d, uin
   uint64_t cl = 0;
   if (l < GFS_CLAIMS) cl = ld_rlx(&d->claims[file].e[l]);
   const uint64_t npages = d->files[file].npages;
+  /* the window leaves out pages evicted after use, unless the marker page is one */
+  const bool clip = !shadow_lane(d, file, m);
   drain_atomics();
   const uint64_t sm = __ballot(l < d->streams && ras.s_valid && ras.s_marker == (uint32_t)m);
   if (sm == 0) {
@@ -2102,7 +2133,7 @@ __device__ __attribute__((noinline)) void async_issue_wave(const gfs_dev* d, uin
   unlock_file_wave(d, file, ticket, ws, cwe);
   __builtin_amdgcn_s_setprio(0);
   uint32_t failed = 0;
-  const uint32_t n = reserve_from_wave(d, file, ws, (uint32_t)(cwe - ws), bs, failed);
+  const uint32_t n = reserve_from_wave(d, file, ws, (uint32_t)(cwe - ws), clip, bs, failed);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   if (l == 0) st_rlx(claim, 0ull);
   wave_sync_lds();

@@ -124,6 +124,10 @@ typedef struct gfs_file_lock {
    bytes of LDS for its per-block state, so a CU holds at most LDS / GFS_BLOCK_LDS_MIN such
    blocks (12 on a 160 KiB CU, 3072 on 256 CUs); gfs_init checks the device. */
 #define GFS_LOCK_SLOTS 4096u
+
+/* pages per file whose eviction after use is remembered, one bit each (64 KiB per file id);
+   later pages of a larger file are not tracked */
+#define GFS_SHADOW_PAGES (1u << 19)
 #define GFS_BLOCK_LDS_MIN 12288u
 
 /* window claims: a block that decided a window under the miss lock records it here and
@@ -210,6 +214,8 @@ typedef struct gfs_dev {
   gfs_file_lock* locks;
   uint64_t* lockq;              /* [max_files][GFS_LOCK_SLOTS] miss-lock queue slots */
   gfs_file_claims* claims;      /* [max_files] windows being reserved */
+  uint64_t* shadow;             /* [max_files][GFS_SHADOW_PAGES / 64]: bit set once the page was
+                                   evicted after it was consumed (cleared with the cache) */
   gfs_pslot* pslots;            /* private policy: [private_slots] */
   uint8_t* pbuf;                /* private policy: [private_slots][ra_cap pages] in the frames allocation */
   uint32_t policy;              /* GFS_POLICY_* */

@@ -54,7 +54,7 @@ struct Layout {
   uint64_t max_req_bytes = 0;
   uint64_t quota = 0;              /* private policy: frames per slot */
   uint64_t pbuf_bytes = 0;         /* private policy: all private buffers */
-  uint64_t off_globals = 0, off_dev = 0, off_files = 0, off_locks = 0, off_lockq = 0, off_claims = 0, off_pslots = 0, off_names = 0, off_fword = 0,
+  uint64_t off_globals = 0, off_dev = 0, off_files = 0, off_locks = 0, off_lockq = 0, off_claims = 0, off_shadow = 0, off_pslots = 0, off_names = 0, off_fword = 0,
            off_ftag = 0, off_pt = 0, off_ffill = 0, off_slot_free = 0, off_slot_tail = 0, off_reqd = 0, off_trace = 0,
            meta_bytes = 0;
 };
@@ -115,6 +115,7 @@ int make_layout(const gfs_config* c, Layout* L) {
   L->off_locks = o; o = align_up(o + sizeof(gfs_file_lock) * nf, kAlign);
   L->off_lockq = o; o = align_up(o + 8ull * GFS_LOCK_SLOTS * nf, kAlign);
   L->off_claims = o; o = align_up(o + sizeof(gfs_file_claims) * nf, kAlign);
+  L->off_shadow = o; o = align_up(o + (uint64_t)(GFS_SHADOW_PAGES / 8) * nf, kAlign);
   L->off_pslots = o;
   if (c->policy == GFS_POLICY_PRIVATE) o = align_up(o + sizeof(gfs_pslot) * c->private_slots, kAlign);
   L->off_names = o; o = align_up(o + (uint64_t)GFS_NAME_MAX * nf, kAlign);
@@ -168,7 +169,8 @@ int download_file_record(gfs_ctx* c, int id, gfs_file_dev* rec) {
   return hip_ok(hipStreamSynchronize(c->stream));
 }
 
-// clear one file id's miss lock, its queue slots and its window claims (no kernel running)
+// clear one file id's miss lock, its queue slots, its window claims and its record of pages
+// evicted after use (no kernel running)
 int zero_file_locks(gfs_ctx* c, int id) {
   const Layout& L = c->L;
   int rc = gfs_internal_zero(c->meta + L.off_locks + sizeof(gfs_file_lock) * (uint64_t)id, sizeof(gfs_file_lock),
@@ -179,6 +181,9 @@ int zero_file_locks(gfs_ctx* c, int id) {
   if (!rc)
     rc = gfs_internal_zero(c->meta + L.off_claims + sizeof(gfs_file_claims) * (uint64_t)id,
                            sizeof(gfs_file_claims), c->stream);
+  if (!rc)
+    rc = gfs_internal_zero(c->meta + L.off_shadow + (uint64_t)(GFS_SHADOW_PAGES / 8) * id, GFS_SHADOW_PAGES / 8,
+                           c->stream);
   return rc;
 }
 
@@ -186,7 +191,7 @@ int zero_file_locks(gfs_ctx* c, int id) {
 int zero_dynamic(gfs_ctx* c) {
   const Layout& L = c->L;
   int rc = gfs_internal_zero(c->meta + L.off_globals, sizeof(gfs_globals), c->stream);
-  // miss locks, their queue slots, window claims, private slots
+  // miss locks, their queue slots, window claims, evicted-after-use bits, private slots
   if (!rc) rc = gfs_internal_zero(c->meta + L.off_locks, L.off_names - L.off_locks, c->stream);
   if (!rc) rc = gfs_internal_zero(c->meta + L.off_fword, L.off_trace - L.off_fword, c->stream);
   if (!rc && c->cfg.trace_capacity)
@@ -346,6 +351,7 @@ int gfs_init(const gfs_config* cfg, void* frames_dev, void* meta_dev, void* hip_
   h.locks = (gfs_file_lock*)(c->meta + L.off_locks);
   h.lockq = (uint64_t*)(c->meta + L.off_lockq);
   h.claims = (gfs_file_claims*)(c->meta + L.off_claims);
+  h.shadow = (uint64_t*)(c->meta + L.off_shadow);
   h.policy = cfg->policy;
   if (cfg->policy == GFS_POLICY_PRIVATE) {
     h.pslots = (gfs_pslot*)(c->meta + L.off_pslots);
