@@ -227,12 +227,15 @@ __device__ __forceinline__ uint64_t key_hash(uint64_t k) {
   k ^= k >> 33;
   return k;
 }
+__device__ __forceinline__ void key_buckets_m(uint32_t mask, uint64_t key, uint32_t& b1, uint32_t& b2) {
+  const uint64_t h = key_hash(key);
+  b1 = (uint32_t)h & mask;
+  b2 = (uint32_t)(h >> 32) & mask;
+  if (b2 == b1) b2 = b1 ^ 1u;
+}
 __device__ __forceinline__ void key_buckets(const gfs_dev* d, uint64_t key, uint32_t& b1,
                                             uint32_t& b2) {
-  const uint64_t h = key_hash(key);
-  b1 = (uint32_t)h & d->nbuckets_mask;
-  b2 = (uint32_t)(h >> 32) & d->nbuckets_mask;
-  if (b2 == b1) b2 = b1 ^ 1u;
+  key_buckets_m(d->nbuckets_mask, key, b1, b2);
 }
 __device__ __forceinline__ uint64_t* slot_ptr(const gfs_dev* d, uint32_t b1, uint32_t b2, int i) {
   return d->pt + (uint64_t)(i < GFS_BUCKET_SLOTS ? b1 : b2) * GFS_BUCKET_SLOTS + (i & 15);
@@ -240,16 +243,19 @@ __device__ __forceinline__ uint64_t* slot_ptr(const gfs_dev* d, uint32_t b1, uin
 
 /* wave-collective: lanes 0-15 read bucket 1, lanes 16-31 bucket 2; uniform result: the
  * frame, kReserved, or -1 when absent */
-__device__ int32_t pt_lookup_wave(const gfs_dev* d, uint64_t key) {
+__device__ __forceinline__ int32_t pt_lookup_at(uint64_t* pt, uint32_t mask, uint64_t key) {
   uint32_t b1, b2;
-  key_buckets(d, key, b1, b2);
+  key_buckets_m(mask, key, b1, b2);
   const uint32_t l = lane();
   uint64_t e = 0;
-  if (l < 32) e = ld_rlx(slot_ptr(d, b1, b2, (int)l));
+  if (l < 32) e = ld_rlx(pt + (uint64_t)(l < GFS_BUCKET_SLOTS ? b1 : b2) * GFS_BUCKET_SLOTS + (l & 15));
   const uint64_t m = __ballot(l < 32 && (e >> GFS_ENTRY_FRAME_BITS) == key);
   if (m == 0) return -1;
   const uint64_t hit = __shfl(e, __ffsll((unsigned long long)m) - 1, 64);
   return (int32_t)(hit & kFrameMask);
+}
+__device__ int32_t pt_lookup_wave(const gfs_dev* d, uint64_t key) {
+  return pt_lookup_at(d->pt, d->nbuckets_mask, key);
 }
 
 /* per lane: the 32 candidate entries of a key, loaded together (one round trip) */
@@ -603,8 +609,9 @@ __device__ int lock_file_wave(const gfs_dev* d, uint32_t file, uint64_t key, uin
  * loses only to the waiter leaving), and the first other ticket gets the grant; if that
  * waiter left just before the exchange, the scan goes on after it. A ticket that has not
  * announced its page yet is granted the lock like any other. */
-__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket, uint64_t lo, uint64_t hi,
-                                 bool has_pre, uint64_t pre) {
+/* lq: the file's queue slots, ticket n in lq[n mod GFS_LOCK_SLOTS] */
+__device__ void unlock_slots_wave(uint64_t* lq, uint64_t ticket, uint64_t lo, uint64_t hi, bool has_pre,
+                                  uint64_t pre) {
   drain_atomics();
   const uint32_t l = lane();
   uint64_t n = ticket + 1;
@@ -612,7 +619,7 @@ __device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticke
   while (true) {
     if (look) {
       const uint64_t nl = n + l;
-      uint64_t* sl = lock_slot(d, file, nl);
+      uint64_t* sl = lq + (nl & (GFS_LOCK_SLOTS - 1));
       uint64_t v = has_pre && n == ticket + 1 ? pre : ld_rlx(sl);
       const uint64_t pg = (v >> 32) & 0x7fffffffull;
       const bool gone = v == lock_left(nl) || v == lock_covered(nl);
@@ -632,13 +639,18 @@ __device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticke
     }
     uint64_t old = 0;
     if (l == 0)
-      old = __hip_atomic_exchange(lock_slot(d, file, n), lock_granted(n), __ATOMIC_RELAXED,
+      old = __hip_atomic_exchange(lq + (n & (GFS_LOCK_SLOTS - 1)), lock_granted(n), __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
     old = __shfl(old, 0, 64);
     if (old != lock_left(n)) return;
     ++n;   /* that waiter had left: look for the next one still in the queue */
     look = true;
   }
+}
+/* the same, given the file instead of its queue slots */
+__device__ void unlock_file_wave(const gfs_dev* d, uint32_t file, uint64_t ticket, uint64_t lo, uint64_t hi,
+                                 bool has_pre, uint64_t pre) {
+  unlock_slots_wave(d->lockq + (uint64_t)file * GFS_LOCK_SLOTS, ticket, lo, hi, has_pre, pre);
 }
 
 /* ------------------------------------------------------------------ readahead detector
@@ -662,15 +674,14 @@ struct RaState {
   uint64_t r, s_next;
   uint32_t s_size, s_last, s_valid, s_marker;
 };
-__device__ __forceinline__ RaState ra_load_lane(const gfs_dev* d, uint32_t file) {
-  gfs_file_dev* fe = &d->files[file];
+__device__ __forceinline__ RaState ra_load_lane(gfs_file_dev* fe, uint32_t nrec, uint32_t nstreams) {
   const uint32_t l = lane();
   RaState st{};
   st.advice = ld_rlx32(&fe->advice);
   if (l == 0) st.clk = ld_rlx32(&fe->clock);
   st.rn = ld_rlx32(&fe->recent_n);
-  if (l < d->ra_recent) st.r = ld_rlx(&fe->recent[l]);
-  if (l < d->streams) {
+  if (l < nrec) st.r = ld_rlx(&fe->recent[l]);
+  if (l < nstreams) {
     gfs_stream* sp = &fe->streams[l];
     st.s_next = ld_rlx(&sp->next);
     st.s_size = ld_rlx32(&sp->size);
@@ -695,6 +706,23 @@ __device__ __forceinline__ uint32_t ra_cap_eff(const gfs_dev* d) {
   uint64_t q = d->nframes / (r ? r : 1);
   if (q < 1) q = 1;
   return d->ra_cap < q ? d->ra_cap : (uint32_t)q;
+}
+
+/* The detector's constants, read before a block takes the miss lock, so that the holder's
+   decision waits on no load of them. */
+struct RaParams {
+  uint32_t cap, nrec, nstreams, near_min, init;
+  uint64_t radius;
+};
+__device__ __forceinline__ RaParams ra_params(const gfs_dev* d) {
+  RaParams q;
+  q.cap = ra_cap_eff(d);
+  q.nrec = d->ra_recent;
+  q.nstreams = d->streams;
+  q.near_min = d->ra_near_min;
+  q.init = d->ra_init;
+  q.radius = d->ra_near_pages;
+  return q;
 }
 
 /* Wave-collective: how many consecutive pages right behind p are in the table (64 per round),
@@ -722,10 +750,9 @@ __device__ uint32_t ra_history_wave(const gfs_dev* d, uint32_t file, uint64_t p,
   return h < hmax ? h : hmax;
 }
 
-__device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint32_t req, uint32_t hist,
-                               const RaState& st, uint64_t& ws, uint32_t& wn, uint32_t& near_out,
+__device__ void ra_decide_wave(gfs_file_dev* fe, uint64_t p, uint32_t req, uint32_t hist,
+                               const RaParams& rp, const RaState& st, uint64_t& ws, uint32_t& wn, uint32_t& near_out,
                                uint32_t& h_out, uint32_t& rule_out, int& slot_out) {
-  gfs_file_dev* fe = &d->files[file];
   const uint32_t advice = st.advice;
   ws = p;
   wn = 1;
@@ -733,10 +760,10 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint
   h_out = 0;
   rule_out = RA_RULE_OFF;
   slot_out = -1;
-  if (d->ra_cap == 0 || advice == GFS_ADV_RANDOM) return;
+  if (rp.cap == 0 || advice == GFS_ADV_RANDOM) return;
   const uint32_t l = lane();
-  const uint32_t cap = ra_cap_eff(d);
-  const uint32_t nrec = d->ra_recent;
+  const uint32_t cap = rp.cap;
+  const uint32_t nrec = rp.nrec;
   uint32_t clk = st.clk;
   const uint32_t rn = st.rn;
   const uint64_t r = st.r;
@@ -744,7 +771,7 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint
   const uint32_t s_size = st.s_size, s_last = st.s_last, s_valid = st.s_valid;
   clk = __shfl(clk, 0, 64) + 1;
   /* how many of the file's last misses lie near p; then remember p */
-  const uint64_t radius = d->ra_near_pages;
+  const uint64_t radius = rp.radius;
   const bool near_l = l < nrec && l < rn && r + radius >= p && r <= p + radius;
   const uint32_t near = (uint32_t)__popcll(__ballot(near_l));
   near_out = near;
@@ -753,7 +780,7 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint
     st_rlx(&fe->recent[rn % nrec], p);
     st_rlx32(&fe->recent_n, rn + 1);
   }
-  const bool cov = l < d->streams && s_valid && s_next <= p && p < s_next + s_size;
+  const bool cov = l < rp.nstreams && s_valid && s_next <= p && p < s_next + s_size;
   const uint64_t cm = __ballot(cov);
   int j;
   if (cm) {
@@ -765,18 +792,18 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint
     wn = 2 * sz < cap ? 2 * sz : cap;
     rule_out = RA_RULE_ZONE;
   } else {
-    const uint64_t inv = __ballot(l < d->streams && !s_valid);
+    const uint64_t inv = __ballot(l < rp.nstreams && !s_valid);
     if (inv) {
       j = __ffsll((unsigned long long)inv) - 1;
     } else {
-      uint64_t k = l < d->streams ? (((uint64_t)s_last << 8) | l) : ~0ull;
+      uint64_t k = l < rp.nstreams ? (((uint64_t)s_last << 8) | l) : ~0ull;
       for (int off = 32; off > 0; off >>= 1) {
         const uint64_t o = __shfl_xor(k, off, 64);
         k = o < k ? o : k;
       }
       j = (int)(k & 0xff);
     }
-    if (near >= d->ra_near_min) {
+    if (near >= rp.near_min) {
       /* many blocks missing close together: the file is read in aggregate (interleaved
          strides); take the cap-sized chunk aligned around p */
       wn = cap;
@@ -796,7 +823,7 @@ __device__ void ra_decide_wave(const gfs_dev* d, uint32_t file, uint64_t p, uint
         w0 = 2 * h;
         rule_out = RA_RULE_CONTEXT;
       } else {
-        w0 = (p == 0 || advice == GFS_ADV_SEQUENTIAL) ? d->ra_init : 1u;
+        w0 = (p == 0 || advice == GFS_ADV_SEQUENTIAL) ? rp.init : 1u;
         rule_out = RA_RULE_NEW;
       }
       if (w0 < r) w0 = r;
@@ -1501,6 +1528,17 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
   const uint32_t req = rl >= p ? (rl - p + 1 < 0xffffffffull ? (uint32_t)(rl - p + 1) : 0xffffffffu) : 1u;
   /* the cached history behind p, counted before the lock (see ra_history_wave) */
   const uint32_t hist_pre = ra_history_wave(d, file, p, req);
+  const RaParams rp = ra_params(d);
+  /* what the critical section needs from the device and file records, read now: after the
+     grant's acquire, each would be a load from memory on the path every waiter waits on */
+  gfs_file_dev* const fe = &d->files[file];
+  uint64_t* const clp = d->claims[file].e;
+  uint64_t* const lq = d->lockq + (uint64_t)file * GFS_LOCK_SLOTS;
+  uint64_t* const pt = d->pt;
+  const uint32_t ptmask = d->nbuckets_mask;
+  const uint64_t npages = fe->npages;
+  const bool tracing = d->trace_level >= 1;
+  const bool async_on = d->ra_async != 0;
   const uint64_t tl0 = wall_clock64();
   uint64_t ticket;
   const int lk = lock_file_wave(d, file, key, p, t0, ticket);
@@ -1531,24 +1569,23 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
   __builtin_amdgcn_s_setprio(3);
   /* one round: the detector state and the file's window claims; then, ordered after the
      claims, the table probe (a claim cleared after its reservations means they show) */
-  const RaState ras = ra_load_lane(d, file);
+  const RaState ras = ra_load_lane(fe, rp.nrec, rp.nstreams);
   uint64_t cl = 0;
-  if (l < GFS_CLAIMS) cl = ld_rlx(&d->claims[file].e[l]);
+  if (l < GFS_CLAIMS) cl = ld_rlx(&clp[l]);
   /* the queue slots behind this ticket, read now for the hand-off: a waiter that arrives or
      leaves after this read is handled by the grant's exchange (it returns what the slot
      holds), and a stale "waiting" value only makes the covered mark's compare-and-swap fail */
-  const uint64_t qv = ld_rlx(lock_slot(d, file, ticket + 1 + l));
-  const uint64_t npages = d->files[file].npages;
+  const uint64_t qv = ld_rlx(lq + ((ticket + 1 + l) & (GFS_LOCK_SLOTS - 1)));
   drain_atomics();   /* the table probe below goes out after the claims were read */
   const bool cl_on = l < GFS_CLAIMS && (cl & 1ull);
   const uint64_t cl_lo = cl >> 32, cl_hi = (cl >> 32) + ((cl & 0xffffffffull) >> 1);
   const bool covered = __ballot(cl_on && cl_lo <= p && p < cl_hi) != 0;
   const uint64_t free_cl = __ballot(l < GFS_CLAIMS && !cl_on);
-  const bool present = pt_lookup_wave(d, key) >= 0;
+  const bool present = pt_lookup_at(pt, ptmask, key) >= 0;
   if (present || covered || free_cl == 0) {
     /* filled, reserved, or about to be reserved by a window being claimed: go to the pin
        path (after a nap if the claim is still running) */
-    unlock_file_wave(d, file, ticket, 0, 0);
+    unlock_slots_wave(lq, ticket, 0, 0, false, 0);
     __builtin_amdgcn_s_setprio(0);
     if (l == 0) bcount(bs, GFS_T_CRIT, wall_clock64() - tl1);
     if (!present) {
@@ -1562,17 +1599,17 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
   uint32_t wn, near, hist, rule;
   int rslot;
   const uint64_t td0 = wall_clock64();
-  ra_decide_wave(d, file, p, req, hist_pre, ras, ws, wn, near, hist, rule, rslot);
+  ra_decide_wave(fe, p, req, hist_pre, rp, ras, ws, wn, near, hist, rule, rslot);
   const uint64_t td1 = wall_clock64();
   if (l == 0) bcount(bs, GFS_T_DECIDE, td1 - td0);
   if (ws + wn > npages) wn = (uint32_t)(npages - ws);
   /* asynchronous readahead: the page after the demanded one is the stream's marker */
   uint64_t mark = ~0ull;
-  if (d->ra_async && rslot >= 0) {
+  if (async_on && rslot >= 0) {
     mark = p + 1 < ws + wn ? p + 1 : ~0ull;
-    if (l == 0) st_rlx32(&d->files[file].streams[rslot].marker, mark == ~0ull ? GFS_NO_MARKER : (uint32_t)mark);
+    if (l == 0) st_rlx32(&fe->streams[rslot].marker, mark == ~0ull ? GFS_NO_MARKER : (uint32_t)mark);
   }
-  if (l == 0)
+  if (tracing && l == 0)
     trace_ev(d, 1, GFS_EV_MISS, bid, file, (uint32_t)p, (near & 0xffu) | (hist << 8) | (rule << 24), wn,
              ws | ((uint64_t)req << 32));
   uint64_t cws = ws, cwe = ws + wn;
@@ -1588,10 +1625,10 @@ __device__ __attribute__((noinline)) int miss_shared_wave(const gfs_dev* d, uint
     cwe = cwe < hi_b ? cwe : hi_b;
   }
   const uint32_t cj = (uint32_t)__builtin_ctzll(free_cl);
-  uint64_t* claim = &d->claims[file].e[cj];
+  uint64_t* claim = &clp[cj];
   if (l == 0) st_rlx(claim, (cws << 32) | ((cwe - cws) << 1) | 1ull);
   const uint64_t tu0 = wall_clock64();
-  unlock_file_wave(d, file, ticket, cws, cwe, true, qv);
+  unlock_slots_wave(lq, ticket, cws, cwe, true, qv);
   __builtin_amdgcn_s_setprio(0);
   const uint64_t tl2 = wall_clock64();
   if (l == 0) {
@@ -2076,7 +2113,7 @@ __device__ __attribute__((noinline)) void async_issue_wave(const gfs_dev* d, uin
     return;
   }
   __builtin_amdgcn_s_setprio(3);
-  const RaState ras = ra_load_lane(d, file);
+  const RaState ras = ra_load_lane(&d->files[file], d->ra_recent, d->streams);
   uint64_t cl = 0;
   if (l < GFS_CLAIMS) cl = ld_rlx(&d->claims[file].e[l]);
   const uint64_t npages = d->files[file].npages;
